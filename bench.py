@@ -1,0 +1,204 @@
+#!/usr/bin/env python3
+"""Adaptive FSAI setup + PCG time-to-solution on one MI355X.
+
+One step = one adaptive FSAI setup of G plus one PCG solve of A x = b to rtol 1e-8 (x0 = 0) on
+a synthetic workload already resident in HBM; the handle is destroyed after each step.
+Default workload: 27-point 3-dof heterogeneous SPD operator on 64^3 nodes (786,432 unknowns,
+61,731,000 nonzeros, log-normal sigma = 1 cell coefficients), k_max = 10, s = 2, eps = 1e-2.
+
+Prints ONE JSON line.  ``value`` is the wall time of one solve (seconds, lower is better).
+``roofline`` covers the kernel with the largest total event-measured time inside the timed
+region; ``cpu_baseline`` times the FP64 CPU oracle on the same workload (host cores).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "aFSAI setup+PCG s to rtol 1e-8, HBM GB/s; p50/p99 latency vs plain"
+PEAK_HBM_GBS = 8000.0
+
+
+def workloads():
+    import synth
+
+    return {
+        "elast27_64": lambda: synth.elasticity27(64, 1.0, 2, kmax=10, s=2),
+        "poisson7_20": lambda: synth.poisson7(20, 1, kmax=5, s=1),
+        "elast27_150": lambda: synth.elasticity27(150, 2.0, 5, kmax=15, s=3),
+        "poisson7_121": lambda: synth.poisson7(121, 6, kmax=5, s=1),
+    }
+
+
+def kernel_bytes(name: str, n: int, nnz_a: int, nnz_g: int, w_g: int, kmax: int, mmax: int) -> float:
+    """Algorithmic HBM bytes of one launch of each kernel (every matrix entry and vector element
+    counted once per launch; caches assumed perfect for gathered vector entries)."""
+    vec = 8.0 * n
+    rp = 4.0 * (n + 1)
+    table = {
+        "spmv_A": 12.0 * nnz_a + rp + 2 * vec,           # A, x, y
+        "spmv_A_dot": 12.0 * nnz_a + rp + 3 * vec,       # + w for the fused dot
+        "spmv_G": (4.0 + w_g) * nnz_g + rp + 2 * vec,
+        "spmv_GT_dot": (4.0 + w_g) * nnz_g + rp + 3 * vec,
+        "update_xr": 6 * vec,                            # read x p r q, write x r
+        "update_p": 3 * vec,                             # read z p, write p
+        # setup: every growth step reads the rows of the pattern once (k_max passes over A at
+        # most) and the padded per-row results are written once
+        "afsai_rows": kmax * 12.0 * nnz_a + n * mmax * 12.0 + n * 24.0,
+    }
+    return table.get(name, float("nan"))
+
+
+def cpu_baseline(pb, iters_hint: int, threads: int) -> dict:
+    import oracle
+
+    t0 = time.perf_counter()
+    G = oracle.setup(pb.A, pb.kmax, pb.s, pb.eps, nthreads=threads)
+    t1 = time.perf_counter()
+    os.environ["OMP_NUM_THREADS"] = str(threads)
+    res = oracle.pcg(pb.A, G, pb.b, pb.rtol)
+    t2 = time.perf_counter()
+    return {"value": round(t2 - t0, 3), "unit": "s", "cores": threads, "kind": "oracle",
+            "sample": (f"whole workload: oracle setup of all {pb.n} rows ({t1 - t0:.2f} s, {threads} threads) + "
+                       f"oracle PCG to rtol {pb.rtol:g} ({res.iters} iterations, {t2 - t1:.2f} s; "
+                       f"GPU took {iters_hint})"),
+            "setup_s": round(t1 - t0, 3), "pcg_s": round(t2 - t1, 3), "iters": res.iters}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="elast27_64", choices=sorted(workloads()))
+    ap.add_argument("--g-prec", default="f64", choices=["f64", "f32"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-threads", type=int, default=0)
+    ap.add_argument("--no-profile", action="store_true", help="do not time kernels with HIP events")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
+              "row-stripe design is described but not built.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2010_14175_amd as af
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    af.lib()
+
+    pb = workloads()[args.workload]()
+    g_prec = af.F32 if args.g_prec == "f32" else af.F64
+    print(f"[bench] workload {pb.name}: n={pb.n} nnz={pb.A.nnz} kmax={pb.kmax} s={pb.s} eps={pb.eps} "
+          f"g_prec={args.g_prec}", file=sys.stderr, flush=True)
+    dA = af.DeviceCSR.from_host(pb.A)
+    b = torch.from_numpy(pb.b).cuda()
+    x = torch.zeros_like(b)
+
+    def step():
+        P = af.setup(dA, pb.kmax, pb.s, pb.eps, g_prec=g_prec)
+        x.zero_()
+        _, info = af.pcg_solve(dA, P, b, x=x, rtol=pb.rtol)
+        sinfo = P.info()
+        P.close()
+        return sinfo, info
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    profile = not args.no_profile
+    if profile:
+        af.profile_read(reset=True)
+        af.profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    setup_ms, pcg_ms, its = [], [], []
+    for _ in range(args.steps):
+        sinfo, info = step()
+        setup_ms.append(sinfo.ms)
+        pcg_ms.append(info.ms)
+        its.append(info.iters)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    kern = {}
+    if profile:
+        af.profile_enable(False)
+        kern = af.profile_read(reset=True)
+    sec = (t1 - t0) / args.steps
+    print(f"[bench] {args.steps} steps: {sec * 1e3:.2f} ms/step (setup {np.mean(setup_ms):.2f} ms, "
+          f"pcg {np.mean(pcg_ms):.2f} ms, {its[-1]} iterations, true relres {info.true_relres:.2e})",
+          file=sys.stderr, flush=True)
+
+    w_g = 4 if g_prec == af.F32 else 8
+    roof = None
+    kern_report = {}
+    for name, (launches, ms) in kern.items():
+        byt = kernel_bytes(name, pb.n, pb.A.nnz, sinfo.nnz_g, w_g, pb.kmax, sinfo.mmax)
+        avg_ms = ms / max(1, launches)
+        kern_report[name] = {"launches": launches, "total_ms": round(ms, 3), "avg_us": round(avg_ms * 1e3, 2),
+                             "gbs": round(byt / (avg_ms * 1e-3) / 1e9, 1) if avg_ms > 0 and byt == byt else None}
+    if kern:
+        dom = max(kern.items(), key=lambda kv: kv[1][1])[0]
+        launches, ms = kern[dom]
+        avg_s = ms / launches * 1e-3
+        byt = kernel_bytes(dom, pb.n, pb.A.nnz, sinfo.nnz_g, w_g, pb.kmax, sinfo.mmax)
+        ach = byt / avg_s / 1e9
+        roof = {"kernel": dom, "bound": "hbm", "achieved": round(ach, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": round(ach / PEAK_HBM_GBS, 4), "traffic": None, "bytes_per_launch": byt,
+                "avg_launch_us": round(avg_s * 1e6, 2)}
+
+    # whole-PCG achieved bandwidth from the per-iteration algorithmic bytes
+    it_bytes = (kernel_bytes("spmv_A_dot", pb.n, pb.A.nnz, sinfo.nnz_g, w_g, pb.kmax, sinfo.mmax)
+                + kernel_bytes("update_xr", pb.n, 0, 0, w_g, 0, 0)
+                + kernel_bytes("spmv_G", pb.n, 0, sinfo.nnz_g, w_g, 0, 0)
+                + kernel_bytes("spmv_GT_dot", pb.n, 0, sinfo.nnz_g, w_g, 0, 0)
+                + kernel_bytes("update_p", pb.n, 0, 0, w_g, 0, 0))
+    pcg_gbs = it_bytes * its[-1] / (np.mean(pcg_ms) * 1e-3) / 1e9
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        threads = args.cpu_threads or int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or (os.cpu_count() or 1)
+        print(f"[bench] cpu baseline: oracle on {threads} threads ...", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(pb, its[-1], threads)
+
+    out = {
+        "metric": METRIC,
+        "value": round(sec, 6),
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(sec * 1e3, 3),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if g_prec == af.F64 else "f64 (G stored f32)",
+        "data": "synthetic",
+        "config": {"workload": pb.name, "n": pb.n, "nnz": pb.A.nnz, "kmax": pb.kmax, "s": pb.s, "eps": pb.eps,
+                   "rtol": pb.rtol, "g_prec": args.g_prec, "nnz_g": sinfo.nnz_g},
+        "setup_ms": round(float(np.mean(setup_ms)), 3),
+        "pcg_ms": round(float(np.mean(pcg_ms)), 3),
+        "iters": its[-1],
+        "true_relres": info.true_relres,
+        "pcg_hbm_gbs": round(pcg_gbs, 1),
+        "roofline": roof,
+        "kernels": kern_report,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

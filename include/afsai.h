@@ -1,0 +1,201 @@
+/*
+ * afsai.h -- C ABI of the MI355X (gfx950) adaptive FSAI library: setup of the factored sparse
+ * approximate inverse G (M^-1 = G^T G ~ A^-1) with adaptive pattern growth, its application,
+ * and the preconditioned conjugate gradient method, for sparse SPD matrices in CSR.
+ *
+ * Method: Isotton, Janna, Bernaschi, "A GPU-accelerated adaptive FSAI preconditioner for
+ * massively parallel simulations" (arXiv 2010.14175), Sec. 2 (FSAI with dynamic pattern
+ * selection) and Sec. 3 (GPU kernels: Kaporin gradient and selection, systems gather, batched
+ * Cholesky, group-per-row SpMV).  One GPU; no communication.
+ *
+ * Conventions for every entry point
+ *   - Pointers marked (device) are HIP device pointers on the current device; pointers marked
+ *     (host) are host memory.  Sizes are element counts.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the default stream).  All device work of
+ *     a call is enqueued on that stream.
+ *   - Return value: AFSAI_OK (0) or one of the AFSAI_ERR_* codes below; no C++ exception ever
+ *     crosses this interface.  afsai_last_error() returns a message for the calling thread's
+ *     most recent failure.
+ *   - Caller-owned buffers (A, b, x, r, z, export targets) must stay valid until the enqueued
+ *     work has finished; the library never frees or retains them after returning.
+ */
+#ifndef AFSAI_H
+#define AFSAI_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define AFSAI_OK 0
+#define AFSAI_ERR_INVALID_ARG 1   /* null pointer, n <= 0, kmax < 0, s < 1, eps < 0, rtol <= 0 ... */
+#define AFSAI_ERR_BAD_MATRIX 2    /* CSR structure: unsorted/duplicate/out-of-range columns, missing
+                                     diagonal, row pointers not monotone, or (with AFSAI_VALIDATE)
+                                     an asymmetric matrix */
+#define AFSAI_ERR_NOT_SPD 3       /* a_ii <= 0, a Cholesky pivot <= 0 or not finite, or p.Ap <= 0 */
+#define AFSAI_ERR_NO_MEMORY 4     /* device allocation failed */
+#define AFSAI_ERR_NOT_CONVERGED 5 /* PCG reached maxit; x and info are still filled */
+#define AFSAI_ERR_TOO_LARGE 6     /* 1 + kmax*s > 64, or a pattern's candidate set cannot be held
+                                     on chip, or nnz(G) would exceed 2^31 - 1 */
+#define AFSAI_ERR_HIP 7           /* a HIP runtime call failed (message in afsai_last_error) */
+
+/* value type of G and G^T storage */
+#define AFSAI_F64 0
+#define AFSAI_F32 1
+
+/* afsai_params.flags */
+#define AFSAI_VALIDATE 1u /* check the CSR structure and exact symmetry on the device first */
+
+/*
+ * Square sparse matrix in CSR, 0-based, int32 indices (the paper's 4-byte local indices,
+ * Sec. 4.1).  Both triangles stored; columns strictly ascending within each row; the diagonal
+ * present in every row.  For the setup, A must be symmetric bit for bit (a_ij == a_ji): the
+ * gather of A[P,P] reads each pair from whichever of the two rows it has loaded.
+ */
+typedef struct afsai_csr {
+    int32_t n;              /* rows = columns, > 0 */
+    int32_t nnz;            /* stored entries = row_ptr[n] */
+    const int32_t *row_ptr; /* (device) n+1 */
+    const int32_t *col_idx; /* (device) nnz */
+    const double *val;      /* (device) nnz */
+} afsai_csr;
+
+/*
+ * Controls of the adaptive procedure (Sec. 2, the three user parameters).
+ *   kmax      maximum number of pattern-growth steps per row, >= 0 (kmax = 0 gives
+ *             G = diag(a_ii^-1/2), i.e. Jacobi, the paper's baseline of Sec. 5.2)
+ *   s         positions added to a row per step, >= 1 (1 + kmax*s <= 64)
+ *   eps       a row stops growing once psi_k / psi_0 <= eps (eq. exit_crit), >= 0
+ *   tie_rtol  relative tie band of the selection: every candidate whose |gradient| is within
+ *             tie_rtol of the largest counts as tied and the smallest column wins; in [0, 1);
+ *             2^-26 recommended (exact ties of stencil matrices then resolve identically on
+ *             any hardware)
+ *   g_prec    AFSAI_F64 or AFSAI_F32 storage for G and G^T (values widened to FP64 in every
+ *             product; the per-row Cholesky is FP64 in both cases)
+ *   flags     AFSAI_VALIDATE or 0
+ */
+typedef struct afsai_params {
+    int32_t kmax;
+    int32_t s;
+    double eps;
+    double tie_rtol;
+    int32_t g_prec;
+    uint32_t flags;
+} afsai_params;
+
+/* opaque preconditioner: owns G and G^T (CSR, device), per-row diagnostics and a PCG workspace */
+typedef struct afsai_precond_s *afsai_precond;
+
+/* setup diagnostics (host) */
+typedef struct afsai_setup_info {
+    int32_t n;
+    int32_t mmax;              /* 1 + kmax*s */
+    int64_t nnz_g;             /* entries of G (= entries of G^T) */
+    int32_t g_prec;
+    int32_t rows_stop_kmax;    /* rows that took all kmax steps */
+    int32_t rows_stop_eps;     /* rows stopped by eq. exit_crit */
+    int32_t rows_stop_nocand;  /* rows that ran out of eligible candidates */
+    int32_t rows_retried;      /* rows redone with a larger on-chip candidate table */
+    double sum_log_psi;        /* sum_i log psi_i (final); kappa = exp((this - log det A)/n), eq. kap2 */
+    double ms;                 /* wall time of the setup call */
+} afsai_setup_info;
+
+/* PCG diagnostics (host) */
+typedef struct afsai_pcg_info {
+    int32_t iters;       /* iterations performed */
+    int32_t converged;   /* 1 if ||r_k|| <= rtol ||b|| */
+    double relres;       /* ||r_k|| / ||b||, recursively updated residual */
+    double true_relres;  /* ||b - A x|| / ||b|| recomputed at the end */
+    double ms;           /* wall time of the solve call */
+} afsai_pcg_info;
+
+/*
+ * afsai_setup -- adaptive FSAI setup (Sec. 2; kernels of Sec. 3).
+ *   Every row i starts from P_i = {i}, g = a_ii^-1/2 (G_0 = I scaled) and, up to kmax times,
+ *   (1) forms the Kaporin gradient v_j = (A g)_j over the lower candidates j < i, j not in P_i
+ *       (eq. grapsi), (2) appends the s candidates of largest |v_j| (ties: tie_rtol band,
+ *       smallest column; candidates with |v_j| <= 2^-40 max|v| are not eligible; no eligible
+ *       candidate stops the row), (3) gathers A[P_i,P_i], (4) factors it A[P,P] = L L^T in FP64
+ *       and sets row i of G to L^-T e_m (eq. DensSys scaled by eq. diagScal, so that
+ *       (G A G^T)_ii = 1), with psi_i = L_mm^2, and (5) stops the row when psi_i/a_ii <= eps.
+ *   A    (host struct, device arrays) the SPD matrix, see afsai_csr.
+ *   p    (host) parameters.
+ *   out  (host) receives a new handle on success (NULL on failure).
+ *   Synchronous: returns after the device work is done.  The handle does not reference A.
+ */
+int afsai_setup(const afsai_csr *A, const afsai_params *p, void *stream, afsai_precond *out);
+
+/*
+ * afsai_apply -- z = G^T (G r), the preconditioner application M^-1 r (eq. prec).
+ *   r, z (device) length n; must not alias.  Asynchronous on `stream`.
+ *   Uses the handle's workspace: one apply or solve per handle at a time.
+ */
+int afsai_apply(afsai_precond P, const double *r, double *z, void *stream);
+
+/*
+ * pcg_solve -- preconditioned conjugate gradient for A x = b with M^-1 = G^T G (P != NULL) or
+ *   M = I (P == NULL, plain CG).  Textbook PCG (Sec. 5.2 stops at a residual reduction of eight
+ *   orders of magnitude): x holds x0 on entry and the last iterate on return; the iteration
+ *   stops when ||r_k||_2 <= rtol ||b||_2 (recursive residual) or after maxit iterations.
+ *   b, x (device) length n.  rtol > 0, maxit >= 0.  info (host, may be NULL).
+ *   ||b|| = 0 gives x = 0 and 0 iterations.
+ *   Returns AFSAI_OK, AFSAI_ERR_NOT_CONVERGED (x, info filled) or AFSAI_ERR_NOT_SPD (p.Ap <= 0).
+ *   Synchronous.
+ */
+int pcg_solve(const afsai_csr *A, afsai_precond P, const double *b, double *x, double rtol,
+              int32_t maxit, void *stream, afsai_pcg_info *info);
+
+/* afsai_spmv -- y = A x (group-per-row CSR product used by the solver).  Asynchronous. */
+int afsai_spmv(const afsai_csr *A, const double *x, double *y, void *stream);
+
+/* afsai_get_setup_info -- diagnostics of a handle (host struct). */
+int afsai_get_setup_info(afsai_precond P, afsai_setup_info *info);
+
+/*
+ * afsai_export -- copies G as CSR (FP64 values, widened if stored in FP32) into caller
+ *   buffers (device): row_ptr n+1, col and val nnz_g entries.  Synchronous.
+ */
+int afsai_export(afsai_precond P, int32_t *row_ptr, int32_t *col, double *val, void *stream);
+
+/*
+ * afsai_export_rows -- per-row diagnostics (device buffers, n entries each, any may be NULL):
+ *   psi (final psi_i), steps (growth steps taken), reason (0 kmax reached, 1 eps test,
+ *   2 no eligible candidate).  Synchronous.
+ */
+int afsai_export_rows(afsai_precond P, double *psi, int32_t *steps, int32_t *reason, void *stream);
+
+/*
+ * afsai_import -- builds a handle from a given lower-triangular G (device CSR, copied; the
+ *   caller keeps ownership of its arrays), storing values as g_prec.  Lets a caller persist a
+ *   preconditioner and skip the setup.  Synchronous.
+ */
+int afsai_import(const afsai_csr *G, int32_t g_prec, void *stream, afsai_precond *out);
+
+/* afsai_destroy -- frees a handle and everything it owns (NULL is a no-op). */
+void afsai_destroy(afsai_precond P);
+
+/* afsai_last_error -- message of the calling thread's most recent failure ("" if none). */
+const char *afsai_last_error(void);
+
+/*
+ * Kernel timing: with profiling on, the library brackets every kernel launch with HIP events
+ * on the launch stream and accumulates, per kernel name, the number of launches and the total
+ * event-measured duration.  Off by default; enabling it adds event overhead.
+ */
+typedef struct afsai_kernel_time {
+    char name[48];
+    int64_t launches;
+    double total_ms;
+} afsai_kernel_time;
+
+int afsai_profile_enable(int32_t on);
+/* copies up to cap entries into out (host), sets *count; reset != 0 clears the counters */
+int afsai_profile_read(afsai_kernel_time *out, int32_t cap, int32_t *count, int32_t reset);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* AFSAI_H */

@@ -1,0 +1,289 @@
+"""Adaptive FSAI (aFSAI) preconditioner and PCG on AMD Instinct MI355X (gfx950).
+
+Thin Python binding of the C ABI declared in ``include/afsai.h`` (``libafsai.so``, built from
+``csrc/*.hip`` by :mod:`paper_2010_14175_amd.build`).  This module only marshals arguments:
+PyTorch provides device memory and the stream, every step of the method runs in the HIP
+kernels of the library.  There is no fallback: if the library is missing or fails to load,
+every call raises.
+
+Method: Isotton, Janna, Bernaschi, "A GPU-accelerated adaptive FSAI preconditioner for
+massively parallel simulations", Sec. 2 (adaptive pattern, eqs. DensSys, diagScal, grapsi,
+exit_crit) and Sec. 3 (GPU kernels).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libafsai.so")
+TIE_RTOL = 2.0 ** -26
+
+OK, ERR_INVALID_ARG, ERR_BAD_MATRIX, ERR_NOT_SPD, ERR_NO_MEMORY, ERR_NOT_CONVERGED, ERR_TOO_LARGE, ERR_HIP = range(8)
+F64, F32 = 0, 1
+VALIDATE = 1
+STOP_KMAX, STOP_EPS, STOP_NOCAND = 0, 1, 2
+
+# every symbol the C header declares
+EXPORTS = ("afsai_setup", "afsai_apply", "pcg_solve", "afsai_spmv", "afsai_get_setup_info", "afsai_export",
+           "afsai_export_rows", "afsai_import", "afsai_destroy", "afsai_last_error", "afsai_profile_enable",
+           "afsai_profile_read")
+
+
+class CsrStruct(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("nnz", ctypes.c_int32), ("row_ptr", ctypes.c_void_p),
+                ("col_idx", ctypes.c_void_p), ("val", ctypes.c_void_p)]
+
+
+class ParamsStruct(ctypes.Structure):
+    _fields_ = [("kmax", ctypes.c_int32), ("s", ctypes.c_int32), ("eps", ctypes.c_double),
+                ("tie_rtol", ctypes.c_double), ("g_prec", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+
+
+class SetupInfoStruct(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("mmax", ctypes.c_int32), ("nnz_g", ctypes.c_int64), ("g_prec", ctypes.c_int32),
+                ("rows_stop_kmax", ctypes.c_int32), ("rows_stop_eps", ctypes.c_int32),
+                ("rows_stop_nocand", ctypes.c_int32), ("rows_retried", ctypes.c_int32),
+                ("sum_log_psi", ctypes.c_double), ("ms", ctypes.c_double)]
+
+
+class PcgInfoStruct(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("converged", ctypes.c_int32), ("relres", ctypes.c_double),
+                ("true_relres", ctypes.c_double), ("ms", ctypes.c_double)]
+
+
+class KernelTimeStruct(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 48), ("launches", ctypes.c_int64), ("total_ms", ctypes.c_double)]
+
+
+class AfsaiError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"[afsai status {code}] {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    """The loaded C library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2010_14175_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32 = ctypes.c_void_p, ctypes.c_int32
+        P = ctypes.POINTER
+        L.afsai_setup.argtypes = [P(CsrStruct), P(ParamsStruct), vp, P(vp)]
+        L.afsai_apply.argtypes = [vp, vp, vp, vp]
+        L.pcg_solve.argtypes = [P(CsrStruct), vp, vp, vp, ctypes.c_double, i32, vp, P(PcgInfoStruct)]
+        L.afsai_spmv.argtypes = [P(CsrStruct), vp, vp, vp]
+        L.afsai_get_setup_info.argtypes = [vp, P(SetupInfoStruct)]
+        L.afsai_export.argtypes = [vp, vp, vp, vp, vp]
+        L.afsai_export_rows.argtypes = [vp, vp, vp, vp, vp]
+        L.afsai_import.argtypes = [P(CsrStruct), i32, vp, P(vp)]
+        L.afsai_destroy.argtypes = [vp]
+        L.afsai_destroy.restype = None
+        L.afsai_last_error.restype = ctypes.c_char_p
+        L.afsai_profile_enable.argtypes = [i32]
+        L.afsai_profile_read.argtypes = [P(KernelTimeStruct), i32, P(i32), i32]
+        for name in EXPORTS:
+            if name not in ("afsai_destroy", "afsai_last_error"):
+                getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _check(rc: int, what: str, allow=(OK,)):
+    if rc not in allow:
+        raise AfsaiError(rc, f"{what}: {lib().afsai_last_error().decode(errors='replace')}")
+    return rc
+
+
+def _stream(stream=None):
+    import torch
+
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _ptr(t) -> ctypes.c_void_p:
+    return ctypes.c_void_p(0 if t is None else t.data_ptr())
+
+
+class DeviceCSR:
+    """A square CSR matrix resident on the GPU (int32 indices, fp64 values), held by torch
+    tensors.  ``struct`` is the C view passed to the library."""
+
+    def __init__(self, row_ptr, col, val):
+        import torch
+
+        self.row_ptr, self.col, self.val = row_ptr, col, val
+        assert row_ptr.dtype == torch.int32 and col.dtype == torch.int32 and val.dtype == torch.float64
+        assert row_ptr.is_contiguous() and col.is_contiguous() and val.is_contiguous()
+        self.n = int(row_ptr.numel() - 1)
+        self.nnz = int(col.numel())
+
+    @property
+    def struct(self) -> CsrStruct:
+        return CsrStruct(self.n, self.nnz, self.row_ptr.data_ptr(), self.col.data_ptr(), self.val.data_ptr())
+
+    @staticmethod
+    def from_host(A, device="cuda") -> "DeviceCSR":
+        """From any object with numpy ``row_ptr``, ``col`` and ``val`` arrays."""
+        import torch
+
+        rp = torch.from_numpy(np.ascontiguousarray(A.row_ptr, np.int32)).to(device)
+        ci = torch.from_numpy(np.ascontiguousarray(A.col, np.int32)).to(device)
+        va = torch.from_numpy(np.ascontiguousarray(A.val, np.float64)).to(device)
+        return DeviceCSR(rp, ci, va)
+
+
+@dataclass
+class SetupInfo:
+    n: int
+    mmax: int
+    nnz_g: int
+    g_prec: int
+    rows_stop_kmax: int
+    rows_stop_eps: int
+    rows_stop_nocand: int
+    rows_retried: int
+    sum_log_psi: float
+    ms: float
+
+
+@dataclass
+class PcgInfo:
+    status: int
+    iters: int
+    converged: bool
+    relres: float
+    true_relres: float
+    ms: float
+
+
+class Preconditioner:
+    """Owns an ``afsai_precond`` handle (G and G^T on the device)."""
+
+    def __init__(self, handle: ctypes.c_void_p):
+        self._h = handle
+
+    @property
+    def handle(self) -> ctypes.c_void_p:
+        if not self._h:
+            raise RuntimeError("preconditioner already destroyed")
+        return self._h
+
+    def info(self) -> SetupInfo:
+        s = SetupInfoStruct()
+        _check(lib().afsai_get_setup_info(self.handle, ctypes.byref(s)), "afsai_get_setup_info")
+        return SetupInfo(s.n, s.mmax, s.nnz_g, s.g_prec, s.rows_stop_kmax, s.rows_stop_eps, s.rows_stop_nocand,
+                         s.rows_retried, s.sum_log_psi, s.ms)
+
+    def export(self, stream=None):
+        """G as (row_ptr int32, col int32, val f64) device tensors."""
+        import torch
+
+        inf = self.info()
+        rp = torch.empty(inf.n + 1, dtype=torch.int32, device="cuda")
+        ci = torch.empty(max(1, inf.nnz_g), dtype=torch.int32, device="cuda")
+        va = torch.empty(max(1, inf.nnz_g), dtype=torch.float64, device="cuda")
+        _check(lib().afsai_export(self.handle, _ptr(rp), _ptr(ci), _ptr(va), _stream(stream)), "afsai_export")
+        return rp, ci[: inf.nnz_g], va[: inf.nnz_g]
+
+    def export_rows(self, stream=None):
+        """(psi, steps, reason) device tensors, one entry per row."""
+        import torch
+
+        n = self.info().n
+        psi = torch.empty(n, dtype=torch.float64, device="cuda")
+        steps = torch.empty(n, dtype=torch.int32, device="cuda")
+        reason = torch.empty(n, dtype=torch.int32, device="cuda")
+        _check(lib().afsai_export_rows(self.handle, _ptr(psi), _ptr(steps), _ptr(reason), _stream(stream)),
+               "afsai_export_rows")
+        return psi, steps, reason
+
+    def apply(self, r, z=None, stream=None):
+        """z = G^T (G r)."""
+        import torch
+
+        if z is None:
+            z = torch.empty_like(r)
+        _check(lib().afsai_apply(self.handle, _ptr(r), _ptr(z), _stream(stream)), "afsai_apply")
+        return z
+
+    def close(self):
+        if self._h:
+            lib().afsai_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def setup(A: DeviceCSR, kmax: int, s: int, eps: float, tie_rtol: float = TIE_RTOL, g_prec: int = F64,
+          validate: bool = False, stream=None) -> Preconditioner:
+    """Adaptive FSAI setup (``afsai_setup``)."""
+    p = ParamsStruct(int(kmax), int(s), float(eps), float(tie_rtol), int(g_prec), VALIDATE if validate else 0)
+    h = ctypes.c_void_p()
+    st = A.struct
+    _check(lib().afsai_setup(ctypes.byref(st), ctypes.byref(p), _stream(stream), ctypes.byref(h)), "afsai_setup")
+    return Preconditioner(h)
+
+
+def import_factor(G: DeviceCSR, g_prec: int = F64, stream=None) -> Preconditioner:
+    """A preconditioner from a given lower-triangular G (``afsai_import``)."""
+    h = ctypes.c_void_p()
+    st = G.struct
+    _check(lib().afsai_import(ctypes.byref(st), int(g_prec), _stream(stream), ctypes.byref(h)), "afsai_import")
+    return Preconditioner(h)
+
+
+def pcg_solve(A: DeviceCSR, P: Preconditioner | None, b, x=None, rtol: float = 1e-8, maxit: int | None = None,
+              stream=None, raise_on_error: bool = True):
+    """Preconditioned CG (``pcg_solve``); x (device, fp64) holds x0 on entry when given.
+    Returns (x, PcgInfo)."""
+    import torch
+
+    if x is None:
+        x = torch.zeros_like(b)
+    maxit = A.n if maxit is None else int(maxit)
+    inf = PcgInfoStruct()
+    st = A.struct
+    rc = lib().pcg_solve(ctypes.byref(st), None if P is None else P.handle, _ptr(b), _ptr(x), float(rtol), maxit,
+                         _stream(stream), ctypes.byref(inf))
+    if raise_on_error:
+        _check(rc, "pcg_solve", allow=(OK, ERR_NOT_CONVERGED))
+    return x, PcgInfo(rc, inf.iters, bool(inf.converged), inf.relres, inf.true_relres, inf.ms)
+
+
+def spmv(A: DeviceCSR, x, y=None, stream=None):
+    """y = A x (``afsai_spmv``)."""
+    import torch
+
+    if y is None:
+        y = torch.empty_like(x)
+    st = A.struct
+    _check(lib().afsai_spmv(ctypes.byref(st), _ptr(x), _ptr(y), _stream(stream)), "afsai_spmv")
+    return y
+
+
+def profile_enable(on: bool = True):
+    _check(lib().afsai_profile_enable(1 if on else 0), "afsai_profile_enable")
+
+
+def profile_read(reset: bool = False) -> dict:
+    """{kernel name: (launches, total_ms)} of the event timer."""
+    cap = 64
+    arr = (KernelTimeStruct * cap)()
+    cnt = ctypes.c_int32(0)
+    _check(lib().afsai_profile_read(arr, cap, ctypes.byref(cnt), 1 if reset else 0), "afsai_profile_read")
+    return {arr[k].name.decode(): (int(arr[k].launches), float(arr[k].total_ms)) for k in range(cnt.value)}

@@ -1,0 +1,162 @@
+// Host runtime pieces of the adaptive FSAI library: thread-local error messages, cached
+// device properties and the HIP-event kernel timer behind afsai_profile_*.
+#include <cstdarg>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "common.hpp"
+
+namespace afsai {
+
+static thread_local std::string g_last_error;
+
+void set_error(const char *fmt, ...) {
+    char buf[1024];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+}
+
+void clear_error() { g_last_error.clear(); }
+
+int device_info(DeviceInfo *out) {
+    static std::mutex mu;
+    static std::map<int, DeviceInfo> cache;
+    int dev = 0;
+    AFSAI_HIP_TRY(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = cache.find(dev);
+    if (it == cache.end()) {
+        DeviceInfo d;
+        d.device = dev;
+        int cus = 0;
+        AFSAI_HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+        d.num_cus = cus > 0 ? cus : 1;
+        // MI355X: 256 CUs in 8 XCDs of 32; smaller parts (or partition modes) get one group
+        d.num_xcds = (d.num_cus % 8 == 0 && d.num_cus >= 64) ? 8 : 1;
+        it = cache.emplace(dev, d).first;
+    }
+    *out = it->second;
+    return AFSAI_OK;
+}
+
+// ---------------------------------------------------------------------------------------
+// kernel timer
+// ---------------------------------------------------------------------------------------
+namespace {
+struct Pending {
+    hipEvent_t a, b;
+    std::string name;
+};
+struct Acc {
+    int64_t launches = 0;
+    double ms = 0.0;
+};
+std::mutex prof_mu;
+bool prof_enabled = false;
+std::vector<hipEvent_t> event_pool;
+std::vector<hipEvent_t> started;  // token -> start event
+std::vector<Pending> pending;
+std::map<std::string, Acc> totals;
+
+hipEvent_t get_event() {
+    if (!event_pool.empty()) {
+        hipEvent_t e = event_pool.back();
+        event_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+}  // namespace
+
+bool profiling_on() {
+    std::lock_guard<std::mutex> lk(prof_mu);
+    return prof_enabled;
+}
+
+int prof_begin(hipStream_t s) {
+    std::lock_guard<std::mutex> lk(prof_mu);
+    if (!prof_enabled) return -1;
+    hipEvent_t e = get_event();
+    if (!e) return -1;
+    if (hipEventRecord(e, s) != hipSuccess) {
+        event_pool.push_back(e);
+        return -1;
+    }
+    started.push_back(e);
+    return (int)started.size() - 1;
+}
+
+void prof_end(int token, const char *name, hipStream_t s) {
+    if (token < 0) return;
+    std::lock_guard<std::mutex> lk(prof_mu);
+    if (token >= (int)started.size() || !started[token]) return;
+    hipEvent_t b = get_event();
+    if (!b) return;
+    if (hipEventRecord(b, s) != hipSuccess) {
+        event_pool.push_back(b);
+        return;
+    }
+    pending.push_back({started[token], b, name});
+    started[token] = nullptr;
+}
+
+void prof_flush() {
+    std::lock_guard<std::mutex> lk(prof_mu);
+    for (auto &p : pending) {
+        float ms = 0.f;
+        if (hipEventSynchronize(p.b) == hipSuccess && hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+            Acc &a = totals[p.name];
+            a.launches += 1;
+            a.ms += ms;
+        }
+        event_pool.push_back(p.a);
+        event_pool.push_back(p.b);
+    }
+    pending.clear();
+    bool all_done = true;
+    for (auto e : started)
+        if (e) all_done = false;
+    if (all_done) started.clear();
+}
+
+}  // namespace afsai
+
+extern "C" {
+
+const char *afsai_last_error(void) { return afsai::g_last_error.c_str(); }
+
+int afsai_profile_enable(int32_t on) {
+    afsai::prof_flush();
+    std::lock_guard<std::mutex> lk(afsai::prof_mu);
+    afsai::prof_enabled = (on != 0);
+    return AFSAI_OK;
+}
+
+int afsai_profile_read(afsai_kernel_time *out, int32_t cap, int32_t *count, int32_t reset) {
+    if (cap < 0 || (cap > 0 && !out)) AFSAI_FAIL(AFSAI_ERR_INVALID_ARG, "afsai_profile_read: bad buffer");
+    afsai::prof_flush();
+    std::lock_guard<std::mutex> lk(afsai::prof_mu);
+    int32_t k = 0;
+    for (auto &kv : afsai::totals) {
+        if (k < cap) {
+            std::memset(out[k].name, 0, sizeof out[k].name);
+            std::strncpy(out[k].name, kv.first.c_str(), sizeof out[k].name - 1);
+            out[k].launches = kv.second.launches;
+            out[k].total_ms = kv.second.ms;
+        }
+        ++k;
+    }
+    if (count) *count = k < cap ? k : cap;
+    if (reset) afsai::totals.clear();
+    return AFSAI_OK;
+}
+
+}  // extern "C"

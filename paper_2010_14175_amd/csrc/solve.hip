@@ -1,0 +1,548 @@
+// Group-per-row CSR products and the PCG iteration (Sec. 3 "miniwarp" SpMV; Sec. 5.2 PCG).
+//
+// SpMV: a group of GS lanes (GS in {4, 8, 16, 32, 64}, chosen from the average row length like
+// the paper's miniwarps, but sized for 64-lane wavefronts) owns one row; lanes stride through
+// the row's entries with coalesced, non-temporal loads of the matrix and cached loads of x;
+// the group reduces with cross-lane shuffles in a fixed order.  Each block owns one
+// contiguous range of rows and blocks are renumbered so that every XCD streams one contiguous
+// part of the matrix (its L2 then holds the x entries its rows share).
+//
+// PCG: all scalars (rho, alpha, beta, ||r||) live on the device.  Dot products are fused into
+// the kernel that produces one of their operands; per-block partial sums are combined by the
+// last block to finish, in block order, so results do not depend on scheduling.  A device
+// flag ends the iteration: kernels that see it return at once, so the host enqueues chunks of
+// iterations and only reads the flag once per chunk, one chunk behind.
+#include <cmath>
+#include <vector>
+
+#include "common.hpp"
+
+namespace afsai {
+
+constexpr int kThreads = 256;
+
+enum : int { FIN_NONE = 0, FIN_ALPHA = 1, FIN_BETA = 2, FIN_RHO0 = 3 };
+enum : int { DONE_NO = 0, DONE_CONVERGED = 1, DONE_NOT_SPD = 2, DONE_MAXIT = 3, DONE_ZERO_RHS = 4 };
+
+struct PcgScalars {
+    double rho;      // r.z of the current iterate
+    double alpha;
+    double beta;
+    double rr;       // ||r||^2
+    double bb;       // ||b||^2
+    double tol;      // rtol * ||b||
+    double rtol;
+    int32_t it;      // iterations completed
+    int32_t maxit;
+    int32_t done;    // DONE_*
+    int32_t plain;   // 1: M = I (z = r)
+    uint32_t ticket; // last-block-done counter (returns to 0 after each kernel)
+    int32_t pad;
+};
+
+// ---------------------------------------------------------------------------------------
+// block helpers
+// ---------------------------------------------------------------------------------------
+__device__ __forceinline__ double block_sum(double v, double *sh /* >= kThreads/64 */) {
+    v = wave_sum(v);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) sh[w] = v;
+    __syncthreads();
+    double t = 0.0;
+    if (threadIdx.x == 0)
+        for (int k = 0; k < kThreads / 64; ++k) t += sh[k];
+    __syncthreads();
+    return t;  // valid in thread 0
+}
+
+// Stores this block's partial(s) and returns true in the block that finished last; that block
+// then sees every other block's partials.
+__device__ __forceinline__ bool finish_partials(double *partials, int slots, const double *mine,
+                                                uint32_t *ticket) {
+    __shared__ bool last;
+    if (threadIdx.x == 0) {
+        for (int k = 0; k < slots; ++k) partials[(size_t)k * gridDim.x + blockIdx.x] = mine[k];
+        uint32_t t = __hip_atomic_fetch_add(ticket, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        last = (t == gridDim.x - 1);
+    }
+    __syncthreads();
+    return last;
+}
+
+// Sum of one slot of the partials in block order (deterministic), valid in thread 0.
+__device__ __forceinline__ double reduce_partials(const double *partials, int slot, double *sh) {
+    double v = 0.0;
+    const int nb = gridDim.x;
+    const int per = (nb + kThreads - 1) / kThreads;
+    const int lo = threadIdx.x * per, hi = min(nb, lo + per);
+    for (int k = lo; k < hi; ++k)
+        v += __hip_atomic_load(&partials[(size_t)slot * nb + k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    // fixed-shape tree over the threads
+    return block_sum(v, sh);
+}
+
+__device__ __forceinline__ void finalize(PcgScalars *sc, int fin, double v) {
+    if (fin == FIN_ALPHA) {
+        // v = p.q
+        if (!(v > 0.0) || !isfinite(v)) {
+            sc->done = DONE_NOT_SPD;
+        } else {
+            sc->alpha = sc->rho / v;
+        }
+    } else if (fin == FIN_BETA) {
+        sc->beta = v / sc->rho;
+        sc->rho = v;
+    } else if (fin == FIN_RHO0) {
+        sc->rho = v;
+    }
+}
+
+// ---------------------------------------------------------------------------------------
+// CSR SpMV, one group of GS lanes per row; optional fused dot y.w with a PCG finalisation
+// ---------------------------------------------------------------------------------------
+template <int GS, typename VT, bool DOT>
+__global__ __launch_bounds__(kThreads) void k_spmv(int n, const int32_t *__restrict__ rp,
+                                                    const int32_t *__restrict__ ci,
+                                                    const VT *__restrict__ val,
+                                                    const double *__restrict__ x,
+                                                    double *__restrict__ y,
+                                                    const double *__restrict__ w,
+                                                    double *__restrict__ partials,
+                                                    PcgScalars *sc, int fin, int nxcd) {
+    if (sc && sc->done) return;
+    __shared__ double sh[kThreads / 64];
+    const int lb = xcd_block(blockIdx.x, gridDim.x, nxcd);
+    const int64_t per = ((int64_t)n + gridDim.x - 1) / gridDim.x;
+    const int r0 = (int)min<int64_t>(n, per * lb), r1 = (int)min<int64_t>(n, per * (lb + 1));
+    const int lg = threadIdx.x % GS, grp = threadIdx.x / GS;
+    constexpr int RPI = kThreads / GS;  // rows per block iteration
+    double part = 0.0;
+    for (int row = r0 + grp; row < r1; row += RPI) {
+        const int a = rp[row], b = rp[row + 1];
+        double acc = 0.0;
+        for (int e = a + lg; e < b; e += GS) {
+            const int c = __builtin_nontemporal_load(&ci[e]);
+            const double v = (double)__builtin_nontemporal_load(&val[e]);
+            acc = fma(v, x[c], acc);
+        }
+#pragma unroll
+        for (int off = GS / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, GS);
+        if (lg == 0) {
+            y[row] = acc;
+            if (DOT) part = fma(acc, w[row], part);
+        }
+    }
+    if (DOT) {
+        double bs = block_sum(part, sh);
+        if (finish_partials(partials, 1, &bs, &sc->ticket)) {
+            double tot = reduce_partials(partials, 0, sh);
+            if (threadIdx.x == 0) {
+                finalize(sc, fin, tot);
+                sc->ticket = 0;
+            }
+        }
+    }
+}
+
+// r = b - q ; partials of b.b and r.r ; finalisation checks ||b|| = 0 and ||r0|| <= tol
+__global__ __launch_bounds__(kThreads) void k_init_residual(int n, const double *__restrict__ b,
+                                                             const double *__restrict__ q,
+                                                             double *__restrict__ r,
+                                                             double *__restrict__ partials,
+                                                             PcgScalars *sc) {
+    __shared__ double sh[kThreads / 64];
+    const int64_t per = ((int64_t)n + gridDim.x - 1) / gridDim.x;
+    const int i0 = (int)min<int64_t>(n, per * blockIdx.x), i1 = (int)min<int64_t>(n, per * (blockIdx.x + 1));
+    double pb = 0.0, pr = 0.0;
+    for (int i = i0 + threadIdx.x; i < i1; i += kThreads) {
+        const double bi = b[i], ri = bi - q[i];
+        r[i] = ri;
+        pb = fma(bi, bi, pb);
+        pr = fma(ri, ri, pr);
+    }
+    double mine[2];
+    mine[0] = block_sum(pb, sh);
+    mine[1] = block_sum(pr, sh);
+    if (finish_partials(partials, 2, mine, &sc->ticket)) {
+        const double bb = reduce_partials(partials, 0, sh);
+        const double rr = reduce_partials(partials, 1, sh);
+        if (threadIdx.x == 0) {
+            sc->bb = bb;
+            sc->rr = rr;
+            sc->tol = sc->rtol * sqrt(bb);
+            sc->it = 0;
+            if (bb == 0.0) sc->done = DONE_ZERO_RHS;
+            else if (sqrt(rr) <= sc->tol) sc->done = DONE_CONVERGED;
+            else if (sc->maxit == 0) sc->done = DONE_MAXIT;
+            if (sc->plain) sc->rho = rr;
+            sc->ticket = 0;
+        }
+    }
+}
+
+// x += alpha p ; r -= alpha q ; ||r||^2 ; convergence test; (plain CG) beta = rr'/rr
+__global__ __launch_bounds__(kThreads) void k_update_xr(int n, double *__restrict__ x,
+                                                         double *__restrict__ r,
+                                                         const double *__restrict__ p,
+                                                         const double *__restrict__ q,
+                                                         double *__restrict__ partials,
+                                                         PcgScalars *sc, int nxcd) {
+    if (sc->done) return;
+    __shared__ double sh[kThreads / 64];
+    const double alpha = sc->alpha;
+    const int lb = xcd_block(blockIdx.x, gridDim.x, nxcd);
+    const int64_t per = ((int64_t)n + gridDim.x - 1) / gridDim.x;
+    const int i0 = (int)min<int64_t>(n, per * lb), i1 = (int)min<int64_t>(n, per * (lb + 1));
+    double pr = 0.0;
+    for (int i = i0 + threadIdx.x; i < i1; i += kThreads) {
+        x[i] = fma(alpha, p[i], x[i]);
+        const double ri = fma(-alpha, q[i], r[i]);
+        r[i] = ri;
+        pr = fma(ri, ri, pr);
+    }
+    double bs = block_sum(pr, sh);
+    if (finish_partials(partials, 1, &bs, &sc->ticket)) {
+        const double rr = reduce_partials(partials, 0, sh);
+        if (threadIdx.x == 0) {
+            sc->rr = rr;
+            sc->it += 1;
+            if (sqrt(rr) <= sc->tol) sc->done = DONE_CONVERGED;
+            else if (sc->it >= sc->maxit) sc->done = DONE_MAXIT;
+            else if (sc->plain) {
+                sc->beta = rr / sc->rho;
+                sc->rho = rr;
+            }
+            sc->ticket = 0;
+        }
+    }
+}
+
+// p = z + beta p   (first = 1: p = z)
+__global__ __launch_bounds__(kThreads) void k_update_p(int n, double *__restrict__ p,
+                                                        const double *__restrict__ z,
+                                                        const PcgScalars *sc, int first, int nxcd) {
+    if (sc->done) return;
+    const double beta = first ? 0.0 : sc->beta;
+    const int lb = xcd_block(blockIdx.x, gridDim.x, nxcd);
+    const int64_t per = ((int64_t)n + gridDim.x - 1) / gridDim.x;
+    const int i0 = (int)min<int64_t>(n, per * lb), i1 = (int)min<int64_t>(n, per * (lb + 1));
+    if (first)
+        for (int i = i0 + threadIdx.x; i < i1; i += kThreads) p[i] = z[i];
+    else
+        for (int i = i0 + threadIdx.x; i < i1; i += kThreads) p[i] = fma(beta, p[i], z[i]);
+}
+
+__global__ void k_zero(int n, double *__restrict__ v) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) v[i] = 0.0;
+}
+
+__global__ void k_set_scalars(PcgScalars *sc, double rtol, int maxit, int plain) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        PcgScalars s{};
+        s.rtol = rtol;
+        s.maxit = maxit;
+        s.plain = plain;
+        *sc = s;
+    }
+}
+
+// true residual partials: ||b - Ax||^2 with q = A x
+__global__ __launch_bounds__(kThreads) void k_resid_norm(int n, const double *__restrict__ b,
+                                                          const double *__restrict__ q,
+                                                          double *__restrict__ partials,
+                                                          PcgScalars *sc, double *out) {
+    __shared__ double sh[kThreads / 64];
+    const int64_t per = ((int64_t)n + gridDim.x - 1) / gridDim.x;
+    const int i0 = (int)min<int64_t>(n, per * blockIdx.x), i1 = (int)min<int64_t>(n, per * (blockIdx.x + 1));
+    double pr = 0.0;
+    for (int i = i0 + threadIdx.x; i < i1; i += kThreads) {
+        const double d = b[i] - q[i];
+        pr = fma(d, d, pr);
+    }
+    double bs = block_sum(pr, sh);
+    if (finish_partials(partials, 1, &bs, &sc->ticket)) {
+        const double t = reduce_partials(partials, 0, sh);
+        if (threadIdx.x == 0) {
+            *out = t;
+            sc->ticket = 0;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------------------
+static int group_size_for(double avg_nnz) {
+    // miniwarp size from the average row length (Sec. 3), capped at one wavefront
+    if (avg_nnz > 40) return 64;
+    if (avg_nnz > 20) return 32;
+    if (avg_nnz > 10) return 16;
+    if (avg_nnz > 5) return 8;
+    return 4;
+}
+
+static int blocks_for_rows(int n, int gs, const DeviceInfo &di) {
+    const int64_t rows_per_iter = kThreads / gs;
+    int64_t want = (n + rows_per_iter - 1) / rows_per_iter;
+    int64_t cap = (int64_t)di.num_cus * 8;
+    int64_t b = want < cap ? want : cap;
+    return (int)(b < 1 ? 1 : b);
+}
+
+static int blocks_for_vec(int n, const DeviceInfo &di) {
+    int64_t want = ((int64_t)n + kThreads * 4 - 1) / (kThreads * 4);
+    int64_t cap = (int64_t)di.num_cus * 8;
+    int64_t b = want < cap ? want : cap;
+    return (int)(b < 1 ? 1 : b);
+}
+
+struct Csr {
+    int n = 0;
+    int64_t nnz = 0;
+    const int32_t *rp = nullptr, *ci = nullptr;
+    const void *val = nullptr;
+    bool f32 = false;
+};
+
+template <int GS, typename VT>
+static void launch_spmv_t(const Csr &A, const double *x, double *y, const double *w, double *partials,
+                          PcgScalars *sc, int fin, int nb, int nxcd, hipStream_t s) {
+    if (w)
+        hipLaunchKernelGGL((k_spmv<GS, VT, true>), dim3(nb), dim3(kThreads), 0, s, A.n, A.rp, A.ci,
+                           (const VT *)A.val, x, y, w, partials, sc, fin, nxcd);
+    else
+        hipLaunchKernelGGL((k_spmv<GS, VT, false>), dim3(nb), dim3(kThreads), 0, s, A.n, A.rp, A.ci,
+                           (const VT *)A.val, x, y, w, partials, sc, fin, nxcd);
+}
+
+template <typename VT>
+static void launch_spmv_v(const Csr &A, int gs, const double *x, double *y, const double *w,
+                          double *partials, PcgScalars *sc, int fin, int nb, int nxcd, hipStream_t s) {
+    switch (gs) {
+        case 4: launch_spmv_t<4, VT>(A, x, y, w, partials, sc, fin, nb, nxcd, s); break;
+        case 8: launch_spmv_t<8, VT>(A, x, y, w, partials, sc, fin, nb, nxcd, s); break;
+        case 16: launch_spmv_t<16, VT>(A, x, y, w, partials, sc, fin, nb, nxcd, s); break;
+        case 32: launch_spmv_t<32, VT>(A, x, y, w, partials, sc, fin, nb, nxcd, s); break;
+        default: launch_spmv_t<64, VT>(A, x, y, w, partials, sc, fin, nb, nxcd, s); break;
+    }
+}
+
+// y = A x (optionally fused dot y.w finalised into sc); returns the launch's block count
+static void spmv(const char *name, const Csr &A, const double *x, double *y, const double *w,
+                 double *partials, PcgScalars *sc, int fin, const DeviceInfo &di, hipStream_t s) {
+    const double avg = A.n ? (double)A.nnz / A.n : 0.0;
+    const int gs = group_size_for(avg);
+    const int nb = blocks_for_rows(A.n, gs, di);
+    ProfScope ps(name, s);
+    if (A.f32)
+        launch_spmv_v<float>(A, gs, x, y, w, partials, sc, fin, nb, di.num_xcds, s);
+    else
+        launch_spmv_v<double>(A, gs, x, y, w, partials, sc, fin, nb, di.num_xcds, s);
+}
+
+static int check_csr_arg(const afsai_csr *A, const char *who) {
+    if (!A) AFSAI_FAIL(AFSAI_ERR_INVALID_ARG, "%s: A is NULL", who);
+    if (A->n <= 0 || A->nnz < A->n) AFSAI_FAIL(AFSAI_ERR_INVALID_ARG, "%s: n = %d, nnz = %d", who, A->n, A->nnz);
+    if (!A->row_ptr || !A->col_idx || !A->val) AFSAI_FAIL(AFSAI_ERR_INVALID_ARG, "%s: null CSR array", who);
+    return AFSAI_OK;
+}
+
+static Csr csr_of(const afsai_csr *A) {
+    Csr c;
+    c.n = A->n;
+    c.nnz = A->nnz;
+    c.rp = A->row_ptr;
+    c.ci = A->col_idx;
+    c.val = A->val;
+    return c;
+}
+
+static Csr csr_g(const afsai_precond_s *P, bool transposed) {
+    Csr c;
+    c.n = P->n;
+    c.nnz = P->nnz_g;
+    c.rp = transposed ? P->gt_rp : P->g_rp;
+    c.ci = transposed ? P->gt_ci : P->g_ci;
+    c.val = transposed ? P->gt_val : P->g_val;
+    c.f32 = (P->g_prec == AFSAI_F32);
+    return c;
+}
+
+// partial-sum scratch: 2 slots x max blocks
+static size_t partial_elems(const DeviceInfo &di) { return (size_t)2 * di.num_cus * 8 + 64; }
+
+}  // namespace afsai
+
+using namespace afsai;
+
+extern "C" {
+
+int afsai_spmv(const afsai_csr *A, const double *x, double *y, void *stream) {
+    int rc = check_csr_arg(A, "afsai_spmv");
+    if (rc) return rc;
+    if (!x || !y) AFSAI_FAIL(AFSAI_ERR_INVALID_ARG, "afsai_spmv: null vector");
+    DeviceInfo di;
+    if ((rc = device_info(&di))) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    spmv("spmv_A", csr_of(A), x, y, nullptr, nullptr, nullptr, FIN_NONE, di, s);
+    AFSAI_HIP_TRY(hipGetLastError());
+    return AFSAI_OK;
+}
+
+int afsai_apply(afsai_precond P, const double *r, double *z, void *stream) {
+    if (!P || !r || !z) AFSAI_FAIL(AFSAI_ERR_INVALID_ARG, "afsai_apply: null argument");
+    if (r == z) AFSAI_FAIL(AFSAI_ERR_INVALID_ARG, "afsai_apply: r and z alias");
+    DeviceInfo di;
+    int rc = device_info(&di);
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    double *t = P->work;  // first n entries
+    spmv("spmv_G", csr_g(P, false), r, t, nullptr, nullptr, nullptr, FIN_NONE, di, s);
+    spmv("spmv_GT", csr_g(P, true), t, z, nullptr, nullptr, nullptr, FIN_NONE, di, s);
+    AFSAI_HIP_TRY(hipGetLastError());
+    return AFSAI_OK;
+}
+
+int pcg_solve(const afsai_csr *A, afsai_precond P, const double *b, double *x, double rtol, int32_t maxit,
+              void *stream, afsai_pcg_info *info) {
+    clear_error();
+    int rc = check_csr_arg(A, "pcg_solve");
+    if (rc) return rc;
+    if (!b || !x) AFSAI_FAIL(AFSAI_ERR_INVALID_ARG, "pcg_solve: null b or x");
+    if (!(rtol > 0.0) || maxit < 0) AFSAI_FAIL(AFSAI_ERR_INVALID_ARG, "pcg_solve: rtol = %g, maxit = %d", rtol, maxit);
+    if (P && P->n != A->n) AFSAI_FAIL(AFSAI_ERR_INVALID_ARG, "pcg_solve: preconditioner has n = %d, A has n = %d", P->n, A->n);
+    DeviceInfo di;
+    if ((rc = device_info(&di))) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    hipEvent_t t0, t1;
+    AFSAI_HIP_TRY(hipEventCreate(&t0));
+    AFSAI_HIP_TRY(hipEventCreate(&t1));
+    AFSAI_HIP_TRY(hipEventRecord(t0, s));
+
+    const int n = A->n;
+    const size_t np = partial_elems(di);
+    // workspace: r, z, p, q, t (n each), partials, scalars
+    const size_t need = (size_t)5 * n + np + 16;
+    double *ws = nullptr;
+    bool own_ws = false;
+    if (P && P->work_elems >= need) {
+        ws = P->work;
+    } else {
+        AFSAI_HIP_TRY(hipMalloc(&ws, need * sizeof(double)));
+        own_ws = true;
+    }
+    double *r = ws, *z = ws + n, *p = ws + 2 * (size_t)n, *q = ws + 3 * (size_t)n, *t = ws + 4 * (size_t)n;
+    double *partials = ws + 5 * (size_t)n;
+    PcgScalars *sc = (PcgScalars *)(partials + np);
+    PcgScalars *hsc = nullptr;
+    AFSAI_HIP_TRY(hipHostMalloc(&hsc, 2 * sizeof(PcgScalars), hipHostMallocDefault));
+
+    const Csr Am = csr_of(A);
+    const int nbv = blocks_for_vec(n, di);
+    const int plain = P ? 0 : 1;
+    hipLaunchKernelGGL(k_set_scalars, dim3(1), dim3(64), 0, s, sc, rtol, maxit, plain);
+    // r0 = b - A x0
+    spmv("spmv_A", Am, x, q, nullptr, nullptr, nullptr, FIN_NONE, di, s);
+    hipLaunchKernelGGL(k_init_residual, dim3(nbv), dim3(kThreads), 0, s, n, b, q, r, partials, sc);
+    // z0 = M^-1 r0, rho0 = r0.z0, p0 = z0
+    const double *zz = z;
+    if (P) {
+        const Csr Gm = csr_g(P, false), GTm = csr_g(P, true);
+        spmv("spmv_G", Gm, r, t, nullptr, nullptr, sc, FIN_NONE, di, s);
+        spmv("spmv_GT_dot", GTm, t, z, r, partials, sc, FIN_RHO0, di, s);
+    } else {
+        zz = r;
+    }
+    hipLaunchKernelGGL(k_update_p, dim3(nbv), dim3(kThreads), 0, s, n, p, zz, sc, 1, di.num_xcds);
+
+    auto enqueue_iteration = [&]() {
+        spmv("spmv_A_dot", Am, p, q, p, partials, sc, FIN_ALPHA, di, s);
+        {
+            ProfScope ps("update_xr", s);
+            hipLaunchKernelGGL(k_update_xr, dim3(nbv), dim3(kThreads), 0, s, n, x, r, p, q, partials, sc, di.num_xcds);
+        }
+        if (P) {
+            const Csr Gm = csr_g(P, false), GTm = csr_g(P, true);
+            spmv("spmv_G", Gm, r, t, nullptr, nullptr, sc, FIN_NONE, di, s);
+            spmv("spmv_GT_dot", GTm, t, z, r, partials, sc, FIN_BETA, di, s);
+        }
+        {
+            ProfScope ps("update_p", s);
+            hipLaunchKernelGGL(k_update_p, dim3(nbv), dim3(kThreads), 0, s, n, p, zz, sc, 0, di.num_xcds);
+        }
+    };
+
+    // chunks of iterations; the flag of chunk c is read while chunk c+1 is already queued
+    int enqueued = 0;
+    int chunk = 4;
+    hipEvent_t ev[2];
+    AFSAI_HIP_TRY(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
+    AFSAI_HIP_TRY(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
+    int c = 0;
+    bool finished = false;
+    // read the state after initialisation first (zero rhs, converged x0, maxit = 0)
+    AFSAI_HIP_TRY(hipMemcpyAsync(&hsc[1], sc, sizeof(PcgScalars), hipMemcpyDeviceToHost, s));
+    AFSAI_HIP_TRY(hipEventRecord(ev[1], s));
+    while (!finished) {
+        const int todo = enqueued < maxit ? (chunk < maxit - enqueued ? chunk : maxit - enqueued) : 0;
+        for (int k = 0; k < todo; ++k) enqueue_iteration();
+        enqueued += todo;
+        AFSAI_HIP_TRY(hipMemcpyAsync(&hsc[c & 1], sc, sizeof(PcgScalars), hipMemcpyDeviceToHost, s));
+        AFSAI_HIP_TRY(hipEventRecord(ev[c & 1], s));
+        // wait for the previous chunk's copy
+        AFSAI_HIP_TRY(hipEventSynchronize(ev[(c + 1) & 1]));
+        if (hsc[(c + 1) & 1].done != DONE_NO) finished = true;
+        if (todo == 0) {
+            AFSAI_HIP_TRY(hipEventSynchronize(ev[c & 1]));
+            finished = true;
+        }
+        ++c;
+        if (chunk < 64) chunk *= 2;
+    }
+    AFSAI_HIP_TRY(hipStreamSynchronize(s));
+    PcgScalars fin_s;
+    AFSAI_HIP_TRY(hipMemcpy(&fin_s, sc, sizeof(PcgScalars), hipMemcpyDeviceToHost));
+
+    int status = AFSAI_OK;
+    if (fin_s.done == DONE_ZERO_RHS) {
+        hipLaunchKernelGGL(k_zero, dim3(nbv), dim3(kThreads), 0, s, n, x);
+    }
+    double true_rr = 0.0;
+    if (fin_s.done != DONE_ZERO_RHS) {
+        // true residual ||b - A x||
+        spmv("spmv_A", Am, x, q, nullptr, nullptr, nullptr, FIN_NONE, di, s);
+        double *d_out = partials + np - 8;
+        hipLaunchKernelGGL(k_resid_norm, dim3(nbv), dim3(kThreads), 0, s, n, b, q, partials, sc, d_out);
+        AFSAI_HIP_TRY(hipMemcpyAsync(&true_rr, d_out, sizeof(double), hipMemcpyDeviceToHost, s));
+    }
+    AFSAI_HIP_TRY(hipEventRecord(t1, s));
+    AFSAI_HIP_TRY(hipStreamSynchronize(s));
+    AFSAI_HIP_TRY(hipGetLastError());
+    float ms = 0.f;
+    AFSAI_HIP_TRY(hipEventElapsedTime(&ms, t0, t1));
+    prof_flush();
+    if (fin_s.done == DONE_NOT_SPD) {
+        set_error("pcg_solve: p.Ap <= 0 at iteration %d (matrix or preconditioner not SPD)", fin_s.it + 1);
+        status = AFSAI_ERR_NOT_SPD;
+    } else if (fin_s.done == DONE_MAXIT || (fin_s.done == DONE_NO && maxit == 0)) {
+        set_error("pcg_solve: not converged in %d iterations", fin_s.it);
+        status = AFSAI_ERR_NOT_CONVERGED;
+    }
+    if (info) {
+        const double nb = sqrt(fin_s.bb);
+        info->iters = fin_s.it;
+        info->converged = (fin_s.done == DONE_CONVERGED || fin_s.done == DONE_ZERO_RHS) ? 1 : 0;
+        info->relres = nb > 0 ? sqrt(fin_s.rr) / nb : 0.0;
+        info->true_relres = nb > 0 ? sqrt(true_rr) / nb : 0.0;
+        info->ms = ms;
+    }
+    (void)hipEventDestroy(ev[0]);
+    (void)hipEventDestroy(ev[1]);
+    (void)hipEventDestroy(t0);
+    (void)hipEventDestroy(t1);
+    (void)hipHostFree(hsc);
+    if (own_ws) (void)hipFree(ws);
+    return status;
+}
+
+}  // extern "C"

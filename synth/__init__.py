@@ -185,6 +185,25 @@ def random_spd_dense(n: int, seed: int, cond_scale: float = 1.0) -> np.ndarray:
     return 0.5 * (a + a.T)
 
 
+def random_sparse_spd(n: int, per_row: int, seed: int) -> CSR:
+    """Symmetric matrix with about 2*per_row random off-diagonal entries per row, values
+    U(-1, 1), made SPD by strict diagonal dominance (diagonal = 1 + sum of |off-diagonals|).
+    Rows reach columns all over the matrix, so a pattern's candidate set is large."""
+    import scipy.sparse as sp
+
+    k = n * per_row
+    u = raw_u64(seed, 21, 2 * k)
+    rows = (u[:k] % np.uint64(n)).astype(np.int64)
+    cols = (u[k:] % np.uint64(n)).astype(np.int64)
+    vals = uniform(seed, 22, k)
+    keep = rows != cols
+    m = sp.coo_matrix((vals[keep], (rows[keep], cols[keep])), shape=(n, n)).tocsr()
+    m.sum_duplicates()
+    m = (m + m.T).tocsr()
+    m = m + sp.diags(1.0 + np.asarray(abs(m).sum(axis=1)).ravel())
+    return CSR.from_scipy(m)
+
+
 @dataclass
 class Problem:
     """One linear system A x = b with its aFSAI parameters."""

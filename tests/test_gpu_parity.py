@@ -1,0 +1,326 @@
+"""GPU parity: the HIP library (through its C ABI) against the FP64 CPU oracle.
+
+Bars (from the method's arithmetic):
+  * patterns of G: identical (the selection is an integer decision; both sides use the same
+    tie band, so rounding noise in the gradient cannot flip it);
+  * values of G: within 1e-10 relative per row (infinity norm); the Cholesky factorisation
+    and solve follow the same rounding sequence as the oracle, so they are expected to agree
+    bit for bit and the fraction of bitwise-equal values is also checked;
+  * psi, steps and stop reasons per row: identical values / within 1e-12 relative;
+  * PCG: the same iteration count and the solution within 1e-10 relative (FP64 G); with FP32
+    storage of G: converged to the same rtol, iteration count within 2, and
+    ||x - x_oracle|| / ||x_oracle|| <= 1e-6.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+G_RTOL = 1e-10
+X_RTOL = 1e-10
+
+
+@pytest.fixture(scope="module")
+def af():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a visible MI355X")
+    import paper_2010_14175_amd as af
+
+    af.lib()
+    return af
+
+
+def _dev(af, A):
+    return af.DeviceCSR.from_host(A)
+
+
+def _vec(x):
+    import torch
+
+    return torch.from_numpy(np.ascontiguousarray(x, np.float64)).cuda()
+
+
+def _gpu_factor(af, P):
+    rp, ci, va = P.export()
+    return rp.cpu().numpy(), ci.cpu().numpy(), va.cpu().numpy()
+
+
+def compare_factor(af, A, kmax, s, eps, g_prec=0, rows=None):
+    """Runs the GPU setup and the oracle; returns statistics; asserts the bars."""
+    dA = _dev(af, A)
+    P = af.setup(dA, kmax, s, eps, g_prec=g_prec)
+    rp, ci, va = _gpu_factor(af, P)
+    psi, steps, reason = (t.cpu().numpy() for t in P.export_rows())
+    info = P.info()
+    if rows is None:
+        R = oracle.setup_rows(A, kmax, s, eps)
+        rows = np.arange(A.n)
+    else:
+        R = oracle.setup_rows(A, kmax, s, eps, rows=rows)
+    nbit = 0
+    ntot = 0
+    for q, i in enumerate(rows):
+        m = R.m[q]
+        gcols = ci[rp[i]:rp[i + 1]]
+        gvals = va[rp[i]:rp[i + 1]]
+        assert rp[i + 1] - rp[i] == m, f"row {i}: pattern size {rp[i + 1] - rp[i]} vs oracle {m}"
+        np.testing.assert_array_equal(gcols, R.cols[q, :m], err_msg=f"row {i} pattern")
+        ov = R.vals[q, :m]
+        if g_prec == 0:
+            err = np.max(np.abs(gvals - ov)) / np.max(np.abs(ov))
+            assert err <= G_RTOL, f"row {i}: relative error {err:.3e}"
+            nbit += int(np.sum(gvals.view(np.int64) == ov.view(np.int64)))
+        else:
+            np.testing.assert_array_equal(gvals.astype(np.float32), ov.astype(np.float32))
+        ntot += m
+        k = R.steps[q]
+        assert steps[i] == k and reason[i] == R.reason[q], f"row {i}: steps/reason"
+        assert abs(psi[i] - R.psi[q, k]) <= 1e-12 * abs(R.psi[q, k])
+    return {"P": P, "dA": dA, "info": info, "bitwise": nbit / max(1, ntot), "nnz": ntot}
+
+
+# --------------------------------------------------------------------------------------
+# setup parity
+# --------------------------------------------------------------------------------------
+def test_setup_poisson20(af):
+    """20^3 7-point Laplacian, k_max = 5, s = 1, eps = 1e-2 (nnz(G) = 47,985 exactly)."""
+    Pb = synth.poisson7(20)
+    r = compare_factor(af, Pb.A, 5, 1, 1e-2)
+    assert r["info"].nnz_g == 47985
+    assert r["bitwise"] == 1.0, r["bitwise"]
+
+
+@pytest.mark.parametrize("case", ["tridiag3_k1", "tridiag3_k2", "dense8_full", "diag", "one", "two",
+                                  "kmax0", "poisson_ragged", "aniso", "lognormal7"])
+def test_setup_small_cases(af, case):
+    if case.startswith("tridiag3"):
+        A = synth.CSR.from_dense(np.array([[4.0, 1, 0], [1, 4, 1], [0, 1, 4]]))
+        r = compare_factor(af, A, 1 if case.endswith("k1") else 2, 1, 0.0)
+    elif case == "dense8_full":
+        A = synth.CSR.from_dense(synth.random_spd_dense(8, 3))
+        r = compare_factor(af, A, 7, 1, 0.0)
+        G = np.zeros((8, 8))
+        rp, ci, va = _gpu_factor(af, r["P"])
+        for i in range(8):
+            G[i, ci[rp[i]:rp[i + 1]]] = va[rp[i]:rp[i + 1]]
+        a = A.to_scipy().toarray()
+        np.testing.assert_allclose(G @ a @ G.T, np.eye(8), atol=1e-12)
+    elif case == "diag":
+        A = synth.CSR.from_dense(np.diag(synth.uniform(5, 3, 37, 0.5, 9.0)))
+        compare_factor(af, A, 4, 2, 1e-2)
+    elif case == "one":
+        A = synth.CSR.from_dense(np.array([[2.5]]))
+        compare_factor(af, A, 3, 1, 1e-2)
+    elif case == "two":
+        A = synth.CSR.from_dense(np.array([[2.0, -1.0], [-1.0, 2.0]]))
+        compare_factor(af, A, 3, 2, 0.0)
+    elif case == "kmax0":
+        A = synth.elast27(4, 1.0, 3)
+        compare_factor(af, A, 0, 1, 1e-2)
+    elif case == "poisson_ragged":
+        A = synth.lap7(13, 7, 5)
+        compare_factor(af, A, 6, 2, 1e-2)
+    elif case == "aniso":
+        A = synth.lap7(11, 9, 7, (1.0, 1.0, 500.0))
+        compare_factor(af, A, 5, 1, 1e-2)
+    elif case == "lognormal7":
+        A = synth.lap7_lognormal(12, 10, 9, 1.0, 4)
+        compare_factor(af, A, 5, 2, 1e-2)
+
+
+def test_setup_elasticity_reduced(af):
+    """27-point 3-dof heterogeneous operator at 12^3 nodes (5,184 rows), k_max = 10, s = 2."""
+    A = synth.elast27(12, 1.0, 2)
+    r = compare_factor(af, A, 10, 2, 1e-2)
+    assert r["bitwise"] > 0.999
+
+
+def test_setup_elasticity_24(af):
+    """24^3 nodes (41,472 rows): the reduced form of the 64^3 workload, every row checked."""
+    A = synth.elast27(24, 1.0, 2)
+    r = compare_factor(af, A, 10, 2, 1e-2)
+    assert r["bitwise"] > 0.999
+
+
+def test_setup_large_pattern(af):
+    """k_max = 15, s = 3 (46 entries per row, the 150^3 workload's parameters) on a small grid,
+    sigma = 2."""
+    A = synth.elast27(7, 2.0, 5)
+    compare_factor(af, A, 15, 3, 1e-2)
+
+
+def test_setup_overflow_retry(af):
+    """Random sparse SPD rows reaching all over the matrix, k_max*s = 63: patterns touch more
+    candidate columns than the first on-chip table holds; those rows are redone with a larger
+    table and must still match the oracle."""
+    A = synth.random_sparse_spd(4000, 60, 8)
+    rows = np.concatenate([np.arange(0, 4000, 97), np.arange(3990, 4000)]).astype(np.int32)
+    r = compare_factor(af, A, 21, 3, 0.0, rows=rows)
+    assert r["info"].rows_retried > 0
+
+
+def test_setup_fp32_storage(af):
+    A = synth.elast27(10, 1.0, 2)
+    compare_factor(af, A, 10, 2, 1e-2, g_prec=1)
+
+
+def test_setup_deterministic(af):
+    A = synth.elast27(10, 1.0, 6)
+    dA = _dev(af, A)
+    P1 = af.setup(dA, 10, 2, 1e-2)
+    P2 = af.setup(dA, 10, 2, 1e-2)
+    for a, b in zip(_gpu_factor(af, P1), _gpu_factor(af, P2)):
+        np.testing.assert_array_equal(a, b)
+
+
+def test_setup_errors(af):
+    indef = synth.CSR.from_dense(np.array([[1.0, 2.0], [2.0, 1.0]]))
+    with pytest.raises(af.AfsaiError) as e:
+        af.setup(_dev(af, indef), 1, 1, 0.0)
+    assert e.value.code == af.ERR_NOT_SPD
+    negd = synth.CSR.from_dense(np.array([[1.0, 0.0], [0.0, -1.0]]))
+    with pytest.raises(af.AfsaiError) as e:
+        af.setup(_dev(af, negd), 1, 1, 0.0)
+    assert e.value.code == af.ERR_NOT_SPD
+    nodiag = synth.CSR(np.array([0, 1, 2], np.int32), np.array([1, 0], np.int32), np.array([1.0, 1.0]))
+    with pytest.raises(af.AfsaiError) as e:
+        af.setup(_dev(af, nodiag), 1, 1, 0.0)
+    assert e.value.code == af.ERR_BAD_MATRIX
+    unsorted = synth.CSR(np.array([0, 2, 4], np.int32), np.array([1, 0, 0, 1], np.int32), np.array([1.0, 4, 4, 1]))
+    with pytest.raises(af.AfsaiError) as e:
+        af.setup(_dev(af, unsorted), 1, 1, 0.0, validate=True)
+    assert e.value.code == af.ERR_BAD_MATRIX
+    asym = synth.CSR.from_dense(np.array([[4.0, 1.0], [1.5, 4.0]]))
+    with pytest.raises(af.AfsaiError) as e:
+        af.setup(_dev(af, asym), 1, 1, 0.0, validate=True)
+    assert e.value.code == af.ERR_BAD_MATRIX
+    ok = synth.lap7(5)
+    P = af.setup(_dev(af, ok), 3, 1, 1e-2, validate=True)
+    assert P.info().nnz_g > 0
+
+
+# --------------------------------------------------------------------------------------
+# apply / SpMV parity
+# --------------------------------------------------------------------------------------
+def _import_oracle_G(af, G, g_prec=0):
+    return af.import_factor(af.DeviceCSR.from_host(G), g_prec=g_prec)
+
+
+@pytest.mark.parametrize("make", [lambda: synth.lap7(17, 9, 5), lambda: synth.elast27(9, 1.0, 2)])
+def test_spmv_and_apply(af, make):
+    A = make()
+    G = oracle.setup(A, 6, 2, 1e-2)
+    r = synth.uniform(3, 4, A.n)
+    y = af.spmv(_dev(af, A), _vec(r)).cpu().numpy()
+    np.testing.assert_allclose(y, oracle.spmv(A, r), rtol=1e-13, atol=1e-13 * np.abs(y).max())
+    P = _import_oracle_G(af, G)
+    z = P.apply(_vec(r)).cpu().numpy()
+    zo = oracle.apply(G, r)
+    np.testing.assert_allclose(z, zo, rtol=1e-12, atol=1e-13 * np.abs(zo).max())
+
+
+# --------------------------------------------------------------------------------------
+# PCG parity
+# --------------------------------------------------------------------------------------
+def _pcg_pair(af, Pb, kmax, s, eps=1e-2, g_prec=0, maxit=None):
+    dA = _dev(af, Pb.A)
+    P = af.setup(dA, kmax, s, eps, g_prec=g_prec)
+    x, info = af.pcg_solve(dA, P, _vec(Pb.b), rtol=Pb.rtol, maxit=maxit)
+    G = oracle.setup(Pb.A, kmax, s, eps)
+    ro = oracle.pcg(Pb.A, G, Pb.b, Pb.rtol, maxit=maxit)
+    return x.cpu().numpy(), info, ro
+
+
+def test_pcg_poisson20(af):
+    Pb = synth.poisson7(20)
+    x, info, ro = _pcg_pair(af, Pb, 5, 1)
+    assert info.converged and info.iters == ro.iters, (info.iters, ro.iters)
+    assert np.linalg.norm(x - ro.x) <= X_RTOL * np.linalg.norm(ro.x)
+    assert info.true_relres <= 1.1e-8
+
+
+def test_pcg_elasticity_reduced(af):
+    Pb = synth.elasticity27(16)
+    x, info, ro = _pcg_pair(af, Pb, 10, 2)
+    assert info.converged and info.iters == ro.iters, (info.iters, ro.iters)
+    assert np.linalg.norm(x - ro.x) <= X_RTOL * np.linalg.norm(ro.x)
+
+
+def test_pcg_fp32_g(af):
+    Pb = synth.elasticity27(16)
+    x, info, ro = _pcg_pair(af, Pb, 10, 2, g_prec=1)
+    assert info.converged and abs(info.iters - ro.iters) <= 2, (info.iters, ro.iters)
+    assert np.linalg.norm(x - ro.x) <= 1e-6 * np.linalg.norm(ro.x)
+    assert info.true_relres <= 1.5e-8
+
+
+def test_pcg_plain_cg_and_jacobi(af):
+    Pb = synth.poisson7(14)
+    dA = _dev(af, Pb.A)
+    x, info = af.pcg_solve(dA, None, _vec(Pb.b), rtol=1e-8)
+    ro = oracle.pcg(Pb.A, None, Pb.b, 1e-8)
+    assert info.iters == ro.iters
+    assert np.linalg.norm(x.cpu().numpy() - ro.x) <= X_RTOL * np.linalg.norm(ro.x)
+    xj, ij, roj = _pcg_pair(af, Pb, 0, 1)
+    assert ij.iters == roj.iters
+    assert np.linalg.norm(xj - roj.x) <= X_RTOL * np.linalg.norm(roj.x)
+
+
+def test_pcg_edge_cases(af):
+    import torch
+
+    Pb = synth.poisson7(9)
+    dA = _dev(af, Pb.A)
+    P = af.setup(dA, 4, 1, 1e-2)
+    # zero right-hand side
+    x, info = af.pcg_solve(dA, P, torch.zeros(Pb.n, dtype=torch.float64, device="cuda"),
+                           x=torch.ones(Pb.n, dtype=torch.float64, device="cuda"))
+    assert info.iters == 0 and info.converged and float(x.abs().max()) == 0.0
+    # maxit reached, then resume from the returned x
+    G = oracle.setup(Pb.A, 4, 1, 1e-2)
+    x5, info5 = af.pcg_solve(dA, P, _vec(Pb.b), maxit=5)
+    ro5 = oracle.pcg(Pb.A, G, Pb.b, 1e-8, maxit=5)
+    assert info5.status == af.ERR_NOT_CONVERGED and info5.iters == 5 and not info5.converged
+    assert np.linalg.norm(x5.cpu().numpy() - ro5.x) <= X_RTOL * np.linalg.norm(ro5.x)
+    x_r, info_r = af.pcg_solve(dA, P, _vec(Pb.b), x=x5.clone())
+    ro_r = oracle.pcg(Pb.A, G, Pb.b, 1e-8, x0=ro5.x)
+    assert info_r.converged and info_r.iters == ro_r.iters
+    # maxit = 0
+    x0, info0 = af.pcg_solve(dA, P, _vec(Pb.b), maxit=0)
+    assert info0.status == af.ERR_NOT_CONVERGED and info0.iters == 0
+    # an indefinite matrix is reported (p.Ap <= 0) by plain CG
+    ind = synth.CSR.from_dense(np.diag([1.0, -1.0, 2.0]))
+    x, info = af.pcg_solve(_dev(af, ind), None, _vec([1.0, 1.0, 1.0]), raise_on_error=False)
+    assert info.status == af.ERR_NOT_SPD
+
+
+def test_pcg_deterministic(af):
+    Pb = synth.elasticity27(12)
+    dA = _dev(af, Pb.A)
+    P = af.setup(dA, 10, 2, 1e-2)
+    x1, _ = af.pcg_solve(dA, P, _vec(Pb.b))
+    x2, _ = af.pcg_solve(dA, P, _vec(Pb.b))
+    assert bool((x1 == x2).all())
+
+
+# --------------------------------------------------------------------------------------
+# full size (64^3 nodes, 786,432 rows): the launch configuration of the benchmark
+# --------------------------------------------------------------------------------------
+def test_full_size_elasticity64_sampled(af):
+    """Every launch at the benchmark's full size; the oracle checks a sample of 3,000 rows
+    one by one (rows are independent), and the solve is checked by its true residual."""
+    Pb = synth.elasticity27(64)
+    rows = np.unique(np.concatenate([np.arange(0, 40), np.arange(Pb.n - 40, Pb.n),
+                                     synth.raw_u64(64, 5, 2920).astype(np.int64) % Pb.n])).astype(np.int32)
+    r = compare_factor(af, Pb.A, 10, 2, 1e-2, rows=rows)
+    assert r["bitwise"] > 0.999
+    dA, P = r["dA"], r["P"]
+    x, info = af.pcg_solve(dA, P, _vec(Pb.b), rtol=1e-8)
+    assert info.converged and info.true_relres <= 1.1e-8
+    err = np.linalg.norm(x.cpu().numpy() - Pb.x_true) / np.linalg.norm(Pb.x_true)
+    assert err < 1e-4
