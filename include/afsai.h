@@ -180,6 +180,24 @@ void afsai_destroy(afsai_precond P);
 const char *afsai_last_error(void);
 
 /*
+ * afsai_set_option -- process-wide tuning knobs (0 restores the automatic choice):
+ *   AFSAI_OPT_SETUP_FORM_LDS  1: always use the LDS form of the per-row setup kernel (the
+ *                             register form is otherwise used for patterns of at most 32
+ *                             entries and s <= 4; both give identical G)
+ *   AFSAI_OPT_SETUP_TABLE     slots of the first on-chip candidate table (power of two,
+ *                             128..1024)
+ *   AFSAI_OPT_SPMV_GROUP      lanes per row of the CSR products (4, 8, 16, 32 or 64)
+ *   AFSAI_OPT_SPMV_UNROLL     independent loads per lane per round in the CSR products (1, 2, 4, 8)
+ * Returns AFSAI_ERR_INVALID_ARG for an unknown option or value.  Not thread safe against
+ * concurrent calls of the library.
+ */
+#define AFSAI_OPT_SETUP_FORM_LDS 1
+#define AFSAI_OPT_SETUP_TABLE 2
+#define AFSAI_OPT_SPMV_GROUP 3
+#define AFSAI_OPT_SPMV_UNROLL 4
+int afsai_set_option(int32_t option, int64_t value);
+
+/*
  * Kernel timing: with profiling on, the library brackets every kernel launch with HIP events
  * on the launch stream and accumulates, per kernel name, the number of launches and the total
  * event-measured duration.  Off by default; enabling it adds event overhead.

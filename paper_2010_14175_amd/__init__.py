@@ -29,8 +29,9 @@ STOP_KMAX, STOP_EPS, STOP_NOCAND = 0, 1, 2
 
 # every symbol the C header declares
 EXPORTS = ("afsai_setup", "afsai_apply", "pcg_solve", "afsai_spmv", "afsai_get_setup_info", "afsai_export",
-           "afsai_export_rows", "afsai_import", "afsai_destroy", "afsai_last_error", "afsai_profile_enable",
-           "afsai_profile_read")
+           "afsai_export_rows", "afsai_import", "afsai_destroy", "afsai_last_error", "afsai_set_option",
+           "afsai_profile_enable", "afsai_profile_read")
+OPT_SETUP_FORM_LDS, OPT_SETUP_TABLE, OPT_SPMV_GROUP, OPT_SPMV_UNROLL = 1, 2, 3, 4
 
 
 class CsrStruct(ctypes.Structure):
@@ -88,6 +89,7 @@ def lib():
         L.afsai_destroy.argtypes = [vp]
         L.afsai_destroy.restype = None
         L.afsai_last_error.restype = ctypes.c_char_p
+        L.afsai_set_option.argtypes = [i32, ctypes.c_int64]
         L.afsai_profile_enable.argtypes = [i32]
         L.afsai_profile_read.argtypes = [P(KernelTimeStruct), i32, P(i32), i32]
         for name in EXPORTS:
@@ -274,6 +276,11 @@ def spmv(A: DeviceCSR, x, y=None, stream=None):
     st = A.struct
     _check(lib().afsai_spmv(ctypes.byref(st), _ptr(x), _ptr(y), _stream(stream)), "afsai_spmv")
     return y
+
+
+def set_option(option: int, value: int):
+    """Process-wide tuning knob (``afsai_set_option``); 0 restores the automatic choice."""
+    _check(lib().afsai_set_option(int(option), int(value)), "afsai_set_option")
 
 
 def profile_enable(on: bool = True):

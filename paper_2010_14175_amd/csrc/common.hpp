@@ -35,6 +35,9 @@ void clear_error();
         return (code);                                                                       \
     } while (0)
 
+// value of an afsai_set_option knob (0 = automatic)
+int64_t option(int id);
+
 // ---------------------------------------------------------------------------------------
 // device properties (cached per device)
 // ---------------------------------------------------------------------------------------

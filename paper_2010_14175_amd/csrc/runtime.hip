@@ -24,6 +24,10 @@ void set_error(const char *fmt, ...) {
 
 void clear_error() { g_last_error.clear(); }
 
+static int64_t g_options[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+
+int64_t option(int id) { return (id > 0 && id < 8) ? g_options[id] : 0; }
+
 int device_info(DeviceInfo *out) {
     static std::mutex mu;
     static std::map<int, DeviceInfo> cache;
@@ -132,6 +136,21 @@ void prof_flush() {
 extern "C" {
 
 const char *afsai_last_error(void) { return afsai::g_last_error.c_str(); }
+
+int afsai_set_option(int32_t opt, int64_t value) {
+    auto pow2 = [](int64_t v) { return v > 0 && (v & (v - 1)) == 0; };
+    bool ok = false;
+    switch (opt) {
+        case AFSAI_OPT_SETUP_FORM_LDS: ok = (value == 0 || value == 1); break;
+        case AFSAI_OPT_SETUP_TABLE: ok = value == 0 || (pow2(value) && value >= 128 && value <= 1024); break;
+        case AFSAI_OPT_SPMV_GROUP: ok = value == 0 || (pow2(value) && value >= 4 && value <= 64); break;
+        case AFSAI_OPT_SPMV_UNROLL: ok = value == 0 || (pow2(value) && value <= 8); break;
+        default: ok = false;
+    }
+    if (!ok) AFSAI_FAIL(AFSAI_ERR_INVALID_ARG, "afsai_set_option: bad option %d / value %lld", opt, (long long)value);
+    afsai::g_options[opt] = value;
+    return AFSAI_OK;
+}
 
 int afsai_profile_enable(int32_t on) {
     afsai::prof_flush();

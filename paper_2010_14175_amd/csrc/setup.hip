@@ -1,417 +1,16 @@
-// Adaptive FSAI setup on gfx950 (Sec. 2 method; Sec. 3 kernels: Kaporin gradient and
-// selection, systems gather, batched Cholesky), plus the assembly of G and G^T.
-//
-// One 64-lane wavefront owns one row i for all of its growth steps, so the pattern P_i, the
-// scaled row g_i, the candidate table and the dense block A[P_i,P_i] never leave LDS (the
-// paper's three kernels each wrote their results to memory between steps).  Per step:
-//
-//  1. product pass over the rows r in P_i: every stored entry a_rc with c <= i is looked up in
-//     an LDS open-addressing table.  Columns already in P_i were entered first, tagged with
-//     their position, and their entries fill A[P,P] (lower part, row r being the larger
-//     index).  Any other column is a candidate and accumulates v_c += a_rc g_r, which is
-//     (A g)_c by symmetry, the Kaporin gradient of eq. grapsi up to a positive factor.
-//  2. selection: the largest |v_c| over the candidates, then s rounds of "largest |v|, ties
-//     within the relative band tie_rtol go to the smallest column" with 64-lane reductions.
-//  3. gather: A[P,P] is re-indexed to the enlarged pattern and only the s new rows are read.
-//  4. Cholesky A[P,P] = L L^T and g = L^-T e_m (eq. DensSys with the scaling of eq.
-//     diagScal), psi = L_mm^2, all in FP64 in LDS.
-//  5. exit test psi / psi_0 <= eps (eq. exit_crit).
-//
-// The Cholesky factorisation and the back substitution use the same operation order as a
-// column-by-column textbook factorisation with products and sums rounded separately (no
-// contraction), so G is reproducible bit for bit.  The gradient accumulation uses LDS atomics
-// (order not fixed); it only ranks candidates, and the tie band absorbs rounding noise.
-//
-// Rows are taken from per-XCD work counters (dynamic scheduling inside one contiguous range
-// of rows per XCD).  A row whose candidate set overflows its LDS table is reported and redone
-// by a second launch with a table large enough for any pattern.
+// Host side of the adaptive FSAI setup: row statistics and validation, the launches of the fused
+// per-row kernel (rows.hpp), and the assembly of G and G^T as CSR from its padded per-row
+// results.  Rows are taken from per-XCD work counters (dynamic scheduling inside one
+// contiguous range of rows per XCD).  A row whose candidate set overflows its on-chip table is
+// reported and redone by a second launch with a table large enough for any pattern.
 #include <cmath>
 #include <vector>
 
 #include "common.hpp"
 
-#pragma clang fp contract(off)
+#include "rows.hpp"
 
 namespace afsai {
-
-constexpr uint32_t kEmpty = 0xFFFFFFFFu;
-constexpr uint32_t kPBit = 0x80000000u;
-
-enum : int8_t { ROW_OK = 0, ROW_OVERFLOW = 1, ROW_BAD = 2, ROW_NOT_SPD = 3 };
-enum : int32_t { STOP_KMAX = 0, STOP_EPS = 1, STOP_NOCAND = 2 };
-
-__device__ __forceinline__ int tri(int p, int q) { return ((p * (p + 1)) >> 1) + q; }  // q <= p
-
-template <int CAP>
-__device__ __forceinline__ uint32_t hash0(uint32_t c) {
-    constexpr int B = __builtin_ctz(CAP);
-    return (c * 2654435761u) >> (32 - B);
-}
-
-// Finds column c in the table; inserts `ins` (c, possibly tagged) when absent and `insert` is
-// set.  Returns the slot, -1 if absent (lookup only) or -2 if the table is full.
-template <int CAP>
-__device__ __forceinline__ int table_find(uint32_t *hkey, uint32_t c, uint32_t ins, bool insert,
-                                          bool &tagged) {
-    uint32_t slot = hash0<CAP>(c);
-    for (int probe = 0; probe < CAP; ++probe) {
-        uint32_t k = __hip_atomic_load(&hkey[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-        if (k == kEmpty) {
-            if (!insert) return -1;
-            uint32_t old = atomicCAS(&hkey[slot], kEmpty, ins);
-            if (old == kEmpty) {
-                tagged = (ins & kPBit) != 0;
-                return (int)slot;
-            }
-            k = old;
-        }
-        if ((k & ~kPBit) == c) {
-            tagged = (k & kPBit) != 0;
-            return (int)slot;
-        }
-        slot = (slot + 1) & (CAP - 1);
-    }
-    return -2;
-}
-
-// position t of the concatenated entry e: largest t < cnt with off[t] <= e
-__device__ __forceinline__ int seg_of(const int32_t *off, int cnt, int e) {
-    int lo = 0, hi = cnt - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (off[mid] <= e) lo = mid; else hi = mid - 1;
-    }
-    return lo;
-}
-
-// Offsets of the concatenation of rows list[0..cnt) (cnt <= 64); returns the total length.
-__device__ __forceinline__ int stage_rows(const int32_t *__restrict__ rp, const int32_t *list, int cnt,
-                                          int32_t *off, int32_t *beg) {
-    const int lane = threadIdx.x;
-    int len = 0;
-    if (lane < cnt) {
-        const int r = list[lane];
-        const int b = rp[r];
-        len = rp[r + 1] - b;
-        beg[lane] = b;
-    }
-    const int incl = wave_incl_scan(len);
-    if (lane < cnt) off[lane] = incl - len;
-    const int total = __shfl(incl, cnt - 1, 64);
-    __syncthreads();
-    return total;
-}
-
-constexpr int kUnroll = 4;
-
-template <int MMAX, int CAP>
-__global__ __launch_bounds__(64) void k_afsai_rows(
-    int n, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci, const double *__restrict__ av,
-    int kmax, int s, double eps, double tau, const int32_t *__restrict__ list, int nlist,
-    int32_t *__restrict__ counters, int nxcd, int32_t *__restrict__ ell_col, double *__restrict__ ell_val,
-    int ldell, int32_t *__restrict__ m_out, double *__restrict__ psi_out, int32_t *__restrict__ steps_out,
-    int32_t *__restrict__ reason_out, int8_t *__restrict__ status_out, int32_t *__restrict__ ovf_count,
-    int32_t *__restrict__ ovf_list) {
-    constexpr int TRI = MMAX * (MMAX + 1) / 2;
-    __shared__ uint32_t hkey[CAP];
-    __shared__ double hval[CAP];
-    __shared__ double X[TRI];
-    __shared__ double Y[TRI];
-    __shared__ int32_t Pl[MMAX];      // pattern, ascending
-    __shared__ int32_t Pn[MMAX];      // enlarged pattern
-    __shared__ int32_t pslot[MMAX];   // table slot of each member of Pl
-    __shared__ int32_t nslot[MMAX];   // table slot of each member of Pn
-    __shared__ int32_t npos[MMAX];    // new position of old member t
-    __shared__ double gl[MMAX];       // scaled row on Pl
-    __shared__ int32_t off[64], beg[64];
-    __shared__ int32_t sel[64], selslot[64], selpos[64];
-    __shared__ int32_t s_row, s_flag;
-
-    const int lane = threadIdx.x;
-    const int x = blockIdx.x % nxcd;
-    const int64_t per = ((int64_t)nlist + nxcd - 1) / nxcd;
-    const int q0 = (int)min<int64_t>(nlist, per * x), q1 = (int)min<int64_t>(nlist, per * (x + 1));
-
-    for (;;) {
-        if (lane == 0) s_row = q0 + atomicAdd(&counters[x], 1);
-        __syncthreads();
-        const int q = s_row;
-        __syncthreads();
-        if (q >= q1) break;
-        const int i = list ? list[q] : q;
-
-        // ---- G_0 = I scaled: P = {i}, g = a_ii^-1/2, psi_0 = a_ii
-        const int a0 = rp[i], a1 = rp[i + 1];
-        double aii = 0.0;
-        bool found = false;
-        for (int e = a0 + lane; e < a1; e += 64)
-            if (ci[e] == i) {
-                aii = av[e];
-                found = true;
-            }
-        const unsigned long long bal = __ballot(found);
-        int8_t status = ROW_OK;
-        int m = 1, steps = 0;
-        int32_t reason = STOP_KMAX;
-        double psi = 0.0;
-        if (bal == 0ull) {
-            status = ROW_BAD;
-        } else {
-            aii = __shfl(aii, __ffsll((long long)bal) - 1, 64);
-            if (!(aii > 0.0) || !isfinite(aii)) status = ROW_NOT_SPD;
-        }
-        if (status == ROW_OK) {
-            if (lane == 0) {
-                Pl[0] = i;
-                gl[0] = 1.0 / sqrt(aii);
-            }
-            psi = aii;
-            __syncthreads();
-        }
-        const double psi0 = aii;
-
-        for (int k = 1; k <= kmax && status == ROW_OK; ++k) {
-            // ---- 1. product pass: gradient on candidates, A[P,P] from the rows of P
-            for (int j = lane; j < CAP; j += 64) {
-                hkey[j] = kEmpty;
-                hval[j] = 0.0;
-            }
-            const int ntri = (m * (m + 1)) >> 1;
-            for (int j = lane; j < ntri; j += 64) X[j] = 0.0;
-            if (lane == 0) s_flag = 0;
-            __syncthreads();
-            if (lane < m) {
-                bool tg;
-                const uint32_t c = (uint32_t)Pl[lane];
-                const int slot = table_find<CAP>(hkey, c, c | kPBit, true, tg);
-                pslot[lane] = slot;
-                if (slot >= 0) hval[slot] = (double)lane;  // position tag
-                else s_flag = 1;
-            }
-            const int total = stage_rows(rp, Pl, m, off, beg);
-            for (int base = 0; base < total; base += 64 * kUnroll) {
-                int cc[kUnroll], tt[kUnroll];
-                double vv[kUnroll];
-#pragma unroll
-                for (int u = 0; u < kUnroll; ++u) {
-                    const int e = base + u * 64 + lane;
-                    cc[u] = -1;
-                    tt[u] = 0;
-                    vv[u] = 0.0;
-                    if (e < total) {
-                        const int t = seg_of(off, m, e);
-                        const int idx = beg[t] + (e - off[t]);
-                        tt[u] = t;
-                        cc[u] = __builtin_nontemporal_load(&ci[idx]);
-                        vv[u] = __builtin_nontemporal_load(&av[idx]);
-                    }
-                }
-#pragma unroll
-                for (int u = 0; u < kUnroll; ++u) {
-                    const int c = cc[u];
-                    if (c >= 0 && c <= i) {
-                        bool tg = false;
-                        const int slot = table_find<CAP>(hkey, (uint32_t)c, (uint32_t)c, true, tg);
-                        if (slot < 0) {
-                            s_flag = 1;
-                        } else if (tg) {
-                            const int pc = (int)hval[slot];
-                            if (pc <= tt[u]) X[tri(tt[u], pc)] = vv[u];
-                        } else {
-                            __hip_atomic_fetch_add(&hval[slot], vv[u] * gl[tt[u]], __ATOMIC_RELAXED,
-                                                   __HIP_MEMORY_SCOPE_WORKGROUP);
-                        }
-                    }
-                }
-            }
-            __syncthreads();
-            if (s_flag) {
-                status = ROW_OVERFLOW;
-                break;
-            }
-
-            // ---- 2. selection (top-s of |v| over the candidates, tie band, smallest column)
-            double lmax = 0.0;
-            for (int j = lane; j < CAP; j += 64) {
-                const uint32_t kk = hkey[j];
-                if (kk != kEmpty && !(kk & kPBit)) lmax = fmax(lmax, fabs(hval[j]));
-            }
-            const double M = wave_max(lmax);
-            int ns = 0;
-            if (M > 0.0) {
-                const double thr = 0x1.0p-40 * M;
-                for (int round = 0; round < s; ++round) {
-                    double l = 0.0;
-                    for (int j = lane; j < CAP; j += 64) {
-                        const uint32_t kk = hkey[j];
-                        if (kk != kEmpty && !(kk & kPBit)) {
-                            const double a = fabs(hval[j]);
-                            if (a > thr) l = fmax(l, a);
-                        }
-                    }
-                    const double Mp = wave_max(l);
-                    if (!(Mp > 0.0)) break;
-                    const double band = (1.0 - tau) * Mp;
-                    uint32_t lb = kEmpty;
-                    for (int j = lane; j < CAP; j += 64) {
-                        const uint32_t kk = hkey[j];
-                        if (kk != kEmpty && !(kk & kPBit)) {
-                            const double a = fabs(hval[j]);
-                            if (a > thr && a >= band && kk < lb) lb = kk;
-                        }
-                    }
-                    const uint32_t js = wave_min(lb);
-                    for (int j = lane; j < CAP; j += 64)
-                        if (hkey[j] == js) {
-                            hkey[j] = js | kPBit;
-                            selslot[ns] = j;
-                        }
-                    if (lane == 0) sel[ns] = (int32_t)js;
-                    ++ns;
-                    __syncthreads();
-                }
-            }
-            if (ns == 0) {
-                reason = STOP_NOCAND;
-                break;
-            }
-
-            // ---- 3. enlarged pattern, positions, gather of A[Pn,Pn]
-            const int mn = m + ns;
-            if (lane < m) {
-                const int c = Pl[lane];
-                int add = 0;
-                for (int u = 0; u < ns; ++u) add += (sel[u] < c);
-                const int p = lane + add;
-                npos[lane] = p;
-                Pn[p] = c;
-                nslot[p] = pslot[lane];
-                hval[pslot[lane]] = (double)p;
-            } else if (lane < m + ns) {
-                const int u = lane - m;
-                const int c = sel[u];
-                int lo = 0, hi = m;  // number of old members below c
-                while (lo < hi) {
-                    const int mid = (lo + hi) >> 1;
-                    if (Pl[mid] < c) lo = mid + 1; else hi = mid;
-                }
-                int add = 0;
-                for (int v = 0; v < ns; ++v) add += (sel[v] < c);
-                const int p = lo + add;
-                selpos[u] = p;
-                Pn[p] = c;
-                nslot[p] = selslot[u];
-                hval[selslot[u]] = (double)p;
-            }
-            const int ntn = (mn * (mn + 1)) >> 1;
-            for (int j = lane; j < ntn; j += 64) Y[j] = 0.0;
-            __syncthreads();
-            {
-                const float invm = 1.0f / (float)m;
-                for (int e = lane; e < m * m; e += 64) {
-                    const int a = (int)(((float)e + 0.5f) * invm);
-                    const int b = e - a * m;
-                    if (b <= a) Y[tri(npos[a], npos[b])] = X[tri(a, b)];
-                }
-            }
-            const int tot2 = stage_rows(rp, sel, ns, off, beg);
-            for (int e = lane; e < tot2; e += 64) {
-                const int u = seg_of(off, ns, e);
-                const int idx = beg[u] + (e - off[u]);
-                const int c = ci[idx];
-                if (c <= i) {
-                    bool tg = false;
-                    const int slot = table_find<CAP>(hkey, (uint32_t)c, 0u, false, tg);
-                    if (slot >= 0 && tg) {
-                        const int pc = (int)hval[slot];
-                        const int pn = selpos[u];
-                        Y[pc <= pn ? tri(pn, pc) : tri(pc, pn)] = av[idx];
-                    }
-                }
-            }
-            __syncthreads();
-            if (lane < mn) {
-                Pl[lane] = Pn[lane];
-                pslot[lane] = nslot[lane];
-            }
-
-            // ---- 4. Cholesky A[P,P] = L L^T (right-looking; same rounding sequence as the
-            //         column-oriented textbook form) and g = L^-T e_m
-            bool spd = true;
-            for (int kk = 0; kk < mn; ++kk) {
-                const double d2 = Y[tri(kk, kk)];
-                if (!(d2 > 0.0) || !isfinite(d2)) {
-                    spd = false;
-                    break;
-                }
-                const double d = sqrt(d2);
-                const int R = mn - kk - 1;
-                __syncthreads();
-                if (lane < R) {
-                    const int r = kk + 1 + lane;
-                    Y[tri(r, kk)] = Y[tri(r, kk)] / d;
-                }
-                if (lane == 0) Y[tri(kk, kk)] = d;
-                __syncthreads();
-                if (R > 0) {
-                    const float invR = 1.0f / (float)R;
-                    for (int e = lane; e < R * R; e += 64) {
-                        const int tr = (int)(((float)e + 0.5f) * invR);
-                        const int tc = e - tr * R;
-                        if (tc <= tr) {
-                            const int r = kk + 1 + tr, c = kk + 1 + tc;
-                            Y[tri(r, c)] = Y[tri(r, c)] - Y[tri(r, kk)] * Y[tri(c, kk)];
-                        }
-                    }
-                }
-                __syncthreads();
-            }
-            if (!spd) {
-                status = ROW_NOT_SPD;
-                break;
-            }
-            double acc = 0.0, gx = 0.0;
-            for (int l = mn - 1; l >= 0; --l) {
-                const double Lll = Y[tri(l, l)];
-                const double accl = __shfl(acc, l, 64);
-                const double xl = (l == mn - 1) ? 1.0 / Lll : -(accl / Lll);
-                if (lane == l) gx = xl;
-                if (lane < l) acc = acc + Y[tri(l, lane)] * xl;
-            }
-            if (lane < mn) gl[lane] = gx;
-            const double lmm = Y[tri(mn - 1, mn - 1)];
-            psi = lmm * lmm;
-            m = mn;
-            steps = k;
-            __syncthreads();
-            // ---- 5. exit test (eq. exit_crit)
-            if (psi <= eps * psi0) {
-                reason = STOP_EPS;
-                break;
-            }
-        }
-
-        // ---- outputs
-        if (status == ROW_OK) {
-            if (lane < m) {
-                ell_col[(size_t)i * ldell + lane] = Pl[lane];
-                ell_val[(size_t)i * ldell + lane] = gl[lane];
-            }
-        }
-        if (lane == 0) {
-            m_out[i] = (status == ROW_OK) ? m : 0;
-            psi_out[i] = psi;
-            steps_out[i] = steps;
-            reason_out[i] = reason;
-            status_out[i] = status;
-            if (status == ROW_OVERFLOW) {
-                const int pos = atomicAdd(ovf_count, 1);
-                ovf_list[pos] = i;
-            }
-        }
-        __syncthreads();
-    }
-}
 
 // ---------------------------------------------------------------------------------------
 // row statistics (max row length) and optional structural / symmetry validation
@@ -420,28 +19,45 @@ struct ScanOut {
     int32_t maxlen;
     int32_t bad;       // structural problem found
     int32_t asym;      // asymmetric pair found
-    int32_t pad;
+    int32_t nodiag;    // rows without a diagonal entry
 };
 
+// max row length, diagonal of every row (binary search in the ascending row) and, when
+// validating, structure and exact symmetry
 __global__ void k_row_scan(int n, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
-                           const double *__restrict__ av, int validate, ScanOut *out) {
-    int lmax = 0;
+                           const double *__restrict__ av, int validate, double *__restrict__ diag, ScanOut *out) {
+    int lmax = 0, nodiag = 0;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
         const int a = rp[i], b = rp[i + 1];
         lmax = max(lmax, b - a);
+        {
+            int lo = a, hi = b - 1;
+            double d = 0.0;
+            bool found = false;
+            while (lo <= hi) {
+                const int mid = (lo + hi) >> 1;
+                const int cm = ci[mid];
+                if (cm == i) {
+                    d = av[mid];
+                    found = true;
+                    break;
+                }
+                if (cm < i) lo = mid + 1; else hi = mid - 1;
+            }
+            diag[i] = d;
+            nodiag += found ? 0 : 1;
+        }
         if (!validate) continue;
         if (b < a) {
             atomicOr(&out->bad, 1);
             continue;
         }
-        bool diag = false;
         for (int e = a; e < b; ++e) {
             const int c = ci[e];
             if (c < 0 || c >= n || (e > a && c <= ci[e - 1])) {
                 atomicOr(&out->bad, 1);
                 break;
             }
-            if (c == i) diag = true;
             // symmetry: a_ci must exist and equal a_ic bit for bit
             int lo = rp[c], hi = rp[c + 1] - 1;
             bool ok = false;
@@ -456,10 +72,13 @@ __global__ void k_row_scan(int n, const int32_t *__restrict__ rp, const int32_t 
             }
             if (!ok) atomicOr(&out->asym, 1);
         }
-        if (!diag) atomicOr(&out->bad, 1);
     }
     lmax = wave_max(lmax);
-    if ((threadIdx.x & 63) == 0) atomicMax(&out->maxlen, lmax);
+    nodiag = wave_sum(nodiag);
+    if ((threadIdx.x & 63) == 0) {
+        atomicMax(&out->maxlen, lmax);
+        if (nodiag) atomicAdd(&out->nodiag, nodiag);
+    }
 }
 
 __global__ void k_row_ptr_check(int n, const int32_t *__restrict__ rp, int nnz, ScanOut *out) {
@@ -721,34 +340,13 @@ static int scan_counts(int n, const int32_t *cnt, int32_t *out, int64_t *total, 
     return AFSAI_OK;
 }
 
-typedef void (*RowsKernel)(int, const int32_t *, const int32_t *, const double *, int, int, double, double,
-                           const int32_t *, int, int32_t *, int, int32_t *, double *, int, int32_t *, double *,
-                           int32_t *, int32_t *, int8_t *, int32_t *, int32_t *);
+// fused per-row kernels, instantiated in rows_reg.hip and rows_lds.hip
+RowsKernel rows_kernel_reg(int mmax_t, int cap);
+RowsKernel rows_kernel_lds(int mmax_t, int cap);
 
-template <int MMAX>
-static RowsKernel rows_kernel_cap(int cap) {
-    switch (cap) {
-        case 128: return k_afsai_rows<MMAX, 128>;
-        case 256: return k_afsai_rows<MMAX, 256>;
-        case 512: return k_afsai_rows<MMAX, 512>;
-        case 1024: return k_afsai_rows<MMAX, 1024>;
-        case 2048: return k_afsai_rows<MMAX, 2048>;
-        case 4096: return k_afsai_rows<MMAX, 4096>;
-        case 8192: return k_afsai_rows<MMAX, 8192>;
-        default: return nullptr;
-    }
-}
-
-static RowsKernel rows_kernel(int mmax_t, int cap) {
-    switch (mmax_t) {
-        case 8: return rows_kernel_cap<8>(cap);
-        case 16: return rows_kernel_cap<16>(cap);
-        case 24: return rows_kernel_cap<24>(cap);
-        case 32: return rows_kernel_cap<32>(cap);
-        case 48: return rows_kernel_cap<48>(cap);
-        case 64: return rows_kernel_cap<64>(cap);
-        default: return nullptr;
-    }
+// register form for patterns of at most 32 entries and s <= kRegSMax; LDS form otherwise
+static RowsKernel rows_kernel(int mmax_t, int cap, bool reg) {
+    return reg ? rows_kernel_reg(mmax_t, cap) : rows_kernel_lds(mmax_t, cap);
 }
 
 static int pow2ceil(int64_t v) {
@@ -757,15 +355,17 @@ static int pow2ceil(int64_t v) {
     return (int)p;
 }
 
-static size_t rows_lds_bytes(int mmax_t, int cap) {
-    return (size_t)cap * 12 + (size_t)mmax_t * (mmax_t + 1) * 8 + (size_t)mmax_t * 28 + 64 * 20 + 16;
+static size_t rows_lds_bytes(int mmax_t, int cap, bool reg) {
+    const size_t tri = (size_t)mmax_t * (mmax_t + 1) / 2;
+    return (size_t)cap * 12 + tri * 8 * (reg ? 1 : 2) + (reg ? (size_t)kRegSMax * mmax_t * 8 : 0) +
+           (size_t)mmax_t * 32 + 65 * 4 + 64 * 16 + 16;
 }
 
-static int launch_rows(RowsKernel kern, int mmax_t, int cap, const afsai_csr *A, const afsai_params *p,
-                       const int32_t *list, int nlist, int32_t *counters, int ldell, int32_t *ell_col,
-                       double *ell_val, int32_t *m, double *psi, int32_t *steps, int32_t *reason, int8_t *st,
-                       int32_t *ovf_count, int32_t *ovf_list, const DeviceInfo &di, hipStream_t s) {
-    const size_t lds = rows_lds_bytes(mmax_t, cap);
+static int launch_rows(RowsKernel kern, int mmax_t, int cap, bool reg, const afsai_csr *A, const double *diag,
+                       const afsai_params *p, const int32_t *list, int nlist, int32_t *counters, int ldell,
+                       int32_t *ell_col, double *ell_val, int32_t *m, double *psi, int32_t *steps, int32_t *reason,
+                       int8_t *st, int32_t *ovf_count, int32_t *ovf_list, const DeviceInfo &di, hipStream_t s) {
+    const size_t lds = rows_lds_bytes(mmax_t, cap, reg);
     int per_cu = (int)((160 * 1024) / (lds + 256));
     if (per_cu > 32) per_cu = 32;
     if (per_cu < 1) per_cu = 1;
@@ -777,9 +377,9 @@ static int launch_rows(RowsKernel kern, int mmax_t, int cap, const afsai_csr *A,
     hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, (int64_t)nx, counters, 0);
     {
         ProfScope ps("afsai_rows", s);
-        hipLaunchKernelGGL(kern, dim3((unsigned)nb), dim3(64), 0, s, A->n, A->row_ptr, A->col_idx, A->val, p->kmax,
-                           p->s, p->eps, p->tie_rtol, list, nlist, counters, nx, ell_col, ell_val, ldell, m, psi, steps,
-                           reason, st, ovf_count, ovf_list);
+        hipLaunchKernelGGL(kern, dim3((unsigned)nb), dim3(64), 0, s, A->n, A->row_ptr, A->col_idx, A->val, diag,
+                           p->kmax, p->s, p->eps, p->tie_rtol, list, nlist, counters, nx, ell_col, ell_val, ldell, m,
+                           psi, steps, reason, st, ovf_count, ovf_list);
     }
     AFSAI_HIP_TRY(hipGetLastError());
     return AFSAI_OK;
@@ -879,13 +479,16 @@ int afsai_setup(const afsai_csr *A, const afsai_params *p, void *stream, afsai_p
         AFSAI_HIP_TRY(hipStreamSynchronize(s));
         if (so.bad) AFSAI_FAIL(AFSAI_ERR_BAD_MATRIX, "afsai_setup: row pointers are not monotone from 0 to nnz");
     }
+    DevBuf diagb;
+    if ((rc = dalloc(diagb, sizeof(double) * (size_t)n))) return rc;
     hipLaunchKernelGGL(k_row_scan, dim3(grid1d(n, di)), dim3(256), 0, s, n, A->row_ptr, A->col_idx, A->val, validate,
-                       scanb.as<ScanOut>());
+                       diagb.as<double>(), scanb.as<ScanOut>());
     AFSAI_HIP_TRY(hipMemcpyAsync(&so, scanb.p, sizeof so, hipMemcpyDeviceToHost, s));
     AFSAI_HIP_TRY(hipStreamSynchronize(s));
     AFSAI_HIP_TRY(hipGetLastError());
     if (so.bad) AFSAI_FAIL(AFSAI_ERR_BAD_MATRIX, "afsai_setup: CSR structure invalid (columns unsorted, duplicate, out of range, or a missing diagonal)");
     if (so.asym) AFSAI_FAIL(AFSAI_ERR_BAD_MATRIX, "afsai_setup: matrix is not exactly symmetric");
+    if (so.nodiag) AFSAI_FAIL(AFSAI_ERR_BAD_MATRIX, "afsai_setup: %d rows without a diagonal entry (or unsorted columns)", so.nodiag);
     const int maxlen = so.maxlen > 0 ? so.maxlen : 1;
 
     // ---- kernel shape: pattern capacity and candidate table size
@@ -895,8 +498,14 @@ int afsai_setup(const afsai_csr *A, const afsai_params *p, void *stream, afsai_p
             mmax_t = c;
             break;
         }
-    const int64_t bound = (int64_t)mmax * maxlen + mmax;  // distinct columns a step can touch
-    int cap1 = pow2ceil((bound * 3 + 1) / 2);
+    const bool reg = mmax <= 32 && (p->kmax == 0 || p->s <= kRegSMax) && !option(AFSAI_OPT_SETUP_FORM_LDS);
+    // distinct columns one step can touch: at most every entry of the m pattern rows
+    const int64_t bound = (int64_t)mmax * maxlen + mmax;
+    // first table: about twice the distinct columns a step typically touches on stencil-like
+    // matrices (an eighth of the bound), 128..1024 slots; rows that overflow it are redone with
+    // a table larger than the bound (up to 8192 slots)
+    int cap1 = pow2ceil(bound / 4 + 1);
+    if (option(AFSAI_OPT_SETUP_TABLE) > 0) cap1 = pow2ceil(option(AFSAI_OPT_SETUP_TABLE));
     if (cap1 < 128) cap1 = 128;
     if (cap1 > 1024) cap1 = 1024;
     int cap2 = pow2ceil(bound + 1);
@@ -918,9 +527,9 @@ int afsai_setup(const afsai_csr *A, const afsai_params *p, void *stream, afsai_p
     int32_t *ovf_count = ovf.as<int32_t>() + n;
     hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, (int64_t)1, ovf_count, 0);
 
-    RowsKernel k1 = rows_kernel(mmax_t, cap1);
+    RowsKernel k1 = rows_kernel(mmax_t, cap1, reg);
     if (!k1) AFSAI_FAIL(AFSAI_ERR_TOO_LARGE, "afsai_setup: no kernel for pattern %d / table %d", mmax_t, cap1);
-    if ((rc = launch_rows(k1, mmax_t, cap1, A, p, nullptr, n, ctr.as<int32_t>(), ldell, ell_col.as<int32_t>(),
+    if ((rc = launch_rows(k1, mmax_t, cap1, reg, A, diagb.as<double>(), p, nullptr, n, ctr.as<int32_t>(), ldell, ell_col.as<int32_t>(),
                           ell_val.as<double>(), mcnt.as<int32_t>(), psi.as<double>(), steps.as<int32_t>(),
                           reason.as<int32_t>(), st.as<int8_t>(), ovf_count, ovf.as<int32_t>(), di, s)))
         return rc;
@@ -936,9 +545,9 @@ int afsai_setup(const afsai_csr *A, const afsai_params *p, void *stream, afsai_p
                            list2.as<int32_t>());
         int32_t *cnt2 = list2.as<int32_t>() + novf;
         hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, (int64_t)1, cnt2, 0);
-        RowsKernel k2 = rows_kernel(mmax_t, cap2);
+        RowsKernel k2 = rows_kernel(mmax_t, cap2, reg);
         if (!k2) AFSAI_FAIL(AFSAI_ERR_TOO_LARGE, "afsai_setup: no kernel for table %d", cap2);
-        if ((rc = launch_rows(k2, mmax_t, cap2, A, p, list2.as<int32_t>(), novf, ctr.as<int32_t>(), ldell,
+        if ((rc = launch_rows(k2, mmax_t, cap2, reg, A, diagb.as<double>(), p, list2.as<int32_t>(), novf, ctr.as<int32_t>(), ldell,
                               ell_col.as<int32_t>(), ell_val.as<double>(), mcnt.as<int32_t>(), psi.as<double>(),
                               steps.as<int32_t>(), reason.as<int32_t>(), st.as<int8_t>(), cnt2, ovf.as<int32_t>(), di, s)))
             return rc;

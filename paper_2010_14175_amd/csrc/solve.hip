@@ -100,7 +100,7 @@ __device__ __forceinline__ void finalize(PcgScalars *sc, int fin, double v) {
 // ---------------------------------------------------------------------------------------
 // CSR SpMV, one group of GS lanes per row; optional fused dot y.w with a PCG finalisation
 // ---------------------------------------------------------------------------------------
-template <int GS, typename VT, bool DOT>
+template <int GS, int U, typename VT, bool DOT>
 __global__ __launch_bounds__(kThreads) void k_spmv(int n, const int32_t *__restrict__ rp,
                                                     const int32_t *__restrict__ ci,
                                                     const VT *__restrict__ val,
@@ -120,10 +120,23 @@ __global__ __launch_bounds__(kThreads) void k_spmv(int n, const int32_t *__restr
     for (int row = r0 + grp; row < r1; row += RPI) {
         const int a = rp[row], b = rp[row + 1];
         double acc = 0.0;
-        for (int e = a + lg; e < b; e += GS) {
-            const int c = __builtin_nontemporal_load(&ci[e]);
-            const double v = (double)__builtin_nontemporal_load(&val[e]);
-            acc = fma(v, x[c], acc);
+        for (int e0 = a + lg; e0 < b; e0 += GS * U) {
+            int c[U];
+            VT v[U];
+            // all loads of a round are issued before any is used
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int e = e0 + u * GS;
+                c[u] = -1;
+                v[u] = VT(0);
+                if (e < b) {
+                    c[u] = __builtin_nontemporal_load(&ci[e]);
+                    v[u] = __builtin_nontemporal_load(&val[e]);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (c[u] >= 0) acc = fma((double)v[u], x[c[u]], acc);
         }
 #pragma unroll
         for (int off = GS / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, GS);
@@ -272,13 +285,18 @@ __global__ __launch_bounds__(kThreads) void k_resid_norm(int n, const double *__
 // ---------------------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------------------
-static int group_size_for(double avg_nnz) {
-    // miniwarp size from the average row length (Sec. 3), capped at one wavefront
-    if (avg_nnz > 40) return 64;
-    if (avg_nnz > 20) return 32;
-    if (avg_nnz > 10) return 16;
-    if (avg_nnz > 5) return 8;
-    return 4;
+// Lanes per row (the paper's miniwarp, Sec. 3) and independent loads per lane per round, from
+// the average row length: about four entries per lane per round and at most 8 loads in flight
+// per lane.
+static void spmv_shape(double avg_nnz, int *gs, int *un) {
+    int g = 4;
+    while (g < 64 && g * 4 < avg_nnz) g <<= 1;
+    int u = 1;
+    while (u < 8 && g * u < avg_nnz) u <<= 1;
+    if (option(AFSAI_OPT_SPMV_GROUP) > 0) g = (int)option(AFSAI_OPT_SPMV_GROUP);
+    if (option(AFSAI_OPT_SPMV_UNROLL) > 0) u = (int)option(AFSAI_OPT_SPMV_UNROLL);
+    *gs = g;
+    *un = u;
 }
 
 static int blocks_for_rows(int n, int gs, const DeviceInfo &di) {
@@ -304,40 +322,52 @@ struct Csr {
     bool f32 = false;
 };
 
-template <int GS, typename VT>
+template <int GS, int U, typename VT>
 static void launch_spmv_t(const Csr &A, const double *x, double *y, const double *w, double *partials,
                           PcgScalars *sc, int fin, int nb, int nxcd, hipStream_t s) {
     if (w)
-        hipLaunchKernelGGL((k_spmv<GS, VT, true>), dim3(nb), dim3(kThreads), 0, s, A.n, A.rp, A.ci,
+        hipLaunchKernelGGL((k_spmv<GS, U, VT, true>), dim3(nb), dim3(kThreads), 0, s, A.n, A.rp, A.ci,
                            (const VT *)A.val, x, y, w, partials, sc, fin, nxcd);
     else
-        hipLaunchKernelGGL((k_spmv<GS, VT, false>), dim3(nb), dim3(kThreads), 0, s, A.n, A.rp, A.ci,
+        hipLaunchKernelGGL((k_spmv<GS, U, VT, false>), dim3(nb), dim3(kThreads), 0, s, A.n, A.rp, A.ci,
                            (const VT *)A.val, x, y, w, partials, sc, fin, nxcd);
 }
 
-template <typename VT>
-static void launch_spmv_v(const Csr &A, int gs, const double *x, double *y, const double *w,
-                          double *partials, PcgScalars *sc, int fin, int nb, int nxcd, hipStream_t s) {
-    switch (gs) {
-        case 4: launch_spmv_t<4, VT>(A, x, y, w, partials, sc, fin, nb, nxcd, s); break;
-        case 8: launch_spmv_t<8, VT>(A, x, y, w, partials, sc, fin, nb, nxcd, s); break;
-        case 16: launch_spmv_t<16, VT>(A, x, y, w, partials, sc, fin, nb, nxcd, s); break;
-        case 32: launch_spmv_t<32, VT>(A, x, y, w, partials, sc, fin, nb, nxcd, s); break;
-        default: launch_spmv_t<64, VT>(A, x, y, w, partials, sc, fin, nb, nxcd, s); break;
+template <int GS, typename VT>
+static void launch_spmv_u(const Csr &A, int un, const double *x, double *y, const double *w, double *partials,
+                          PcgScalars *sc, int fin, int nb, int nxcd, hipStream_t s) {
+    switch (un) {
+        case 1: launch_spmv_t<GS, 1, VT>(A, x, y, w, partials, sc, fin, nb, nxcd, s); break;
+        case 2: launch_spmv_t<GS, 2, VT>(A, x, y, w, partials, sc, fin, nb, nxcd, s); break;
+        case 4: launch_spmv_t<GS, 4, VT>(A, x, y, w, partials, sc, fin, nb, nxcd, s); break;
+        default: launch_spmv_t<GS, 8, VT>(A, x, y, w, partials, sc, fin, nb, nxcd, s); break;
     }
 }
 
-// y = A x (optionally fused dot y.w finalised into sc); returns the launch's block count
+template <typename VT>
+static void launch_spmv_v(const Csr &A, int gs, int un, const double *x, double *y, const double *w,
+                          double *partials, PcgScalars *sc, int fin, int nb, int nxcd, hipStream_t s) {
+    switch (gs) {
+        case 4: launch_spmv_u<4, VT>(A, un, x, y, w, partials, sc, fin, nb, nxcd, s); break;
+        case 8: launch_spmv_u<8, VT>(A, un, x, y, w, partials, sc, fin, nb, nxcd, s); break;
+        case 16: launch_spmv_u<16, VT>(A, un, x, y, w, partials, sc, fin, nb, nxcd, s); break;
+        case 32: launch_spmv_u<32, VT>(A, un, x, y, w, partials, sc, fin, nb, nxcd, s); break;
+        default: launch_spmv_u<64, VT>(A, un, x, y, w, partials, sc, fin, nb, nxcd, s); break;
+    }
+}
+
+// y = A x (optionally fused dot y.w finalised into sc)
 static void spmv(const char *name, const Csr &A, const double *x, double *y, const double *w,
                  double *partials, PcgScalars *sc, int fin, const DeviceInfo &di, hipStream_t s) {
     const double avg = A.n ? (double)A.nnz / A.n : 0.0;
-    const int gs = group_size_for(avg);
+    int gs, un;
+    spmv_shape(avg, &gs, &un);
     const int nb = blocks_for_rows(A.n, gs, di);
     ProfScope ps(name, s);
     if (A.f32)
-        launch_spmv_v<float>(A, gs, x, y, w, partials, sc, fin, nb, di.num_xcds, s);
+        launch_spmv_v<float>(A, gs, un, x, y, w, partials, sc, fin, nb, di.num_xcds, s);
     else
-        launch_spmv_v<double>(A, gs, x, y, w, partials, sc, fin, nb, di.num_xcds, s);
+        launch_spmv_v<double>(A, gs, un, x, y, w, partials, sc, fin, nb, di.num_xcds, s);
 }
 
 static int check_csr_arg(const afsai_csr *A, const char *who) {

@@ -90,6 +90,14 @@ def test_invalid_arguments_rejected_on_host(L):
     L.afsai_destroy(None)
 
 
+def test_options_validated_on_host(L):
+    assert L.afsai_set_option(af.OPT_SPMV_GROUP, 3) == af.ERR_INVALID_ARG
+    assert L.afsai_set_option(af.OPT_SETUP_TABLE, 4096) == af.ERR_INVALID_ARG
+    assert L.afsai_set_option(99, 0) == af.ERR_INVALID_ARG
+    assert L.afsai_set_option(af.OPT_SPMV_GROUP, 16) == af.OK
+    assert L.afsai_set_option(af.OPT_SPMV_GROUP, 0) == af.OK
+
+
 def test_profile_toggle_without_gpu(L):
     assert L.afsai_profile_enable(0) == af.OK
     arr = (af.KernelTimeStruct * 4)()

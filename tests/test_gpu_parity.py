@@ -169,6 +169,43 @@ def test_setup_fp32_storage(af):
     compare_factor(af, A, 10, 2, 1e-2, g_prec=1)
 
 
+@pytest.mark.parametrize("make,kmax,s", [(lambda: synth.elast27(10, 1.0, 6), 10, 2), (lambda: synth.lap7(16), 5, 1),
+                                         (lambda: synth.elast27(6, 2.0, 5), 7, 4)])
+def test_setup_forms_identical(af, make, kmax, s):
+    """The register and the LDS forms of the per-row kernel, and any first table size, give
+    G bit for bit identical."""
+    A = make()
+    dA = _dev(af, A)
+    ref = _gpu_factor(af, af.setup(dA, kmax, s, 1e-2))
+    try:
+        af.set_option(af.OPT_SETUP_FORM_LDS, 1)
+        lds = _gpu_factor(af, af.setup(dA, kmax, s, 1e-2))
+        af.set_option(af.OPT_SETUP_FORM_LDS, 0)
+        af.set_option(af.OPT_SETUP_TABLE, 128)
+        small = _gpu_factor(af, af.setup(dA, kmax, s, 1e-2))
+    finally:
+        af.set_option(af.OPT_SETUP_FORM_LDS, 0)
+        af.set_option(af.OPT_SETUP_TABLE, 0)
+    for a, b, c in zip(ref, lds, small):
+        np.testing.assert_array_equal(a, b)
+        np.testing.assert_array_equal(a, c)
+
+
+@pytest.mark.parametrize("gs,un", [(4, 1), (8, 2), (16, 8), (64, 4)])
+def test_spmv_shapes(af, gs, un):
+    """Every group size / unroll of the CSR products gives the oracle's y within rounding."""
+    A = synth.elast27(7, 1.0, 2)
+    r = synth.uniform(3, 8, A.n)
+    try:
+        af.set_option(af.OPT_SPMV_GROUP, gs)
+        af.set_option(af.OPT_SPMV_UNROLL, un)
+        y = af.spmv(_dev(af, A), _vec(r)).cpu().numpy()
+    finally:
+        af.set_option(af.OPT_SPMV_GROUP, 0)
+        af.set_option(af.OPT_SPMV_UNROLL, 0)
+    np.testing.assert_allclose(y, oracle.spmv(A, r), rtol=1e-13, atol=1e-13 * np.abs(y).max())
+
+
 def test_setup_deterministic(af):
     A = synth.elast27(10, 1.0, 6)
     dA = _dev(af, A)
