@@ -176,6 +176,13 @@ int afsai_import(const afsai_csr *G, int32_t g_prec, void *stream, afsai_precond
 /* afsai_destroy -- frees a handle and everything it owns (NULL is a no-op). */
 void afsai_destroy(afsai_precond P);
 
+/*
+ * afsai_release_cache -- the library keeps device blocks it has freed (temporaries of setup
+ *   and solve, destroyed handles) for reuse; this returns them all to the HIP runtime.
+ *   Call only while no other library call is running.
+ */
+int afsai_release_cache(void);
+
 /* afsai_last_error -- message of the calling thread's most recent failure ("" if none). */
 const char *afsai_last_error(void);
 
@@ -187,7 +194,10 @@ const char *afsai_last_error(void);
  *   AFSAI_OPT_SETUP_TABLE     slots of the first on-chip candidate table (power of two,
  *                             128..1024)
  *   AFSAI_OPT_SPMV_GROUP      lanes per row of the CSR products (4, 8, 16, 32 or 64)
- *   AFSAI_OPT_SPMV_UNROLL     independent loads per lane per round in the CSR products (1, 2, 4, 8)
+ *   AFSAI_OPT_SPMV_UNROLL     independent loads per lane per round in the sparse products
+ *                             (1, 2, 4, 8)
+ *   AFSAI_OPT_PCG_CSR_A       1: pcg_solve multiplies by A in CSR (group per row) instead of
+ *                             converting it to the SELL-64 layout first
  * Returns AFSAI_ERR_INVALID_ARG for an unknown option or value.  Not thread safe against
  * concurrent calls of the library.
  */
@@ -195,6 +205,7 @@ const char *afsai_last_error(void);
 #define AFSAI_OPT_SETUP_TABLE 2
 #define AFSAI_OPT_SPMV_GROUP 3
 #define AFSAI_OPT_SPMV_UNROLL 4
+#define AFSAI_OPT_PCG_CSR_A 5
 int afsai_set_option(int32_t option, int64_t value);
 
 /*

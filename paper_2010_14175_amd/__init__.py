@@ -30,8 +30,9 @@ STOP_KMAX, STOP_EPS, STOP_NOCAND = 0, 1, 2
 # every symbol the C header declares
 EXPORTS = ("afsai_setup", "afsai_apply", "pcg_solve", "afsai_spmv", "afsai_get_setup_info", "afsai_export",
            "afsai_export_rows", "afsai_import", "afsai_destroy", "afsai_last_error", "afsai_set_option",
+           "afsai_release_cache",
            "afsai_profile_enable", "afsai_profile_read")
-OPT_SETUP_FORM_LDS, OPT_SETUP_TABLE, OPT_SPMV_GROUP, OPT_SPMV_UNROLL = 1, 2, 3, 4
+OPT_SETUP_FORM_LDS, OPT_SETUP_TABLE, OPT_SPMV_GROUP, OPT_SPMV_UNROLL, OPT_PCG_CSR_A = 1, 2, 3, 4, 5
 
 
 class CsrStruct(ctypes.Structure):
@@ -276,6 +277,11 @@ def spmv(A: DeviceCSR, x, y=None, stream=None):
     st = A.struct
     _check(lib().afsai_spmv(ctypes.byref(st), _ptr(x), _ptr(y), _stream(stream)), "afsai_spmv")
     return y
+
+
+def release_cache():
+    """Returns the library's cached device blocks to the HIP runtime."""
+    _check(lib().afsai_release_cache(), "afsai_release_cache")
 
 
 def set_option(option: int, value: int):

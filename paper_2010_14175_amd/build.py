@@ -17,7 +17,7 @@ LIB = os.path.join(HERE, "libafsai.so")
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 HIPCC = os.path.join(ROCM, "bin", "hipcc")
 
-SOURCES = ["rows_reg.hip", "rows_lds.hip", "setup.hip", "solve.hip", "runtime.hip"]
+SOURCES = ["rows_reg.hip", "rows_lds.hip", "setup.hip", "solve.hip", "sell.hip", "runtime.hip"]
 
 HIPFLAGS = [
     "--offload-arch=gfx950",
@@ -42,7 +42,7 @@ def _compile(src: str) -> str:
 
 def build(verbose: bool = True) -> str:
     os.makedirs(BUILD, exist_ok=True)
-    with cf.ThreadPoolExecutor(max_workers=min(len(SOURCES), 5)) as ex:
+    with cf.ThreadPoolExecutor(max_workers=min(len(SOURCES), 6)) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = LIB + ".tmp"
     cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs]

@@ -39,6 +39,52 @@ void clear_error();
 int64_t option(int id);
 
 // ---------------------------------------------------------------------------------------
+// device memory: caching allocator (blocks are kept per device and reused by size class;
+// afsai_release_cache() returns them to the runtime)
+// ---------------------------------------------------------------------------------------
+void *pool_alloc(size_t bytes);  // nullptr on failure
+void pool_free(void *p);          // p may be nullptr; the caller guarantees no pending use
+
+// temporary device buffer, returned to the pool when it goes out of scope; the stream is
+// synchronised first so that no enqueued kernel still uses it
+struct DevBuf {
+    void *p = nullptr;
+    hipStream_t s = nullptr;
+    DevBuf() = default;
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    ~DevBuf() {
+        if (p) {
+            (void)hipStreamSynchronize(s);
+            pool_free(p);
+        }
+    }
+    template <typename T>
+    T *as() { return (T *)p; }
+    void *release() {
+        void *q = p;
+        p = nullptr;
+        return q;
+    }
+};
+
+inline int dalloc(DevBuf &b, size_t bytes, hipStream_t s) {
+    b.s = s;
+    b.p = pool_alloc(bytes ? bytes : 16);
+    if (!b.p) {
+        set_error("out of device memory (%zu bytes)", bytes);
+        return AFSAI_ERR_NO_MEMORY;
+    }
+    return AFSAI_OK;
+}
+
+inline int pow2ceil(int64_t v) {
+    int64_t p = 1;
+    while (p < v) p <<= 1;
+    return (int)p;
+}
+
+// ---------------------------------------------------------------------------------------
 // device properties (cached per device)
 // ---------------------------------------------------------------------------------------
 struct DeviceInfo {
@@ -47,6 +93,18 @@ struct DeviceInfo {
     int num_xcds = 8;
 };
 int device_info(DeviceInfo *out);
+
+// grid for a grid-stride loop over `work` items
+inline int grid1d(int64_t work, const DeviceInfo &di, int threads = 256) {
+    int64_t b = (work + threads - 1) / threads;
+    const int64_t cap = (int64_t)di.num_cus * 16;
+    if (b > cap) b = cap;
+    return (int)(b < 1 ? 1 : b);
+}
+
+// exclusive scan of cnt[0..n) into out[0..n] (out[n] = total, int32); *total (host) gets the
+// 64-bit total; synchronous on s
+int scan_counts(int n, const int32_t *cnt, int32_t *out, int64_t *total, const DeviceInfo &di, hipStream_t s);
 
 // Blocks of a launch are dealt to the XCDs round robin (block b runs on XCD b % num_xcds).
 // xcd_block() renumbers them so that each XCD receives one contiguous range of logical
@@ -107,6 +165,10 @@ int prof_begin(hipStream_t s);
 void prof_end(int token, const char *name, hipStream_t s);
 // resolves pending events (called at synchronisation points)
 void prof_flush();
+// position in the list of timed launches not yet resolved, and removal of a range of them
+// (launches that returned at once because the iteration had already ended)
+int prof_mark();
+void prof_drop(int from, int to);
 
 struct ProfScope {
     int tok;
@@ -118,24 +180,3 @@ struct ProfScope {
 
 }  // namespace afsai
 
-// opaque handle
-struct afsai_precond_s {
-    int device = -1;
-    int32_t n = 0;
-    int64_t nnz_g = 0;
-    int32_t g_prec = AFSAI_F64;
-    int32_t mmax = 1;
-    // G (lower) and G^T as CSR
-    int32_t *g_rp = nullptr, *g_ci = nullptr;
-    void *g_val = nullptr;  // double* or float*
-    int32_t *gt_rp = nullptr, *gt_ci = nullptr;
-    void *gt_val = nullptr;
-    // per-row diagnostics (device)
-    double *psi = nullptr;
-    int32_t *steps = nullptr;
-    int32_t *reason = nullptr;
-    // workspace for apply (t) and PCG (r, z, p, q, t) and reductions
-    double *work = nullptr;
-    size_t work_elems = 0;
-    afsai_setup_info info{};
-};

@@ -1,0 +1,25 @@
+// The opaque preconditioner handle behind afsai_precond.
+#pragma once
+
+#include "sell.hpp"
+
+struct afsai_precond_s {
+    int device = -1;
+    int32_t n = 0;
+    int64_t nnz_g = 0;
+    int32_t g_prec = AFSAI_F64;
+    int32_t mmax = 1;
+    // G (lower triangular) as CSR, for afsai_export
+    int32_t *g_rp = nullptr, *g_ci = nullptr;
+    void *g_val = nullptr;  // double* or float*
+    // G and G^T in the SELL-64 layout used by afsai_apply and pcg_solve
+    afsai::Sell sg, sgt;
+    // per-row diagnostics (device)
+    double *psi = nullptr;
+    int32_t *steps = nullptr;
+    int32_t *reason = nullptr;
+    // workspace for apply (t) and PCG (r, z, p, q, t) and reductions
+    double *work = nullptr;
+    size_t work_elems = 0;
+    afsai_setup_info info{};
+};

@@ -28,6 +28,75 @@ static int64_t g_options[8] = {0, 0, 0, 0, 0, 0, 0, 0};
 
 int64_t option(int id) { return (id > 0 && id < 8) ? g_options[id] : 0; }
 
+// ---------------------------------------------------------------------------------------
+// caching allocator
+// ---------------------------------------------------------------------------------------
+namespace {
+std::mutex pool_mu;
+struct Block {
+    size_t size;
+    int device;
+};
+std::map<void *, Block> pool_live;                       // allocated blocks
+std::map<int, std::multimap<size_t, void *>> pool_free_; // per device: size -> block
+
+size_t size_class(size_t b) {
+    if (b <= (1u << 20)) {
+        size_t p = 256;
+        while (p < b) p <<= 1;
+        return p;
+    }
+    const size_t g = (size_t)2 << 20;  // 2 MiB granules above 1 MiB
+    return (b + g - 1) / g * g;
+}
+}  // namespace
+
+void *pool_alloc(size_t bytes) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+    const size_t sz = size_class(bytes);
+    {
+        std::lock_guard<std::mutex> lk(pool_mu);
+        auto &fl = pool_free_[dev];
+        auto it = fl.lower_bound(sz);
+        // reuse a cached block of the same class (or up to twice as large)
+        if (it != fl.end() && it->first <= 2 * sz) {
+            void *p = it->second;
+            pool_live[p] = {it->first, dev};
+            fl.erase(it);
+            return p;
+        }
+    }
+    void *p = nullptr;
+    if (hipMalloc(&p, sz) != hipSuccess) {
+        (void)hipGetLastError();
+        // release cached blocks of this device and retry once
+        std::vector<void *> drop;
+        {
+            std::lock_guard<std::mutex> lk(pool_mu);
+            for (auto &kv : pool_free_[dev]) drop.push_back(kv.second);
+            pool_free_[dev].clear();
+        }
+        for (void *q : drop) (void)hipFree(q);
+        if (hipMalloc(&p, sz) != hipSuccess) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+    }
+    std::lock_guard<std::mutex> lk(pool_mu);
+    pool_live[p] = {sz, dev};
+    return p;
+}
+
+void pool_free(void *p) {
+    if (!p) return;
+    std::lock_guard<std::mutex> lk(pool_mu);
+    auto it = pool_live.find(p);
+    if (it == pool_live.end()) return;
+    pool_free_[it->second.device].emplace(it->second.size, p);
+    pool_live.erase(it);
+}
+
 int device_info(DeviceInfo *out) {
     static std::mutex mu;
     static std::map<int, DeviceInfo> cache;
@@ -131,6 +200,24 @@ void prof_flush() {
     if (all_done) started.clear();
 }
 
+int prof_mark() {
+    std::lock_guard<std::mutex> lk(prof_mu);
+    return (int)pending.size();
+}
+
+void prof_drop(int from, int to) {
+    std::lock_guard<std::mutex> lk(prof_mu);
+    if (from < 0) from = 0;
+    if (to > (int)pending.size()) to = (int)pending.size();
+    if (from >= to) return;
+    for (int k = from; k < to; ++k) {
+        (void)hipEventSynchronize(pending[k].b);
+        event_pool.push_back(pending[k].a);
+        event_pool.push_back(pending[k].b);
+    }
+    pending.erase(pending.begin() + from, pending.begin() + to);
+}
+
 }  // namespace afsai
 
 extern "C" {
@@ -145,10 +232,23 @@ int afsai_set_option(int32_t opt, int64_t value) {
         case AFSAI_OPT_SETUP_TABLE: ok = value == 0 || (pow2(value) && value >= 128 && value <= 1024); break;
         case AFSAI_OPT_SPMV_GROUP: ok = value == 0 || (pow2(value) && value >= 4 && value <= 64); break;
         case AFSAI_OPT_SPMV_UNROLL: ok = value == 0 || (pow2(value) && value <= 8); break;
+        case AFSAI_OPT_PCG_CSR_A: ok = (value == 0 || value == 1); break;
         default: ok = false;
     }
     if (!ok) AFSAI_FAIL(AFSAI_ERR_INVALID_ARG, "afsai_set_option: bad option %d / value %lld", opt, (long long)value);
     afsai::g_options[opt] = value;
+    return AFSAI_OK;
+}
+
+int afsai_release_cache(void) {
+    std::vector<void *> drop;
+    {
+        std::lock_guard<std::mutex> lk(afsai::pool_mu);
+        for (auto &dv : afsai::pool_free_)
+            for (auto &kv : dv.second) drop.push_back(kv.second);
+        afsai::pool_free_.clear();
+    }
+    for (void *q : drop) AFSAI_HIP_TRY(hipFree(q));
     return AFSAI_OK;
 }
 

@@ -6,8 +6,7 @@
 #include <cmath>
 #include <vector>
 
-#include "common.hpp"
-
+#include "handle.hpp"
 #include "rows.hpp"
 
 namespace afsai {
@@ -88,129 +87,71 @@ __global__ void k_row_ptr_check(int n, const int32_t *__restrict__ rp, int nnz, 
 }
 
 // ---------------------------------------------------------------------------------------
-// per-row status summary
+// per-row status summary (two stages, fixed order: deterministic)
 // ---------------------------------------------------------------------------------------
 struct Summary {
     int64_t nnz;
-    int32_t nbad, nnotspd, novf;
-    int32_t stop[3];
-    double sumlog;  // not deterministic in order; diagnostics only
+    int64_t nbad, nnotspd, novf;
+    int64_t stop[3];
+    double sumlog;
 };
 
-__global__ void k_summary(int n, const int32_t *__restrict__ m, const int8_t *__restrict__ st,
-                          const int32_t *__restrict__ reason, const double *__restrict__ psi, Summary *out) {
-    int64_t nnz = 0;
-    int c_bad = 0, c_spd = 0, c_ovf = 0, c0 = 0, c1 = 0, c2 = 0;
-    double sl = 0.0;
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-        nnz += m[i];
-        const int8_t s = st[i];
-        c_bad += (s == ROW_BAD);
-        c_spd += (s == ROW_NOT_SPD);
-        c_ovf += (s == ROW_OVERFLOW);
-        const int r = reason[i];
-        c0 += (r == STOP_KMAX);
-        c1 += (r == STOP_EPS);
-        c2 += (r == STOP_NOCAND);
-        if (s == ROW_OK) sl += log(psi[i]);
-    }
-    nnz = wave_sum(nnz);
-    c_bad = wave_sum(c_bad);
-    c_spd = wave_sum(c_spd);
-    c_ovf = wave_sum(c_ovf);
-    c0 = wave_sum(c0);
-    c1 = wave_sum(c1);
-    c2 = wave_sum(c2);
-    sl = wave_sum(sl);
-    if ((threadIdx.x & 63) == 0) {
-        atomicAdd((unsigned long long *)&out->nnz, (unsigned long long)nnz);
-        atomicAdd(&out->nbad, c_bad);
-        atomicAdd(&out->nnotspd, c_spd);
-        atomicAdd(&out->novf, c_ovf);
-        atomicAdd(&out->stop[0], c0);
-        atomicAdd(&out->stop[1], c1);
-        atomicAdd(&out->stop[2], c2);
-        atomicAdd(&out->sumlog, sl);
-    }
+__device__ __forceinline__ void summary_add(Summary &a, const Summary &b) {
+    a.nnz += b.nnz;
+    a.nbad += b.nbad;
+    a.nnotspd += b.nnotspd;
+    a.novf += b.novf;
+    for (int k = 0; k < 3; ++k) a.stop[k] += b.stop[k];
+    a.sumlog += b.sumlog;
 }
 
-// ---------------------------------------------------------------------------------------
-// exclusive scan of int32 counts into int32 offsets (three phases; deterministic)
-// ---------------------------------------------------------------------------------------
-constexpr int kScanThreads = 256, kScanItems = 8, kScanTile = kScanThreads * kScanItems;
-
-__device__ __forceinline__ int64_t block_excl_scan(int64_t v, int64_t *sh, int64_t &total) {
-    // sh: kScanThreads/64 + 1 entries
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    int64_t incl = v;
+__device__ Summary block_summary(Summary v) {
+    __shared__ Summary sh[4];
 #pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const int64_t t = __shfl_up(incl, o, 64);
-        if (lane >= o) incl += t;
+    for (int off = 32; off > 0; off >>= 1) {
+        v.nnz += __shfl_xor(v.nnz, off, 64);
+        v.nbad += __shfl_xor(v.nbad, off, 64);
+        v.nnotspd += __shfl_xor(v.nnotspd, off, 64);
+        v.novf += __shfl_xor(v.novf, off, 64);
+        for (int k = 0; k < 3; ++k) v.stop[k] += __shfl_xor(v.stop[k], off, 64);
+        v.sumlog += __shfl_xor(v.sumlog, off, 64);
     }
-    if (lane == 63) sh[w] = incl;
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
     __syncthreads();
-    if (threadIdx.x == 0) {
-        int64_t acc = 0;
-        for (int k = 0; k < kScanThreads / 64; ++k) {
-            const int64_t t = sh[k];
-            sh[k] = acc;
-            acc += t;
-        }
-        sh[kScanThreads / 64] = acc;
-    }
+    Summary t{};
+    if (threadIdx.x == 0)
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) summary_add(t, sh[w]);
     __syncthreads();
-    total = sh[kScanThreads / 64];
-    const int64_t r = sh[w] + incl - v;
-    __syncthreads();
-    return r;
+    return t;
 }
 
-__global__ __launch_bounds__(kScanThreads) void k_scan_tiles(int n, const int32_t *__restrict__ cnt,
-                                                             int64_t *__restrict__ tile_sum) {
-    __shared__ int64_t sh[kScanThreads / 64 + 1];
-    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
-    int64_t v = 0;
-    for (int k = 0; k < kScanItems; ++k)
-        if (base + k < n) v += cnt[base + k];
-    int64_t tot;
-    block_excl_scan(v, sh, tot);
-    if (threadIdx.x == 0) tile_sum[blockIdx.x] = tot;
-}
-
-__global__ __launch_bounds__(kScanThreads) void k_scan_sums(int ntiles, int64_t *__restrict__ tile_sum,
-                                                            int64_t *__restrict__ total) {
-    __shared__ int64_t sh[kScanThreads / 64 + 1];
-    const int per = (ntiles + kScanThreads - 1) / kScanThreads;
-    const int lo = threadIdx.x * per, hi = min(ntiles, lo + per);
-    int64_t v = 0;
-    for (int k = lo; k < hi; ++k) v += tile_sum[k];
-    int64_t tot;
-    int64_t off = block_excl_scan(v, sh, tot);
-    for (int k = lo; k < hi; ++k) {
-        const int64_t t = tile_sum[k];
-        tile_sum[k] = off;
-        off += t;
+__global__ __launch_bounds__(256) void k_summary(int n, const int32_t *__restrict__ m, const int8_t *__restrict__ st,
+                                                 const int32_t *__restrict__ reason, const double *__restrict__ psi,
+                                                 Summary *part) {
+    Summary v{};
+    const int64_t per = ((int64_t)n + gridDim.x - 1) / gridDim.x;
+    const int i0 = (int)min<int64_t>(n, per * blockIdx.x), i1 = (int)min<int64_t>(n, per * (blockIdx.x + 1));
+    for (int i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
+        v.nnz += m[i];
+        const int8_t s = st[i];
+        v.nbad += (s == ROW_BAD);
+        v.nnotspd += (s == ROW_NOT_SPD);
+        v.novf += (s == ROW_OVERFLOW);
+        const int r = reason[i];
+        v.stop[0] += (r == STOP_KMAX);
+        v.stop[1] += (r == STOP_EPS);
+        v.stop[2] += (r == STOP_NOCAND);
+        if (s == ROW_OK) v.sumlog += log(psi[i]);
     }
-    if (threadIdx.x == 0) *total = tot;
+    Summary t = block_summary(v);
+    if (threadIdx.x == 0) part[blockIdx.x] = t;
 }
 
-__global__ __launch_bounds__(kScanThreads) void k_scan_apply(int n, const int32_t *__restrict__ cnt,
-                                                             const int64_t *__restrict__ tile_off,
-                                                             int32_t *__restrict__ out /* n+1 */) {
-    __shared__ int64_t sh[kScanThreads / 64 + 1];
-    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
-    int64_t v = 0;
-    for (int k = 0; k < kScanItems; ++k)
-        if (base + k < n) v += cnt[base + k];
-    int64_t tot;
-    int64_t off = block_excl_scan(v, sh, tot) + tile_off[blockIdx.x];
-    for (int k = 0; k < kScanItems; ++k) {
-        if (base + k < n) {
-            out[base + k] = (int32_t)off;
-            off += cnt[base + k];
-        }
-        if (base + k == n - 1) out[n] = (int32_t)off;
+__global__ void k_summary_final(int nparts, const Summary *__restrict__ part, Summary *out) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        Summary t{};
+        for (int k = 0; k < nparts; ++k) summary_add(t, part[k]);
+        *out = t;
     }
 }
 
@@ -236,35 +177,60 @@ __global__ void k_count_cols(int nnz, const int32_t *__restrict__ ci, int32_t *_
     for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < nnz; e += gridDim.x * blockDim.x) atomicAdd(&cnt[ci[e]], 1);
 }
 
+// entry (i, c) of G goes to row c of G^T at a slot taken with an atomic counter (the order
+// within a row is fixed afterwards by k_sort_rows); one wavefront per row of G, one lane per entry
 template <typename VT>
-__global__ void k_transpose_fill(int n, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
-                                 const VT *__restrict__ val, const int32_t *__restrict__ t_rp,
-                                 int32_t *__restrict__ fill, int32_t *__restrict__ t_ci, VT *__restrict__ t_val) {
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
-        for (int e = rp[i]; e < rp[i + 1]; ++e) {
+__global__ __launch_bounds__(256) void k_transpose_fill(int n, const int32_t *__restrict__ rp,
+                                                        const int32_t *__restrict__ ci, const VT *__restrict__ val,
+                                                        const int32_t *__restrict__ t_rp, int32_t *__restrict__ fill,
+                                                        int32_t *__restrict__ t_ci, VT *__restrict__ t_val) {
+    const int lane = threadIdx.x & 63;
+    for (int i = (blockIdx.x * blockDim.x + threadIdx.x) >> 6; i < n; i += (gridDim.x * blockDim.x) >> 6) {
+        const int a = rp[i], b = rp[i + 1];
+        for (int e = a + lane; e < b; e += 64) {
             const int c = ci[e];
             const int d = t_rp[c] + atomicAdd(&fill[c], 1);
             t_ci[d] = i;
             t_val[d] = val[e];
         }
+    }
 }
 
-// each row of G^T sorted by column (= row of G): the atomic fill order is not deterministic
+// Sorts every row of G^T by column (= row of G).  One wavefront per row: rows of up to 64
+// entries are ranked in registers (each lane counts the smaller keys); longer rows fall back
+// to an insertion sort by one lane.
 template <typename VT>
-__global__ void k_sort_rows(int n, const int32_t *__restrict__ rp, int32_t *__restrict__ ci, VT *__restrict__ val) {
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-        const int a = rp[i], b = rp[i + 1];
-        for (int e = a + 1; e < b; ++e) {
-            const int c = ci[e];
-            const VT v = val[e];
-            int f = e - 1;
-            while (f >= a && ci[f] > c) {
-                ci[f + 1] = ci[f];
-                val[f + 1] = val[f];
-                --f;
+__global__ __launch_bounds__(256) void k_sort_rows(int n, const int32_t *__restrict__ rp, int32_t *__restrict__ ci,
+                                                   VT *__restrict__ val) {
+    const int lane = threadIdx.x & 63;
+    for (int i = (blockIdx.x * blockDim.x + threadIdx.x) >> 6; i < n; i += (gridDim.x * blockDim.x) >> 6) {
+        const int a = rp[i], b = rp[i + 1], len = b - a;
+        if (len <= 64) {
+            int key = 0x7fffffff;
+            VT v = VT(0);
+            if (lane < len) {
+                key = ci[a + lane];
+                v = val[a + lane];
             }
-            ci[f + 1] = c;
-            val[f + 1] = v;
+            int rank = 0;
+            for (int t = 0; t < len; ++t) rank += (__shfl(key, t, 64) < key) ? 1 : 0;
+            if (lane < len) {
+                ci[a + rank] = key;
+                val[a + rank] = v;
+            }
+        } else if (lane == 0) {
+            for (int e = a + 1; e < b; ++e) {
+                const int c = ci[e];
+                const VT v = val[e];
+                int f = e - 1;
+                while (f >= a && ci[f] > c) {
+                    ci[f + 1] = ci[f];
+                    val[f + 1] = val[f];
+                    --f;
+                }
+                ci[f + 1] = c;
+                val[f + 1] = v;
+            }
         }
     }
 }
@@ -290,56 +256,9 @@ __global__ void k_fill_i32(int64_t n, int32_t *__restrict__ p, int32_t v) {
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) p[e] = v;
 }
 
-__global__ void k_row_counts(int n, const int32_t *__restrict__ rp, int32_t *__restrict__ cnt) {
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) cnt[i] = rp[i + 1] - rp[i];
-}
-
 // ---------------------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------------------
-struct DevBuf {
-    void *p = nullptr;
-    ~DevBuf() {
-        if (p) (void)hipFree(p);
-    }
-    template <typename T>
-    T *as() { return (T *)p; }
-    void *release() {
-        void *q = p;
-        p = nullptr;
-        return q;
-    }
-};
-
-static int dalloc(DevBuf &b, size_t bytes) {
-    AFSAI_HIP_TRY(hipMalloc(&b.p, bytes ? bytes : 16));
-    return AFSAI_OK;
-}
-
-static int grid1d(int64_t work, const DeviceInfo &di, int threads = 256) {
-    int64_t b = (work + threads - 1) / threads;
-    const int64_t cap = (int64_t)di.num_cus * 16;
-    if (b > cap) b = cap;
-    return (int)(b < 1 ? 1 : b);
-}
-
-// exclusive scan cnt[0..n) -> out[0..n]; returns the total through *total (host)
-static int scan_counts(int n, const int32_t *cnt, int32_t *out, int64_t *total, const DeviceInfo &di,
-                       hipStream_t s) {
-    (void)di;
-    const int ntiles = (int)(((int64_t)n + kScanTile - 1) / kScanTile);
-    DevBuf ts, tot;
-    int rc;
-    if ((rc = dalloc(ts, sizeof(int64_t) * (size_t)(ntiles + 1)))) return rc;
-    if ((rc = dalloc(tot, sizeof(int64_t)))) return rc;
-    hipLaunchKernelGGL(k_scan_tiles, dim3(ntiles), dim3(kScanThreads), 0, s, n, cnt, ts.as<int64_t>());
-    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(kScanThreads), 0, s, ntiles, ts.as<int64_t>(), tot.as<int64_t>());
-    hipLaunchKernelGGL(k_scan_apply, dim3(ntiles), dim3(kScanThreads), 0, s, n, cnt, ts.as<int64_t>(), out);
-    AFSAI_HIP_TRY(hipMemcpyAsync(total, tot.p, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-    AFSAI_HIP_TRY(hipStreamSynchronize(s));
-    return AFSAI_OK;
-}
-
 // fused per-row kernels, instantiated in rows_reg.hip and rows_lds.hip
 RowsKernel rows_kernel_reg(int mmax_t, int cap);
 RowsKernel rows_kernel_lds(int mmax_t, int cap);
@@ -347,12 +266,6 @@ RowsKernel rows_kernel_lds(int mmax_t, int cap);
 // register form for patterns of at most 32 entries and s <= kRegSMax; LDS form otherwise
 static RowsKernel rows_kernel(int mmax_t, int cap, bool reg) {
     return reg ? rows_kernel_reg(mmax_t, cap) : rows_kernel_lds(mmax_t, cap);
-}
-
-static int pow2ceil(int64_t v) {
-    int64_t p = 1;
-    while (p < v) p <<= 1;
-    return (int)p;
 }
 
 static size_t rows_lds_bytes(int mmax_t, int cap, bool reg) {
@@ -385,53 +298,59 @@ static int launch_rows(RowsKernel kern, int mmax_t, int cap, bool reg, const afs
     return AFSAI_OK;
 }
 
-// builds G^T (CSR, rows sorted) from G
+static void free_handle(afsai_precond_s *P) {
+    if (!P) return;
+    pool_free(P->g_rp);
+    pool_free(P->g_ci);
+    pool_free(P->g_val);
+    sell_free(&P->sg);
+    sell_free(&P->sgt);
+    pool_free(P->psi);
+    pool_free(P->steps);
+    pool_free(P->reason);
+    pool_free(P->work);
+    delete P;
+}
+
+// G^T as SELL-64, built from the CSR G of the handle (count, scan, fill, sort, convert)
 template <typename VT>
 static int build_transpose(afsai_precond_s *P, const DeviceInfo &di, hipStream_t s) {
     const int n = P->n;
     const int64_t nnz = P->nnz_g;
     DevBuf cnt, rp, ci, val;
     int rc;
-    if ((rc = dalloc(cnt, sizeof(int32_t) * (size_t)n))) return rc;
-    if ((rc = dalloc(rp, sizeof(int32_t) * (size_t)(n + 1)))) return rc;
-    if ((rc = dalloc(ci, sizeof(int32_t) * (size_t)nnz))) return rc;
-    if ((rc = dalloc(val, sizeof(VT) * (size_t)nnz))) return rc;
-    hipLaunchKernelGGL(k_fill_i32, dim3(grid1d(n, di)), dim3(256), 0, s, (int64_t)n, cnt.as<int32_t>(), 0);
-    hipLaunchKernelGGL(k_count_cols, dim3(grid1d(nnz, di)), dim3(256), 0, s, (int)nnz, P->g_ci, cnt.as<int32_t>());
+    if ((rc = dalloc(cnt, sizeof(int32_t) * (size_t)n, s))) return rc;
+    if ((rc = dalloc(rp, sizeof(int32_t) * (size_t)(n + 1), s))) return rc;
+    if ((rc = dalloc(ci, sizeof(int32_t) * (size_t)nnz, s))) return rc;
+    if ((rc = dalloc(val, sizeof(VT) * (size_t)nnz, s))) return rc;
+    {
+        ProfScope ps("transpose", s);
+        hipLaunchKernelGGL(k_fill_i32, dim3(grid1d(n, di)), dim3(256), 0, s, (int64_t)n, cnt.as<int32_t>(), 0);
+        hipLaunchKernelGGL(k_count_cols, dim3(grid1d(nnz, di)), dim3(256), 0, s, (int)nnz, P->g_ci, cnt.as<int32_t>());
+    }
     int64_t tot = 0;
     if ((rc = scan_counts(n, cnt.as<int32_t>(), rp.as<int32_t>(), &tot, di, s))) return rc;
-    hipLaunchKernelGGL(k_fill_i32, dim3(grid1d(n, di)), dim3(256), 0, s, (int64_t)n, cnt.as<int32_t>(), 0);
-    hipLaunchKernelGGL((k_transpose_fill<VT>), dim3(grid1d(n, di)), dim3(256), 0, s, n, P->g_rp, P->g_ci,
-                       (const VT *)P->g_val, rp.as<int32_t>(), cnt.as<int32_t>(), ci.as<int32_t>(), val.as<VT>());
-    hipLaunchKernelGGL((k_sort_rows<VT>), dim3(grid1d(n, di)), dim3(256), 0, s, n, rp.as<int32_t>(), ci.as<int32_t>(),
-                       val.as<VT>());
+    {
+        ProfScope ps("transpose", s);
+        hipLaunchKernelGGL(k_fill_i32, dim3(grid1d(n, di)), dim3(256), 0, s, (int64_t)n, cnt.as<int32_t>(), 0);
+        hipLaunchKernelGGL((k_transpose_fill<VT>), dim3(grid1d((int64_t)n * 64, di)), dim3(256), 0, s, n, P->g_rp,
+                           P->g_ci, (const VT *)P->g_val, rp.as<int32_t>(), cnt.as<int32_t>(), ci.as<int32_t>(),
+                           val.as<VT>());
+        hipLaunchKernelGGL((k_sort_rows<VT>), dim3(grid1d((int64_t)n * 64, di)), dim3(256), 0, s, n, rp.as<int32_t>(),
+                           ci.as<int32_t>(), val.as<VT>());
+    }
     AFSAI_HIP_TRY(hipGetLastError());
-    P->gt_rp = (int32_t *)rp.release();
-    P->gt_ci = (int32_t *)ci.release();
-    P->gt_val = val.release();
-    return AFSAI_OK;
-}
-
-static void free_handle(afsai_precond_s *P) {
-    if (!P) return;
-    (void)hipFree(P->g_rp);
-    (void)hipFree(P->g_ci);
-    (void)hipFree(P->g_val);
-    (void)hipFree(P->gt_rp);
-    (void)hipFree(P->gt_ci);
-    (void)hipFree(P->gt_val);
-    (void)hipFree(P->psi);
-    (void)hipFree(P->steps);
-    (void)hipFree(P->reason);
-    (void)hipFree(P->work);
-    delete P;
+    const bool f32 = sizeof(VT) == 4;
+    ProfScope ps("sell_GT", s);
+    return sell_from_csr(n, rp.as<int32_t>(), ci.as<int32_t>(), val.p, f32, f32, &P->sgt, di, s);
 }
 
 static int alloc_workspace(afsai_precond_s *P, const DeviceInfo &di) {
     // PCG: r, z, p, q, t (n each) + partial sums + scalars (must cover the solver's layout)
-    const size_t np = (size_t)2 * di.num_cus * 8 + 64;
+    const size_t np = (size_t)2 * di.num_cus * 16 + 64;
     P->work_elems = (size_t)5 * P->n + np + 16;
-    AFSAI_HIP_TRY(hipMalloc(&P->work, P->work_elems * sizeof(double)));
+    P->work = (double *)pool_alloc(P->work_elems * sizeof(double));
+    if (!P->work) AFSAI_FAIL(AFSAI_ERR_NO_MEMORY, "out of device memory for the solver workspace");
     return AFSAI_OK;
 }
 
@@ -463,30 +382,32 @@ int afsai_setup(const afsai_csr *A, const afsai_params *p, void *stream, afsai_p
     AFSAI_HIP_TRY(hipEventCreate(&t1));
     AFSAI_HIP_TRY(hipEventRecord(t0, s));
     const int n = A->n;
+    const bool f32 = (p->g_prec == AFSAI_F32);
 
     // ---- row statistics / validation
-    DevBuf scanb;
-    if ((rc = dalloc(scanb, sizeof(ScanOut)))) return rc;
+    DevBuf scanb, diagb;
+    if ((rc = dalloc(scanb, sizeof(ScanOut), s))) return rc;
+    if ((rc = dalloc(diagb, sizeof(double) * (size_t)n, s))) return rc;
     AFSAI_HIP_TRY(hipMemsetAsync(scanb.p, 0, sizeof(ScanOut), s));
     const int validate = (p->flags & AFSAI_VALIDATE) ? 1 : 0;
-    if (validate)
-        hipLaunchKernelGGL(k_row_ptr_check, dim3((n + 256) / 256), dim3(256), 0, s, n, A->row_ptr, A->nnz,
-                           scanb.as<ScanOut>());
     ScanOut so{};
     if (validate) {
         // row pointers must be sane before rows are scanned
+        hipLaunchKernelGGL(k_row_ptr_check, dim3((n + 256) / 256), dim3(256), 0, s, n, A->row_ptr, A->nnz,
+                           scanb.as<ScanOut>());
         AFSAI_HIP_TRY(hipMemcpyAsync(&so, scanb.p, sizeof so, hipMemcpyDeviceToHost, s));
         AFSAI_HIP_TRY(hipStreamSynchronize(s));
         if (so.bad) AFSAI_FAIL(AFSAI_ERR_BAD_MATRIX, "afsai_setup: row pointers are not monotone from 0 to nnz");
     }
-    DevBuf diagb;
-    if ((rc = dalloc(diagb, sizeof(double) * (size_t)n))) return rc;
-    hipLaunchKernelGGL(k_row_scan, dim3(grid1d(n, di)), dim3(256), 0, s, n, A->row_ptr, A->col_idx, A->val, validate,
-                       diagb.as<double>(), scanb.as<ScanOut>());
+    {
+        ProfScope ps("row_scan", s);
+        hipLaunchKernelGGL(k_row_scan, dim3(grid1d(n, di)), dim3(256), 0, s, n, A->row_ptr, A->col_idx, A->val,
+                           validate, diagb.as<double>(), scanb.as<ScanOut>());
+    }
     AFSAI_HIP_TRY(hipMemcpyAsync(&so, scanb.p, sizeof so, hipMemcpyDeviceToHost, s));
     AFSAI_HIP_TRY(hipStreamSynchronize(s));
     AFSAI_HIP_TRY(hipGetLastError());
-    if (so.bad) AFSAI_FAIL(AFSAI_ERR_BAD_MATRIX, "afsai_setup: CSR structure invalid (columns unsorted, duplicate, out of range, or a missing diagonal)");
+    if (so.bad) AFSAI_FAIL(AFSAI_ERR_BAD_MATRIX, "afsai_setup: CSR structure invalid (columns unsorted, duplicate or out of range)");
     if (so.asym) AFSAI_FAIL(AFSAI_ERR_BAD_MATRIX, "afsai_setup: matrix is not exactly symmetric");
     if (so.nodiag) AFSAI_FAIL(AFSAI_ERR_BAD_MATRIX, "afsai_setup: %d rows without a diagonal entry (or unsorted columns)", so.nodiag);
     const int maxlen = so.maxlen > 0 ? so.maxlen : 1;
@@ -515,23 +436,24 @@ int afsai_setup(const afsai_csr *A, const afsai_params *p, void *stream, afsai_p
     // ---- per-row results (padded) and diagnostics
     const int ldell = mmax;
     DevBuf ell_col, ell_val, mcnt, psi, steps, reason, st, ctr, ovf;
-    if ((rc = dalloc(ell_col, sizeof(int32_t) * (size_t)n * ldell))) return rc;
-    if ((rc = dalloc(ell_val, sizeof(double) * (size_t)n * ldell))) return rc;
-    if ((rc = dalloc(mcnt, sizeof(int32_t) * (size_t)n))) return rc;
-    if ((rc = dalloc(psi, sizeof(double) * (size_t)n))) return rc;
-    if ((rc = dalloc(steps, sizeof(int32_t) * (size_t)n))) return rc;
-    if ((rc = dalloc(reason, sizeof(int32_t) * (size_t)n))) return rc;
-    if ((rc = dalloc(st, sizeof(int8_t) * (size_t)n))) return rc;
-    if ((rc = dalloc(ctr, sizeof(int32_t) * 16))) return rc;
-    if ((rc = dalloc(ovf, sizeof(int32_t) * ((size_t)n + 1)))) return rc;
+    if ((rc = dalloc(ell_col, sizeof(int32_t) * (size_t)n * ldell, s))) return rc;
+    if ((rc = dalloc(ell_val, sizeof(double) * (size_t)n * ldell, s))) return rc;
+    if ((rc = dalloc(mcnt, sizeof(int32_t) * (size_t)n, s))) return rc;
+    if ((rc = dalloc(psi, sizeof(double) * (size_t)n, s))) return rc;
+    if ((rc = dalloc(steps, sizeof(int32_t) * (size_t)n, s))) return rc;
+    if ((rc = dalloc(reason, sizeof(int32_t) * (size_t)n, s))) return rc;
+    if ((rc = dalloc(st, sizeof(int8_t) * (size_t)n, s))) return rc;
+    if ((rc = dalloc(ctr, sizeof(int32_t) * 16, s))) return rc;
+    if ((rc = dalloc(ovf, sizeof(int32_t) * ((size_t)n + 1), s))) return rc;
     int32_t *ovf_count = ovf.as<int32_t>() + n;
     hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, (int64_t)1, ovf_count, 0);
 
     RowsKernel k1 = rows_kernel(mmax_t, cap1, reg);
     if (!k1) AFSAI_FAIL(AFSAI_ERR_TOO_LARGE, "afsai_setup: no kernel for pattern %d / table %d", mmax_t, cap1);
-    if ((rc = launch_rows(k1, mmax_t, cap1, reg, A, diagb.as<double>(), p, nullptr, n, ctr.as<int32_t>(), ldell, ell_col.as<int32_t>(),
-                          ell_val.as<double>(), mcnt.as<int32_t>(), psi.as<double>(), steps.as<int32_t>(),
-                          reason.as<int32_t>(), st.as<int8_t>(), ovf_count, ovf.as<int32_t>(), di, s)))
+    if ((rc = launch_rows(k1, mmax_t, cap1, reg, A, diagb.as<double>(), p, nullptr, n, ctr.as<int32_t>(), ldell,
+                          ell_col.as<int32_t>(), ell_val.as<double>(), mcnt.as<int32_t>(), psi.as<double>(),
+                          steps.as<int32_t>(), reason.as<int32_t>(), st.as<int8_t>(), ovf_count, ovf.as<int32_t>(), di,
+                          s)))
         return rc;
     int32_t novf = 0;
     AFSAI_HIP_TRY(hipMemcpyAsync(&novf, ovf_count, sizeof novf, hipMemcpyDeviceToHost, s));
@@ -540,68 +462,90 @@ int afsai_setup(const afsai_csr *A, const afsai_params *p, void *stream, afsai_p
     if (novf > 0 && cap2 > cap1) {
         retried = novf;
         DevBuf list2;
-        if ((rc = dalloc(list2, sizeof(int32_t) * ((size_t)novf + 1)))) return rc;
+        if ((rc = dalloc(list2, sizeof(int32_t) * ((size_t)novf + 1), s))) return rc;
         hipLaunchKernelGGL(k_copy_i32, dim3(grid1d(novf, di)), dim3(256), 0, s, (int64_t)novf, ovf.as<int32_t>(),
                            list2.as<int32_t>());
         int32_t *cnt2 = list2.as<int32_t>() + novf;
         hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, (int64_t)1, cnt2, 0);
         RowsKernel k2 = rows_kernel(mmax_t, cap2, reg);
         if (!k2) AFSAI_FAIL(AFSAI_ERR_TOO_LARGE, "afsai_setup: no kernel for table %d", cap2);
-        if ((rc = launch_rows(k2, mmax_t, cap2, reg, A, diagb.as<double>(), p, list2.as<int32_t>(), novf, ctr.as<int32_t>(), ldell,
-                              ell_col.as<int32_t>(), ell_val.as<double>(), mcnt.as<int32_t>(), psi.as<double>(),
-                              steps.as<int32_t>(), reason.as<int32_t>(), st.as<int8_t>(), cnt2, ovf.as<int32_t>(), di, s)))
+        if ((rc = launch_rows(k2, mmax_t, cap2, reg, A, diagb.as<double>(), p, list2.as<int32_t>(), novf,
+                              ctr.as<int32_t>(), ldell, ell_col.as<int32_t>(), ell_val.as<double>(), mcnt.as<int32_t>(),
+                              psi.as<double>(), steps.as<int32_t>(), reason.as<int32_t>(), st.as<int8_t>(), cnt2,
+                              ovf.as<int32_t>(), di, s)))
             return rc;
         AFSAI_HIP_TRY(hipStreamSynchronize(s));
     }
 
     // ---- status summary
+    const int nsb = grid1d(n, di);
     DevBuf sumb;
-    if ((rc = dalloc(sumb, sizeof(Summary)))) return rc;
-    AFSAI_HIP_TRY(hipMemsetAsync(sumb.p, 0, sizeof(Summary), s));
-    hipLaunchKernelGGL(k_summary, dim3(grid1d(n, di)), dim3(256), 0, s, n, mcnt.as<int32_t>(), st.as<int8_t>(),
-                       reason.as<int32_t>(), psi.as<double>(), sumb.as<Summary>());
+    if ((rc = dalloc(sumb, sizeof(Summary) * (size_t)(nsb + 1), s))) return rc;
+    Summary *sum_out = sumb.as<Summary>() + nsb;
+    {
+        ProfScope ps("summary", s);
+        hipLaunchKernelGGL(k_summary, dim3(nsb), dim3(256), 0, s, n, mcnt.as<int32_t>(), st.as<int8_t>(),
+                           reason.as<int32_t>(), psi.as<double>(), sumb.as<Summary>());
+        hipLaunchKernelGGL(k_summary_final, dim3(1), dim3(64), 0, s, nsb, sumb.as<Summary>(), sum_out);
+    }
     Summary sm{};
-    AFSAI_HIP_TRY(hipMemcpyAsync(&sm, sumb.p, sizeof sm, hipMemcpyDeviceToHost, s));
+    AFSAI_HIP_TRY(hipMemcpyAsync(&sm, sum_out, sizeof sm, hipMemcpyDeviceToHost, s));
     AFSAI_HIP_TRY(hipStreamSynchronize(s));
     AFSAI_HIP_TRY(hipGetLastError());
-    if (sm.nbad) AFSAI_FAIL(AFSAI_ERR_BAD_MATRIX, "afsai_setup: %d rows without a diagonal entry", sm.nbad);
-    if (sm.nnotspd) AFSAI_FAIL(AFSAI_ERR_NOT_SPD, "afsai_setup: %d rows met a non-positive pivot (A not SPD)", sm.nnotspd);
-    if (sm.novf) AFSAI_FAIL(AFSAI_ERR_TOO_LARGE, "afsai_setup: %d rows touch more candidate columns than fit on chip", sm.novf);
-    if (sm.nnz >= ((int64_t)1 << 31)) AFSAI_FAIL(AFSAI_ERR_TOO_LARGE, "afsai_setup: nnz(G) = %lld exceeds int32", (long long)sm.nnz);
+    if (sm.nbad) AFSAI_FAIL(AFSAI_ERR_BAD_MATRIX, "afsai_setup: %lld rows without a diagonal entry", (long long)sm.nbad);
+    if (sm.nnotspd)
+        AFSAI_FAIL(AFSAI_ERR_NOT_SPD, "afsai_setup: %lld rows met a non-positive pivot (A not SPD)", (long long)sm.nnotspd);
+    if (sm.novf)
+        AFSAI_FAIL(AFSAI_ERR_TOO_LARGE, "afsai_setup: %lld rows touch more candidate columns than fit on chip",
+                   (long long)sm.novf);
+    if (sm.nnz >= ((int64_t)1 << 31))
+        AFSAI_FAIL(AFSAI_ERR_TOO_LARGE, "afsai_setup: nnz(G) = %lld exceeds int32", (long long)sm.nnz);
 
-    // ---- G as CSR
+    // ---- G as CSR (export) and SELL-64 (products); G^T as SELL-64
     afsai_precond_s *P = new afsai_precond_s();
     P->device = di.device;
     P->n = n;
     P->mmax = mmax;
     P->g_prec = p->g_prec;
     auto fail = [&](int code) {
+        (void)hipStreamSynchronize(s);
         free_handle(P);
         return code;
     };
-    if (hipMalloc(&P->g_rp, sizeof(int32_t) * (size_t)(n + 1)) != hipSuccess) {
+    P->g_rp = (int32_t *)pool_alloc(sizeof(int32_t) * (size_t)(n + 1));
+    if (!P->g_rp) {
         set_error("afsai_setup: out of device memory");
         return fail(AFSAI_ERR_NO_MEMORY);
     }
     int64_t nnz = 0;
     if ((rc = scan_counts(n, mcnt.as<int32_t>(), P->g_rp, &nnz, di, s))) return fail(rc);
     P->nnz_g = nnz;
-    const size_t vsz = (p->g_prec == AFSAI_F32) ? sizeof(float) : sizeof(double);
-    if (hipMalloc(&P->g_ci, sizeof(int32_t) * (size_t)nnz) != hipSuccess ||
-        hipMalloc(&P->g_val, vsz * (size_t)nnz) != hipSuccess) {
+    const size_t vsz = f32 ? sizeof(float) : sizeof(double);
+    P->g_ci = (int32_t *)pool_alloc(sizeof(int32_t) * (size_t)nnz);
+    P->g_val = pool_alloc(vsz * (size_t)nnz);
+    if (!P->g_ci || !P->g_val) {
         set_error("afsai_setup: out of device memory for G");
         return fail(AFSAI_ERR_NO_MEMORY);
     }
-    if (p->g_prec == AFSAI_F32)
-        hipLaunchKernelGGL((k_fill_g<float>), dim3(grid1d((int64_t)n * ldell, di)), dim3(256), 0, s, n, ldell,
-                           mcnt.as<int32_t>(), ell_col.as<int32_t>(), ell_val.as<double>(), P->g_rp, P->g_ci,
-                           (float *)P->g_val);
-    else
-        hipLaunchKernelGGL((k_fill_g<double>), dim3(grid1d((int64_t)n * ldell, di)), dim3(256), 0, s, n, ldell,
-                           mcnt.as<int32_t>(), ell_col.as<int32_t>(), ell_val.as<double>(), P->g_rp, P->g_ci,
-                           (double *)P->g_val);
+    {
+        ProfScope ps("assemble_G", s);
+        if (f32)
+            hipLaunchKernelGGL((k_fill_g<float>), dim3(grid1d((int64_t)n * ldell, di)), dim3(256), 0, s, n, ldell,
+                               mcnt.as<int32_t>(), ell_col.as<int32_t>(), ell_val.as<double>(), P->g_rp, P->g_ci,
+                               (float *)P->g_val);
+        else
+            hipLaunchKernelGGL((k_fill_g<double>), dim3(grid1d((int64_t)n * ldell, di)), dim3(256), 0, s, n, ldell,
+                               mcnt.as<int32_t>(), ell_col.as<int32_t>(), ell_val.as<double>(), P->g_rp, P->g_ci,
+                               (double *)P->g_val);
+    }
     AFSAI_HIP_TRY(hipGetLastError());
-    rc = (p->g_prec == AFSAI_F32) ? build_transpose<float>(P, di, s) : build_transpose<double>(P, di, s);
+    {
+        ProfScope ps("sell_G", s);
+        if ((rc = sell_from_ell(n, ldell, mcnt.as<int32_t>(), ell_col.as<int32_t>(), ell_val.as<double>(), f32, &P->sg,
+                                di, s)))
+            return fail(rc);
+    }
+    rc = f32 ? build_transpose<float>(P, di, s) : build_transpose<double>(P, di, s);
     if (rc) return fail(rc);
     P->psi = (double *)psi.release();
     P->steps = (int32_t *)steps.release();
@@ -620,9 +564,9 @@ int afsai_setup(const afsai_csr *A, const afsai_params *p, void *stream, afsai_p
     inf.mmax = mmax;
     inf.nnz_g = nnz;
     inf.g_prec = p->g_prec;
-    inf.rows_stop_kmax = sm.stop[0];
-    inf.rows_stop_eps = sm.stop[1];
-    inf.rows_stop_nocand = sm.stop[2];
+    inf.rows_stop_kmax = (int32_t)sm.stop[0];
+    inf.rows_stop_eps = (int32_t)sm.stop[1];
+    inf.rows_stop_nocand = (int32_t)sm.stop[2];
     inf.rows_retried = retried;
     inf.sum_log_psi = sm.sumlog;
     inf.ms = ms;
@@ -684,14 +628,17 @@ int afsai_import(const afsai_csr *G, int32_t g_prec, void *stream, afsai_precond
     P->n = G->n;
     P->nnz_g = G->nnz;
     P->g_prec = g_prec;
+    const bool f32 = (g_prec == AFSAI_F32);
     auto fail = [&](int code) {
+        (void)hipStreamSynchronize(s);
         free_handle(P);
         return code;
     };
-    const size_t vsz = (g_prec == AFSAI_F32) ? sizeof(float) : sizeof(double);
-    if (hipMalloc(&P->g_rp, sizeof(int32_t) * (size_t)(G->n + 1)) != hipSuccess ||
-        hipMalloc(&P->g_ci, sizeof(int32_t) * (size_t)(G->nnz ? G->nnz : 1)) != hipSuccess ||
-        hipMalloc(&P->g_val, vsz * (size_t)(G->nnz ? G->nnz : 1)) != hipSuccess) {
+    const size_t vsz = f32 ? sizeof(float) : sizeof(double);
+    P->g_rp = (int32_t *)pool_alloc(sizeof(int32_t) * (size_t)(G->n + 1));
+    P->g_ci = (int32_t *)pool_alloc(sizeof(int32_t) * (size_t)(G->nnz ? G->nnz : 1));
+    P->g_val = pool_alloc(vsz * (size_t)(G->nnz ? G->nnz : 1));
+    if (!P->g_rp || !P->g_ci || !P->g_val) {
         set_error("afsai_import: out of device memory");
         return fail(AFSAI_ERR_NO_MEMORY);
     }
@@ -700,14 +647,15 @@ int afsai_import(const afsai_csr *G, int32_t g_prec, void *stream, afsai_precond
         set_error("afsai_import: copy failed");
         return fail(AFSAI_ERR_HIP);
     }
-    if (g_prec == AFSAI_F32)
+    if (f32)
         hipLaunchKernelGGL((k_narrow<float>), dim3(grid1d(G->nnz, di)), dim3(256), 0, s, (int64_t)G->nnz, G->val,
                            (float *)P->g_val);
     else if (hipMemcpyAsync(P->g_val, G->val, sizeof(double) * (size_t)G->nnz, hipMemcpyDeviceToDevice, s) != hipSuccess) {
         set_error("afsai_import: copy failed");
         return fail(AFSAI_ERR_HIP);
     }
-    rc = (g_prec == AFSAI_F32) ? build_transpose<float>(P, di, s) : build_transpose<double>(P, di, s);
+    if ((rc = sell_from_csr(P->n, P->g_rp, P->g_ci, P->g_val, f32, f32, &P->sg, di, s))) return fail(rc);
+    rc = f32 ? build_transpose<float>(P, di, s) : build_transpose<double>(P, di, s);
     if (rc) return fail(rc);
     if ((rc = alloc_workspace(P, di))) return fail(rc);
     if (hipStreamSynchronize(s) != hipSuccess) {

@@ -15,7 +15,7 @@
 #include <cmath>
 #include <vector>
 
-#include "common.hpp"
+#include "handle.hpp"
 
 namespace afsai {
 
@@ -143,6 +143,65 @@ __global__ __launch_bounds__(kThreads) void k_spmv(int n, const int32_t *__restr
         if (lg == 0) {
             y[row] = acc;
             if (DOT) part = fma(acc, w[row], part);
+        }
+    }
+    if (DOT) {
+        double bs = block_sum(part, sh);
+        if (finish_partials(partials, 1, &bs, &sc->ticket)) {
+            double tot = reduce_partials(partials, 0, sh);
+            if (threadIdx.x == 0) {
+                finalize(sc, fin, tot);
+                sc->ticket = 0;
+            }
+        }
+    }
+}
+
+// SELL-64 product: one wavefront per slice of 64 rows, one lane per row; entry k of the 64
+// rows is one contiguous wave load.  Optional fused dot y.w with a PCG finalisation.
+template <int U, typename VT, bool DOT>
+__global__ __launch_bounds__(kThreads) void k_sell_spmv(int n, int nslices, const uint32_t *__restrict__ sptr,
+                                                         const int32_t *__restrict__ perm,
+                                                         const int32_t *__restrict__ col,
+                                                         const VT *__restrict__ val,
+                                                         const double *__restrict__ x, double *__restrict__ y,
+                                                         const double *__restrict__ w,
+                                                         double *__restrict__ partials, PcgScalars *sc, int fin,
+                                                         int nxcd) {
+    if (sc && sc->done) return;
+    __shared__ double sh[kThreads / 64];
+    const int lb = xcd_block(blockIdx.x, gridDim.x, nxcd);
+    const int64_t per = ((int64_t)nslices + gridDim.x - 1) / gridDim.x;
+    const int s0 = (int)min<int64_t>(nslices, per * lb), s1 = (int)min<int64_t>(nslices, per * (lb + 1));
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    double part = 0.0;
+    for (int sl = s0 + wv; sl < s1; sl += kThreads / 64) {
+        int r = sl * kSlice + lane;
+        if (perm) r = perm[r];
+        const uint32_t c0 = sptr[sl];
+        const int width = (int)(sptr[sl + 1] - c0);
+        const int64_t base = (int64_t)c0 * kSlice + lane;
+        double acc = 0.0;
+        for (int k0 = 0; k0 < width; k0 += U) {
+            int c[U];
+            VT v[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                c[u] = -1;
+                v[u] = VT(0);
+                if (k0 + u < width) {
+                    const int64_t d = base + (int64_t)(k0 + u) * kSlice;
+                    c[u] = __builtin_nontemporal_load(&col[d]);
+                    v[u] = __builtin_nontemporal_load(&val[d]);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (c[u] >= 0) acc = fma((double)v[u], x[c[u]], acc);
+        }
+        if (r >= 0 && r < n) {
+            y[r] = acc;
+            if (DOT) part = fma(acc, w[r], part);
         }
     }
     if (DOT) {
@@ -370,6 +429,43 @@ static void spmv(const char *name, const Csr &A, const double *x, double *y, con
         launch_spmv_v<double>(A, gs, un, x, y, w, partials, sc, fin, nb, di.num_xcds, s);
 }
 
+template <int U, typename VT>
+static void launch_sell_t(const Sell &S, const double *x, double *y, const double *w, double *partials,
+                          PcgScalars *sc, int fin, int nb, int nxcd, hipStream_t s) {
+    if (w)
+        hipLaunchKernelGGL((k_sell_spmv<U, VT, true>), dim3(nb), dim3(kThreads), 0, s, S.n, S.nslices, S.sptr,
+                           S.perm, S.col, (const VT *)S.val, x, y, w, partials, sc, fin, nxcd);
+    else
+        hipLaunchKernelGGL((k_sell_spmv<U, VT, false>), dim3(nb), dim3(kThreads), 0, s, S.n, S.nslices, S.sptr,
+                           S.perm, S.col, (const VT *)S.val, x, y, w, partials, sc, fin, nxcd);
+}
+
+template <typename VT>
+static void launch_sell_v(const Sell &S, int un, const double *x, double *y, const double *w, double *partials,
+                          PcgScalars *sc, int fin, int nb, int nxcd, hipStream_t s) {
+    switch (un) {
+        case 1: launch_sell_t<1, VT>(S, x, y, w, partials, sc, fin, nb, nxcd, s); break;
+        case 2: launch_sell_t<2, VT>(S, x, y, w, partials, sc, fin, nb, nxcd, s); break;
+        case 4: launch_sell_t<4, VT>(S, x, y, w, partials, sc, fin, nb, nxcd, s); break;
+        default: launch_sell_t<8, VT>(S, x, y, w, partials, sc, fin, nb, nxcd, s); break;
+    }
+}
+
+// y = S x for a SELL-64 matrix (optionally fused dot y.w finalised into sc)
+static void sell_spmv(const char *name, const Sell &S, const double *x, double *y, const double *w,
+                      double *partials, PcgScalars *sc, int fin, const DeviceInfo &di, hipStream_t s) {
+    int un = option(AFSAI_OPT_SPMV_UNROLL) > 0 ? (int)option(AFSAI_OPT_SPMV_UNROLL) : 8;
+    int64_t nb = ((int64_t)S.nslices + kThreads / 64 - 1) / (kThreads / 64);
+    const int64_t cap = (int64_t)di.num_cus * 16;
+    if (nb > cap) nb = cap;
+    if (nb < 1) nb = 1;
+    ProfScope ps(name, s);
+    if (S.f32)
+        launch_sell_v<float>(S, un, x, y, w, partials, sc, fin, (int)nb, di.num_xcds, s);
+    else
+        launch_sell_v<double>(S, un, x, y, w, partials, sc, fin, (int)nb, di.num_xcds, s);
+}
+
 static int check_csr_arg(const afsai_csr *A, const char *who) {
     if (!A) AFSAI_FAIL(AFSAI_ERR_INVALID_ARG, "%s: A is NULL", who);
     if (A->n <= 0 || A->nnz < A->n) AFSAI_FAIL(AFSAI_ERR_INVALID_ARG, "%s: n = %d, nnz = %d", who, A->n, A->nnz);
@@ -387,19 +483,8 @@ static Csr csr_of(const afsai_csr *A) {
     return c;
 }
 
-static Csr csr_g(const afsai_precond_s *P, bool transposed) {
-    Csr c;
-    c.n = P->n;
-    c.nnz = P->nnz_g;
-    c.rp = transposed ? P->gt_rp : P->g_rp;
-    c.ci = transposed ? P->gt_ci : P->g_ci;
-    c.val = transposed ? P->gt_val : P->g_val;
-    c.f32 = (P->g_prec == AFSAI_F32);
-    return c;
-}
-
 // partial-sum scratch: 2 slots x max blocks
-static size_t partial_elems(const DeviceInfo &di) { return (size_t)2 * di.num_cus * 8 + 64; }
+static size_t partial_elems(const DeviceInfo &di) { return (size_t)2 * di.num_cus * 16 + 64; }
 
 }  // namespace afsai
 
@@ -427,8 +512,8 @@ int afsai_apply(afsai_precond P, const double *r, double *z, void *stream) {
     if (rc) return rc;
     hipStream_t s = (hipStream_t)stream;
     double *t = P->work;  // first n entries
-    spmv("spmv_G", csr_g(P, false), r, t, nullptr, nullptr, nullptr, FIN_NONE, di, s);
-    spmv("spmv_GT", csr_g(P, true), t, z, nullptr, nullptr, nullptr, FIN_NONE, di, s);
+    sell_spmv("spmv_G", P->sg, r, t, nullptr, nullptr, nullptr, FIN_NONE, di, s);
+    sell_spmv("spmv_GT", P->sgt, t, z, nullptr, nullptr, nullptr, FIN_NONE, di, s);
     AFSAI_HIP_TRY(hipGetLastError());
     return AFSAI_OK;
 }
@@ -453,48 +538,72 @@ int pcg_solve(const afsai_csr *A, afsai_precond P, const double *b, double *x, d
     const size_t np = partial_elems(di);
     // workspace: r, z, p, q, t (n each), partials, scalars
     const size_t need = (size_t)5 * n + np + 16;
+    DevBuf own;
     double *ws = nullptr;
-    bool own_ws = false;
     if (P && P->work_elems >= need) {
         ws = P->work;
     } else {
-        AFSAI_HIP_TRY(hipMalloc(&ws, need * sizeof(double)));
-        own_ws = true;
+        if ((rc = dalloc(own, need * sizeof(double), s))) return rc;
+        ws = own.as<double>();
     }
     double *r = ws, *z = ws + n, *p = ws + 2 * (size_t)n, *q = ws + 3 * (size_t)n, *t = ws + 4 * (size_t)n;
     double *partials = ws + 5 * (size_t)n;
     PcgScalars *sc = (PcgScalars *)(partials + np);
-    PcgScalars *hsc = nullptr;
-    AFSAI_HIP_TRY(hipHostMalloc(&hsc, 2 * sizeof(PcgScalars), hipHostMallocDefault));
+    // pinned host copies of the scalars, one pair per thread for the life of the process
+    static thread_local PcgScalars *hsc = nullptr;
+    if (!hsc) AFSAI_HIP_TRY(hipHostMalloc(&hsc, 2 * sizeof(PcgScalars), hipHostMallocDefault));
 
+    // A in the SELL-64 layout for the iteration (one conversion per solve)
+    Sell As;
+    const bool use_sell = option(AFSAI_OPT_PCG_CSR_A) == 0;
+    if (use_sell) {
+        ProfScope ps("sell_A", s);
+        if ((rc = sell_from_csr(n, A->row_ptr, A->col_idx, A->val, false, false, &As, di, s))) return rc;
+    }
+    struct SellGuard {
+        Sell *S;
+        hipStream_t s;
+        ~SellGuard() {
+            (void)hipStreamSynchronize(s);
+            sell_free(S);
+        }
+    } sell_guard{&As, s};
     const Csr Am = csr_of(A);
+    auto spmv_A = [&](const char *name, const double *xin, double *yout, const double *w, int fin, PcgScalars *scp) {
+        if (use_sell) sell_spmv(name, As, xin, yout, w, w ? partials : nullptr, scp, fin, di, s);
+        else spmv(name, Am, xin, yout, w, w ? partials : nullptr, scp, fin, di, s);
+    };
+
     const int nbv = blocks_for_vec(n, di);
     const int plain = P ? 0 : 1;
     hipLaunchKernelGGL(k_set_scalars, dim3(1), dim3(64), 0, s, sc, rtol, maxit, plain);
     // r0 = b - A x0
-    spmv("spmv_A", Am, x, q, nullptr, nullptr, nullptr, FIN_NONE, di, s);
+    spmv_A("spmv_A", x, q, nullptr, FIN_NONE, nullptr);
     hipLaunchKernelGGL(k_init_residual, dim3(nbv), dim3(kThreads), 0, s, n, b, q, r, partials, sc);
     // z0 = M^-1 r0, rho0 = r0.z0, p0 = z0
     const double *zz = z;
     if (P) {
-        const Csr Gm = csr_g(P, false), GTm = csr_g(P, true);
-        spmv("spmv_G", Gm, r, t, nullptr, nullptr, sc, FIN_NONE, di, s);
-        spmv("spmv_GT_dot", GTm, t, z, r, partials, sc, FIN_RHO0, di, s);
+        sell_spmv("spmv_G", P->sg, r, t, nullptr, nullptr, sc, FIN_NONE, di, s);
+        sell_spmv("spmv_GT_dot", P->sgt, t, z, r, partials, sc, FIN_RHO0, di, s);
     } else {
         zz = r;
     }
     hipLaunchKernelGGL(k_update_p, dim3(nbv), dim3(kThreads), 0, s, n, p, zz, sc, 1, di.num_xcds);
 
+    // timer marks: after the update of each iteration (launches past the last iteration that
+    // ran are dropped from the kernel timer at the end)
+    std::vector<int> marks;
+    const int mark0 = prof_mark();
     auto enqueue_iteration = [&]() {
-        spmv("spmv_A_dot", Am, p, q, p, partials, sc, FIN_ALPHA, di, s);
+        spmv_A("spmv_A_dot", p, q, p, FIN_ALPHA, sc);
         {
             ProfScope ps("update_xr", s);
             hipLaunchKernelGGL(k_update_xr, dim3(nbv), dim3(kThreads), 0, s, n, x, r, p, q, partials, sc, di.num_xcds);
         }
+        marks.push_back(prof_mark());
         if (P) {
-            const Csr Gm = csr_g(P, false), GTm = csr_g(P, true);
-            spmv("spmv_G", Gm, r, t, nullptr, nullptr, sc, FIN_NONE, di, s);
-            spmv("spmv_GT_dot", GTm, t, z, r, partials, sc, FIN_BETA, di, s);
+            sell_spmv("spmv_G", P->sg, r, t, nullptr, nullptr, sc, FIN_NONE, di, s);
+            sell_spmv("spmv_GT_dot", P->sgt, t, z, r, partials, sc, FIN_BETA, di, s);
         }
         {
             ProfScope ps("update_p", s);
@@ -502,26 +611,46 @@ int pcg_solve(const afsai_csr *A, afsai_precond P, const double *b, double *x, d
         }
     };
 
-    // chunks of iterations; the flag of chunk c is read while chunk c+1 is already queued
-    int enqueued = 0;
-    int chunk = 4;
+    // Chunks of iterations; the state after chunk c is read while chunk c+1 is already queued.
+    // Chunk sizes follow the observed residual reduction rate so that few iterations are
+    // queued past convergence (those return at once on the device flag).
     hipEvent_t ev[2];
     AFSAI_HIP_TRY(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
     AFSAI_HIP_TRY(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
-    int c = 0;
-    bool finished = false;
-    // read the state after initialisation first (zero rhs, converged x0, maxit = 0)
     AFSAI_HIP_TRY(hipMemcpyAsync(&hsc[1], sc, sizeof(PcgScalars), hipMemcpyDeviceToHost, s));
     AFSAI_HIP_TRY(hipEventRecord(ev[1], s));
+    int enqueued = 0, c = 0, chunk = 4;
+    bool finished = false, have_prev = false;
+    int prev_it = 0;
+    double prev_rr = 0.0, rate = 0.0;  // log of the per-iteration reduction of ||r||^2
     while (!finished) {
-        const int todo = enqueued < maxit ? (chunk < maxit - enqueued ? chunk : maxit - enqueued) : 0;
+        int todo = chunk;
+        if (rate < 0.0 && have_prev) {
+            const double tol2 = hsc[(c + 1) & 1].tol * hsc[(c + 1) & 1].tol;
+            const double need_it = std::ceil(std::log(tol2 / prev_rr) / rate);
+            int rem = (int)need_it - (enqueued - prev_it) + 1;
+            todo = rem < 1 ? 1 : (rem > 64 ? 64 : rem);
+        }
+        if (todo > maxit - enqueued) todo = maxit - enqueued;
         for (int k = 0; k < todo; ++k) enqueue_iteration();
         enqueued += todo;
         AFSAI_HIP_TRY(hipMemcpyAsync(&hsc[c & 1], sc, sizeof(PcgScalars), hipMemcpyDeviceToHost, s));
         AFSAI_HIP_TRY(hipEventRecord(ev[c & 1], s));
-        // wait for the previous chunk's copy
+        // state after the previous chunk
         AFSAI_HIP_TRY(hipEventSynchronize(ev[(c + 1) & 1]));
-        if (hsc[(c + 1) & 1].done != DONE_NO) finished = true;
+        const PcgScalars &st = hsc[(c + 1) & 1];
+        if (st.done != DONE_NO) finished = true;
+        else {
+            if (have_prev && st.it > prev_it && st.rr > 0.0 && prev_rr > 0.0) {
+                const double rt = std::log(st.rr / prev_rr) / (st.it - prev_it);
+                if (rt < 0.0) rate = rt;
+            }
+            if (st.rr > 0.0) {
+                prev_rr = st.rr;
+                prev_it = st.it;
+                have_prev = true;
+            }
+        }
         if (todo == 0) {
             AFSAI_HIP_TRY(hipEventSynchronize(ev[c & 1]));
             finished = true;
@@ -532,6 +661,10 @@ int pcg_solve(const afsai_csr *A, afsai_precond P, const double *b, double *x, d
     AFSAI_HIP_TRY(hipStreamSynchronize(s));
     PcgScalars fin_s;
     AFSAI_HIP_TRY(hipMemcpy(&fin_s, sc, sizeof(PcgScalars), hipMemcpyDeviceToHost));
+    {
+        const int keep_to = fin_s.it >= 1 && fin_s.it <= (int)marks.size() ? marks[fin_s.it - 1] : mark0;
+        prof_drop(keep_to, prof_mark());
+    }
 
     int status = AFSAI_OK;
     if (fin_s.done == DONE_ZERO_RHS) {
@@ -540,7 +673,7 @@ int pcg_solve(const afsai_csr *A, afsai_precond P, const double *b, double *x, d
     double true_rr = 0.0;
     if (fin_s.done != DONE_ZERO_RHS) {
         // true residual ||b - A x||
-        spmv("spmv_A", Am, x, q, nullptr, nullptr, nullptr, FIN_NONE, di, s);
+        spmv_A("spmv_A", x, q, nullptr, FIN_NONE, nullptr);
         double *d_out = partials + np - 8;
         hipLaunchKernelGGL(k_resid_norm, dim3(nbv), dim3(kThreads), 0, s, n, b, q, partials, sc, d_out);
         AFSAI_HIP_TRY(hipMemcpyAsync(&true_rr, d_out, sizeof(double), hipMemcpyDeviceToHost, s));
@@ -570,8 +703,6 @@ int pcg_solve(const afsai_csr *A, afsai_precond P, const double *b, double *x, d
     (void)hipEventDestroy(ev[1]);
     (void)hipEventDestroy(t0);
     (void)hipEventDestroy(t1);
-    (void)hipHostFree(hsc);
-    if (own_ws) (void)hipFree(ws);
     return status;
 }
 
