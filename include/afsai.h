@@ -198,6 +198,8 @@ const char *afsai_last_error(void);
  *                             (1, 2, 4, 8)
  *   AFSAI_OPT_PCG_CSR_A       1: pcg_solve multiplies by A in CSR (group per row) instead of
  *                             converting it to the SELL-64 layout first
+ *   AFSAI_OPT_PCG_UNFUSED     1: separate vector-update kernels in the preconditioned
+ *                             iteration (the fused form gives identical results)
  * Returns AFSAI_ERR_INVALID_ARG for an unknown option or value.  Not thread safe against
  * concurrent calls of the library.
  */
@@ -206,6 +208,7 @@ const char *afsai_last_error(void);
 #define AFSAI_OPT_SPMV_GROUP 3
 #define AFSAI_OPT_SPMV_UNROLL 4
 #define AFSAI_OPT_PCG_CSR_A 5
+#define AFSAI_OPT_PCG_UNFUSED 6
 int afsai_set_option(int32_t option, int64_t value);
 
 /*

@@ -233,6 +233,7 @@ int afsai_set_option(int32_t opt, int64_t value) {
         case AFSAI_OPT_SPMV_GROUP: ok = value == 0 || (pow2(value) && value >= 4 && value <= 64); break;
         case AFSAI_OPT_SPMV_UNROLL: ok = value == 0 || (pow2(value) && value <= 8); break;
         case AFSAI_OPT_PCG_CSR_A: ok = (value == 0 || value == 1); break;
+        case AFSAI_OPT_PCG_UNFUSED: ok = (value == 0 || value == 1); break;
         default: ok = false;
     }
     if (!ok) AFSAI_FAIL(AFSAI_ERR_INVALID_ARG, "afsai_set_option: bad option %d / value %lld", opt, (long long)value);

@@ -182,14 +182,26 @@ __global__ __launch_bounds__(256) void k_sell_fill(int n, int nslices, const int
         const int pad_col = valid ? r : n - 1;
         const int64_t base = (int64_t)sptr[sl] * kSlice + lane;
         const int width = sptr[sl + 1] - sptr[sl];
-        for (int k = 0; k < width; ++k) {
-            const int64_t d = base + (int64_t)k * kSlice;
-            if (k < len) {
-                col[d] = ci[start + k];
-                out[d] = (VO)val[start + k];
-            } else {
-                col[d] = pad_col;
-                out[d] = VO(0);
+        for (int k0 = 0; k0 < width; k0 += 8) {
+            int cv[8];
+            VO vv[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int k = k0 + u;
+                cv[u] = pad_col;
+                vv[u] = VO(0);
+                if (k < len) {
+                    cv[u] = ci[start + k];
+                    vv[u] = (VO)val[start + k];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                if (k0 + u < width) {
+                    const int64_t d = base + (int64_t)(k0 + u) * kSlice;
+                    col[d] = cv[u];
+                    out[d] = vv[u];
+                }
             }
         }
     }
@@ -204,8 +216,8 @@ void sell_free(Sell *S) {
     *S = Sell();
 }
 
-static int sell_build(int n, const int32_t *rp, const int32_t *m, int ld, const int32_t *ci, const void *val,
-                      bool val_f32, bool out_f32, Sell *out, const DeviceInfo &di, hipStream_t s) {
+static int sell_build(int n, int64_t nnz_in, const int32_t *rp, const int32_t *m, int ld, const int32_t *ci,
+                      const void *val, bool val_f32, bool out_f32, Sell *out, const DeviceInfo &di, hipStream_t s) {
     Sell S;
     S.n = n;
     S.nslices = (n + kSlice - 1) / kSlice;
@@ -223,14 +235,8 @@ static int sell_build(int n, const int32_t *rp, const int32_t *m, int ld, const 
         sell_free(&S);
         return rc;
     }
-    int64_t nnz = 0;
-    if (rp) {
-        int32_t last = 0;
-        AFSAI_HIP_TRY(hipMemcpy(&last, rp + n, sizeof last, hipMemcpyDeviceToHost));
-        nnz = last;
-    } else {
-        nnz = cols * kSlice;  // per-row results: rows of equal length in practice; no sort
-    }
+    // per-row results (rp == nullptr) have rows of nearly equal length: never sorted
+    const int64_t nnz = rp ? nnz_in : cols * kSlice;
     if (cols * kSlice > nnz + nnz / 10 && n > kSlice) {
         // rows of very different lengths: sort by length inside windows, then re-measure
         S.perm = (int32_t *)pool_alloc(sizeof(int32_t) * (size_t)S.nslices * kSlice);
@@ -282,14 +288,14 @@ static int sell_build(int n, const int32_t *rp, const int32_t *m, int ld, const 
     return AFSAI_OK;
 }
 
-int sell_from_csr(int n, const int32_t *rp, const int32_t *ci, const void *val, bool val_f32, bool out_f32,
-                  Sell *out, const DeviceInfo &di, hipStream_t s) {
-    return sell_build(n, rp, nullptr, 0, ci, val, val_f32, out_f32, out, di, s);
+int sell_from_csr(int n, int64_t nnz, const int32_t *rp, const int32_t *ci, const void *val, bool val_f32,
+                  bool out_f32, Sell *out, const DeviceInfo &di, hipStream_t s) {
+    return sell_build(n, nnz, rp, nullptr, 0, ci, val, val_f32, out_f32, out, di, s);
 }
 
 int sell_from_ell(int n, int ld, const int32_t *m, const int32_t *ell_col, const double *ell_val, bool out_f32,
                   Sell *out, const DeviceInfo &di, hipStream_t s) {
-    return sell_build(n, nullptr, m, ld, ell_col, ell_val, false, out_f32, out, di, s);
+    return sell_build(n, 0, nullptr, m, ld, ell_col, ell_val, false, out_f32, out, di, s);
 }
 
 }  // namespace afsai

@@ -29,8 +29,8 @@ struct Sell {
 
 // SELL-64 copy of a CSR matrix (device arrays); values converted to out_f32 ? float : double.
 // Synchronous on s.  On failure nothing is left allocated.
-int sell_from_csr(int n, const int32_t *rp, const int32_t *ci, const void *val, bool val_f32, bool out_f32,
-                  Sell *out, const DeviceInfo &di, hipStream_t s);
+int sell_from_csr(int n, int64_t nnz, const int32_t *rp, const int32_t *ci, const void *val, bool val_f32,
+                  bool out_f32, Sell *out, const DeviceInfo &di, hipStream_t s);
 // SELL-64 copy of padded row-major per-row results (ell_col/ell_val, ld entries per row, m[i]
 // valid): the setup's direct output for G.
 int sell_from_ell(int n, int ld, const int32_t *m, const int32_t *ell_col, const double *ell_val, bool out_f32,

@@ -147,12 +147,15 @@ __global__ __launch_bounds__(256) void k_summary(int n, const int32_t *__restric
     if (threadIdx.x == 0) part[blockIdx.x] = t;
 }
 
-__global__ void k_summary_final(int nparts, const Summary *__restrict__ part, Summary *out) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
-        Summary t{};
-        for (int k = 0; k < nparts; ++k) summary_add(t, part[k]);
-        *out = t;
-    }
+// sums the block partials: thread t adds a contiguous run in order, then the runs are added
+// in thread order (fixed shape: deterministic)
+__global__ __launch_bounds__(256) void k_summary_final(int nparts, const Summary *__restrict__ part, Summary *out) {
+    const int per = (nparts + 255) / 256;
+    const int lo = threadIdx.x * per, hi = min(nparts, lo + per);
+    Summary v{};
+    for (int k = lo; k < hi; ++k) summary_add(v, part[k]);
+    Summary t = block_summary(v);
+    if (threadIdx.x == 0) *out = t;
 }
 
 // ---------------------------------------------------------------------------------------
@@ -342,13 +345,13 @@ static int build_transpose(afsai_precond_s *P, const DeviceInfo &di, hipStream_t
     AFSAI_HIP_TRY(hipGetLastError());
     const bool f32 = sizeof(VT) == 4;
     ProfScope ps("sell_GT", s);
-    return sell_from_csr(n, rp.as<int32_t>(), ci.as<int32_t>(), val.p, f32, f32, &P->sgt, di, s);
+    return sell_from_csr(n, nnz, rp.as<int32_t>(), ci.as<int32_t>(), val.p, f32, f32, &P->sgt, di, s);
 }
 
 static int alloc_workspace(afsai_precond_s *P, const DeviceInfo &di) {
-    // PCG: r, z, p, q, t (n each) + partial sums + scalars (must cover the solver's layout)
+    // PCG: r, r', z, p, p', q, t (n each) + partial sums + scalars (the solver's layout)
     const size_t np = (size_t)2 * di.num_cus * 16 + 64;
-    P->work_elems = (size_t)5 * P->n + np + 16;
+    P->work_elems = (size_t)7 * P->n + np + 16;
     P->work = (double *)pool_alloc(P->work_elems * sizeof(double));
     if (!P->work) AFSAI_FAIL(AFSAI_ERR_NO_MEMORY, "out of device memory for the solver workspace");
     return AFSAI_OK;
@@ -486,7 +489,7 @@ int afsai_setup(const afsai_csr *A, const afsai_params *p, void *stream, afsai_p
         ProfScope ps("summary", s);
         hipLaunchKernelGGL(k_summary, dim3(nsb), dim3(256), 0, s, n, mcnt.as<int32_t>(), st.as<int8_t>(),
                            reason.as<int32_t>(), psi.as<double>(), sumb.as<Summary>());
-        hipLaunchKernelGGL(k_summary_final, dim3(1), dim3(64), 0, s, nsb, sumb.as<Summary>(), sum_out);
+        hipLaunchKernelGGL(k_summary_final, dim3(1), dim3(256), 0, s, nsb, sumb.as<Summary>(), sum_out);
     }
     Summary sm{};
     AFSAI_HIP_TRY(hipMemcpyAsync(&sm, sum_out, sizeof sm, hipMemcpyDeviceToHost, s));
@@ -654,7 +657,7 @@ int afsai_import(const afsai_csr *G, int32_t g_prec, void *stream, afsai_precond
         set_error("afsai_import: copy failed");
         return fail(AFSAI_ERR_HIP);
     }
-    if ((rc = sell_from_csr(P->n, P->g_rp, P->g_ci, P->g_val, f32, f32, &P->sg, di, s))) return fail(rc);
+    if ((rc = sell_from_csr(P->n, P->nnz_g, P->g_rp, P->g_ci, P->g_val, f32, f32, &P->sg, di, s))) return fail(rc);
     rc = f32 ? build_transpose<float>(P, di, s) : build_transpose<double>(P, di, s);
     if (rc) return fail(rc);
     if ((rc = alloc_workspace(P, di))) return fail(rc);

@@ -8,10 +8,13 @@
 // part of the matrix (its L2 then holds the x entries its rows share).
 //
 // PCG: all scalars (rho, alpha, beta, ||r||) live on the device.  Dot products are fused into
-// the kernel that produces one of their operands; per-block partial sums are combined by the
-// last block to finish, in block order, so results do not depend on scheduling.  A device
-// flag ends the iteration: kernels that see it return at once, so the host enqueues chunks of
-// iterations and only reads the flag once per chunk, one chunk behind.
+// the kernel that produces one of their operands, which stores one partial sum per block; a
+// one-block kernel then adds the partials in block order (results do not depend on
+// scheduling) and updates the scalars.  (A last-block-done reduction inside the producing
+// kernel needs a device-scope release per block, which on this 8-XCD part writes back the
+// L2 and cost more than the extra launch.)  A device flag ends the iteration: kernels that
+// see it return at once, so the host enqueues chunks of iterations and reads the flag once
+// per chunk, one chunk behind.
 #include <cmath>
 #include <vector>
 
@@ -21,7 +24,7 @@ namespace afsai {
 
 constexpr int kThreads = 256;
 
-enum : int { FIN_NONE = 0, FIN_ALPHA = 1, FIN_BETA = 2, FIN_RHO0 = 3 };
+enum : int { FIN_NONE = 0, FIN_ALPHA = 1, FIN_BETA = 2, FIN_RHO0 = 3, FIN_INIT = 4, FIN_UPDATE = 5, FIN_RESID = 6 };
 enum : int { DONE_NO = 0, DONE_CONVERGED = 1, DONE_NOT_SPD = 2, DONE_MAXIT = 3, DONE_ZERO_RHS = 4 };
 
 struct PcgScalars {
@@ -36,8 +39,7 @@ struct PcgScalars {
     int32_t maxit;
     int32_t done;    // DONE_*
     int32_t plain;   // 1: M = I (z = r)
-    uint32_t ticket; // last-block-done counter (returns to 0 after each kernel)
-    int32_t pad;
+    double resid;    // ||b - A x||^2 of the final check
 };
 
 // ---------------------------------------------------------------------------------------
@@ -55,45 +57,67 @@ __device__ __forceinline__ double block_sum(double v, double *sh /* >= kThreads/
     return t;  // valid in thread 0
 }
 
-// Stores this block's partial(s) and returns true in the block that finished last; that block
-// then sees every other block's partials.
-__device__ __forceinline__ bool finish_partials(double *partials, int slots, const double *mine,
-                                                uint32_t *ticket) {
-    __shared__ bool last;
-    if (threadIdx.x == 0) {
+// thread 0 stores this block's partial sums, slot k at partials[k * gridDim.x + blockIdx.x]
+__device__ __forceinline__ void store_partials(double *partials, int slots, const double *mine) {
+    if (threadIdx.x == 0)
         for (int k = 0; k < slots; ++k) partials[(size_t)k * gridDim.x + blockIdx.x] = mine[k];
-        uint32_t t = __hip_atomic_fetch_add(ticket, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        last = (t == gridDim.x - 1);
+}
+
+// One block: sums the partials of the previous kernel in block order and updates the scalars.
+__global__ __launch_bounds__(kThreads) void k_finalize(const double *__restrict__ partials, int nparts, int fin,
+                                                       PcgScalars *sc) {
+    if ((fin == FIN_ALPHA || fin == FIN_BETA || fin == FIN_UPDATE || fin == FIN_RHO0) && sc->done) return;
+    __shared__ double sh[kThreads / 64];
+    const int slots = (fin == FIN_INIT) ? 2 : 1;
+    double tot[2] = {0.0, 0.0};
+    const int per = (nparts + kThreads - 1) / kThreads;
+    const int lo = threadIdx.x * per, hi = min(nparts, lo + per);
+    for (int k = 0; k < slots; ++k) {
+        double v = 0.0;
+        for (int j = lo; j < hi; ++j) v += partials[(size_t)k * nparts + j];
+        tot[k] = block_sum(v, sh);
     }
-    __syncthreads();
-    return last;
-}
-
-// Sum of one slot of the partials in block order (deterministic), valid in thread 0.
-__device__ __forceinline__ double reduce_partials(const double *partials, int slot, double *sh) {
-    double v = 0.0;
-    const int nb = gridDim.x;
-    const int per = (nb + kThreads - 1) / kThreads;
-    const int lo = threadIdx.x * per, hi = min(nb, lo + per);
-    for (int k = lo; k < hi; ++k)
-        v += __hip_atomic_load(&partials[(size_t)slot * nb + k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    // fixed-shape tree over the threads
-    return block_sum(v, sh);
-}
-
-__device__ __forceinline__ void finalize(PcgScalars *sc, int fin, double v) {
-    if (fin == FIN_ALPHA) {
-        // v = p.q
-        if (!(v > 0.0) || !isfinite(v)) {
-            sc->done = DONE_NOT_SPD;
-        } else {
-            sc->alpha = sc->rho / v;
+    if (threadIdx.x != 0) return;
+    const double v = tot[0];
+    switch (fin) {
+        case FIN_ALPHA:  // v = p.q
+            if (!(v > 0.0) || !isfinite(v)) sc->done = DONE_NOT_SPD;
+            else sc->alpha = sc->rho / v;
+            break;
+        case FIN_BETA:  // v = r.z
+            sc->beta = v / sc->rho;
+            sc->rho = v;
+            break;
+        case FIN_RHO0:
+            sc->rho = v;
+            break;
+        case FIN_INIT: {  // v = b.b, tot[1] = r.r
+            const double bb = v, rr = tot[1];
+            sc->bb = bb;
+            sc->rr = rr;
+            sc->tol = sc->rtol * sqrt(bb);
+            sc->it = 0;
+            if (bb == 0.0) sc->done = DONE_ZERO_RHS;
+            else if (sqrt(rr) <= sc->tol) sc->done = DONE_CONVERGED;
+            else if (sc->maxit == 0) sc->done = DONE_MAXIT;
+            if (sc->plain) sc->rho = rr;
+            break;
         }
-    } else if (fin == FIN_BETA) {
-        sc->beta = v / sc->rho;
-        sc->rho = v;
-    } else if (fin == FIN_RHO0) {
-        sc->rho = v;
+        case FIN_UPDATE:  // v = r.r after the update
+            sc->rr = v;
+            sc->it += 1;
+            if (sqrt(v) <= sc->tol) sc->done = DONE_CONVERGED;
+            else if (sc->it >= sc->maxit) sc->done = DONE_MAXIT;
+            else if (sc->plain) {
+                sc->beta = v / sc->rho;
+                sc->rho = v;
+            }
+            break;
+        case FIN_RESID:
+            sc->resid = v;
+            break;
+        default:
+            break;
     }
 }
 
@@ -146,14 +170,8 @@ __global__ __launch_bounds__(kThreads) void k_spmv(int n, const int32_t *__restr
         }
     }
     if (DOT) {
-        double bs = block_sum(part, sh);
-        if (finish_partials(partials, 1, &bs, &sc->ticket)) {
-            double tot = reduce_partials(partials, 0, sh);
-            if (threadIdx.x == 0) {
-                finalize(sc, fin, tot);
-                sc->ticket = 0;
-            }
-        }
+        const double bs = block_sum(part, sh);
+        store_partials(partials, 1, &bs);
     }
 }
 
@@ -205,23 +223,88 @@ __global__ __launch_bounds__(kThreads) void k_sell_spmv(int n, int nslices, cons
         }
     }
     if (DOT) {
-        double bs = block_sum(part, sh);
-        if (finish_partials(partials, 1, &bs, &sc->ticket)) {
-            double tot = reduce_partials(partials, 0, sh);
-            if (threadIdx.x == 0) {
-                finalize(sc, fin, tot);
-                sc->ticket = 0;
+        const double bs = block_sum(part, sh);
+        store_partials(partials, 1, &bs);
+    }
+}
+
+// Fused PCG products (SELL-64, one lane per row).  The vector being multiplied is formed on
+// the fly from two others with the same fma the separate update kernel would use, so the
+// result is identical to update-then-multiply; the owner lane of each row also stores the
+// updated entry.
+//   FUSE_AP:  p_new = z + beta p_old (p_new = z on the first iteration); q = A p_new;
+//             partial sums of p_new.q
+//   FUSE_GR:  r_new = r_old - alpha q; x += alpha p_new; t = G r_new; partial sums of r_new.r_new
+enum : int { FUSE_AP = 1, FUSE_GR = 2 };
+
+template <int U, typename VT, int MODE>
+__global__ __launch_bounds__(kThreads) void k_sell_fused(int n, int nslices, const uint32_t *__restrict__ sptr,
+                                                          const int32_t *__restrict__ col,
+                                                          const VT *__restrict__ val,
+                                                          const double *__restrict__ va,   // z | r_old
+                                                          const double *__restrict__ vb,   // p_old | q
+                                                          double *__restrict__ own_out,    // p_new | r_new
+                                                          double *__restrict__ x,          // - | x
+                                                          const double *__restrict__ pn,   // - | p_new
+                                                          double *__restrict__ y,          // q | t
+                                                          double *__restrict__ partials,
+                                                          const PcgScalars *sc, int first, int nxcd) {
+    if (sc->done) return;
+    __shared__ double sh[kThreads / 64];
+    const double alpha = sc->alpha;
+    const double coef = (MODE == FUSE_AP) ? sc->beta : -alpha;
+    const int lb = xcd_block(blockIdx.x, gridDim.x, nxcd);
+    const int64_t per = ((int64_t)nslices + gridDim.x - 1) / gridDim.x;
+    const int s0 = (int)min<int64_t>(nslices, per * lb), s1 = (int)min<int64_t>(nslices, per * (lb + 1));
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    double part = 0.0;
+    for (int sl = s0 + wv; sl < s1; sl += kThreads / 64) {
+        const int r = sl * kSlice + lane;
+        const uint32_t c0 = sptr[sl];
+        const int width = (int)(sptr[sl + 1] - c0);
+        const int64_t base = (int64_t)c0 * kSlice + lane;
+        double acc = 0.0;
+        for (int k0 = 0; k0 < width; k0 += U) {
+            int c[U];
+            VT v[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                c[u] = -1;
+                v[u] = VT(0);
+                if (k0 + u < width) {
+                    const int64_t d = base + (int64_t)(k0 + u) * kSlice;
+                    c[u] = __builtin_nontemporal_load(&col[d]);
+                    v[u] = __builtin_nontemporal_load(&val[d]);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (c[u] >= 0) {
+                    const double xv = (MODE == FUSE_AP && first) ? va[c[u]] : fma(coef, vb[c[u]], va[c[u]]);
+                    acc = fma((double)v[u], xv, acc);
+                }
+        }
+        if (r < n) {
+            const double own = (MODE == FUSE_AP && first) ? va[r] : fma(coef, vb[r], va[r]);
+            own_out[r] = own;
+            y[r] = acc;
+            if (MODE == FUSE_AP) {
+                part = fma(own, acc, part);
+            } else {
+                x[r] = fma(alpha, pn[r], x[r]);
+                part = fma(own, own, part);
             }
         }
     }
+    const double bs = block_sum(part, sh);
+    store_partials(partials, 1, &bs);
 }
 
 // r = b - q ; partials of b.b and r.r ; finalisation checks ||b|| = 0 and ||r0|| <= tol
 __global__ __launch_bounds__(kThreads) void k_init_residual(int n, const double *__restrict__ b,
                                                              const double *__restrict__ q,
                                                              double *__restrict__ r,
-                                                             double *__restrict__ partials,
-                                                             PcgScalars *sc) {
+                                                             double *__restrict__ partials) {
     __shared__ double sh[kThreads / 64];
     const int64_t per = ((int64_t)n + gridDim.x - 1) / gridDim.x;
     const int i0 = (int)min<int64_t>(n, per * blockIdx.x), i1 = (int)min<int64_t>(n, per * (blockIdx.x + 1));
@@ -235,21 +318,7 @@ __global__ __launch_bounds__(kThreads) void k_init_residual(int n, const double 
     double mine[2];
     mine[0] = block_sum(pb, sh);
     mine[1] = block_sum(pr, sh);
-    if (finish_partials(partials, 2, mine, &sc->ticket)) {
-        const double bb = reduce_partials(partials, 0, sh);
-        const double rr = reduce_partials(partials, 1, sh);
-        if (threadIdx.x == 0) {
-            sc->bb = bb;
-            sc->rr = rr;
-            sc->tol = sc->rtol * sqrt(bb);
-            sc->it = 0;
-            if (bb == 0.0) sc->done = DONE_ZERO_RHS;
-            else if (sqrt(rr) <= sc->tol) sc->done = DONE_CONVERGED;
-            else if (sc->maxit == 0) sc->done = DONE_MAXIT;
-            if (sc->plain) sc->rho = rr;
-            sc->ticket = 0;
-        }
-    }
+    store_partials(partials, 2, mine);
 }
 
 // x += alpha p ; r -= alpha q ; ||r||^2 ; convergence test; (plain CG) beta = rr'/rr
@@ -272,21 +341,8 @@ __global__ __launch_bounds__(kThreads) void k_update_xr(int n, double *__restric
         r[i] = ri;
         pr = fma(ri, ri, pr);
     }
-    double bs = block_sum(pr, sh);
-    if (finish_partials(partials, 1, &bs, &sc->ticket)) {
-        const double rr = reduce_partials(partials, 0, sh);
-        if (threadIdx.x == 0) {
-            sc->rr = rr;
-            sc->it += 1;
-            if (sqrt(rr) <= sc->tol) sc->done = DONE_CONVERGED;
-            else if (sc->it >= sc->maxit) sc->done = DONE_MAXIT;
-            else if (sc->plain) {
-                sc->beta = rr / sc->rho;
-                sc->rho = rr;
-            }
-            sc->ticket = 0;
-        }
-    }
+    const double bs = block_sum(pr, sh);
+    store_partials(partials, 1, &bs);
 }
 
 // p = z + beta p   (first = 1: p = z)
@@ -321,8 +377,7 @@ __global__ void k_set_scalars(PcgScalars *sc, double rtol, int maxit, int plain)
 // true residual partials: ||b - Ax||^2 with q = A x
 __global__ __launch_bounds__(kThreads) void k_resid_norm(int n, const double *__restrict__ b,
                                                           const double *__restrict__ q,
-                                                          double *__restrict__ partials,
-                                                          PcgScalars *sc, double *out) {
+                                                          double *__restrict__ partials) {
     __shared__ double sh[kThreads / 64];
     const int64_t per = ((int64_t)n + gridDim.x - 1) / gridDim.x;
     const int i0 = (int)min<int64_t>(n, per * blockIdx.x), i1 = (int)min<int64_t>(n, per * (blockIdx.x + 1));
@@ -331,14 +386,8 @@ __global__ __launch_bounds__(kThreads) void k_resid_norm(int n, const double *__
         const double d = b[i] - q[i];
         pr = fma(d, d, pr);
     }
-    double bs = block_sum(pr, sh);
-    if (finish_partials(partials, 1, &bs, &sc->ticket)) {
-        const double t = reduce_partials(partials, 0, sh);
-        if (threadIdx.x == 0) {
-            *out = t;
-            sc->ticket = 0;
-        }
-    }
+    const double bs = block_sum(pr, sh);
+    store_partials(partials, 1, &bs);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -422,11 +471,14 @@ static void spmv(const char *name, const Csr &A, const double *x, double *y, con
     int gs, un;
     spmv_shape(avg, &gs, &un);
     const int nb = blocks_for_rows(A.n, gs, di);
-    ProfScope ps(name, s);
-    if (A.f32)
-        launch_spmv_v<float>(A, gs, un, x, y, w, partials, sc, fin, nb, di.num_xcds, s);
-    else
-        launch_spmv_v<double>(A, gs, un, x, y, w, partials, sc, fin, nb, di.num_xcds, s);
+    {
+        ProfScope ps(name, s);
+        if (A.f32)
+            launch_spmv_v<float>(A, gs, un, x, y, w, partials, sc, fin, nb, di.num_xcds, s);
+        else
+            launch_spmv_v<double>(A, gs, un, x, y, w, partials, sc, fin, nb, di.num_xcds, s);
+    }
+    if (w) hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kThreads), 0, s, partials, nb, fin, sc);
 }
 
 template <int U, typename VT>
@@ -459,11 +511,54 @@ static void sell_spmv(const char *name, const Sell &S, const double *x, double *
     const int64_t cap = (int64_t)di.num_cus * 16;
     if (nb > cap) nb = cap;
     if (nb < 1) nb = 1;
-    ProfScope ps(name, s);
-    if (S.f32)
-        launch_sell_v<float>(S, un, x, y, w, partials, sc, fin, (int)nb, di.num_xcds, s);
-    else
-        launch_sell_v<double>(S, un, x, y, w, partials, sc, fin, (int)nb, di.num_xcds, s);
+    {
+        ProfScope ps(name, s);
+        if (S.f32)
+            launch_sell_v<float>(S, un, x, y, w, partials, sc, fin, (int)nb, di.num_xcds, s);
+        else
+            launch_sell_v<double>(S, un, x, y, w, partials, sc, fin, (int)nb, di.num_xcds, s);
+    }
+    if (w) hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kThreads), 0, s, partials, (int)nb, fin, sc);
+}
+
+template <int U, typename VT, int MODE>
+static void launch_fused_t(const Sell &S, const double *va, const double *vb, double *own, double *x,
+                           const double *pn, double *y, double *partials, PcgScalars *sc, int first, int nb, int nxcd,
+                           hipStream_t s) {
+    hipLaunchKernelGGL((k_sell_fused<U, VT, MODE>), dim3(nb), dim3(kThreads), 0, s, S.n, S.nslices, S.sptr, S.col,
+                       (const VT *)S.val, va, vb, own, x, pn, y, partials, sc, first, nxcd);
+}
+
+template <typename VT, int MODE>
+static void launch_fused_v(const Sell &S, int un, const double *va, const double *vb, double *own, double *x,
+                           const double *pn, double *y, double *partials, PcgScalars *sc, int first, int nb, int nxcd,
+                           hipStream_t s) {
+    switch (un) {
+        case 1: launch_fused_t<1, VT, MODE>(S, va, vb, own, x, pn, y, partials, sc, first, nb, nxcd, s); break;
+        case 2: launch_fused_t<2, VT, MODE>(S, va, vb, own, x, pn, y, partials, sc, first, nb, nxcd, s); break;
+        case 4: launch_fused_t<4, VT, MODE>(S, va, vb, own, x, pn, y, partials, sc, first, nb, nxcd, s); break;
+        default: launch_fused_t<8, VT, MODE>(S, va, vb, own, x, pn, y, partials, sc, first, nb, nxcd, s); break;
+    }
+}
+
+// fused product (rows in natural order only) followed by the finalisation of its dot
+template <int MODE>
+static void sell_fused(const char *name, const Sell &S, const double *va, const double *vb, double *own, double *x,
+                       const double *pn, double *y, double *partials, PcgScalars *sc, int first, int fin,
+                       const DeviceInfo &di, hipStream_t s) {
+    const int un = option(AFSAI_OPT_SPMV_UNROLL) > 0 ? (int)option(AFSAI_OPT_SPMV_UNROLL) : 8;
+    int64_t nb = ((int64_t)S.nslices + kThreads / 64 - 1) / (kThreads / 64);
+    const int64_t cap = (int64_t)di.num_cus * 16;
+    if (nb > cap) nb = cap;
+    if (nb < 1) nb = 1;
+    {
+        ProfScope ps(name, s);
+        if (S.f32)
+            launch_fused_v<float, MODE>(S, un, va, vb, own, x, pn, y, partials, sc, first, (int)nb, di.num_xcds, s);
+        else
+            launch_fused_v<double, MODE>(S, un, va, vb, own, x, pn, y, partials, sc, first, (int)nb, di.num_xcds, s);
+    }
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kThreads), 0, s, partials, (int)nb, fin, sc);
 }
 
 static int check_csr_arg(const afsai_csr *A, const char *who) {
@@ -485,6 +580,9 @@ static Csr csr_of(const afsai_csr *A) {
 
 // partial-sum scratch: 2 slots x max blocks
 static size_t partial_elems(const DeviceInfo &di) { return (size_t)2 * di.num_cus * 16 + 64; }
+
+// work vectors of the solver: r, r', z, p, p', q, t
+constexpr int kWorkVectors = 7;
 
 }  // namespace afsai
 
@@ -536,8 +634,8 @@ int pcg_solve(const afsai_csr *A, afsai_precond P, const double *b, double *x, d
 
     const int n = A->n;
     const size_t np = partial_elems(di);
-    // workspace: r, z, p, q, t (n each), partials, scalars
-    const size_t need = (size_t)5 * n + np + 16;
+    // workspace: r, r', z, p, p', q, t (n each), partials, scalars
+    const size_t need = (size_t)kWorkVectors * n + np + 16;
     DevBuf own;
     double *ws = nullptr;
     if (P && P->work_elems >= need) {
@@ -546,8 +644,9 @@ int pcg_solve(const afsai_csr *A, afsai_precond P, const double *b, double *x, d
         if ((rc = dalloc(own, need * sizeof(double), s))) return rc;
         ws = own.as<double>();
     }
-    double *r = ws, *z = ws + n, *p = ws + 2 * (size_t)n, *q = ws + 3 * (size_t)n, *t = ws + 4 * (size_t)n;
-    double *partials = ws + 5 * (size_t)n;
+    double *r = ws, *r2 = ws + n, *z = ws + 2 * (size_t)n, *p = ws + 3 * (size_t)n, *p2 = ws + 4 * (size_t)n;
+    double *q = ws + 5 * (size_t)n, *t = ws + 6 * (size_t)n;
+    double *partials = ws + kWorkVectors * (size_t)n;
     PcgScalars *sc = (PcgScalars *)(partials + np);
     // pinned host copies of the scalars, one pair per thread for the life of the process
     static thread_local PcgScalars *hsc = nullptr;
@@ -558,7 +657,7 @@ int pcg_solve(const afsai_csr *A, afsai_precond P, const double *b, double *x, d
     const bool use_sell = option(AFSAI_OPT_PCG_CSR_A) == 0;
     if (use_sell) {
         ProfScope ps("sell_A", s);
-        if ((rc = sell_from_csr(n, A->row_ptr, A->col_idx, A->val, false, false, &As, di, s))) return rc;
+        if ((rc = sell_from_csr(n, A->nnz, A->row_ptr, A->col_idx, A->val, false, false, &As, di, s))) return rc;
     }
     struct SellGuard {
         Sell *S;
@@ -579,7 +678,8 @@ int pcg_solve(const afsai_csr *A, afsai_precond P, const double *b, double *x, d
     hipLaunchKernelGGL(k_set_scalars, dim3(1), dim3(64), 0, s, sc, rtol, maxit, plain);
     // r0 = b - A x0
     spmv_A("spmv_A", x, q, nullptr, FIN_NONE, nullptr);
-    hipLaunchKernelGGL(k_init_residual, dim3(nbv), dim3(kThreads), 0, s, n, b, q, r, partials, sc);
+    hipLaunchKernelGGL(k_init_residual, dim3(nbv), dim3(kThreads), 0, s, n, b, q, r, partials);
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kThreads), 0, s, partials, nbv, (int)FIN_INIT, sc);
     // z0 = M^-1 r0, rho0 = r0.z0, p0 = z0
     const double *zz = z;
     if (P) {
@@ -588,18 +688,36 @@ int pcg_solve(const afsai_csr *A, afsai_precond P, const double *b, double *x, d
     } else {
         zz = r;
     }
-    hipLaunchKernelGGL(k_update_p, dim3(nbv), dim3(kThreads), 0, s, n, p, zz, sc, 1, di.num_xcds);
+    // fused iteration (preconditioned, A in SELL-64): p and r are double-buffered because the
+    // products read neighbours' old entries while owners store the new ones
+    const bool fused = P && use_sell && option(AFSAI_OPT_PCG_UNFUSED) == 0;
+    if (!fused) hipLaunchKernelGGL(k_update_p, dim3(nbv), dim3(kThreads), 0, s, n, p, zz, sc, 1, di.num_xcds);
+    int iter_no = 0;  // iterations enqueued so far
 
     // timer marks: after the update of each iteration (launches past the last iteration that
     // ran are dropped from the kernel timer at the end)
     std::vector<int> marks;
     const int mark0 = prof_mark();
     auto enqueue_iteration = [&]() {
+        if (fused) {
+            const bool odd = (iter_no & 1) == 0;  // iteration 1, 3, ...: p -> p2, r -> r2
+            double *p_old = odd ? p : p2, *p_new = odd ? p2 : p;
+            double *r_old = odd ? r : r2, *r_new = odd ? r2 : r;
+            sell_fused<FUSE_AP>("spmv_A_dot", As, z, p_old, p_new, nullptr, nullptr, q, partials, sc,
+                                iter_no == 0 ? 1 : 0, FIN_ALPHA, di, s);
+            sell_fused<FUSE_GR>("spmv_G_upd", P->sg, r_old, q, r_new, x, p_new, t, partials, sc, 0, FIN_UPDATE,
+                                di, s);
+            marks.push_back(prof_mark());
+            sell_spmv("spmv_GT_dot", P->sgt, t, z, r_new, partials, sc, FIN_BETA, di, s);
+            ++iter_no;
+            return;
+        }
         spmv_A("spmv_A_dot", p, q, p, FIN_ALPHA, sc);
         {
             ProfScope ps("update_xr", s);
             hipLaunchKernelGGL(k_update_xr, dim3(nbv), dim3(kThreads), 0, s, n, x, r, p, q, partials, sc, di.num_xcds);
         }
+        hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kThreads), 0, s, partials, nbv, (int)FIN_UPDATE, sc);
         marks.push_back(prof_mark());
         if (P) {
             sell_spmv("spmv_G", P->sg, r, t, nullptr, nullptr, sc, FIN_NONE, di, s);
@@ -609,6 +727,7 @@ int pcg_solve(const afsai_csr *A, afsai_precond P, const double *b, double *x, d
             ProfScope ps("update_p", s);
             hipLaunchKernelGGL(k_update_p, dim3(nbv), dim3(kThreads), 0, s, n, p, zz, sc, 0, di.num_xcds);
         }
+        ++iter_no;
     };
 
     // Chunks of iterations; the state after chunk c is read while chunk c+1 is already queued.
@@ -674,9 +793,11 @@ int pcg_solve(const afsai_csr *A, afsai_precond P, const double *b, double *x, d
     if (fin_s.done != DONE_ZERO_RHS) {
         // true residual ||b - A x||
         spmv_A("spmv_A", x, q, nullptr, FIN_NONE, nullptr);
-        double *d_out = partials + np - 8;
-        hipLaunchKernelGGL(k_resid_norm, dim3(nbv), dim3(kThreads), 0, s, n, b, q, partials, sc, d_out);
-        AFSAI_HIP_TRY(hipMemcpyAsync(&true_rr, d_out, sizeof(double), hipMemcpyDeviceToHost, s));
+        hipLaunchKernelGGL(k_resid_norm, dim3(nbv), dim3(kThreads), 0, s, n, b, q, partials);
+        hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kThreads), 0, s, partials, nbv, (int)FIN_RESID, sc);
+        AFSAI_HIP_TRY(hipMemcpyAsync(&hsc[0], sc, sizeof(PcgScalars), hipMemcpyDeviceToHost, s));
+        AFSAI_HIP_TRY(hipStreamSynchronize(s));
+        true_rr = hsc[0].resid;
     }
     AFSAI_HIP_TRY(hipEventRecord(t1, s));
     AFSAI_HIP_TRY(hipStreamSynchronize(s));

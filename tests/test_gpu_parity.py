@@ -336,6 +336,27 @@ def test_pcg_edge_cases(af):
     assert info.status == af.ERR_NOT_SPD
 
 
+@pytest.mark.parametrize("opt", ["unfused", "csr_a"])
+def test_pcg_forms_identical(af, opt):
+    """The fused iteration equals the separate update kernels bit for bit; the CSR product for
+    A agrees with the SELL-64 one to rounding (same iteration count)."""
+    Pb = synth.elasticity27(10)
+    dA = _dev(af, Pb.A)
+    P = af.setup(dA, 10, 2, 1e-2)
+    x1, i1 = af.pcg_solve(dA, P, _vec(Pb.b))
+    o = af.OPT_PCG_UNFUSED if opt == "unfused" else af.OPT_PCG_CSR_A
+    try:
+        af.set_option(o, 1)
+        x2, i2 = af.pcg_solve(dA, P, _vec(Pb.b))
+    finally:
+        af.set_option(o, 0)
+    assert i1.iters == i2.iters
+    if opt == "unfused":
+        assert bool((x1 == x2).all())
+    else:
+        assert float((x1 - x2).norm() / x1.norm()) < X_RTOL
+
+
 def test_pcg_deterministic(af):
     Pb = synth.elasticity27(12)
     dA = _dev(af, Pb.A)
