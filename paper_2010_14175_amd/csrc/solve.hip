@@ -57,10 +57,11 @@ __device__ __forceinline__ double block_sum(double v, double *sh /* >= kThreads/
     return t;  // valid in thread 0
 }
 
-// thread 0 stores this block's partial sums, slot k at partials[k * gridDim.x + blockIdx.x]
-__device__ __forceinline__ void store_partials(double *partials, int slots, const double *mine) {
+// thread 0 stores this block's partial sums, slot k at partials[k * gridDim.x + idx], idx being
+// the index of the block's range of rows (so the sums are added in row order)
+__device__ __forceinline__ void store_partials(double *partials, int slots, const double *mine, int idx) {
     if (threadIdx.x == 0)
-        for (int k = 0; k < slots; ++k) partials[(size_t)k * gridDim.x + blockIdx.x] = mine[k];
+        for (int k = 0; k < slots; ++k) partials[(size_t)k * gridDim.x + idx] = mine[k];
 }
 
 // One block: sums the partials of the previous kernel in block order and updates the scalars.
@@ -171,7 +172,7 @@ __global__ __launch_bounds__(kThreads) void k_spmv(int n, const int32_t *__restr
     }
     if (DOT) {
         const double bs = block_sum(part, sh);
-        store_partials(partials, 1, &bs);
+        store_partials(partials, 1, &bs, lb);
     }
 }
 
@@ -224,7 +225,7 @@ __global__ __launch_bounds__(kThreads) void k_sell_spmv(int n, int nslices, cons
     }
     if (DOT) {
         const double bs = block_sum(part, sh);
-        store_partials(partials, 1, &bs);
+        store_partials(partials, 1, &bs, lb);
     }
 }
 
@@ -239,6 +240,7 @@ enum : int { FUSE_AP = 1, FUSE_GR = 2 };
 
 template <int U, typename VT, int MODE>
 __global__ __launch_bounds__(kThreads) void k_sell_fused(int n, int nslices, const uint32_t *__restrict__ sptr,
+                                                          const int32_t *__restrict__ perm,
                                                           const int32_t *__restrict__ col,
                                                           const VT *__restrict__ val,
                                                           const double *__restrict__ va,   // z | r_old
@@ -259,7 +261,8 @@ __global__ __launch_bounds__(kThreads) void k_sell_fused(int n, int nslices, con
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
     double part = 0.0;
     for (int sl = s0 + wv; sl < s1; sl += kThreads / 64) {
-        const int r = sl * kSlice + lane;
+        int r = sl * kSlice + lane;
+        if (perm) r = perm[r];
         const uint32_t c0 = sptr[sl];
         const int width = (int)(sptr[sl + 1] - c0);
         const int64_t base = (int64_t)c0 * kSlice + lane;
@@ -284,7 +287,7 @@ __global__ __launch_bounds__(kThreads) void k_sell_fused(int n, int nslices, con
                     acc = fma((double)v[u], xv, acc);
                 }
         }
-        if (r < n) {
+        if (r >= 0 && r < n) {
             const double own = (MODE == FUSE_AP && first) ? va[r] : fma(coef, vb[r], va[r]);
             own_out[r] = own;
             y[r] = acc;
@@ -297,7 +300,7 @@ __global__ __launch_bounds__(kThreads) void k_sell_fused(int n, int nslices, con
         }
     }
     const double bs = block_sum(part, sh);
-    store_partials(partials, 1, &bs);
+    store_partials(partials, 1, &bs, lb);
 }
 
 // r = b - q ; partials of b.b and r.r ; finalisation checks ||b|| = 0 and ||r0|| <= tol
@@ -318,7 +321,7 @@ __global__ __launch_bounds__(kThreads) void k_init_residual(int n, const double 
     double mine[2];
     mine[0] = block_sum(pb, sh);
     mine[1] = block_sum(pr, sh);
-    store_partials(partials, 2, mine);
+    store_partials(partials, 2, mine, blockIdx.x);
 }
 
 // x += alpha p ; r -= alpha q ; ||r||^2 ; convergence test; (plain CG) beta = rr'/rr
@@ -342,7 +345,7 @@ __global__ __launch_bounds__(kThreads) void k_update_xr(int n, double *__restric
         pr = fma(ri, ri, pr);
     }
     const double bs = block_sum(pr, sh);
-    store_partials(partials, 1, &bs);
+    store_partials(partials, 1, &bs, lb);
 }
 
 // p = z + beta p   (first = 1: p = z)
@@ -387,7 +390,7 @@ __global__ __launch_bounds__(kThreads) void k_resid_norm(int n, const double *__
         pr = fma(d, d, pr);
     }
     const double bs = block_sum(pr, sh);
-    store_partials(partials, 1, &bs);
+    store_partials(partials, 1, &bs, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -525,8 +528,8 @@ template <int U, typename VT, int MODE>
 static void launch_fused_t(const Sell &S, const double *va, const double *vb, double *own, double *x,
                            const double *pn, double *y, double *partials, PcgScalars *sc, int first, int nb, int nxcd,
                            hipStream_t s) {
-    hipLaunchKernelGGL((k_sell_fused<U, VT, MODE>), dim3(nb), dim3(kThreads), 0, s, S.n, S.nslices, S.sptr, S.col,
-                       (const VT *)S.val, va, vb, own, x, pn, y, partials, sc, first, nxcd);
+    hipLaunchKernelGGL((k_sell_fused<U, VT, MODE>), dim3(nb), dim3(kThreads), 0, s, S.n, S.nslices, S.sptr, S.perm,
+                       S.col, (const VT *)S.val, va, vb, own, x, pn, y, partials, sc, first, nxcd);
 }
 
 template <typename VT, int MODE>
@@ -541,7 +544,7 @@ static void launch_fused_v(const Sell &S, int un, const double *va, const double
     }
 }
 
-// fused product (rows in natural order only) followed by the finalisation of its dot
+// fused product followed by the finalisation of its dot
 template <int MODE>
 static void sell_fused(const char *name, const Sell &S, const double *va, const double *vb, double *own, double *x,
                        const double *pn, double *y, double *partials, PcgScalars *sc, int first, int fin,

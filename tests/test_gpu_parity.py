@@ -314,6 +314,12 @@ def test_pcg_edge_cases(af):
     Pb = synth.poisson7(9)
     dA = _dev(af, Pb.A)
     P = af.setup(dA, 4, 1, 1e-2)
+    G = oracle.setup(Pb.A, 4, 1, 1e-2)
+    for maxit in (1, 2, 3, 7):
+        xm, im = af.pcg_solve(dA, P, _vec(Pb.b), maxit=maxit)
+        rom = oracle.pcg(Pb.A, G, Pb.b, 1e-8, maxit=maxit)
+        assert im.iters == maxit
+        assert np.linalg.norm(xm.cpu().numpy() - rom.x) <= X_RTOL * np.linalg.norm(rom.x), maxit
     # zero right-hand side
     x, info = af.pcg_solve(dA, P, torch.zeros(Pb.n, dtype=torch.float64, device="cuda"),
                            x=torch.ones(Pb.n, dtype=torch.float64, device="cuda"))
@@ -336,11 +342,13 @@ def test_pcg_edge_cases(af):
     assert info.status == af.ERR_NOT_SPD
 
 
-@pytest.mark.parametrize("opt", ["unfused", "csr_a"])
-def test_pcg_forms_identical(af, opt):
+@pytest.mark.parametrize("opt,make", [("unfused", lambda: synth.elasticity27(10)), ("csr_a", lambda: synth.elasticity27(10)),
+                                      ("unfused", lambda: synth.poisson7(9)), ("csr_a", lambda: synth.poisson7(9))])
+def test_pcg_forms_identical(af, opt, make):
     """The fused iteration equals the separate update kernels bit for bit; the CSR product for
-    A agrees with the SELL-64 one to rounding (same iteration count)."""
-    Pb = synth.elasticity27(10)
+    A agrees with the SELL-64 one to rounding (same iteration count).  The 9^3 Poisson matrix
+    has enough short boundary rows to get the length-sorted SELL layout."""
+    Pb = make()
     dA = _dev(af, Pb.A)
     P = af.setup(dA, 10, 2, 1e-2)
     x1, i1 = af.pcg_solve(dA, P, _vec(Pb.b))
