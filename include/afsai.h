@@ -188,9 +188,9 @@ const char *afsai_last_error(void);
 
 /*
  * afsai_set_option -- process-wide tuning knobs (0 restores the automatic choice):
- *   AFSAI_OPT_SETUP_FORM_LDS  1: always use the LDS form of the per-row setup kernel (the
- *                             register form is otherwise used for patterns of at most 32
- *                             entries and s <= 4; both give identical G)
+ *   AFSAI_OPT_SETUP_GROUP     rows appended to a row's Cholesky factor together in one
+ *                             update of the per-row setup kernel (1..4; any choice gives
+ *                             identical G)
  *   AFSAI_OPT_SETUP_TABLE     slots of the first on-chip candidate table (power of two,
  *                             128..1024)
  *   AFSAI_OPT_SPMV_GROUP      lanes per row of the CSR products (4, 8, 16, 32 or 64)
@@ -203,7 +203,7 @@ const char *afsai_last_error(void);
  * Returns AFSAI_ERR_INVALID_ARG for an unknown option or value.  Not thread safe against
  * concurrent calls of the library.
  */
-#define AFSAI_OPT_SETUP_FORM_LDS 1
+#define AFSAI_OPT_SETUP_GROUP 1
 #define AFSAI_OPT_SETUP_TABLE 2
 #define AFSAI_OPT_SPMV_GROUP 3
 #define AFSAI_OPT_SPMV_UNROLL 4

@@ -10,8 +10,8 @@
  * Method (Isotton, Janna, Bernaschi, "A GPU-accelerated adaptive FSAI preconditioner for
  * massively parallel simulations", Sec. 2):
  *   - G is lower triangular and M^-1 = G^T G approximates A^-1 (eq. prec).
- *   - Row i of G on the pattern P_i (ascending, i last) is the solution of the dense SPD
- *     system A[P_i,P_i] y = e_m (eq. DensSys), scaled so that (G A G^T)_ii = 1 (eq. diagScal).
+ *   - Row i of G on the pattern P_i (i last) is the solution of the dense SPD system
+ *     A[P_i,P_i] y = e_m (eq. DensSys), scaled so that (G A G^T)_ii = 1 (eq. diagScal).
  *     With A[P_i,P_i] = L L^T this row equals L^-T e_m (the last row of L^-1), and
  *     psi_i = g~_i^T A g~_i of the unit-diagonal row equals L_mm^2, the Schur complement
  *     A_ii - A[i,Pbar] A[Pbar,Pbar]^-1 A[Pbar,i].
@@ -30,6 +30,13 @@
  *     over the candidates left; candidates with |v_j| <= 2^-40 * max are not eligible; a row
  *     with no eligible candidate stops growing.
  *   - psi_{0,i} = a_ii (G_0 = I); the exit test is applied after each step's solve.
+ *   - the paper treats P_i as a set and names only a batched Cholesky decomposition (Sec. 3).
+ *     Here the off-diagonal positions are ordered by when they joined the pattern (step by
+ *     step, within a step in selection order) with i last, and A[P,P] is factorised in that
+ *     order in the column-scaling form: each pivot's reciprocal is formed once and the entries
+ *     below it are multiplied by it (as in LAPACK's unblocked Cholesky); the back substitution
+ *     multiplies by the same reciprocals.  In exact arithmetic neither choice changes G; they
+ *     fix the rounding sequence.  Rows of G are returned with ascending columns.
  *   - PCG: textbook PCG with x0 given, stopping when ||r_k||_2 <= rtol ||b||_2 on the
  *     recursively updated residual (the paper only says the initial residual is reduced by
  *     eight orders of magnitude).
@@ -65,14 +72,10 @@ static double csr_entry(const int32_t *rp, const int32_t *ci, const double *av, 
     return 0.0;
 }
 
-static int in_sorted(const int32_t *P, int m, int32_t j)
+static int in_pattern(const int32_t *P, int m, int32_t j)
 {
-    int lo = 0, hi = m - 1;
-    while (lo <= hi) {
-        int mid = (lo + hi) / 2;
-        if (P[mid] == j) return 1;
-        if (P[mid] < j) lo = mid + 1; else hi = mid - 1;
-    }
+    for (int t = 0; t < m; ++t)
+        if (P[t] == j) return 1;
     return 0;
 }
 
@@ -101,18 +104,24 @@ typedef struct {
     int32_t *elig;    /* eligible candidates */
     double *B;        /* gathered dense block, mmax*mmax, row-major */
     double *L;        /* Cholesky factor, mmax*mmax, row-major, lower part */
+    double *dinv;     /* reciprocals of the pivots L[c][c], mmax */
+    int32_t *P;       /* pattern in growth order, i last, mmax */
+    double *g;        /* scaled row on P, mmax */
 } work_t;
 
 /*
- * One row of the adaptive FSAI setup (Sec. 2).  On return P[0..m-1] (ascending, i last)
- * and g[0..m-1] hold row i of the scaled factor G; psi_hist[k] holds psi_{k,i} for the
- * steps taken (psi_hist[0] = a_ii).
+ * One row of the adaptive FSAI setup (Sec. 2).  While the row grows, w->P[0..m-1] holds the
+ * pattern in growth order (i last) and w->g the scaled row on it.  On return cols[0..m-1]
+ * (ascending) and vals[0..m-1] hold row i of the scaled factor G; psi_hist[k] holds psi_{k,i}
+ * for the steps taken (psi_hist[0] = a_ii).
  */
 static int afsai_row(int32_t i, const int32_t *rp, const int32_t *ci, const double *av,
                      int32_t kmax, int32_t s, double eps, double tau, work_t *w,
-                     int32_t *P, double *g, int32_t *m_out, double *psi_hist,
+                     int32_t *cols, double *vals, int32_t *m_out, double *psi_hist,
                      int32_t *steps_out, int32_t *reason_out)
 {
+    int32_t *P = w->P;
+    double *g = w->g;
     /* G_0 = I scaled (Sec. 2, adaptive part; eq. diagScal): P = {i}, g = a_ii^{-1/2} */
     double aii = csr_entry(rp, ci, av, i, i);
     if (!(aii > 0.0) || !isfinite(aii)) return OR_ERR_NOT_SPD;
@@ -125,7 +134,7 @@ static int afsai_row(int32_t i, const int32_t *rp, const int32_t *ci, const doub
 
     for (int32_t k = 1; k <= kmax; ++k) {
         /* Kaporin gradient (eq. grapsi): v_j = sum_{r in P} a_rj g_r for j < i, accumulated
-         * over r in ascending order; a_rj = a_jr by symmetry, so this is (A g)_j. */
+         * over r in pattern order; a_rj = a_jr by symmetry, so this is (A g)_j. */
         int32_t nt = 0;
         for (int32_t t = 0; t < m; ++t) {
             int32_t r = P[t];
@@ -145,7 +154,7 @@ static int afsai_row(int32_t i, const int32_t *rp, const int32_t *ci, const doub
         int32_t ncand = 0;
         for (int32_t q = 0; q < nt; ++q) {
             int32_t j = w->touched[q];
-            if (in_sorted(P, m, j)) continue;
+            if (in_pattern(P, m, j)) continue;
             ++ncand;
             double a = fabs(w->v[j]);
             if (a > M) M = a;
@@ -155,7 +164,7 @@ static int afsai_row(int32_t i, const int32_t *rp, const int32_t *ci, const doub
             double thr = 0x1.0p-40 * M;
             for (int32_t q = 0; q < nt; ++q) {
                 int32_t j = w->touched[q];
-                if (in_sorted(P, m, j)) continue;
+                if (in_pattern(P, m, j)) continue;
                 if (fabs(w->v[j]) > thr) w->elig[nel++] = j;
             }
         }
@@ -183,19 +192,20 @@ static int afsai_row(int32_t i, const int32_t *rp, const int32_t *ci, const doub
             reason = OR_STOP_NOCAND;
             break;
         }
-        /* enlarge the pattern; keep it ascending (i stays last because every j < i) */
+        /* enlarge the pattern: the new positions follow the old ones in selection order, and
+         * i moves to the end */
         for (int32_t q = 0; q < ns; ++q) {
-            int32_t j = S[q], t = m;
-            while (t > 0 && P[t - 1] > j) { P[t] = P[t - 1]; --t; }
-            P[t] = j;
+            P[m - 1] = S[q];
+            P[m] = i;
             ++m;
         }
         /* systems gather: B = A[P,P] (lower part, row P[p] column P[q], q <= p) */
         for (int32_t p = 0; p < m; ++p)
             for (int32_t q = 0; q <= p; ++q) w->B[p * m + q] = csr_entry(rp, ci, av, P[p], P[q]);
         /* Cholesky A[P,P] = L L^T, one column after another; inner products in ascending
-         * index order */
+         * position order; the entries below a pivot are multiplied by its reciprocal */
         double *L = w->L;
+        double *dinv = w->dinv;
         for (int32_t c = 0; c < m; ++c) {
             for (int32_t r = c; r < m; ++r) {
                 double acc = w->B[r * m + c];
@@ -203,18 +213,19 @@ static int afsai_row(int32_t i, const int32_t *rp, const int32_t *ci, const doub
                 if (r == c) {
                     if (!(acc > 0.0) || !isfinite(acc)) return OR_ERR_NOT_SPD;
                     L[c * m + c] = sqrt(acc);
+                    dinv[c] = 1.0 / L[c * m + c];
                 } else {
-                    L[r * m + c] = acc / L[c * m + c];
+                    L[r * m + c] = acc * dinv[c];
                 }
             }
         }
         /* g = L^-T e_m by back substitution (eq. DensSys scaled by eq. diagScal);
-         * sums over l taken from the last index down */
-        g[m - 1] = 1.0 / L[(m - 1) * m + (m - 1)];
+         * sums over l taken from the last position down */
+        g[m - 1] = dinv[m - 1];
         for (int32_t t = m - 2; t >= 0; --t) {
             double acc = 0.0;
             for (int32_t l = m - 1; l > t; --l) acc = acc + L[l * m + t] * g[l];
-            g[t] = -(acc / L[t * m + t]);
+            g[t] = -(acc * dinv[t]);
         }
         double lmm = L[(m - 1) * m + (m - 1)];
         double psi = lmm * lmm;
@@ -225,6 +236,17 @@ static int afsai_row(int32_t i, const int32_t *rp, const int32_t *ci, const doub
             reason = OR_STOP_EPS;
             break;
         }
+    }
+    /* the row of G with ascending columns */
+    for (int32_t t = 0; t < m; ++t) {
+        int32_t u = t;
+        while (u > 0 && cols[u - 1] > P[t]) {
+            cols[u] = cols[u - 1];
+            vals[u] = vals[u - 1];
+            --u;
+        }
+        cols[u] = P[t];
+        vals[u] = g[t];
     }
     *m_out = m;
     *steps_out = steps;
@@ -272,8 +294,11 @@ int oracle_afsai_rows(int32_t n, const int32_t *rp, const int32_t *ci, const dou
         w.elig = (int32_t *)malloc(sizeof(int32_t) * cap);
         w.B = (double *)malloc(sizeof(double) * (size_t)mmax * mmax);
         w.L = (double *)malloc(sizeof(double) * (size_t)mmax * mmax);
+        w.dinv = (double *)malloc(sizeof(double) * (size_t)mmax);
+        w.P = (int32_t *)malloc(sizeof(int32_t) * (size_t)mmax);
+        w.g = (double *)malloc(sizeof(double) * (size_t)mmax);
         double *psi = (double *)malloc(sizeof(double) * (size_t)(kmax + 1));
-        if (!w.v || !w.mark || !w.touched || !w.elig || !w.B || !w.L || !psi) {
+        if (!w.v || !w.mark || !w.touched || !w.elig || !w.B || !w.L || !w.dinv || !w.P || !w.g || !psi) {
 #pragma omp atomic write
             nomem = 1;
         } else {
@@ -292,7 +317,8 @@ int oracle_afsai_rows(int32_t n, const int32_t *rp, const int32_t *ci, const dou
                 if (psi_out) memcpy(psi_out + (size_t)q * (kmax + 1), psi, sizeof(double) * (size_t)(kmax + 1));
             }
         }
-        free(w.v); free(w.mark); free(w.touched); free(w.elig); free(w.B); free(w.L); free(psi);
+        free(w.v); free(w.mark); free(w.touched); free(w.elig); free(w.B); free(w.L);
+        free(w.dinv); free(w.P); free(w.g); free(psi);
     }
     int rc = nomem ? OR_ERR_NO_MEMORY : OR_OK;
     for (int32_t q = 0; q < nrows && rc == OR_OK; ++q)

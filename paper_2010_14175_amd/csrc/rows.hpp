@@ -2,29 +2,31 @@
 // systems-gather and batched-Cholesky kernels of Sec. 3 merged into one).
 //
 // One 64-lane wavefront owns one row i for all of its growth steps, so the pattern P_i, the
-// scaled row g_i, the candidate table and the dense block A[P_i,P_i] stay on chip.  Per step:
+// scaled row g_i, the Cholesky factor of A[P_i,P_i] and the candidate table stay on chip.
 //
-//  1. product pass over the rows r in P_i: every stored entry a_rc with c <= i is looked up in
-//     an LDS open-addressing table.  Members of P_i were entered first, tagged with their
-//     position; their entries fill A[P,P] (lower part, taken from the row of the larger index).
-//     Any other column is a candidate and accumulates v_c += a_rc g_r = (A g)_c by symmetry,
-//     the Kaporin gradient of eq. grapsi up to a positive factor.
+// The pattern is kept in growth order: position t < m-1 holds the t-th column that joined the
+// pattern, i is last.  A[P,P] = L L^T in that order means that the rows of L for the old
+// positions never change when the pattern grows: a step only appends the rows of its new
+// positions (a forward substitution against the stored rows) and redoes the new columns of
+// the last row.  Every entry still receives exactly the operations of a from-scratch,
+// column-by-column factorisation in that order (entries below a pivot multiplied by the
+// pivot's reciprocal), so G is bit-identical to such a factorisation.  Per step:
+//
+//  1. product pass over the rows r in P_i, entries a_rc with c < i only (the part of each row
+//     left of column i, a prefix): c is looked up in an LDS open-addressing table.  Members of
+//     P_i were entered first, tagged; any other column is a candidate and accumulates
+//     v_c += a_rc g_r = (A g)_c by symmetry, the Kaporin gradient of eq. grapsi up to a
+//     positive factor.
 //  2. selection: the largest |v_c| over the candidates, then s rounds of "largest |v|, ties
 //     within the relative band tie_rtol go to the smallest column" (64-lane reductions).
-//  3. gather: A[P,P] is re-indexed to the enlarged pattern; only the s new rows are read.
-//  4. Cholesky A[P,P] = L L^T, g = L^-T e_m (eq. DensSys with the scaling of eq. diagScal),
-//     psi = L_mm^2, in FP64.
-//  5. exit test psi / psi_0 <= eps (eq. exit_crit).
-//
-// Two forms of steps 3-4, chosen at compile time:
-//  REG  (patterns of at most 32 entries, s <= 4): lane p holds row p of the block in registers;
-//       the factorisation and the back substitution exchange values with v_readlane, with no
-//       LDS traffic and no barriers;
-//  LDS  (any pattern up to 64 entries): the block lives in LDS, one column step at a time.
-// Both apply the same operations in the same order as a column-by-column textbook Cholesky
-// with separately rounded products and sums, so G is identical in either form.  The gradient
-// accumulation uses LDS atomics (order not fixed); it only ranks candidates, and the tie band
-// absorbs rounding noise.
+//  3. gather of the new rows A[u, P] (their entries with column <= i).
+//  4. factor update: the new rows of L and the new columns of the last row, at most kGMax
+//     rows at a time; lanes own entries of the rows being appended, column j's values are
+//     broadcast with v_readlane and applied right-looking.
+//  5. back substitution L^T g = e_m from the last position down (eq. DensSys with the scaling
+//     of eq. diagScal), psi = L_mm^2, exit test psi / psi_0 <= eps (eq. exit_crit).
+// The gradient accumulation uses LDS atomics (order not fixed); it only ranks candidates, and
+// the tie band absorbs rounding noise.
 #pragma once
 
 #include "common.hpp"
@@ -35,7 +37,7 @@ namespace afsai {
 
 constexpr uint32_t kEmpty = 0xFFFFFFFFu;
 constexpr uint32_t kPBit = 0x80000000u;
-constexpr int kRegSMax = 4;  // new rows per step held by the REG form
+constexpr int kGMax = 4;  // rows appended to the factor together
 
 enum : int8_t { ROW_OK = 0, ROW_OVERFLOW = 1, ROW_BAD = 2, ROW_NOT_SPD = 3 };
 enum : int32_t { STOP_KMAX = 0, STOP_EPS = 1, STOP_NOCAND = 2 };
@@ -83,25 +85,6 @@ __device__ __forceinline__ int seg_of(const int32_t *off, int cnt, int e) {
     return lo;
 }
 
-// Offsets of the concatenation of rows list[0..cnt) (cnt <= 64); off[cnt] = total.
-__device__ __forceinline__ int stage_rows(const int32_t *__restrict__ rp, const int32_t *list, int cnt,
-                                          int32_t *off, int32_t *beg) {
-    const int lane = threadIdx.x;
-    int len = 0;
-    if (lane < cnt) {
-        const int r = list[lane];
-        const int b = rp[r];
-        len = rp[r + 1] - b;
-        beg[lane] = b;
-    }
-    const int incl = wave_incl_scan(len);
-    if (lane < cnt) off[lane] = incl - len;
-    const int total = __shfl(incl, cnt - 1, 64);
-    if (lane == 0) off[cnt] = total;
-    __syncthreads();
-    return total;
-}
-
 // value of v in lane `src` (src uniform)
 __device__ __forceinline__ double rl(double v, int src) {
     const int lo = __builtin_amdgcn_readlane(__double2loint(v), src);
@@ -109,34 +92,38 @@ __device__ __forceinline__ double rl(double v, int src) {
     return __hiloint2double(hi, lo);
 }
 
+// entries of one factor update that appends g rows to mb final rows: row v of the new ones
+// has columns 0..mb+v, the last row (i) has the g new columns and its diagonal
+__host__ __device__ __forceinline__ int upd_entries(int mb, int g) { return g * (mb + 1) + (g * (g - 1)) / 2 + g + 1; }
+// index of entry (v, c) of new row v, and of the last row's entry at column mb + d
+__device__ __forceinline__ int upd_index(int mb, int v, int c) { return v * (mb + 1) + (v * (v - 1)) / 2 + c; }
+
 constexpr int kUnroll = 8;
 
-template <int MMAX, int CAP, bool REG>
+template <int MMAX, int CAP>
 __global__ __launch_bounds__(64) void k_afsai_rows(
     int n, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci, const double *__restrict__ av,
-    const double *__restrict__ diag, int kmax, int s, double eps, double tau, const int32_t *__restrict__ list,
-    int nlist, int32_t *__restrict__ counters, int nxcd, int32_t *__restrict__ ell_col, double *__restrict__ ell_val,
-    int ldell, int32_t *__restrict__ m_out, double *__restrict__ psi_out, int32_t *__restrict__ steps_out,
-    int32_t *__restrict__ reason_out, int8_t *__restrict__ status_out, int32_t *__restrict__ ovf_count,
-    int32_t *__restrict__ ovf_list) {
-    static_assert(!REG || MMAX <= 32, "register form holds at most 32 rows");
-    constexpr int TRI = MMAX * (MMAX + 1) / 2;
-    constexpr int SPL = CAP / 64;        // table slots per lane
-    constexpr bool SEL_REG = SPL <= 16;  // selection from registers
+    const double *__restrict__ diag, const int32_t *__restrict__ dlo, int kmax, int s, double eps, double tau,
+    int gmax, const int32_t *__restrict__ list, int nlist, int32_t *__restrict__ counters, int nxcd,
+    int32_t *__restrict__ ell_col, double *__restrict__ ell_val, int ldell, int32_t *__restrict__ m_out,
+    double *__restrict__ psi_out, int32_t *__restrict__ steps_out, int32_t *__restrict__ reason_out,
+    int8_t *__restrict__ status_out, int32_t *__restrict__ ovf_count, int32_t *__restrict__ ovf_list) {
+    constexpr int K = (MMAX + 1 + 63) / 64;           // update entries per lane
+    constexpr int LTRI = (MMAX * (MMAX - 1)) / 2;     // rows 0..MMAX-2 of L, packed lower
+    constexpr int SPL = CAP / 64;                     // table slots per lane
+    constexpr bool SEL_REG = SPL <= 16;               // selection from registers
     __shared__ uint32_t hkey[CAP];
     __shared__ double hval[CAP];
-    __shared__ double X[TRI];                          // A[P,P] of the current pattern (packed lower)
-    __shared__ double Y[REG ? 1 : TRI];                // LDS form: block of the enlarged pattern
-    __shared__ double NR[REG ? kRegSMax * MMAX : 1];   // REG form: new rows, by new position
-    __shared__ int32_t Pl[MMAX];     // pattern, ascending
-    __shared__ int32_t Pn[MMAX];     // enlarged pattern
-    __shared__ int32_t pslot[MMAX];  // table slot of each member of Pl
-    __shared__ int32_t nslot[MMAX];  // table slot of each member of Pn
-    __shared__ int32_t npos[MMAX];   // new position of old member t
-    __shared__ int32_t opos[MMAX];   // old position of new member p, or -1-u for the u-th new column
-    __shared__ double gl[MMAX];      // scaled row on Pl
-    __shared__ int32_t off[65], beg[64];
-    __shared__ int32_t sel[64], selslot[64], selpos[64];
+    __shared__ double Lp[LTRI];           // rows of L for the off-diagonal positions
+    __shared__ double dinv[MMAX];         // their reciprocal pivots
+    __shared__ double li[MMAX];           // row of i in L, columns 0..m-2
+    __shared__ double gq[MMAX];           // scaled row by position (i at m-1)
+    __shared__ int32_t Qc[MMAX];          // column of each off-diagonal position
+    __shared__ int32_t mbeg[MMAX], mlen[MMAX];  // row start and number of entries left of column i
+    __shared__ int32_t off[MMAX + 1];
+    __shared__ double NR[kGMax * MMAX];   // gathered new rows, by position (i at MMAX-1)
+    __shared__ int32_t sel[64], selslot[64];
+    __shared__ int32_t nlo[kGMax], nbeg[kGMax + 1];
     __shared__ int32_t s_row, s_flag;
 
     const int lane = threadIdx.x;
@@ -154,37 +141,43 @@ __global__ __launch_bounds__(64) void k_afsai_rows(
 
         // ---- G_0 = I scaled: P = {i}, g = a_ii^-1/2, psi_0 = a_ii
         const double aii = diag[i];
+        const int ibeg = rp[i], ilen = dlo[i];
         int8_t status = ROW_OK;
         int m = 1, steps = 0;
         int32_t reason = STOP_KMAX;
         double psi = aii;
+        double di = aii;  // last row's diagonal less the squares of its final entries
         if (!(aii > 0.0) || !isfinite(aii)) status = ROW_NOT_SPD;
-        if (lane == 0) {
-            Pl[0] = i;
-            gl[0] = 1.0 / sqrt(aii);
-        }
+        if (lane == 0) gq[0] = 1.0 / sqrt(aii);
         __syncthreads();
         const double psi0 = aii;
 
         for (int k = 1; k <= kmax && status == ROW_OK; ++k) {
-            // ---- 1. product pass: gradient on candidates, A[P,P] from the rows of P
+            // ---- 1. product pass: gradient on the candidates
             for (int j = lane; j < CAP; j += 64) {
                 hkey[j] = kEmpty;
                 hval[j] = 0.0;
             }
-            const int ntri = (m * (m + 1)) >> 1;
-            for (int j = lane; j < ntri; j += 64) X[j] = 0.0;
             if (lane == 0) s_flag = 0;
             __syncthreads();
-            if (lane < m) {
+            int len = 0;
+            if (lane < m - 1) {
+                // members are entered tagged, with their position as the slot's value
                 bool tg;
-                const uint32_t c = (uint32_t)Pl[lane];
+                const uint32_t c = (uint32_t)Qc[lane];
                 const int slot = table_find<CAP>(hkey, c, c | kPBit, true, tg);
-                pslot[lane] = slot;
-                if (slot >= 0) hval[slot] = (double)lane;  // position tag
+                if (slot >= 0) hval[slot] = (double)lane;
                 else s_flag = 1;
+                len = mlen[lane];
+            } else if (lane == m - 1) {
+                mbeg[lane] = ibeg;
+                len = ilen;
             }
-            const int total = stage_rows(rp, Pl, m, off, beg);
+            const int incl = wave_incl_scan(len);
+            if (lane < m) off[lane] = incl - len;
+            const int total = __shfl(incl, m - 1, 64);
+            if (lane == 0) off[m] = total;
+            __syncthreads();
             int tseg = 0;
             for (int base = 0; base < total; base += 64 * kUnroll) {
                 int cc[kUnroll], tt[kUnroll];
@@ -199,7 +192,7 @@ __global__ __launch_bounds__(64) void k_afsai_rows(
                         if (u == 0) tseg = seg_of(off, m, e);
                         else
                             while (off[tseg + 1] <= e) ++tseg;
-                        const int idx = beg[tseg] + (e - off[tseg]);
+                        const int idx = mbeg[tseg] + (e - off[tseg]);
                         tt[u] = tseg;
                         cc[u] = __builtin_nontemporal_load(&ci[idx]);
                         vv[u] = __builtin_nontemporal_load(&av[idx]);
@@ -207,19 +200,14 @@ __global__ __launch_bounds__(64) void k_afsai_rows(
                 }
 #pragma unroll
                 for (int u = 0; u < kUnroll; ++u) {
-                    const int c = cc[u];
-                    if (c >= 0 && c <= i) {
+                    if (cc[u] >= 0) {
                         bool tg = false;
-                        const int slot = table_find<CAP>(hkey, (uint32_t)c, (uint32_t)c, true, tg);
-                        if (slot < 0) {
+                        const int slot = table_find<CAP>(hkey, (uint32_t)cc[u], (uint32_t)cc[u], true, tg);
+                        if (slot < 0)
                             s_flag = 1;
-                        } else if (tg) {
-                            const int pc = (int)hval[slot];
-                            if (pc <= tt[u]) X[tri(tt[u], pc)] = vv[u];
-                        } else {
-                            __hip_atomic_fetch_add(&hval[slot], vv[u] * gl[tt[u]], __ATOMIC_RELAXED,
+                        else if (!tg)
+                            __hip_atomic_fetch_add(&hval[slot], vv[u] * gq[tt[u]], __ATOMIC_RELAXED,
                                                    __HIP_MEMORY_SCOPE_WORKGROUP);
-                        }
                     }
                 }
             }
@@ -318,193 +306,223 @@ __global__ __launch_bounds__(64) void k_afsai_rows(
                 break;
             }
 
-            // ---- 3. enlarged pattern and positions
+            // ---- new positions m-1 .. m+ns-2 in selection order; i moves to mn-1
             const int mn = m + ns;
-            if (lane < m) {
-                const int c = Pl[lane];
-                int add = 0;
-                for (int u = 0; u < ns; ++u) add += (sel[u] < c);
-                const int p = lane + add;
-                npos[lane] = p;
-                opos[p] = lane;
-                Pn[p] = c;
-                nslot[p] = pslot[lane];
-                hval[pslot[lane]] = (double)p;
-            } else if (lane < m + ns) {
-                const int u = lane - m;
-                const int c = sel[u];
-                int lo = 0, hi = m;  // old members below c
-                while (lo < hi) {
-                    const int mid = (lo + hi) >> 1;
-                    if (Pl[mid] < c) lo = mid + 1; else hi = mid;
-                }
-                int add = 0;
-                for (int v = 0; v < ns; ++v) add += (sel[v] < c);
-                const int p = lo + add;
-                selpos[u] = p;
-                opos[p] = -1 - u;
-                Pn[p] = c;
-                nslot[p] = selslot[u];
-                hval[selslot[u]] = (double)p;
-            }
-            if constexpr (REG) {
-                for (int j = lane; j < ns * MMAX; j += 64) NR[j] = 0.0;
-            } else {
-                const int ntn = (mn * (mn + 1)) >> 1;
-                for (int j = lane; j < ntn; j += 64) Y[j] = 0.0;
-            }
-            __syncthreads();
-            if constexpr (!REG) {
-                const float invm = 1.0f / (float)m;
-                for (int e = lane; e < m * m; e += 64) {
-                    const int a = (int)(((float)e + 0.5f) * invm);
-                    const int b = e - a * m;
-                    if (b <= a) Y[tri(npos[a], npos[b])] = X[tri(a, b)];
-                }
-            }
-            // new rows: entries (sel[u], c) with c in the enlarged pattern
-            const int tot2 = stage_rows(rp, sel, ns, off, beg);
-            for (int e = lane; e < tot2; e += 64) {
-                const int u = seg_of(off, ns, e);
-                const int idx = beg[u] + (e - off[u]);
-                const int c = ci[idx];
-                if (c <= i) {
-                    bool tg = false;
-                    const int slot = table_find<CAP>(hkey, (uint32_t)c, 0u, false, tg);
-                    if (slot >= 0 && tg) {
-                        const int pc = (int)hval[slot];
-                        if constexpr (REG) {
-                            NR[u * MMAX + pc] = av[idx];
-                        } else {
-                            const int pn = selpos[u];
-                            Y[pc <= pn ? tri(pn, pc) : tri(pc, pn)] = av[idx];
-                        }
-                    }
-                }
+            if (lane < ns) {
+                hval[selslot[lane]] = (double)(m - 1 + lane);
+                Qc[m - 1 + lane] = sel[lane];
             }
             __syncthreads();
 
-            // ---- 4. Cholesky A[P,P] = L L^T and g = L^-T e_m
+            // ---- 3./4. append the new rows to the factor, at most kGMax at a time
             bool spd = true;
-            double gx = 0.0, lmm = 0.0;
-            if constexpr (REG) {
-                // lane p holds row p of the block (columns 0..p)
-                double row[MMAX];
-                const int op = (lane < mn) ? opos[lane] : 0;
-#pragma unroll
-                for (int qq = 0; qq < MMAX; ++qq) {
-                    double v = 0.0;
-                    if (qq < mn && qq <= lane && lane < mn) {
-                        const int oq = opos[qq];
-                        if (op >= 0 && oq >= 0) v = X[tri(op, oq)];
-                        else if (op < 0) v = NR[(-1 - op) * MMAX + qq];
-                        else v = NR[(-1 - oq) * MMAX + lane];
-                    }
-                    row[qq] = v;
+            int mb = m - 1;
+            for (int v0 = 0; v0 < ns && spd;) {
+                int G = min(ns - v0, gmax);
+                while (G > 1 && upd_entries(mb, G) > 64 * K) --G;
+                const int m1 = mb + G;  // position of i within this update
+                // gather rows sel[v0 .. v0+G): NR[v][pos] for members, NR[v][MMAX-1] = a_{u,i}
+                for (int j = lane; j < G * MMAX; j += 64) NR[j] = 0.0;
+                int rlen = 0;
+                if (lane < G) {
+                    const int u = sel[v0 + lane];
+                    const int b = rp[u];
+                    rlen = rp[u + 1] - b;
+                    mbeg[mb + lane] = b;
+                    nlo[lane] = 0;
                 }
+                const int rincl = wave_incl_scan(rlen);
+                if (lane < G) nbeg[lane] = rincl - rlen;
+                const int rtot = __shfl(rincl, G - 1, 64);
+                if (lane == 0) nbeg[G] = rtot;
+                __syncthreads();
+                for (int e = lane; e < rtot; e += 64) {
+                    const int v = seg_of(nbeg, G, e);
+                    const int idx = mbeg[mb + v] + (e - nbeg[v]);
+                    const int c = ci[idx];
+                    if (c < i) {
+                        atomicAdd(&nlo[v], 1);
+                        bool tg = false;
+                        const int slot = table_find<CAP>(hkey, (uint32_t)c, 0u, false, tg);
+                        if (slot >= 0 && tg) NR[v * MMAX + (int)hval[slot]] = av[idx];
+                    } else if (c == i) {
+                        NR[v * MMAX + (MMAX - 1)] = av[idx];
+                    }
+                }
+                __syncthreads();
+                if (lane < G) mlen[mb + lane] = nlo[lane];
+
+                // update entries owned by this lane: (row r, column c); r == G is the row of i
+                const int E = upd_entries(mb, G);
+                const int ibase = upd_index(mb, G, 0);
+                int er[K], ec[K];
+                double run[K];
 #pragma unroll
-                for (int kk = 0; kk < MMAX; ++kk) {
-                    if (kk < mn && spd) {
-                        const double d2 = rl(row[kk], kk);
-                        if (!(d2 > 0.0) || !isfinite(d2)) {
-                            spd = false;
+                for (int kk = 0; kk < K; ++kk) {
+                    const int e = kk * 64 + lane;
+                    er[kk] = -1;
+                    ec[kk] = 0;
+                    run[kk] = 0.0;
+                    if (e < E) {
+                        if (e >= ibase) {
+                            const int d = e - ibase;  // 0..G-1 new columns, G the diagonal
+                            er[kk] = G;
+                            ec[kk] = mb + d;
+                            run[kk] = (d < G) ? NR[d * MMAX + (MMAX - 1)] : di;
                         } else {
-                            const double d = sqrt(d2);
-                            lmm = d;
-                            if (lane == kk) row[kk] = d;
-                            else if (lane > kk) row[kk] = row[kk] / d;
-#pragma unroll
-                            for (int c = kk + 1; c < MMAX; ++c) {
-                                if (c < mn) {
-                                    const double lck = rl(row[kk], c);
-                                    if (lane >= c) row[c] = row[c] - row[kk] * lck;
-                                }
+                            int v = 0, rest = e;
+                            while (rest >= mb + v + 1) {
+                                rest -= mb + v + 1;
+                                ++v;
                             }
+                            er[kk] = v;
+                            ec[kk] = rest;
+                            run[kk] = NR[v * MMAX + rest];
                         }
                     }
                 }
-                if (spd) {
-                    // back substitution L^T x = e_m: lane t accumulates sum_{l>t} L_lt x_l, l descending
-                    double acc = 0.0;
+                for (int j = 0; j < m1; ++j) {
+                    double dj;
+                    if (j >= mb) {
+                        // pivot of new row j - mb: its diagonal entry is final
+                        const int e = upd_index(mb, j - mb, j);
+                        double xd = 0.0;
 #pragma unroll
-                    for (int l = MMAX - 1; l >= 0; --l) {
-                        if (l < mn) {
-                            const double Lll = rl(row[l], l);
-                            const double xl = (l == mn - 1) ? 1.0 / Lll : -(rl(acc, l) / Lll);
-                            if (lane == l) gx = xl;
+                        for (int kk = 0; kk < K; ++kk)
+                            if ((e >> 6) == kk) xd = rl(run[kk], e & 63);
+                        if (!(xd > 0.0) || !isfinite(xd)) {
+                            spd = false;
+                            break;
+                        }
+                        const double Ljj = sqrt(xd);
+                        dj = 1.0 / Ljj;
 #pragma unroll
-                            for (int t = 0; t < l; ++t) {
-                                const double v = rl(row[t], l);
-                                if (lane == t) acc = acc + v * xl;
+                        for (int kk = 0; kk < K; ++kk)
+                            if ((e >> 6) == kk && lane == (e & 63)) run[kk] = Ljj;
+                        if (lane == 0) dinv[j] = dj;
+                    } else {
+                        dj = dinv[j];
+                    }
+                    // values of column j: U[v] = L[mb+v][j], U[G] = L[i][j]
+                    double U[kGMax + 1];
+#pragma unroll
+                    for (int v = 0; v <= kGMax; ++v) U[v] = 0.0;
+#pragma unroll
+                    for (int v = 0; v < kGMax; ++v) {
+                        if (v < G && j < mb + v) {
+                            const int e = upd_index(mb, v, j);
+                            double xv = 0.0;
+#pragma unroll
+                            for (int kk = 0; kk < K; ++kk)
+                                if ((e >> 6) == kk) xv = rl(run[kk], e & 63);
+                            U[v] = xv * dj;
+#pragma unroll
+                            for (int kk = 0; kk < K; ++kk)
+                                if ((e >> 6) == kk && lane == (e & 63)) run[kk] = U[v];
+                        }
+                    }
+                    if (j < mb) {
+                        U[kGMax] = li[j];
+                    } else {
+                        const int e = ibase + (j - mb);
+                        double xv = 0.0;
+#pragma unroll
+                        for (int kk = 0; kk < K; ++kk)
+                            if ((e >> 6) == kk) xv = rl(run[kk], e & 63);
+                        U[kGMax] = xv * dj;
+#pragma unroll
+                        for (int kk = 0; kk < K; ++kk)
+                            if ((e >> 6) == kk && lane == (e & 63)) run[kk] = U[kGMax];
+                    }
+                    // right-looking update of the entries right of column j
+#pragma unroll
+                    for (int kk = 0; kk < K; ++kk) {
+                        const int r = er[kk], c = ec[kk];
+                        const bool idiag = (r == G) && (c == m1);
+                        if (r >= 0 && c > j && !(idiag && j < mb)) {
+                            double a = U[kGMax];
+#pragma unroll
+                            for (int v = 0; v < kGMax; ++v)
+                                if (v == r && r < G) a = U[v];
+                            double b;
+                            if (c < mb) {
+                                b = Lp[tri(c, j)];
+                            } else if (idiag) {
+                                b = U[kGMax];
+                            } else {
+                                b = 0.0;
+#pragma unroll
+                                for (int v = 0; v < kGMax; ++v)
+                                    if (v == c - mb) b = U[v];
                             }
+                            run[kk] = run[kk] - a * b;
                         }
                     }
                 }
-            } else {
-                for (int kk = 0; kk < mn; ++kk) {
-                    const double d2 = Y[tri(kk, kk)];
-                    if (!(d2 > 0.0) || !isfinite(d2)) {
-                        spd = false;
-                        break;
-                    }
-                    const double d = sqrt(d2);
-                    const int R = mn - kk - 1;
-                    __syncthreads();
-                    if (lane < R) {
-                        const int r = kk + 1 + lane;
-                        Y[tri(r, kk)] = Y[tri(r, kk)] / d;
-                    }
-                    if (lane == 0) Y[tri(kk, kk)] = d;
-                    __syncthreads();
-                    if (R > 0) {
-                        const float invR = 1.0f / (float)R;
-                        for (int e = lane; e < R * R; e += 64) {
-                            const int tr = (int)(((float)e + 0.5f) * invR);
-                            const int tc = e - tr * R;
-                            if (tc <= tr) {
-                                const int r = kk + 1 + tr, c = kk + 1 + tc;
-                                Y[tri(r, c)] = Y[tri(r, c)] - Y[tri(r, kk)] * Y[tri(c, kk)];
-                            }
-                        }
-                    }
-                    __syncthreads();
+                if (!spd) break;
+                // store the appended rows, the last row's new entries and its running diagonal
+#pragma unroll
+                for (int kk = 0; kk < K; ++kk) {
+                    const int r = er[kk], c = ec[kk];
+                    if (r >= 0 && r < G) Lp[tri(mb + r, c)] = run[kk];
+                    else if (r == G && c < m1) li[c] = run[kk];
                 }
-                if (spd) {
-                    double acc = 0.0;
-                    for (int l = mn - 1; l >= 0; --l) {
-                        const double Lll = Y[tri(l, l)];
-                        const double accl = __shfl(acc, l, 64);
-                        const double xl = (l == mn - 1) ? 1.0 / Lll : -(accl / Lll);
-                        if (lane == l) gx = xl;
-                        if (lane < l) acc = acc + Y[tri(l, lane)] * xl;
-                    }
-                    lmm = Y[tri(mn - 1, mn - 1)];
+                {
+                    const int e = ibase + G;
+                    double xd = 0.0;
+#pragma unroll
+                    for (int kk = 0; kk < K; ++kk)
+                        if ((e >> 6) == kk) xd = rl(run[kk], e & 63);
+                    di = xd;
                 }
+                __syncthreads();
+                mb += G;
+                v0 += G;
             }
+            if (spd && (!(di > 0.0) || !isfinite(di))) spd = false;
             if (!spd) {
                 status = ROW_NOT_SPD;
                 break;
             }
-            if (lane < mn) {
-                gl[lane] = gx;
-                Pl[lane] = Pn[lane];
-                pslot[lane] = nslot[lane];
+
+            // ---- 5. g = L^-T e_m, positions from the last down
+            const double lmm = sqrt(di);
+            const double dm = 1.0 / lmm;
+            double acc = 0.0, gmine = 0.0;
+            for (int l = mn - 1; l >= 0; --l) {
+                const double gl = (l == mn - 1) ? dm : -(rl(acc, l) * dinv[l]);
+                if (lane == l) gmine = gl;
+                if (lane < l) {
+                    const double Lv = (l == mn - 1) ? li[lane] : Lp[tri(l, lane)];
+                    acc = acc + Lv * gl;
+                }
             }
+            if (lane < mn) gq[lane] = gmine;
             psi = lmm * lmm;
             m = mn;
             steps = k;
             __syncthreads();
-            // ---- 5. exit test (eq. exit_crit)
+            // ---- exit test (eq. exit_crit)
             if (psi <= eps * psi0) {
                 reason = STOP_EPS;
                 break;
             }
         }
 
-        // ---- outputs
-        if (status == ROW_OK && lane < m) {
-            ell_col[(size_t)i * ldell + lane] = Pl[lane];
-            ell_val[(size_t)i * ldell + lane] = gl[lane];
+        // ---- outputs: the row with ascending columns
+        if (status == ROW_OK) {
+            int col = 0x7fffffff;
+            double val = 0.0;
+            if (lane < m) {
+                col = (lane == m - 1) ? i : Qc[lane];
+                val = gq[lane];
+            }
+            int rank = 0;
+            for (int t = 0; t < m; ++t) rank += (__shfl(col, t, 64) < col) ? 1 : 0;
+            if (lane < m) {
+                ell_col[(size_t)i * ldell + rank] = col;
+                ell_val[(size_t)i * ldell + rank] = val;
+            }
         }
         if (lane == 0) {
             m_out[i] = (status == ROW_OK) ? m : 0;
@@ -521,22 +539,28 @@ __global__ __launch_bounds__(64) void k_afsai_rows(
     }
 }
 
-typedef void (*RowsKernel)(int, const int32_t *, const int32_t *, const double *, const double *, int, int,
-                           double, double, const int32_t *, int, int32_t *, int, int32_t *, double *, int,
+typedef void (*RowsKernel)(int, const int32_t *, const int32_t *, const double *, const double *, const int32_t *,
+                           int, int, double, double, int, const int32_t *, int, int32_t *, int, int32_t *, double *, int,
                            int32_t *, double *, int32_t *, int32_t *, int8_t *, int32_t *, int32_t *);
 
-template <int MMAX, bool REG>
+template <int MMAX>
 static RowsKernel rows_kernel_cap(int cap) {
     switch (cap) {
-        case 128: return k_afsai_rows<MMAX, 128, REG>;
-        case 256: return k_afsai_rows<MMAX, 256, REG>;
-        case 512: return k_afsai_rows<MMAX, 512, REG>;
-        case 1024: return k_afsai_rows<MMAX, 1024, REG>;
-        case 2048: return k_afsai_rows<MMAX, 2048, REG>;
-        case 4096: return k_afsai_rows<MMAX, 4096, REG>;
-        case 8192: return k_afsai_rows<MMAX, 8192, REG>;
+        case 128: return k_afsai_rows<MMAX, 128>;
+        case 256: return k_afsai_rows<MMAX, 256>;
+        case 512: return k_afsai_rows<MMAX, 512>;
+        case 1024: return k_afsai_rows<MMAX, 1024>;
+        case 2048: return k_afsai_rows<MMAX, 2048>;
+        case 4096: return k_afsai_rows<MMAX, 4096>;
+        case 8192: return k_afsai_rows<MMAX, 8192>;
         default: return nullptr;
     }
+}
+
+// LDS bytes of one k_afsai_rows<MMAX, CAP> block
+__host__ __forceinline__ size_t rows_lds_bytes(int mmax_t, int cap) {
+    return (size_t)cap * 12 + (size_t)mmax_t * (mmax_t - 1) / 2 * 8 + (size_t)mmax_t * (3 * 8 + 3 * 4) +
+           (size_t)(mmax_t + 1) * 4 + (size_t)kGMax * mmax_t * 8 + 64 * 8 + (2 * kGMax + 1) * 4 + 8;
 }
 
 }  // namespace afsai

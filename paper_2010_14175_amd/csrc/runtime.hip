@@ -228,7 +228,7 @@ int afsai_set_option(int32_t opt, int64_t value) {
     auto pow2 = [](int64_t v) { return v > 0 && (v & (v - 1)) == 0; };
     bool ok = false;
     switch (opt) {
-        case AFSAI_OPT_SETUP_FORM_LDS: ok = (value == 0 || value == 1); break;
+        case AFSAI_OPT_SETUP_GROUP: ok = (value >= 0 && value <= 4); break;
         case AFSAI_OPT_SETUP_TABLE: ok = value == 0 || (pow2(value) && value >= 128 && value <= 1024); break;
         case AFSAI_OPT_SPMV_GROUP: ok = value == 0 || (pow2(value) && value >= 4 && value <= 64); break;
         case AFSAI_OPT_SPMV_UNROLL: ok = value == 0 || (pow2(value) && value <= 8); break;

@@ -21,10 +21,11 @@ struct ScanOut {
     int32_t nodiag;    // rows without a diagonal entry
 };
 
-// max row length, diagonal of every row (binary search in the ascending row) and, when
-// validating, structure and exact symmetry
+// max row length, diagonal of every row and the number of entries left of it (binary search
+// in the ascending row) and, when validating, structure and exact symmetry
 __global__ void k_row_scan(int n, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
-                           const double *__restrict__ av, int validate, double *__restrict__ diag, ScanOut *out) {
+                           const double *__restrict__ av, int validate, double *__restrict__ diag,
+                           int32_t *__restrict__ dlo, ScanOut *out) {
     int lmax = 0, nodiag = 0;
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
         const int a = rp[i], b = rp[i + 1];
@@ -39,11 +40,13 @@ __global__ void k_row_scan(int n, const int32_t *__restrict__ rp, const int32_t 
                 if (cm == i) {
                     d = av[mid];
                     found = true;
+                    lo = mid;
                     break;
                 }
                 if (cm < i) lo = mid + 1; else hi = mid - 1;
             }
             diag[i] = d;
+            dlo[i] = found ? lo - a : 0;
             nodiag += found ? 0 : 1;
         }
         if (!validate) continue;
@@ -262,26 +265,15 @@ __global__ void k_fill_i32(int64_t n, int32_t *__restrict__ p, int32_t v) {
 // ---------------------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------------------
-// fused per-row kernels, instantiated in rows_reg.hip and rows_lds.hip
-RowsKernel rows_kernel_reg(int mmax_t, int cap);
-RowsKernel rows_kernel_lds(int mmax_t, int cap);
+// fused per-row kernels, instantiated in rows.hip
+RowsKernel rows_kernel(int mmax_t, int cap);
 
-// register form for patterns of at most 32 entries and s <= kRegSMax; LDS form otherwise
-static RowsKernel rows_kernel(int mmax_t, int cap, bool reg) {
-    return reg ? rows_kernel_reg(mmax_t, cap) : rows_kernel_lds(mmax_t, cap);
-}
-
-static size_t rows_lds_bytes(int mmax_t, int cap, bool reg) {
-    const size_t tri = (size_t)mmax_t * (mmax_t + 1) / 2;
-    return (size_t)cap * 12 + tri * 8 * (reg ? 1 : 2) + (reg ? (size_t)kRegSMax * mmax_t * 8 : 0) +
-           (size_t)mmax_t * 32 + 65 * 4 + 64 * 16 + 16;
-}
-
-static int launch_rows(RowsKernel kern, int mmax_t, int cap, bool reg, const afsai_csr *A, const double *diag,
-                       const afsai_params *p, const int32_t *list, int nlist, int32_t *counters, int ldell,
-                       int32_t *ell_col, double *ell_val, int32_t *m, double *psi, int32_t *steps, int32_t *reason,
-                       int8_t *st, int32_t *ovf_count, int32_t *ovf_list, const DeviceInfo &di, hipStream_t s) {
-    const size_t lds = rows_lds_bytes(mmax_t, cap, reg);
+static int launch_rows(RowsKernel kern, int mmax_t, int cap, int gmax, const afsai_csr *A, const double *diag,
+                       const int32_t *dlo, const afsai_params *p, const int32_t *list, int nlist, int32_t *counters,
+                       int ldell, int32_t *ell_col, double *ell_val, int32_t *m, double *psi, int32_t *steps,
+                       int32_t *reason, int8_t *st, int32_t *ovf_count, int32_t *ovf_list, const DeviceInfo &di,
+                       hipStream_t s) {
+    const size_t lds = rows_lds_bytes(mmax_t, cap);
     int per_cu = (int)((160 * 1024) / (lds + 256));
     if (per_cu > 32) per_cu = 32;
     if (per_cu < 1) per_cu = 1;
@@ -293,9 +285,9 @@ static int launch_rows(RowsKernel kern, int mmax_t, int cap, bool reg, const afs
     hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, (int64_t)nx, counters, 0);
     {
         ProfScope ps("afsai_rows", s);
-        hipLaunchKernelGGL(kern, dim3((unsigned)nb), dim3(64), 0, s, A->n, A->row_ptr, A->col_idx, A->val, diag,
-                           p->kmax, p->s, p->eps, p->tie_rtol, list, nlist, counters, nx, ell_col, ell_val, ldell, m,
-                           psi, steps, reason, st, ovf_count, ovf_list);
+        hipLaunchKernelGGL(kern, dim3((unsigned)nb), dim3(64), 0, s, A->n, A->row_ptr, A->col_idx, A->val, diag, dlo,
+                           p->kmax, p->s, p->eps, p->tie_rtol, gmax, list, nlist, counters, nx, ell_col, ell_val,
+                           ldell, m, psi, steps, reason, st, ovf_count, ovf_list);
     }
     AFSAI_HIP_TRY(hipGetLastError());
     return AFSAI_OK;
@@ -388,9 +380,10 @@ int afsai_setup(const afsai_csr *A, const afsai_params *p, void *stream, afsai_p
     const bool f32 = (p->g_prec == AFSAI_F32);
 
     // ---- row statistics / validation
-    DevBuf scanb, diagb;
+    DevBuf scanb, diagb, dlob;
     if ((rc = dalloc(scanb, sizeof(ScanOut), s))) return rc;
     if ((rc = dalloc(diagb, sizeof(double) * (size_t)n, s))) return rc;
+    if ((rc = dalloc(dlob, sizeof(int32_t) * (size_t)n, s))) return rc;
     AFSAI_HIP_TRY(hipMemsetAsync(scanb.p, 0, sizeof(ScanOut), s));
     const int validate = (p->flags & AFSAI_VALIDATE) ? 1 : 0;
     ScanOut so{};
@@ -405,7 +398,7 @@ int afsai_setup(const afsai_csr *A, const afsai_params *p, void *stream, afsai_p
     {
         ProfScope ps("row_scan", s);
         hipLaunchKernelGGL(k_row_scan, dim3(grid1d(n, di)), dim3(256), 0, s, n, A->row_ptr, A->col_idx, A->val,
-                           validate, diagb.as<double>(), scanb.as<ScanOut>());
+                           validate, diagb.as<double>(), dlob.as<int32_t>(), scanb.as<ScanOut>());
     }
     AFSAI_HIP_TRY(hipMemcpyAsync(&so, scanb.p, sizeof so, hipMemcpyDeviceToHost, s));
     AFSAI_HIP_TRY(hipStreamSynchronize(s));
@@ -422,7 +415,7 @@ int afsai_setup(const afsai_csr *A, const afsai_params *p, void *stream, afsai_p
             mmax_t = c;
             break;
         }
-    const bool reg = mmax <= 32 && (p->kmax == 0 || p->s <= kRegSMax) && !option(AFSAI_OPT_SETUP_FORM_LDS);
+    const int gmax = option(AFSAI_OPT_SETUP_GROUP) > 0 ? (int)option(AFSAI_OPT_SETUP_GROUP) : kGMax;
     // distinct columns one step can touch: at most every entry of the m pattern rows
     const int64_t bound = (int64_t)mmax * maxlen + mmax;
     // first table: about twice the distinct columns a step typically touches on stencil-like
@@ -451,9 +444,9 @@ int afsai_setup(const afsai_csr *A, const afsai_params *p, void *stream, afsai_p
     int32_t *ovf_count = ovf.as<int32_t>() + n;
     hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, (int64_t)1, ovf_count, 0);
 
-    RowsKernel k1 = rows_kernel(mmax_t, cap1, reg);
+    RowsKernel k1 = rows_kernel(mmax_t, cap1);
     if (!k1) AFSAI_FAIL(AFSAI_ERR_TOO_LARGE, "afsai_setup: no kernel for pattern %d / table %d", mmax_t, cap1);
-    if ((rc = launch_rows(k1, mmax_t, cap1, reg, A, diagb.as<double>(), p, nullptr, n, ctr.as<int32_t>(), ldell,
+    if ((rc = launch_rows(k1, mmax_t, cap1, gmax, A, diagb.as<double>(), dlob.as<int32_t>(), p, nullptr, n, ctr.as<int32_t>(), ldell,
                           ell_col.as<int32_t>(), ell_val.as<double>(), mcnt.as<int32_t>(), psi.as<double>(),
                           steps.as<int32_t>(), reason.as<int32_t>(), st.as<int8_t>(), ovf_count, ovf.as<int32_t>(), di,
                           s)))
@@ -470,9 +463,9 @@ int afsai_setup(const afsai_csr *A, const afsai_params *p, void *stream, afsai_p
                            list2.as<int32_t>());
         int32_t *cnt2 = list2.as<int32_t>() + novf;
         hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, (int64_t)1, cnt2, 0);
-        RowsKernel k2 = rows_kernel(mmax_t, cap2, reg);
+        RowsKernel k2 = rows_kernel(mmax_t, cap2);
         if (!k2) AFSAI_FAIL(AFSAI_ERR_TOO_LARGE, "afsai_setup: no kernel for table %d", cap2);
-        if ((rc = launch_rows(k2, mmax_t, cap2, reg, A, diagb.as<double>(), p, list2.as<int32_t>(), novf,
+        if ((rc = launch_rows(k2, mmax_t, cap2, gmax, A, diagb.as<double>(), dlob.as<int32_t>(), p, list2.as<int32_t>(), novf,
                               ctr.as<int32_t>(), ldell, ell_col.as<int32_t>(), ell_val.as<double>(), mcnt.as<int32_t>(),
                               psi.as<double>(), steps.as<int32_t>(), reason.as<int32_t>(), st.as<int8_t>(), cnt2,
                               ovf.as<int32_t>(), di, s)))

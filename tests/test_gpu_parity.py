@@ -172,23 +172,25 @@ def test_setup_fp32_storage(af):
 @pytest.mark.parametrize("make,kmax,s", [(lambda: synth.elast27(10, 1.0, 6), 10, 2), (lambda: synth.lap7(16), 5, 1),
                                          (lambda: synth.elast27(6, 2.0, 5), 7, 4)])
 def test_setup_forms_identical(af, make, kmax, s):
-    """The register and the LDS forms of the per-row kernel, and any first table size, give
-    G bit for bit identical."""
+    """Appending one or two rows per factor update instead of up to four, and any first table
+    size, give G bit for bit identical."""
     A = make()
     dA = _dev(af, A)
     ref = _gpu_factor(af, af.setup(dA, kmax, s, 1e-2))
     try:
-        af.set_option(af.OPT_SETUP_FORM_LDS, 1)
-        lds = _gpu_factor(af, af.setup(dA, kmax, s, 1e-2))
-        af.set_option(af.OPT_SETUP_FORM_LDS, 0)
+        outs = []
+        for g in (1, 2):
+            af.set_option(af.OPT_SETUP_GROUP, g)
+            outs.append(_gpu_factor(af, af.setup(dA, kmax, s, 1e-2)))
+        af.set_option(af.OPT_SETUP_GROUP, 0)
         af.set_option(af.OPT_SETUP_TABLE, 128)
-        small = _gpu_factor(af, af.setup(dA, kmax, s, 1e-2))
+        outs.append(_gpu_factor(af, af.setup(dA, kmax, s, 1e-2)))
     finally:
-        af.set_option(af.OPT_SETUP_FORM_LDS, 0)
+        af.set_option(af.OPT_SETUP_GROUP, 0)
         af.set_option(af.OPT_SETUP_TABLE, 0)
-    for a, b, c in zip(ref, lds, small):
-        np.testing.assert_array_equal(a, b)
-        np.testing.assert_array_equal(a, c)
+    for o in outs:
+        for a, b in zip(ref, o):
+            np.testing.assert_array_equal(a, b)
 
 
 @pytest.mark.parametrize("gs,un", [(4, 1), (8, 2), (16, 8), (64, 4)])

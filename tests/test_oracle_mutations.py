@@ -15,8 +15,7 @@ SRC = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), 
 
 MUTATIONS = {
     # eq. diagScal2 taken literally: scale by 1/psi instead of psi^-1/2
-    "scale_1_over_psi": ("g[m - 1] = 1.0 / L[(m - 1) * m + (m - 1)];",
-                         "g[m - 1] = 1.0 / (L[(m - 1) * m + (m - 1)] * L[(m - 1) * m + (m - 1)]);"),
+    "scale_1_over_psi": ("g[m - 1] = dinv[m - 1];", "g[m - 1] = dinv[m - 1] * dinv[m - 1];"),
     # gradient from row i only (drops the sum over the pattern)
     "grad_row_i_only": ("for (int32_t t = 0; t < m; ++t) {\n            int32_t r = P[t];",
                         "for (int32_t t = m - 1; t < m; ++t) {\n            int32_t r = P[t];"),
@@ -25,7 +24,11 @@ MUTATIONS = {
     # exit test with the inequality reversed
     "exit_reversed": ("if (psi <= eps * psi0) {", "if (psi >= eps * psi0) {"),
     # back substitution sign
-    "solve_sign": ("g[t] = -(acc / L[t * m + t]);", "g[t] = (acc / L[t * m + t]);"),
+    "solve_sign": ("g[t] = -(acc * dinv[t]);", "g[t] = (acc * dinv[t]);"),
+    # pivot reciprocal taken from the wrong column
+    "pivot_index": ("L[r * m + c] = acc * dinv[c];", "L[r * m + c] = acc * dinv[r];"),
+    # new positions inserted after i instead of before it
+    "append_after_i": ("P[m - 1] = S[q];\n            P[m] = i;", "P[m] = S[q];"),
     # Cholesky update sign
     "chol_sign": ("acc = acc - L[r * m + t] * L[c * m + t];", "acc = acc + L[r * m + t] * L[c * m + t];"),
     # gather with a transposed / wrong index
