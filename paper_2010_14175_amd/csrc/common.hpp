@@ -157,6 +157,55 @@ __device__ __forceinline__ int wave_incl_scan(int v) {
 }
 
 // ---------------------------------------------------------------------------------------
+// the same operations with DPP lane moves (no LDS-pipe round trip).  GFX9 DPP controls:
+// row_shr:k = 0x110+k, row_ror:k = 0x120+k (rows of 16 lanes), row_bcast:15 = 0x142 (lane 15
+// of each row to the next row), row_bcast:31 = 0x143 (lane 31 to rows 2 and 3).  Lanes of
+// rows outside row_mask keep `old`.
+// ---------------------------------------------------------------------------------------
+template <int CTRL, int ROWMASK, bool BOUND>
+__device__ __forceinline__ int dpp_i32(int old, int v) {
+    return __builtin_amdgcn_update_dpp(old, v, CTRL, ROWMASK, 0xF, BOUND);
+}
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ double dpp_f64(double old, double v) {
+    const int lo = dpp_i32<CTRL, ROWMASK, false>(__double2loint(old), __double2loint(v));
+    const int hi = dpp_i32<CTRL, ROWMASK, false>(__double2hiint(old), __double2hiint(v));
+    return __hiloint2double(hi, lo);
+}
+// maximum over the 64 lanes, returned uniform (read from lane 63)
+__device__ __forceinline__ double wave_max_dpp(double v) {
+    v = fmax(v, dpp_f64<0x121, 0xF>(v, v));
+    v = fmax(v, dpp_f64<0x122, 0xF>(v, v));
+    v = fmax(v, dpp_f64<0x124, 0xF>(v, v));
+    v = fmax(v, dpp_f64<0x128, 0xF>(v, v));
+    v = fmax(v, dpp_f64<0x142, 0xA>(v, v));
+    v = fmax(v, dpp_f64<0x143, 0xC>(v, v));
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
+    return __hiloint2double(hi, lo);
+}
+// minimum over the 64 lanes (unsigned), returned uniform
+__device__ __forceinline__ uint32_t wave_min_dpp(uint32_t v) {
+    v = min(v, (uint32_t)dpp_i32<0x121, 0xF, false>((int)v, (int)v));
+    v = min(v, (uint32_t)dpp_i32<0x122, 0xF, false>((int)v, (int)v));
+    v = min(v, (uint32_t)dpp_i32<0x124, 0xF, false>((int)v, (int)v));
+    v = min(v, (uint32_t)dpp_i32<0x128, 0xF, false>((int)v, (int)v));
+    v = min(v, (uint32_t)dpp_i32<0x142, 0xA, false>((int)v, (int)v));
+    v = min(v, (uint32_t)dpp_i32<0x143, 0xC, false>((int)v, (int)v));
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
+}
+// inclusive prefix sum over the 64 lanes
+__device__ __forceinline__ int wave_scan_dpp(int v) {
+    v += dpp_i32<0x111, 0xF, true>(0, v);
+    v += dpp_i32<0x112, 0xF, true>(0, v);
+    v += dpp_i32<0x114, 0xF, true>(0, v);
+    v += dpp_i32<0x118, 0xF, true>(0, v);
+    v += dpp_i32<0x142, 0xA, false>(0, v);
+    v += dpp_i32<0x143, 0xC, false>(0, v);
+    return v;
+}
+
+// ---------------------------------------------------------------------------------------
 // kernel timer (HIP events around each launch while profiling is on)
 // ---------------------------------------------------------------------------------------
 bool profiling_on();

@@ -98,7 +98,60 @@ __host__ __device__ __forceinline__ int upd_entries(int mb, int g) { return g * 
 // index of entry (v, c) of new row v, and of the last row's entry at column mb + d
 __device__ __forceinline__ int upd_index(int mb, int v, int c) { return v * (mb + 1) + (v * (v - 1)) / 2 + c; }
 
-constexpr int kUnroll = 8;
+// entry e of the update entries held K per lane (lane e % 64, register e / 64): read as a
+// uniform value, and replaced in its owner lane
+template <int K>
+__device__ __forceinline__ double ent_get(const double (&run)[K], int e) {
+    if constexpr (K == 1) {
+        return rl(run[0], e);
+    } else {
+        return (e < 64) ? rl(run[0], e) : rl(run[1], e - 64);
+    }
+}
+template <int K>
+__device__ __forceinline__ void ent_set(double (&run)[K], int e, double v, int lane) {
+#pragma unroll
+    for (int kk = 0; kk < K; ++kk) run[kk] = (lane == e - 64 * kk) ? v : run[kk];
+}
+
+// Columns j < mb of one factor update that appends G rows (the rows of L for positions below
+// mb are final): column j of each new row is scaled by the pivot reciprocal, and every entry
+// right of column j receives its product term (right-looking).  The last row's entries for
+// these columns are final already; its new-column entries are updated, its diagonal is not.
+template <int G, int K>
+__device__ __forceinline__ void upd_old_columns(int mb, const int (&base)[kGMax], const int (&er)[K],
+                                                const int (&ec)[K], double (&run)[K], double r_dinv, double r_li,
+                                                const double *Lp, int lane) {
+    for (int j = 0; j < mb; ++j) {
+        const double dj = rl(r_dinv, j);
+        double U[G + 1];
+#pragma unroll
+        for (int v = 0; v < G; ++v) {
+            const int e = base[v] + j;
+            U[v] = ent_get<K>(run, e) * dj;
+            ent_set<K>(run, e, U[v], lane);
+        }
+        U[G] = rl(r_li, j);
+#pragma unroll
+        for (int kk = 0; kk < K; ++kk) {
+            const int r = er[kk], c = ec[kk];
+            const bool upd = (r >= 0) && (c > j) && !(r == G && c == mb + G);
+            double a = U[G];
+#pragma unroll
+            for (int v = 0; v < G; ++v) a = (r == v) ? U[v] : a;
+            double b = Lp[(upd && c < mb) ? tri(c, j) : 0];
+#pragma unroll
+            for (int v = 0; v < G; ++v) b = (c - mb == v) ? U[v] : b;
+            const double nv = run[kk] - a * b;
+            run[kk] = upd ? nv : run[kk];
+        }
+    }
+}
+
+// Slot-list entries per table slot: each member row's entries left of column i are looked up
+// once, when the row joins the pattern, and their table slots are kept for the later steps.
+template <int CAP>
+constexpr int sl_cap() { return CAP >= 2048 ? 2 * CAP : 4 * CAP; }
 
 template <int MMAX, int CAP>
 __global__ __launch_bounds__(64) void k_afsai_rows(
@@ -108,23 +161,19 @@ __global__ __launch_bounds__(64) void k_afsai_rows(
     int32_t *__restrict__ ell_col, double *__restrict__ ell_val, int ldell, int32_t *__restrict__ m_out,
     double *__restrict__ psi_out, int32_t *__restrict__ steps_out, int32_t *__restrict__ reason_out,
     int8_t *__restrict__ status_out, int32_t *__restrict__ ovf_count, int32_t *__restrict__ ovf_list) {
-    constexpr int K = (MMAX + 1 + 63) / 64;           // update entries per lane
-    constexpr int LTRI = (MMAX * (MMAX - 1)) / 2;     // rows 0..MMAX-2 of L, packed lower
-    constexpr int SPL = CAP / 64;                     // table slots per lane
-    constexpr bool SEL_REG = SPL <= 16;               // selection from registers
-    __shared__ uint32_t hkey[CAP];
-    __shared__ double hval[CAP];
-    __shared__ double Lp[LTRI];           // rows of L for the off-diagonal positions
-    __shared__ double dinv[MMAX];         // their reciprocal pivots
-    __shared__ double li[MMAX];           // row of i in L, columns 0..m-2
-    __shared__ double gq[MMAX];           // scaled row by position (i at m-1)
-    __shared__ int32_t Qc[MMAX];          // column of each off-diagonal position
-    __shared__ int32_t mbeg[MMAX], mlen[MMAX];  // row start and number of entries left of column i
-    __shared__ int32_t off[MMAX + 1];
-    __shared__ double NR[kGMax * MMAX];   // gathered new rows, by position (i at MMAX-1)
-    __shared__ int32_t sel[64], selslot[64];
-    __shared__ int32_t nlo[kGMax], nbeg[kGMax + 1];
-    __shared__ int32_t s_row, s_flag;
+    static_assert(MMAX <= 64, "one lane per pattern position");
+    constexpr int K = (MMAX + 1 + 63) / 64;        // update entries per lane
+    constexpr int LTRI = (MMAX * (MMAX - 1)) / 2;  // rows 0..MMAX-2 of L, packed lower
+    constexpr int SPL = CAP / 64;                  // table slots per lane
+    constexpr bool SEL_REG = SPL <= 16;            // selection from registers
+    constexpr int SLCAP = sl_cap<CAP>();
+    __shared__ uint32_t hkey[CAP];       // column (tagged when a member), kept for the whole row
+    __shared__ double hval[CAP];         // gradient of this step
+    __shared__ int8_t hpos[CAP];         // position of a member
+    __shared__ uint16_t SL[SLCAP];       // table slots of the member rows' entries left of i
+    __shared__ double Lp[LTRI];          // rows of L for the off-diagonal positions
+    __shared__ double NR[kGMax * MMAX];  // gathered new rows, by position (a_{u,i} at MMAX-1)
+    __shared__ int32_t s_row;
 
     const int lane = threadIdx.x;
     const int x = blockIdx.x % nxcd;
@@ -139,6 +188,13 @@ __global__ __launch_bounds__(64) void k_afsai_rows(
         if (q >= q1) break;
         const int i = list ? list[q] : q;
 
+        // per-position state, lane t = position t (i at m-1): column, row start, number of
+        // row entries left of column i, their offset in SL, scaled row value, reciprocal
+        // pivot, L[i][t]
+        int r_col = i, r_beg = 0, r_len = 0, r_so = 0;
+        double r_g = 0.0, r_dinv = 0.0, r_li = 0.0;
+        int r_nb = 0, r_ne = 0;  // row extents of the columns selected in this step (lane = rank)
+
         // ---- G_0 = I scaled: P = {i}, g = a_ii^-1/2, psi_0 = a_ii
         const double aii = diag[i];
         const int ibeg = rp[i], ilen = dlo[i];
@@ -148,90 +204,96 @@ __global__ __launch_bounds__(64) void k_afsai_rows(
         double psi = aii;
         double di = aii;  // last row's diagonal less the squares of its final entries
         if (!(aii > 0.0) || !isfinite(aii)) status = ROW_NOT_SPD;
-        if (lane == 0) gq[0] = 1.0 / sqrt(aii);
-        __syncthreads();
         const double psi0 = aii;
+        int sl_used = 0;  // SL entries in use (uniform)
+
+        // table: empty; row i's entries left of the diagonal are entered as candidates
+        for (int j = lane; j < CAP; j += 64) hkey[j] = kEmpty;
+        __syncthreads();
+        if (kmax > 0 && status == ROW_OK) {
+            bool ovf = ilen > SLCAP;
+            for (int o = lane; o < ilen && !ovf; o += 64) {
+                bool tg;
+                const int slot = table_find<CAP>(hkey, (uint32_t)ci[ibeg + o], (uint32_t)ci[ibeg + o], true, tg);
+                if (slot < 0) ovf = true;
+                else SL[o] = (uint16_t)slot;
+            }
+            if (__ballot(ovf)) status = ROW_OVERFLOW;
+            sl_used = ilen;
+        }
+        if (lane == 0) {
+            r_g = 1.0 / sqrt(aii);
+            r_beg = ibeg;
+            r_len = ilen;
+            r_so = 0;
+        }
+        __syncthreads();
 
         for (int k = 1; k <= kmax && status == ROW_OK; ++k) {
-            // ---- 1. product pass: gradient on the candidates
-            for (int j = lane; j < CAP; j += 64) {
-                hkey[j] = kEmpty;
-                hval[j] = 0.0;
-            }
-            if (lane == 0) s_flag = 0;
+            // ---- 1. product pass: v_c += a_rc g_r over the members' entries left of i (the
+            //         slots of members collect values that are never read)
+            for (int j = lane; j < CAP; j += 64) hval[j] = 0.0;
             __syncthreads();
-            int len = 0;
-            if (lane < m - 1) {
-                // members are entered tagged, with their position as the slot's value
-                bool tg;
-                const uint32_t c = (uint32_t)Qc[lane];
-                const int slot = table_find<CAP>(hkey, c, c | kPBit, true, tg);
-                if (slot >= 0) hval[slot] = (double)lane;
-                else s_flag = 1;
-                len = mlen[lane];
-            } else if (lane == m - 1) {
-                mbeg[lane] = ibeg;
-                len = ilen;
-            }
-            const int incl = wave_incl_scan(len);
-            if (lane < m) off[lane] = incl - len;
-            const int total = __shfl(incl, m - 1, 64);
-            if (lane == 0) off[m] = total;
-            __syncthreads();
-            int tseg = 0;
-            for (int base = 0; base < total; base += 64 * kUnroll) {
-                int cc[kUnroll], tt[kUnroll];
-                double vv[kUnroll];
+            for (int t0 = 0; t0 < m; t0 += 4) {
+                int sl[8];
+                double aa[8], gg[4];
+                int lens[4], begs[4], sos[4];
 #pragma unroll
-                for (int u = 0; u < kUnroll; ++u) {
-                    const int e = base + u * 64 + lane;
-                    cc[u] = -1;
-                    tt[u] = 0;
-                    vv[u] = 0.0;
-                    if (e < total) {
-                        if (u == 0) tseg = seg_of(off, m, e);
-                        else
-                            while (off[tseg + 1] <= e) ++tseg;
-                        const int idx = mbeg[tseg] + (e - off[tseg]);
-                        tt[u] = tseg;
-                        cc[u] = __builtin_nontemporal_load(&ci[idx]);
-                        vv[u] = __builtin_nontemporal_load(&av[idx]);
+                for (int u = 0; u < 4; ++u) {
+                    const int t = t0 + u;
+                    lens[u] = 0;
+                    begs[u] = 0;
+                    sos[u] = 0;
+                    gg[u] = 0.0;
+                    if (t < m) {
+                        lens[u] = __builtin_amdgcn_readlane(r_len, t);
+                        begs[u] = __builtin_amdgcn_readlane(r_beg, t);
+                        sos[u] = __builtin_amdgcn_readlane(r_so, t);
+                        gg[u] = rl(r_g, t);
+                    }
+#pragma unroll
+                    for (int hh = 0; hh < 2; ++hh) {
+                        const int o = hh * 64 + lane;
+                        sl[2 * u + hh] = -1;
+                        aa[2 * u + hh] = 0.0;
+                        if (o < lens[u]) {
+                            sl[2 * u + hh] = SL[sos[u] + o];
+                            aa[2 * u + hh] = __builtin_nontemporal_load(&av[begs[u] + o]);
+                        }
                     }
                 }
 #pragma unroll
-                for (int u = 0; u < kUnroll; ++u) {
-                    if (cc[u] >= 0) {
-                        bool tg = false;
-                        const int slot = table_find<CAP>(hkey, (uint32_t)cc[u], (uint32_t)cc[u], true, tg);
-                        if (slot < 0)
-                            s_flag = 1;
-                        else if (!tg)
-                            __hip_atomic_fetch_add(&hval[slot], vv[u] * gq[tt[u]], __ATOMIC_RELAXED,
+                for (int u = 0; u < 4; ++u)
+#pragma unroll
+                    for (int hh = 0; hh < 2; ++hh)
+                        if (sl[2 * u + hh] >= 0)
+                            __hip_atomic_fetch_add(&hval[sl[2 * u + hh]], aa[2 * u + hh] * gg[u], __ATOMIC_RELAXED,
                                                    __HIP_MEMORY_SCOPE_WORKGROUP);
-                    }
-                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    for (int o = 128 + lane; o < lens[u]; o += 64)
+                        __hip_atomic_fetch_add(&hval[SL[sos[u] + o]], av[begs[u] + o] * gg[u], __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_WORKGROUP);
             }
             __syncthreads();
-            if (s_flag) {
-                status = ROW_OVERFLOW;
-                break;
-            }
 
-            // ---- 2. selection (top-s of |v| over the candidates, tie band, smallest column)
+            // ---- 2. selection (top-s of |v| over the candidates, tie band, smallest column);
+            //         the j-th selected column takes position m-1+j, and its row extents are
+            //         fetched at once into lane j
             int ns = 0;
             if constexpr (SEL_REG) {
                 uint32_t kr[SPL];
                 double ar[SPL];
-                double lmax = -1.0;
+                double lm = -1.0;
 #pragma unroll
                 for (int j = 0; j < SPL; ++j) {
                     const uint32_t kk = hkey[lane + 64 * j];
                     const bool cand = (kk != kEmpty) && !(kk & kPBit);
                     kr[j] = cand ? kk : kEmpty;
                     ar[j] = cand ? fabs(hval[lane + 64 * j]) : -1.0;
-                    lmax = fmax(lmax, ar[j]);
+                    lm = fmax(lm, ar[j]);
                 }
-                const double M = wave_max(lmax);
+                const double M = wave_max_dpp(lm);
                 if (M > 0.0) {
                     const double thr = 0x1.0p-40 * M;
                     for (int round = 0; round < s; ++round) {
@@ -239,34 +301,43 @@ __global__ __launch_bounds__(64) void k_afsai_rows(
 #pragma unroll
                         for (int j = 0; j < SPL; ++j)
                             if (ar[j] > thr) l = fmax(l, ar[j]);
-                        const double Mp = wave_max(l);
+                        const double Mp = wave_max_dpp(l);
                         if (!(Mp > 0.0)) break;
                         const double band = (1.0 - tau) * Mp;
                         uint32_t lb = kEmpty;
 #pragma unroll
                         for (int j = 0; j < SPL; ++j)
                             if (ar[j] > thr && ar[j] >= band && kr[j] < lb) lb = kr[j];
-                        const uint32_t js = wave_min(lb);
+                        const uint32_t js = wave_min_dpp(lb);
+                        int myslot = -1;
 #pragma unroll
-                        for (int j = 0; j < SPL; ++j)
-                            if (kr[j] == js) {
-                                hkey[lane + 64 * j] = js | kPBit;
-                                selslot[ns] = lane + 64 * j;
-                                kr[j] = kEmpty;
-                                ar[j] = -1.0;
-                            }
-                        if (lane == 0) sel[ns] = (int32_t)js;
+                        for (int j = 0; j < SPL; ++j) {
+                            const bool hit = (kr[j] == js);
+                            myslot = hit ? lane + 64 * j : myslot;
+                            kr[j] = hit ? kEmpty : kr[j];
+                            ar[j] = hit ? -1.0 : ar[j];
+                        }
+                        const uint64_t who = __ballot(myslot >= 0);
+                        const int wslot = __builtin_amdgcn_readlane(myslot, (int)__builtin_ctzll(who));
+                        if (lane == 0) {
+                            hkey[wslot] = js | kPBit;
+                            hpos[wslot] = (int8_t)(m - 1 + ns);
+                        }
+                        if (lane == ns) {
+                            r_nb = rp[js];
+                            r_ne = rp[js + 1];
+                        }
+                        if (lane == m - 1 + ns) r_col = (int)js;
                         ++ns;
                     }
                 }
-                __syncthreads();
             } else {
-                double lmax = 0.0;
+                double lm = 0.0;
                 for (int j = lane; j < CAP; j += 64) {
                     const uint32_t kk = hkey[j];
-                    if (kk != kEmpty && !(kk & kPBit)) lmax = fmax(lmax, fabs(hval[j]));
+                    if (kk != kEmpty && !(kk & kPBit)) lm = fmax(lm, fabs(hval[j]));
                 }
-                const double M = wave_max(lmax);
+                const double M = wave_max_dpp(lm);
                 if (M > 0.0) {
                     const double thr = 0x1.0p-40 * M;
                     for (int round = 0; round < s; ++round) {
@@ -278,7 +349,7 @@ __global__ __launch_bounds__(64) void k_afsai_rows(
                                 if (a > thr) l = fmax(l, a);
                             }
                         }
-                        const double Mp = wave_max(l);
+                        const double Mp = wave_max_dpp(l);
                         if (!(Mp > 0.0)) break;
                         const double band = (1.0 - tau) * Mp;
                         uint32_t lb = kEmpty;
@@ -289,68 +360,77 @@ __global__ __launch_bounds__(64) void k_afsai_rows(
                                 if (a > thr && a >= band && kk < lb) lb = kk;
                             }
                         }
-                        const uint32_t js = wave_min(lb);
+                        const uint32_t js = wave_min_dpp(lb);
                         for (int j = lane; j < CAP; j += 64)
                             if (hkey[j] == js) {
                                 hkey[j] = js | kPBit;
-                                selslot[ns] = j;
+                                hpos[j] = (int8_t)(m - 1 + ns);
                             }
-                        if (lane == 0) sel[ns] = (int32_t)js;
+                        if (lane == ns) {
+                            r_nb = rp[js];
+                            r_ne = rp[js + 1];
+                        }
+                        if (lane == m - 1 + ns) r_col = (int)js;
                         ++ns;
                         __syncthreads();
                     }
                 }
             }
+            __syncthreads();
             if (ns == 0) {
                 reason = STOP_NOCAND;
                 break;
             }
 
-            // ---- new positions m-1 .. m+ns-2 in selection order; i moves to mn-1
+            // ---- 3./4. append the new rows to the factor, at most gmax at a time
             const int mn = m + ns;
-            if (lane < ns) {
-                hval[selslot[lane]] = (double)(m - 1 + lane);
-                Qc[m - 1 + lane] = sel[lane];
-            }
-            __syncthreads();
-
-            // ---- 3./4. append the new rows to the factor, at most kGMax at a time
-            bool spd = true;
+            bool spd = true, ovf = false;
             int mb = m - 1;
-            for (int v0 = 0; v0 < ns && spd;) {
+            for (int v0 = 0; v0 < ns && spd && !ovf;) {
                 int G = min(ns - v0, gmax);
                 while (G > 1 && upd_entries(mb, G) > 64 * K) --G;
                 const int m1 = mb + G;  // position of i within this update
-                // gather rows sel[v0 .. v0+G): NR[v][pos] for members, NR[v][MMAX-1] = a_{u,i}
+                // gather rows v0 .. v0+G-1: NR[v][pos] for members, NR[v][MMAX-1] = a_{u,i};
+                // their entries left of i are entered in the table and their slots listed
                 for (int j = lane; j < G * MMAX; j += 64) NR[j] = 0.0;
-                int rlen = 0;
-                if (lane < G) {
-                    const int u = sel[v0 + lane];
-                    const int b = rp[u];
-                    rlen = rp[u + 1] - b;
-                    mbeg[mb + lane] = b;
-                    nlo[lane] = 0;
-                }
-                const int rincl = wave_incl_scan(rlen);
-                if (lane < G) nbeg[lane] = rincl - rlen;
-                const int rtot = __shfl(rincl, G - 1, 64);
-                if (lane == 0) nbeg[G] = rtot;
                 __syncthreads();
-                for (int e = lane; e < rtot; e += 64) {
-                    const int v = seg_of(nbeg, G, e);
-                    const int idx = mbeg[mb + v] + (e - nbeg[v]);
-                    const int c = ci[idx];
-                    if (c < i) {
-                        atomicAdd(&nlo[v], 1);
-                        bool tg = false;
-                        const int slot = table_find<CAP>(hkey, (uint32_t)c, 0u, false, tg);
-                        if (slot >= 0 && tg) NR[v * MMAX + (int)hval[slot]] = av[idx];
-                    } else if (c == i) {
-                        NR[v * MMAX + (MMAX - 1)] = av[idx];
+                for (int v = 0; v < G; ++v) {
+                    const int nb = __builtin_amdgcn_readlane(r_nb, v0 + v);
+                    const int nl = __builtin_amdgcn_readlane(r_ne, v0 + v) - nb;
+                    if (sl_used + nl > SLCAP) ovf = true;  // uniform
+                    int nlo = 0;
+                    for (int h = 0; h * 64 < nl && !ovf; ++h) {
+                        const int o = h * 64 + lane;
+                        int c = 0x7fffffff;
+                        double a = 0.0;
+                        if (o < nl) {
+                            c = ci[nb + o];
+                            a = av[nb + o];
+                        }
+                        if (c == i) NR[v * MMAX + (MMAX - 1)] = a;
+                        bool bad = false;
+                        if (c < i) {
+                            bool tg = false;
+                            const int slot = table_find<CAP>(hkey, (uint32_t)c, (uint32_t)c, true, tg);
+                            if (slot < 0) {
+                                bad = true;
+                            } else {
+                                SL[sl_used + o] = (uint16_t)slot;
+                                if (tg) NR[v * MMAX + hpos[slot]] = a;
+                            }
+                        }
+                        nlo += __popcll(__ballot(c < i));
+                        if (__ballot(bad)) ovf = true;
                     }
+                    if (lane == mb + v) {
+                        r_beg = nb;
+                        r_len = nlo;
+                        r_so = sl_used;
+                    }
+                    sl_used += nlo;
                 }
                 __syncthreads();
-                if (lane < G) mlen[mb + lane] = nlo[lane];
+                if (ovf) break;
 
                 // update entries owned by this lane: (row r, column c); r == G is the row of i
                 const int E = upd_entries(mb, G);
@@ -381,7 +461,18 @@ __global__ __launch_bounds__(64) void k_afsai_rows(
                         }
                     }
                 }
-                for (int j = 0; j < m1; ++j) {
+                {
+                    int base[kGMax];
+#pragma unroll
+                    for (int v = 0; v < kGMax; ++v) base[v] = upd_index(mb, v, 0);
+                    switch (G) {
+                        case 1: upd_old_columns<1, K>(mb, base, er, ec, run, r_dinv, r_li, Lp, lane); break;
+                        case 2: upd_old_columns<2, K>(mb, base, er, ec, run, r_dinv, r_li, Lp, lane); break;
+                        case 3: upd_old_columns<3, K>(mb, base, er, ec, run, r_dinv, r_li, Lp, lane); break;
+                        default: upd_old_columns<4, K>(mb, base, er, ec, run, r_dinv, r_li, Lp, lane); break;
+                    }
+                }
+                for (int j = mb; j < m1; ++j) {
                     double dj;
                     if (j >= mb) {
                         // pivot of new row j - mb: its diagonal entry is final
@@ -399,11 +490,11 @@ __global__ __launch_bounds__(64) void k_afsai_rows(
 #pragma unroll
                         for (int kk = 0; kk < K; ++kk)
                             if ((e >> 6) == kk && lane == (e & 63)) run[kk] = Ljj;
-                        if (lane == 0) dinv[j] = dj;
+                        if (lane == j) r_dinv = dj;
                     } else {
-                        dj = dinv[j];
+                        dj = rl(r_dinv, j);
                     }
-                    // values of column j: U[v] = L[mb+v][j], U[G] = L[i][j]
+                    // values of column j: U[v] = L[mb+v][j], U[kGMax] = L[i][j]
                     double U[kGMax + 1];
 #pragma unroll
                     for (int v = 0; v <= kGMax; ++v) U[v] = 0.0;
@@ -422,7 +513,7 @@ __global__ __launch_bounds__(64) void k_afsai_rows(
                         }
                     }
                     if (j < mb) {
-                        U[kGMax] = li[j];
+                        U[kGMax] = rl(r_li, j);
                     } else {
                         const int e = ibase + (j - mb);
                         double xv = 0.0;
@@ -465,19 +556,29 @@ __global__ __launch_bounds__(64) void k_afsai_rows(
                 for (int kk = 0; kk < K; ++kk) {
                     const int r = er[kk], c = ec[kk];
                     if (r >= 0 && r < G) Lp[tri(mb + r, c)] = run[kk];
-                    else if (r == G && c < m1) li[c] = run[kk];
                 }
-                {
-                    const int e = ibase + G;
-                    double xd = 0.0;
 #pragma unroll
-                    for (int kk = 0; kk < K; ++kk)
-                        if ((e >> 6) == kk) xd = rl(run[kk], e & 63);
-                    di = xd;
+                for (int d = 0; d <= kGMax; ++d) {
+                    if (d <= G) {
+                        const int e = ibase + d;
+                        double xv = 0.0;
+#pragma unroll
+                        for (int kk = 0; kk < K; ++kk)
+                            if ((e >> 6) == kk) xv = rl(run[kk], e & 63);
+                        if (d < G) {
+                            if (lane == mb + d) r_li = xv;
+                        } else {
+                            di = xv;
+                        }
+                    }
                 }
                 __syncthreads();
                 mb += G;
                 v0 += G;
+            }
+            if (ovf) {
+                status = ROW_OVERFLOW;
+                break;
             }
             if (spd && (!(di > 0.0) || !isfinite(di))) spd = false;
             if (!spd) {
@@ -488,20 +589,25 @@ __global__ __launch_bounds__(64) void k_afsai_rows(
             // ---- 5. g = L^-T e_m, positions from the last down
             const double lmm = sqrt(di);
             const double dm = 1.0 / lmm;
-            double acc = 0.0, gmine = 0.0;
-            for (int l = mn - 1; l >= 0; --l) {
-                const double gl = (l == mn - 1) ? dm : -(rl(acc, l) * dinv[l]);
-                if (lane == l) gmine = gl;
-                if (lane < l) {
-                    const double Lv = (l == mn - 1) ? li[lane] : Lp[tri(l, lane)];
-                    acc = acc + Lv * gl;
-                }
+            // l = mn-1 (row i of L), then the stored rows; lane t accumulates sum_l L[l][t] g_l
+            double gmine = (lane == mn - 1) ? dm : 0.0;
+            double acc = (lane < mn - 1) ? 0.0 + r_li * dm : 0.0;
+            for (int l = mn - 2; l >= 0; --l) {
+                const double Lv = Lp[tri(l, lane < l ? lane : 0)];
+                const double gl = -(rl(acc, l) * rl(r_dinv, l));
+                gmine = (lane == l) ? gl : gmine;
+                const double na = acc + Lv * gl;
+                acc = (lane < l) ? na : acc;
             }
-            if (lane < mn) gq[lane] = gmine;
+            if (lane < mn) r_g = gmine;
+            if (lane == mn - 1) {
+                r_beg = ibeg;
+                r_len = ilen;
+                r_so = 0;
+            }
             psi = lmm * lmm;
             m = mn;
             steps = k;
-            __syncthreads();
             // ---- exit test (eq. exit_crit)
             if (psi <= eps * psi0) {
                 reason = STOP_EPS;
@@ -511,17 +617,12 @@ __global__ __launch_bounds__(64) void k_afsai_rows(
 
         // ---- outputs: the row with ascending columns
         if (status == ROW_OK) {
-            int col = 0x7fffffff;
-            double val = 0.0;
-            if (lane < m) {
-                col = (lane == m - 1) ? i : Qc[lane];
-                val = gq[lane];
-            }
+            const int col = (lane < m - 1) ? r_col : (lane == m - 1 ? i : 0x7fffffff);
             int rank = 0;
-            for (int t = 0; t < m; ++t) rank += (__shfl(col, t, 64) < col) ? 1 : 0;
+            for (int t = 0; t < m; ++t) rank += (__builtin_amdgcn_readlane(col, t) < col) ? 1 : 0;
             if (lane < m) {
                 ell_col[(size_t)i * ldell + rank] = col;
-                ell_val[(size_t)i * ldell + rank] = val;
+                ell_val[(size_t)i * ldell + rank] = r_g;
             }
         }
         if (lane == 0) {
@@ -559,8 +660,8 @@ static RowsKernel rows_kernel_cap(int cap) {
 
 // LDS bytes of one k_afsai_rows<MMAX, CAP> block
 __host__ __forceinline__ size_t rows_lds_bytes(int mmax_t, int cap) {
-    return (size_t)cap * 12 + (size_t)mmax_t * (mmax_t - 1) / 2 * 8 + (size_t)mmax_t * (3 * 8 + 3 * 4) +
-           (size_t)(mmax_t + 1) * 4 + (size_t)kGMax * mmax_t * 8 + 64 * 8 + (2 * kGMax + 1) * 4 + 8;
+    const size_t slcap = cap >= 2048 ? 2 * (size_t)cap : 4 * (size_t)cap;
+    return (size_t)cap * 13 + slcap * 2 + (size_t)mmax_t * (mmax_t - 1) / 2 * 8 + (size_t)kGMax * mmax_t * 8 + 16;
 }
 
 }  // namespace afsai
