@@ -198,8 +198,16 @@ const char *afsai_last_error(void);
  *                             (1, 2, 4, 8)
  *   AFSAI_OPT_PCG_CSR_A       1: pcg_solve multiplies by A in CSR (group per row) instead of
  *                             converting it to the SELL-64 layout first
- *   AFSAI_OPT_PCG_UNFUSED     1: separate vector-update kernels in the preconditioned
- *                             iteration (the fused form gives identical results)
+ *   AFSAI_OPT_PCG_FORM        0: automatic (products that also form the updated vectors
+ *                             below 200,000 rows, separate update kernels above); 1: separate
+ *                             update kernels; 2: fused products (used only when no SELL
+ *                             matrix of the solve is split, see AFSAI_OPT_SELL_WIDTH); all
+ *                             forms give identical results
+ *   AFSAI_OPT_SELL_WIDTH      entries per row held by the 64-row slices of every SELL layout
+ *                             built afterwards; longer rows keep their leading entries in a
+ *                             second, length-sorted layout multiplied first (0: split only
+ *                             when padding would exceed a tenth of the entries, at the width
+ *                             that minimises the work; products are identical either way)
  * Returns AFSAI_ERR_INVALID_ARG for an unknown option or value.  Not thread safe against
  * concurrent calls of the library.
  */
@@ -208,7 +216,8 @@ const char *afsai_last_error(void);
 #define AFSAI_OPT_SPMV_GROUP 3
 #define AFSAI_OPT_SPMV_UNROLL 4
 #define AFSAI_OPT_PCG_CSR_A 5
-#define AFSAI_OPT_PCG_UNFUSED 6
+#define AFSAI_OPT_PCG_FORM 6
+#define AFSAI_OPT_SELL_WIDTH 7
 int afsai_set_option(int32_t option, int64_t value);
 
 /*

@@ -32,7 +32,8 @@ EXPORTS = ("afsai_setup", "afsai_apply", "pcg_solve", "afsai_spmv", "afsai_get_s
            "afsai_export_rows", "afsai_import", "afsai_destroy", "afsai_last_error", "afsai_set_option",
            "afsai_release_cache",
            "afsai_profile_enable", "afsai_profile_read")
-OPT_SETUP_GROUP, OPT_SETUP_TABLE, OPT_SPMV_GROUP, OPT_SPMV_UNROLL, OPT_PCG_CSR_A, OPT_PCG_UNFUSED = 1, 2, 3, 4, 5, 6
+(OPT_SETUP_GROUP, OPT_SETUP_TABLE, OPT_SPMV_GROUP, OPT_SPMV_UNROLL, OPT_PCG_CSR_A, OPT_PCG_FORM,
+ OPT_SELL_WIDTH) = 1, 2, 3, 4, 5, 6, 7
 
 
 class CsrStruct(ctypes.Structure):

@@ -17,6 +17,8 @@ namespace afsai {
 // errors
 // ---------------------------------------------------------------------------------------
 void set_error(const char *fmt, ...);
+// set_error, returning `code`
+int set_error_code(int code, const char *fmt, ...);
 void clear_error();
 
 #define AFSAI_HIP_TRY(expr)                                                                  \

@@ -22,9 +22,19 @@ void set_error(const char *fmt, ...) {
     g_last_error = buf;
 }
 
+int set_error_code(int code, const char *fmt, ...) {
+    char buf[1024];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
 void clear_error() { g_last_error.clear(); }
 
-static int64_t g_options[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+static int64_t g_options[16] = {0};
 
 int64_t option(int id) { return (id > 0 && id < 8) ? g_options[id] : 0; }
 
@@ -233,7 +243,8 @@ int afsai_set_option(int32_t opt, int64_t value) {
         case AFSAI_OPT_SPMV_GROUP: ok = value == 0 || (pow2(value) && value >= 4 && value <= 64); break;
         case AFSAI_OPT_SPMV_UNROLL: ok = value == 0 || (pow2(value) && value <= 8); break;
         case AFSAI_OPT_PCG_CSR_A: ok = (value == 0 || value == 1); break;
-        case AFSAI_OPT_PCG_UNFUSED: ok = (value == 0 || value == 1); break;
+        case AFSAI_OPT_PCG_FORM: ok = (value >= 0 && value <= 2); break;
+        case AFSAI_OPT_SELL_WIDTH: ok = (value >= 0 && value <= 4096); break;
         default: ok = false;
     }
     if (!ok) AFSAI_FAIL(AFSAI_ERR_INVALID_ARG, "afsai_set_option: bad option %d / value %lld", opt, (long long)value);

@@ -1,4 +1,7 @@
 // Device scan and the SELL-64 layout used by the PCG products (sell.hpp).
+#include <algorithm>
+#include <vector>
+
 #include "sell.hpp"
 
 namespace afsai {
@@ -99,8 +102,16 @@ int scan_counts(int n, const int32_t *cnt, int32_t *out, int64_t *total, const D
 }
 
 // ---------------------------------------------------------------------------------------
-// SELL-64 construction
+// SELL-64 construction.  Rows come either from a CSR matrix (rp) or from padded per-row
+// results (m[r] entries at r * ld).
 // ---------------------------------------------------------------------------------------
+__device__ __forceinline__ int row_len(const int32_t *rp, const int32_t *m, int r) {
+    return rp ? rp[r + 1] - rp[r] : m[r];
+}
+__device__ __forceinline__ int64_t row_start(const int32_t *rp, int ld, int r) {
+    return rp ? (int64_t)rp[r] : (int64_t)r * ld;
+}
+
 // rows sorted by length (longest first, ties by row index) inside windows of kSortWindow rows;
 // one block per window, bitonic sort of (length, row) keys in LDS
 __global__ __launch_bounds__(1024) void k_sell_sort(int n, const int32_t *__restrict__ rp,
@@ -111,7 +122,7 @@ __global__ __launch_bounds__(1024) void k_sell_sort(int n, const int32_t *__rest
         const int r = w0 + j;
         unsigned long long k = ~0ull;
         if (r < n) {
-            const uint32_t len = (uint32_t)(rp ? rp[r + 1] - rp[r] : m[r]);
+            const uint32_t len = (uint32_t)row_len(rp, m, r);
             k = ((unsigned long long)(0xFFFFFFFFu - len) << 32) | (uint32_t)j;
         }
         key[j] = k;
@@ -140,44 +151,62 @@ __global__ __launch_bounds__(1024) void k_sell_sort(int n, const int32_t *__rest
     }
 }
 
-// width of each slice = longest row in it (one wavefront per slice)
+// width of each slice = its longest row, capped at `cap` entries (one wavefront per slice)
 __global__ __launch_bounds__(256) void k_sell_width(int n, int nslices, const int32_t *__restrict__ rp,
                                                      const int32_t *__restrict__ m, const int32_t *__restrict__ perm,
-                                                     int32_t *__restrict__ width) {
+                                                     int cap, int32_t *__restrict__ width) {
     const int lane = threadIdx.x & 63;
     for (int sl = (blockIdx.x * blockDim.x + threadIdx.x) >> 6; sl < nslices; sl += (gridDim.x * blockDim.x) >> 6) {
         int r = sl * kSlice + lane;
         if (perm) r = perm[r];
         int len = 0;
-        if (r >= 0 && r < n) len = rp ? rp[r + 1] - rp[r] : m[r];
+        if (r >= 0 && r < n) len = min(row_len(rp, m, r), cap);
         len = wave_max(len);
         if (lane == 0) width[sl] = len;
     }
 }
 
-// one wavefront per slice; lane = row; padding entries are (own row, 0)
+constexpr int kHistBins = 256;
+constexpr bool kSortTail = false;  // tail rows stay in row order (local gathers and writes)
+
+// histogram of row lengths (the last bin holds every longer row)
+__global__ __launch_bounds__(256) void k_len_hist(int n, const int32_t *__restrict__ rp, const int32_t *__restrict__ m,
+                                                   int32_t *__restrict__ hist) {
+    __shared__ int32_t h[kHistBins];
+    for (int j = threadIdx.x; j < kHistBins; j += blockDim.x) h[j] = 0;
+    __syncthreads();
+    for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < n; r += gridDim.x * blockDim.x)
+        atomicAdd(&h[min(row_len(rp, m, r), kHistBins - 1)], 1);
+    __syncthreads();
+    for (int j = threadIdx.x; j < kHistBins; j += blockDim.x)
+        if (h[j]) atomicAdd(&hist[j], h[j]);
+}
+
+// One wavefront per slice; lane = row; the slices hold the last min(len, cap) entries of each
+// row; padding entries are (own row, 0).  init[sl] marks the lanes whose rows are longer.
 template <typename VI, typename VO>
 __global__ __launch_bounds__(256) void k_sell_fill(int n, int nslices, const int32_t *__restrict__ rp,
                                                     const int32_t *__restrict__ m, int ld,
                                                     const int32_t *__restrict__ ci, const VI *__restrict__ val,
                                                     const int32_t *__restrict__ perm,
-                                                    const int32_t *__restrict__ sptr, int32_t *__restrict__ col,
-                                                    VO *__restrict__ out) {
+                                                    const int32_t *__restrict__ sptr, int cap,
+                                                    int32_t *__restrict__ col, VO *__restrict__ out,
+                                                    uint64_t *__restrict__ init) {
     const int lane = threadIdx.x & 63;
     for (int sl = (blockIdx.x * blockDim.x + threadIdx.x) >> 6; sl < nslices; sl += (gridDim.x * blockDim.x) >> 6) {
         int r = sl * kSlice + lane;
         if (perm) r = perm[r];
-        int len = 0;
+        int len = 0, keep = 0;
         int64_t start = 0;
         const bool valid = r >= 0 && r < n;
         if (valid) {
-            if (rp) {
-                start = rp[r];
-                len = rp[r + 1] - rp[r];
-            } else {
-                start = (int64_t)r * ld;
-                len = m[r];
-            }
+            len = row_len(rp, m, r);
+            keep = min(len, cap);
+            start = row_start(rp, ld, r) + (len - keep);
+        }
+        if (init) {
+            const uint64_t longer = __ballot(valid && len > cap);
+            if (lane == 0) init[sl] = longer;
         }
         const int pad_col = valid ? r : n - 1;
         const int64_t base = (int64_t)sptr[sl] * kSlice + lane;
@@ -190,7 +219,7 @@ __global__ __launch_bounds__(256) void k_sell_fill(int n, int nslices, const int
                 const int k = k0 + u;
                 cv[u] = pad_col;
                 vv[u] = VO(0);
-                if (k < len) {
+                if (k < keep) {
                     cv[u] = ci[start + k];
                     vv[u] = (VO)val[start + k];
                 }
@@ -207,17 +236,129 @@ __global__ __launch_bounds__(256) void k_sell_fill(int n, int nslices, const int
     }
 }
 
+// leading entries of the rows longer than cap: count per row, and a 0/1 flag per row
+__global__ void k_tail_count(int n, const int32_t *__restrict__ rp, const int32_t *__restrict__ m, int cap,
+                             int32_t *__restrict__ tl, int32_t *__restrict__ flag) {
+    for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < n; r += gridDim.x * blockDim.x) {
+        const int t = max(0, row_len(rp, m, r) - cap);
+        tl[r] = t;
+        flag[r] = t > 0 ? 1 : 0;
+    }
+}
+
+// the tail as CSR over the longer rows (ascending): row k = rowlist[k], its first len - cap
+// entries
+template <typename VI>
+__global__ void k_tail_fill(int n, const int32_t *__restrict__ rp, const int32_t *__restrict__ m, int ld,
+                            const int32_t *__restrict__ ci, const VI *__restrict__ val, const int32_t *__restrict__ tl,
+                            const int32_t *__restrict__ toff, const int32_t *__restrict__ pos,
+                            int32_t *__restrict__ trp, int32_t *__restrict__ tci, VI *__restrict__ tval,
+                            int32_t *__restrict__ rowlist) {
+    for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < n; r += gridDim.x * blockDim.x) {
+        const int t = tl[r];
+        if (t <= 0) continue;
+        const int k = pos[r];
+        rowlist[k] = r;
+        trp[k] = toff[r];
+        const int64_t src = row_start(rp, ld, r);
+        for (int e = 0; e < t; ++e) {
+            tci[toff[r] + e] = ci[src + e];
+            tval[toff[r] + e] = val[src + e];
+        }
+    }
+}
+
+__global__ void k_set_i32(int32_t *p, int32_t v) { *p = v; }
+
 void sell_free(Sell *S) {
     if (!S) return;
     pool_free(S->sptr);
     pool_free(S->col);
     pool_free(S->val);
     pool_free(S->perm);
+    pool_free(S->rowmap);
+    pool_free(S->init);
+    if (S->tail) {
+        sell_free(S->tail);
+        delete S->tail;
+    }
     *S = Sell();
 }
 
-static int sell_build(int n, int64_t nnz_in, const int32_t *rp, const int32_t *m, int ld, const int32_t *ci,
-                      const void *val, bool val_f32, bool out_f32, Sell *out, const DeviceInfo &di, hipStream_t s) {
+static int sell_build(int n, int64_t nnz, const int32_t *rp, const int32_t *m, int ld, const int32_t *ci,
+                      const void *val, bool val_f32, bool out_f32, bool top, Sell *out, const DeviceInfo &di,
+                      hipStream_t s);
+
+// The tail of a split layout: CSR of the leading entries of the rows longer than cap, then
+// a sorted SELL of it whose rows map back to rows of the full matrix.
+static int build_tail(int n, const int32_t *rp, const int32_t *m, int ld, const int32_t *ci, const void *val,
+                      bool val_f32, bool out_f32, int cap, Sell **out, const DeviceInfo &di, hipStream_t s) {
+    DevBuf tl, flag, toff, pos;
+    int rc;
+    if ((rc = dalloc(tl, sizeof(int32_t) * (size_t)n, s))) return rc;
+    if ((rc = dalloc(flag, sizeof(int32_t) * (size_t)n, s))) return rc;
+    if ((rc = dalloc(toff, sizeof(int32_t) * (size_t)(n + 1), s))) return rc;
+    if ((rc = dalloc(pos, sizeof(int32_t) * (size_t)(n + 1), s))) return rc;
+    hipLaunchKernelGGL(k_tail_count, dim3(grid1d(n, di)), dim3(256), 0, s, n, rp, m, cap, tl.as<int32_t>(),
+                       flag.as<int32_t>());
+    int64_t tnnz = 0, nrows = 0;
+    if ((rc = scan_counts(n, tl.as<int32_t>(), toff.as<int32_t>(), &tnnz, di, s))) return rc;
+    if ((rc = scan_counts(n, flag.as<int32_t>(), pos.as<int32_t>(), &nrows, di, s))) return rc;
+    *out = nullptr;
+    if (nrows == 0) return AFSAI_OK;
+    const size_t vb = val_f32 ? sizeof(float) : sizeof(double);
+    DevBuf trp, tci, tval;
+    if ((rc = dalloc(trp, sizeof(int32_t) * (size_t)(nrows + 1), s))) return rc;
+    if ((rc = dalloc(tci, sizeof(int32_t) * (size_t)tnnz, s))) return rc;
+    if ((rc = dalloc(tval, vb * (size_t)tnnz, s))) return rc;
+    int32_t *rowlist = (int32_t *)pool_alloc(sizeof(int32_t) * (size_t)nrows);
+    if (!rowlist) AFSAI_FAIL(AFSAI_ERR_NO_MEMORY, "SELL layout: out of device memory");
+    if (val_f32)
+        hipLaunchKernelGGL(k_tail_fill<float>, dim3(grid1d(n, di)), dim3(256), 0, s, n, rp, m, ld, ci,
+                           (const float *)val, tl.as<int32_t>(), toff.as<int32_t>(), pos.as<int32_t>(),
+                           trp.as<int32_t>(), tci.as<int32_t>(), tval.as<float>(), rowlist);
+    else
+        hipLaunchKernelGGL(k_tail_fill<double>, dim3(grid1d(n, di)), dim3(256), 0, s, n, rp, m, ld, ci,
+                           (const double *)val, tl.as<int32_t>(), toff.as<int32_t>(), pos.as<int32_t>(),
+                           trp.as<int32_t>(), tci.as<int32_t>(), tval.as<double>(), rowlist);
+    hipLaunchKernelGGL(k_set_i32, dim3(1), dim3(1), 0, s, trp.as<int32_t>() + nrows, (int32_t)tnnz);
+    Sell *T = new Sell();
+    rc = sell_build((int)nrows, tnnz, trp.as<int32_t>(), nullptr, 0, tci.as<int32_t>(), tval.p, val_f32, out_f32,
+                    false, T, di, s);
+    if (rc) {
+        pool_free(rowlist);
+        delete T;
+        return rc;
+    }
+    T->rowmap = rowlist;
+    *out = T;
+    return AFSAI_OK;
+}
+
+// Splitting width: minimises the slice entries (padding included) plus three times the tail
+// entries (gathered through a second, sorted layout), from the slice widths and the length
+// histogram.  Returns 0 when keeping whole rows is cheapest.
+static int choose_cap(const std::vector<int32_t> &width, const std::vector<int32_t> &hist) {
+    int maxw = 0;
+    for (int w : width) maxw = std::max(maxw, w);
+    double best = 0.0;
+    for (int w : width) best += (double)w * kSlice;
+    int best_cap = 0;
+    for (int cap = 1; cap < std::min(maxw, kHistBins - 1); ++cap) {
+        double cost = 0.0;
+        for (int w : width) cost += (double)std::min(w, cap) * kSlice;
+        for (int L = cap + 1; L < kHistBins; ++L) cost += 3.0 * (double)(L - cap) * hist[L];
+        if (cost < best) {
+            best = cost;
+            best_cap = cap;
+        }
+    }
+    return best_cap;
+}
+
+static int sell_build(int n, int64_t nnz, const int32_t *rp, const int32_t *m, int ld, const int32_t *ci,
+                      const void *val, bool val_f32, bool out_f32, bool top, Sell *out, const DeviceInfo &di,
+                      hipStream_t s) {
     Sell S;
     S.n = n;
     S.nslices = (n + kSlice - 1) / kSlice;
@@ -228,74 +369,94 @@ static int sell_build(int n, int64_t nnz_in, const int32_t *rp, const int32_t *m
     const int nbs = grid1d((int64_t)S.nslices * 64, di);
     S.sptr = (uint32_t *)pool_alloc(sizeof(uint32_t) * (size_t)(S.nslices + 1));
     if (!S.sptr) AFSAI_FAIL(AFSAI_ERR_NO_MEMORY, "SELL layout: out of device memory");
-    // stored entries of the plain layout
-    hipLaunchKernelGGL(k_sell_width, dim3(nbs), dim3(256), 0, s, n, S.nslices, rp, m, nullptr, width.as<int32_t>());
-    int64_t cols = 0;
-    if ((rc = scan_counts(S.nslices, width.as<int32_t>(), (int32_t *)S.sptr, &cols, di, s))) {
+    auto fail = [&](int code) {
         sell_free(&S);
-        return rc;
-    }
-    // per-row results (rp == nullptr) have rows of nearly equal length: never sorted
-    const int64_t nnz = rp ? nnz_in : cols * kSlice;
-    if (cols * kSlice > nnz + nnz / 10 && n > kSlice) {
+        return code;
+    };
+    const int kNoCap = 0x7fffffff;
+    hipLaunchKernelGGL(k_sell_width, dim3(nbs), dim3(256), 0, s, n, S.nslices, rp, m, nullptr, kNoCap,
+                       width.as<int32_t>());
+    int64_t cols = 0;
+    if ((rc = scan_counts(S.nslices, width.as<int32_t>(), (int32_t *)S.sptr, &cols, di, s))) return fail(rc);
+    int cap = kNoCap;
+    const bool padded = cols * kSlice > nnz + nnz / 10 && n > kSlice;
+    if (top) {
+        const int forced = (int)option(AFSAI_OPT_SELL_WIDTH);
+        if (forced > 0) {
+            cap = forced;
+        } else if (padded) {
+            // split at the width that minimises the work (host choice from device statistics)
+            DevBuf hist;
+            if ((rc = dalloc(hist, sizeof(int32_t) * kHistBins, s))) return fail(rc);
+            if (hipMemsetAsync(hist.p, 0, sizeof(int32_t) * kHistBins, s) != hipSuccess)
+                return fail(set_error_code(AFSAI_ERR_HIP, "SELL layout: memset failed"));
+            hipLaunchKernelGGL(k_len_hist, dim3(grid1d(n, di)), dim3(256), 0, s, n, rp, m, hist.as<int32_t>());
+            std::vector<int32_t> hw(S.nslices), hh(kHistBins);
+            if (hipMemcpyAsync(hw.data(), width.p, sizeof(int32_t) * S.nslices, hipMemcpyDeviceToHost, s) != hipSuccess ||
+                hipMemcpyAsync(hh.data(), hist.p, sizeof(int32_t) * kHistBins, hipMemcpyDeviceToHost, s) != hipSuccess ||
+                hipStreamSynchronize(s) != hipSuccess)
+                return fail(set_error_code(AFSAI_ERR_HIP, "SELL layout: statistics copy failed"));
+            const int c = choose_cap(hw, hh);
+            if (c > 0) cap = c;
+        }
+        if (cap != kNoCap) {
+            hipLaunchKernelGGL(k_sell_width, dim3(nbs), dim3(256), 0, s, n, S.nslices, rp, m, nullptr, cap,
+                               width.as<int32_t>());
+            if ((rc = scan_counts(S.nslices, width.as<int32_t>(), (int32_t *)S.sptr, &cols, di, s))) return fail(rc);
+            if ((rc = build_tail(n, rp, m, ld, ci, val, val_f32, out_f32, cap, &S.tail, di, s))) return fail(rc);
+            if (S.tail) {
+                S.width_cap = cap;
+                S.init = (uint64_t *)pool_alloc(sizeof(uint64_t) * (size_t)S.nslices);
+                if (!S.init) return fail(set_error_code(AFSAI_ERR_NO_MEMORY, "SELL layout: out of device memory"));
+            } else {
+                cap = kNoCap;
+            }
+        }
+    } else if (padded && rp && kSortTail) {
         // rows of very different lengths: sort by length inside windows, then re-measure
         S.perm = (int32_t *)pool_alloc(sizeof(int32_t) * (size_t)S.nslices * kSlice);
-        if (!S.perm) {
-            sell_free(&S);
-            AFSAI_FAIL(AFSAI_ERR_NO_MEMORY, "SELL layout: out of device memory");
-        }
+        if (!S.perm) return fail(set_error_code(AFSAI_ERR_NO_MEMORY, "SELL layout: out of device memory"));
         const int nwin = (n + kSortWindow - 1) / kSortWindow;
         hipLaunchKernelGGL(k_sell_sort, dim3(nwin), dim3(1024), 0, s, n, rp, m, S.perm);
-        hipLaunchKernelGGL(k_sell_width, dim3(nbs), dim3(256), 0, s, n, S.nslices, rp, m, S.perm,
+        hipLaunchKernelGGL(k_sell_width, dim3(nbs), dim3(256), 0, s, n, S.nslices, rp, m, S.perm, kNoCap,
                            width.as<int32_t>());
-        if ((rc = scan_counts(S.nslices, width.as<int32_t>(), (int32_t *)S.sptr, &cols, di, s))) {
-            sell_free(&S);
-            return rc;
-        }
+        if ((rc = scan_counts(S.nslices, width.as<int32_t>(), (int32_t *)S.sptr, &cols, di, s))) return fail(rc);
     }
-    if (cols >= ((int64_t)1 << 31)) {
-        sell_free(&S);
-        AFSAI_FAIL(AFSAI_ERR_TOO_LARGE, "SELL layout: %lld columns", (long long)cols);
-    }
-    S.entries = cols * kSlice;
-    S.col = (int32_t *)pool_alloc(sizeof(int32_t) * (size_t)S.entries);
-    S.val = pool_alloc((out_f32 ? sizeof(float) : sizeof(double)) * (size_t)S.entries);
-    if (!S.col || !S.val) {
-        sell_free(&S);
-        AFSAI_FAIL(AFSAI_ERR_NO_MEMORY, "SELL layout: out of device memory");
-    }
+    if (cols >= ((int64_t)1 << 31))
+        return fail(set_error_code(AFSAI_ERR_TOO_LARGE, "SELL layout: %lld columns", (long long)cols));
+    S.entries = cols * kSlice + (S.tail ? S.tail->entries : 0);
+    S.col = (int32_t *)pool_alloc(sizeof(int32_t) * (size_t)cols * kSlice);
+    S.val = pool_alloc((out_f32 ? sizeof(float) : sizeof(double)) * (size_t)cols * kSlice);
+    if (!S.col || !S.val) return fail(set_error_code(AFSAI_ERR_NO_MEMORY, "SELL layout: out of device memory"));
     const int32_t *sp = (const int32_t *)S.sptr;
     if (val_f32) {
         if (out_f32)
             hipLaunchKernelGGL((k_sell_fill<float, float>), dim3(nbs), dim3(256), 0, s, n, S.nslices, rp, m, ld, ci,
-                               (const float *)val, S.perm, sp, S.col, (float *)S.val);
+                               (const float *)val, S.perm, sp, cap, S.col, (float *)S.val, S.init);
         else
             hipLaunchKernelGGL((k_sell_fill<float, double>), dim3(nbs), dim3(256), 0, s, n, S.nslices, rp, m, ld, ci,
-                               (const float *)val, S.perm, sp, S.col, (double *)S.val);
+                               (const float *)val, S.perm, sp, cap, S.col, (double *)S.val, S.init);
     } else {
         if (out_f32)
             hipLaunchKernelGGL((k_sell_fill<double, float>), dim3(nbs), dim3(256), 0, s, n, S.nslices, rp, m, ld, ci,
-                               (const double *)val, S.perm, sp, S.col, (float *)S.val);
+                               (const double *)val, S.perm, sp, cap, S.col, (float *)S.val, S.init);
         else
             hipLaunchKernelGGL((k_sell_fill<double, double>), dim3(nbs), dim3(256), 0, s, n, S.nslices, rp, m, ld,
-                               ci, (const double *)val, S.perm, sp, S.col, (double *)S.val);
+                               ci, (const double *)val, S.perm, sp, cap, S.col, (double *)S.val, S.init);
     }
-    if (hipGetLastError() != hipSuccess) {
-        sell_free(&S);
-        AFSAI_FAIL(AFSAI_ERR_HIP, "SELL layout: launch failed");
-    }
+    if (hipGetLastError() != hipSuccess) return fail(set_error_code(AFSAI_ERR_HIP, "SELL layout: launch failed"));
     *out = S;
     return AFSAI_OK;
 }
 
 int sell_from_csr(int n, int64_t nnz, const int32_t *rp, const int32_t *ci, const void *val, bool val_f32,
                   bool out_f32, Sell *out, const DeviceInfo &di, hipStream_t s) {
-    return sell_build(n, nnz, rp, nullptr, 0, ci, val, val_f32, out_f32, out, di, s);
+    return sell_build(n, nnz, rp, nullptr, 0, ci, val, val_f32, out_f32, true, out, di, s);
 }
 
-int sell_from_ell(int n, int ld, const int32_t *m, const int32_t *ell_col, const double *ell_val, bool out_f32,
-                  Sell *out, const DeviceInfo &di, hipStream_t s) {
-    return sell_build(n, 0, nullptr, m, ld, ell_col, ell_val, false, out_f32, out, di, s);
+int sell_from_ell(int n, int64_t nnz, int ld, const int32_t *m, const int32_t *ell_col, const double *ell_val,
+                  bool out_f32, Sell *out, const DeviceInfo &di, hipStream_t s) {
+    return sell_build(n, nnz, nullptr, m, ld, ell_col, ell_val, false, out_f32, true, out, di, s);
 }
 
 }  // namespace afsai

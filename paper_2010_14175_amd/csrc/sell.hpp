@@ -3,10 +3,16 @@
 // rows is contiguous, so one lane per row reads the matrix with fully coalesced 512-byte
 // (values) and 256-byte (columns) wave loads, and the x entries of neighbouring rows are read
 // together.  Rows shorter than the slice's longest row are padded with (own row, 0.0).
+//
 // When that padding would exceed a tenth of the entries (rows of very different lengths, as
-// in G^T), rows are first sorted by length inside windows of kSortWindow rows and the slices
-// follow that order (SELL-C-sigma, Kreutzer et al. 2014); `perm` then maps slice lanes back
-// to rows.
+// in G^T), the layout is split: every row keeps its last w entries in the slices (w chosen
+// from the length histogram), and the leading entries of the longer rows form a second, small
+// SELL matrix (`tail`) over those rows only, sorted by length inside windows of kSortWindow
+// rows (SELL-C-sigma, Kreutzer et al. 2014; `perm` maps its slice lanes to its rows and
+// `rowmap` its rows to rows of the full matrix).  The tail is multiplied first; the main
+// product then continues the sums of the rows marked in `init` from y.  Each row's sum is
+// one sequential chain over its entries in stored order either way, so all layouts give
+// bit-identical products.
 #pragma once
 
 #include "common.hpp"
@@ -19,12 +25,16 @@ constexpr int kSortWindow = 4096;
 struct Sell {
     int n = 0;
     int nslices = 0;
-    uint32_t *sptr = nullptr;  // [nslices + 1] offsets in 64-entry columns
-    int32_t *col = nullptr;    // [sptr[nslices] * 64]
-    void *val = nullptr;       // double or float, same layout
-    int32_t *perm = nullptr;   // [nslices * 64] row of each slice lane (nullptr: identity)
+    uint32_t *sptr = nullptr;   // [nslices + 1] offsets in 64-entry columns
+    int32_t *col = nullptr;     // [sptr[nslices] * 64]
+    void *val = nullptr;        // double or float, same layout
+    int32_t *perm = nullptr;    // [nslices * 64] row of each slice lane (nullptr: identity)
+    int32_t *rowmap = nullptr;  // [n] output row of each row (nullptr: identity)
+    uint64_t *init = nullptr;   // [nslices] lanes whose sums continue from y (nullptr: none)
+    Sell *tail = nullptr;       // leading entries of the rows longer than the slices hold
     bool f32 = false;
-    int64_t entries = 0;       // stored entries including padding
+    int64_t entries = 0;        // stored entries including padding (tail included)
+    int width_cap = 0;          // entries per row held by the slices (0: all)
 };
 
 // SELL-64 copy of a CSR matrix (device arrays); values converted to out_f32 ? float : double.
@@ -32,9 +42,9 @@ struct Sell {
 int sell_from_csr(int n, int64_t nnz, const int32_t *rp, const int32_t *ci, const void *val, bool val_f32,
                   bool out_f32, Sell *out, const DeviceInfo &di, hipStream_t s);
 // SELL-64 copy of padded row-major per-row results (ell_col/ell_val, ld entries per row, m[i]
-// valid): the setup's direct output for G.
-int sell_from_ell(int n, int ld, const int32_t *m, const int32_t *ell_col, const double *ell_val, bool out_f32,
-                  Sell *out, const DeviceInfo &di, hipStream_t s);
+// valid, nnz in total): the setup's direct output for G.
+int sell_from_ell(int n, int64_t nnz, int ld, const int32_t *m, const int32_t *ell_col, const double *ell_val,
+                  bool out_f32, Sell *out, const DeviceInfo &di, hipStream_t s);
 void sell_free(Sell *S);
 
 }  // namespace afsai

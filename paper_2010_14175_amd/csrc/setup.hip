@@ -537,7 +537,7 @@ int afsai_setup(const afsai_csr *A, const afsai_params *p, void *stream, afsai_p
     AFSAI_HIP_TRY(hipGetLastError());
     {
         ProfScope ps("sell_G", s);
-        if ((rc = sell_from_ell(n, ldell, mcnt.as<int32_t>(), ell_col.as<int32_t>(), ell_val.as<double>(), f32, &P->sg,
+        if ((rc = sell_from_ell(n, P->nnz_g, ldell, mcnt.as<int32_t>(), ell_col.as<int32_t>(), ell_val.as<double>(), f32, &P->sg,
                                 di, s)))
             return fail(rc);
     }

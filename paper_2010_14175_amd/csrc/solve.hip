@@ -23,6 +23,7 @@
 namespace afsai {
 
 constexpr int kThreads = 256;
+constexpr int kFusedMaxRows = 200000;  // automatic PCG form: fused products below this size
 
 enum : int { FIN_NONE = 0, FIN_ALPHA = 1, FIN_BETA = 2, FIN_RHO0 = 3, FIN_INIT = 4, FIN_UPDATE = 5, FIN_RESID = 6 };
 enum : int { DONE_NO = 0, DONE_CONVERGED = 1, DONE_NOT_SPD = 2, DONE_MAXIT = 3, DONE_ZERO_RHS = 4 };
@@ -181,6 +182,8 @@ __global__ __launch_bounds__(kThreads) void k_spmv(int n, const int32_t *__restr
 template <int U, typename VT, bool DOT>
 __global__ __launch_bounds__(kThreads) void k_sell_spmv(int n, int nslices, const uint32_t *__restrict__ sptr,
                                                          const int32_t *__restrict__ perm,
+                                                         const int32_t *__restrict__ rowmap,
+                                                         const uint64_t *__restrict__ init,
                                                          const int32_t *__restrict__ col,
                                                          const VT *__restrict__ val,
                                                          const double *__restrict__ x, double *__restrict__ y,
@@ -197,10 +200,13 @@ __global__ __launch_bounds__(kThreads) void k_sell_spmv(int n, int nslices, cons
     for (int sl = s0 + wv; sl < s1; sl += kThreads / 64) {
         int r = sl * kSlice + lane;
         if (perm) r = perm[r];
+        const bool valid = r >= 0 && r < n;
+        const int ro = (valid && rowmap) ? rowmap[r] : r;
         const uint32_t c0 = sptr[sl];
         const int width = (int)(sptr[sl + 1] - c0);
         const int64_t base = (int64_t)c0 * kSlice + lane;
-        double acc = 0.0;
+        // rows split between the two layouts continue the sum their tail started
+        double acc = (init && valid && ((init[sl] >> lane) & 1)) ? y[ro] : 0.0;
         for (int k0 = 0; k0 < width; k0 += U) {
             int c[U];
             VT v[U];
@@ -218,9 +224,9 @@ __global__ __launch_bounds__(kThreads) void k_sell_spmv(int n, int nslices, cons
             for (int u = 0; u < U; ++u)
                 if (c[u] >= 0) acc = fma((double)v[u], x[c[u]], acc);
         }
-        if (r >= 0 && r < n) {
-            y[r] = acc;
-            if (DOT) part = fma(acc, w[r], part);
+        if (valid) {
+            y[ro] = acc;
+            if (DOT) part = fma(acc, w[ro], part);
         }
     }
     if (DOT) {
@@ -489,10 +495,10 @@ static void launch_sell_t(const Sell &S, const double *x, double *y, const doubl
                           PcgScalars *sc, int fin, int nb, int nxcd, hipStream_t s) {
     if (w)
         hipLaunchKernelGGL((k_sell_spmv<U, VT, true>), dim3(nb), dim3(kThreads), 0, s, S.n, S.nslices, S.sptr,
-                           S.perm, S.col, (const VT *)S.val, x, y, w, partials, sc, fin, nxcd);
+                           S.perm, S.rowmap, S.init, S.col, (const VT *)S.val, x, y, w, partials, sc, fin, nxcd);
     else
         hipLaunchKernelGGL((k_sell_spmv<U, VT, false>), dim3(nb), dim3(kThreads), 0, s, S.n, S.nslices, S.sptr,
-                           S.perm, S.col, (const VT *)S.val, x, y, w, partials, sc, fin, nxcd);
+                           S.perm, S.rowmap, S.init, S.col, (const VT *)S.val, x, y, w, partials, sc, fin, nxcd);
 }
 
 template <typename VT>
@@ -506,14 +512,29 @@ static void launch_sell_v(const Sell &S, int un, const double *x, double *y, con
     }
 }
 
-// y = S x for a SELL-64 matrix (optionally fused dot y.w finalised into sc)
-static void sell_spmv(const char *name, const Sell &S, const double *x, double *y, const double *w,
-                      double *partials, PcgScalars *sc, int fin, const DeviceInfo &di, hipStream_t s) {
-    int un = option(AFSAI_OPT_SPMV_UNROLL) > 0 ? (int)option(AFSAI_OPT_SPMV_UNROLL) : 8;
+static int sell_blocks(const Sell &S, const DeviceInfo &di) {
     int64_t nb = ((int64_t)S.nslices + kThreads / 64 - 1) / (kThreads / 64);
     const int64_t cap = (int64_t)di.num_cus * 16;
     if (nb > cap) nb = cap;
     if (nb < 1) nb = 1;
+    return (int)nb;
+}
+
+// y = S x for a SELL-64 matrix (optionally fused dot y.w finalised into sc); a split layout's
+// tail is multiplied first
+static void sell_spmv(const char *name, const Sell &S, const double *x, double *y, const double *w,
+                      double *partials, PcgScalars *sc, int fin, const DeviceInfo &di, hipStream_t s) {
+    int un = option(AFSAI_OPT_SPMV_UNROLL) > 0 ? (int)option(AFSAI_OPT_SPMV_UNROLL) : 8;
+    if (S.tail) {
+        const Sell &T = *S.tail;
+        const int nbt = sell_blocks(T, di);
+        ProfScope ps("sell_tail", s);
+        if (T.f32)
+            launch_sell_v<float>(T, un, x, y, nullptr, nullptr, sc, FIN_NONE, nbt, di.num_xcds, s);
+        else
+            launch_sell_v<double>(T, un, x, y, nullptr, nullptr, sc, FIN_NONE, nbt, di.num_xcds, s);
+    }
+    const int64_t nb = sell_blocks(S, di);
     {
         ProfScope ps(name, s);
         if (S.f32)
@@ -693,7 +714,11 @@ int pcg_solve(const afsai_csr *A, afsai_precond P, const double *b, double *x, d
     }
     // fused iteration (preconditioned, A in SELL-64): p and r are double-buffered because the
     // products read neighbours' old entries while owners store the new ones
-    const bool fused = P && use_sell && option(AFSAI_OPT_PCG_UNFUSED) == 0;
+    // fused products where launches dominate (small systems), separate updates where the
+    // fused products' second gather costs more than the update kernels
+    const int64_t form = option(AFSAI_OPT_PCG_FORM);
+    const bool want_fused = form == 2 || (form == 0 && n < kFusedMaxRows);
+    const bool fused = P && use_sell && want_fused && !As.tail && !P->sg.tail;
     if (!fused) hipLaunchKernelGGL(k_update_p, dim3(nbv), dim3(kThreads), 0, s, n, p, zz, sc, 1, di.num_xcds);
     int iter_no = 0;  // iterations enqueued so far
 

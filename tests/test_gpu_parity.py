@@ -344,27 +344,54 @@ def test_pcg_edge_cases(af):
     assert info.status == af.ERR_NOT_SPD
 
 
-@pytest.mark.parametrize("opt,make", [("unfused", lambda: synth.elasticity27(10)), ("csr_a", lambda: synth.elasticity27(10)),
-                                      ("unfused", lambda: synth.poisson7(9)), ("csr_a", lambda: synth.poisson7(9))])
+@pytest.mark.parametrize("opt,make", [("separate", lambda: synth.elasticity27(10)), ("fused", lambda: synth.elasticity27(10)),
+                                      ("csr_a", lambda: synth.elasticity27(10)), ("separate", lambda: synth.poisson7(9)),
+                                      ("fused", lambda: synth.poisson7(9)), ("csr_a", lambda: synth.poisson7(9))])
 def test_pcg_forms_identical(af, opt, make):
-    """The fused iteration equals the separate update kernels bit for bit; the CSR product for
-    A agrees with the SELL-64 one to rounding (same iteration count).  The 9^3 Poisson matrix
-    has enough short boundary rows to get the length-sorted SELL layout."""
+    """Fused products and separate update kernels give the same iterates bit for bit; the CSR
+    product for A agrees with the SELL-64 one to rounding (same iteration count).  The 9^3
+    Poisson matrix has enough short boundary rows to get a split SELL layout for A."""
     Pb = make()
     dA = _dev(af, Pb.A)
     P = af.setup(dA, 10, 2, 1e-2)
     x1, i1 = af.pcg_solve(dA, P, _vec(Pb.b))
-    o = af.OPT_PCG_UNFUSED if opt == "unfused" else af.OPT_PCG_CSR_A
+    o, v = {"separate": (af.OPT_PCG_FORM, 1), "fused": (af.OPT_PCG_FORM, 2), "csr_a": (af.OPT_PCG_CSR_A, 1)}[opt]
     try:
-        af.set_option(o, 1)
+        af.set_option(o, v)
         x2, i2 = af.pcg_solve(dA, P, _vec(Pb.b))
     finally:
         af.set_option(o, 0)
     assert i1.iters == i2.iters
-    if opt == "unfused":
+    if opt != "csr_a":
         assert bool((x1 == x2).all())
     else:
         assert float((x1 - x2).norm() / x1.norm()) < X_RTOL
+
+
+@pytest.mark.parametrize("width", [1, 3, 8, 17])
+@pytest.mark.parametrize("make", [lambda: synth.elasticity27(10), lambda: synth.random_sparse_spd(3000, 40, 3)])
+def test_split_layouts_identical(af, make, width):
+    """SELL layouts split at any width (the slices keep each row's last w entries, a sorted
+    second layout the leading ones, multiplied first) give G^T(G r) and the PCG iterates bit
+    for bit equal to the automatic layouts: each row is one sequential chain either way."""
+    Pb = make()
+    A = Pb.A if hasattr(Pb, "A") else Pb
+    b = Pb.b if hasattr(Pb, "b") else A.to_scipy() @ synth.uniform(7, 2, A.n, -1.0, 1.0)
+    dA = _dev(af, A)
+    r = _vec(synth.uniform(5, 9, A.n))
+    P1 = af.setup(dA, 6, 2, 1e-2)
+    z1 = P1.apply(r)
+    x1, i1 = af.pcg_solve(dA, P1, _vec(b), maxit=2000)
+    try:
+        af.set_option(af.OPT_SELL_WIDTH, width)
+        P2 = af.setup(dA, 6, 2, 1e-2)
+        z2 = P2.apply(r)
+        x2, i2 = af.pcg_solve(dA, P2, _vec(b), maxit=2000)
+    finally:
+        af.set_option(af.OPT_SELL_WIDTH, 0)
+    assert bool((z1 == z2).all())
+    assert i1.iters == i2.iters
+    assert bool((x1 == x2).all())
 
 
 def test_pcg_deterministic(af):
