@@ -147,6 +147,38 @@ int afsai_apply(afsai_precond P, const double *r, double *z, void *stream);
 int pcg_solve(const afsai_csr *A, afsai_precond P, const double *b, double *x, double rtol,
               int32_t maxit, void *stream, afsai_pcg_info *info);
 
+/*
+ * Batches of independent systems (many small SPD systems solved together).
+ *   The systems are given as one block-diagonal CSR matrix: system k owns rows (and columns)
+ *   offsets[k] .. offsets[k+1]-1, and no row has an entry outside its system.  Because rows are
+ *   set up independently (Sec. 2) and gradients never leave a block, the setup of the batch is
+ *   one launch of the setup over the whole matrix; the candidate tie rule (smallest column) does
+ *   not depend on where a system sits, so each system's G is the one a separate afsai_setup of
+ *   that system gives, bit for bit.  The solver then runs all systems together, each with its
+ *   own scalars and stopping test; a system's iterates and x are those of a separate pcg_solve
+ *   of it, bit for bit (its dot products are summed over the same partition).
+ *   offsets (host) nsys + 1 entries, offsets[0] = 0, strictly increasing, offsets[nsys] = n.
+ */
+
+/*
+ * afsai_setup_batched -- afsai_setup of a batch.  Returns AFSAI_ERR_BAD_MATRIX when a row has
+ *   an entry outside its system.  The handle's products follow the systems (every system
+ *   starts a new 64-row slice); it can only be used with pcg_solve_batched and the same
+ *   offsets, or with afsai_apply.
+ */
+int afsai_setup_batched(const afsai_csr *A, int32_t nsys, const int32_t *offsets, const afsai_params *p,
+                        void *stream, afsai_precond *out);
+
+/*
+ * pcg_solve_batched -- pcg_solve of every system of a batch at once.  P is NULL (plain CG) or
+ *   a handle from afsai_setup_batched with the same offsets.  b, x (device) length n.
+ *   info (host, may be NULL): nsys entries, one per system.  Iteration ends when every system
+ *   has stopped.  Returns AFSAI_OK when all converged, else the status of the first system
+ *   that did not (AFSAI_ERR_NOT_SPD, AFSAI_ERR_NOT_CONVERGED; x and info filled).  Synchronous.
+ */
+int pcg_solve_batched(const afsai_csr *A, afsai_precond P, int32_t nsys, const int32_t *offsets, const double *b,
+                      double *x, double rtol, int32_t maxit, void *stream, afsai_pcg_info *info);
+
 /* afsai_spmv -- y = A x (group-per-row CSR product used by the solver).  Asynchronous. */
 int afsai_spmv(const afsai_csr *A, const double *x, double *y, void *stream);
 

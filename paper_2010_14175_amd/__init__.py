@@ -28,7 +28,8 @@ VALIDATE = 1
 STOP_KMAX, STOP_EPS, STOP_NOCAND = 0, 1, 2
 
 # every symbol the C header declares
-EXPORTS = ("afsai_setup", "afsai_apply", "pcg_solve", "afsai_spmv", "afsai_get_setup_info", "afsai_export",
+EXPORTS = ("afsai_setup", "afsai_apply", "pcg_solve", "afsai_setup_batched", "pcg_solve_batched", "afsai_spmv",
+           "afsai_get_setup_info", "afsai_export",
            "afsai_export_rows", "afsai_import", "afsai_destroy", "afsai_last_error", "afsai_set_option",
            "afsai_release_cache",
            "afsai_profile_enable", "afsai_profile_read")
@@ -84,6 +85,9 @@ def lib():
         L.afsai_apply.argtypes = [vp, vp, vp, vp]
         L.pcg_solve.argtypes = [P(CsrStruct), vp, vp, vp, ctypes.c_double, i32, vp, P(PcgInfoStruct)]
         L.afsai_spmv.argtypes = [P(CsrStruct), vp, vp, vp]
+        L.afsai_setup_batched.argtypes = [P(CsrStruct), i32, P(i32), P(ParamsStruct), vp, P(vp)]
+        L.pcg_solve_batched.argtypes = [P(CsrStruct), vp, i32, P(i32), vp, vp, ctypes.c_double, i32, vp,
+                                        P(PcgInfoStruct)]
         L.afsai_get_setup_info.argtypes = [vp, P(SetupInfoStruct)]
         L.afsai_export.argtypes = [vp, vp, vp, vp, vp]
         L.afsai_export_rows.argtypes = [vp, vp, vp, vp, vp]
@@ -267,6 +271,44 @@ def pcg_solve(A: DeviceCSR, P: Preconditioner | None, b, x=None, rtol: float = 1
     if raise_on_error:
         _check(rc, "pcg_solve", allow=(OK, ERR_NOT_CONVERGED))
     return x, PcgInfo(rc, inf.iters, bool(inf.converged), inf.relres, inf.true_relres, inf.ms)
+
+
+def _offsets(offsets):
+    import numpy as np
+
+    off = np.ascontiguousarray(np.asarray(offsets, dtype=np.int32))
+    return off, off.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), len(off) - 1
+
+
+def setup_batched(A: DeviceCSR, offsets, kmax: int, s: int, eps: float, tie_rtol: float = TIE_RTOL,
+                  g_prec: int = F64, validate: bool = False, stream=None) -> Preconditioner:
+    """Setup of a batch of independent systems given as one block-diagonal matrix whose system
+    k owns rows offsets[k] .. offsets[k+1]-1 (``afsai_setup_batched``)."""
+    p = ParamsStruct(int(kmax), int(s), float(eps), float(tie_rtol), int(g_prec), VALIDATE if validate else 0)
+    off, optr, nsys = _offsets(offsets)
+    h = ctypes.c_void_p()
+    st = A.struct
+    _check(lib().afsai_setup_batched(ctypes.byref(st), nsys, optr, ctypes.byref(p), _stream(stream), ctypes.byref(h)),
+           "afsai_setup_batched")
+    return Preconditioner(h)
+
+
+def pcg_solve_batched(A: DeviceCSR, P: Preconditioner | None, offsets, b, x=None, rtol: float = 1e-8,
+                      maxit: int | None = None, stream=None, raise_on_error: bool = True):
+    """PCG on every system of a batch (``pcg_solve_batched``).  Returns (x, [PcgInfo per system])."""
+    import torch
+
+    off, optr, nsys = _offsets(offsets)
+    if x is None:
+        x = torch.zeros_like(b)
+    maxit = int(max(off[1:] - off[:-1])) if maxit is None else int(maxit)
+    infs = (PcgInfoStruct * nsys)()
+    st = A.struct
+    rc = lib().pcg_solve_batched(ctypes.byref(st), None if P is None else P.handle, nsys, optr, _ptr(b), _ptr(x),
+                                 float(rtol), maxit, _stream(stream), infs)
+    if raise_on_error:
+        _check(rc, "pcg_solve_batched", allow=(OK, ERR_NOT_CONVERGED))
+    return x, [PcgInfo(rc, f.iters, bool(f.converged), f.relres, f.true_relres, f.ms) for f in infs]
 
 
 def spmv(A: DeviceCSR, x, y=None, stream=None):

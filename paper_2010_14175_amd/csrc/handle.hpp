@@ -1,6 +1,8 @@
 // The opaque preconditioner handle behind afsai_precond.
 #pragma once
 
+#include <vector>
+
 #include "sell.hpp"
 
 struct afsai_precond_s {
@@ -22,4 +24,7 @@ struct afsai_precond_s {
     double *work = nullptr;
     size_t work_elems = 0;
     afsai_setup_info info{};
+    // batch of independent systems (afsai_setup_batched): first row of each system, nsys + 1
+    // entries; empty for a single system
+    std::vector<int32_t> seg_row0;
 };

@@ -112,6 +112,17 @@ __device__ __forceinline__ int64_t row_start(const int32_t *rp, int ld, int r) {
     return rp ? (int64_t)rp[r] : (int64_t)r * ld;
 }
 
+// rows [r0, r1) of slice sl
+__device__ __forceinline__ void slice_rows(const int32_t *srow0, int n, int sl, int &r0, int &r1) {
+    if (srow0) {
+        r0 = srow0[sl];
+        r1 = srow0[sl + 1];
+    } else {
+        r0 = sl * kSlice;
+        r1 = min(n, r0 + kSlice);
+    }
+}
+
 // rows sorted by length (longest first, ties by row index) inside windows of kSortWindow rows;
 // one block per window, bitonic sort of (length, row) keys in LDS
 __global__ __launch_bounds__(1024) void k_sell_sort(int n, const int32_t *__restrict__ rp,
@@ -154,13 +165,16 @@ __global__ __launch_bounds__(1024) void k_sell_sort(int n, const int32_t *__rest
 // width of each slice = its longest row, capped at `cap` entries (one wavefront per slice)
 __global__ __launch_bounds__(256) void k_sell_width(int n, int nslices, const int32_t *__restrict__ rp,
                                                      const int32_t *__restrict__ m, const int32_t *__restrict__ perm,
-                                                     int cap, int32_t *__restrict__ width) {
+                                                     const int32_t *__restrict__ srow0, int cap,
+                                                     int32_t *__restrict__ width) {
     const int lane = threadIdx.x & 63;
     for (int sl = (blockIdx.x * blockDim.x + threadIdx.x) >> 6; sl < nslices; sl += (gridDim.x * blockDim.x) >> 6) {
-        int r = sl * kSlice + lane;
-        if (perm) r = perm[r];
+        int r0, r1;
+        slice_rows(srow0, n, sl, r0, r1);
+        int r = r0 + lane;
+        if (perm) r = perm[sl * kSlice + lane];
         int len = 0;
-        if (r >= 0 && r < n) len = min(row_len(rp, m, r), cap);
+        if (r >= 0 && r < (perm ? n : r1)) len = min(row_len(rp, m, r), cap);
         len = wave_max(len);
         if (lane == 0) width[sl] = len;
     }
@@ -189,16 +203,19 @@ __global__ __launch_bounds__(256) void k_sell_fill(int n, int nslices, const int
                                                     const int32_t *__restrict__ m, int ld,
                                                     const int32_t *__restrict__ ci, const VI *__restrict__ val,
                                                     const int32_t *__restrict__ perm,
+                                                    const int32_t *__restrict__ srow0,
                                                     const int32_t *__restrict__ sptr, int cap,
                                                     int32_t *__restrict__ col, VO *__restrict__ out,
                                                     uint64_t *__restrict__ init) {
     const int lane = threadIdx.x & 63;
     for (int sl = (blockIdx.x * blockDim.x + threadIdx.x) >> 6; sl < nslices; sl += (gridDim.x * blockDim.x) >> 6) {
-        int r = sl * kSlice + lane;
-        if (perm) r = perm[r];
+        int r0, r1;
+        slice_rows(srow0, n, sl, r0, r1);
+        int r = r0 + lane;
+        if (perm) r = perm[sl * kSlice + lane];
         int len = 0, keep = 0;
         int64_t start = 0;
-        const bool valid = r >= 0 && r < n;
+        const bool valid = r >= 0 && r < (perm ? n : r1);
         if (valid) {
             len = row_len(rp, m, r);
             keep = min(len, cap);
@@ -208,7 +225,7 @@ __global__ __launch_bounds__(256) void k_sell_fill(int n, int nslices, const int
             const uint64_t longer = __ballot(valid && len > cap);
             if (lane == 0) init[sl] = longer;
         }
-        const int pad_col = valid ? r : n - 1;
+        const int pad_col = valid ? r : r0;
         const int64_t base = (int64_t)sptr[sl] * kSlice + lane;
         const int width = sptr[sl + 1] - sptr[sl];
         for (int k0 = 0; k0 < width; k0 += 8) {
@@ -278,6 +295,7 @@ void sell_free(Sell *S) {
     pool_free(S->perm);
     pool_free(S->rowmap);
     pool_free(S->init);
+    pool_free(S->srow0);
     if (S->tail) {
         sell_free(S->tail);
         delete S->tail;
@@ -287,7 +305,7 @@ void sell_free(Sell *S) {
 
 static int sell_build(int n, int64_t nnz, const int32_t *rp, const int32_t *m, int ld, const int32_t *ci,
                       const void *val, bool val_f32, bool out_f32, bool top, Sell *out, const DeviceInfo &di,
-                      hipStream_t s);
+                      hipStream_t s, const Segments &seg);
 
 // The tail of a split layout: CSR of the leading entries of the rows longer than cap, then
 // a sorted SELL of it whose rows map back to rows of the full matrix.
@@ -324,7 +342,7 @@ static int build_tail(int n, const int32_t *rp, const int32_t *m, int ld, const 
     hipLaunchKernelGGL(k_set_i32, dim3(1), dim3(1), 0, s, trp.as<int32_t>() + nrows, (int32_t)tnnz);
     Sell *T = new Sell();
     rc = sell_build((int)nrows, tnnz, trp.as<int32_t>(), nullptr, 0, tci.as<int32_t>(), tval.p, val_f32, out_f32,
-                    false, T, di, s);
+                    false, T, di, s, Segments());
     if (rc) {
         pool_free(rowlist);
         delete T;
@@ -356,25 +374,51 @@ static int choose_cap(const std::vector<int32_t> &width, const std::vector<int32
     return best_cap;
 }
 
+void segment_slices(const Segments &seg, int n, int32_t *slice0) {
+    slice0[0] = 0;
+    if (!seg.row0 || seg.nsys <= 1) {
+        slice0[1] = (n + kSlice - 1) / kSlice;
+        return;
+    }
+    for (int k = 0; k < seg.nsys; ++k)
+        slice0[k + 1] = slice0[k] + (seg.row0[k + 1] - seg.row0[k] + kSlice - 1) / kSlice;
+}
+
 static int sell_build(int n, int64_t nnz, const int32_t *rp, const int32_t *m, int ld, const int32_t *ci,
                       const void *val, bool val_f32, bool out_f32, bool top, Sell *out, const DeviceInfo &di,
-                      hipStream_t s) {
+                      hipStream_t s, const Segments &seg) {
     Sell S;
     S.n = n;
-    S.nslices = (n + kSlice - 1) / kSlice;
     S.f32 = out_f32;
-    DevBuf width;
     int rc;
-    if ((rc = dalloc(width, sizeof(int32_t) * (size_t)S.nslices, s))) return rc;
-    const int nbs = grid1d((int64_t)S.nslices * 64, di);
-    S.sptr = (uint32_t *)pool_alloc(sizeof(uint32_t) * (size_t)(S.nslices + 1));
-    if (!S.sptr) AFSAI_FAIL(AFSAI_ERR_NO_MEMORY, "SELL layout: out of device memory");
     auto fail = [&](int code) {
         sell_free(&S);
         return code;
     };
+    if (seg.row0 && seg.nsys > 1) {
+        // every system starts a new slice
+        std::vector<int32_t> slice0(seg.nsys + 1);
+        segment_slices(seg, n, slice0.data());
+        S.nslices = slice0[seg.nsys];
+        std::vector<int32_t> h(S.nslices + 1);
+        for (int k = 0; k < seg.nsys; ++k)
+            for (int j = slice0[k]; j < slice0[k + 1]; ++j) h[j] = seg.row0[k] + (j - slice0[k]) * kSlice;
+        h[S.nslices] = n;
+        S.srow0 = (int32_t *)pool_alloc(sizeof(int32_t) * h.size());
+        if (!S.srow0) return fail(set_error_code(AFSAI_ERR_NO_MEMORY, "SELL layout: out of device memory"));
+        if (hipMemcpyAsync(S.srow0, h.data(), sizeof(int32_t) * h.size(), hipMemcpyHostToDevice, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+            return fail(set_error_code(AFSAI_ERR_HIP, "SELL layout: copy of the slice rows failed"));
+    } else {
+        S.nslices = (n + kSlice - 1) / kSlice;
+    }
+    DevBuf width;
+    if ((rc = dalloc(width, sizeof(int32_t) * (size_t)S.nslices, s))) return fail(rc);
+    const int nbs = grid1d((int64_t)S.nslices * 64, di);
+    S.sptr = (uint32_t *)pool_alloc(sizeof(uint32_t) * (size_t)(S.nslices + 1));
+    if (!S.sptr) return fail(set_error_code(AFSAI_ERR_NO_MEMORY, "SELL layout: out of device memory"));
     const int kNoCap = 0x7fffffff;
-    hipLaunchKernelGGL(k_sell_width, dim3(nbs), dim3(256), 0, s, n, S.nslices, rp, m, nullptr, kNoCap,
+    hipLaunchKernelGGL(k_sell_width, dim3(nbs), dim3(256), 0, s, n, S.nslices, rp, m, nullptr, S.srow0, kNoCap,
                        width.as<int32_t>());
     int64_t cols = 0;
     if ((rc = scan_counts(S.nslices, width.as<int32_t>(), (int32_t *)S.sptr, &cols, di, s))) return fail(rc);
@@ -400,7 +444,7 @@ static int sell_build(int n, int64_t nnz, const int32_t *rp, const int32_t *m, i
             if (c > 0) cap = c;
         }
         if (cap != kNoCap) {
-            hipLaunchKernelGGL(k_sell_width, dim3(nbs), dim3(256), 0, s, n, S.nslices, rp, m, nullptr, cap,
+            hipLaunchKernelGGL(k_sell_width, dim3(nbs), dim3(256), 0, s, n, S.nslices, rp, m, nullptr, S.srow0, cap,
                                width.as<int32_t>());
             if ((rc = scan_counts(S.nslices, width.as<int32_t>(), (int32_t *)S.sptr, &cols, di, s))) return fail(rc);
             if ((rc = build_tail(n, rp, m, ld, ci, val, val_f32, out_f32, cap, &S.tail, di, s))) return fail(rc);
@@ -418,7 +462,7 @@ static int sell_build(int n, int64_t nnz, const int32_t *rp, const int32_t *m, i
         if (!S.perm) return fail(set_error_code(AFSAI_ERR_NO_MEMORY, "SELL layout: out of device memory"));
         const int nwin = (n + kSortWindow - 1) / kSortWindow;
         hipLaunchKernelGGL(k_sell_sort, dim3(nwin), dim3(1024), 0, s, n, rp, m, S.perm);
-        hipLaunchKernelGGL(k_sell_width, dim3(nbs), dim3(256), 0, s, n, S.nslices, rp, m, S.perm, kNoCap,
+        hipLaunchKernelGGL(k_sell_width, dim3(nbs), dim3(256), 0, s, n, S.nslices, rp, m, S.perm, nullptr, kNoCap,
                            width.as<int32_t>());
         if ((rc = scan_counts(S.nslices, width.as<int32_t>(), (int32_t *)S.sptr, &cols, di, s))) return fail(rc);
     }
@@ -432,17 +476,17 @@ static int sell_build(int n, int64_t nnz, const int32_t *rp, const int32_t *m, i
     if (val_f32) {
         if (out_f32)
             hipLaunchKernelGGL((k_sell_fill<float, float>), dim3(nbs), dim3(256), 0, s, n, S.nslices, rp, m, ld, ci,
-                               (const float *)val, S.perm, sp, cap, S.col, (float *)S.val, S.init);
+                               (const float *)val, S.perm, S.srow0, sp, cap, S.col, (float *)S.val, S.init);
         else
             hipLaunchKernelGGL((k_sell_fill<float, double>), dim3(nbs), dim3(256), 0, s, n, S.nslices, rp, m, ld, ci,
-                               (const float *)val, S.perm, sp, cap, S.col, (double *)S.val, S.init);
+                               (const float *)val, S.perm, S.srow0, sp, cap, S.col, (double *)S.val, S.init);
     } else {
         if (out_f32)
             hipLaunchKernelGGL((k_sell_fill<double, float>), dim3(nbs), dim3(256), 0, s, n, S.nslices, rp, m, ld, ci,
-                               (const double *)val, S.perm, sp, cap, S.col, (float *)S.val, S.init);
+                               (const double *)val, S.perm, S.srow0, sp, cap, S.col, (float *)S.val, S.init);
         else
             hipLaunchKernelGGL((k_sell_fill<double, double>), dim3(nbs), dim3(256), 0, s, n, S.nslices, rp, m, ld,
-                               ci, (const double *)val, S.perm, sp, cap, S.col, (double *)S.val, S.init);
+                               ci, (const double *)val, S.perm, S.srow0, sp, cap, S.col, (double *)S.val, S.init);
     }
     if (hipGetLastError() != hipSuccess) return fail(set_error_code(AFSAI_ERR_HIP, "SELL layout: launch failed"));
     *out = S;
@@ -450,13 +494,13 @@ static int sell_build(int n, int64_t nnz, const int32_t *rp, const int32_t *m, i
 }
 
 int sell_from_csr(int n, int64_t nnz, const int32_t *rp, const int32_t *ci, const void *val, bool val_f32,
-                  bool out_f32, Sell *out, const DeviceInfo &di, hipStream_t s) {
-    return sell_build(n, nnz, rp, nullptr, 0, ci, val, val_f32, out_f32, true, out, di, s);
+                  bool out_f32, Sell *out, const DeviceInfo &di, hipStream_t s, const Segments &seg) {
+    return sell_build(n, nnz, rp, nullptr, 0, ci, val, val_f32, out_f32, true, out, di, s, seg);
 }
 
 int sell_from_ell(int n, int64_t nnz, int ld, const int32_t *m, const int32_t *ell_col, const double *ell_val,
-                  bool out_f32, Sell *out, const DeviceInfo &di, hipStream_t s) {
-    return sell_build(n, nnz, nullptr, m, ld, ell_col, ell_val, false, out_f32, true, out, di, s);
+                  bool out_f32, Sell *out, const DeviceInfo &di, hipStream_t s, const Segments &seg) {
+    return sell_build(n, nnz, nullptr, m, ld, ell_col, ell_val, false, out_f32, true, out, di, s, seg);
 }
 
 }  // namespace afsai

@@ -32,19 +32,30 @@ struct Sell {
     int32_t *rowmap = nullptr;  // [n] output row of each row (nullptr: identity)
     uint64_t *init = nullptr;   // [nslices] lanes whose sums continue from y (nullptr: none)
     Sell *tail = nullptr;       // leading entries of the rows longer than the slices hold
+    int32_t *srow0 = nullptr;   // [nslices + 1] first row of each slice (nullptr: 64 * slice);
+                                // set when slices follow the systems of a batch
     bool f32 = false;
     int64_t entries = 0;        // stored entries including padding (tail included)
     int width_cap = 0;          // entries per row held by the slices (0: all)
 };
 
+// Rows of a batch of independent systems: system k owns rows row0[k] .. row0[k+1]-1 (host).
+// With nsys > 1 every system starts a new slice, so a slice never holds rows of two systems.
+struct Segments {
+    int nsys = 1;
+    const int32_t *row0 = nullptr;  // host, nsys + 1 entries (nullptr: one system)
+};
+// slices of each system under a segmentation: slice0[k] .. slice0[k+1]-1 (host, nsys + 1)
+void segment_slices(const Segments &seg, int n, int32_t *slice0);
+
 // SELL-64 copy of a CSR matrix (device arrays); values converted to out_f32 ? float : double.
 // Synchronous on s.  On failure nothing is left allocated.
 int sell_from_csr(int n, int64_t nnz, const int32_t *rp, const int32_t *ci, const void *val, bool val_f32,
-                  bool out_f32, Sell *out, const DeviceInfo &di, hipStream_t s);
+                  bool out_f32, Sell *out, const DeviceInfo &di, hipStream_t s, const Segments &seg = Segments());
 // SELL-64 copy of padded row-major per-row results (ell_col/ell_val, ld entries per row, m[i]
 // valid, nnz in total): the setup's direct output for G.
 int sell_from_ell(int n, int64_t nnz, int ld, const int32_t *m, const int32_t *ell_col, const double *ell_val,
-                  bool out_f32, Sell *out, const DeviceInfo &di, hipStream_t s);
+                  bool out_f32, Sell *out, const DeviceInfo &di, hipStream_t s, const Segments &seg = Segments());
 void sell_free(Sell *S);
 
 }  // namespace afsai

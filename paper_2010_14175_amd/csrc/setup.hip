@@ -262,6 +262,21 @@ __global__ void k_fill_i32(int64_t n, int32_t *__restrict__ p, int32_t v) {
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) p[e] = v;
 }
 
+// batches: every row's first and last column lie inside its own system (rows ascending), so
+// the matrix is block diagonal
+__global__ void k_block_check(int n, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci, int nsys,
+                              const int32_t *__restrict__ row0, ScanOut *out) {
+    for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < n; r += gridDim.x * blockDim.x) {
+        int lo = 0, hi = nsys - 1;  // system k with row0[k] <= r < row0[k+1]
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (row0[mid] <= r) lo = mid; else hi = mid - 1;
+        }
+        const int a = rp[r], b = rp[r + 1];
+        if (b > a && (ci[a] < row0[lo] || ci[b - 1] >= row0[lo + 1])) atomicOr(&out->bad, 1);
+    }
+}
+
 // ---------------------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------------------
@@ -309,7 +324,7 @@ static void free_handle(afsai_precond_s *P) {
 
 // G^T as SELL-64, built from the CSR G of the handle (count, scan, fill, sort, convert)
 template <typename VT>
-static int build_transpose(afsai_precond_s *P, const DeviceInfo &di, hipStream_t s) {
+static int build_transpose(afsai_precond_s *P, const DeviceInfo &di, hipStream_t s, const Segments &seg) {
     const int n = P->n;
     const int64_t nnz = P->nnz_g;
     DevBuf cnt, rp, ci, val;
@@ -337,7 +352,7 @@ static int build_transpose(afsai_precond_s *P, const DeviceInfo &di, hipStream_t
     AFSAI_HIP_TRY(hipGetLastError());
     const bool f32 = sizeof(VT) == 4;
     ProfScope ps("sell_GT", s);
-    return sell_from_csr(n, nnz, rp.as<int32_t>(), ci.as<int32_t>(), val.p, f32, f32, &P->sgt, di, s);
+    return sell_from_csr(n, nnz, rp.as<int32_t>(), ci.as<int32_t>(), val.p, f32, f32, &P->sgt, di, s, seg);
 }
 
 static int alloc_workspace(afsai_precond_s *P, const DeviceInfo &di) {
@@ -355,8 +370,10 @@ using namespace afsai;
 
 extern "C" {
 
-int afsai_setup(const afsai_csr *A, const afsai_params *p, void *stream, afsai_precond *out) {
-    clear_error();
+// The adaptive setup of A; a batch (nsys > 1, row0: host, nsys + 1 entries) must be block
+// diagonal, and its G and G^T layouts then follow the systems.
+static int setup_core(const afsai_csr *A, const afsai_params *p, int nsys, const int32_t *row0, void *stream,
+                      afsai_precond *out) {
     if (out) *out = nullptr;
     if (!A || !p || !out) AFSAI_FAIL(AFSAI_ERR_INVALID_ARG, "afsai_setup: null argument");
     if (A->n <= 0 || A->nnz < A->n) AFSAI_FAIL(AFSAI_ERR_INVALID_ARG, "afsai_setup: n = %d, nnz = %d", A->n, A->nnz);
@@ -406,6 +423,20 @@ int afsai_setup(const afsai_csr *A, const afsai_params *p, void *stream, afsai_p
     if (so.bad) AFSAI_FAIL(AFSAI_ERR_BAD_MATRIX, "afsai_setup: CSR structure invalid (columns unsorted, duplicate or out of range)");
     if (so.asym) AFSAI_FAIL(AFSAI_ERR_BAD_MATRIX, "afsai_setup: matrix is not exactly symmetric");
     if (so.nodiag) AFSAI_FAIL(AFSAI_ERR_BAD_MATRIX, "afsai_setup: %d rows without a diagonal entry (or unsorted columns)", so.nodiag);
+    Segments seg;
+    if (nsys > 1) {
+        seg.nsys = nsys;
+        seg.row0 = row0;
+        DevBuf r0b;
+        if ((rc = dalloc(r0b, sizeof(int32_t) * (size_t)(nsys + 1), s))) return rc;
+        AFSAI_HIP_TRY(hipMemcpyAsync(r0b.p, row0, sizeof(int32_t) * (size_t)(nsys + 1), hipMemcpyHostToDevice, s));
+        AFSAI_HIP_TRY(hipMemsetAsync(scanb.p, 0, sizeof(ScanOut), s));
+        hipLaunchKernelGGL(k_block_check, dim3(grid1d(n, di)), dim3(256), 0, s, n, A->row_ptr, A->col_idx, nsys,
+                           r0b.as<int32_t>(), scanb.as<ScanOut>());
+        AFSAI_HIP_TRY(hipMemcpyAsync(&so, scanb.p, sizeof so, hipMemcpyDeviceToHost, s));
+        AFSAI_HIP_TRY(hipStreamSynchronize(s));
+        if (so.bad) AFSAI_FAIL(AFSAI_ERR_BAD_MATRIX, "afsai_setup_batched: a row has entries outside its system");
+    }
     const int maxlen = so.maxlen > 0 ? so.maxlen : 1;
 
     // ---- kernel shape: pattern capacity and candidate table size
@@ -538,10 +569,11 @@ int afsai_setup(const afsai_csr *A, const afsai_params *p, void *stream, afsai_p
     {
         ProfScope ps("sell_G", s);
         if ((rc = sell_from_ell(n, P->nnz_g, ldell, mcnt.as<int32_t>(), ell_col.as<int32_t>(), ell_val.as<double>(), f32, &P->sg,
-                                di, s)))
+                                di, s, seg)))
             return fail(rc);
     }
-    rc = f32 ? build_transpose<float>(P, di, s) : build_transpose<double>(P, di, s);
+    if (nsys > 1) P->seg_row0.assign(row0, row0 + nsys + 1);
+    rc = f32 ? build_transpose<float>(P, di, s, seg) : build_transpose<double>(P, di, s, seg);
     if (rc) return fail(rc);
     P->psi = (double *)psi.release();
     P->steps = (int32_t *)steps.release();
@@ -568,6 +600,24 @@ int afsai_setup(const afsai_csr *A, const afsai_params *p, void *stream, afsai_p
     inf.ms = ms;
     *out = P;
     return AFSAI_OK;
+}
+
+int afsai_setup(const afsai_csr *A, const afsai_params *p, void *stream, afsai_precond *out) {
+    clear_error();
+    return setup_core(A, p, 1, nullptr, stream, out);
+}
+
+int afsai_setup_batched(const afsai_csr *A, int32_t nsys, const int32_t *offsets, const afsai_params *p, void *stream,
+                        afsai_precond *out) {
+    clear_error();
+    if (out) *out = nullptr;
+    if (!A || !offsets || nsys < 1) AFSAI_FAIL(AFSAI_ERR_INVALID_ARG, "afsai_setup_batched: null argument or nsys < 1");
+    if (offsets[0] != 0 || offsets[nsys] != A->n)
+        AFSAI_FAIL(AFSAI_ERR_INVALID_ARG, "afsai_setup_batched: offsets must run from 0 to n = %d", A->n);
+    for (int k = 0; k < nsys; ++k)
+        if (offsets[k + 1] <= offsets[k])
+            AFSAI_FAIL(AFSAI_ERR_INVALID_ARG, "afsai_setup_batched: system %d is empty or offsets decrease", k);
+    return setup_core(A, p, nsys, offsets, stream, out);
 }
 
 int afsai_get_setup_info(afsai_precond P, afsai_setup_info *info) {
@@ -651,7 +701,7 @@ int afsai_import(const afsai_csr *G, int32_t g_prec, void *stream, afsai_precond
         return fail(AFSAI_ERR_HIP);
     }
     if ((rc = sell_from_csr(P->n, P->nnz_g, P->g_rp, P->g_ci, P->g_val, f32, f32, &P->sg, di, s))) return fail(rc);
-    rc = f32 ? build_transpose<float>(P, di, s) : build_transpose<double>(P, di, s);
+    rc = f32 ? build_transpose<float>(P, di, s, Segments()) : build_transpose<double>(P, di, s, Segments());
     if (rc) return fail(rc);
     if ((rc = alloc_workspace(P, di))) return fail(rc);
     if (hipStreamSynchronize(s) != hipSuccess) {

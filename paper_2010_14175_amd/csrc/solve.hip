@@ -7,6 +7,12 @@
 // contiguous range of rows and blocks are renumbered so that every XCD streams one contiguous
 // part of the matrix (its L2 then holds the x entries its rows share).
 //
+// Batches: the solver always runs over a batch of independent systems (one system for
+// pcg_solve).  Each system keeps its own scalars and done flag; every launch maps its blocks
+// to (system, block within the system) with the block count a single-system solve of that
+// system would use, and dot products are summed per system over exactly those blocks, so a
+// system's iterates do not depend on its batch-mates (bit for bit).
+//
 // PCG: all scalars (rho, alpha, beta, ||r||) live on the device.  Dot products are fused into
 // the kernel that produces one of their operands, which stores one partial sum per block; a
 // one-block kernel then adds the partials in block order (results do not depend on
@@ -15,6 +21,7 @@
 // L2 and cost more than the extra launch.)  A device flag ends the iteration: kernels that
 // see it return at once, so the host enqueues chunks of iterations and reads the flag once
 // per chunk, one chunk behind.
+#include <algorithm>
 #include <cmath>
 #include <vector>
 
@@ -43,6 +50,57 @@ struct PcgScalars {
     double resid;    // ||b - A x||^2 of the final check
 };
 
+// Systems of a batch (device arrays; nullptr: one system covering everything)
+struct Systems {
+    const int32_t *row0 = nullptr;    // [nsys + 1] first row of each system
+    const int32_t *slice0 = nullptr;  // [nsys + 1] first SELL slice of each system
+};
+// Blocks of one launch shape (device arrays; nullptr: one system, block b = its block b)
+struct Map {
+    const int32_t *blk_sys = nullptr;  // [nblocks] system of each (logical) block
+    const int32_t *sys_b0 = nullptr;   // [nsys] first block of each system
+    const int32_t *sys_nb = nullptr;   // [nsys] blocks of each system
+};
+
+struct Job {
+    int k;   // system
+    int lb;  // block within the system
+    int nb;  // blocks of the system
+    int gb;  // logical block of the launch (index of the partial sums)
+};
+
+__device__ __forceinline__ Job block_job(const Map &mp, int nxcd) {
+    Job j;
+    j.gb = xcd_block(blockIdx.x, gridDim.x, nxcd);
+    if (mp.blk_sys) {
+        j.k = mp.blk_sys[j.gb];
+        j.lb = j.gb - mp.sys_b0[j.k];
+        j.nb = mp.sys_nb[j.k];
+    } else {
+        j.k = 0;
+        j.lb = j.gb;
+        j.nb = gridDim.x;
+    }
+    return j;
+}
+
+// [lo, hi) of the `count` items starting at `base` that block lb of nb owns
+__device__ __forceinline__ void block_range(int base, int count, int lb, int nb, int &lo, int &hi) {
+    const int64_t per = ((int64_t)count + nb - 1) / nb;
+    lo = base + (int)min<int64_t>(count, per * lb);
+    hi = base + (int)min<int64_t>(count, per * (lb + 1));
+}
+
+__device__ __forceinline__ void sys_rows(const Systems &sy, int n, int k, int &r0, int &r1) {
+    if (sy.row0) {
+        r0 = sy.row0[k];
+        r1 = sy.row0[k + 1];
+    } else {
+        r0 = 0;
+        r1 = n;
+    }
+}
+
 // ---------------------------------------------------------------------------------------
 // block helpers
 // ---------------------------------------------------------------------------------------
@@ -58,26 +116,31 @@ __device__ __forceinline__ double block_sum(double v, double *sh /* >= kThreads/
     return t;  // valid in thread 0
 }
 
-// thread 0 stores this block's partial sums, slot k at partials[k * gridDim.x + idx], idx being
-// the index of the block's range of rows (so the sums are added in row order)
-__device__ __forceinline__ void store_partials(double *partials, int slots, const double *mine, int idx) {
+// thread 0 stores this block's partial sums, slot k at partials[k * gridDim.x + gb], gb being
+// the logical block (blocks of one system are consecutive and cover its rows in order)
+__device__ __forceinline__ void store_partials(double *partials, int slots, const double *mine, int gb) {
     if (threadIdx.x == 0)
-        for (int k = 0; k < slots; ++k) partials[(size_t)k * gridDim.x + idx] = mine[k];
+        for (int k = 0; k < slots; ++k) partials[(size_t)k * gridDim.x + gb] = mine[k];
 }
 
-// One block: sums the partials of the previous kernel in block order and updates the scalars.
-__global__ __launch_bounds__(kThreads) void k_finalize(const double *__restrict__ partials, int nparts, int fin,
-                                                       PcgScalars *sc) {
+// One block per system: sums the system's partials of the previous launch (nblocks blocks in
+// all) in block order and updates its scalars.
+__global__ __launch_bounds__(kThreads) void k_finalize(const double *__restrict__ partials, int nblocks, Map mp,
+                                                       int fin, PcgScalars *scs) {
+    const int k = blockIdx.x;
+    PcgScalars *sc = scs + k;
     if ((fin == FIN_ALPHA || fin == FIN_BETA || fin == FIN_UPDATE || fin == FIN_RHO0) && sc->done) return;
+    const int b0 = mp.blk_sys ? mp.sys_b0[k] : 0;
+    const int nparts = mp.blk_sys ? mp.sys_nb[k] : nblocks;
     __shared__ double sh[kThreads / 64];
     const int slots = (fin == FIN_INIT) ? 2 : 1;
     double tot[2] = {0.0, 0.0};
     const int per = (nparts + kThreads - 1) / kThreads;
     const int lo = threadIdx.x * per, hi = min(nparts, lo + per);
-    for (int k = 0; k < slots; ++k) {
+    for (int sl = 0; sl < slots; ++sl) {
         double v = 0.0;
-        for (int j = lo; j < hi; ++j) v += partials[(size_t)k * nparts + j];
-        tot[k] = block_sum(v, sh);
+        for (int j = lo; j < hi; ++j) v += partials[(size_t)sl * nblocks + b0 + j];
+        tot[sl] = block_sum(v, sh);
     }
     if (threadIdx.x != 0) return;
     const double v = tot[0];
@@ -124,7 +187,7 @@ __global__ __launch_bounds__(kThreads) void k_finalize(const double *__restrict_
 }
 
 // ---------------------------------------------------------------------------------------
-// CSR SpMV, one group of GS lanes per row; optional fused dot y.w with a PCG finalisation
+// CSR SpMV, one group of GS lanes per row; optional fused dot y.w (one system)
 // ---------------------------------------------------------------------------------------
 template <int GS, int U, typename VT, bool DOT>
 __global__ __launch_bounds__(kThreads) void k_spmv(int n, const int32_t *__restrict__ rp,
@@ -134,12 +197,12 @@ __global__ __launch_bounds__(kThreads) void k_spmv(int n, const int32_t *__restr
                                                     double *__restrict__ y,
                                                     const double *__restrict__ w,
                                                     double *__restrict__ partials,
-                                                    PcgScalars *sc, int fin, int nxcd) {
+                                                    PcgScalars *sc, int nxcd) {
     if (sc && sc->done) return;
     __shared__ double sh[kThreads / 64];
     const int lb = xcd_block(blockIdx.x, gridDim.x, nxcd);
-    const int64_t per = ((int64_t)n + gridDim.x - 1) / gridDim.x;
-    const int r0 = (int)min<int64_t>(n, per * lb), r1 = (int)min<int64_t>(n, per * (lb + 1));
+    int r0, r1;
+    block_range(0, n, lb, gridDim.x, r0, r1);
     const int lg = threadIdx.x % GS, grp = threadIdx.x / GS;
     constexpr int RPI = kThreads / GS;  // rows per block iteration
     double part = 0.0;
@@ -177,10 +240,23 @@ __global__ __launch_bounds__(kThreads) void k_spmv(int n, const int32_t *__restr
     }
 }
 
+// rows [r0, r1) of SELL slice sl
+__device__ __forceinline__ void sell_slice_rows(const int32_t *srow0, int n, int sl, int &r0, int &r1) {
+    if (srow0) {
+        r0 = srow0[sl];
+        r1 = srow0[sl + 1];
+    } else {
+        r0 = sl * kSlice;
+        r1 = min(n, r0 + kSlice);
+    }
+}
+
 // SELL-64 product: one wavefront per slice of 64 rows, one lane per row; entry k of the 64
-// rows is one contiguous wave load.  Optional fused dot y.w with a PCG finalisation.
+// rows is one contiguous wave load.  Optional fused dot y.w.  For the tail of a split layout
+// (perm/rowmap set) the launch is not tied to systems (mp, sy empty, scs may be null).
 template <int U, typename VT, bool DOT>
 __global__ __launch_bounds__(kThreads) void k_sell_spmv(int n, int nslices, const uint32_t *__restrict__ sptr,
+                                                         const int32_t *__restrict__ srow0,
                                                          const int32_t *__restrict__ perm,
                                                          const int32_t *__restrict__ rowmap,
                                                          const uint64_t *__restrict__ init,
@@ -188,19 +264,23 @@ __global__ __launch_bounds__(kThreads) void k_sell_spmv(int n, int nslices, cons
                                                          const VT *__restrict__ val,
                                                          const double *__restrict__ x, double *__restrict__ y,
                                                          const double *__restrict__ w,
-                                                         double *__restrict__ partials, PcgScalars *sc, int fin,
-                                                         int nxcd) {
-    if (sc && sc->done) return;
+                                                         double *__restrict__ partials, PcgScalars *scs, Map mp,
+                                                         Systems sy, int nxcd) {
+    const Job jb = block_job(mp, nxcd);
+    if (scs && scs[jb.k].done) return;
     __shared__ double sh[kThreads / 64];
-    const int lb = xcd_block(blockIdx.x, gridDim.x, nxcd);
-    const int64_t per = ((int64_t)nslices + gridDim.x - 1) / gridDim.x;
-    const int s0 = (int)min<int64_t>(nslices, per * lb), s1 = (int)min<int64_t>(nslices, per * (lb + 1));
+    const int sb = sy.slice0 ? sy.slice0[jb.k] : 0;
+    const int sn = sy.slice0 ? sy.slice0[jb.k + 1] - sb : nslices;
+    int s0, s1;
+    block_range(sb, sn, jb.lb, jb.nb, s0, s1);
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
     double part = 0.0;
     for (int sl = s0 + wv; sl < s1; sl += kThreads / 64) {
-        int r = sl * kSlice + lane;
-        if (perm) r = perm[r];
-        const bool valid = r >= 0 && r < n;
+        int r0, r1;
+        sell_slice_rows(srow0, n, sl, r0, r1);
+        int r = r0 + lane;
+        if (perm) r = perm[sl * kSlice + lane];
+        const bool valid = r >= 0 && r < (perm ? n : r1);
         const int ro = (valid && rowmap) ? rowmap[r] : r;
         const uint32_t c0 = sptr[sl];
         const int width = (int)(sptr[sl + 1] - c0);
@@ -231,14 +311,14 @@ __global__ __launch_bounds__(kThreads) void k_sell_spmv(int n, int nslices, cons
     }
     if (DOT) {
         const double bs = block_sum(part, sh);
-        store_partials(partials, 1, &bs, lb);
+        store_partials(partials, 1, &bs, jb.gb);
     }
 }
 
-// Fused PCG products (SELL-64, one lane per row).  The vector being multiplied is formed on
-// the fly from two others with the same fma the separate update kernel would use, so the
-// result is identical to update-then-multiply; the owner lane of each row also stores the
-// updated entry.
+// Fused PCG products (SELL-64, one lane per row, layouts without a tail).  The vector being
+// multiplied is formed on the fly from two others with the same fma the separate update
+// kernel would use, so the result is identical to update-then-multiply; the owner lane of
+// each row also stores the updated entry.
 //   FUSE_AP:  p_new = z + beta p_old (p_new = z on the first iteration); q = A p_new;
 //             partial sums of p_new.q
 //   FUSE_GR:  r_new = r_old - alpha q; x += alpha p_new; t = G r_new; partial sums of r_new.r_new
@@ -246,7 +326,7 @@ enum : int { FUSE_AP = 1, FUSE_GR = 2 };
 
 template <int U, typename VT, int MODE>
 __global__ __launch_bounds__(kThreads) void k_sell_fused(int n, int nslices, const uint32_t *__restrict__ sptr,
-                                                          const int32_t *__restrict__ perm,
+                                                          const int32_t *__restrict__ srow0,
                                                           const int32_t *__restrict__ col,
                                                           const VT *__restrict__ val,
                                                           const double *__restrict__ va,   // z | r_old
@@ -256,19 +336,24 @@ __global__ __launch_bounds__(kThreads) void k_sell_fused(int n, int nslices, con
                                                           const double *__restrict__ pn,   // - | p_new
                                                           double *__restrict__ y,          // q | t
                                                           double *__restrict__ partials,
-                                                          const PcgScalars *sc, int first, int nxcd) {
+                                                          const PcgScalars *scs, int first, Map mp, Systems sy,
+                                                          int nxcd) {
+    const Job jb = block_job(mp, nxcd);
+    const PcgScalars *sc = scs + jb.k;
     if (sc->done) return;
     __shared__ double sh[kThreads / 64];
     const double alpha = sc->alpha;
     const double coef = (MODE == FUSE_AP) ? sc->beta : -alpha;
-    const int lb = xcd_block(blockIdx.x, gridDim.x, nxcd);
-    const int64_t per = ((int64_t)nslices + gridDim.x - 1) / gridDim.x;
-    const int s0 = (int)min<int64_t>(nslices, per * lb), s1 = (int)min<int64_t>(nslices, per * (lb + 1));
+    const int sb = sy.slice0 ? sy.slice0[jb.k] : 0;
+    const int sn = sy.slice0 ? sy.slice0[jb.k + 1] - sb : nslices;
+    int s0, s1;
+    block_range(sb, sn, jb.lb, jb.nb, s0, s1);
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
     double part = 0.0;
     for (int sl = s0 + wv; sl < s1; sl += kThreads / 64) {
-        int r = sl * kSlice + lane;
-        if (perm) r = perm[r];
+        int r0, r1;
+        sell_slice_rows(srow0, n, sl, r0, r1);
+        const int r = r0 + lane;
         const uint32_t c0 = sptr[sl];
         const int width = (int)(sptr[sl + 1] - c0);
         const int64_t base = (int64_t)c0 * kSlice + lane;
@@ -293,7 +378,7 @@ __global__ __launch_bounds__(kThreads) void k_sell_fused(int n, int nslices, con
                     acc = fma((double)v[u], xv, acc);
                 }
         }
-        if (r >= 0 && r < n) {
+        if (r < r1) {
             const double own = (MODE == FUSE_AP && first) ? va[r] : fma(coef, vb[r], va[r]);
             own_out[r] = own;
             y[r] = acc;
@@ -306,17 +391,20 @@ __global__ __launch_bounds__(kThreads) void k_sell_fused(int n, int nslices, con
         }
     }
     const double bs = block_sum(part, sh);
-    store_partials(partials, 1, &bs, lb);
+    store_partials(partials, 1, &bs, jb.gb);
 }
 
 // r = b - q ; partials of b.b and r.r ; finalisation checks ||b|| = 0 and ||r0|| <= tol
 __global__ __launch_bounds__(kThreads) void k_init_residual(int n, const double *__restrict__ b,
                                                              const double *__restrict__ q,
                                                              double *__restrict__ r,
-                                                             double *__restrict__ partials) {
+                                                             double *__restrict__ partials, Map mp, Systems sy,
+                                                             int nxcd) {
     __shared__ double sh[kThreads / 64];
-    const int64_t per = ((int64_t)n + gridDim.x - 1) / gridDim.x;
-    const int i0 = (int)min<int64_t>(n, per * blockIdx.x), i1 = (int)min<int64_t>(n, per * (blockIdx.x + 1));
+    const Job jb = block_job(mp, nxcd);
+    int a0, a1, i0, i1;
+    sys_rows(sy, n, jb.k, a0, a1);
+    block_range(a0, a1 - a0, jb.lb, jb.nb, i0, i1);
     double pb = 0.0, pr = 0.0;
     for (int i = i0 + threadIdx.x; i < i1; i += kThreads) {
         const double bi = b[i], ri = bi - q[i];
@@ -327,7 +415,7 @@ __global__ __launch_bounds__(kThreads) void k_init_residual(int n, const double 
     double mine[2];
     mine[0] = block_sum(pb, sh);
     mine[1] = block_sum(pr, sh);
-    store_partials(partials, 2, mine, blockIdx.x);
+    store_partials(partials, 2, mine, jb.gb);
 }
 
 // x += alpha p ; r -= alpha q ; ||r||^2 ; convergence test; (plain CG) beta = rr'/rr
@@ -336,13 +424,15 @@ __global__ __launch_bounds__(kThreads) void k_update_xr(int n, double *__restric
                                                          const double *__restrict__ p,
                                                          const double *__restrict__ q,
                                                          double *__restrict__ partials,
-                                                         PcgScalars *sc, int nxcd) {
+                                                         PcgScalars *scs, Map mp, Systems sy, int nxcd) {
+    const Job jb = block_job(mp, nxcd);
+    const PcgScalars *sc = scs + jb.k;
     if (sc->done) return;
     __shared__ double sh[kThreads / 64];
     const double alpha = sc->alpha;
-    const int lb = xcd_block(blockIdx.x, gridDim.x, nxcd);
-    const int64_t per = ((int64_t)n + gridDim.x - 1) / gridDim.x;
-    const int i0 = (int)min<int64_t>(n, per * lb), i1 = (int)min<int64_t>(n, per * (lb + 1));
+    int a0, a1, i0, i1;
+    sys_rows(sy, n, jb.k, a0, a1);
+    block_range(a0, a1 - a0, jb.lb, jb.nb, i0, i1);
     double pr = 0.0;
     for (int i = i0 + threadIdx.x; i < i1; i += kThreads) {
         x[i] = fma(alpha, p[i], x[i]);
@@ -351,52 +441,65 @@ __global__ __launch_bounds__(kThreads) void k_update_xr(int n, double *__restric
         pr = fma(ri, ri, pr);
     }
     const double bs = block_sum(pr, sh);
-    store_partials(partials, 1, &bs, lb);
+    store_partials(partials, 1, &bs, jb.gb);
 }
 
 // p = z + beta p   (first = 1: p = z)
 __global__ __launch_bounds__(kThreads) void k_update_p(int n, double *__restrict__ p,
                                                         const double *__restrict__ z,
-                                                        const PcgScalars *sc, int first, int nxcd) {
+                                                        const PcgScalars *scs, int first, Map mp, Systems sy,
+                                                        int nxcd) {
+    const Job jb = block_job(mp, nxcd);
+    const PcgScalars *sc = scs + jb.k;
     if (sc->done) return;
     const double beta = first ? 0.0 : sc->beta;
-    const int lb = xcd_block(blockIdx.x, gridDim.x, nxcd);
-    const int64_t per = ((int64_t)n + gridDim.x - 1) / gridDim.x;
-    const int i0 = (int)min<int64_t>(n, per * lb), i1 = (int)min<int64_t>(n, per * (lb + 1));
+    int a0, a1, i0, i1;
+    sys_rows(sy, n, jb.k, a0, a1);
+    block_range(a0, a1 - a0, jb.lb, jb.nb, i0, i1);
     if (first)
         for (int i = i0 + threadIdx.x; i < i1; i += kThreads) p[i] = z[i];
     else
         for (int i = i0 + threadIdx.x; i < i1; i += kThreads) p[i] = fma(beta, p[i], z[i]);
 }
 
-__global__ void k_zero(int n, double *__restrict__ v) {
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) v[i] = 0.0;
+// x = 0 for the systems whose right-hand side is zero
+__global__ __launch_bounds__(kThreads) void k_zero_rhs(int n, double *__restrict__ x, const PcgScalars *scs, Map mp,
+                                                       Systems sy, int nxcd) {
+    const Job jb = block_job(mp, nxcd);
+    if (scs[jb.k].done != DONE_ZERO_RHS) return;
+    int a0, a1, i0, i1;
+    sys_rows(sy, n, jb.k, a0, a1);
+    block_range(a0, a1 - a0, jb.lb, jb.nb, i0, i1);
+    for (int i = i0 + threadIdx.x; i < i1; i += kThreads) x[i] = 0.0;
 }
 
-__global__ void k_set_scalars(PcgScalars *sc, double rtol, int maxit, int plain) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
+__global__ void k_set_scalars(PcgScalars *scs, int nsys, double rtol, int maxit, int plain) {
+    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < nsys; k += gridDim.x * blockDim.x) {
         PcgScalars s{};
         s.rtol = rtol;
         s.maxit = maxit;
         s.plain = plain;
-        *sc = s;
+        scs[k] = s;
     }
 }
 
 // true residual partials: ||b - Ax||^2 with q = A x
 __global__ __launch_bounds__(kThreads) void k_resid_norm(int n, const double *__restrict__ b,
                                                           const double *__restrict__ q,
-                                                          double *__restrict__ partials) {
+                                                          double *__restrict__ partials, Map mp, Systems sy,
+                                                          int nxcd) {
     __shared__ double sh[kThreads / 64];
-    const int64_t per = ((int64_t)n + gridDim.x - 1) / gridDim.x;
-    const int i0 = (int)min<int64_t>(n, per * blockIdx.x), i1 = (int)min<int64_t>(n, per * (blockIdx.x + 1));
+    const Job jb = block_job(mp, nxcd);
+    int a0, a1, i0, i1;
+    sys_rows(sy, n, jb.k, a0, a1);
+    block_range(a0, a1 - a0, jb.lb, jb.nb, i0, i1);
     double pr = 0.0;
     for (int i = i0 + threadIdx.x; i < i1; i += kThreads) {
         const double d = b[i] - q[i];
         pr = fma(d, d, pr);
     }
     const double bs = block_sum(pr, sh);
-    store_partials(partials, 1, &bs, blockIdx.x);
+    store_partials(partials, 1, &bs, jb.gb);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -431,6 +534,14 @@ static int blocks_for_vec(int n, const DeviceInfo &di) {
     return (int)(b < 1 ? 1 : b);
 }
 
+static int blocks_for_slices(int nslices, const DeviceInfo &di) {
+    int64_t nb = ((int64_t)nslices + kThreads / 64 - 1) / (kThreads / 64);
+    const int64_t cap = (int64_t)di.num_cus * 16;
+    if (nb > cap) nb = cap;
+    if (nb < 1) nb = 1;
+    return (int)nb;
+}
+
 struct Csr {
     int n = 0;
     int64_t nnz = 0;
@@ -441,39 +552,39 @@ struct Csr {
 
 template <int GS, int U, typename VT>
 static void launch_spmv_t(const Csr &A, const double *x, double *y, const double *w, double *partials,
-                          PcgScalars *sc, int fin, int nb, int nxcd, hipStream_t s) {
+                          PcgScalars *sc, int nb, int nxcd, hipStream_t s) {
     if (w)
         hipLaunchKernelGGL((k_spmv<GS, U, VT, true>), dim3(nb), dim3(kThreads), 0, s, A.n, A.rp, A.ci,
-                           (const VT *)A.val, x, y, w, partials, sc, fin, nxcd);
+                           (const VT *)A.val, x, y, w, partials, sc, nxcd);
     else
         hipLaunchKernelGGL((k_spmv<GS, U, VT, false>), dim3(nb), dim3(kThreads), 0, s, A.n, A.rp, A.ci,
-                           (const VT *)A.val, x, y, w, partials, sc, fin, nxcd);
+                           (const VT *)A.val, x, y, w, partials, sc, nxcd);
 }
 
 template <int GS, typename VT>
 static void launch_spmv_u(const Csr &A, int un, const double *x, double *y, const double *w, double *partials,
-                          PcgScalars *sc, int fin, int nb, int nxcd, hipStream_t s) {
+                          PcgScalars *sc, int nb, int nxcd, hipStream_t s) {
     switch (un) {
-        case 1: launch_spmv_t<GS, 1, VT>(A, x, y, w, partials, sc, fin, nb, nxcd, s); break;
-        case 2: launch_spmv_t<GS, 2, VT>(A, x, y, w, partials, sc, fin, nb, nxcd, s); break;
-        case 4: launch_spmv_t<GS, 4, VT>(A, x, y, w, partials, sc, fin, nb, nxcd, s); break;
-        default: launch_spmv_t<GS, 8, VT>(A, x, y, w, partials, sc, fin, nb, nxcd, s); break;
+        case 1: launch_spmv_t<GS, 1, VT>(A, x, y, w, partials, sc, nb, nxcd, s); break;
+        case 2: launch_spmv_t<GS, 2, VT>(A, x, y, w, partials, sc, nb, nxcd, s); break;
+        case 4: launch_spmv_t<GS, 4, VT>(A, x, y, w, partials, sc, nb, nxcd, s); break;
+        default: launch_spmv_t<GS, 8, VT>(A, x, y, w, partials, sc, nb, nxcd, s); break;
     }
 }
 
 template <typename VT>
 static void launch_spmv_v(const Csr &A, int gs, int un, const double *x, double *y, const double *w,
-                          double *partials, PcgScalars *sc, int fin, int nb, int nxcd, hipStream_t s) {
+                          double *partials, PcgScalars *sc, int nb, int nxcd, hipStream_t s) {
     switch (gs) {
-        case 4: launch_spmv_u<4, VT>(A, un, x, y, w, partials, sc, fin, nb, nxcd, s); break;
-        case 8: launch_spmv_u<8, VT>(A, un, x, y, w, partials, sc, fin, nb, nxcd, s); break;
-        case 16: launch_spmv_u<16, VT>(A, un, x, y, w, partials, sc, fin, nb, nxcd, s); break;
-        case 32: launch_spmv_u<32, VT>(A, un, x, y, w, partials, sc, fin, nb, nxcd, s); break;
-        default: launch_spmv_u<64, VT>(A, un, x, y, w, partials, sc, fin, nb, nxcd, s); break;
+        case 4: launch_spmv_u<4, VT>(A, un, x, y, w, partials, sc, nb, nxcd, s); break;
+        case 8: launch_spmv_u<8, VT>(A, un, x, y, w, partials, sc, nb, nxcd, s); break;
+        case 16: launch_spmv_u<16, VT>(A, un, x, y, w, partials, sc, nb, nxcd, s); break;
+        case 32: launch_spmv_u<32, VT>(A, un, x, y, w, partials, sc, nb, nxcd, s); break;
+        default: launch_spmv_u<64, VT>(A, un, x, y, w, partials, sc, nb, nxcd, s); break;
     }
 }
 
-// y = A x (optionally fused dot y.w finalised into sc)
+// y = A x, CSR (one system; optionally fused dot y.w finalised into sc)
 static void spmv(const char *name, const Csr &A, const double *x, double *y, const double *w,
                  double *partials, PcgScalars *sc, int fin, const DeviceInfo &di, hipStream_t s) {
     const double avg = A.n ? (double)A.nnz / A.n : 0.0;
@@ -483,106 +594,178 @@ static void spmv(const char *name, const Csr &A, const double *x, double *y, con
     {
         ProfScope ps(name, s);
         if (A.f32)
-            launch_spmv_v<float>(A, gs, un, x, y, w, partials, sc, fin, nb, di.num_xcds, s);
+            launch_spmv_v<float>(A, gs, un, x, y, w, partials, sc, nb, di.num_xcds, s);
         else
-            launch_spmv_v<double>(A, gs, un, x, y, w, partials, sc, fin, nb, di.num_xcds, s);
+            launch_spmv_v<double>(A, gs, un, x, y, w, partials, sc, nb, di.num_xcds, s);
     }
-    if (w) hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kThreads), 0, s, partials, nb, fin, sc);
+    if (w) hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kThreads), 0, s, partials, nb, Map(), fin, sc);
+}
+
+// Block maps of a batch for the three launch shapes (SELL products, vector kernels), held on
+// the device for one solve; empty for a single system.
+struct Shape {
+    Map mp;
+    int nblocks = 0;
+};
+struct BatchMaps {
+    int nsys = 1;
+    Systems sy;
+    Shape sell, vec;
+    DevBuf buf;
+};
+
+static int make_batch_maps(int n, int nsys, const int32_t *row0, const DeviceInfo &di, hipStream_t s,
+                           BatchMaps *bm) {
+    bm->nsys = nsys;
+    std::vector<int32_t> slice0(nsys + 1);
+    Segments seg;
+    seg.nsys = nsys;
+    seg.row0 = row0;
+    segment_slices(seg, n, slice0.data());
+    if (nsys == 1) {
+        bm->sell.nblocks = blocks_for_slices(slice0[1], di);
+        bm->vec.nblocks = blocks_for_vec(n, di);
+        return AFSAI_OK;
+    }
+    std::vector<int32_t> nb_sell(nsys), nb_vec(nsys);
+    int64_t tot_sell = 0, tot_vec = 0;
+    for (int k = 0; k < nsys; ++k) {
+        nb_sell[k] = blocks_for_slices(slice0[k + 1] - slice0[k], di);
+        nb_vec[k] = blocks_for_vec(row0[k + 1] - row0[k], di);
+        tot_sell += nb_sell[k];
+        tot_vec += nb_vec[k];
+    }
+    if (tot_sell >= (1 << 30) || tot_vec >= (1 << 30)) AFSAI_FAIL(AFSAI_ERR_TOO_LARGE, "batch: too many blocks");
+    // layout: row0 | slice0 | sell: blk_sys, b0, nb | vec: blk_sys, b0, nb
+    std::vector<int32_t> h;
+    h.reserve((size_t)2 * (nsys + 1) + tot_sell + tot_vec + 4 * (size_t)nsys);
+    h.insert(h.end(), row0, row0 + nsys + 1);
+    h.insert(h.end(), slice0.begin(), slice0.end());
+    size_t off_sell = h.size();
+    for (int k = 0; k < nsys; ++k) h.insert(h.end(), nb_sell[k], k);
+    size_t off_sell_b0 = h.size();
+    int32_t acc = 0;
+    for (int k = 0; k < nsys; ++k) {
+        h.push_back(acc);
+        acc += nb_sell[k];
+    }
+    size_t off_sell_nb = h.size();
+    h.insert(h.end(), nb_sell.begin(), nb_sell.end());
+    size_t off_vec = h.size();
+    for (int k = 0; k < nsys; ++k) h.insert(h.end(), nb_vec[k], k);
+    size_t off_vec_b0 = h.size();
+    acc = 0;
+    for (int k = 0; k < nsys; ++k) {
+        h.push_back(acc);
+        acc += nb_vec[k];
+    }
+    size_t off_vec_nb = h.size();
+    h.insert(h.end(), nb_vec.begin(), nb_vec.end());
+    int rc;
+    if ((rc = dalloc(bm->buf, sizeof(int32_t) * h.size(), s))) return rc;
+    AFSAI_HIP_TRY(hipMemcpyAsync(bm->buf.p, h.data(), sizeof(int32_t) * h.size(), hipMemcpyHostToDevice, s));
+    AFSAI_HIP_TRY(hipStreamSynchronize(s));
+    const int32_t *d = bm->buf.as<int32_t>();
+    bm->sy.row0 = d;
+    bm->sy.slice0 = d + nsys + 1;
+    bm->sell.mp = Map{d + off_sell, d + off_sell_b0, d + off_sell_nb};
+    bm->sell.nblocks = (int)tot_sell;
+    bm->vec.mp = Map{d + off_vec, d + off_vec_b0, d + off_vec_nb};
+    bm->vec.nblocks = (int)tot_vec;
+    return AFSAI_OK;
 }
 
 template <int U, typename VT>
 static void launch_sell_t(const Sell &S, const double *x, double *y, const double *w, double *partials,
-                          PcgScalars *sc, int fin, int nb, int nxcd, hipStream_t s) {
+                          PcgScalars *scs, const Map &mp, const Systems &sy, int nb, int nxcd, hipStream_t s) {
     if (w)
         hipLaunchKernelGGL((k_sell_spmv<U, VT, true>), dim3(nb), dim3(kThreads), 0, s, S.n, S.nslices, S.sptr,
-                           S.perm, S.rowmap, S.init, S.col, (const VT *)S.val, x, y, w, partials, sc, fin, nxcd);
+                           S.srow0, S.perm, S.rowmap, S.init, S.col, (const VT *)S.val, x, y, w, partials, scs, mp,
+                           sy, nxcd);
     else
         hipLaunchKernelGGL((k_sell_spmv<U, VT, false>), dim3(nb), dim3(kThreads), 0, s, S.n, S.nslices, S.sptr,
-                           S.perm, S.rowmap, S.init, S.col, (const VT *)S.val, x, y, w, partials, sc, fin, nxcd);
+                           S.srow0, S.perm, S.rowmap, S.init, S.col, (const VT *)S.val, x, y, w, partials, scs, mp,
+                           sy, nxcd);
 }
 
 template <typename VT>
 static void launch_sell_v(const Sell &S, int un, const double *x, double *y, const double *w, double *partials,
-                          PcgScalars *sc, int fin, int nb, int nxcd, hipStream_t s) {
+                          PcgScalars *scs, const Map &mp, const Systems &sy, int nb, int nxcd, hipStream_t s) {
     switch (un) {
-        case 1: launch_sell_t<1, VT>(S, x, y, w, partials, sc, fin, nb, nxcd, s); break;
-        case 2: launch_sell_t<2, VT>(S, x, y, w, partials, sc, fin, nb, nxcd, s); break;
-        case 4: launch_sell_t<4, VT>(S, x, y, w, partials, sc, fin, nb, nxcd, s); break;
-        default: launch_sell_t<8, VT>(S, x, y, w, partials, sc, fin, nb, nxcd, s); break;
+        case 1: launch_sell_t<1, VT>(S, x, y, w, partials, scs, mp, sy, nb, nxcd, s); break;
+        case 2: launch_sell_t<2, VT>(S, x, y, w, partials, scs, mp, sy, nb, nxcd, s); break;
+        case 4: launch_sell_t<4, VT>(S, x, y, w, partials, scs, mp, sy, nb, nxcd, s); break;
+        default: launch_sell_t<8, VT>(S, x, y, w, partials, scs, mp, sy, nb, nxcd, s); break;
     }
 }
 
-static int sell_blocks(const Sell &S, const DeviceInfo &di) {
-    int64_t nb = ((int64_t)S.nslices + kThreads / 64 - 1) / (kThreads / 64);
-    const int64_t cap = (int64_t)di.num_cus * 16;
-    if (nb > cap) nb = cap;
-    if (nb < 1) nb = 1;
-    return (int)nb;
-}
+static int sell_unroll() { return option(AFSAI_OPT_SPMV_UNROLL) > 0 ? (int)option(AFSAI_OPT_SPMV_UNROLL) : 8; }
 
-// y = S x for a SELL-64 matrix (optionally fused dot y.w finalised into sc); a split layout's
-// tail is multiplied first
-static void sell_spmv(const char *name, const Sell &S, const double *x, double *y, const double *w,
-                      double *partials, PcgScalars *sc, int fin, const DeviceInfo &di, hipStream_t s) {
-    int un = option(AFSAI_OPT_SPMV_UNROLL) > 0 ? (int)option(AFSAI_OPT_SPMV_UNROLL) : 8;
+// y = S x for a SELL-64 matrix laid out for the batch (optionally fused dot y.w finalised into
+// the systems' scalars); a split layout's tail is multiplied first
+static void sell_spmv(const char *name, const Sell &S, const BatchMaps &bm, const double *x, double *y,
+                      const double *w, double *partials, PcgScalars *scs, int fin, const DeviceInfo &di,
+                      hipStream_t s) {
+    const int un = sell_unroll();
     if (S.tail) {
         const Sell &T = *S.tail;
-        const int nbt = sell_blocks(T, di);
+        const int nbt = blocks_for_slices(T.nslices, di);
+        // the tail's rows belong to any system: with one system it stops with it
+        PcgScalars *tsc = (bm.nsys == 1) ? scs : nullptr;
         ProfScope ps("sell_tail", s);
         if (T.f32)
-            launch_sell_v<float>(T, un, x, y, nullptr, nullptr, sc, FIN_NONE, nbt, di.num_xcds, s);
+            launch_sell_v<float>(T, un, x, y, nullptr, nullptr, tsc, Map(), Systems(), nbt, di.num_xcds, s);
         else
-            launch_sell_v<double>(T, un, x, y, nullptr, nullptr, sc, FIN_NONE, nbt, di.num_xcds, s);
+            launch_sell_v<double>(T, un, x, y, nullptr, nullptr, tsc, Map(), Systems(), nbt, di.num_xcds, s);
     }
-    const int64_t nb = sell_blocks(S, di);
+    const int nb = bm.sell.nblocks;
     {
         ProfScope ps(name, s);
         if (S.f32)
-            launch_sell_v<float>(S, un, x, y, w, partials, sc, fin, (int)nb, di.num_xcds, s);
+            launch_sell_v<float>(S, un, x, y, w, partials, scs, bm.sell.mp, bm.sy, nb, di.num_xcds, s);
         else
-            launch_sell_v<double>(S, un, x, y, w, partials, sc, fin, (int)nb, di.num_xcds, s);
+            launch_sell_v<double>(S, un, x, y, w, partials, scs, bm.sell.mp, bm.sy, nb, di.num_xcds, s);
     }
-    if (w) hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kThreads), 0, s, partials, (int)nb, fin, sc);
+    if (w)
+        hipLaunchKernelGGL(k_finalize, dim3(bm.nsys), dim3(kThreads), 0, s, partials, nb, bm.sell.mp, fin, scs);
 }
 
 template <int U, typename VT, int MODE>
 static void launch_fused_t(const Sell &S, const double *va, const double *vb, double *own, double *x,
-                           const double *pn, double *y, double *partials, PcgScalars *sc, int first, int nb, int nxcd,
-                           hipStream_t s) {
-    hipLaunchKernelGGL((k_sell_fused<U, VT, MODE>), dim3(nb), dim3(kThreads), 0, s, S.n, S.nslices, S.sptr, S.perm,
-                       S.col, (const VT *)S.val, va, vb, own, x, pn, y, partials, sc, first, nxcd);
+                           const double *pn, double *y, double *partials, PcgScalars *scs, int first,
+                           const BatchMaps &bm, int nxcd, hipStream_t s) {
+    hipLaunchKernelGGL((k_sell_fused<U, VT, MODE>), dim3(bm.sell.nblocks), dim3(kThreads), 0, s, S.n, S.nslices,
+                       S.sptr, S.srow0, S.col, (const VT *)S.val, va, vb, own, x, pn, y, partials, scs, first,
+                       bm.sell.mp, bm.sy, nxcd);
 }
 
 template <typename VT, int MODE>
 static void launch_fused_v(const Sell &S, int un, const double *va, const double *vb, double *own, double *x,
-                           const double *pn, double *y, double *partials, PcgScalars *sc, int first, int nb, int nxcd,
-                           hipStream_t s) {
+                           const double *pn, double *y, double *partials, PcgScalars *scs, int first,
+                           const BatchMaps &bm, int nxcd, hipStream_t s) {
     switch (un) {
-        case 1: launch_fused_t<1, VT, MODE>(S, va, vb, own, x, pn, y, partials, sc, first, nb, nxcd, s); break;
-        case 2: launch_fused_t<2, VT, MODE>(S, va, vb, own, x, pn, y, partials, sc, first, nb, nxcd, s); break;
-        case 4: launch_fused_t<4, VT, MODE>(S, va, vb, own, x, pn, y, partials, sc, first, nb, nxcd, s); break;
-        default: launch_fused_t<8, VT, MODE>(S, va, vb, own, x, pn, y, partials, sc, first, nb, nxcd, s); break;
+        case 1: launch_fused_t<1, VT, MODE>(S, va, vb, own, x, pn, y, partials, scs, first, bm, nxcd, s); break;
+        case 2: launch_fused_t<2, VT, MODE>(S, va, vb, own, x, pn, y, partials, scs, first, bm, nxcd, s); break;
+        case 4: launch_fused_t<4, VT, MODE>(S, va, vb, own, x, pn, y, partials, scs, first, bm, nxcd, s); break;
+        default: launch_fused_t<8, VT, MODE>(S, va, vb, own, x, pn, y, partials, scs, first, bm, nxcd, s); break;
     }
 }
 
 // fused product followed by the finalisation of its dot
 template <int MODE>
-static void sell_fused(const char *name, const Sell &S, const double *va, const double *vb, double *own, double *x,
-                       const double *pn, double *y, double *partials, PcgScalars *sc, int first, int fin,
-                       const DeviceInfo &di, hipStream_t s) {
-    const int un = option(AFSAI_OPT_SPMV_UNROLL) > 0 ? (int)option(AFSAI_OPT_SPMV_UNROLL) : 8;
-    int64_t nb = ((int64_t)S.nslices + kThreads / 64 - 1) / (kThreads / 64);
-    const int64_t cap = (int64_t)di.num_cus * 16;
-    if (nb > cap) nb = cap;
-    if (nb < 1) nb = 1;
+static void sell_fused(const char *name, const Sell &S, const BatchMaps &bm, const double *va, const double *vb,
+                       double *own, double *x, const double *pn, double *y, double *partials, PcgScalars *scs,
+                       int first, int fin, const DeviceInfo &di, hipStream_t s) {
+    const int un = sell_unroll();
     {
         ProfScope ps(name, s);
         if (S.f32)
-            launch_fused_v<float, MODE>(S, un, va, vb, own, x, pn, y, partials, sc, first, (int)nb, di.num_xcds, s);
+            launch_fused_v<float, MODE>(S, un, va, vb, own, x, pn, y, partials, scs, first, bm, di.num_xcds, s);
         else
-            launch_fused_v<double, MODE>(S, un, va, vb, own, x, pn, y, partials, sc, first, (int)nb, di.num_xcds, s);
+            launch_fused_v<double, MODE>(S, un, va, vb, own, x, pn, y, partials, scs, first, bm, di.num_xcds, s);
     }
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kThreads), 0, s, partials, (int)nb, fin, sc);
+    hipLaunchKernelGGL(k_finalize, dim3(bm.nsys), dim3(kThreads), 0, s, partials, bm.sell.nblocks, bm.sell.mp, fin,
+                       scs);
 }
 
 static int check_csr_arg(const afsai_csr *A, const char *who) {
@@ -602,11 +785,274 @@ static Csr csr_of(const afsai_csr *A) {
     return c;
 }
 
-// partial-sum scratch: 2 slots x max blocks
-static size_t partial_elems(const DeviceInfo &di) { return (size_t)2 * di.num_cus * 16 + 64; }
-
 // work vectors of the solver: r, r', z, p, p', q, t
 constexpr int kWorkVectors = 7;
+
+// pinned host copies of the systems' scalars (two sets), per thread for the life of the process
+static int host_scalars(int nsys, PcgScalars **out) {
+    static thread_local PcgScalars *hsc = nullptr;
+    static thread_local int cap = 0;
+    if (cap < nsys) {
+        if (hsc) (void)hipHostFree(hsc);
+        hsc = nullptr;
+        cap = 0;
+        int want = nsys < 4 ? 4 : nsys;
+        AFSAI_HIP_TRY(hipHostMalloc(&hsc, 2 * sizeof(PcgScalars) * (size_t)want, hipHostMallocDefault));
+        cap = want;
+    }
+    *out = hsc;
+    return AFSAI_OK;
+}
+
+// The preconditioned CG of Sec. 5.2 over a batch of nsys independent systems (row0: host,
+// nsys + 1 entries, nullptr for one system); info: nsys entries (may be null).
+static int pcg_batch(const afsai_csr *A, afsai_precond P, int nsys, const int32_t *row0_in, const double *b,
+                     double *x, double rtol, int32_t maxit, hipStream_t s, afsai_pcg_info *info) {
+    const int n = A->n;
+    DeviceInfo di;
+    int rc;
+    if ((rc = device_info(&di))) return rc;
+    hipEvent_t t0, t1;
+    AFSAI_HIP_TRY(hipEventCreate(&t0));
+    AFSAI_HIP_TRY(hipEventCreate(&t1));
+    AFSAI_HIP_TRY(hipEventRecord(t0, s));
+
+    std::vector<int32_t> row0_one = {0, n};
+    const int32_t *row0 = (nsys > 1) ? row0_in : row0_one.data();
+    BatchMaps bm;
+    if ((rc = make_batch_maps(n, nsys, row0, di, s, &bm))) return rc;
+    Segments seg;
+    seg.nsys = nsys;
+    seg.row0 = row0;
+
+    const size_t np = (size_t)2 * std::max(bm.sell.nblocks, std::max(bm.vec.nblocks, di.num_cus * 16)) + 64;
+    const size_t nsc_elems = (sizeof(PcgScalars) * (size_t)nsys + sizeof(double) - 1) / sizeof(double);
+    const size_t need = (size_t)kWorkVectors * n + np + nsc_elems + 16;
+    DevBuf own;
+    double *ws = nullptr;
+    if (P && P->work_elems >= need) {
+        ws = P->work;
+    } else {
+        if ((rc = dalloc(own, need * sizeof(double), s))) return rc;
+        ws = own.as<double>();
+    }
+    double *r = ws, *r2 = ws + n, *z = ws + 2 * (size_t)n, *p = ws + 3 * (size_t)n, *p2 = ws + 4 * (size_t)n;
+    double *q = ws + 5 * (size_t)n, *t = ws + 6 * (size_t)n;
+    double *partials = ws + kWorkVectors * (size_t)n;
+    PcgScalars *sc = (PcgScalars *)(partials + np);
+    PcgScalars *hsc = nullptr;
+    if ((rc = host_scalars(nsys, &hsc))) return rc;
+
+    // A in the SELL-64 layout for the iteration (one conversion per solve); CSR only for one
+    // system when asked for
+    Sell As;
+    const bool use_sell = option(AFSAI_OPT_PCG_CSR_A) == 0 || nsys > 1;
+    if (use_sell) {
+        ProfScope ps("sell_A", s);
+        if ((rc = sell_from_csr(n, A->nnz, A->row_ptr, A->col_idx, A->val, false, false, &As, di, s, seg))) return rc;
+    }
+    struct SellGuard {
+        Sell *S;
+        hipStream_t s;
+        ~SellGuard() {
+            (void)hipStreamSynchronize(s);
+            sell_free(S);
+        }
+    } sell_guard{&As, s};
+    const Csr Am = csr_of(A);
+    // products inside the iteration stop with their system (gate); the first and the final
+    // A x run for every system
+    auto spmv_A = [&](const char *name, const double *xin, double *yout, const double *w, int fin, bool gate) {
+        PcgScalars *g = gate ? sc : nullptr;
+        if (use_sell) sell_spmv(name, As, bm, xin, yout, w, w ? partials : nullptr, g, fin, di, s);
+        else spmv(name, Am, xin, yout, w, w ? partials : nullptr, g, fin, di, s);
+    };
+    const dim3 gv(bm.vec.nblocks), gs(bm.nsys);
+
+    const int plain = P ? 0 : 1;
+    hipLaunchKernelGGL(k_set_scalars, dim3((nsys + 255) / 256), dim3(256), 0, s, sc, nsys, rtol, maxit, plain);
+    // r0 = b - A x0
+    spmv_A("spmv_A", x, q, nullptr, FIN_NONE, false);
+    hipLaunchKernelGGL(k_init_residual, gv, dim3(kThreads), 0, s, n, b, q, r, partials, bm.vec.mp, bm.sy,
+                       di.num_xcds);
+    hipLaunchKernelGGL(k_finalize, gs, dim3(kThreads), 0, s, partials, bm.vec.nblocks, bm.vec.mp, (int)FIN_INIT, sc);
+    // z0 = M^-1 r0, rho0 = r0.z0, p0 = z0
+    const double *zz = z;
+    if (P) {
+        sell_spmv("spmv_G", P->sg, bm, r, t, nullptr, nullptr, sc, FIN_NONE, di, s);
+        sell_spmv("spmv_GT_dot", P->sgt, bm, t, z, r, partials, sc, FIN_RHO0, di, s);
+    } else {
+        zz = r;
+    }
+    // fused products where launches dominate (small systems), separate updates where the
+    // fused products' second gather costs more than the update kernels; the fused kernels
+    // need layouts without a tail
+    const int64_t form = option(AFSAI_OPT_PCG_FORM);
+    int nmax = 0;
+    for (int k = 0; k < nsys; ++k) nmax = std::max(nmax, row0[k + 1] - row0[k]);
+    const bool want_fused = form == 2 || (form == 0 && nmax < kFusedMaxRows);
+    const bool fused = P && use_sell && want_fused && !As.tail && !P->sg.tail;
+    if (!fused)
+        hipLaunchKernelGGL(k_update_p, gv, dim3(kThreads), 0, s, n, p, zz, sc, 1, bm.vec.mp, bm.sy, di.num_xcds);
+    int iter_no = 0;  // iterations enqueued so far
+
+    // timer marks: after the update of each iteration (launches past the last iteration that
+    // ran are dropped from the kernel timer at the end)
+    std::vector<int> marks;
+    const int mark0 = prof_mark();
+    auto enqueue_iteration = [&]() {
+        if (fused) {
+            // p and r are double-buffered: the products read neighbours' old entries while
+            // owners store the new ones
+            const bool odd = (iter_no & 1) == 0;  // iteration 1, 3, ...: p -> p2, r -> r2
+            double *p_old = odd ? p : p2, *p_new = odd ? p2 : p;
+            double *r_old = odd ? r : r2, *r_new = odd ? r2 : r;
+            sell_fused<FUSE_AP>("spmv_A_dot", As, bm, z, p_old, p_new, nullptr, nullptr, q, partials, sc,
+                                iter_no == 0 ? 1 : 0, FIN_ALPHA, di, s);
+            sell_fused<FUSE_GR>("spmv_G_upd", P->sg, bm, r_old, q, r_new, x, p_new, t, partials, sc, 0, FIN_UPDATE,
+                                di, s);
+            marks.push_back(prof_mark());
+            sell_spmv("spmv_GT_dot", P->sgt, bm, t, z, r_new, partials, sc, FIN_BETA, di, s);
+            ++iter_no;
+            return;
+        }
+        spmv_A("spmv_A_dot", p, q, p, FIN_ALPHA, true);
+        {
+            ProfScope ps("update_xr", s);
+            hipLaunchKernelGGL(k_update_xr, gv, dim3(kThreads), 0, s, n, x, r, p, q, partials, sc, bm.vec.mp, bm.sy,
+                               di.num_xcds);
+        }
+        hipLaunchKernelGGL(k_finalize, gs, dim3(kThreads), 0, s, partials, bm.vec.nblocks, bm.vec.mp,
+                           (int)FIN_UPDATE, sc);
+        marks.push_back(prof_mark());
+        if (P) {
+            sell_spmv("spmv_G", P->sg, bm, r, t, nullptr, nullptr, sc, FIN_NONE, di, s);
+            sell_spmv("spmv_GT_dot", P->sgt, bm, t, z, r, partials, sc, FIN_BETA, di, s);
+        }
+        {
+            ProfScope ps("update_p", s);
+            hipLaunchKernelGGL(k_update_p, gv, dim3(kThreads), 0, s, n, p, zz, sc, 0, bm.vec.mp, bm.sy, di.num_xcds);
+        }
+        ++iter_no;
+    };
+
+    // Chunks of iterations; the state after chunk c is read while chunk c+1 is already queued.
+    // Chunk sizes follow the observed residual reduction rate of the slowest system so that
+    // few iterations are queued past convergence (those return at once on the device flags).
+    hipEvent_t ev[2];
+    AFSAI_HIP_TRY(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
+    AFSAI_HIP_TRY(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
+    PcgScalars *hs[2] = {hsc, hsc + nsys};
+    const size_t scbytes = sizeof(PcgScalars) * (size_t)nsys;
+    AFSAI_HIP_TRY(hipMemcpyAsync(hs[1], sc, scbytes, hipMemcpyDeviceToHost, s));
+    AFSAI_HIP_TRY(hipEventRecord(ev[1], s));
+    int enqueued = 0, c = 0, chunk = 4;
+    bool finished = false;
+    std::vector<int> prev_it(nsys, 0);
+    std::vector<double> prev_rr(nsys, 0.0), rate(nsys, 0.0);
+    std::vector<char> have_prev(nsys, 0);
+    while (!finished) {
+        int todo = chunk;
+        {
+            // iterations the slowest active system still needs, from its observed rate
+            int need_max = -1;
+            const PcgScalars *st = hs[(c + 1) & 1];
+            for (int k = 0; k < nsys; ++k) {
+                if (st[k].done != DONE_NO) continue;
+                if (!(rate[k] < 0.0 && have_prev[k])) {
+                    need_max = -1;
+                    break;
+                }
+                const double tol2 = st[k].tol * st[k].tol;
+                const double need_it = std::ceil(std::log(tol2 / prev_rr[k]) / rate[k]);
+                need_max = std::max(need_max, (int)need_it - (enqueued - prev_it[k]) + 1);
+            }
+            if (need_max >= 0 && c > 0) todo = need_max < 1 ? 1 : (need_max > 64 ? 64 : need_max);
+        }
+        if (todo > maxit - enqueued) todo = maxit - enqueued;
+        for (int k = 0; k < todo; ++k) enqueue_iteration();
+        enqueued += todo;
+        AFSAI_HIP_TRY(hipMemcpyAsync(hs[c & 1], sc, scbytes, hipMemcpyDeviceToHost, s));
+        AFSAI_HIP_TRY(hipEventRecord(ev[c & 1], s));
+        // state after the previous chunk
+        AFSAI_HIP_TRY(hipEventSynchronize(ev[(c + 1) & 1]));
+        const PcgScalars *st = hs[(c + 1) & 1];
+        bool all_done = true;
+        for (int k = 0; k < nsys; ++k) {
+            if (st[k].done != DONE_NO) continue;
+            all_done = false;
+            if (have_prev[k] && st[k].it > prev_it[k] && st[k].rr > 0.0 && prev_rr[k] > 0.0) {
+                const double rt = std::log(st[k].rr / prev_rr[k]) / (st[k].it - prev_it[k]);
+                if (rt < 0.0) rate[k] = rt;
+            }
+            if (st[k].rr > 0.0) {
+                prev_rr[k] = st[k].rr;
+                prev_it[k] = st[k].it;
+                have_prev[k] = 1;
+            }
+        }
+        if (all_done) finished = true;
+        if (todo == 0) {
+            AFSAI_HIP_TRY(hipEventSynchronize(ev[c & 1]));
+            finished = true;
+        }
+        ++c;
+        if (chunk < 64) chunk *= 2;
+    }
+    AFSAI_HIP_TRY(hipStreamSynchronize(s));
+    std::vector<PcgScalars> fin_s(nsys);
+    AFSAI_HIP_TRY(hipMemcpy(fin_s.data(), sc, scbytes, hipMemcpyDeviceToHost));
+    int it_max = 0;
+    for (int k = 0; k < nsys; ++k) it_max = std::max(it_max, (int)fin_s[k].it);
+    {
+        const int keep_to = it_max >= 1 && it_max <= (int)marks.size() ? marks[it_max - 1] : mark0;
+        prof_drop(keep_to, prof_mark());
+    }
+
+    hipLaunchKernelGGL(k_zero_rhs, gv, dim3(kThreads), 0, s, n, x, sc, bm.vec.mp, bm.sy, di.num_xcds);
+    // true residuals ||b - A x||
+    spmv_A("spmv_A", x, q, nullptr, FIN_NONE, false);
+    hipLaunchKernelGGL(k_resid_norm, gv, dim3(kThreads), 0, s, n, b, q, partials, bm.vec.mp, bm.sy, di.num_xcds);
+    hipLaunchKernelGGL(k_finalize, gs, dim3(kThreads), 0, s, partials, bm.vec.nblocks, bm.vec.mp, (int)FIN_RESID, sc);
+    AFSAI_HIP_TRY(hipMemcpyAsync(hs[0], sc, scbytes, hipMemcpyDeviceToHost, s));
+    AFSAI_HIP_TRY(hipEventRecord(t1, s));
+    AFSAI_HIP_TRY(hipStreamSynchronize(s));
+    AFSAI_HIP_TRY(hipGetLastError());
+    float ms = 0.f;
+    AFSAI_HIP_TRY(hipEventElapsedTime(&ms, t0, t1));
+    prof_flush();
+    int status = AFSAI_OK;
+    for (int k = 0; k < nsys && status == AFSAI_OK; ++k) {
+        const PcgScalars &f = fin_s[k];
+        if (f.done == DONE_NOT_SPD) {
+            if (nsys == 1)
+                set_error("pcg_solve: p.Ap <= 0 at iteration %d (matrix or preconditioner not SPD)", f.it + 1);
+            else
+                set_error("pcg_solve_batched: system %d: p.Ap <= 0 at iteration %d (not SPD)", k, f.it + 1);
+            status = AFSAI_ERR_NOT_SPD;
+        } else if (f.done == DONE_MAXIT || (f.done == DONE_NO && maxit == 0)) {
+            if (nsys == 1) set_error("pcg_solve: not converged in %d iterations", f.it);
+            else set_error("pcg_solve_batched: system %d not converged in %d iterations", k, f.it);
+            status = AFSAI_ERR_NOT_CONVERGED;
+        }
+    }
+    if (info) {
+        for (int k = 0; k < nsys; ++k) {
+            const PcgScalars &f = fin_s[k];
+            const double nb = sqrt(f.bb);
+            info[k].iters = f.it;
+            info[k].converged = (f.done == DONE_CONVERGED || f.done == DONE_ZERO_RHS) ? 1 : 0;
+            info[k].relres = nb > 0 ? sqrt(f.rr) / nb : 0.0;
+            info[k].true_relres = (nb > 0 && f.done != DONE_ZERO_RHS) ? sqrt(hs[0][k].resid) / nb : 0.0;
+            info[k].ms = ms;
+        }
+    }
+    (void)hipEventDestroy(ev[0]);
+    (void)hipEventDestroy(ev[1]);
+    (void)hipEventDestroy(t0);
+    (void)hipEventDestroy(t1);
+    return status;
+}
 
 }  // namespace afsai
 
@@ -634,8 +1080,13 @@ int afsai_apply(afsai_precond P, const double *r, double *z, void *stream) {
     if (rc) return rc;
     hipStream_t s = (hipStream_t)stream;
     double *t = P->work;  // first n entries
-    sell_spmv("spmv_G", P->sg, r, t, nullptr, nullptr, nullptr, FIN_NONE, di, s);
-    sell_spmv("spmv_GT", P->sgt, t, z, nullptr, nullptr, nullptr, FIN_NONE, di, s);
+    // products only (no dots): the whole matrix as one system
+    BatchMaps bm;
+    if ((rc = make_batch_maps(P->sg.nslices * kSlice, 1, nullptr, di, s, &bm))) return rc;
+    bm.sell.nblocks = blocks_for_slices(P->sg.nslices, di);
+    sell_spmv("spmv_G", P->sg, bm, r, t, nullptr, nullptr, nullptr, FIN_NONE, di, s);
+    bm.sell.nblocks = blocks_for_slices(P->sgt.nslices, di);
+    sell_spmv("spmv_GT", P->sgt, bm, t, z, nullptr, nullptr, nullptr, FIN_NONE, di, s);
     AFSAI_HIP_TRY(hipGetLastError());
     return AFSAI_OK;
 }
@@ -648,211 +1099,32 @@ int pcg_solve(const afsai_csr *A, afsai_precond P, const double *b, double *x, d
     if (!b || !x) AFSAI_FAIL(AFSAI_ERR_INVALID_ARG, "pcg_solve: null b or x");
     if (!(rtol > 0.0) || maxit < 0) AFSAI_FAIL(AFSAI_ERR_INVALID_ARG, "pcg_solve: rtol = %g, maxit = %d", rtol, maxit);
     if (P && P->n != A->n) AFSAI_FAIL(AFSAI_ERR_INVALID_ARG, "pcg_solve: preconditioner has n = %d, A has n = %d", P->n, A->n);
-    DeviceInfo di;
-    if ((rc = device_info(&di))) return rc;
-    hipStream_t s = (hipStream_t)stream;
-    hipEvent_t t0, t1;
-    AFSAI_HIP_TRY(hipEventCreate(&t0));
-    AFSAI_HIP_TRY(hipEventCreate(&t1));
-    AFSAI_HIP_TRY(hipEventRecord(t0, s));
+    if (P && P->seg_row0.size() > 2)
+        AFSAI_FAIL(AFSAI_ERR_INVALID_ARG, "pcg_solve: the preconditioner is for a batch; use pcg_solve_batched");
+    return pcg_batch(A, P, 1, nullptr, b, x, rtol, maxit, (hipStream_t)stream, info);
+}
 
-    const int n = A->n;
-    const size_t np = partial_elems(di);
-    // workspace: r, r', z, p, p', q, t (n each), partials, scalars
-    const size_t need = (size_t)kWorkVectors * n + np + 16;
-    DevBuf own;
-    double *ws = nullptr;
-    if (P && P->work_elems >= need) {
-        ws = P->work;
-    } else {
-        if ((rc = dalloc(own, need * sizeof(double), s))) return rc;
-        ws = own.as<double>();
-    }
-    double *r = ws, *r2 = ws + n, *z = ws + 2 * (size_t)n, *p = ws + 3 * (size_t)n, *p2 = ws + 4 * (size_t)n;
-    double *q = ws + 5 * (size_t)n, *t = ws + 6 * (size_t)n;
-    double *partials = ws + kWorkVectors * (size_t)n;
-    PcgScalars *sc = (PcgScalars *)(partials + np);
-    // pinned host copies of the scalars, one pair per thread for the life of the process
-    static thread_local PcgScalars *hsc = nullptr;
-    if (!hsc) AFSAI_HIP_TRY(hipHostMalloc(&hsc, 2 * sizeof(PcgScalars), hipHostMallocDefault));
-
-    // A in the SELL-64 layout for the iteration (one conversion per solve)
-    Sell As;
-    const bool use_sell = option(AFSAI_OPT_PCG_CSR_A) == 0;
-    if (use_sell) {
-        ProfScope ps("sell_A", s);
-        if ((rc = sell_from_csr(n, A->nnz, A->row_ptr, A->col_idx, A->val, false, false, &As, di, s))) return rc;
-    }
-    struct SellGuard {
-        Sell *S;
-        hipStream_t s;
-        ~SellGuard() {
-            (void)hipStreamSynchronize(s);
-            sell_free(S);
-        }
-    } sell_guard{&As, s};
-    const Csr Am = csr_of(A);
-    auto spmv_A = [&](const char *name, const double *xin, double *yout, const double *w, int fin, PcgScalars *scp) {
-        if (use_sell) sell_spmv(name, As, xin, yout, w, w ? partials : nullptr, scp, fin, di, s);
-        else spmv(name, Am, xin, yout, w, w ? partials : nullptr, scp, fin, di, s);
-    };
-
-    const int nbv = blocks_for_vec(n, di);
-    const int plain = P ? 0 : 1;
-    hipLaunchKernelGGL(k_set_scalars, dim3(1), dim3(64), 0, s, sc, rtol, maxit, plain);
-    // r0 = b - A x0
-    spmv_A("spmv_A", x, q, nullptr, FIN_NONE, nullptr);
-    hipLaunchKernelGGL(k_init_residual, dim3(nbv), dim3(kThreads), 0, s, n, b, q, r, partials);
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kThreads), 0, s, partials, nbv, (int)FIN_INIT, sc);
-    // z0 = M^-1 r0, rho0 = r0.z0, p0 = z0
-    const double *zz = z;
+int pcg_solve_batched(const afsai_csr *A, afsai_precond P, int32_t nsys, const int32_t *offsets, const double *b,
+                      double *x, double rtol, int32_t maxit, void *stream, afsai_pcg_info *info) {
+    clear_error();
+    int rc = check_csr_arg(A, "pcg_solve_batched");
+    if (rc) return rc;
+    if (!b || !x || !offsets || nsys < 1) AFSAI_FAIL(AFSAI_ERR_INVALID_ARG, "pcg_solve_batched: null argument or nsys < 1");
+    if (!(rtol > 0.0) || maxit < 0)
+        AFSAI_FAIL(AFSAI_ERR_INVALID_ARG, "pcg_solve_batched: rtol = %g, maxit = %d", rtol, maxit);
+    if (offsets[0] != 0 || offsets[nsys] != A->n)
+        AFSAI_FAIL(AFSAI_ERR_INVALID_ARG, "pcg_solve_batched: offsets must run from 0 to n = %d", A->n);
+    for (int k = 0; k < nsys; ++k)
+        if (offsets[k + 1] <= offsets[k])
+            AFSAI_FAIL(AFSAI_ERR_INVALID_ARG, "pcg_solve_batched: system %d is empty or offsets decrease", k);
     if (P) {
-        sell_spmv("spmv_G", P->sg, r, t, nullptr, nullptr, sc, FIN_NONE, di, s);
-        sell_spmv("spmv_GT_dot", P->sgt, t, z, r, partials, sc, FIN_RHO0, di, s);
-    } else {
-        zz = r;
+        if (P->n != A->n) AFSAI_FAIL(AFSAI_ERR_INVALID_ARG, "pcg_solve_batched: preconditioner has n = %d, A has n = %d", P->n, A->n);
+        const bool same = (nsys == 1 && P->seg_row0.size() <= 2) ||
+                          (P->seg_row0.size() == (size_t)nsys + 1 &&
+                           std::equal(P->seg_row0.begin(), P->seg_row0.end(), offsets));
+        if (!same) AFSAI_FAIL(AFSAI_ERR_INVALID_ARG, "pcg_solve_batched: the preconditioner was set up for other systems");
     }
-    // fused iteration (preconditioned, A in SELL-64): p and r are double-buffered because the
-    // products read neighbours' old entries while owners store the new ones
-    // fused products where launches dominate (small systems), separate updates where the
-    // fused products' second gather costs more than the update kernels
-    const int64_t form = option(AFSAI_OPT_PCG_FORM);
-    const bool want_fused = form == 2 || (form == 0 && n < kFusedMaxRows);
-    const bool fused = P && use_sell && want_fused && !As.tail && !P->sg.tail;
-    if (!fused) hipLaunchKernelGGL(k_update_p, dim3(nbv), dim3(kThreads), 0, s, n, p, zz, sc, 1, di.num_xcds);
-    int iter_no = 0;  // iterations enqueued so far
-
-    // timer marks: after the update of each iteration (launches past the last iteration that
-    // ran are dropped from the kernel timer at the end)
-    std::vector<int> marks;
-    const int mark0 = prof_mark();
-    auto enqueue_iteration = [&]() {
-        if (fused) {
-            const bool odd = (iter_no & 1) == 0;  // iteration 1, 3, ...: p -> p2, r -> r2
-            double *p_old = odd ? p : p2, *p_new = odd ? p2 : p;
-            double *r_old = odd ? r : r2, *r_new = odd ? r2 : r;
-            sell_fused<FUSE_AP>("spmv_A_dot", As, z, p_old, p_new, nullptr, nullptr, q, partials, sc,
-                                iter_no == 0 ? 1 : 0, FIN_ALPHA, di, s);
-            sell_fused<FUSE_GR>("spmv_G_upd", P->sg, r_old, q, r_new, x, p_new, t, partials, sc, 0, FIN_UPDATE,
-                                di, s);
-            marks.push_back(prof_mark());
-            sell_spmv("spmv_GT_dot", P->sgt, t, z, r_new, partials, sc, FIN_BETA, di, s);
-            ++iter_no;
-            return;
-        }
-        spmv_A("spmv_A_dot", p, q, p, FIN_ALPHA, sc);
-        {
-            ProfScope ps("update_xr", s);
-            hipLaunchKernelGGL(k_update_xr, dim3(nbv), dim3(kThreads), 0, s, n, x, r, p, q, partials, sc, di.num_xcds);
-        }
-        hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kThreads), 0, s, partials, nbv, (int)FIN_UPDATE, sc);
-        marks.push_back(prof_mark());
-        if (P) {
-            sell_spmv("spmv_G", P->sg, r, t, nullptr, nullptr, sc, FIN_NONE, di, s);
-            sell_spmv("spmv_GT_dot", P->sgt, t, z, r, partials, sc, FIN_BETA, di, s);
-        }
-        {
-            ProfScope ps("update_p", s);
-            hipLaunchKernelGGL(k_update_p, dim3(nbv), dim3(kThreads), 0, s, n, p, zz, sc, 0, di.num_xcds);
-        }
-        ++iter_no;
-    };
-
-    // Chunks of iterations; the state after chunk c is read while chunk c+1 is already queued.
-    // Chunk sizes follow the observed residual reduction rate so that few iterations are
-    // queued past convergence (those return at once on the device flag).
-    hipEvent_t ev[2];
-    AFSAI_HIP_TRY(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
-    AFSAI_HIP_TRY(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
-    AFSAI_HIP_TRY(hipMemcpyAsync(&hsc[1], sc, sizeof(PcgScalars), hipMemcpyDeviceToHost, s));
-    AFSAI_HIP_TRY(hipEventRecord(ev[1], s));
-    int enqueued = 0, c = 0, chunk = 4;
-    bool finished = false, have_prev = false;
-    int prev_it = 0;
-    double prev_rr = 0.0, rate = 0.0;  // log of the per-iteration reduction of ||r||^2
-    while (!finished) {
-        int todo = chunk;
-        if (rate < 0.0 && have_prev) {
-            const double tol2 = hsc[(c + 1) & 1].tol * hsc[(c + 1) & 1].tol;
-            const double need_it = std::ceil(std::log(tol2 / prev_rr) / rate);
-            int rem = (int)need_it - (enqueued - prev_it) + 1;
-            todo = rem < 1 ? 1 : (rem > 64 ? 64 : rem);
-        }
-        if (todo > maxit - enqueued) todo = maxit - enqueued;
-        for (int k = 0; k < todo; ++k) enqueue_iteration();
-        enqueued += todo;
-        AFSAI_HIP_TRY(hipMemcpyAsync(&hsc[c & 1], sc, sizeof(PcgScalars), hipMemcpyDeviceToHost, s));
-        AFSAI_HIP_TRY(hipEventRecord(ev[c & 1], s));
-        // state after the previous chunk
-        AFSAI_HIP_TRY(hipEventSynchronize(ev[(c + 1) & 1]));
-        const PcgScalars &st = hsc[(c + 1) & 1];
-        if (st.done != DONE_NO) finished = true;
-        else {
-            if (have_prev && st.it > prev_it && st.rr > 0.0 && prev_rr > 0.0) {
-                const double rt = std::log(st.rr / prev_rr) / (st.it - prev_it);
-                if (rt < 0.0) rate = rt;
-            }
-            if (st.rr > 0.0) {
-                prev_rr = st.rr;
-                prev_it = st.it;
-                have_prev = true;
-            }
-        }
-        if (todo == 0) {
-            AFSAI_HIP_TRY(hipEventSynchronize(ev[c & 1]));
-            finished = true;
-        }
-        ++c;
-        if (chunk < 64) chunk *= 2;
-    }
-    AFSAI_HIP_TRY(hipStreamSynchronize(s));
-    PcgScalars fin_s;
-    AFSAI_HIP_TRY(hipMemcpy(&fin_s, sc, sizeof(PcgScalars), hipMemcpyDeviceToHost));
-    {
-        const int keep_to = fin_s.it >= 1 && fin_s.it <= (int)marks.size() ? marks[fin_s.it - 1] : mark0;
-        prof_drop(keep_to, prof_mark());
-    }
-
-    int status = AFSAI_OK;
-    if (fin_s.done == DONE_ZERO_RHS) {
-        hipLaunchKernelGGL(k_zero, dim3(nbv), dim3(kThreads), 0, s, n, x);
-    }
-    double true_rr = 0.0;
-    if (fin_s.done != DONE_ZERO_RHS) {
-        // true residual ||b - A x||
-        spmv_A("spmv_A", x, q, nullptr, FIN_NONE, nullptr);
-        hipLaunchKernelGGL(k_resid_norm, dim3(nbv), dim3(kThreads), 0, s, n, b, q, partials);
-        hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kThreads), 0, s, partials, nbv, (int)FIN_RESID, sc);
-        AFSAI_HIP_TRY(hipMemcpyAsync(&hsc[0], sc, sizeof(PcgScalars), hipMemcpyDeviceToHost, s));
-        AFSAI_HIP_TRY(hipStreamSynchronize(s));
-        true_rr = hsc[0].resid;
-    }
-    AFSAI_HIP_TRY(hipEventRecord(t1, s));
-    AFSAI_HIP_TRY(hipStreamSynchronize(s));
-    AFSAI_HIP_TRY(hipGetLastError());
-    float ms = 0.f;
-    AFSAI_HIP_TRY(hipEventElapsedTime(&ms, t0, t1));
-    prof_flush();
-    if (fin_s.done == DONE_NOT_SPD) {
-        set_error("pcg_solve: p.Ap <= 0 at iteration %d (matrix or preconditioner not SPD)", fin_s.it + 1);
-        status = AFSAI_ERR_NOT_SPD;
-    } else if (fin_s.done == DONE_MAXIT || (fin_s.done == DONE_NO && maxit == 0)) {
-        set_error("pcg_solve: not converged in %d iterations", fin_s.it);
-        status = AFSAI_ERR_NOT_CONVERGED;
-    }
-    if (info) {
-        const double nb = sqrt(fin_s.bb);
-        info->iters = fin_s.it;
-        info->converged = (fin_s.done == DONE_CONVERGED || fin_s.done == DONE_ZERO_RHS) ? 1 : 0;
-        info->relres = nb > 0 ? sqrt(fin_s.rr) / nb : 0.0;
-        info->true_relres = nb > 0 ? sqrt(true_rr) / nb : 0.0;
-        info->ms = ms;
-    }
-    (void)hipEventDestroy(ev[0]);
-    (void)hipEventDestroy(ev[1]);
-    (void)hipEventDestroy(t0);
-    (void)hipEventDestroy(t1);
-    return status;
+    return pcg_batch(A, P, nsys, offsets, b, x, rtol, maxit, (hipStream_t)stream, info);
 }
 
 }  // extern "C"

@@ -260,3 +260,29 @@ def aniso_batch(nsys: int = 512, seed: int = 3, side_lo: int = 10, side_hi: int 
         probs.append(Problem(f"aniso7_{k}", A, b, x, kmax, s,
                              meta={"sides": sides, "coef": c, "seed": seed, "index": k}))
     return probs
+
+
+def block_diag(probs: list[Problem]) -> tuple[CSR, np.ndarray, np.ndarray, np.ndarray]:
+    """The systems of a batch as one block-diagonal CSR matrix: (A, offsets, b, x_true), system
+    k owning rows offsets[k] .. offsets[k+1]-1."""
+    sizes = np.array([p.A.n for p in probs], dtype=np.int64)
+    offsets = np.zeros(len(probs) + 1, dtype=np.int64)
+    offsets[1:] = np.cumsum(sizes)
+    nnzs = np.array([p.A.nnz for p in probs], dtype=np.int64)
+    nnz_off = np.zeros(len(probs) + 1, dtype=np.int64)
+    nnz_off[1:] = np.cumsum(nnzs)
+    n, nnz = int(offsets[-1]), int(nnz_off[-1])
+    if n >= 2**31 or nnz >= 2**31:
+        raise ValueError("batch too large for int32 indices")
+    rp = np.empty(n + 1, dtype=np.int32)
+    col = np.empty(nnz, dtype=np.int32)
+    val = np.empty(nnz, dtype=np.float64)
+    for k, p in enumerate(probs):
+        o, e = int(offsets[k]), int(nnz_off[k])
+        rp[o:o + p.A.n] = p.A.row_ptr[:-1] + e
+        col[e:e + p.A.nnz] = p.A.col + o
+        val[e:e + p.A.nnz] = p.A.val
+    rp[n] = nnz
+    b = np.concatenate([p.b for p in probs])
+    x = np.concatenate([p.x_true for p in probs])
+    return CSR(rp, col, val), offsets.astype(np.int32), b, x

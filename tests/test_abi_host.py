@@ -104,3 +104,30 @@ def test_profile_toggle_without_gpu(L):
     cnt = ctypes.c_int32(-1)
     assert L.afsai_profile_read(arr, 4, ctypes.byref(cnt), 1) == af.OK
     assert cnt.value == 0
+
+
+def test_batched_arguments_rejected_on_host(L):
+    h = ctypes.c_void_p()
+    p = af.ParamsStruct(5, 1, 1e-2, af.TIE_RTOL, af.F64, 0)
+    A = _fake_csr(n=10, nnz=10)
+    I32 = ctypes.c_int32
+
+    def offs(*v):
+        return (I32 * len(v))(*v)
+
+    assert L.afsai_setup_batched(ctypes.byref(A), 2, None, ctypes.byref(p), None, ctypes.byref(h)) == af.ERR_INVALID_ARG
+    assert L.afsai_setup_batched(ctypes.byref(A), 0, offs(0, 10), ctypes.byref(p), None,
+                                 ctypes.byref(h)) == af.ERR_INVALID_ARG
+    assert L.afsai_setup_batched(ctypes.byref(A), 2, offs(1, 5, 10), ctypes.byref(p), None,
+                                 ctypes.byref(h)) == af.ERR_INVALID_ARG
+    assert L.afsai_setup_batched(ctypes.byref(A), 2, offs(0, 5, 9), ctypes.byref(p), None,
+                                 ctypes.byref(h)) == af.ERR_INVALID_ARG
+    assert L.afsai_setup_batched(ctypes.byref(A), 2, offs(0, 5, 5), ctypes.byref(p), None,
+                                 ctypes.byref(h)) == af.ERR_INVALID_ARG
+    assert h.value is None
+    info = (af.PcgInfoStruct * 2)()
+    x = ctypes.c_void_p(0x10)
+    bb = ctypes.c_void_p(0x20)
+    assert L.pcg_solve_batched(ctypes.byref(A), None, 2, offs(0, 7, 6), bb, x, 1e-8, 10, None, info) == af.ERR_INVALID_ARG
+    assert L.pcg_solve_batched(ctypes.byref(A), None, 2, None, bb, x, 1e-8, 10, None, info) == af.ERR_INVALID_ARG
+    assert L.pcg_solve_batched(ctypes.byref(A), None, 2, offs(0, 5, 10), bb, x, 0.0, 10, None, info) == af.ERR_INVALID_ARG
