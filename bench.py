@@ -27,6 +27,77 @@ METRIC = "aFSAI setup+PCG s to rtol 1e-8, HBM GB/s; p50/p99 latency vs plain"
 PEAK_HBM_GBS = 8000.0
 
 
+BATCH_WORKLOADS = {"aniso_batch512": 512}
+
+
+def batch_bench(args):
+    """Batching form: one step = afsai_setup_batched + pcg_solve_batched over the whole batch of
+    anisotropic 7-point systems (sides U{10..40}, k_max = 5, s = 1, eps = 1e-2, rtol = 1e-8);
+    "plain" = the same systems set up and solved one after another with afsai_setup + pcg_solve."""
+    import torch
+
+    import paper_2010_14175_amd as af
+    import synth
+
+    nsys = BATCH_WORKLOADS[args.workload]
+    probs = synth.aniso_batch(nsys=nsys, seed=3, side_lo=10, side_hi=40, kmax=5, s=1)
+    A, off, b_h, _ = synth.block_diag(probs)
+    print(f"[bench] workload {args.workload}: {nsys} systems, n={A.n} nnz={A.nnz}", file=sys.stderr, flush=True)
+    dA = af.DeviceCSR.from_host(A)
+    b = torch.from_numpy(b_h).cuda()
+    x = torch.zeros_like(b)
+
+    def step():
+        P = af.setup_batched(dA, off, 5, 1, 1e-2)
+        x.zero_()
+        _, infos = af.pcg_solve_batched(dA, P, off, b, x=x, rtol=1e-8)
+        sinfo = P.info()
+        P.close()
+        return sinfo, infos
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    if not args.no_profile:
+        af.profile_read(reset=True)
+        af.profile_enable(True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        sinfo, infos = step()
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / args.steps
+    kern = {}
+    if not args.no_profile:
+        af.profile_enable(False)
+        kern = {k: {"launches": v[0], "total_ms": round(v[1], 3), "avg_us": round(v[1] / max(1, v[0]) * 1e3, 2)}
+                for k, v in af.profile_read(reset=True).items()}
+    its = np.array([i.iters for i in infos])
+    worst = max(i.true_relres for i in infos)
+    # plain form, one system after another (timed once after one warm-up system)
+    singles = [(af.DeviceCSR.from_host(pb.A), torch.from_numpy(pb.b).cuda()) for pb in probs]
+    af.pcg_solve(singles[0][0], af.setup(singles[0][0], 5, 1, 1e-2), singles[0][1])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for dk, bk in singles:
+        Pk = af.setup(dk, 5, 1, 1e-2)
+        af.pcg_solve(dk, Pk, bk, rtol=1e-8)
+        Pk.close()
+    torch.cuda.synchronize()
+    plain = time.perf_counter() - t0
+    print(f"[bench] {args.steps} steps: {sec * 1e3:.2f} ms/step batched (setup {sinfo.ms:.2f} ms, pcg "
+          f"{infos[0].ms:.2f} ms, iterations {its.min()}..{its.max()}, worst true relres {worst:.2e}); "
+          f"plain one by one {plain * 1e3:.1f} ms", file=sys.stderr, flush=True)
+    out = {"metric": METRIC, "value": round(sec, 6), "unit": "s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": round(sec * 1e3, 3), "higher_is_better": False, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": args.workload, "systems": nsys, "n": A.n, "nnz": A.nnz, "kmax": 5, "s": 1,
+                      "eps": 1e-2, "rtol": 1e-8},
+           "setup_ms": round(sinfo.ms, 3), "pcg_ms": round(infos[0].ms, 3), "iters_min": int(its.min()),
+           "iters_max": int(its.max()), "worst_true_relres": worst, "plain_one_by_one_s": round(plain, 4),
+           "speedup_vs_plain": round(plain / sec, 2), "roofline": None, "kernels": kern, "cpu_baseline": None}
+    print(json.dumps(out), flush=True)
+
+
 def workloads():
     import synth
 
@@ -129,7 +200,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="elast27_64", choices=sorted(workloads()))
+    ap.add_argument("--workload", default="elast27_64", choices=sorted(list(workloads()) + list(BATCH_WORKLOADS)))
     ap.add_argument("--g-prec", default="f64", choices=["f64", "f32"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=0)
@@ -154,6 +225,9 @@ def main():
     torch.cuda.set_device(0)
     af.lib()
 
+    if args.workload in BATCH_WORKLOADS:
+        batch_bench(args)
+        return
     pb = workloads()[args.workload]()
     g_prec = af.F32 if args.g_prec == "f32" else af.F64
     print(f"[bench] workload {pb.name}: n={pb.n} nnz={pb.A.nnz} kmax={pb.kmax} s={pb.s} eps={pb.eps} "

@@ -22,6 +22,7 @@
 #ifndef AFSAI_H
 #define AFSAI_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -178,6 +179,63 @@ int afsai_setup_batched(const afsai_csr *A, int32_t nsys, const int32_t *offsets
  */
 int pcg_solve_batched(const afsai_csr *A, afsai_precond P, int32_t nsys, const int32_t *offsets, const double *b,
                       double *x, double rtol, int32_t maxit, void *stream, afsai_pcg_info *info);
+
+/*
+ * Serving: a request loop that admits SPD systems of mixed sizes, sets each up (afsai_setup)
+ *   and solves it (pcg_solve, x0 = 0) while others are in progress.
+ *   Requests wait in arrival order and are admitted while fewer than max_slots are admitted and
+ *   the admitted requests' device footprints (setup results, G and G^T, the SELL copy of A,
+ *   the solver vectors; an estimate from n, nnz and params, reported per request) fit in
+ *   hbm_budget; a finished request frees its slot and memory at once and admits the next
+ *   (continuous batching).  Each admitted request has its own stream: setup threads set up new
+ *   requests while one scheduler thread keeps the PCG iterations of all solving requests in
+ *   flight together.  A request's x is the one a separate afsai_setup + pcg_solve with the same
+ *   parameters gives, bit for bit, whatever else is served.  Kernel timing (afsai_profile_*)
+ *   must be off while a server runs.
+ */
+typedef struct afsai_server_s *afsai_server;
+
+typedef struct afsai_server_config {
+    size_t hbm_budget;      /* bytes of device memory admitted requests may hold (> 0) */
+    int32_t max_slots;      /* requests admitted at once (>= 1; 1 serves one request at a time) */
+    int32_t setup_threads;  /* host threads running setups (1..64) */
+    afsai_params params;    /* setup parameters of every request */
+    double rtol;            /* PCG stopping tolerance of every request */
+    int32_t maxit;          /* PCG iteration limit of every request */
+} afsai_server_config;
+
+typedef struct afsai_request_result {
+    int64_t ticket;         /* from afsai_server_submit */
+    int32_t status;         /* AFSAI_OK, or the error of its setup or solve */
+    int32_t iters;
+    int32_t converged;
+    double true_relres;     /* ||b - A x|| / ||b|| */
+    int64_t footprint;      /* device bytes the request held while admitted (estimate) */
+    double submit_ms, admit_ms, setup_done_ms, done_ms;  /* times since the server was created */
+} afsai_request_result;
+
+/* afsai_server_create -- starts the setup threads and the scheduler on the current device. */
+int afsai_server_create(const afsai_server_config *cfg, afsai_server *out);
+
+/*
+ * afsai_server_submit -- queues the solve of A x = b (A, b, x device arrays; A's arrays, b and
+ *   x must stay valid and untouched until the request's result has been polled).  x is set to
+ *   0 before the solve.  Returns AFSAI_ERR_TOO_LARGE when the request alone exceeds the budget.
+ */
+int afsai_server_submit(afsai_server S, const afsai_csr *A, const double *b, double *x, int64_t *ticket);
+
+/*
+ * afsai_server_poll -- moves up to max_results finished requests (in completion order) into out
+ *   (host) and sets *count; waits up to wait_ms for one when none has finished.
+ */
+int afsai_server_poll(afsai_server S, afsai_request_result *out, int32_t max_results, int32_t *count,
+                      int32_t wait_ms);
+
+/* afsai_server_pending -- requests not yet finished, device bytes and slots currently admitted. */
+int afsai_server_pending(afsai_server S, int64_t *outstanding, int64_t *bytes_in_use, int32_t *slots_in_use);
+
+/* afsai_server_destroy -- waits for every submitted request, then stops the server. */
+int afsai_server_destroy(afsai_server S);
 
 /* afsai_spmv -- y = A x (group-per-row CSR product used by the solver).  Asynchronous. */
 int afsai_spmv(const afsai_csr *A, const double *x, double *y, void *stream);

@@ -28,13 +28,26 @@ VALIDATE = 1
 STOP_KMAX, STOP_EPS, STOP_NOCAND = 0, 1, 2
 
 # every symbol the C header declares
-EXPORTS = ("afsai_setup", "afsai_apply", "pcg_solve", "afsai_setup_batched", "pcg_solve_batched", "afsai_spmv",
+EXPORTS = ("afsai_setup", "afsai_apply", "pcg_solve", "afsai_setup_batched", "pcg_solve_batched",
+           "afsai_server_create", "afsai_server_submit", "afsai_server_poll", "afsai_server_pending",
+           "afsai_server_destroy", "afsai_spmv",
            "afsai_get_setup_info", "afsai_export",
            "afsai_export_rows", "afsai_import", "afsai_destroy", "afsai_last_error", "afsai_set_option",
            "afsai_release_cache",
            "afsai_profile_enable", "afsai_profile_read")
 (OPT_SETUP_GROUP, OPT_SETUP_TABLE, OPT_SPMV_GROUP, OPT_SPMV_UNROLL, OPT_PCG_CSR_A, OPT_PCG_FORM,
  OPT_SELL_WIDTH) = 1, 2, 3, 4, 5, 6, 7
+
+
+class ServerConfigStruct(ctypes.Structure):
+    pass
+
+
+class RequestResultStruct(ctypes.Structure):
+    _fields_ = [("ticket", ctypes.c_int64), ("status", ctypes.c_int32), ("iters", ctypes.c_int32),
+                ("converged", ctypes.c_int32), ("true_relres", ctypes.c_double), ("footprint", ctypes.c_int64),
+                ("submit_ms", ctypes.c_double), ("admit_ms", ctypes.c_double), ("setup_done_ms", ctypes.c_double),
+                ("done_ms", ctypes.c_double)]
 
 
 class CsrStruct(ctypes.Structure):
@@ -45,6 +58,11 @@ class CsrStruct(ctypes.Structure):
 class ParamsStruct(ctypes.Structure):
     _fields_ = [("kmax", ctypes.c_int32), ("s", ctypes.c_int32), ("eps", ctypes.c_double),
                 ("tie_rtol", ctypes.c_double), ("g_prec", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+
+
+ServerConfigStruct._fields_ = [("hbm_budget", ctypes.c_size_t), ("max_slots", ctypes.c_int32),
+                               ("setup_threads", ctypes.c_int32), ("params", ParamsStruct), ("rtol", ctypes.c_double),
+                               ("maxit", ctypes.c_int32)]
 
 
 class SetupInfoStruct(ctypes.Structure):
@@ -85,6 +103,11 @@ def lib():
         L.afsai_apply.argtypes = [vp, vp, vp, vp]
         L.pcg_solve.argtypes = [P(CsrStruct), vp, vp, vp, ctypes.c_double, i32, vp, P(PcgInfoStruct)]
         L.afsai_spmv.argtypes = [P(CsrStruct), vp, vp, vp]
+        L.afsai_server_create.argtypes = [P(ServerConfigStruct), P(vp)]
+        L.afsai_server_submit.argtypes = [vp, P(CsrStruct), vp, vp, P(ctypes.c_int64)]
+        L.afsai_server_poll.argtypes = [vp, P(RequestResultStruct), i32, P(i32), i32]
+        L.afsai_server_pending.argtypes = [vp, P(ctypes.c_int64), P(ctypes.c_int64), P(i32)]
+        L.afsai_server_destroy.argtypes = [vp]
         L.afsai_setup_batched.argtypes = [P(CsrStruct), i32, P(i32), P(ParamsStruct), vp, P(vp)]
         L.pcg_solve_batched.argtypes = [P(CsrStruct), vp, i32, P(i32), vp, vp, ctypes.c_double, i32, vp,
                                         P(PcgInfoStruct)]
@@ -309,6 +332,78 @@ def pcg_solve_batched(A: DeviceCSR, P: Preconditioner | None, offsets, b, x=None
     if raise_on_error:
         _check(rc, "pcg_solve_batched", allow=(OK, ERR_NOT_CONVERGED))
     return x, [PcgInfo(rc, f.iters, bool(f.converged), f.relres, f.true_relres, f.ms) for f in infs]
+
+
+@dataclass
+class RequestResult:
+    ticket: int
+    status: int
+    iters: int
+    converged: bool
+    true_relres: float
+    footprint: int
+    submit_ms: float
+    admit_ms: float
+    setup_done_ms: float
+    done_ms: float
+
+    @property
+    def latency_ms(self) -> float:
+        return self.done_ms - self.submit_ms
+
+
+class Server:
+    """Serving loop (``afsai_server_*``): requests are admitted while slots and the device-memory
+    budget allow, set up and solved concurrently; results come back through ``poll``."""
+
+    def __init__(self, hbm_budget: int, max_slots: int, kmax: int, s: int, eps: float, rtol: float = 1e-8,
+                 maxit: int = 100000, g_prec: int = F64, setup_threads: int = 2, tie_rtol: float = TIE_RTOL):
+        cfg = ServerConfigStruct(int(hbm_budget), int(max_slots), int(setup_threads),
+                                 ParamsStruct(int(kmax), int(s), float(eps), float(tie_rtol), int(g_prec), 0),
+                                 float(rtol), int(maxit))
+        h = ctypes.c_void_p()
+        _check(lib().afsai_server_create(ctypes.byref(cfg), ctypes.byref(h)), "afsai_server_create")
+        self._h = h
+        self._keep = {}  # ticket -> (A, b, x) kept alive until the result is polled
+
+    def submit(self, A: DeviceCSR, b, x) -> int:
+        """Queues A x = b (device data; x is overwritten).  Returns the request's ticket."""
+        t = ctypes.c_int64()
+        st = A.struct
+        _check(lib().afsai_server_submit(self._h, ctypes.byref(st), _ptr(b), _ptr(x), ctypes.byref(t)),
+               "afsai_server_submit")
+        self._keep[t.value] = (A, b, x)
+        return t.value
+
+    def poll(self, wait_ms: int = 0, max_results: int = 256) -> list[RequestResult]:
+        out = (RequestResultStruct * max_results)()
+        cnt = ctypes.c_int32()
+        _check(lib().afsai_server_poll(self._h, out, max_results, ctypes.byref(cnt), int(wait_ms)), "afsai_server_poll")
+        res = []
+        for r in out[: cnt.value]:
+            self._keep.pop(r.ticket, None)
+            res.append(RequestResult(r.ticket, r.status, r.iters, bool(r.converged), r.true_relres, r.footprint,
+                                     r.submit_ms, r.admit_ms, r.setup_done_ms, r.done_ms))
+        return res
+
+    def pending(self) -> tuple[int, int, int]:
+        """(requests not finished, device bytes admitted, slots admitted)."""
+        o, b = ctypes.c_int64(), ctypes.c_int64()
+        sl = ctypes.c_int32()
+        _check(lib().afsai_server_pending(self._h, ctypes.byref(o), ctypes.byref(b), ctypes.byref(sl)),
+               "afsai_server_pending")
+        return o.value, b.value, sl.value
+
+    def close(self):
+        if self._h:
+            lib().afsai_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def spmv(A: DeviceCSR, x, y=None, stream=None):

@@ -17,7 +17,7 @@ LIB = os.path.join(HERE, "libafsai.so")
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 HIPCC = os.path.join(ROCM, "bin", "hipcc")
 
-SOURCES = ["rows.hip", "setup.hip", "solve.hip", "sell.hip", "runtime.hip"]
+SOURCES = ["rows.hip", "setup.hip", "solve.hip", "sell.hip", "serve.hip", "runtime.hip"]
 
 HIPFLAGS = [
     "--offload-arch=gfx950",

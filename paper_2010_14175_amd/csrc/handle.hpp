@@ -28,3 +28,14 @@ struct afsai_precond_s {
     // entries; empty for a single system
     std::vector<int32_t> seg_row0;
 };
+
+namespace afsai {
+// A single-system solve as a task for the serving loop (solve.hip): begin enqueues the start
+// on `stream`; advance never waits when block is false; finish waits and fills info.
+struct PcgTask;
+int pcg_task_begin(const afsai_csr &A, afsai_precond P, const double *b, double *x, double rtol, int32_t maxit,
+                   hipStream_t stream, PcgTask **out);
+int pcg_task_advance(PcgTask *t, bool block, bool *finished);
+int pcg_task_finish(PcgTask *t, afsai_pcg_info *info);
+void pcg_task_free(PcgTask *t);
+}  // namespace afsai

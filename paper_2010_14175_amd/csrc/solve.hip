@@ -788,270 +788,351 @@ static Csr csr_of(const afsai_csr *A) {
 // work vectors of the solver: r, r', z, p, p', q, t
 constexpr int kWorkVectors = 7;
 
-// pinned host copies of the systems' scalars (two sets), per thread for the life of the process
-static int host_scalars(int nsys, PcgScalars **out) {
-    static thread_local PcgScalars *hsc = nullptr;
-    static thread_local int cap = 0;
-    if (cap < nsys) {
-        if (hsc) (void)hipHostFree(hsc);
-        hsc = nullptr;
-        cap = 0;
-        int want = nsys < 4 ? 4 : nsys;
-        AFSAI_HIP_TRY(hipHostMalloc(&hsc, 2 * sizeof(PcgScalars) * (size_t)want, hipHostMallocDefault));
-        cap = want;
+// A solve in progress: PCG (Sec. 5.2) over a batch of nsys independent systems (row0: host,
+// nsys + 1 entries; one system when nsys == 1).  begin() enqueues the start and two chunks of
+// iterations; advance() reads the state after the oldest chunk in flight (waiting for it when
+// `block`, else returning at once if it is not there yet) and enqueues the next chunk, sized from
+// the slowest system's convergence rate so that few iterations are queued past convergence
+// (those return at once on the device flags); finish() computes the true residuals and the
+// results.  All work goes to one stream; any number of runs may be in progress on different
+// streams (the serving loop advances many of them from one host thread).
+class PcgRun {
+  public:
+    PcgRun(const afsai_csr &A, afsai_precond P, int nsys, const int32_t *row0, const double *b, double *x,
+           double rtol, int32_t maxit, hipStream_t s)
+        : A_(A), P_(P), nsys_(nsys), b_(b), x_(x), rtol_(rtol), maxit_(maxit), s_(s) {
+        if (nsys > 1 && row0) row0_.assign(row0, row0 + nsys + 1);
+        else row0_ = {0, A.n};
     }
-    *out = hsc;
-    return AFSAI_OK;
-}
-
-// The preconditioned CG of Sec. 5.2 over a batch of nsys independent systems (row0: host,
-// nsys + 1 entries, nullptr for one system); info: nsys entries (may be null).
-static int pcg_batch(const afsai_csr *A, afsai_precond P, int nsys, const int32_t *row0_in, const double *b,
-                     double *x, double rtol, int32_t maxit, hipStream_t s, afsai_pcg_info *info) {
-    const int n = A->n;
-    DeviceInfo di;
-    int rc;
-    if ((rc = device_info(&di))) return rc;
-    hipEvent_t t0, t1;
-    AFSAI_HIP_TRY(hipEventCreate(&t0));
-    AFSAI_HIP_TRY(hipEventCreate(&t1));
-    AFSAI_HIP_TRY(hipEventRecord(t0, s));
-
-    std::vector<int32_t> row0_one = {0, n};
-    const int32_t *row0 = (nsys > 1) ? row0_in : row0_one.data();
-    BatchMaps bm;
-    if ((rc = make_batch_maps(n, nsys, row0, di, s, &bm))) return rc;
-    Segments seg;
-    seg.nsys = nsys;
-    seg.row0 = row0;
-
-    const size_t np = (size_t)2 * std::max(bm.sell.nblocks, std::max(bm.vec.nblocks, di.num_cus * 16)) + 64;
-    const size_t nsc_elems = (sizeof(PcgScalars) * (size_t)nsys + sizeof(double) - 1) / sizeof(double);
-    const size_t need = (size_t)kWorkVectors * n + np + nsc_elems + 16;
-    DevBuf own;
-    double *ws = nullptr;
-    if (P && P->work_elems >= need) {
-        ws = P->work;
-    } else {
-        if ((rc = dalloc(own, need * sizeof(double), s))) return rc;
-        ws = own.as<double>();
+    ~PcgRun() {
+        if (started_) (void)hipStreamSynchronize(s_);
+        sell_free(&As_);
+        for (hipEvent_t e : {t0_, t1_, ev_[0], ev_[1]})
+            if (e) (void)hipEventDestroy(e);
+        if (hsc_) (void)hipHostFree(hsc_);
     }
-    double *r = ws, *r2 = ws + n, *z = ws + 2 * (size_t)n, *p = ws + 3 * (size_t)n, *p2 = ws + 4 * (size_t)n;
-    double *q = ws + 5 * (size_t)n, *t = ws + 6 * (size_t)n;
-    double *partials = ws + kWorkVectors * (size_t)n;
-    PcgScalars *sc = (PcgScalars *)(partials + np);
-    PcgScalars *hsc = nullptr;
-    if ((rc = host_scalars(nsys, &hsc))) return rc;
+    PcgRun(const PcgRun &) = delete;
+    PcgRun &operator=(const PcgRun &) = delete;
 
-    // A in the SELL-64 layout for the iteration (one conversion per solve); CSR only for one
-    // system when asked for
-    Sell As;
-    const bool use_sell = option(AFSAI_OPT_PCG_CSR_A) == 0 || nsys > 1;
-    if (use_sell) {
-        ProfScope ps("sell_A", s);
-        if ((rc = sell_from_csr(n, A->nnz, A->row_ptr, A->col_idx, A->val, false, false, &As, di, s, seg))) return rc;
+    int begin() {
+        const int n = A_.n;
+        int rc;
+        if ((rc = device_info(&di_))) return rc;
+        AFSAI_HIP_TRY(hipEventCreate(&t0_));
+        AFSAI_HIP_TRY(hipEventCreate(&t1_));
+        AFSAI_HIP_TRY(hipEventCreateWithFlags(&ev_[0], hipEventDisableTiming));
+        AFSAI_HIP_TRY(hipEventCreateWithFlags(&ev_[1], hipEventDisableTiming));
+        AFSAI_HIP_TRY(hipHostMalloc(&hsc_, 2 * sizeof(PcgScalars) * (size_t)nsys_, hipHostMallocDefault));
+        hs_[0] = hsc_;
+        hs_[1] = hsc_ + nsys_;
+        AFSAI_HIP_TRY(hipEventRecord(t0_, s_));
+        started_ = true;
+        if ((rc = make_batch_maps(n, nsys_, row0_.data(), di_, s_, &bm_))) return rc;
+        Segments seg;
+        seg.nsys = nsys_;
+        seg.row0 = row0_.data();
+
+        const size_t np = (size_t)2 * std::max(bm_.sell.nblocks, std::max(bm_.vec.nblocks, di_.num_cus * 16)) + 64;
+        const size_t nsc_elems = (sizeof(PcgScalars) * (size_t)nsys_ + sizeof(double) - 1) / sizeof(double);
+        const size_t need = (size_t)kWorkVectors * n + np + nsc_elems + 16;
+        double *ws = nullptr;
+        if (P_ && P_->work_elems >= need) {
+            ws = P_->work;
+        } else {
+            if ((rc = dalloc(own_, need * sizeof(double), s_))) return rc;
+            ws = own_.as<double>();
+        }
+        r_ = ws;
+        r2_ = ws + n;
+        z_ = ws + 2 * (size_t)n;
+        p_ = ws + 3 * (size_t)n;
+        p2_ = ws + 4 * (size_t)n;
+        q_ = ws + 5 * (size_t)n;
+        t_ = ws + 6 * (size_t)n;
+        partials_ = ws + kWorkVectors * (size_t)n;
+        sc_ = (PcgScalars *)(partials_ + np);
+
+        // A in the SELL-64 layout for the iteration (one conversion per solve); CSR only for one
+        // system when asked for
+        use_sell_ = option(AFSAI_OPT_PCG_CSR_A) == 0 || nsys_ > 1;
+        if (use_sell_) {
+            ProfScope ps("sell_A", s_);
+            if ((rc = sell_from_csr(n, A_.nnz, A_.row_ptr, A_.col_idx, A_.val, false, false, &As_, di_, s_, seg)))
+                return rc;
+        }
+        const dim3 gv(bm_.vec.nblocks), gs(bm_.nsys);
+        const int plain = P_ ? 0 : 1;
+        hipLaunchKernelGGL(k_set_scalars, dim3((nsys_ + 255) / 256), dim3(256), 0, s_, sc_, nsys_, rtol_, maxit_,
+                           plain);
+        // r0 = b - A x0
+        spmv_A("spmv_A", x_, q_, nullptr, FIN_NONE, false);
+        hipLaunchKernelGGL(k_init_residual, gv, dim3(kThreads), 0, s_, n, b_, q_, r_, partials_, bm_.vec.mp, bm_.sy,
+                           di_.num_xcds);
+        hipLaunchKernelGGL(k_finalize, gs, dim3(kThreads), 0, s_, partials_, bm_.vec.nblocks, bm_.vec.mp,
+                           (int)FIN_INIT, sc_);
+        // z0 = M^-1 r0, rho0 = r0.z0, p0 = z0
+        zz_ = z_;
+        if (P_) {
+            sell_spmv("spmv_G", P_->sg, bm_, r_, t_, nullptr, nullptr, sc_, FIN_NONE, di_, s_);
+            sell_spmv("spmv_GT_dot", P_->sgt, bm_, t_, z_, r_, partials_, sc_, FIN_RHO0, di_, s_);
+        } else {
+            zz_ = r_;
+        }
+        // fused products where launches dominate (small systems), separate updates where the
+        // fused products' second gather costs more than the update kernels; the fused kernels
+        // need layouts without a tail
+        const int64_t form = option(AFSAI_OPT_PCG_FORM);
+        int nmax = 0;
+        for (int k = 0; k < nsys_; ++k) nmax = std::max(nmax, row0_[k + 1] - row0_[k]);
+        const bool want_fused = form == 2 || (form == 0 && nmax < kFusedMaxRows);
+        fused_ = P_ && use_sell_ && want_fused && !As_.tail && !P_->sg.tail;
+        if (!fused_)
+            hipLaunchKernelGGL(k_update_p, gv, dim3(kThreads), 0, s_, n, p_, zz_, sc_, 1, bm_.vec.mp, bm_.sy,
+                               di_.num_xcds);
+        mark0_ = prof_mark();
+        prev_it_.assign(nsys_, 0);
+        prev_rr_.assign(nsys_, 0.0);
+        rate_.assign(nsys_, 0.0);
+        tol_.assign(nsys_, 0.0);
+        have_prev_.assign(nsys_, 0);
+        // the state after the start (a chunk of no iterations) and a first chunk in flight
+        // before any state is read
+        if ((rc = enqueue_chunk(0))) return rc;
+        if ((rc = enqueue_chunk(4))) return rc;
+        return AFSAI_OK;
     }
-    struct SellGuard {
-        Sell *S;
-        hipStream_t s;
-        ~SellGuard() {
-            (void)hipStreamSynchronize(s);
-            sell_free(S);
-        }
-    } sell_guard{&As, s};
-    const Csr Am = csr_of(A);
-    // products inside the iteration stop with their system (gate); the first and the final
-    // A x run for every system
-    auto spmv_A = [&](const char *name, const double *xin, double *yout, const double *w, int fin, bool gate) {
-        PcgScalars *g = gate ? sc : nullptr;
-        if (use_sell) sell_spmv(name, As, bm, xin, yout, w, w ? partials : nullptr, g, fin, di, s);
-        else spmv(name, Am, xin, yout, w, w ? partials : nullptr, g, fin, di, s);
-    };
-    const dim3 gv(bm.vec.nblocks), gs(bm.nsys);
 
-    const int plain = P ? 0 : 1;
-    hipLaunchKernelGGL(k_set_scalars, dim3((nsys + 255) / 256), dim3(256), 0, s, sc, nsys, rtol, maxit, plain);
-    // r0 = b - A x0
-    spmv_A("spmv_A", x, q, nullptr, FIN_NONE, false);
-    hipLaunchKernelGGL(k_init_residual, gv, dim3(kThreads), 0, s, n, b, q, r, partials, bm.vec.mp, bm.sy,
-                       di.num_xcds);
-    hipLaunchKernelGGL(k_finalize, gs, dim3(kThreads), 0, s, partials, bm.vec.nblocks, bm.vec.mp, (int)FIN_INIT, sc);
-    // z0 = M^-1 r0, rho0 = r0.z0, p0 = z0
-    const double *zz = z;
-    if (P) {
-        sell_spmv("spmv_G", P->sg, bm, r, t, nullptr, nullptr, sc, FIN_NONE, di, s);
-        sell_spmv("spmv_GT_dot", P->sgt, bm, t, z, r, partials, sc, FIN_RHO0, di, s);
-    } else {
-        zz = r;
-    }
-    // fused products where launches dominate (small systems), separate updates where the
-    // fused products' second gather costs more than the update kernels; the fused kernels
-    // need layouts without a tail
-    const int64_t form = option(AFSAI_OPT_PCG_FORM);
-    int nmax = 0;
-    for (int k = 0; k < nsys; ++k) nmax = std::max(nmax, row0[k + 1] - row0[k]);
-    const bool want_fused = form == 2 || (form == 0 && nmax < kFusedMaxRows);
-    const bool fused = P && use_sell && want_fused && !As.tail && !P->sg.tail;
-    if (!fused)
-        hipLaunchKernelGGL(k_update_p, gv, dim3(kThreads), 0, s, n, p, zz, sc, 1, bm.vec.mp, bm.sy, di.num_xcds);
-    int iter_no = 0;  // iterations enqueued so far
-
-    // timer marks: after the update of each iteration (launches past the last iteration that
-    // ran are dropped from the kernel timer at the end)
-    std::vector<int> marks;
-    const int mark0 = prof_mark();
-    auto enqueue_iteration = [&]() {
-        if (fused) {
-            // p and r are double-buffered: the products read neighbours' old entries while
-            // owners store the new ones
-            const bool odd = (iter_no & 1) == 0;  // iteration 1, 3, ...: p -> p2, r -> r2
-            double *p_old = odd ? p : p2, *p_new = odd ? p2 : p;
-            double *r_old = odd ? r : r2, *r_new = odd ? r2 : r;
-            sell_fused<FUSE_AP>("spmv_A_dot", As, bm, z, p_old, p_new, nullptr, nullptr, q, partials, sc,
-                                iter_no == 0 ? 1 : 0, FIN_ALPHA, di, s);
-            sell_fused<FUSE_GR>("spmv_G_upd", P->sg, bm, r_old, q, r_new, x, p_new, t, partials, sc, 0, FIN_UPDATE,
-                                di, s);
-            marks.push_back(prof_mark());
-            sell_spmv("spmv_GT_dot", P->sgt, bm, t, z, r_new, partials, sc, FIN_BETA, di, s);
-            ++iter_no;
-            return;
+    // Returns AFSAI_OK and sets *finished; with block == false returns at once (finished
+    // false) when the oldest chunk in flight has not completed.
+    int advance(bool block, bool *finished) {
+        *finished = false;
+        if (done_) {
+            *finished = true;
+            return AFSAI_OK;
         }
-        spmv_A("spmv_A_dot", p, q, p, FIN_ALPHA, true);
-        {
-            ProfScope ps("update_xr", s);
-            hipLaunchKernelGGL(k_update_xr, gv, dim3(kThreads), 0, s, n, x, r, p, q, partials, sc, bm.vec.mp, bm.sy,
-                               di.num_xcds);
+        const int slot = (c_ - 2) & 1;  // state after the oldest chunk in flight
+        if (!block) {
+            const hipError_t q = hipEventQuery(ev_[slot]);
+            if (q == hipErrorNotReady) return AFSAI_OK;
+            if (q != hipSuccess) AFSAI_HIP_TRY(q);
+        } else {
+            AFSAI_HIP_TRY(hipEventSynchronize(ev_[slot]));
         }
-        hipLaunchKernelGGL(k_finalize, gs, dim3(kThreads), 0, s, partials, bm.vec.nblocks, bm.vec.mp,
-                           (int)FIN_UPDATE, sc);
-        marks.push_back(prof_mark());
-        if (P) {
-            sell_spmv("spmv_G", P->sg, bm, r, t, nullptr, nullptr, sc, FIN_NONE, di, s);
-            sell_spmv("spmv_GT_dot", P->sgt, bm, t, z, r, partials, sc, FIN_BETA, di, s);
-        }
-        {
-            ProfScope ps("update_p", s);
-            hipLaunchKernelGGL(k_update_p, gv, dim3(kThreads), 0, s, n, p, zz, sc, 0, bm.vec.mp, bm.sy, di.num_xcds);
-        }
-        ++iter_no;
-    };
-
-    // Chunks of iterations; the state after chunk c is read while chunk c+1 is already queued.
-    // Chunk sizes follow the observed residual reduction rate of the slowest system so that
-    // few iterations are queued past convergence (those return at once on the device flags).
-    hipEvent_t ev[2];
-    AFSAI_HIP_TRY(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
-    AFSAI_HIP_TRY(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
-    PcgScalars *hs[2] = {hsc, hsc + nsys};
-    const size_t scbytes = sizeof(PcgScalars) * (size_t)nsys;
-    AFSAI_HIP_TRY(hipMemcpyAsync(hs[1], sc, scbytes, hipMemcpyDeviceToHost, s));
-    AFSAI_HIP_TRY(hipEventRecord(ev[1], s));
-    int enqueued = 0, c = 0, chunk = 4;
-    bool finished = false;
-    std::vector<int> prev_it(nsys, 0);
-    std::vector<double> prev_rr(nsys, 0.0), rate(nsys, 0.0);
-    std::vector<char> have_prev(nsys, 0);
-    while (!finished) {
-        int todo = chunk;
-        {
-            // iterations the slowest active system still needs, from its observed rate
-            int need_max = -1;
-            const PcgScalars *st = hs[(c + 1) & 1];
-            for (int k = 0; k < nsys; ++k) {
-                if (st[k].done != DONE_NO) continue;
-                if (!(rate[k] < 0.0 && have_prev[k])) {
-                    need_max = -1;
-                    break;
-                }
-                const double tol2 = st[k].tol * st[k].tol;
-                const double need_it = std::ceil(std::log(tol2 / prev_rr[k]) / rate[k]);
-                need_max = std::max(need_max, (int)need_it - (enqueued - prev_it[k]) + 1);
-            }
-            if (need_max >= 0 && c > 0) todo = need_max < 1 ? 1 : (need_max > 64 ? 64 : need_max);
-        }
-        if (todo > maxit - enqueued) todo = maxit - enqueued;
-        for (int k = 0; k < todo; ++k) enqueue_iteration();
-        enqueued += todo;
-        AFSAI_HIP_TRY(hipMemcpyAsync(hs[c & 1], sc, scbytes, hipMemcpyDeviceToHost, s));
-        AFSAI_HIP_TRY(hipEventRecord(ev[c & 1], s));
-        // state after the previous chunk
-        AFSAI_HIP_TRY(hipEventSynchronize(ev[(c + 1) & 1]));
-        const PcgScalars *st = hs[(c + 1) & 1];
+        const PcgScalars *st = hs_[slot];
         bool all_done = true;
-        for (int k = 0; k < nsys; ++k) {
+        for (int k = 0; k < nsys_; ++k) {
             if (st[k].done != DONE_NO) continue;
             all_done = false;
-            if (have_prev[k] && st[k].it > prev_it[k] && st[k].rr > 0.0 && prev_rr[k] > 0.0) {
-                const double rt = std::log(st[k].rr / prev_rr[k]) / (st[k].it - prev_it[k]);
-                if (rt < 0.0) rate[k] = rt;
+            tol_[k] = st[k].tol;
+            if (have_prev_[k] && st[k].it > prev_it_[k] && st[k].rr > 0.0 && prev_rr_[k] > 0.0) {
+                const double rt = std::log(st[k].rr / prev_rr_[k]) / (st[k].it - prev_it_[k]);
+                if (rt < 0.0) rate_[k] = rt;
             }
             if (st[k].rr > 0.0) {
-                prev_rr[k] = st[k].rr;
-                prev_it[k] = st[k].it;
-                have_prev[k] = 1;
+                prev_rr_[k] = st[k].rr;
+                prev_it_[k] = st[k].it;
+                have_prev_[k] = 1;
             }
         }
-        if (all_done) finished = true;
-        if (todo == 0) {
-            AFSAI_HIP_TRY(hipEventSynchronize(ev[c & 1]));
-            finished = true;
+        if (all_done || enqueued_ >= maxit_) {
+            done_ = true;
+            *finished = true;
+            return AFSAI_OK;
         }
-        ++c;
-        if (chunk < 64) chunk *= 2;
-    }
-    AFSAI_HIP_TRY(hipStreamSynchronize(s));
-    std::vector<PcgScalars> fin_s(nsys);
-    AFSAI_HIP_TRY(hipMemcpy(fin_s.data(), sc, scbytes, hipMemcpyDeviceToHost));
-    int it_max = 0;
-    for (int k = 0; k < nsys; ++k) it_max = std::max(it_max, (int)fin_s[k].it);
-    {
-        const int keep_to = it_max >= 1 && it_max <= (int)marks.size() ? marks[it_max - 1] : mark0;
-        prof_drop(keep_to, prof_mark());
+        // iterations the slowest active system still needs, from its observed rate
+        int todo = chunk_;
+        int need_max = -1;
+        for (int k = 0; k < nsys_; ++k) {
+            if (st[k].done != DONE_NO) continue;
+            if (!(rate_[k] < 0.0 && have_prev_[k])) {
+                need_max = -1;
+                break;
+            }
+            const double need_it = std::ceil(std::log(tol_[k] * tol_[k] / prev_rr_[k]) / rate_[k]);
+            need_max = std::max(need_max, (int)need_it - (enqueued_ - prev_it_[k]) + 1);
+        }
+        if (need_max >= 0) todo = need_max < 1 ? 1 : (need_max > 64 ? 64 : need_max);
+        if (chunk_ < 64) chunk_ *= 2;
+        return enqueue_chunk(todo);
     }
 
-    hipLaunchKernelGGL(k_zero_rhs, gv, dim3(kThreads), 0, s, n, x, sc, bm.vec.mp, bm.sy, di.num_xcds);
-    // true residuals ||b - A x||
-    spmv_A("spmv_A", x, q, nullptr, FIN_NONE, false);
-    hipLaunchKernelGGL(k_resid_norm, gv, dim3(kThreads), 0, s, n, b, q, partials, bm.vec.mp, bm.sy, di.num_xcds);
-    hipLaunchKernelGGL(k_finalize, gs, dim3(kThreads), 0, s, partials, bm.vec.nblocks, bm.vec.mp, (int)FIN_RESID, sc);
-    AFSAI_HIP_TRY(hipMemcpyAsync(hs[0], sc, scbytes, hipMemcpyDeviceToHost, s));
-    AFSAI_HIP_TRY(hipEventRecord(t1, s));
-    AFSAI_HIP_TRY(hipStreamSynchronize(s));
-    AFSAI_HIP_TRY(hipGetLastError());
-    float ms = 0.f;
-    AFSAI_HIP_TRY(hipEventElapsedTime(&ms, t0, t1));
-    prof_flush();
-    int status = AFSAI_OK;
-    for (int k = 0; k < nsys && status == AFSAI_OK; ++k) {
-        const PcgScalars &f = fin_s[k];
-        if (f.done == DONE_NOT_SPD) {
-            if (nsys == 1)
-                set_error("pcg_solve: p.Ap <= 0 at iteration %d (matrix or preconditioner not SPD)", f.it + 1);
-            else
-                set_error("pcg_solve_batched: system %d: p.Ap <= 0 at iteration %d (not SPD)", k, f.it + 1);
-            status = AFSAI_ERR_NOT_SPD;
-        } else if (f.done == DONE_MAXIT || (f.done == DONE_NO && maxit == 0)) {
-            if (nsys == 1) set_error("pcg_solve: not converged in %d iterations", f.it);
-            else set_error("pcg_solve_batched: system %d not converged in %d iterations", k, f.it);
-            status = AFSAI_ERR_NOT_CONVERGED;
+    int finish(afsai_pcg_info *info) {
+        const int n = A_.n;
+        AFSAI_HIP_TRY(hipStreamSynchronize(s_));
+        std::vector<PcgScalars> fin_s(nsys_);
+        const size_t scbytes = sizeof(PcgScalars) * (size_t)nsys_;
+        AFSAI_HIP_TRY(hipMemcpyAsync(fin_s.data(), sc_, scbytes, hipMemcpyDeviceToHost, s_));
+        AFSAI_HIP_TRY(hipStreamSynchronize(s_));
+        int it_max = 0;
+        for (int k = 0; k < nsys_; ++k) it_max = std::max(it_max, (int)fin_s[k].it);
+        {
+            const int keep_to = it_max >= 1 && it_max <= (int)marks_.size() ? marks_[it_max - 1] : mark0_;
+            prof_drop(keep_to, prof_mark());
         }
-    }
-    if (info) {
-        for (int k = 0; k < nsys; ++k) {
+        const dim3 gv(bm_.vec.nblocks), gs(bm_.nsys);
+        hipLaunchKernelGGL(k_zero_rhs, gv, dim3(kThreads), 0, s_, n, x_, sc_, bm_.vec.mp, bm_.sy, di_.num_xcds);
+        // true residuals ||b - A x||
+        spmv_A("spmv_A", x_, q_, nullptr, FIN_NONE, false);
+        hipLaunchKernelGGL(k_resid_norm, gv, dim3(kThreads), 0, s_, n, b_, q_, partials_, bm_.vec.mp, bm_.sy,
+                           di_.num_xcds);
+        hipLaunchKernelGGL(k_finalize, gs, dim3(kThreads), 0, s_, partials_, bm_.vec.nblocks, bm_.vec.mp,
+                           (int)FIN_RESID, sc_);
+        AFSAI_HIP_TRY(hipMemcpyAsync(hs_[0], sc_, scbytes, hipMemcpyDeviceToHost, s_));
+        AFSAI_HIP_TRY(hipEventRecord(t1_, s_));
+        AFSAI_HIP_TRY(hipStreamSynchronize(s_));
+        AFSAI_HIP_TRY(hipGetLastError());
+        float ms = 0.f;
+        AFSAI_HIP_TRY(hipEventElapsedTime(&ms, t0_, t1_));
+        prof_flush();
+        int status = AFSAI_OK;
+        for (int k = 0; k < nsys_ && status == AFSAI_OK; ++k) {
             const PcgScalars &f = fin_s[k];
-            const double nb = sqrt(f.bb);
-            info[k].iters = f.it;
-            info[k].converged = (f.done == DONE_CONVERGED || f.done == DONE_ZERO_RHS) ? 1 : 0;
-            info[k].relres = nb > 0 ? sqrt(f.rr) / nb : 0.0;
-            info[k].true_relres = (nb > 0 && f.done != DONE_ZERO_RHS) ? sqrt(hs[0][k].resid) / nb : 0.0;
-            info[k].ms = ms;
+            if (f.done == DONE_NOT_SPD) {
+                if (nsys_ == 1)
+                    set_error("pcg_solve: p.Ap <= 0 at iteration %d (matrix or preconditioner not SPD)", f.it + 1);
+                else
+                    set_error("pcg_solve_batched: system %d: p.Ap <= 0 at iteration %d (not SPD)", k, f.it + 1);
+                status = AFSAI_ERR_NOT_SPD;
+            } else if (f.done == DONE_MAXIT || f.done == DONE_NO) {
+                if (nsys_ == 1) set_error("pcg_solve: not converged in %d iterations", f.it);
+                else set_error("pcg_solve_batched: system %d not converged in %d iterations", k, f.it);
+                status = AFSAI_ERR_NOT_CONVERGED;
+            }
         }
+        if (info) {
+            for (int k = 0; k < nsys_; ++k) {
+                const PcgScalars &f = fin_s[k];
+                const double nb = sqrt(f.bb);
+                info[k].iters = f.it;
+                info[k].converged = (f.done == DONE_CONVERGED || f.done == DONE_ZERO_RHS) ? 1 : 0;
+                info[k].relres = nb > 0 ? sqrt(f.rr) / nb : 0.0;
+                info[k].true_relres = (nb > 0 && f.done != DONE_ZERO_RHS) ? sqrt(hs_[0][k].resid) / nb : 0.0;
+                info[k].ms = ms;
+            }
+        }
+        return status;
     }
-    (void)hipEventDestroy(ev[0]);
-    (void)hipEventDestroy(ev[1]);
-    (void)hipEventDestroy(t0);
-    (void)hipEventDestroy(t1);
-    return status;
+
+  private:
+    // products inside the iteration stop with their system (gate); the first and the final
+    // A x run for every system
+    void spmv_A(const char *name, const double *xin, double *yout, const double *w, int fin, bool gate) {
+        PcgScalars *g = gate ? sc_ : nullptr;
+        if (use_sell_) sell_spmv(name, As_, bm_, xin, yout, w, w ? partials_ : nullptr, g, fin, di_, s_);
+        else spmv(name, csr_of(&A_), xin, yout, w, w ? partials_ : nullptr, g, fin, di_, s_);
+    }
+
+    void enqueue_iteration() {
+        const int n = A_.n;
+        const dim3 gv(bm_.vec.nblocks), gs(bm_.nsys);
+        if (fused_) {
+            // p and r are double-buffered: the products read neighbours' old entries while
+            // owners store the new ones
+            const bool odd = (iter_no_ & 1) == 0;  // iteration 1, 3, ...: p -> p2, r -> r2
+            double *p_old = odd ? p_ : p2_, *p_new = odd ? p2_ : p_;
+            double *r_old = odd ? r_ : r2_, *r_new = odd ? r2_ : r_;
+            sell_fused<FUSE_AP>("spmv_A_dot", As_, bm_, z_, p_old, p_new, nullptr, nullptr, q_, partials_, sc_,
+                                iter_no_ == 0 ? 1 : 0, FIN_ALPHA, di_, s_);
+            sell_fused<FUSE_GR>("spmv_G_upd", P_->sg, bm_, r_old, q_, r_new, x_, p_new, t_, partials_, sc_, 0,
+                                FIN_UPDATE, di_, s_);
+            marks_.push_back(prof_mark());
+            sell_spmv("spmv_GT_dot", P_->sgt, bm_, t_, z_, r_new, partials_, sc_, FIN_BETA, di_, s_);
+            ++iter_no_;
+            return;
+        }
+        spmv_A("spmv_A_dot", p_, q_, p_, FIN_ALPHA, true);
+        {
+            ProfScope ps("update_xr", s_);
+            hipLaunchKernelGGL(k_update_xr, gv, dim3(kThreads), 0, s_, n, x_, r_, p_, q_, partials_, sc_, bm_.vec.mp,
+                               bm_.sy, di_.num_xcds);
+        }
+        hipLaunchKernelGGL(k_finalize, gs, dim3(kThreads), 0, s_, partials_, bm_.vec.nblocks, bm_.vec.mp,
+                           (int)FIN_UPDATE, sc_);
+        marks_.push_back(prof_mark());
+        if (P_) {
+            sell_spmv("spmv_G", P_->sg, bm_, r_, t_, nullptr, nullptr, sc_, FIN_NONE, di_, s_);
+            sell_spmv("spmv_GT_dot", P_->sgt, bm_, t_, z_, r_, partials_, sc_, FIN_BETA, di_, s_);
+        }
+        {
+            ProfScope ps("update_p", s_);
+            hipLaunchKernelGGL(k_update_p, gv, dim3(kThreads), 0, s_, n, p_, zz_, sc_, 0, bm_.vec.mp, bm_.sy,
+                               di_.num_xcds);
+        }
+        ++iter_no_;
+    }
+
+    // todo iterations (at most what maxit leaves), then a copy of the scalars into the host
+    // slot of this chunk and its event
+    int enqueue_chunk(int todo) {
+        if (todo > maxit_ - enqueued_) todo = maxit_ - enqueued_;
+        for (int k = 0; k < todo; ++k) enqueue_iteration();
+        enqueued_ += todo;
+        const int slot = c_ & 1;
+        AFSAI_HIP_TRY(hipMemcpyAsync(hs_[slot], sc_, sizeof(PcgScalars) * (size_t)nsys_, hipMemcpyDeviceToHost, s_));
+        AFSAI_HIP_TRY(hipEventRecord(ev_[slot], s_));
+        ++c_;
+        return AFSAI_OK;
+    }
+
+    const afsai_csr A_;
+    afsai_precond P_;
+    int nsys_;
+    std::vector<int32_t> row0_;
+    const double *b_;
+    double *x_;
+    double rtol_;
+    int32_t maxit_;
+    hipStream_t s_;
+    DeviceInfo di_;
+    BatchMaps bm_;
+    DevBuf own_;
+    Sell As_;
+    bool use_sell_ = true, fused_ = false, started_ = false, done_ = false;
+    double *r_ = nullptr, *r2_ = nullptr, *z_ = nullptr, *p_ = nullptr, *p2_ = nullptr, *q_ = nullptr, *t_ = nullptr;
+    const double *zz_ = nullptr;
+    double *partials_ = nullptr;
+    PcgScalars *sc_ = nullptr;
+    PcgScalars *hsc_ = nullptr;
+    PcgScalars *hs_[2] = {nullptr, nullptr};
+    hipEvent_t t0_ = nullptr, t1_ = nullptr, ev_[2] = {nullptr, nullptr};
+    int iter_no_ = 0, enqueued_ = 0, c_ = 0, chunk_ = 8, mark0_ = 0;
+    std::vector<int> marks_, prev_it_;
+    std::vector<double> prev_rr_, rate_, tol_;
+    std::vector<char> have_prev_;
+};
+
+struct PcgTask {
+    PcgRun run;
+    PcgTask(const afsai_csr &A, afsai_precond P, const double *b, double *x, double rtol, int32_t maxit,
+            hipStream_t s)
+        : run(A, P, 1, nullptr, b, x, rtol, maxit, s) {}
+};
+
+int pcg_task_begin(const afsai_csr &A, afsai_precond P, const double *b, double *x, double rtol, int32_t maxit,
+                   hipStream_t stream, PcgTask **out) {
+    *out = nullptr;
+    PcgTask *t = new PcgTask(A, P, b, x, rtol, maxit, stream);
+    const int rc = t->run.begin();
+    if (rc) {
+        delete t;
+        return rc;
+    }
+    *out = t;
+    return AFSAI_OK;
+}
+int pcg_task_advance(PcgTask *t, bool block, bool *finished) { return t->run.advance(block, finished); }
+int pcg_task_finish(PcgTask *t, afsai_pcg_info *info) { return t->run.finish(info); }
+void pcg_task_free(PcgTask *t) { delete t; }
+
+static int pcg_batch(const afsai_csr *A, afsai_precond P, int nsys, const int32_t *row0, const double *b, double *x,
+                     double rtol, int32_t maxit, hipStream_t s, afsai_pcg_info *info) {
+    PcgRun run(*A, P, nsys, row0, b, x, rtol, maxit, s);
+    int rc = run.begin();
+    if (rc) return rc;
+    bool fin = false;
+    while (!fin)
+        if ((rc = run.advance(true, &fin))) return rc;
+    return run.finish(info);
 }
 
 }  // namespace afsai
