@@ -14,6 +14,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -95,6 +96,99 @@ def batch_bench(args):
            "setup_ms": round(sinfo.ms, 3), "pcg_ms": round(infos[0].ms, 3), "iters_min": int(its.min()),
            "iters_max": int(its.max()), "worst_true_relres": worst, "plain_one_by_one_s": round(plain, 4),
            "speedup_vs_plain": round(plain / sec, 2), "roofline": None, "kernels": kern, "cpu_baseline": None}
+    print(json.dumps(out), flush=True)
+
+
+def serve_bench(args):
+    """Serving form: Poisson arrivals of SPD systems, n log-uniform in [1e4, 2e6], half 7-point
+    (log-normal sigma = 1 cell coefficients, k_max = 5, s = 1), half 27-point 3-dof (the C2
+    construction, k_max = 10, s = 2), FP32 G, FP64 PCG to rtol 1e-8, x0 = 0.  Matrices come from
+    a seeded pool of distinct systems; every request gets its own right-hand side b = A x with
+    x ~ U(-1, 1).  The plain form serves one request at a time in arrival order (one slot);
+    continuous batching admits up to 16 requests by memory.  Loads are 0.5 and 0.8 of the plain
+    form's saturation throughput."""
+    import torch
+
+    import paper_2010_14175_amd as af
+    import synth
+
+    nreq, npool = args.requests, args.pool
+    u = synth.uniform(4, 40, 3 * npool, 0.0, 1.0).reshape(npool, 3)
+    pool = []
+    for k in range(npool):
+        n_want = math.exp(math.log(1e4) + u[k, 0] * (math.log(2e6) - math.log(1e4)))
+        if u[k, 1] < 0.5:
+            N = max(4, round(n_want ** (1 / 3)))
+            A = synth.lap7_lognormal(N, N, N, 1.0, 100 + k)
+            kind, kmax, s = "7pt", 5, 1
+        else:
+            N = max(3, round((n_want / 3) ** (1 / 3)))
+            A = synth.elast27(N, 1.0, 200 + k)
+            kind, kmax, s = "27pt", 10, 2
+        pool.append((kind, kmax, s, af.DeviceCSR.from_host(A), A.n))
+    print(f"[bench] serve: pool of {npool} systems, n = {sorted(p[4] for p in pool)}", file=sys.stderr, flush=True)
+    pick = (synth.uniform(4, 41, nreq, 0.0, 1.0) * npool).astype(np.int64) % npool
+    # right-hand sides on the device: b = A x, x ~ U(-1, 1) seeded per request
+    gen = torch.Generator(device="cuda")
+    bs = []
+    for q in range(nreq):
+        dA = pool[pick[q]][3]
+        gen.manual_seed(1000 + q)
+        xq = torch.rand(dA.n, dtype=torch.float64, device="cuda", generator=gen) * 2 - 1
+        bs.append(af.spmv(dA, xq))
+    torch.cuda.synchronize()
+
+    def run(slots, arrivals):
+        """Serves the requests arriving at `arrivals` (s) with `slots` slots; latency = completion
+        minus arrival."""
+        srv = af.Server(args.budget_gb * 2**30, slots, 5, 1, 1e-2, rtol=1e-8, g_prec=af.F32,
+                        setup_threads=4 if slots > 1 else 1)
+        xs = [torch.empty_like(b) for b in bs]
+        t0 = time.perf_counter()
+        sub, lat, bad = {}, [], 0
+        q = done = 0
+        while done < nreq:
+            while q < nreq and arrivals[q] <= time.perf_counter() - t0:
+                _, kmax, s_, dA, _ = pool[pick[q]]
+                t = srv.submit(dA, bs[q], xs[q], kmax=kmax, s=s_)
+                sub[t] = (arrivals[q], time.perf_counter() - t0)
+                q += 1
+            for r in srv.poll(wait_ms=0):
+                arr, ts = sub.pop(r.ticket)
+                lat.append((r.done_ms - r.submit_ms) / 1e3 + (ts - arr))
+                bad += int(r.status != af.OK or not r.converged)
+                done += 1
+            if q < nreq:
+                time.sleep(max(0.0, min(0.002, arrivals[q] - (time.perf_counter() - t0))))
+            elif done < nreq:
+                time.sleep(0.0005)
+        span = time.perf_counter() - t0
+        srv.close()
+        return np.array(lat), span, bad
+
+    # saturation throughput of the plain form: every request present at t = 0
+    _, span0, bad0 = run(1, np.zeros(nreq))
+    sat = nreq / span0
+    print(f"[bench] plain saturation: {sat:.2f} solves/s ({span0:.1f} s for {nreq})", file=sys.stderr, flush=True)
+    res = {"plain_saturation_solves_per_s": round(sat, 3)}
+    rng_u = synth.uniform(4, 42, nreq, 1e-12, 1.0)
+    for load in (0.5, 0.8):
+        qps = load * sat
+        arrivals = np.cumsum(-np.log(rng_u) / qps)
+        for name, slots in (("plain_fifo", 1), ("continuous", 16)):
+            lat, span, bad = run(slots, arrivals)
+            key = f"{name}@{load}"
+            res[key] = {"qps": round(qps, 3), "p50_s": round(float(np.percentile(lat, 50)), 4),
+                        "p99_s": round(float(np.percentile(lat, 99)), 4), "solves_per_s": round(nreq / span, 3),
+                        "failed": bad}
+            print(f"[bench] {key}: p50 {res[key]['p50_s']} s, p99 {res[key]['p99_s']} s, "
+                  f"{res[key]['solves_per_s']} solves/s", file=sys.stderr, flush=True)
+    out = {"metric": METRIC, "value": res["continuous@0.8"]["p99_s"], "unit": "s (p99 latency, continuous, 0.8 load)",
+           "n_gpus": 1, "steps": nreq, "warmup": 0, "higher_is_better": False, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64 (G stored f32)", "data": "synthetic",
+           "config": {"workload": "serve", "requests": nreq, "pool": npool, "n_range": [1e4, 2e6],
+                      "budget_gb": args.budget_gb},
+           "serving": res, "roofline": None, "cpu_baseline": None}
     print(json.dumps(out), flush=True)
 
 
@@ -200,7 +294,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="elast27_64", choices=sorted(list(workloads()) + list(BATCH_WORKLOADS)))
+    ap.add_argument("--workload", default="elast27_64",
+                    choices=sorted(list(workloads()) + list(BATCH_WORKLOADS) + ["serve"]))
+    ap.add_argument("--requests", type=int, default=300, help="serve: number of requests")
+    ap.add_argument("--pool", type=int, default=16, help="serve: distinct systems the requests draw from")
+    ap.add_argument("--budget-gb", type=int, default=96, help="serve: device memory budget of the servers")
     ap.add_argument("--g-prec", default="f64", choices=["f64", "f32"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=0)
@@ -227,6 +325,9 @@ def main():
 
     if args.workload in BATCH_WORKLOADS:
         batch_bench(args)
+        return
+    if args.workload == "serve":
+        serve_bench(args)
         return
     pb = workloads()[args.workload]()
     g_prec = af.F32 if args.g_prec == "f32" else af.F64

@@ -219,10 +219,12 @@ int afsai_server_create(const afsai_server_config *cfg, afsai_server *out);
 
 /*
  * afsai_server_submit -- queues the solve of A x = b (A, b, x device arrays; A's arrays, b and
- *   x must stay valid and untouched until the request's result has been polled).  x is set to
- *   0 before the solve.  Returns AFSAI_ERR_TOO_LARGE when the request alone exceeds the budget.
+ *   x must stay valid and untouched until the request's result has been polled).  p (host) are
+ *   this request's setup parameters (NULL: the server's).  x is set to 0 before the solve.
+ *   Returns AFSAI_ERR_TOO_LARGE when the request alone exceeds the budget.
  */
-int afsai_server_submit(afsai_server S, const afsai_csr *A, const double *b, double *x, int64_t *ticket);
+int afsai_server_submit(afsai_server S, const afsai_csr *A, const afsai_params *p, const double *b, double *x,
+                        int64_t *ticket);
 
 /*
  * afsai_server_poll -- moves up to max_results finished requests (in completion order) into out

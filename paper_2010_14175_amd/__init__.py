@@ -104,7 +104,7 @@ def lib():
         L.pcg_solve.argtypes = [P(CsrStruct), vp, vp, vp, ctypes.c_double, i32, vp, P(PcgInfoStruct)]
         L.afsai_spmv.argtypes = [P(CsrStruct), vp, vp, vp]
         L.afsai_server_create.argtypes = [P(ServerConfigStruct), P(vp)]
-        L.afsai_server_submit.argtypes = [vp, P(CsrStruct), vp, vp, P(ctypes.c_int64)]
+        L.afsai_server_submit.argtypes = [vp, P(CsrStruct), P(ParamsStruct), vp, vp, P(ctypes.c_int64)]
         L.afsai_server_poll.argtypes = [vp, P(RequestResultStruct), i32, P(i32), i32]
         L.afsai_server_pending.argtypes = [vp, P(ctypes.c_int64), P(ctypes.c_int64), P(i32)]
         L.afsai_server_destroy.argtypes = [vp]
@@ -364,13 +364,22 @@ class Server:
         h = ctypes.c_void_p()
         _check(lib().afsai_server_create(ctypes.byref(cfg), ctypes.byref(h)), "afsai_server_create")
         self._h = h
+        self._params = cfg.params
         self._keep = {}  # ticket -> (A, b, x) kept alive until the result is polled
 
-    def submit(self, A: DeviceCSR, b, x) -> int:
-        """Queues A x = b (device data; x is overwritten).  Returns the request's ticket."""
+    def submit(self, A: DeviceCSR, b, x, kmax: int | None = None, s: int | None = None, eps: float | None = None,
+               g_prec: int | None = None) -> int:
+        """Queues A x = b (device data; x is overwritten), with the server's setup parameters or the
+        ones given here.  Returns the request's ticket."""
         t = ctypes.c_int64()
         st = A.struct
-        _check(lib().afsai_server_submit(self._h, ctypes.byref(st), _ptr(b), _ptr(x), ctypes.byref(t)),
+        p = None
+        if kmax is not None or s is not None or eps is not None or g_prec is not None:
+            d = self._params
+            p = ctypes.byref(ParamsStruct(d.kmax if kmax is None else int(kmax), d.s if s is None else int(s),
+                                          d.eps if eps is None else float(eps), d.tie_rtol,
+                                          d.g_prec if g_prec is None else int(g_prec), 0))
+        _check(lib().afsai_server_submit(self._h, ctypes.byref(st), p, _ptr(b), _ptr(x), ctypes.byref(t)),
                "afsai_server_submit")
         self._keep[t.value] = (A, b, x)
         return t.value

@@ -30,6 +30,7 @@ using Clock = std::chrono::steady_clock;
 struct Request {
     int64_t ticket = 0;
     afsai_csr A{};
+    afsai_params params{};
     const double *b = nullptr;
     double *x = nullptr;
     size_t footprint = 0;
@@ -143,7 +144,7 @@ struct afsai_server_s {
             }
             if (rc == AFSAI_OK && hipMemsetAsync(r->x, 0, sizeof(double) * (size_t)r->A.n, r->stream) != hipSuccess)
                 rc = AFSAI_ERR_HIP;
-            if (rc == AFSAI_OK) rc = afsai_setup(&r->A, &cfg.params, r->stream, &r->P);
+            if (rc == AFSAI_OK) rc = afsai_setup(&r->A, &r->params, r->stream, &r->P);
             r->t_setup = now();
             if (rc != AFSAI_OK) {
                 r->status = rc;
@@ -205,6 +206,8 @@ struct afsai_server_s {
     }
 };
 
+static bool params_ok(const afsai_params &p);
+
 extern "C" {
 
 int afsai_server_create(const afsai_server_config *cfg, afsai_server *out) {
@@ -215,11 +218,7 @@ int afsai_server_create(const afsai_server_config *cfg, afsai_server *out) {
         !(cfg->rtol > 0.0) || cfg->maxit < 0)
         AFSAI_FAIL(AFSAI_ERR_INVALID_ARG, "afsai_server_create: bad configuration (slots %d, setup threads %d)",
                    cfg->max_slots, cfg->setup_threads);
-    const afsai_params &p = cfg->params;
-    if (p.kmax < 0 || (p.kmax > 0 && p.s < 1) || 1 + (int64_t)p.kmax * (p.kmax > 0 ? p.s : 0) > 64 ||
-        !(p.eps >= 0.0) || !(p.tie_rtol >= 0.0 && p.tie_rtol < 1.0) ||
-        (p.g_prec != AFSAI_F64 && p.g_prec != AFSAI_F32))
-        AFSAI_FAIL(AFSAI_ERR_INVALID_ARG, "afsai_server_create: bad setup parameters");
+    if (!params_ok(cfg->params)) AFSAI_FAIL(AFSAI_ERR_INVALID_ARG, "afsai_server_create: bad setup parameters");
     afsai_server S = new afsai_server_s();
     S->cfg = *cfg;
     if (hipGetDevice(&S->device) != hipSuccess) {
@@ -233,16 +232,25 @@ int afsai_server_create(const afsai_server_config *cfg, afsai_server *out) {
     return AFSAI_OK;
 }
 
-int afsai_server_submit(afsai_server S, const afsai_csr *A, const double *b, double *x, int64_t *ticket) {
+static bool params_ok(const afsai_params &p) {
+    return !(p.kmax < 0 || (p.kmax > 0 && p.s < 1) || 1 + (int64_t)p.kmax * (p.kmax > 0 ? p.s : 0) > 64 ||
+             !(p.eps >= 0.0) || !(p.tie_rtol >= 0.0 && p.tie_rtol < 1.0) ||
+             (p.g_prec != AFSAI_F64 && p.g_prec != AFSAI_F32) || (p.flags & ~AFSAI_VALIDATE));
+}
+
+int afsai_server_submit(afsai_server S, const afsai_csr *A, const afsai_params *p, const double *b, double *x,
+                        int64_t *ticket) {
     clear_error();
     if (!S || !A || !b || !x || !ticket) AFSAI_FAIL(AFSAI_ERR_INVALID_ARG, "afsai_server_submit: null argument");
     if (A->n <= 0 || A->nnz < A->n || !A->row_ptr || !A->col_idx || !A->val)
         AFSAI_FAIL(AFSAI_ERR_INVALID_ARG, "afsai_server_submit: bad matrix (n = %d, nnz = %d)", A->n, A->nnz);
+    if (p && !params_ok(*p)) AFSAI_FAIL(AFSAI_ERR_INVALID_ARG, "afsai_server_submit: bad setup parameters");
     Request *r = new Request();
     r->A = *A;
+    r->params = p ? *p : S->cfg.params;
     r->b = b;
     r->x = x;
-    r->footprint = footprint(*A, S->cfg.params);
+    r->footprint = footprint(*A, r->params);
     if (r->footprint > S->cfg.hbm_budget) {
         const size_t fp = r->footprint;
         delete r;

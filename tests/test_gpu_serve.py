@@ -35,7 +35,8 @@ def _vec(x):
 
 
 def _requests():
-    """Mixed kinds and sizes: 7-point (plain, log-normal, anisotropic) and 27-point 3-dof."""
+    """Mixed kinds and sizes: 7-point (plain, log-normal, anisotropic; k_max = 5, s = 1) and
+    27-point 3-dof (k_max = 10, s = 2): each request carries its own setup parameters."""
     probs = [synth.poisson7(12), synth.elasticity27(6), synth.poisson7(7)]
     probs += synth.aniso_batch(nsys=5, seed=11, side_lo=5, side_hi=14)
     A = synth.lap7_lognormal(9, 8, 10, 1.0, 4)
@@ -50,7 +51,7 @@ def _serve(af, probs, budget, slots):
         dA = af.DeviceCSR.from_host(pb.A)
         b = _vec(pb.b)
         x = _vec(np.full(pb.n, 7.0))  # overwritten by the server
-        data.append((dA, b, x, srv.submit(dA, b, x)))
+        data.append((dA, b, x, srv.submit(dA, b, x, kmax=pb.kmax, s=pb.s)))
     results = {}
     while len(results) < len(probs):
         for r in srv.poll(wait_ms=1000):
@@ -61,7 +62,7 @@ def _serve(af, probs, budget, slots):
 
 def _alone(af, pb):
     dA = af.DeviceCSR.from_host(pb.A)
-    P = af.setup(dA, KMAX, S, EPS)
+    P = af.setup(dA, pb.kmax, pb.s, EPS)
     x, info = af.pcg_solve(dA, P, _vec(pb.b), rtol=1e-8)
     return x.cpu().numpy(), info
 
@@ -86,7 +87,7 @@ def test_admission_respects_budget_and_slots(af):
     for pb in probs:  # footprints as the server estimates them
         dA = af.DeviceCSR.from_host(pb.A)
         b, x = _vec(pb.b), _vec(np.zeros(pb.n))
-        srv.submit(dA, b, x)
+        srv.submit(dA, b, x, kmax=pb.kmax, s=pb.s)
     done = []
     while len(done) < len(probs):
         done += srv.poll(wait_ms=1000)
