@@ -224,7 +224,7 @@ def kernel_bytes(name: str, n: int, nnz_a: int, nnz_g: int, w_g: int, kmax: int,
     return table.get(name, float("nan"))
 
 
-def cpu_baseline(pb, iters_hint: int, threads: int) -> dict:
+def cpu_baseline(pb, iters_hint: int, threads: int, x_gpu=None) -> dict:
     import oracle
 
     t0 = time.perf_counter()
@@ -237,7 +237,9 @@ def cpu_baseline(pb, iters_hint: int, threads: int) -> dict:
             "sample": (f"whole workload: oracle setup of all {pb.n} rows ({t1 - t0:.2f} s, {threads} threads) + "
                        f"oracle PCG to rtol {pb.rtol:g} ({res.iters} iterations, {t2 - t1:.2f} s; "
                        f"GPU took {iters_hint})"),
-            "setup_s": round(t1 - t0, 3), "pcg_s": round(t2 - t1, 3), "iters": res.iters}
+            "setup_s": round(t1 - t0, 3), "pcg_s": round(t2 - t1, 3), "iters": res.iters,
+            "gpu_x_rel_err_vs_oracle": (float(np.linalg.norm(x_gpu - res.x) / np.linalg.norm(res.x))
+                                        if x_gpu is not None else None)}
 
 
 COPY_BYTES = 1 << 30
@@ -406,7 +408,7 @@ def main():
     if not args.no_cpu_baseline:
         threads = args.cpu_threads or int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or (os.cpu_count() or 1)
         print(f"[bench] cpu baseline: oracle on {threads} threads ...", file=sys.stderr, flush=True)
-        cpu = cpu_baseline(pb, its[-1], threads)
+        cpu = cpu_baseline(pb, its[-1], threads, x.cpu().numpy())
 
     out = {
         "metric": METRIC,

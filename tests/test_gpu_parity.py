@@ -419,3 +419,22 @@ def test_full_size_elasticity64_sampled(af):
     assert info.converged and info.true_relres <= 1.1e-8
     err = np.linalg.norm(x.cpu().numpy() - Pb.x_true) / np.linalg.norm(Pb.x_true)
     assert err < 1e-4
+
+
+def test_full_size_elasticity150_sampled(af):
+    """The largest configuration (150^3 nodes x 3 dof: 10,125,000 rows, 809,238,528 nonzeros,
+    log-normal sigma = 2, k_max = 15, s = 3, patterns of up to 46 entries) with G stored in FP32:
+    3,000 sampled rows against the oracle (pattern identical, values equal after rounding the
+    oracle's to FP32), and the solve by its true residual."""
+    import time
+
+    t0 = time.time()
+    Pb = synth.elasticity27(150, 2.0, 5, kmax=15, s=3)
+    rows = np.unique(np.concatenate([np.arange(0, 30), np.arange(Pb.n - 30, Pb.n),
+                                     synth.raw_u64(150, 5, 2940).astype(np.int64) % Pb.n])).astype(np.int32)
+    r = compare_factor(af, Pb.A, 15, 3, 1e-2, g_prec=1, rows=rows)
+    dA, P = r["dA"], r["P"]
+    x, info = af.pcg_solve(dA, P, _vec(Pb.b), rtol=1e-8)
+    assert info.converged and info.true_relres <= 1.1e-8
+    print(f"C5: setup {r['info'].ms:.0f} ms, nnz(G) {r['info'].nnz_g}, PCG {info.iters} iterations "
+          f"{info.ms:.0f} ms, test {time.time() - t0:.0f} s")
