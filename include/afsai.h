@@ -300,6 +300,11 @@ const char *afsai_last_error(void);
  *                             second, length-sorted layout multiplied first (0: split only
  *                             when padding would exceed a tenth of the entries, at the width
  *                             that minimises the work; products are identical either way)
+ *   AFSAI_OPT_PCG_GRAPH       0 (automatic) and 1: the kernels of each PCG iteration are
+ *                             enqueued one by one; 2: the iteration is captured once per solve
+ *                             into a HIP graph (once per buffer parity in the fused form) and
+ *                             replayed (never while the kernel timer is on). Results are
+ *                             identical.
  * Returns AFSAI_ERR_INVALID_ARG for an unknown option or value.  Not thread safe against
  * concurrent calls of the library.
  */
@@ -310,6 +315,7 @@ const char *afsai_last_error(void);
 #define AFSAI_OPT_PCG_CSR_A 5
 #define AFSAI_OPT_PCG_FORM 6
 #define AFSAI_OPT_SELL_WIDTH 7
+#define AFSAI_OPT_PCG_GRAPH 8
 int afsai_set_option(int32_t option, int64_t value);
 
 /*

@@ -36,7 +36,7 @@ void clear_error() { g_last_error.clear(); }
 
 static int64_t g_options[16] = {0};
 
-int64_t option(int id) { return (id > 0 && id < 8) ? g_options[id] : 0; }
+int64_t option(int id) { return (id > 0 && id < 16) ? g_options[id] : 0; }
 
 // ---------------------------------------------------------------------------------------
 // caching allocator
@@ -245,6 +245,7 @@ int afsai_set_option(int32_t opt, int64_t value) {
         case AFSAI_OPT_PCG_CSR_A: ok = (value == 0 || value == 1); break;
         case AFSAI_OPT_PCG_FORM: ok = (value >= 0 && value <= 2); break;
         case AFSAI_OPT_SELL_WIDTH: ok = (value >= 0 && value <= 4096); break;
+        case AFSAI_OPT_PCG_GRAPH: ok = (value >= 0 && value <= 2); break;
         default: ok = false;
     }
     if (!ok) AFSAI_FAIL(AFSAI_ERR_INVALID_ARG, "afsai_set_option: bad option %d / value %lld", opt, (long long)value);

@@ -31,11 +31,16 @@ namespace afsai {
 
 constexpr int kThreads = 256;
 constexpr int kFusedMaxRows = 200000;  // automatic PCG form: fused products below this size
+// resumable solver: iterations of the first chunk, least GPU time of a chunk and its share of
+// the GPU time so far
+constexpr int kFirstChunk = 4;
+constexpr double kMinChunkUs = 100.0;
+constexpr double kChunkShare = 0.125;
 
 enum : int { FIN_NONE = 0, FIN_ALPHA = 1, FIN_BETA = 2, FIN_RHO0 = 3, FIN_INIT = 4, FIN_UPDATE = 5, FIN_RESID = 6 };
 enum : int { DONE_NO = 0, DONE_CONVERGED = 1, DONE_NOT_SPD = 2, DONE_MAXIT = 3, DONE_ZERO_RHS = 4 };
 
-struct PcgScalars {
+struct PcgScalars {  // 80 bytes: copied as 10 double words
     double rho;      // r.z of the current iterate
     double alpha;
     double beta;
@@ -49,6 +54,7 @@ struct PcgScalars {
     int32_t plain;   // 1: M = I (z = r)
     double resid;    // ||b - A x||^2 of the final check
 };
+static_assert(sizeof(PcgScalars) == 80, "PcgScalars is copied as 10 double words");
 
 // Systems of a batch (device arrays; nullptr: one system covering everything)
 struct Systems {
@@ -473,6 +479,15 @@ __global__ __launch_bounds__(kThreads) void k_zero_rhs(int n, double *__restrict
     for (int i = i0 + threadIdx.x; i < i1; i += kThreads) x[i] = 0.0;
 }
 
+// Copies the scalars of every system into pinned host memory (mapped), where the host reads
+// them once the chunk's event has completed; a kernel is cheaper here than a copy engine
+// transfer of a few hundred bytes.
+__global__ void k_publish(const PcgScalars *__restrict__ sc, int nwords, PcgScalars *__restrict__ host) {
+    const double *src = reinterpret_cast<const double *>(sc);
+    double *dst = reinterpret_cast<double *>(host);
+    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < nwords; k += gridDim.x * blockDim.x) dst[k] = src[k];
+}
+
 __global__ void k_set_scalars(PcgScalars *scs, int nsys, double rtol, int maxit, int plain) {
     for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < nsys; k += gridDim.x * blockDim.x) {
         PcgScalars s{};
@@ -796,6 +811,24 @@ constexpr int kWorkVectors = 7;
 // (those return at once on the device flags); finish() computes the true residuals and the
 // results.  All work goes to one stream; any number of runs may be in progress on different
 // streams (the serving loop advances many of them from one host thread).
+// A stream per thread and device on which iterations are captured into graphs (never run).
+static hipStream_t capture_stream(int device) {
+    struct Streams {
+        hipStream_t s[64] = {};
+        ~Streams() {
+            for (hipStream_t &x : s)
+                if (x) (void)hipStreamDestroy(x);
+        }
+    };
+    thread_local Streams ts;
+    if (device < 0 || device >= 64) return nullptr;
+    if (!ts.s[device] && hipStreamCreateWithFlags(&ts.s[device], hipStreamNonBlocking) != hipSuccess) {
+        (void)hipGetLastError();
+        ts.s[device] = nullptr;
+    }
+    return ts.s[device];
+}
+
 class PcgRun {
   public:
     PcgRun(const afsai_csr &A, afsai_precond P, int nsys, const int32_t *row0, const double *b, double *x,
@@ -806,8 +839,12 @@ class PcgRun {
     }
     ~PcgRun() {
         if (started_) (void)hipStreamSynchronize(s_);
+        for (int k = 0; k < 2; ++k) {
+            if (gexec_[k]) (void)hipGraphExecDestroy(gexec_[k]);
+            if (graph_[k]) (void)hipGraphDestroy(graph_[k]);
+        }
         sell_free(&As_);
-        for (hipEvent_t e : {t0_, t1_, ev_[0], ev_[1]})
+        for (hipEvent_t e : {t0_, t1_, ev_[0], ev_[1], ev_[2], ev_[3]})
             if (e) (void)hipEventDestroy(e);
         if (hsc_) (void)hipHostFree(hsc_);
     }
@@ -820,11 +857,12 @@ class PcgRun {
         if ((rc = device_info(&di_))) return rc;
         AFSAI_HIP_TRY(hipEventCreate(&t0_));
         AFSAI_HIP_TRY(hipEventCreate(&t1_));
-        AFSAI_HIP_TRY(hipEventCreateWithFlags(&ev_[0], hipEventDisableTiming));
-        AFSAI_HIP_TRY(hipEventCreateWithFlags(&ev_[1], hipEventDisableTiming));
+        for (hipEvent_t &e : ev_) AFSAI_HIP_TRY(hipEventCreate(&e));
         AFSAI_HIP_TRY(hipHostMalloc(&hsc_, 2 * sizeof(PcgScalars) * (size_t)nsys_, hipHostMallocDefault));
         hs_[0] = hsc_;
         hs_[1] = hsc_ + nsys_;
+        AFSAI_HIP_TRY(hipHostGetDevicePointer((void **)&dhs_[0], hsc_, 0));
+        dhs_[1] = dhs_[0] + nsys_;
         AFSAI_HIP_TRY(hipEventRecord(t0_, s_));
         started_ = true;
         if ((rc = make_batch_maps(n, nsys_, row0_.data(), di_, s_, &bm_))) return rc;
@@ -886,6 +924,10 @@ class PcgRun {
         for (int k = 0; k < nsys_; ++k) nmax = std::max(nmax, row0_[k + 1] - row0_[k]);
         const bool want_fused = form == 2 || (form == 0 && nmax < kFusedMaxRows);
         fused_ = P_ && use_sell_ && want_fused && !As_.tail && !P_->sg.tail;
+        // iterations replayed from captured graphs only when asked for (never while the kernel
+        // timer is on: its events would be captured); on MI355X with ROCm 7 enqueuing the
+        // kernels measured faster than replaying graphs at every size tried
+        use_graph_ = !profiling_on() && option(AFSAI_OPT_PCG_GRAPH) == 2;
         if (!fused_)
             hipLaunchKernelGGL(k_update_p, gv, dim3(kThreads), 0, s_, n, p_, zz_, sc_, 1, bm_.vec.mp, bm_.sy,
                                di_.num_xcds);
@@ -898,7 +940,7 @@ class PcgRun {
         // the state after the start (a chunk of no iterations) and a first chunk in flight
         // before any state is read
         if ((rc = enqueue_chunk(0))) return rc;
-        if ((rc = enqueue_chunk(4))) return rc;
+        if ((rc = enqueue_chunk(kFirstChunk))) return rc;
         return AFSAI_OK;
     }
 
@@ -911,12 +953,23 @@ class PcgRun {
             return AFSAI_OK;
         }
         const int slot = (c_ - 2) & 1;  // state after the oldest chunk in flight
+        hipEvent_t ev = ev_[(c_ - 2) & 3];
         if (!block) {
-            const hipError_t q = hipEventQuery(ev_[slot]);
+            const hipError_t q = hipEventQuery(ev);
             if (q == hipErrorNotReady) return AFSAI_OK;
             if (q != hipSuccess) AFSAI_HIP_TRY(q);
         } else {
-            AFSAI_HIP_TRY(hipEventSynchronize(ev_[slot]));
+            AFSAI_HIP_TRY(hipEventSynchronize(ev));
+        }
+        // GPU time of that chunk (from the end of the chunk before it)
+        if (c_ >= 3 && its_[(c_ - 2) & 3] > 0) {
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, ev_[(c_ - 3) & 3], ev) == hipSuccess && ms > 0.f) {
+                gpu_us_ += 1e3 * ms;
+                it_us_ = 1e3 * ms / its_[(c_ - 2) & 3];
+            } else {
+                (void)hipGetLastError();
+            }
         }
         const PcgScalars *st = hs_[slot];
         bool all_done = true;
@@ -939,8 +992,15 @@ class PcgRun {
             *finished = true;
             return AFSAI_OK;
         }
-        // iterations the slowest active system still needs, from its observed rate
-        int todo = chunk_;
+        // Chunk size: enough GPU work to cover the host's turnaround (two chunks are in flight)
+        // and a fixed share of the time so far, so that the iterations enqueued past
+        // convergence stay a small part of the solve; capped by the iterations the slowest
+        // active system still needs at its observed rate.
+        int todo = kFirstChunk;
+        if (it_us_ > 0.0) {
+            const double window_us = std::max(kMinChunkUs, gpu_us_ * kChunkShare);
+            todo = (int)std::min(64.0, std::max(1.0, std::ceil(window_us / it_us_)));
+        }
         int need_max = -1;
         for (int k = 0; k < nsys_; ++k) {
             if (st[k].done != DONE_NO) continue;
@@ -951,8 +1011,7 @@ class PcgRun {
             const double need_it = std::ceil(std::log(tol_[k] * tol_[k] / prev_rr_[k]) / rate_[k]);
             need_max = std::max(need_max, (int)need_it - (enqueued_ - prev_it_[k]) + 1);
         }
-        if (need_max >= 0) todo = need_max < 1 ? 1 : (need_max > 64 ? 64 : need_max);
-        if (chunk_ < 64) chunk_ *= 2;
+        if (need_max >= 0) todo = std::min(todo, std::max(1, need_max));
         return enqueue_chunk(todo);
     }
 
@@ -1022,6 +1081,49 @@ class PcgRun {
         else spmv(name, csr_of(&A_), xin, yout, w, w ? partials_ : nullptr, g, fin, di_, s_);
     }
 
+    // One iteration: from the captured graph of its buffer parity (captured at its first use;
+    // the first fused iteration, which forms p = z, always runs directly), else enqueued.
+    // Capture runs on a private stream of this thread (the caller's stream may be the null
+    // stream, which cannot capture); nothing executes there, the graph is launched on s_.
+    int launch_iteration() {
+        const int par = fused_ ? (iter_no_ & 1) : 0;
+        if (!use_graph_ || (fused_ && iter_no_ == 0)) {
+            enqueue_iteration();
+            return AFSAI_OK;
+        }
+        if (!gexec_[par]) {
+            hipStream_t cs = capture_stream(di_.device);
+            hipGraph_t g = nullptr;
+            hipError_t e = cs ? hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) : hipErrorUnknown;
+            if (e == hipSuccess) {
+                const int it0 = iter_no_;
+                const size_t nmarks = marks_.size();
+                hipStream_t keep = s_;
+                s_ = cs;
+                enqueue_iteration();
+                s_ = keep;
+                iter_no_ = it0;
+                marks_.resize(nmarks);
+                e = hipStreamEndCapture(cs, &g);
+            }
+            if (e == hipSuccess && g) e = hipGraphInstantiate(&gexec_[par], g, nullptr, nullptr, 0);
+            if (e != hipSuccess || !gexec_[par]) {
+                // capture not available: enqueue directly from here on
+                (void)hipGetLastError();
+                if (g) (void)hipGraphDestroy(g);
+                gexec_[par] = nullptr;
+                use_graph_ = false;
+                enqueue_iteration();
+                return AFSAI_OK;
+            }
+            graph_[par] = g;
+        }
+        AFSAI_HIP_TRY(hipGraphLaunch(gexec_[par], s_));
+        marks_.push_back(prof_mark());
+        ++iter_no_;
+        return AFSAI_OK;
+    }
+
     void enqueue_iteration() {
         const int n = A_.n;
         const dim3 gv(bm_.vec.nblocks), gs(bm_.nsys);
@@ -1065,11 +1167,17 @@ class PcgRun {
     // slot of this chunk and its event
     int enqueue_chunk(int todo) {
         if (todo > maxit_ - enqueued_) todo = maxit_ - enqueued_;
-        for (int k = 0; k < todo; ++k) enqueue_iteration();
+        for (int k = 0; k < todo; ++k) {
+            int rc;
+            if ((rc = launch_iteration())) return rc;
+        }
         enqueued_ += todo;
         const int slot = c_ & 1;
-        AFSAI_HIP_TRY(hipMemcpyAsync(hs_[slot], sc_, sizeof(PcgScalars) * (size_t)nsys_, hipMemcpyDeviceToHost, s_));
-        AFSAI_HIP_TRY(hipEventRecord(ev_[slot], s_));
+        const int nw = nsys_ * (int)(sizeof(PcgScalars) / sizeof(double));
+        hipLaunchKernelGGL(k_publish, dim3((nw + kThreads - 1) / kThreads), dim3(kThreads), 0, s_, sc_, nw,
+                           dhs_[slot]);
+        its_[c_ & 3] = todo;
+        AFSAI_HIP_TRY(hipEventRecord(ev_[c_ & 3], s_));
         ++c_;
         return AFSAI_OK;
     }
@@ -1087,15 +1195,20 @@ class PcgRun {
     BatchMaps bm_;
     DevBuf own_;
     Sell As_;
-    bool use_sell_ = true, fused_ = false, started_ = false, done_ = false;
+    bool use_sell_ = true, fused_ = false, started_ = false, done_ = false, use_graph_ = false;
+    hipGraph_t graph_[2] = {nullptr, nullptr};
+    hipGraphExec_t gexec_[2] = {nullptr, nullptr};
     double *r_ = nullptr, *r2_ = nullptr, *z_ = nullptr, *p_ = nullptr, *p2_ = nullptr, *q_ = nullptr, *t_ = nullptr;
     const double *zz_ = nullptr;
     double *partials_ = nullptr;
     PcgScalars *sc_ = nullptr;
     PcgScalars *hsc_ = nullptr;
     PcgScalars *hs_[2] = {nullptr, nullptr};
-    hipEvent_t t0_ = nullptr, t1_ = nullptr, ev_[2] = {nullptr, nullptr};
-    int iter_no_ = 0, enqueued_ = 0, c_ = 0, chunk_ = 8, mark0_ = 0;
+    PcgScalars *dhs_[2] = {nullptr, nullptr};  // device addresses of hs_
+    hipEvent_t t0_ = nullptr, t1_ = nullptr, ev_[4] = {nullptr, nullptr, nullptr, nullptr};
+    int its_[4] = {0, 0, 0, 0};
+    double gpu_us_ = 0.0, it_us_ = 0.0;
+    int iter_no_ = 0, enqueued_ = 0, c_ = 0, mark0_ = 0;
     std::vector<int> marks_, prev_it_;
     std::vector<double> prev_rr_, rate_, tol_;
     std::vector<char> have_prev_;
