@@ -305,6 +305,10 @@ const char *afsai_last_error(void);
  *                             into a HIP graph (once per buffer parity in the fused form) and
  *                             replayed (never while the kernel timer is on). Results are
  *                             identical.
+ *   AFSAI_OPT_SETUP_SLOTS     where the setup kernel keeps the table slots of the pattern rows'
+ *                             entries: 0 automatic (registers when every row of A has at most
+ *                             128 entries and 1 + k_max * s <= 32, else LDS), 1 LDS, 2 registers
+ *                             (AFSAI_ERR_INVALID_ARG from afsai_setup when not possible)
  * Returns AFSAI_ERR_INVALID_ARG for an unknown option or value.  Not thread safe against
  * concurrent calls of the library.
  */
@@ -316,6 +320,7 @@ const char *afsai_last_error(void);
 #define AFSAI_OPT_PCG_FORM 6
 #define AFSAI_OPT_SELL_WIDTH 7
 #define AFSAI_OPT_PCG_GRAPH 8
+#define AFSAI_OPT_SETUP_SLOTS 9
 int afsai_set_option(int32_t option, int64_t value);
 
 /*

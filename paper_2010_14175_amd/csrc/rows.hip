@@ -1,17 +1,27 @@
 // Instantiations of the fused per-row setup kernel: pattern capacity 8..64 (LDS sizing of the
-// factor) times candidate table 128..8192 slots.
+// factor) times candidate table 128..8192 slots, with slot lists in LDS, or in registers for
+// patterns of at most 32 positions.
 #include "rows.hpp"
 
 namespace afsai {
 
-RowsKernel rows_kernel(int mmax_t, int cap) {
+RowsKernel rows_kernel(int mmax_t, int cap, bool rsl) {
+    if (rsl) {
+        switch (mmax_t) {
+            case 8: return rows_kernel_cap<8, true>(cap);
+            case 16: return rows_kernel_cap<16, true>(cap);
+            case 24: return rows_kernel_cap<24, true>(cap);
+            case 32: return rows_kernel_cap<32, true>(cap);
+            default: return nullptr;
+        }
+    }
     switch (mmax_t) {
-        case 8: return rows_kernel_cap<8>(cap);
-        case 16: return rows_kernel_cap<16>(cap);
-        case 24: return rows_kernel_cap<24>(cap);
-        case 32: return rows_kernel_cap<32>(cap);
-        case 48: return rows_kernel_cap<48>(cap);
-        case 64: return rows_kernel_cap<64>(cap);
+        case 8: return rows_kernel_cap<8, false>(cap);
+        case 16: return rows_kernel_cap<16, false>(cap);
+        case 24: return rows_kernel_cap<24, false>(cap);
+        case 32: return rows_kernel_cap<32, false>(cap);
+        case 48: return rows_kernel_cap<48, false>(cap);
+        case 64: return rows_kernel_cap<64, false>(cap);
         default: return nullptr;
     }
 }

@@ -153,7 +153,10 @@ __device__ __forceinline__ void upd_old_columns(int mb, const int (&base)[kGMax]
 template <int CAP>
 constexpr int sl_cap() { return CAP >= 2048 ? 2 * CAP : 4 * CAP; }
 
-template <int MMAX, int CAP>
+// RSL: the slot lists live in registers (rows of at most 128 entries: lane l keeps the slots of
+// entries l and 64 + l of every member, packed in one 32-bit register per member) instead of LDS,
+// which frees LDS for more resident rows.
+template <int MMAX, int CAP, bool RSL>
 __global__ __launch_bounds__(64) void k_afsai_rows(
     int n, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci, const double *__restrict__ av,
     const double *__restrict__ diag, const int32_t *__restrict__ dlo, int kmax, int s, double eps, double tau,
@@ -162,11 +165,12 @@ __global__ __launch_bounds__(64) void k_afsai_rows(
     double *__restrict__ psi_out, int32_t *__restrict__ steps_out, int32_t *__restrict__ reason_out,
     int8_t *__restrict__ status_out, int32_t *__restrict__ ovf_count, int32_t *__restrict__ ovf_list) {
     static_assert(MMAX <= 64, "one lane per pattern position");
+    static_assert(!RSL || MMAX <= 32, "register slot lists for at most 32 positions");
     constexpr int K = (MMAX + 1 + 63) / 64;        // update entries per lane
     constexpr int LTRI = (MMAX * (MMAX - 1)) / 2;  // rows 0..MMAX-2 of L, packed lower
     constexpr int SPL = CAP / 64;                  // table slots per lane
     constexpr bool SEL_REG = SPL <= 16;            // selection from registers
-    constexpr int SLCAP = sl_cap<CAP>();
+    constexpr int SLCAP = RSL ? 1 : sl_cap<CAP>();
     __shared__ uint32_t hkey[CAP];       // column (tagged when a member), kept for the whole row
     __shared__ double hval[CAP];         // gradient of this step
     __shared__ int8_t hpos[CAP];         // position of a member
@@ -206,16 +210,21 @@ __global__ __launch_bounds__(64) void k_afsai_rows(
         if (!(aii > 0.0) || !isfinite(aii)) status = ROW_NOT_SPD;
         const double psi0 = aii;
         int sl_used = 0;  // SL entries in use (uniform)
+        // register slot lists: member 0 is row i, member t + 1 the column at position t
+        uint32_t slr[RSL ? MMAX : 1];
+#pragma unroll
+        for (int q = 0; q < (RSL ? MMAX : 1); ++q) slr[q] = 0u;
 
         // table: empty; row i's entries left of the diagonal are entered as candidates
         for (int j = lane; j < CAP; j += 64) hkey[j] = kEmpty;
         __syncthreads();
         if (kmax > 0 && status == ROW_OK) {
-            bool ovf = ilen > SLCAP;
+            bool ovf = RSL ? ilen > 128 : ilen > SLCAP;
             for (int o = lane; o < ilen && !ovf; o += 64) {
                 bool tg;
                 const int slot = table_find<CAP>(hkey, (uint32_t)ci[ibeg + o], (uint32_t)ci[ibeg + o], true, tg);
                 if (slot < 0) ovf = true;
+                else if constexpr (RSL) slr[0] |= (uint32_t)slot << (o >= 64 ? 16 : 0);
                 else SL[o] = (uint16_t)slot;
             }
             if (__ballot(ovf)) status = ROW_OVERFLOW;
@@ -234,46 +243,87 @@ __global__ __launch_bounds__(64) void k_afsai_rows(
             //         slots of members collect values that are never read)
             for (int j = lane; j < CAP; j += 64) hval[j] = 0.0;
             __syncthreads();
-            for (int t0 = 0; t0 < m; t0 += 4) {
-                int sl[8];
-                double aa[8], gg[4];
-                int lens[4], begs[4], sos[4];
+            if constexpr (RSL) {
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const int t = t0 + u;
-                    lens[u] = 0;
-                    begs[u] = 0;
-                    sos[u] = 0;
-                    gg[u] = 0.0;
-                    if (t < m) {
-                        lens[u] = __builtin_amdgcn_readlane(r_len, t);
-                        begs[u] = __builtin_amdgcn_readlane(r_beg, t);
-                        sos[u] = __builtin_amdgcn_readlane(r_so, t);
-                        gg[u] = rl(r_g, t);
-                    }
+                for (int q0 = 0; q0 < MMAX; q0 += 4) {
+                    if (q0 < m) {
+                        int sl[8];
+                        double aa[8], gg[4];
+                        int lens[4], begs[4];
 #pragma unroll
-                    for (int hh = 0; hh < 2; ++hh) {
-                        const int o = hh * 64 + lane;
-                        sl[2 * u + hh] = -1;
-                        aa[2 * u + hh] = 0.0;
-                        if (o < lens[u]) {
-                            sl[2 * u + hh] = SL[sos[u] + o];
-                            aa[2 * u + hh] = __builtin_nontemporal_load(&av[begs[u] + o]);
+                        for (int u = 0; u < 4; ++u) {
+                            const int q = q0 + u;
+                            const int pos = (q == 0) ? m - 1 : q - 1;
+                            lens[u] = 0;
+                            begs[u] = 0;
+                            gg[u] = 0.0;
+                            if (q < m) {
+                                lens[u] = __builtin_amdgcn_readlane(r_len, pos);
+                                begs[u] = __builtin_amdgcn_readlane(r_beg, pos);
+                                gg[u] = rl(r_g, pos);
+                            }
+#pragma unroll
+                            for (int hh = 0; hh < 2; ++hh) {
+                                const int o = hh * 64 + lane;
+                                sl[2 * u + hh] = -1;
+                                aa[2 * u + hh] = 0.0;
+                                if (o < lens[u]) {
+                                    sl[2 * u + hh] = (int)((slr[q] >> (16 * hh)) & 0xffffu);
+                                    aa[2 * u + hh] = __builtin_nontemporal_load(&av[begs[u] + o]);
+                                }
+                            }
                         }
+#pragma unroll
+                        for (int u = 0; u < 4; ++u)
+#pragma unroll
+                            for (int hh = 0; hh < 2; ++hh)
+                                if (sl[2 * u + hh] >= 0)
+                                    __hip_atomic_fetch_add(&hval[sl[2 * u + hh]], aa[2 * u + hh] * gg[u],
+                                                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
                     }
                 }
-#pragma unroll
-                for (int u = 0; u < 4; ++u)
-#pragma unroll
-                    for (int hh = 0; hh < 2; ++hh)
-                        if (sl[2 * u + hh] >= 0)
-                            __hip_atomic_fetch_add(&hval[sl[2 * u + hh]], aa[2 * u + hh] * gg[u], __ATOMIC_RELAXED,
+            } else {
+                for (int t0 = 0; t0 < m; t0 += 4) {
+                    int sl[8];
+                    double aa[8], gg[4];
+                    int lens[4], begs[4], sos[4];
+    #pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const int t = t0 + u;
+                        lens[u] = 0;
+                        begs[u] = 0;
+                        sos[u] = 0;
+                        gg[u] = 0.0;
+                        if (t < m) {
+                            lens[u] = __builtin_amdgcn_readlane(r_len, t);
+                            begs[u] = __builtin_amdgcn_readlane(r_beg, t);
+                            sos[u] = __builtin_amdgcn_readlane(r_so, t);
+                            gg[u] = rl(r_g, t);
+                        }
+    #pragma unroll
+                        for (int hh = 0; hh < 2; ++hh) {
+                            const int o = hh * 64 + lane;
+                            sl[2 * u + hh] = -1;
+                            aa[2 * u + hh] = 0.0;
+                            if (o < lens[u]) {
+                                sl[2 * u + hh] = SL[sos[u] + o];
+                                aa[2 * u + hh] = __builtin_nontemporal_load(&av[begs[u] + o]);
+                            }
+                        }
+                    }
+    #pragma unroll
+                    for (int u = 0; u < 4; ++u)
+    #pragma unroll
+                        for (int hh = 0; hh < 2; ++hh)
+                            if (sl[2 * u + hh] >= 0)
+                                __hip_atomic_fetch_add(&hval[sl[2 * u + hh]], aa[2 * u + hh] * gg[u], __ATOMIC_RELAXED,
+                                                       __HIP_MEMORY_SCOPE_WORKGROUP);
+    #pragma unroll
+                    for (int u = 0; u < 4; ++u)
+                        for (int o = 128 + lane; o < lens[u]; o += 64)
+                            __hip_atomic_fetch_add(&hval[SL[sos[u] + o]], av[begs[u] + o] * gg[u], __ATOMIC_RELAXED,
                                                    __HIP_MEMORY_SCOPE_WORKGROUP);
-#pragma unroll
-                for (int u = 0; u < 4; ++u)
-                    for (int o = 128 + lane; o < lens[u]; o += 64)
-                        __hip_atomic_fetch_add(&hval[SL[sos[u] + o]], av[begs[u] + o] * gg[u], __ATOMIC_RELAXED,
-                                               __HIP_MEMORY_SCOPE_WORKGROUP);
+                }
             }
             __syncthreads();
 
@@ -397,8 +447,10 @@ __global__ __launch_bounds__(64) void k_afsai_rows(
                 for (int v = 0; v < G; ++v) {
                     const int nb = __builtin_amdgcn_readlane(r_nb, v0 + v);
                     const int nl = __builtin_amdgcn_readlane(r_ne, v0 + v) - nb;
-                    if (sl_used + nl > SLCAP) ovf = true;  // uniform
+                    if (!RSL && sl_used + nl > SLCAP) ovf = true;  // uniform
+                    if (RSL && nl > 128) ovf = true;
                     int nlo = 0;
+                    uint32_t pk = 0u;  // register slot list of this row (RSL)
                     for (int h = 0; h * 64 < nl && !ovf; ++h) {
                         const int o = h * 64 + lane;
                         int c = 0x7fffffff;
@@ -415,7 +467,8 @@ __global__ __launch_bounds__(64) void k_afsai_rows(
                             if (slot < 0) {
                                 bad = true;
                             } else {
-                                SL[sl_used + o] = (uint16_t)slot;
+                                if constexpr (RSL) pk |= (uint32_t)slot << (16 * h);
+                                else SL[sl_used + o] = (uint16_t)slot;
                                 if (tg) NR[v * MMAX + hpos[slot]] = a;
                             }
                         }
@@ -426,6 +479,12 @@ __global__ __launch_bounds__(64) void k_afsai_rows(
                         r_beg = nb;
                         r_len = nlo;
                         r_so = sl_used;
+                    }
+                    if constexpr (RSL) {
+                        const int qn = mb + v + 1;  // member of position mb + v
+#pragma unroll
+                        for (int qq = 1; qq < (RSL ? MMAX : 1); ++qq)
+                            if (qq == qn) slr[qq] = pk;
                     }
                     sl_used += nlo;
                 }
@@ -644,23 +703,23 @@ typedef void (*RowsKernel)(int, const int32_t *, const int32_t *, const double *
                            int, int, double, double, int, const int32_t *, int, int32_t *, int, int32_t *, double *, int,
                            int32_t *, double *, int32_t *, int32_t *, int8_t *, int32_t *, int32_t *);
 
-template <int MMAX>
+template <int MMAX, bool RSL>
 static RowsKernel rows_kernel_cap(int cap) {
     switch (cap) {
-        case 128: return k_afsai_rows<MMAX, 128>;
-        case 256: return k_afsai_rows<MMAX, 256>;
-        case 512: return k_afsai_rows<MMAX, 512>;
-        case 1024: return k_afsai_rows<MMAX, 1024>;
-        case 2048: return k_afsai_rows<MMAX, 2048>;
-        case 4096: return k_afsai_rows<MMAX, 4096>;
-        case 8192: return k_afsai_rows<MMAX, 8192>;
+        case 128: return k_afsai_rows<MMAX, 128, RSL>;
+        case 256: return k_afsai_rows<MMAX, 256, RSL>;
+        case 512: return k_afsai_rows<MMAX, 512, RSL>;
+        case 1024: return k_afsai_rows<MMAX, 1024, RSL>;
+        case 2048: return k_afsai_rows<MMAX, 2048, RSL>;
+        case 4096: return k_afsai_rows<MMAX, 4096, RSL>;
+        case 8192: return k_afsai_rows<MMAX, 8192, RSL>;
         default: return nullptr;
     }
 }
 
-// LDS bytes of one k_afsai_rows<MMAX, CAP> block
-__host__ __forceinline__ size_t rows_lds_bytes(int mmax_t, int cap) {
-    const size_t slcap = cap >= 2048 ? 2 * (size_t)cap : 4 * (size_t)cap;
+// LDS bytes of one k_afsai_rows<MMAX, CAP, RSL> block
+__host__ __forceinline__ size_t rows_lds_bytes(int mmax_t, int cap, bool rsl) {
+    const size_t slcap = rsl ? 1 : (cap >= 2048 ? 2 * (size_t)cap : 4 * (size_t)cap);
     return (size_t)cap * 13 + slcap * 2 + (size_t)mmax_t * (mmax_t - 1) / 2 * 8 + (size_t)kGMax * mmax_t * 8 + 16;
 }
 

@@ -281,14 +281,14 @@ __global__ void k_block_check(int n, const int32_t *__restrict__ rp, const int32
 // host side
 // ---------------------------------------------------------------------------------------
 // fused per-row kernels, instantiated in rows.hip
-RowsKernel rows_kernel(int mmax_t, int cap);
+RowsKernel rows_kernel(int mmax_t, int cap, bool rsl);
 
-static int launch_rows(RowsKernel kern, int mmax_t, int cap, int gmax, const afsai_csr *A, const double *diag,
+static int launch_rows(RowsKernel kern, int mmax_t, int cap, bool rsl, int gmax, const afsai_csr *A, const double *diag,
                        const int32_t *dlo, const afsai_params *p, const int32_t *list, int nlist, int32_t *counters,
                        int ldell, int32_t *ell_col, double *ell_val, int32_t *m, double *psi, int32_t *steps,
                        int32_t *reason, int8_t *st, int32_t *ovf_count, int32_t *ovf_list, const DeviceInfo &di,
                        hipStream_t s) {
-    const size_t lds = rows_lds_bytes(mmax_t, cap);
+    const size_t lds = rows_lds_bytes(mmax_t, cap, rsl);
     int per_cu = (int)((160 * 1024) / (lds + 256));
     if (per_cu > 32) per_cu = 32;
     if (per_cu < 1) per_cu = 1;
@@ -456,6 +456,11 @@ static int setup_core(const afsai_csr *A, const afsai_params *p, int nsys, const
     if (option(AFSAI_OPT_SETUP_TABLE) > 0) cap1 = pow2ceil(option(AFSAI_OPT_SETUP_TABLE));
     if (cap1 < 128) cap1 = 128;
     if (cap1 > 1024) cap1 = 1024;
+    // slot lists in registers where every row has at most 128 entries and the pattern at most
+    // 32 positions (more rows resident per CU), else in LDS
+    const int64_t slopt = option(AFSAI_OPT_SETUP_SLOTS);
+    const bool rsl = slopt == 1 ? false : (maxlen <= 128 && mmax_t <= 32);
+    if (slopt == 2 && !rsl) AFSAI_FAIL(AFSAI_ERR_INVALID_ARG, "afsai_setup: register slot lists need rows of at most 128 entries and 1 + k_max * s <= 32");
     int cap2 = pow2ceil(bound + 1);
     if (cap2 < cap1) cap2 = cap1;
     if (cap2 > 8192) cap2 = 8192;
@@ -475,9 +480,9 @@ static int setup_core(const afsai_csr *A, const afsai_params *p, int nsys, const
     int32_t *ovf_count = ovf.as<int32_t>() + n;
     hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, (int64_t)1, ovf_count, 0);
 
-    RowsKernel k1 = rows_kernel(mmax_t, cap1);
+    RowsKernel k1 = rows_kernel(mmax_t, cap1, rsl);
     if (!k1) AFSAI_FAIL(AFSAI_ERR_TOO_LARGE, "afsai_setup: no kernel for pattern %d / table %d", mmax_t, cap1);
-    if ((rc = launch_rows(k1, mmax_t, cap1, gmax, A, diagb.as<double>(), dlob.as<int32_t>(), p, nullptr, n, ctr.as<int32_t>(), ldell,
+    if ((rc = launch_rows(k1, mmax_t, cap1, rsl, gmax, A, diagb.as<double>(), dlob.as<int32_t>(), p, nullptr, n, ctr.as<int32_t>(), ldell,
                           ell_col.as<int32_t>(), ell_val.as<double>(), mcnt.as<int32_t>(), psi.as<double>(),
                           steps.as<int32_t>(), reason.as<int32_t>(), st.as<int8_t>(), ovf_count, ovf.as<int32_t>(), di,
                           s)))
@@ -494,9 +499,9 @@ static int setup_core(const afsai_csr *A, const afsai_params *p, int nsys, const
                            list2.as<int32_t>());
         int32_t *cnt2 = list2.as<int32_t>() + novf;
         hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, (int64_t)1, cnt2, 0);
-        RowsKernel k2 = rows_kernel(mmax_t, cap2);
+        RowsKernel k2 = rows_kernel(mmax_t, cap2, rsl);
         if (!k2) AFSAI_FAIL(AFSAI_ERR_TOO_LARGE, "afsai_setup: no kernel for table %d", cap2);
-        if ((rc = launch_rows(k2, mmax_t, cap2, gmax, A, diagb.as<double>(), dlob.as<int32_t>(), p, list2.as<int32_t>(), novf,
+        if ((rc = launch_rows(k2, mmax_t, cap2, rsl, gmax, A, diagb.as<double>(), dlob.as<int32_t>(), p, list2.as<int32_t>(), novf,
                               ctr.as<int32_t>(), ldell, ell_col.as<int32_t>(), ell_val.as<double>(), mcnt.as<int32_t>(),
                               psi.as<double>(), steps.as<int32_t>(), reason.as<int32_t>(), st.as<int8_t>(), cnt2,
                               ovf.as<int32_t>(), di, s)))

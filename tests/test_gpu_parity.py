@@ -193,6 +193,40 @@ def test_setup_forms_identical(af, make, kmax, s):
             np.testing.assert_array_equal(a, b)
 
 
+@pytest.mark.parametrize("slots", [1, 2])
+@pytest.mark.parametrize("make,kmax,s", [(lambda: synth.elast27(12, 1.0, 2), 10, 2), (lambda: synth.lap7(16), 5, 1),
+                                         (lambda: synth.random_sparse_spd(3000, 40, 3), 10, 3)])
+def test_setup_slot_lists(af, slots, make, kmax, s):
+    """The table slots of the pattern rows' entries kept in LDS (1) or in registers (2): both
+    give the oracle's patterns and values (bitwise here), and equal each other bit for bit."""
+    A = make()
+    try:
+        af.set_option(af.OPT_SETUP_SLOTS, slots)
+        r = compare_factor(af, A, kmax, s, 1e-2)
+        other = 1 if slots == 2 else 2
+        af.set_option(af.OPT_SETUP_SLOTS, other)
+        o = _gpu_factor(af, af.setup(r["dA"], kmax, s, 1e-2))
+    finally:
+        af.set_option(af.OPT_SETUP_SLOTS, 0)
+    assert r["bitwise"] > 0.999
+    for a, b in zip(_gpu_factor(af, r["P"]), o):
+        np.testing.assert_array_equal(a, b)
+
+
+def test_setup_slot_lists_refused(af):
+    """Register slot lists need at most 32 pattern positions: asked for with k_max * s = 45 the
+    setup reports an invalid argument instead of running."""
+    A = synth.elast27(5, 1.0, 2)
+    dA = _dev(af, A)
+    try:
+        af.set_option(af.OPT_SETUP_SLOTS, 2)
+        with pytest.raises(af.AfsaiError) as e:
+            af.setup(dA, 15, 3, 1e-2)
+        assert e.value.code == af.ERR_INVALID_ARG
+    finally:
+        af.set_option(af.OPT_SETUP_SLOTS, 0)
+
+
 @pytest.mark.parametrize("gs,un", [(4, 1), (8, 2), (16, 8), (64, 4)])
 def test_spmv_shapes(af, gs, un):
     """Every group size / unroll of the CSR products gives the oracle's y within rounding."""
