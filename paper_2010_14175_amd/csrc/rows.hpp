@@ -37,7 +37,13 @@ namespace afsai {
 
 constexpr uint32_t kEmpty = 0xFFFFFFFFu;
 constexpr uint32_t kPBit = 0x80000000u;
+// keys of the register-list form: column in bits 0..23, a member's position in bits 24..30
+constexpr uint32_t kCol24 = 0x00FFFFFFu;
 constexpr int kGMax = 4;  // rows appended to the factor together
+#ifndef AFSAI_PROD_BATCH
+#define AFSAI_PROD_BATCH 4
+#endif
+constexpr int kProdBatch = AFSAI_PROD_BATCH;
 
 enum : int8_t { ROW_OK = 0, ROW_OVERFLOW = 1, ROW_BAD = 2, ROW_NOT_SPD = 3 };
 enum : int32_t { STOP_KMAX = 0, STOP_EPS = 1, STOP_NOCAND = 2 };
@@ -51,9 +57,11 @@ __device__ __forceinline__ uint32_t hash0(uint32_t c) {
 }
 
 // Finds column c in the table; inserts `ins` (c, possibly tagged) when absent and `insert` is
-// set.  Returns the slot, -1 if absent (lookup only) or -2 if the table is full.
-template <int CAP>
-__device__ __forceinline__ int table_find(uint32_t *hkey, uint32_t c, uint32_t ins, bool insert, bool &tagged) {
+// set.  Returns the slot, -1 if absent (lookup only) or -2 if the table is full; `key` is the
+// stored key.  KM masks the column out of a key.
+template <int CAP, uint32_t KM = ~kPBit>
+__device__ __forceinline__ int table_find(uint32_t *hkey, uint32_t c, uint32_t ins, bool insert, bool &tagged,
+                                          uint32_t &key) {
     uint32_t slot = hash0<CAP>(c);
     for (int probe = 0; probe < CAP; ++probe) {
         uint32_t k = __hip_atomic_load(&hkey[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -62,12 +70,14 @@ __device__ __forceinline__ int table_find(uint32_t *hkey, uint32_t c, uint32_t i
             const uint32_t old = atomicCAS(&hkey[slot], kEmpty, ins);
             if (old == kEmpty) {
                 tagged = (ins & kPBit) != 0;
+                key = ins;
                 return (int)slot;
             }
             k = old;
         }
-        if ((k & ~kPBit) == c) {
+        if ((k & KM) == c) {
             tagged = (k & kPBit) != 0;
+            key = k;
             return (int)slot;
         }
         slot = (slot + 1) & (CAP - 1);
@@ -155,17 +165,24 @@ constexpr int sl_cap() { return CAP >= 2048 ? 2 * CAP : 4 * CAP; }
 
 // RSL: the slot lists live in registers (rows of at most 128 entries: lane l keeps the slots of
 // entries l and 64 + l of every member, packed in one 32-bit register per member) instead of LDS,
-// which frees LDS for more resident rows.
+// which frees LDS for more resident rows; in this form a member's position is kept in its table
+// key (columns below 2^24), the gathered rows share the gradient's array (not in use from the
+// selection to the next product pass) and the rows of L are sized by the launch (dynamic LDS).
+// The register-list form fits 20 rows per CU in LDS (at most 512 table slots); the register
+// budget is set for 5 waves per SIMD to match, measured faster than 4 waves without spills.
 template <int MMAX, int CAP, bool RSL>
-__global__ __launch_bounds__(64) void k_afsai_rows(
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(!RSL ? 1 : (MMAX <= 8 && CAP <= 256) ? 8 : (CAP <= 512 ? 5 : 1), 8))) void k_afsai_rows(
     int n, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci, const double *__restrict__ av,
     const double *__restrict__ diag, const int32_t *__restrict__ dlo, int kmax, int s, double eps, double tau,
-    int gmax, const int32_t *__restrict__ list, int nlist, int32_t *__restrict__ counters, int nxcd,
+    int gmax, const int32_t *__restrict__ list, int nlist, int32_t *__restrict__ counters, int nxcd, int claim,
     int32_t *__restrict__ ell_col, double *__restrict__ ell_val, int ldell, int32_t *__restrict__ m_out,
     double *__restrict__ psi_out, int32_t *__restrict__ steps_out, int32_t *__restrict__ reason_out,
     int8_t *__restrict__ status_out, int32_t *__restrict__ ovf_count, int32_t *__restrict__ ovf_list) {
     static_assert(MMAX <= 64, "one lane per pattern position");
     static_assert(!RSL || MMAX <= 32, "register slot lists for at most 32 positions");
+    static_assert(!RSL || CAP >= kGMax * MMAX, "gathered rows fit in the gradient array");
+    constexpr uint32_t KM = RSL ? kCol24 : ~kPBit;
+    constexpr int QB = kProdBatch;  // members whose entries one product round loads together (RSL)
     constexpr int K = (MMAX + 1 + 63) / 64;        // update entries per lane
     constexpr int LTRI = (MMAX * (MMAX - 1)) / 2;  // rows 0..MMAX-2 of L, packed lower
     constexpr int SPL = CAP / 64;                  // table slots per lane
@@ -173,10 +190,13 @@ __global__ __launch_bounds__(64) void k_afsai_rows(
     constexpr int SLCAP = RSL ? 1 : sl_cap<CAP>();
     __shared__ uint32_t hkey[CAP];       // column (tagged when a member), kept for the whole row
     __shared__ double hval[CAP];         // gradient of this step
-    __shared__ int8_t hpos[CAP];         // position of a member
-    __shared__ uint16_t SL[SLCAP];       // table slots of the member rows' entries left of i
-    __shared__ double Lp[LTRI];          // rows of L for the off-diagonal positions
-    __shared__ double NR[kGMax * MMAX];  // gathered new rows, by position (a_{u,i} at MMAX-1)
+    __shared__ int8_t hpos[RSL ? 1 : CAP];                 // position of a member
+    __shared__ uint16_t SL[SLCAP];                         // table slots of the member rows' entries left of i
+    __shared__ double Lp_s[RSL ? 1 : LTRI];                // rows of L for the off-diagonal positions
+    __shared__ double NR_s[RSL ? 1 : kGMax * MMAX];        // gathered new rows, by position (a_{u,i} at MMAX-1)
+    extern __shared__ double lds_dyn[];                    // RSL: rows of L, sized by the launch
+    double *const Lp = RSL ? lds_dyn : Lp_s;
+    double *const NR = RSL ? hval : NR_s;
     __shared__ int32_t s_row;
 
     const int lane = threadIdx.x;
@@ -184,13 +204,19 @@ __global__ __launch_bounds__(64) void k_afsai_rows(
     const int64_t per = ((int64_t)nlist + nxcd - 1) / nxcd;
     const int q0 = (int)min<int64_t>(nlist, per * x), q1 = (int)min<int64_t>(nlist, per * (x + 1));
 
+    // rows are claimed `claim` at a time from the XCD's counter (one atomic per claim)
+    int qn = 0, qe = 0;
     for (;;) {
-        if (lane == 0) s_row = q0 + atomicAdd(&counters[x], 1);
-        __syncthreads();
-        const int q = s_row;
-        __syncthreads();
-        if (q >= q1) break;
-        const int i = list ? list[q] : q;
+        if (qn >= qe) {
+            if (lane == 0) s_row = q0 + atomicAdd(&counters[x], claim);
+            __syncthreads();
+            qn = s_row;
+            __syncthreads();
+            if (qn >= q1) break;
+            qe = min(qn + claim, q1);
+        }
+        const int i = list ? list[qn] : qn;
+        ++qn;
 
         // per-position state, lane t = position t (i at m-1): column, row start, number of
         // row entries left of column i, their offset in SL, scaled row value, reciprocal
@@ -222,7 +248,8 @@ __global__ __launch_bounds__(64) void k_afsai_rows(
             bool ovf = RSL ? ilen > 128 : ilen > SLCAP;
             for (int o = lane; o < ilen && !ovf; o += 64) {
                 bool tg;
-                const int slot = table_find<CAP>(hkey, (uint32_t)ci[ibeg + o], (uint32_t)ci[ibeg + o], true, tg);
+                uint32_t kf;
+                const int slot = table_find<CAP, KM>(hkey, (uint32_t)ci[ibeg + o], (uint32_t)ci[ibeg + o], true, tg, kf);
                 if (slot < 0) ovf = true;
                 else if constexpr (RSL) slr[0] |= (uint32_t)slot << (o >= 64 ? 16 : 0);
                 else SL[o] = (uint16_t)slot;
@@ -245,13 +272,13 @@ __global__ __launch_bounds__(64) void k_afsai_rows(
             __syncthreads();
             if constexpr (RSL) {
 #pragma unroll
-                for (int q0 = 0; q0 < MMAX; q0 += 4) {
+                for (int q0 = 0; q0 < MMAX; q0 += QB) {
                     if (q0 < m) {
-                        int sl[8];
-                        double aa[8], gg[4];
-                        int lens[4], begs[4];
+                        int sl[2 * QB];
+                        double aa[2 * QB], gg[QB];
+                        int lens[QB], begs[QB];
 #pragma unroll
-                        for (int u = 0; u < 4; ++u) {
+                        for (int u = 0; u < QB; ++u) {
                             const int q = q0 + u;
                             const int pos = (q == 0) ? m - 1 : q - 1;
                             lens[u] = 0;
@@ -274,7 +301,7 @@ __global__ __launch_bounds__(64) void k_afsai_rows(
                             }
                         }
 #pragma unroll
-                        for (int u = 0; u < 4; ++u)
+                        for (int u = 0; u < QB; ++u)
 #pragma unroll
                             for (int hh = 0; hh < 2; ++hh)
                                 if (sl[2 * u + hh] >= 0)
@@ -370,8 +397,12 @@ __global__ __launch_bounds__(64) void k_afsai_rows(
                         const uint64_t who = __ballot(myslot >= 0);
                         const int wslot = __builtin_amdgcn_readlane(myslot, (int)__builtin_ctzll(who));
                         if (lane == 0) {
-                            hkey[wslot] = js | kPBit;
-                            hpos[wslot] = (int8_t)(m - 1 + ns);
+                            if constexpr (RSL) {
+                                hkey[wslot] = js | kPBit | ((uint32_t)(m - 1 + ns) << 24);
+                            } else {
+                                hkey[wslot] = js | kPBit;
+                                hpos[wslot] = (int8_t)(m - 1 + ns);
+                            }
                         }
                         if (lane == ns) {
                             r_nb = rp[js];
@@ -413,8 +444,12 @@ __global__ __launch_bounds__(64) void k_afsai_rows(
                         const uint32_t js = wave_min_dpp(lb);
                         for (int j = lane; j < CAP; j += 64)
                             if (hkey[j] == js) {
-                                hkey[j] = js | kPBit;
-                                hpos[j] = (int8_t)(m - 1 + ns);
+                                if constexpr (RSL) {
+                                    hkey[j] = js | kPBit | ((uint32_t)(m - 1 + ns) << 24);
+                                } else {
+                                    hkey[j] = js | kPBit;
+                                    hpos[j] = (int8_t)(m - 1 + ns);
+                                }
                             }
                         if (lane == ns) {
                             r_nb = rp[js];
@@ -463,13 +498,14 @@ __global__ __launch_bounds__(64) void k_afsai_rows(
                         bool bad = false;
                         if (c < i) {
                             bool tg = false;
-                            const int slot = table_find<CAP>(hkey, (uint32_t)c, (uint32_t)c, true, tg);
+                            uint32_t kf = 0u;
+                            const int slot = table_find<CAP, KM>(hkey, (uint32_t)c, (uint32_t)c, true, tg, kf);
                             if (slot < 0) {
                                 bad = true;
                             } else {
                                 if constexpr (RSL) pk |= (uint32_t)slot << (16 * h);
                                 else SL[sl_used + o] = (uint16_t)slot;
-                                if (tg) NR[v * MMAX + hpos[slot]] = a;
+                                if (tg) NR[v * MMAX + (RSL ? (int)((kf >> 24) & 0x7Fu) : (int)hpos[slot])] = a;
                             }
                         }
                         nlo += __popcll(__ballot(c < i));
@@ -700,7 +736,7 @@ __global__ __launch_bounds__(64) void k_afsai_rows(
 }
 
 typedef void (*RowsKernel)(int, const int32_t *, const int32_t *, const double *, const double *, const int32_t *,
-                           int, int, double, double, int, const int32_t *, int, int32_t *, int, int32_t *, double *, int,
+                           int, int, double, double, int, const int32_t *, int, int32_t *, int, int, int32_t *, double *, int,
                            int32_t *, double *, int32_t *, int32_t *, int8_t *, int32_t *, int32_t *);
 
 template <int MMAX, bool RSL>
@@ -717,9 +753,14 @@ static RowsKernel rows_kernel_cap(int cap) {
     }
 }
 
-// LDS bytes of one k_afsai_rows<MMAX, CAP, RSL> block
-__host__ __forceinline__ size_t rows_lds_bytes(int mmax_t, int cap, bool rsl) {
-    const size_t slcap = rsl ? 1 : (cap >= 2048 ? 2 * (size_t)cap : 4 * (size_t)cap);
+// dynamic LDS bytes of one k_afsai_rows<MMAX, CAP, RSL> block (rows 0..mmax-2 of L; RSL only)
+__host__ __forceinline__ size_t rows_lds_dyn_bytes(int mmax, bool rsl) {
+    return rsl ? (size_t)(mmax > 1 ? mmax - 1 : 1) * (size_t)mmax / 2 * 8 + 8 : 0;
+}
+// LDS bytes of one k_afsai_rows<MMAX, CAP, RSL> block, static and dynamic
+__host__ __forceinline__ size_t rows_lds_bytes(int mmax_t, int mmax, int cap, bool rsl) {
+    if (rsl) return (size_t)cap * 12 + 2 + 8 + 8 + rows_lds_dyn_bytes(mmax, rsl) + 16;
+    const size_t slcap = cap >= 2048 ? 2 * (size_t)cap : 4 * (size_t)cap;
     return (size_t)cap * 13 + slcap * 2 + (size_t)mmax_t * (mmax_t - 1) / 2 * 8 + (size_t)kGMax * mmax_t * 8 + 16;
 }
 

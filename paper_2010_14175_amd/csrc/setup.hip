@@ -283,13 +283,15 @@ __global__ void k_block_check(int n, const int32_t *__restrict__ rp, const int32
 // fused per-row kernels, instantiated in rows.hip
 RowsKernel rows_kernel(int mmax_t, int cap, bool rsl);
 
-static int launch_rows(RowsKernel kern, int mmax_t, int cap, bool rsl, int gmax, const afsai_csr *A, const double *diag,
+static int launch_rows(RowsKernel kern, int mmax_t, int mmax, int cap, bool rsl, int gmax, const afsai_csr *A, const double *diag,
                        const int32_t *dlo, const afsai_params *p, const int32_t *list, int nlist, int32_t *counters,
                        int ldell, int32_t *ell_col, double *ell_val, int32_t *m, double *psi, int32_t *steps,
                        int32_t *reason, int8_t *st, int32_t *ovf_count, int32_t *ovf_list, const DeviceInfo &di,
                        hipStream_t s) {
-    const size_t lds = rows_lds_bytes(mmax_t, cap, rsl);
-    int per_cu = (int)((160 * 1024) / (lds + 256));
+    // resident rows per CU: LDS is allocated in 512-byte granules
+    const size_t lds = (rows_lds_bytes(mmax_t, mmax, cap, rsl) + 511) / 512 * 512;
+    const size_t dyn = rows_lds_dyn_bytes(mmax, rsl);
+    int per_cu = (int)((160 * 1024) / lds);
     if (per_cu > 32) per_cu = 32;
     if (per_cu < 1) per_cu = 1;
     int64_t nb = (int64_t)di.num_cus * per_cu;
@@ -297,11 +299,13 @@ static int launch_rows(RowsKernel kern, int mmax_t, int cap, bool rsl, int gmax,
     const int nx = di.num_xcds;
     nb = ((nb + nx - 1) / nx) * nx;
     if (nb < nx) nb = nx;
+    // rows per claim: about 1/128 of a resident row-slot's share, 1..16 (the tail stays short)
+    int claim = (int)std::min<int64_t>(16, std::max<int64_t>(1, nlist / (nb * 128)));
     hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, (int64_t)nx, counters, 0);
     {
         ProfScope ps("afsai_rows", s);
-        hipLaunchKernelGGL(kern, dim3((unsigned)nb), dim3(64), 0, s, A->n, A->row_ptr, A->col_idx, A->val, diag, dlo,
-                           p->kmax, p->s, p->eps, p->tie_rtol, gmax, list, nlist, counters, nx, ell_col, ell_val,
+        hipLaunchKernelGGL(kern, dim3((unsigned)nb), dim3(64), dyn, s, A->n, A->row_ptr, A->col_idx, A->val, diag, dlo,
+                           p->kmax, p->s, p->eps, p->tie_rtol, gmax, list, nlist, counters, nx, claim, ell_col, ell_val,
                            ldell, m, psi, steps, reason, st, ovf_count, ovf_list);
     }
     AFSAI_HIP_TRY(hipGetLastError());
@@ -459,8 +463,11 @@ static int setup_core(const afsai_csr *A, const afsai_params *p, int nsys, const
     // slot lists in registers where every row has at most 128 entries and the pattern at most
     // 32 positions (more rows resident per CU), else in LDS
     const int64_t slopt = option(AFSAI_OPT_SETUP_SLOTS);
-    const bool rsl = slopt == 1 ? false : (maxlen <= 128 && mmax_t <= 32);
-    if (slopt == 2 && !rsl) AFSAI_FAIL(AFSAI_ERR_INVALID_ARG, "afsai_setup: register slot lists need rows of at most 128 entries and 1 + k_max * s <= 32");
+    const bool rsl = slopt == 1 ? false : (maxlen <= 128 && mmax_t <= 32 && n <= (1 << 24));
+    if (slopt == 2 && !rsl)
+        AFSAI_FAIL(AFSAI_ERR_INVALID_ARG,
+                   "afsai_setup: register slot lists need rows of at most 128 entries, 1 + k_max * s <= 32 "
+                   "and n <= 2^24");
     int cap2 = pow2ceil(bound + 1);
     if (cap2 < cap1) cap2 = cap1;
     if (cap2 > 8192) cap2 = 8192;
@@ -482,7 +489,7 @@ static int setup_core(const afsai_csr *A, const afsai_params *p, int nsys, const
 
     RowsKernel k1 = rows_kernel(mmax_t, cap1, rsl);
     if (!k1) AFSAI_FAIL(AFSAI_ERR_TOO_LARGE, "afsai_setup: no kernel for pattern %d / table %d", mmax_t, cap1);
-    if ((rc = launch_rows(k1, mmax_t, cap1, rsl, gmax, A, diagb.as<double>(), dlob.as<int32_t>(), p, nullptr, n, ctr.as<int32_t>(), ldell,
+    if ((rc = launch_rows(k1, mmax_t, mmax, cap1, rsl, gmax, A, diagb.as<double>(), dlob.as<int32_t>(), p, nullptr, n, ctr.as<int32_t>(), ldell,
                           ell_col.as<int32_t>(), ell_val.as<double>(), mcnt.as<int32_t>(), psi.as<double>(),
                           steps.as<int32_t>(), reason.as<int32_t>(), st.as<int8_t>(), ovf_count, ovf.as<int32_t>(), di,
                           s)))
@@ -501,7 +508,7 @@ static int setup_core(const afsai_csr *A, const afsai_params *p, int nsys, const
         hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, (int64_t)1, cnt2, 0);
         RowsKernel k2 = rows_kernel(mmax_t, cap2, rsl);
         if (!k2) AFSAI_FAIL(AFSAI_ERR_TOO_LARGE, "afsai_setup: no kernel for table %d", cap2);
-        if ((rc = launch_rows(k2, mmax_t, cap2, rsl, gmax, A, diagb.as<double>(), dlob.as<int32_t>(), p, list2.as<int32_t>(), novf,
+        if ((rc = launch_rows(k2, mmax_t, mmax, cap2, rsl, gmax, A, diagb.as<double>(), dlob.as<int32_t>(), p, list2.as<int32_t>(), novf,
                               ctr.as<int32_t>(), ldell, ell_col.as<int32_t>(), ell_val.as<double>(), mcnt.as<int32_t>(),
                               psi.as<double>(), steps.as<int32_t>(), reason.as<int32_t>(), st.as<int8_t>(), cnt2,
                               ovf.as<int32_t>(), di, s)))
