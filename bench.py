@@ -194,6 +194,56 @@ def serve_bench(args):
     print(json.dumps(out), flush=True)
 
 
+def jacobi_bench(args):
+    """aFSAI against Jacobi (k_max = 0: G = D^-1/2, M^-1 = D^-1) time to solution, rtol 1e-8,
+    x0 = 0, on the 7-point 20^3 and 121^3 problems, the 27-point 64^3 workload and, with
+    --with-largest, the 27-point 150^3 one.  One step = setup + PCG; median of the steps."""
+    import torch
+
+    import paper_2010_14175_amd as af
+
+    names = ["poisson7_20", "poisson7_121", "elast27_64"] + (["elast27_150"] if args.with_largest else [])
+    res = {}
+    for name in names:
+        pb = workloads()[name]()
+        g_prec = af.F32 if name == "elast27_150" else af.F64
+        dA = af.DeviceCSR.from_host(pb.A)
+        b = torch.from_numpy(pb.b).cuda()
+        x = torch.zeros_like(b)
+        row = {"n": pb.n, "nnz": pb.A.nnz}
+        for label, kmax in (("afsai", pb.kmax), ("jacobi", 0)):
+            tot, st, pc, its = [], [], [], 0
+            for k in range(args.warmup + args.steps):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                P = af.setup(dA, kmax, pb.s, pb.eps, g_prec=g_prec)
+                x.zero_()
+                _, info = af.pcg_solve(dA, P, b, x=x, rtol=pb.rtol, maxit=20 * pb.n)
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                sinfo = P.info()
+                P.close()
+                if k >= args.warmup:
+                    tot.append((t1 - t0) * 1e3)
+                    st.append(sinfo.ms)
+                    pc.append(info.ms)
+                its = info.iters
+            row[label] = {"ms": round(float(np.median(tot)), 3), "setup_ms": round(float(np.median(st)), 3),
+                          "pcg_ms": round(float(np.median(pc)), 3), "iters": its, "nnz_g": sinfo.nnz_g,
+                          "true_relres": info.true_relres, "converged": info.converged}
+            print(f"[bench] {name} {label}: {row[label]['ms']:.2f} ms (setup {row[label]['setup_ms']:.2f}, pcg "
+                  f"{row[label]['pcg_ms']:.2f}), {its} iterations, true relres {info.true_relres:.2e}",
+                  file=sys.stderr, flush=True)
+        row["time_ratio"] = round(row["jacobi"]["ms"] / row["afsai"]["ms"], 3)
+        row["iter_ratio"] = round(row["jacobi"]["iters"] / max(1, row["afsai"]["iters"]), 3)
+        res[name] = row
+    out = {"metric": "time to solution, Jacobi-PCG / aFSAI-PCG (rtol 1e-8)", "value": res["elast27_64"]["time_ratio"],
+           "unit": "ratio", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "higher_is_better": True,
+           "vs_baseline": None, "dtype": "f64", "data": "synthetic", "config": {"workload": "jacobi_compare"},
+           "results": res}
+    print(json.dumps(out), flush=True)
+
+
 def workloads():
     import synth
 
@@ -299,7 +349,8 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="elast27_64",
-                    choices=sorted(list(workloads()) + list(BATCH_WORKLOADS) + ["serve"]))
+                    choices=sorted(list(workloads()) + list(BATCH_WORKLOADS) + ["serve", "jacobi_compare"]))
+    ap.add_argument("--with-largest", action="store_true", help="jacobi_compare: add the 150^3 27-point workload")
     ap.add_argument("--requests", type=int, default=300, help="serve: number of requests")
     ap.add_argument("--pool", type=int, default=16, help="serve: distinct systems the requests draw from")
     ap.add_argument("--budget-gb", type=int, default=96, help="serve: device memory budget of the servers")
@@ -334,6 +385,9 @@ def main():
         return
     if args.workload == "serve":
         serve_bench(args)
+        return
+    if args.workload == "jacobi_compare":
+        jacobi_bench(args)
         return
     pb = workloads()[args.workload]()
     g_prec = af.F32 if args.g_prec == "f32" else af.F64

@@ -307,7 +307,7 @@ const char *afsai_last_error(void);
  *                             identical.
  *   AFSAI_OPT_SETUP_SLOTS     where the setup kernel keeps the table slots of the pattern rows'
  *                             entries: 0 automatic (registers when every row of A has at most
- *                             128 entries and 1 + k_max * s <= 32, else LDS), 1 LDS, 2 registers
+ *                             128 entries and n <= 2^24, else LDS), 1 LDS, 2 registers
  *                             (AFSAI_ERR_INVALID_ARG from afsai_setup when not possible)
  * Returns AFSAI_ERR_INVALID_ARG for an unknown option or value.  Not thread safe against
  * concurrent calls of the library.

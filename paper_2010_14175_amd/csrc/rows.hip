@@ -1,6 +1,5 @@
 // Instantiations of the fused per-row setup kernel: pattern capacity 8..64 (LDS sizing of the
-// factor) times candidate table 128..8192 slots, with slot lists in LDS, or in registers for
-// patterns of at most 32 positions.
+// factor) times candidate table 128..8192 slots, with slot lists in LDS or in registers.
 #include "rows.hpp"
 
 namespace afsai {
@@ -12,6 +11,8 @@ RowsKernel rows_kernel(int mmax_t, int cap, bool rsl) {
             case 16: return rows_kernel_cap<16, true>(cap);
             case 24: return rows_kernel_cap<24, true>(cap);
             case 32: return rows_kernel_cap<32, true>(cap);
+            case 48: return rows_kernel_cap<48, true>(cap);
+            case 64: return rows_kernel_cap<64, true>(cap);
             default: return nullptr;
         }
     }

@@ -168,10 +168,12 @@ constexpr int sl_cap() { return CAP >= 2048 ? 2 * CAP : 4 * CAP; }
 // which frees LDS for more resident rows; in this form a member's position is kept in its table
 // key (columns below 2^24), the gathered rows share the gradient's array (not in use from the
 // selection to the next product pass) and the rows of L are sized by the launch (dynamic LDS).
-// The register-list form fits 20 rows per CU in LDS (at most 512 table slots); the register
-// budget is set for 5 waves per SIMD to match, measured faster than 4 waves without spills.
+// Register budget of the register-list form: patterns of at most 32 positions with at most 512
+// table slots fit 20 rows per CU in LDS, and 5 waves per SIMD measured faster than 4 without
+// spills; the smallest patterns target 8.  Larger patterns and tables are limited by LDS, and
+// the compiler keeps all their registers.
 template <int MMAX, int CAP, bool RSL>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(!RSL ? 1 : (MMAX <= 8 && CAP <= 256) ? 8 : (CAP <= 512 ? 5 : 1), 8))) void k_afsai_rows(
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(!RSL ? 1 : (MMAX <= 8 && CAP <= 256) ? 8 : ((MMAX <= 32 && CAP <= 512) ? 5 : 1), 8))) void k_afsai_rows(
     int n, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci, const double *__restrict__ av,
     const double *__restrict__ diag, const int32_t *__restrict__ dlo, int kmax, int s, double eps, double tau,
     int gmax, const int32_t *__restrict__ list, int nlist, int32_t *__restrict__ counters, int nxcd, int claim,
@@ -179,8 +181,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(!RSL ? 1 : (
     double *__restrict__ psi_out, int32_t *__restrict__ steps_out, int32_t *__restrict__ reason_out,
     int8_t *__restrict__ status_out, int32_t *__restrict__ ovf_count, int32_t *__restrict__ ovf_list) {
     static_assert(MMAX <= 64, "one lane per pattern position");
-    static_assert(!RSL || MMAX <= 32, "register slot lists for at most 32 positions");
-    static_assert(!RSL || CAP >= kGMax * MMAX, "gathered rows fit in the gradient array");
+    static_assert(!RSL || MMAX <= 64, "positions fit the 7-bit field of a key");
+    constexpr bool NR_ALIAS = RSL && CAP >= kGMax * MMAX;  // gathered rows in the gradient array
     constexpr uint32_t KM = RSL ? kCol24 : ~kPBit;
     constexpr int QB = kProdBatch;  // members whose entries one product round loads together (RSL)
     constexpr int K = (MMAX + 1 + 63) / 64;        // update entries per lane
@@ -193,10 +195,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(!RSL ? 1 : (
     __shared__ int8_t hpos[RSL ? 1 : CAP];                 // position of a member
     __shared__ uint16_t SL[SLCAP];                         // table slots of the member rows' entries left of i
     __shared__ double Lp_s[RSL ? 1 : LTRI];                // rows of L for the off-diagonal positions
-    __shared__ double NR_s[RSL ? 1 : kGMax * MMAX];        // gathered new rows, by position (a_{u,i} at MMAX-1)
+    __shared__ double NR_s[NR_ALIAS ? 1 : kGMax * MMAX];   // gathered new rows, by position (a_{u,i} at MMAX-1)
     extern __shared__ double lds_dyn[];                    // RSL: rows of L, sized by the launch
     double *const Lp = RSL ? lds_dyn : Lp_s;
-    double *const NR = RSL ? hval : NR_s;
+    double *const NR = NR_ALIAS ? hval : NR_s;
     __shared__ int32_t s_row;
 
     const int lane = threadIdx.x;
@@ -759,7 +761,10 @@ __host__ __forceinline__ size_t rows_lds_dyn_bytes(int mmax, bool rsl) {
 }
 // LDS bytes of one k_afsai_rows<MMAX, CAP, RSL> block, static and dynamic
 __host__ __forceinline__ size_t rows_lds_bytes(int mmax_t, int mmax, int cap, bool rsl) {
-    if (rsl) return (size_t)cap * 12 + 2 + 8 + 8 + rows_lds_dyn_bytes(mmax, rsl) + 16;
+    if (rsl) {
+        const size_t nr = (size_t)cap >= (size_t)kGMax * mmax_t ? 8 : (size_t)kGMax * mmax_t * 8;
+        return (size_t)cap * 12 + 2 + 8 + nr + rows_lds_dyn_bytes(mmax, rsl) + 16;
+    }
     const size_t slcap = cap >= 2048 ? 2 * (size_t)cap : 4 * (size_t)cap;
     return (size_t)cap * 13 + slcap * 2 + (size_t)mmax_t * (mmax_t - 1) / 2 * 8 + (size_t)kGMax * mmax_t * 8 + 16;
 }

@@ -283,7 +283,7 @@ __global__ void k_block_check(int n, const int32_t *__restrict__ rp, const int32
 // fused per-row kernels, instantiated in rows.hip
 RowsKernel rows_kernel(int mmax_t, int cap, bool rsl);
 
-static int launch_rows(RowsKernel kern, int mmax_t, int mmax, int cap, bool rsl, int gmax, const afsai_csr *A, const double *diag,
+static int launch_rows(RowsKernel kern, int mmax_t, int mmax, int64_t row_work, int cap, bool rsl, int gmax, const afsai_csr *A, const double *diag,
                        const int32_t *dlo, const afsai_params *p, const int32_t *list, int nlist, int32_t *counters,
                        int ldell, int32_t *ell_col, double *ell_val, int32_t *m, double *psi, int32_t *steps,
                        int32_t *reason, int8_t *st, int32_t *ovf_count, int32_t *ovf_list, const DeviceInfo &di,
@@ -299,8 +299,11 @@ static int launch_rows(RowsKernel kern, int mmax_t, int mmax, int cap, bool rsl,
     const int nx = di.num_xcds;
     nb = ((nb + nx - 1) / nx) * nx;
     if (nb < nx) nb = nx;
-    // rows per claim: about 1/128 of a resident row-slot's share, 1..16 (the tail stays short)
-    int claim = (int)std::min<int64_t>(16, std::max<int64_t>(1, nlist / (nb * 128)));
+    // rows per claim (one atomic on the XCD's counter each): enough rows for about 4,000 table
+    // entries of work, 1..16, and at most a quarter of a resident row-slot's share (short tail)
+    int64_t claim64 = (4000 + row_work - 1) / std::max<int64_t>(1, row_work);
+    claim64 = std::min<int64_t>(claim64, std::max<int64_t>(1, nlist / (nb * 4)));
+    const int claim = (int)std::min<int64_t>(16, std::max<int64_t>(1, claim64));
     hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, (int64_t)nx, counters, 0);
     {
         ProfScope ps("afsai_rows", s);
@@ -460,14 +463,13 @@ static int setup_core(const afsai_csr *A, const afsai_params *p, int nsys, const
     if (option(AFSAI_OPT_SETUP_TABLE) > 0) cap1 = pow2ceil(option(AFSAI_OPT_SETUP_TABLE));
     if (cap1 < 128) cap1 = 128;
     if (cap1 > 1024) cap1 = 1024;
-    // slot lists in registers where every row has at most 128 entries and the pattern at most
-    // 32 positions (more rows resident per CU), else in LDS
+    // slot lists in registers where every row has at most 128 entries (more rows resident per
+    // CU), else in LDS
     const int64_t slopt = option(AFSAI_OPT_SETUP_SLOTS);
-    const bool rsl = slopt == 1 ? false : (maxlen <= 128 && mmax_t <= 32 && n <= (1 << 24));
+    const bool rsl = slopt == 1 ? false : (maxlen <= 128 && n <= (1 << 24));
     if (slopt == 2 && !rsl)
         AFSAI_FAIL(AFSAI_ERR_INVALID_ARG,
-                   "afsai_setup: register slot lists need rows of at most 128 entries, 1 + k_max * s <= 32 "
-                   "and n <= 2^24");
+                   "afsai_setup: register slot lists need rows of at most 128 entries and n <= 2^24");
     int cap2 = pow2ceil(bound + 1);
     if (cap2 < cap1) cap2 = cap1;
     if (cap2 > 8192) cap2 = 8192;
@@ -489,7 +491,9 @@ static int setup_core(const afsai_csr *A, const afsai_params *p, int nsys, const
 
     RowsKernel k1 = rows_kernel(mmax_t, cap1, rsl);
     if (!k1) AFSAI_FAIL(AFSAI_ERR_TOO_LARGE, "afsai_setup: no kernel for pattern %d / table %d", mmax_t, cap1);
-    if ((rc = launch_rows(k1, mmax_t, mmax, cap1, rsl, gmax, A, diagb.as<double>(), dlob.as<int32_t>(), p, nullptr, n, ctr.as<int32_t>(), ldell,
+    // table entries one row touches over its steps (bound per step times k_max, plus its own row)
+    const int64_t row_work = (int64_t)p->kmax * bound + maxlen;
+    if ((rc = launch_rows(k1, mmax_t, mmax, row_work, cap1, rsl, gmax, A, diagb.as<double>(), dlob.as<int32_t>(), p, nullptr, n, ctr.as<int32_t>(), ldell,
                           ell_col.as<int32_t>(), ell_val.as<double>(), mcnt.as<int32_t>(), psi.as<double>(),
                           steps.as<int32_t>(), reason.as<int32_t>(), st.as<int8_t>(), ovf_count, ovf.as<int32_t>(), di,
                           s)))
@@ -508,7 +512,7 @@ static int setup_core(const afsai_csr *A, const afsai_params *p, int nsys, const
         hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, (int64_t)1, cnt2, 0);
         RowsKernel k2 = rows_kernel(mmax_t, cap2, rsl);
         if (!k2) AFSAI_FAIL(AFSAI_ERR_TOO_LARGE, "afsai_setup: no kernel for table %d", cap2);
-        if ((rc = launch_rows(k2, mmax_t, mmax, cap2, rsl, gmax, A, diagb.as<double>(), dlob.as<int32_t>(), p, list2.as<int32_t>(), novf,
+        if ((rc = launch_rows(k2, mmax_t, mmax, row_work, cap2, rsl, gmax, A, diagb.as<double>(), dlob.as<int32_t>(), p, list2.as<int32_t>(), novf,
                               ctr.as<int32_t>(), ldell, ell_col.as<int32_t>(), ell_val.as<double>(), mcnt.as<int32_t>(),
                               psi.as<double>(), steps.as<int32_t>(), reason.as<int32_t>(), st.as<int8_t>(), cnt2,
                               ovf.as<int32_t>(), di, s)))

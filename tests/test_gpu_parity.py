@@ -195,7 +195,9 @@ def test_setup_forms_identical(af, make, kmax, s):
 
 @pytest.mark.parametrize("slots", [1, 2])
 @pytest.mark.parametrize("make,kmax,s", [(lambda: synth.elast27(12, 1.0, 2), 10, 2), (lambda: synth.lap7(16), 5, 1),
-                                         (lambda: synth.random_sparse_spd(3000, 40, 3), 10, 3)])
+                                         (lambda: synth.random_sparse_spd(3000, 40, 3), 10, 3),
+                                         (lambda: synth.elast27(7, 2.0, 5), 15, 3),
+                                         (lambda: synth.elast27(6, 1.0, 3), 21, 3)])
 def test_setup_slot_lists(af, slots, make, kmax, s):
     """The table slots of the pattern rows' entries kept in LDS (1) or in registers (2): both
     give the oracle's patterns and values (bitwise here), and equal each other bit for bit."""
@@ -214,14 +216,15 @@ def test_setup_slot_lists(af, slots, make, kmax, s):
 
 
 def test_setup_slot_lists_refused(af):
-    """Register slot lists need at most 32 pattern positions: asked for with k_max * s = 45 the
-    setup reports an invalid argument instead of running."""
-    A = synth.elast27(5, 1.0, 2)
+    """Register slot lists need rows of at most 128 entries: asked for on a matrix with longer
+    rows the setup reports an invalid argument instead of running."""
+    A = synth.random_sparse_spd(2000, 90, 4)
+    assert np.diff(A.row_ptr).max() > 128
     dA = _dev(af, A)
     try:
         af.set_option(af.OPT_SETUP_SLOTS, 2)
         with pytest.raises(af.AfsaiError) as e:
-            af.setup(dA, 15, 3, 1e-2)
+            af.setup(dA, 2, 1, 1e-2)
         assert e.value.code == af.ERR_INVALID_ARG
     finally:
         af.set_option(af.OPT_SETUP_SLOTS, 0)
