@@ -335,6 +335,10 @@ typedef struct afsai_kernel_time {
 } afsai_kernel_time;
 
 int afsai_profile_enable(int32_t on);
+/* restricts the timing to the kernels named in `names` (comma-separated timer names such as
+ * "afsai_rows,spmv_A_dot", host string); NULL or "" times every kernel again.  The other
+ * kernels then run without events, so the timed ones are measured inside an undisturbed run. */
+int afsai_profile_only(const char *names);
 /* copies up to cap entries into out (host), sets *count; reset != 0 clears the counters */
 int afsai_profile_read(afsai_kernel_time *out, int32_t cap, int32_t *count, int32_t reset);
 

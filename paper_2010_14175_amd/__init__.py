@@ -34,7 +34,7 @@ EXPORTS = ("afsai_setup", "afsai_apply", "pcg_solve", "afsai_setup_batched", "pc
            "afsai_get_setup_info", "afsai_export",
            "afsai_export_rows", "afsai_import", "afsai_destroy", "afsai_last_error", "afsai_set_option",
            "afsai_release_cache",
-           "afsai_profile_enable", "afsai_profile_read")
+           "afsai_profile_enable", "afsai_profile_only", "afsai_profile_read")
 (OPT_SETUP_GROUP, OPT_SETUP_TABLE, OPT_SPMV_GROUP, OPT_SPMV_UNROLL, OPT_PCG_CSR_A, OPT_PCG_FORM,
  OPT_SELL_WIDTH, OPT_PCG_GRAPH, OPT_SETUP_SLOTS) = 1, 2, 3, 4, 5, 6, 7, 8, 9
 
@@ -120,6 +120,7 @@ def lib():
         L.afsai_last_error.restype = ctypes.c_char_p
         L.afsai_set_option.argtypes = [i32, ctypes.c_int64]
         L.afsai_profile_enable.argtypes = [i32]
+        L.afsai_profile_only.argtypes = [ctypes.c_char_p]
         L.afsai_profile_read.argtypes = [P(KernelTimeStruct), i32, P(i32), i32]
         for name in EXPORTS:
             if name not in ("afsai_destroy", "afsai_last_error"):
@@ -438,6 +439,12 @@ def set_option(option: int, value: int):
 
 def profile_enable(on: bool = True):
     _check(lib().afsai_profile_enable(1 if on else 0), "afsai_profile_enable")
+
+
+def profile_only(names=None):
+    """Times only the kernels named (``afsai_profile_only``); None times all of them."""
+    arg = None if not names else ",".join(names).encode()
+    _check(lib().afsai_profile_only(arg), "afsai_profile_only")
 
 
 def profile_read(reset: bool = False) -> dict:

@@ -212,7 +212,7 @@ __device__ __forceinline__ int wave_scan_dpp(int v) {
 // ---------------------------------------------------------------------------------------
 bool profiling_on();
 // records a start event on `s` and returns a token (or -1 when profiling is off)
-int prof_begin(hipStream_t s);
+int prof_begin(const char *name, hipStream_t s);
 void prof_end(int token, const char *name, hipStream_t s);
 // resolves pending events (called at synchronisation points)
 void prof_flush();
@@ -225,7 +225,7 @@ struct ProfScope {
     int tok;
     const char *name;
     hipStream_t s;
-    ProfScope(const char *n, hipStream_t st) : tok(prof_begin(st)), name(n), s(st) {}
+    ProfScope(const char *n, hipStream_t st) : tok(prof_begin(n, st)), name(n), s(st) {}
     ~ProfScope() { prof_end(tok, name, s); }
 };
 

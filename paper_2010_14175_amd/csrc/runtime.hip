@@ -142,6 +142,7 @@ struct Acc {
 };
 std::mutex prof_mu;
 bool prof_enabled = false;
+std::vector<std::string> prof_only;  // kernel names to time; empty: all
 std::vector<hipEvent_t> event_pool;
 std::vector<hipEvent_t> started;  // token -> start event
 std::vector<Pending> pending;
@@ -164,9 +165,14 @@ bool profiling_on() {
     return prof_enabled;
 }
 
-int prof_begin(hipStream_t s) {
+int prof_begin(const char *name, hipStream_t s) {
     std::lock_guard<std::mutex> lk(prof_mu);
     if (!prof_enabled) return -1;
+    if (!prof_only.empty()) {
+        bool hit = false;
+        for (const std::string &k : prof_only) hit = hit || (name && k == name);
+        if (!hit) return -1;
+    }
     hipEvent_t e = get_event();
     if (!e) return -1;
     if (hipEventRecord(e, s) != hipSuccess) {
@@ -270,6 +276,25 @@ int afsai_profile_enable(int32_t on) {
     afsai::prof_flush();
     std::lock_guard<std::mutex> lk(afsai::prof_mu);
     afsai::prof_enabled = (on != 0);
+    return AFSAI_OK;
+}
+
+int afsai_profile_only(const char *names) {
+    std::vector<std::string> v;
+    if (names) {
+        std::string cur;
+        for (const char *c = names;; ++c) {
+            if (*c == ',' || *c == '\0') {
+                if (!cur.empty()) v.push_back(cur);
+                cur.clear();
+                if (*c == '\0') break;
+            } else {
+                cur.push_back(*c);
+            }
+        }
+    }
+    std::lock_guard<std::mutex> lk(afsai::prof_mu);
+    afsai::prof_only = v;
     return AFSAI_OK;
 }
 
