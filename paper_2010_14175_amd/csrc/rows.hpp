@@ -481,6 +481,71 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(!RSL ? 1 : (
                 // their entries left of i are entered in the table and their slots listed
                 for (int j = lane; j < G * MMAX; j += 64) NR[j] = 0.0;
                 __syncthreads();
+                if constexpr (RSL && MMAX >= 16) {
+                    // rows of at most 128 entries: every new row's entries are loaded first, so
+                    // that their latencies overlap, then entered in the table (not for the
+                    // smallest patterns, whose registers it would spill)
+                    int gnb[kGMax], gnl[kGMax], gc[kGMax][2];
+                    double ga[kGMax][2];
+#pragma unroll
+                    for (int v = 0; v < kGMax; ++v) {
+                        gnb[v] = 0;
+                        gnl[v] = 0;
+                        if (v < G) {
+                            gnb[v] = __builtin_amdgcn_readlane(r_nb, v0 + v);
+                            gnl[v] = __builtin_amdgcn_readlane(r_ne, v0 + v) - gnb[v];
+                        }
+                        if (gnl[v] > 128) ovf = true;  // uniform
+#pragma unroll
+                        for (int h = 0; h < 2; ++h) {
+                            const int o = h * 64 + lane;
+                            gc[v][h] = 0x7fffffff;
+                            ga[v][h] = 0.0;
+                            if (o < gnl[v] && o < 128) {
+                                gc[v][h] = ci[gnb[v] + o];
+                                ga[v][h] = av[gnb[v] + o];
+                            }
+                        }
+                    }
+#pragma unroll
+                    for (int v = 0; v < kGMax; ++v) {
+                        if (v < G && !ovf) {
+                            int nlo = 0;
+                            uint32_t pk = 0u;
+#pragma unroll
+                            for (int h = 0; h < 2; ++h) {
+                                if (h * 64 < gnl[v]) {
+                                    const int c = gc[v][h];
+                                    const double a = ga[v][h];
+                                    if (c == i) NR[v * MMAX + (MMAX - 1)] = a;
+                                    bool bad = false;
+                                    if (c < i) {
+                                        bool tg = false;
+                                        uint32_t kf = 0u;
+                                        const int slot =
+                                            table_find<CAP, KM>(hkey, (uint32_t)c, (uint32_t)c, true, tg, kf);
+                                        if (slot < 0) {
+                                            bad = true;
+                                        } else {
+                                            pk |= (uint32_t)slot << (16 * h);
+                                            if (tg) NR[v * MMAX + (int)((kf >> 24) & 0x7Fu)] = a;
+                                        }
+                                    }
+                                    nlo += __popcll(__ballot(c < i));
+                                    if (__ballot(bad)) ovf = true;
+                                }
+                            }
+                            if (lane == mb + v) {
+                                r_beg = gnb[v];
+                                r_len = nlo;
+                            }
+                            const int qn = mb + v + 1;  // member of position mb + v
+#pragma unroll
+                            for (int qq = 1; qq < (RSL ? MMAX : 1); ++qq)
+                                if (qq == qn) slr[qq] = pk;
+                        }
+                    }
+                } else
                 for (int v = 0; v < G; ++v) {
                     const int nb = __builtin_amdgcn_readlane(r_nb, v0 + v);
                     const int nl = __builtin_amdgcn_readlane(r_ne, v0 + v) - nb;
