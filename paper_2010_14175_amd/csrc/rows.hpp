@@ -102,60 +102,63 @@ __device__ __forceinline__ double rl(double v, int src) {
     return __hiloint2double(hi, lo);
 }
 
-// entries of one factor update that appends g rows to mb final rows: row v of the new ones
-// has columns 0..mb+v, the last row (i) has the g new columns and its diagonal
-__host__ __device__ __forceinline__ int upd_entries(int mb, int g) { return g * (mb + 1) + (g * (g - 1)) / 2 + g + 1; }
-// index of entry (v, c) of new row v, and of the last row's entry at column mb + d
-__device__ __forceinline__ int upd_index(int mb, int v, int c) { return v * (mb + 1) + (v * (v - 1)) / 2 + c; }
-
-// entry e of the update entries held K per lane (lane e % 64, register e / 64): read as a
-// uniform value, and replaced in its owner lane
-template <int K>
-__device__ __forceinline__ double ent_get(const double (&run)[K], int e) {
-    if constexpr (K == 1) {
-        return rl(run[0], e);
-    } else {
-        return (e < 64) ? rl(run[0], e) : rl(run[1], e - 64);
-    }
-}
-template <int K>
-__device__ __forceinline__ void ent_set(double (&run)[K], int e, double v, int lane) {
+// One factor update that appends G rows (positions mb .. mb+G-1; the rows of L for the positions
+// below mb are final) and moves the last row (row i) behind them.  Lane l holds column l: R[v]
+// the running value of entry (mb + v, l) and, for the new columns l >= mb, R[GA] the running
+// value of entry (i, l).  Columns are taken left to right; column j's values of the new rows
+// (and of row i) are scaled by the pivot reciprocal, broadcast, and every entry right of column
+// j receives its product term (right-looking), so each entry gets the operations of a
+// column-by-column factorisation in the same order.  Column j of the new rows goes to Lp; the
+// last row's entries of the old columns are final already and its diagonal `di` receives the
+// squares of its new entries.  Returns false on a pivot that is not positive.
+template <int G, int GA>
+__device__ __forceinline__ bool upd_lanes(int mb, double (&R)[GA + 1], double &r_dinv, double &r_li, double &di,
+                                          double *Lp, int lane) {
+    static_assert(G <= GA, "group fits the register array");
+    const int m1 = mb + G;  // position of i after the update
+    const int rowbase = tri(lane, 0);
+    for (int j = 0; j < m1; ++j) {
+        double U[G], A;
+        if (j < mb) {
+            const double dj = rl(r_dinv, j);
 #pragma unroll
-    for (int kk = 0; kk < K; ++kk) run[kk] = (lane == e - 64 * kk) ? v : run[kk];
-}
-
-// Columns j < mb of one factor update that appends G rows (the rows of L for positions below
-// mb are final): column j of each new row is scaled by the pivot reciprocal, and every entry
-// right of column j receives its product term (right-looking).  The last row's entries for
-// these columns are final already; its new-column entries are updated, its diagonal is not.
-template <int G, int K>
-__device__ __forceinline__ void upd_old_columns(int mb, const int (&base)[kGMax], const int (&er)[K],
-                                                const int (&ec)[K], double (&run)[K], double r_dinv, double r_li,
-                                                const double *Lp, int lane) {
-    for (int j = 0; j < mb; ++j) {
-        const double dj = rl(r_dinv, j);
-        double U[G + 1];
+            for (int v = 0; v < G; ++v) U[v] = rl(R[v], j) * dj;
+            A = rl(r_li, j);
+        } else {
+            // pivot of new row w = j - mb: its diagonal entry has all its terms
+            const int w = j - mb;
+            double xd = 0.0;
 #pragma unroll
-        for (int v = 0; v < G; ++v) {
-            const int e = base[v] + j;
-            U[v] = ent_get<K>(run, e) * dj;
-            ent_set<K>(run, e, U[v], lane);
+            for (int v = 0; v < G; ++v)
+                if (v == w) xd = rl(R[v], j);
+            if (!(xd > 0.0) || !isfinite(xd)) return false;
+            const double Ljj = sqrt(xd);
+            const double dj = 1.0 / Ljj;
+#pragma unroll
+            for (int v = 0; v < G; ++v) U[v] = (v == w) ? Ljj : rl(R[v], j) * dj;  // rows v < w unused
+            A = rl(R[GA], j) * dj;                                                   // L[i][j]
+            if (lane == j) {
+                r_dinv = dj;
+                r_li = A;
+            }
+            di = di - A * A;
         }
-        U[G] = rl(r_li, j);
+        if (lane == 0) {
 #pragma unroll
-        for (int kk = 0; kk < K; ++kk) {
-            const int r = er[kk], c = ec[kk];
-            const bool upd = (r >= 0) && (c > j) && !(r == G && c == mb + G);
-            double a = U[G];
+            for (int v = 0; v < G; ++v)
+                if (j < mb + v + 1) Lp[tri(mb + v, j)] = U[v];
+        }
+        if (lane > j && lane < m1) {
+            double b = (lane < mb) ? Lp[rowbase + j] : U[0];
 #pragma unroll
-            for (int v = 0; v < G; ++v) a = (r == v) ? U[v] : a;
-            double b = Lp[(upd && c < mb) ? tri(c, j) : 0];
+            for (int v = 1; v < G; ++v)
+                if (lane == mb + v) b = U[v];
 #pragma unroll
-            for (int v = 0; v < G; ++v) b = (c - mb == v) ? U[v] : b;
-            const double nv = run[kk] - a * b;
-            run[kk] = upd ? nv : run[kk];
+            for (int v = 0; v < G; ++v) R[v] = R[v] - U[v] * b;
+            R[GA] = R[GA] - A * b;
         }
     }
+    return true;
 }
 
 // Slot-list entries per table slot: each member row's entries left of column i are looked up
@@ -185,7 +188,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(!RSL ? 1 : (
     constexpr bool NR_ALIAS = RSL && CAP >= kGMax * MMAX;  // gathered rows in the gradient array
     constexpr uint32_t KM = RSL ? kCol24 : ~kPBit;
     constexpr int QB = kProdBatch;  // members whose entries one product round loads together (RSL)
-    constexpr int K = (MMAX + 1 + 63) / 64;        // update entries per lane
+    constexpr int GCAP = MMAX <= 8 ? 2 : kGMax;  // rows one factor update appends at most
     constexpr int LTRI = (MMAX * (MMAX - 1)) / 2;  // rows 0..MMAX-2 of L, packed lower
     constexpr int SPL = CAP / 64;                  // table slots per lane
     constexpr bool SEL_REG = SPL <= 16;            // selection from registers
@@ -474,8 +477,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(!RSL ? 1 : (
             bool spd = true, ovf = false;
             int mb = m - 1;
             for (int v0 = 0; v0 < ns && spd && !ovf;) {
-                int G = min(ns - v0, gmax);
-                while (G > 1 && upd_entries(mb, G) > 64 * K) --G;
+                const int G = min(ns - v0, min(gmax, GCAP));
                 const int m1 = mb + G;  // position of i within this update
                 // gather rows v0 .. v0+G-1: NR[v][pos] for members, NR[v][MMAX-1] = a_{u,i};
                 // their entries left of i are entered in the table and their slots listed
@@ -594,146 +596,22 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(!RSL ? 1 : (
                 __syncthreads();
                 if (ovf) break;
 
-                // update entries owned by this lane: (row r, column c); r == G is the row of i
-                const int E = upd_entries(mb, G);
-                const int ibase = upd_index(mb, G, 0);
-                int er[K], ec[K];
-                double run[K];
+                // factor update: lane l holds the running values of column l for the new rows
+                // (R[v] = entry (mb + v, l)) and, for the new columns, of the last row (R[G])
+                double R[GCAP + 1];
 #pragma unroll
-                for (int kk = 0; kk < K; ++kk) {
-                    const int e = kk * 64 + lane;
-                    er[kk] = -1;
-                    ec[kk] = 0;
-                    run[kk] = 0.0;
-                    if (e < E) {
-                        if (e >= ibase) {
-                            const int d = e - ibase;  // 0..G-1 new columns, G the diagonal
-                            er[kk] = G;
-                            ec[kk] = mb + d;
-                            run[kk] = (d < G) ? NR[d * MMAX + (MMAX - 1)] : di;
-                        } else {
-                            int v = 0, rest = e;
-                            while (rest >= mb + v + 1) {
-                                rest -= mb + v + 1;
-                                ++v;
-                            }
-                            er[kk] = v;
-                            ec[kk] = rest;
-                            run[kk] = NR[v * MMAX + rest];
-                        }
-                    }
-                }
-                {
-                    int base[kGMax];
+                for (int v = 0; v < GCAP; ++v) R[v] = (v < G && lane < m1) ? NR[v * MMAX + lane] : 0.0;
+                R[GCAP] = 0.0;
 #pragma unroll
-                    for (int v = 0; v < kGMax; ++v) base[v] = upd_index(mb, v, 0);
-                    switch (G) {
-                        case 1: upd_old_columns<1, K>(mb, base, er, ec, run, r_dinv, r_li, Lp, lane); break;
-                        case 2: upd_old_columns<2, K>(mb, base, er, ec, run, r_dinv, r_li, Lp, lane); break;
-                        case 3: upd_old_columns<3, K>(mb, base, er, ec, run, r_dinv, r_li, Lp, lane); break;
-                        default: upd_old_columns<4, K>(mb, base, er, ec, run, r_dinv, r_li, Lp, lane); break;
-                    }
-                }
-                for (int j = mb; j < m1; ++j) {
-                    double dj;
-                    if (j >= mb) {
-                        // pivot of new row j - mb: its diagonal entry is final
-                        const int e = upd_index(mb, j - mb, j);
-                        double xd = 0.0;
-#pragma unroll
-                        for (int kk = 0; kk < K; ++kk)
-                            if ((e >> 6) == kk) xd = rl(run[kk], e & 63);
-                        if (!(xd > 0.0) || !isfinite(xd)) {
-                            spd = false;
-                            break;
-                        }
-                        const double Ljj = sqrt(xd);
-                        dj = 1.0 / Ljj;
-#pragma unroll
-                        for (int kk = 0; kk < K; ++kk)
-                            if ((e >> 6) == kk && lane == (e & 63)) run[kk] = Ljj;
-                        if (lane == j) r_dinv = dj;
-                    } else {
-                        dj = rl(r_dinv, j);
-                    }
-                    // values of column j: U[v] = L[mb+v][j], U[kGMax] = L[i][j]
-                    double U[kGMax + 1];
-#pragma unroll
-                    for (int v = 0; v <= kGMax; ++v) U[v] = 0.0;
-#pragma unroll
-                    for (int v = 0; v < kGMax; ++v) {
-                        if (v < G && j < mb + v) {
-                            const int e = upd_index(mb, v, j);
-                            double xv = 0.0;
-#pragma unroll
-                            for (int kk = 0; kk < K; ++kk)
-                                if ((e >> 6) == kk) xv = rl(run[kk], e & 63);
-                            U[v] = xv * dj;
-#pragma unroll
-                            for (int kk = 0; kk < K; ++kk)
-                                if ((e >> 6) == kk && lane == (e & 63)) run[kk] = U[v];
-                        }
-                    }
-                    if (j < mb) {
-                        U[kGMax] = rl(r_li, j);
-                    } else {
-                        const int e = ibase + (j - mb);
-                        double xv = 0.0;
-#pragma unroll
-                        for (int kk = 0; kk < K; ++kk)
-                            if ((e >> 6) == kk) xv = rl(run[kk], e & 63);
-                        U[kGMax] = xv * dj;
-#pragma unroll
-                        for (int kk = 0; kk < K; ++kk)
-                            if ((e >> 6) == kk && lane == (e & 63)) run[kk] = U[kGMax];
-                    }
-                    // right-looking update of the entries right of column j
-#pragma unroll
-                    for (int kk = 0; kk < K; ++kk) {
-                        const int r = er[kk], c = ec[kk];
-                        const bool idiag = (r == G) && (c == m1);
-                        if (r >= 0 && c > j && !(idiag && j < mb)) {
-                            double a = U[kGMax];
-#pragma unroll
-                            for (int v = 0; v < kGMax; ++v)
-                                if (v == r && r < G) a = U[v];
-                            double b;
-                            if (c < mb) {
-                                b = Lp[tri(c, j)];
-                            } else if (idiag) {
-                                b = U[kGMax];
-                            } else {
-                                b = 0.0;
-#pragma unroll
-                                for (int v = 0; v < kGMax; ++v)
-                                    if (v == c - mb) b = U[v];
-                            }
-                            run[kk] = run[kk] - a * b;
-                        }
-                    }
+                for (int w = 0; w < GCAP; ++w)
+                    if (w < G && lane == mb + w) R[GCAP] = NR[w * MMAX + (MMAX - 1)];
+                switch (G) {
+                    case 1: spd = upd_lanes<1, GCAP>(mb, R, r_dinv, r_li, di, Lp, lane); break;
+                    case 2: spd = upd_lanes<(GCAP < 2 ? GCAP : 2), GCAP>(mb, R, r_dinv, r_li, di, Lp, lane); break;
+                    case 3: spd = upd_lanes<(GCAP < 3 ? GCAP : 3), GCAP>(mb, R, r_dinv, r_li, di, Lp, lane); break;
+                    default: spd = upd_lanes<GCAP, GCAP>(mb, R, r_dinv, r_li, di, Lp, lane); break;
                 }
                 if (!spd) break;
-                // store the appended rows, the last row's new entries and its running diagonal
-#pragma unroll
-                for (int kk = 0; kk < K; ++kk) {
-                    const int r = er[kk], c = ec[kk];
-                    if (r >= 0 && r < G) Lp[tri(mb + r, c)] = run[kk];
-                }
-#pragma unroll
-                for (int d = 0; d <= kGMax; ++d) {
-                    if (d <= G) {
-                        const int e = ibase + d;
-                        double xv = 0.0;
-#pragma unroll
-                        for (int kk = 0; kk < K; ++kk)
-                            if ((e >> 6) == kk) xv = rl(run[kk], e & 63);
-                        if (d < G) {
-                            if (lane == mb + d) r_li = xv;
-                        } else {
-                            di = xv;
-                        }
-                    }
-                }
                 __syncthreads();
                 mb += G;
                 v0 += G;
