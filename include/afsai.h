@@ -309,6 +309,9 @@ const char *afsai_last_error(void);
  *                             entries: 0 automatic (registers when every row of A has at most
  *                             128 entries and n <= 2^24, else LDS), 1 LDS, 2 registers
  *                             (AFSAI_ERR_INVALID_ARG from afsai_setup when not possible)
+ *   AFSAI_OPT_SELL_TAIL       products with a split SELL-64 layout: 0 (automatic) the leading
+ *                             entries of the long rows run in a launch of their own first,
+ *                             1 inside the slices' kernel (identical results)
  * Returns AFSAI_ERR_INVALID_ARG for an unknown option or value.  Not thread safe against
  * concurrent calls of the library.
  */
@@ -321,6 +324,7 @@ const char *afsai_last_error(void);
 #define AFSAI_OPT_SELL_WIDTH 7
 #define AFSAI_OPT_PCG_GRAPH 8
 #define AFSAI_OPT_SETUP_SLOTS 9
+#define AFSAI_OPT_SELL_TAIL 10
 int afsai_set_option(int32_t option, int64_t value);
 
 /*

@@ -379,11 +379,15 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(!RSL ? 1 : (
                 if (M > 0.0) {
                     const double thr = 0x1.0p-40 * M;
                     for (int round = 0; round < s; ++round) {
-                        double l = 0.0;
+                        // the first round's largest eligible value is M itself (M > thr)
+                        double Mp = M;
+                        if (round > 0) {
+                            double l = 0.0;
 #pragma unroll
-                        for (int j = 0; j < SPL; ++j)
-                            if (ar[j] > thr) l = fmax(l, ar[j]);
-                        const double Mp = wave_max_dpp(l);
+                            for (int j = 0; j < SPL; ++j)
+                                if (ar[j] > thr) l = fmax(l, ar[j]);
+                            Mp = wave_max_dpp(l);
+                        }
                         if (!(Mp > 0.0)) break;
                         const double band = (1.0 - tau) * Mp;
                         uint32_t lb = kEmpty;
@@ -427,15 +431,18 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(!RSL ? 1 : (
                 if (M > 0.0) {
                     const double thr = 0x1.0p-40 * M;
                     for (int round = 0; round < s; ++round) {
-                        double l = 0.0;
-                        for (int j = lane; j < CAP; j += 64) {
-                            const uint32_t kk = hkey[j];
-                            if (kk != kEmpty && !(kk & kPBit)) {
-                                const double a = fabs(hval[j]);
-                                if (a > thr) l = fmax(l, a);
+                        double Mp = M;
+                        if (round > 0) {
+                            double l = 0.0;
+                            for (int j = lane; j < CAP; j += 64) {
+                                const uint32_t kk = hkey[j];
+                                if (kk != kEmpty && !(kk & kPBit)) {
+                                    const double a = fabs(hval[j]);
+                                    if (a > thr) l = fmax(l, a);
+                                }
                             }
+                            Mp = wave_max_dpp(l);
                         }
-                        const double Mp = wave_max_dpp(l);
                         if (!(Mp > 0.0)) break;
                         const double band = (1.0 - tau) * Mp;
                         uint32_t lb = kEmpty;

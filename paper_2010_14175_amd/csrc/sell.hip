@@ -287,6 +287,12 @@ __global__ void k_tail_fill(int n, const int32_t *__restrict__ rp, const int32_t
 
 __global__ void k_set_i32(int32_t *p, int32_t v) { *p = v; }
 
+// rows of each slice that continue from the tail (count of its init bits)
+__global__ void k_init_count(int nslices, const uint64_t *__restrict__ init, int32_t *__restrict__ cnt) {
+    for (int sl = blockIdx.x * blockDim.x + threadIdx.x; sl < nslices; sl += gridDim.x * blockDim.x)
+        cnt[sl] = __popcll(init[sl]);
+}
+
 void sell_free(Sell *S) {
     if (!S) return;
     pool_free(S->sptr);
@@ -295,6 +301,7 @@ void sell_free(Sell *S) {
     pool_free(S->perm);
     pool_free(S->rowmap);
     pool_free(S->init);
+    pool_free(S->toff);
     pool_free(S->srow0);
     if (S->tail) {
         sell_free(S->tail);
@@ -489,6 +496,20 @@ static int sell_build(int n, int64_t nnz, const int32_t *rp, const int32_t *m, i
                                ci, (const double *)val, S.perm, S.srow0, sp, cap, S.col, (double *)S.val, S.init);
     }
     if (hipGetLastError() != hipSuccess) return fail(set_error_code(AFSAI_ERR_HIP, "SELL layout: launch failed"));
+    if (S.tail) {
+        // first tail row of each slice, so that a slice's product can run its rows' tails itself
+        DevBuf icnt;
+        int64_t ntail = 0;
+        if ((rc = dalloc(icnt, sizeof(int32_t) * (size_t)S.nslices, s))) return fail(rc);
+        S.toff = (int32_t *)pool_alloc(sizeof(int32_t) * (size_t)(S.nslices + 1));
+        if (!S.toff) return fail(set_error_code(AFSAI_ERR_NO_MEMORY, "SELL layout: out of device memory"));
+        hipLaunchKernelGGL(k_init_count, dim3(grid1d(S.nslices, di)), dim3(256), 0, s, S.nslices, S.init,
+                           icnt.as<int32_t>());
+        if ((rc = scan_counts(S.nslices, icnt.as<int32_t>(), S.toff, &ntail, di, s))) return fail(rc);
+        if (ntail != S.tail->n)
+            return fail(set_error_code(AFSAI_ERR_HIP, "SELL layout: %lld split rows against %d tail rows",
+                                       (long long)ntail, S.tail->n));
+    }
     *out = S;
     return AFSAI_OK;
 }

@@ -32,6 +32,8 @@ struct Sell {
     int32_t *rowmap = nullptr;  // [n] output row of each row (nullptr: identity)
     uint64_t *init = nullptr;   // [nslices] lanes whose sums continue from y (nullptr: none)
     Sell *tail = nullptr;       // leading entries of the rows longer than the slices hold
+    int32_t *toff = nullptr;    // [nslices + 1] with a tail: its first row for each slice (the
+                                // rows of a slice marked in init are consecutive tail rows)
     int32_t *srow0 = nullptr;   // [nslices + 1] first row of each slice (nullptr: 64 * slice);
                                 // set when slices follow the systems of a batch
     bool f32 = false;

@@ -271,7 +271,10 @@ __global__ __launch_bounds__(kThreads) void k_sell_spmv(int n, int nslices, cons
                                                          const double *__restrict__ x, double *__restrict__ y,
                                                          const double *__restrict__ w,
                                                          double *__restrict__ partials, PcgScalars *scs, Map mp,
-                                                         Systems sy, int nxcd) {
+                                                         Systems sy, int nxcd, const uint32_t *__restrict__ tsptr,
+                                                         const int32_t *__restrict__ tcol,
+                                                         const VT *__restrict__ tval,
+                                                         const int32_t *__restrict__ toff) {
     const Job jb = block_job(mp, nxcd);
     if (scs && scs[jb.k].done) return;
     __shared__ double sh[kThreads / 64];
@@ -291,8 +294,24 @@ __global__ __launch_bounds__(kThreads) void k_sell_spmv(int n, int nslices, cons
         const uint32_t c0 = sptr[sl];
         const int width = (int)(sptr[sl + 1] - c0);
         const int64_t base = (int64_t)c0 * kSlice + lane;
-        // rows split between the two layouts continue the sum their tail started
-        double acc = (init && valid && ((init[sl] >> lane) & 1)) ? y[ro] : 0.0;
+        // rows split between the two layouts start with their leading entries: run here from the
+        // tail layout (tcol set; the slice's split rows are consecutive tail rows), or continue
+        // the sum a separate tail product left in y
+        double acc = 0.0;
+        if (init && valid && ((init[sl] >> lane) & 1)) {
+            if (tcol) {
+                const int t = toff[sl] + __popcll(init[sl] & ((1ull << lane) - 1ull));
+                const uint32_t tc0 = tsptr[t >> 6];
+                const int tw = (int)(tsptr[(t >> 6) + 1] - tc0);
+                const int64_t tb = (int64_t)tc0 * kSlice + (t & 63);
+                for (int k = 0; k < tw; ++k) {
+                    const int64_t d = tb + (int64_t)k * kSlice;
+                    acc = fma((double)tval[d], x[tcol[d]], acc);
+                }
+            } else {
+                acc = y[ro];
+            }
+        }
         for (int k0 = 0; k0 < width; k0 += U) {
             int c[U];
             VT v[U];
@@ -690,27 +709,35 @@ static int make_batch_maps(int n, int nsys, const int32_t *row0, const DeviceInf
     return AFSAI_OK;
 }
 
+// fused: a split layout's tail runs inside the slices' product (else the caller launched it)
 template <int U, typename VT>
 static void launch_sell_t(const Sell &S, const double *x, double *y, const double *w, double *partials,
-                          PcgScalars *scs, const Map &mp, const Systems &sy, int nb, int nxcd, hipStream_t s) {
+                          PcgScalars *scs, const Map &mp, const Systems &sy, int nb, int nxcd, hipStream_t s,
+                          bool fused) {
+    const Sell *T = fused ? S.tail : nullptr;
+    const uint32_t *tsp = T ? T->sptr : nullptr;
+    const int32_t *tcl = T ? T->col : nullptr;
+    const VT *tvl = T ? (const VT *)T->val : nullptr;
+    const int32_t *tof = T ? S.toff : nullptr;
     if (w)
         hipLaunchKernelGGL((k_sell_spmv<U, VT, true>), dim3(nb), dim3(kThreads), 0, s, S.n, S.nslices, S.sptr,
                            S.srow0, S.perm, S.rowmap, S.init, S.col, (const VT *)S.val, x, y, w, partials, scs, mp,
-                           sy, nxcd);
+                           sy, nxcd, tsp, tcl, tvl, tof);
     else
         hipLaunchKernelGGL((k_sell_spmv<U, VT, false>), dim3(nb), dim3(kThreads), 0, s, S.n, S.nslices, S.sptr,
                            S.srow0, S.perm, S.rowmap, S.init, S.col, (const VT *)S.val, x, y, w, partials, scs, mp,
-                           sy, nxcd);
+                           sy, nxcd, tsp, tcl, tvl, tof);
 }
 
 template <typename VT>
 static void launch_sell_v(const Sell &S, int un, const double *x, double *y, const double *w, double *partials,
-                          PcgScalars *scs, const Map &mp, const Systems &sy, int nb, int nxcd, hipStream_t s) {
+                          PcgScalars *scs, const Map &mp, const Systems &sy, int nb, int nxcd, hipStream_t s,
+                          bool fused = false) {
     switch (un) {
-        case 1: launch_sell_t<1, VT>(S, x, y, w, partials, scs, mp, sy, nb, nxcd, s); break;
-        case 2: launch_sell_t<2, VT>(S, x, y, w, partials, scs, mp, sy, nb, nxcd, s); break;
-        case 4: launch_sell_t<4, VT>(S, x, y, w, partials, scs, mp, sy, nb, nxcd, s); break;
-        default: launch_sell_t<8, VT>(S, x, y, w, partials, scs, mp, sy, nb, nxcd, s); break;
+        case 1: launch_sell_t<1, VT>(S, x, y, w, partials, scs, mp, sy, nb, nxcd, s, fused); break;
+        case 2: launch_sell_t<2, VT>(S, x, y, w, partials, scs, mp, sy, nb, nxcd, s, fused); break;
+        case 4: launch_sell_t<4, VT>(S, x, y, w, partials, scs, mp, sy, nb, nxcd, s, fused); break;
+        default: launch_sell_t<8, VT>(S, x, y, w, partials, scs, mp, sy, nb, nxcd, s, fused); break;
     }
 }
 
@@ -722,7 +749,11 @@ static void sell_spmv(const char *name, const Sell &S, const BatchMaps &bm, cons
                       const double *w, double *partials, PcgScalars *scs, int fin, const DeviceInfo &di,
                       hipStream_t s) {
     const int un = sell_unroll();
-    if (S.tail) {
+    // a split layout's tail runs in a launch of its own first; inside the slices' product when
+    // asked for (measured slower: the lanes of long rows serialise their tails while the rest of
+    // the wavefront waits)
+    const bool fused = S.tail && S.toff && option(AFSAI_OPT_SELL_TAIL) == 1;
+    if (S.tail && !fused) {
         const Sell &T = *S.tail;
         const int nbt = blocks_for_slices(T.nslices, di);
         // the tail's rows belong to any system: with one system it stops with it
@@ -737,9 +768,9 @@ static void sell_spmv(const char *name, const Sell &S, const BatchMaps &bm, cons
     {
         ProfScope ps(name, s);
         if (S.f32)
-            launch_sell_v<float>(S, un, x, y, w, partials, scs, bm.sell.mp, bm.sy, nb, di.num_xcds, s);
+            launch_sell_v<float>(S, un, x, y, w, partials, scs, bm.sell.mp, bm.sy, nb, di.num_xcds, s, fused);
         else
-            launch_sell_v<double>(S, un, x, y, w, partials, scs, bm.sell.mp, bm.sy, nb, di.num_xcds, s);
+            launch_sell_v<double>(S, un, x, y, w, partials, scs, bm.sell.mp, bm.sy, nb, di.num_xcds, s, fused);
     }
     if (w)
         hipLaunchKernelGGL(k_finalize, dim3(bm.nsys), dim3(kThreads), 0, s, partials, nb, bm.sell.mp, fin, scs);

@@ -431,6 +431,35 @@ def test_split_layouts_identical(af, make, width):
     assert bool((x1 == x2).all())
 
 
+@pytest.mark.parametrize("width", [0, 3, 8])
+@pytest.mark.parametrize("make", [lambda: synth.elasticity27(10), lambda: synth.random_sparse_spd(3000, 40, 3)])
+def test_split_tail_fused_identical(af, make, width):
+    """The leading entries of split rows run inside the slices' product or in a launch of their
+    own before it: G^T(G r) and the PCG iterates are bit for bit the same (width 0: the
+    automatic split)."""
+    Pb = make()
+    A = Pb.A if hasattr(Pb, "A") else Pb
+    b = Pb.b if hasattr(Pb, "b") else A.to_scipy() @ synth.uniform(7, 2, A.n, -1.0, 1.0)
+    dA = _dev(af, A)
+    r = _vec(synth.uniform(5, 9, A.n))
+    try:
+        af.set_option(af.OPT_SELL_WIDTH, width)
+        P = af.setup(dA, 6, 2, 1e-2)
+        out = []
+        for tail in (0, 1):
+            af.set_option(af.OPT_SELL_TAIL, tail)
+            z = P.apply(r)
+            x, i = af.pcg_solve(dA, P, _vec(b), maxit=2000)
+            out.append((z, x, i.iters))
+    finally:
+        af.set_option(af.OPT_SELL_WIDTH, 0)
+        af.set_option(af.OPT_SELL_TAIL, 0)
+    (z0, x0, i0), (z1, x1, i1) = out
+    assert bool((z0 == z1).all())
+    assert i0 == i1
+    assert bool((x0 == x1).all())
+
+
 def test_pcg_deterministic(af):
     Pb = synth.elasticity27(12)
     dA = _dev(af, Pb.A)
