@@ -362,6 +362,8 @@ def main():
     ap.add_argument("--serve-slots", type=int, nargs="+", default=[2, 4],
                     help="serve: slot counts of the continuous-batching runs")
     ap.add_argument("--g-prec", default="f64", choices=["f64", "f32"])
+    ap.add_argument("--setup-f32", action="store_true",
+                    help="per-row setup arithmetic in FP32 (reports pattern agreement with the FP64 setup)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=0)
     ap.add_argument("--no-profile", action="store_true", help="do not time kernels with HIP events")
@@ -403,7 +405,7 @@ def main():
     x = torch.zeros_like(b)
 
     def step():
-        P = af.setup(dA, pb.kmax, pb.s, pb.eps, g_prec=g_prec)
+        P = af.setup(dA, pb.kmax, pb.s, pb.eps, g_prec=g_prec, setup_f32=args.setup_f32)
         x.zero_()
         _, info = af.pcg_solve(dA, P, b, x=x, rtol=pb.rtol)
         sinfo = P.info()
@@ -481,6 +483,37 @@ def main():
         print(f"[bench] cpu baseline: oracle on {threads} threads ...", file=sys.stderr, flush=True)
         cpu = cpu_baseline(pb, its[-1], threads, x.cpu().numpy())
 
+    f32_eval = None
+    if args.setup_f32:
+        # the FP32 setup against the FP64 one (which equals the oracle's bit for bit, tested):
+        # rows with the same pattern, relative error of G on them, PCG iterations of both
+        P32 = af.setup(dA, pb.kmax, pb.s, pb.eps, setup_f32=True)
+        P64 = af.setup(dA, pb.kmax, pb.s, pb.eps)
+        (r32, c32, v32), (r64, c64, v64) = ([t.cpu().numpy() for t in Pk.export()] for Pk in (P32, P64))
+        same_len = np.diff(r32) == np.diff(r64)
+        rows_same = 0
+        if same_len.all() and np.array_equal(r32, r64):
+            eq = c32 == c64
+            row_of = np.repeat(np.arange(pb.n), np.diff(r64))
+            bad = np.zeros(pb.n, bool)
+            np.logical_or.at(bad, row_of[~eq], True)
+            rows_same = int((~bad).sum())
+            ok = ~bad[row_of]
+            rel = np.abs(v32[ok] - v64[ok]) / np.maximum(np.abs(v64[ok]), 1e-300)
+            gerr = float(np.linalg.norm(v32 - v64) / np.linalg.norm(v64))
+        else:
+            rows_same = int(sum(np.array_equal(c32[r32[i]:r32[i + 1]], c64[r64[i]:r64[i + 1]]) for i in range(pb.n)))
+            rel = np.array([np.nan])
+            gerr = None
+        x.zero_()
+        _, i64 = af.pcg_solve(dA, P64, b, x=x, rtol=pb.rtol)
+        f32_eval = {"rows_same_pattern": rows_same / pb.n, "g_rel_err_same_rows_max": float(np.nanmax(rel)),
+                    "g_rel_err_fro": gerr, "iters_f32_setup": its[-1], "iters_f64_setup": i64.iters}
+        P32.close()
+        P64.close()
+        print(f"[bench] FP32 setup: {100 * rows_same / pb.n:.2f}% rows with the FP64 pattern, iterations "
+              f"{its[-1]} vs {i64.iters}", file=sys.stderr, flush=True)
+
     out = {
         "metric": METRIC,
         "value": round(sec, 6),
@@ -492,10 +525,11 @@ def main():
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if g_prec == af.F64 else "f64 (G stored f32)",
+        "dtype": ("f32 setup, " if args.setup_f32 else "") + ("f64" if g_prec == af.F64 else "f64 (G stored f32)"),
         "data": "synthetic",
         "config": {"workload": pb.name, "n": pb.n, "nnz": pb.A.nnz, "kmax": pb.kmax, "s": pb.s, "eps": pb.eps,
-                   "rtol": pb.rtol, "g_prec": args.g_prec, "nnz_g": sinfo.nnz_g},
+                   "rtol": pb.rtol, "g_prec": args.g_prec, "setup_prec": "f32" if args.setup_f32 else "f64",
+                   "nnz_g": sinfo.nnz_g},
         "setup_ms": round(float(np.mean(setup_ms)), 3),
         "pcg_ms": round(float(np.mean(pcg_ms)), 3),
         "iters": its[-1],
@@ -505,6 +539,8 @@ def main():
         "kernels": kern_report,
         "cpu_baseline": cpu,
     }
+    if f32_eval:
+        out["setup_f32_eval"] = f32_eval
     print(json.dumps(out), flush=True)
 
 

@@ -48,6 +48,12 @@ extern "C" {
 
 /* afsai_params.flags */
 #define AFSAI_VALIDATE 1u /* check the CSR structure and exact symmetry on the device first */
+/* per-row setup arithmetic (gradient, selection, dense factorisation, g) in FP32, A's values
+ * rounded to FP32 where they are read: the fully single-precision setup the paper discusses
+ * (Sec. 3).  Patterns may then differ from an FP64 setup where gradients are within FP32
+ * rounding of each other.  Needs every row of A to have at most 128 entries and n <= 2^24
+ * (AFSAI_ERR_INVALID_ARG otherwise). */
+#define AFSAI_SETUP_F32 2u
 
 /*
  * Square sparse matrix in CSR, 0-based, int32 indices (the paper's 4-byte local indices,
@@ -75,7 +81,7 @@ typedef struct afsai_csr {
  *             any hardware)
  *   g_prec    AFSAI_F64 or AFSAI_F32 storage for G and G^T (values widened to FP64 in every
  *             product; the per-row Cholesky is FP64 in both cases)
- *   flags     AFSAI_VALIDATE or 0
+ *   flags     AFSAI_VALIDATE, AFSAI_SETUP_F32, both or 0
  */
 typedef struct afsai_params {
     int32_t kmax;

@@ -25,6 +25,7 @@ TIE_RTOL = 2.0 ** -26
 OK, ERR_INVALID_ARG, ERR_BAD_MATRIX, ERR_NOT_SPD, ERR_NO_MEMORY, ERR_NOT_CONVERGED, ERR_TOO_LARGE, ERR_HIP = range(8)
 F64, F32 = 0, 1
 VALIDATE = 1
+SETUP_F32 = 2
 STOP_KMAX, STOP_EPS, STOP_NOCAND = 0, 1, 2
 
 # every symbol the C header declares
@@ -262,9 +263,10 @@ class Preconditioner:
 
 
 def setup(A: DeviceCSR, kmax: int, s: int, eps: float, tie_rtol: float = TIE_RTOL, g_prec: int = F64,
-          validate: bool = False, stream=None) -> Preconditioner:
-    """Adaptive FSAI setup (``afsai_setup``)."""
-    p = ParamsStruct(int(kmax), int(s), float(eps), float(tie_rtol), int(g_prec), VALIDATE if validate else 0)
+          validate: bool = False, stream=None, setup_f32: bool = False) -> Preconditioner:
+    """Adaptive FSAI setup (``afsai_setup``); setup_f32: the per-row arithmetic in FP32."""
+    p = ParamsStruct(int(kmax), int(s), float(eps), float(tie_rtol), int(g_prec),
+                     (VALIDATE if validate else 0) | (SETUP_F32 if setup_f32 else 0))
     h = ctypes.c_void_p()
     st = A.struct
     _check(lib().afsai_setup(ctypes.byref(st), ctypes.byref(p), _stream(stream), ctypes.byref(h)), "afsai_setup")
@@ -305,10 +307,11 @@ def _offsets(offsets):
 
 
 def setup_batched(A: DeviceCSR, offsets, kmax: int, s: int, eps: float, tie_rtol: float = TIE_RTOL,
-                  g_prec: int = F64, validate: bool = False, stream=None) -> Preconditioner:
+                  g_prec: int = F64, validate: bool = False, stream=None, setup_f32: bool = False) -> Preconditioner:
     """Setup of a batch of independent systems given as one block-diagonal matrix whose system
     k owns rows offsets[k] .. offsets[k+1]-1 (``afsai_setup_batched``)."""
-    p = ParamsStruct(int(kmax), int(s), float(eps), float(tie_rtol), int(g_prec), VALIDATE if validate else 0)
+    p = ParamsStruct(int(kmax), int(s), float(eps), float(tie_rtol), int(g_prec),
+                     (VALIDATE if validate else 0) | (SETUP_F32 if setup_f32 else 0))
     off, optr, nsys = _offsets(offsets)
     h = ctypes.c_void_p()
     st = A.struct

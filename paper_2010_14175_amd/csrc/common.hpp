@@ -186,6 +186,15 @@ __device__ __forceinline__ double wave_max_dpp(double v) {
     const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
     return __hiloint2double(hi, lo);
 }
+__device__ __forceinline__ float wave_max_dpp(float v) {
+    v = fmaxf(v, __int_as_float(dpp_i32<0x121, 0xF, false>(__float_as_int(v), __float_as_int(v))));
+    v = fmaxf(v, __int_as_float(dpp_i32<0x122, 0xF, false>(__float_as_int(v), __float_as_int(v))));
+    v = fmaxf(v, __int_as_float(dpp_i32<0x124, 0xF, false>(__float_as_int(v), __float_as_int(v))));
+    v = fmaxf(v, __int_as_float(dpp_i32<0x128, 0xF, false>(__float_as_int(v), __float_as_int(v))));
+    v = fmaxf(v, __int_as_float(dpp_i32<0x142, 0xA, false>(__float_as_int(v), __float_as_int(v))));
+    v = fmaxf(v, __int_as_float(dpp_i32<0x143, 0xC, false>(__float_as_int(v), __float_as_int(v))));
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+}
 // minimum over the 64 lanes (unsigned), returned uniform
 __device__ __forceinline__ uint32_t wave_min_dpp(uint32_t v) {
     v = min(v, (uint32_t)dpp_i32<0x121, 0xF, false>((int)v, (int)v));

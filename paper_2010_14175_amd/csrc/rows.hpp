@@ -101,6 +101,9 @@ __device__ __forceinline__ double rl(double v, int src) {
     const int hi = __builtin_amdgcn_readlane(__double2hiint(v), src);
     return __hiloint2double(hi, lo);
 }
+__device__ __forceinline__ float rl(float v, int src) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), src));
+}
 
 // One factor update that appends G rows (positions mb .. mb+G-1; the rows of L for the positions
 // below mb are final) and moves the last row (row i) behind them.  Lane l holds column l: R[v]
@@ -111,29 +114,29 @@ __device__ __forceinline__ double rl(double v, int src) {
 // column-by-column factorisation in the same order.  Column j of the new rows goes to Lp; the
 // last row's entries of the old columns are final already and its diagonal `di` receives the
 // squares of its new entries.  Returns false on a pivot that is not positive.
-template <int G, int GA>
-__device__ __forceinline__ bool upd_lanes(int mb, double (&R)[GA + 1], double &r_dinv, double &r_li, double &di,
-                                          double *Lp, int lane) {
+template <int G, int GA, typename T>
+__device__ __forceinline__ bool upd_lanes(int mb, T (&R)[GA + 1], T &r_dinv, T &r_li, T &di,
+                                          T *Lp, int lane) {
     static_assert(G <= GA, "group fits the register array");
     const int m1 = mb + G;  // position of i after the update
     const int rowbase = tri(lane, 0);
     for (int j = 0; j < m1; ++j) {
-        double U[G], A;
+        T U[G], A;
         if (j < mb) {
-            const double dj = rl(r_dinv, j);
+            const T dj = rl(r_dinv, j);
 #pragma unroll
             for (int v = 0; v < G; ++v) U[v] = rl(R[v], j) * dj;
             A = rl(r_li, j);
         } else {
             // pivot of new row w = j - mb: its diagonal entry has all its terms
             const int w = j - mb;
-            double xd = 0.0;
+            T xd = T(0);
 #pragma unroll
             for (int v = 0; v < G; ++v)
                 if (v == w) xd = rl(R[v], j);
-            if (!(xd > 0.0) || !isfinite(xd)) return false;
-            const double Ljj = sqrt(xd);
-            const double dj = 1.0 / Ljj;
+            if (!(xd > T(0)) || !isfinite(xd)) return false;
+            const T Ljj = sqrt(xd);
+            const T dj = T(1) / Ljj;
 #pragma unroll
             for (int v = 0; v < G; ++v) U[v] = (v == w) ? Ljj : rl(R[v], j) * dj;  // rows v < w unused
             A = rl(R[GA], j) * dj;                                                   // L[i][j]
@@ -149,7 +152,7 @@ __device__ __forceinline__ bool upd_lanes(int mb, double (&R)[GA + 1], double &r
                 if (j < mb + v + 1) Lp[tri(mb + v, j)] = U[v];
         }
         if (lane > j && lane < m1) {
-            double b = (lane < mb) ? Lp[rowbase + j] : U[0];
+            T b = (lane < mb) ? Lp[rowbase + j] : U[0];
 #pragma unroll
             for (int v = 1; v < G; ++v)
                 if (lane == mb + v) b = U[v];
@@ -175,8 +178,8 @@ constexpr int sl_cap() { return CAP >= 2048 ? 2 * CAP : 4 * CAP; }
 // table slots fit 20 rows per CU in LDS, and 5 waves per SIMD measured faster than 4 without
 // spills; the smallest patterns target 8.  Larger patterns and tables are limited by LDS, and
 // the compiler keeps all their registers.
-template <int MMAX, int CAP, bool RSL>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(!RSL ? 1 : (MMAX <= 8 && CAP <= 256) ? 8 : ((MMAX <= 32 && CAP <= 512) ? 5 : 1), 8))) void k_afsai_rows(
+template <int MMAX, int CAP, bool RSL, typename T>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(!RSL ? 1 : (MMAX <= 8 && CAP <= 256) ? 8 : ((MMAX <= 32 && CAP <= 512) ? (sizeof(T) == 4 ? 6 : 5) : 1), 8))) void k_afsai_rows(
     int n, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci, const double *__restrict__ av,
     const double *__restrict__ diag, const int32_t *__restrict__ dlo, int kmax, int s, double eps, double tau,
     int gmax, const int32_t *__restrict__ list, int nlist, int32_t *__restrict__ counters, int nxcd, int claim,
@@ -194,14 +197,15 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(!RSL ? 1 : (
     constexpr bool SEL_REG = SPL <= 16;            // selection from registers
     constexpr int SLCAP = RSL ? 1 : sl_cap<CAP>();
     __shared__ uint32_t hkey[CAP];       // column (tagged when a member), kept for the whole row
-    __shared__ double hval[CAP];         // gradient of this step
+    __shared__ T hval[CAP];         // gradient of this step
     __shared__ int8_t hpos[RSL ? 1 : CAP];                 // position of a member
     __shared__ uint16_t SL[SLCAP];                         // table slots of the member rows' entries left of i
-    __shared__ double Lp_s[RSL ? 1 : LTRI];                // rows of L for the off-diagonal positions
-    __shared__ double NR_s[NR_ALIAS ? 1 : kGMax * MMAX];   // gathered new rows, by position (a_{u,i} at MMAX-1)
-    extern __shared__ double lds_dyn[];                    // RSL: rows of L, sized by the launch
-    double *const Lp = RSL ? lds_dyn : Lp_s;
-    double *const NR = NR_ALIAS ? hval : NR_s;
+    __shared__ T Lp_s[RSL ? 1 : LTRI];                // rows of L for the off-diagonal positions
+    __shared__ T NR_s[NR_ALIAS ? 1 : kGMax * MMAX];   // gathered new rows, by position (a_{u,i} at MMAX-1)
+    extern __shared__ __align__(8) unsigned char lds_dyn_b[];  // RSL: rows of L, sized by the launch
+    T *const Lp = RSL ? reinterpret_cast<T *>(lds_dyn_b) : Lp_s;
+    const T epsT = (T)eps, tauT = (T)tau;
+    T *const NR = NR_ALIAS ? hval : NR_s;
     __shared__ int32_t s_row;
 
     const int lane = threadIdx.x;
@@ -227,19 +231,19 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(!RSL ? 1 : (
         // row entries left of column i, their offset in SL, scaled row value, reciprocal
         // pivot, L[i][t]
         int r_col = i, r_beg = 0, r_len = 0, r_so = 0;
-        double r_g = 0.0, r_dinv = 0.0, r_li = 0.0;
+        T r_g = T(0), r_dinv = T(0), r_li = T(0);
         int r_nb = 0, r_ne = 0;  // row extents of the columns selected in this step (lane = rank)
 
         // ---- G_0 = I scaled: P = {i}, g = a_ii^-1/2, psi_0 = a_ii
-        const double aii = diag[i];
+        const T aii = (T)diag[i];
         const int ibeg = rp[i], ilen = dlo[i];
         int8_t status = ROW_OK;
         int m = 1, steps = 0;
         int32_t reason = STOP_KMAX;
-        double psi = aii;
-        double di = aii;  // last row's diagonal less the squares of its final entries
-        if (!(aii > 0.0) || !isfinite(aii)) status = ROW_NOT_SPD;
-        const double psi0 = aii;
+        T psi = aii;
+        T di = aii;  // last row's diagonal less the squares of its final entries
+        if (!(aii > T(0)) || !isfinite(aii)) status = ROW_NOT_SPD;
+        const T psi0 = aii;
         int sl_used = 0;  // SL entries in use (uniform)
         // register slot lists: member 0 is row i, member t + 1 the column at position t
         uint32_t slr[RSL ? MMAX : 1];
@@ -263,7 +267,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(!RSL ? 1 : (
             sl_used = ilen;
         }
         if (lane == 0) {
-            r_g = 1.0 / sqrt(aii);
+            r_g = T(1) / sqrt(aii);
             r_beg = ibeg;
             r_len = ilen;
             r_so = 0;
@@ -273,14 +277,14 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(!RSL ? 1 : (
         for (int k = 1; k <= kmax && status == ROW_OK; ++k) {
             // ---- 1. product pass: v_c += a_rc g_r over the members' entries left of i (the
             //         slots of members collect values that are never read)
-            for (int j = lane; j < CAP; j += 64) hval[j] = 0.0;
+            for (int j = lane; j < CAP; j += 64) hval[j] = T(0);
             __syncthreads();
             if constexpr (RSL) {
 #pragma unroll
                 for (int q0 = 0; q0 < MMAX; q0 += QB) {
                     if (q0 < m) {
                         int sl[2 * QB];
-                        double aa[2 * QB], gg[QB];
+                        T aa[2 * QB], gg[QB];
                         int lens[QB], begs[QB];
 #pragma unroll
                         for (int u = 0; u < QB; ++u) {
@@ -288,7 +292,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(!RSL ? 1 : (
                             const int pos = (q == 0) ? m - 1 : q - 1;
                             lens[u] = 0;
                             begs[u] = 0;
-                            gg[u] = 0.0;
+                            gg[u] = T(0);
                             if (q < m) {
                                 lens[u] = __builtin_amdgcn_readlane(r_len, pos);
                                 begs[u] = __builtin_amdgcn_readlane(r_beg, pos);
@@ -298,10 +302,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(!RSL ? 1 : (
                             for (int hh = 0; hh < 2; ++hh) {
                                 const int o = hh * 64 + lane;
                                 sl[2 * u + hh] = -1;
-                                aa[2 * u + hh] = 0.0;
+                                aa[2 * u + hh] = T(0);
                                 if (o < lens[u]) {
                                     sl[2 * u + hh] = (int)((slr[q] >> (16 * hh)) & 0xffffu);
-                                    aa[2 * u + hh] = __builtin_nontemporal_load(&av[begs[u] + o]);
+                                    aa[2 * u + hh] = (T)__builtin_nontemporal_load(&av[begs[u] + o]);
                                 }
                             }
                         }
@@ -317,7 +321,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(!RSL ? 1 : (
             } else {
                 for (int t0 = 0; t0 < m; t0 += 4) {
                     int sl[8];
-                    double aa[8], gg[4];
+                    T aa[8], gg[4];
                     int lens[4], begs[4], sos[4];
     #pragma unroll
                     for (int u = 0; u < 4; ++u) {
@@ -325,7 +329,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(!RSL ? 1 : (
                         lens[u] = 0;
                         begs[u] = 0;
                         sos[u] = 0;
-                        gg[u] = 0.0;
+                        gg[u] = T(0);
                         if (t < m) {
                             lens[u] = __builtin_amdgcn_readlane(r_len, t);
                             begs[u] = __builtin_amdgcn_readlane(r_beg, t);
@@ -336,10 +340,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(!RSL ? 1 : (
                         for (int hh = 0; hh < 2; ++hh) {
                             const int o = hh * 64 + lane;
                             sl[2 * u + hh] = -1;
-                            aa[2 * u + hh] = 0.0;
+                            aa[2 * u + hh] = T(0);
                             if (o < lens[u]) {
                                 sl[2 * u + hh] = SL[sos[u] + o];
-                                aa[2 * u + hh] = __builtin_nontemporal_load(&av[begs[u] + o]);
+                                aa[2 * u + hh] = (T)__builtin_nontemporal_load(&av[begs[u] + o]);
                             }
                         }
                     }
@@ -353,7 +357,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(!RSL ? 1 : (
     #pragma unroll
                     for (int u = 0; u < 4; ++u)
                         for (int o = 128 + lane; o < lens[u]; o += 64)
-                            __hip_atomic_fetch_add(&hval[SL[sos[u] + o]], av[begs[u] + o] * gg[u], __ATOMIC_RELAXED,
+                            __hip_atomic_fetch_add(&hval[SL[sos[u] + o]], (T)av[begs[u] + o] * gg[u], __ATOMIC_RELAXED,
                                                    __HIP_MEMORY_SCOPE_WORKGROUP);
                 }
             }
@@ -365,31 +369,31 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(!RSL ? 1 : (
             int ns = 0;
             if constexpr (SEL_REG) {
                 uint32_t kr[SPL];
-                double ar[SPL];
-                double lm = -1.0;
+                T ar[SPL];
+                T lm = T(-1);
 #pragma unroll
                 for (int j = 0; j < SPL; ++j) {
                     const uint32_t kk = hkey[lane + 64 * j];
                     const bool cand = (kk != kEmpty) && !(kk & kPBit);
                     kr[j] = cand ? kk : kEmpty;
-                    ar[j] = cand ? fabs(hval[lane + 64 * j]) : -1.0;
+                    ar[j] = cand ? fabs(hval[lane + 64 * j]) : T(-1);
                     lm = fmax(lm, ar[j]);
                 }
-                const double M = wave_max_dpp(lm);
-                if (M > 0.0) {
-                    const double thr = 0x1.0p-40 * M;
+                const T M = wave_max_dpp(lm);
+                if (M > T(0)) {
+                    const T thr = T(0x1.0p-40) * M;
                     for (int round = 0; round < s; ++round) {
                         // the first round's largest eligible value is M itself (M > thr)
-                        double Mp = M;
+                        T Mp = M;
                         if (round > 0) {
-                            double l = 0.0;
+                            T l = T(0);
 #pragma unroll
                             for (int j = 0; j < SPL; ++j)
                                 if (ar[j] > thr) l = fmax(l, ar[j]);
                             Mp = wave_max_dpp(l);
                         }
-                        if (!(Mp > 0.0)) break;
-                        const double band = (1.0 - tau) * Mp;
+                        if (!(Mp > T(0))) break;
+                        const T band = (T(1) - tauT) * Mp;
                         uint32_t lb = kEmpty;
 #pragma unroll
                         for (int j = 0; j < SPL; ++j)
@@ -401,7 +405,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(!RSL ? 1 : (
                             const bool hit = (kr[j] == js);
                             myslot = hit ? lane + 64 * j : myslot;
                             kr[j] = hit ? kEmpty : kr[j];
-                            ar[j] = hit ? -1.0 : ar[j];
+                            ar[j] = hit ? T(-1) : ar[j];
                         }
                         const uint64_t who = __ballot(myslot >= 0);
                         const int wslot = __builtin_amdgcn_readlane(myslot, (int)__builtin_ctzll(who));
@@ -422,34 +426,34 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(!RSL ? 1 : (
                     }
                 }
             } else {
-                double lm = 0.0;
+                T lm = T(0);
                 for (int j = lane; j < CAP; j += 64) {
                     const uint32_t kk = hkey[j];
                     if (kk != kEmpty && !(kk & kPBit)) lm = fmax(lm, fabs(hval[j]));
                 }
-                const double M = wave_max_dpp(lm);
-                if (M > 0.0) {
-                    const double thr = 0x1.0p-40 * M;
+                const T M = wave_max_dpp(lm);
+                if (M > T(0)) {
+                    const T thr = T(0x1.0p-40) * M;
                     for (int round = 0; round < s; ++round) {
-                        double Mp = M;
+                        T Mp = M;
                         if (round > 0) {
-                            double l = 0.0;
+                            T l = T(0);
                             for (int j = lane; j < CAP; j += 64) {
                                 const uint32_t kk = hkey[j];
                                 if (kk != kEmpty && !(kk & kPBit)) {
-                                    const double a = fabs(hval[j]);
+                                    const T a = fabs(hval[j]);
                                     if (a > thr) l = fmax(l, a);
                                 }
                             }
                             Mp = wave_max_dpp(l);
                         }
-                        if (!(Mp > 0.0)) break;
-                        const double band = (1.0 - tau) * Mp;
+                        if (!(Mp > T(0))) break;
+                        const T band = (T(1) - tauT) * Mp;
                         uint32_t lb = kEmpty;
                         for (int j = lane; j < CAP; j += 64) {
                             const uint32_t kk = hkey[j];
                             if (kk != kEmpty && !(kk & kPBit)) {
-                                const double a = fabs(hval[j]);
+                                const T a = fabs(hval[j]);
                                 if (a > thr && a >= band && kk < lb) lb = kk;
                             }
                         }
@@ -488,14 +492,14 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(!RSL ? 1 : (
                 const int m1 = mb + G;  // position of i within this update
                 // gather rows v0 .. v0+G-1: NR[v][pos] for members, NR[v][MMAX-1] = a_{u,i};
                 // their entries left of i are entered in the table and their slots listed
-                for (int j = lane; j < G * MMAX; j += 64) NR[j] = 0.0;
+                for (int j = lane; j < G * MMAX; j += 64) NR[j] = T(0);
                 __syncthreads();
                 if constexpr (RSL && MMAX >= 16) {
                     // rows of at most 128 entries: every new row's entries are loaded first, so
                     // that their latencies overlap, then entered in the table (not for the
                     // smallest patterns, whose registers it would spill)
                     int gnb[kGMax], gnl[kGMax], gc[kGMax][2];
-                    double ga[kGMax][2];
+                    T ga[kGMax][2];
 #pragma unroll
                     for (int v = 0; v < kGMax; ++v) {
                         gnb[v] = 0;
@@ -509,10 +513,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(!RSL ? 1 : (
                         for (int h = 0; h < 2; ++h) {
                             const int o = h * 64 + lane;
                             gc[v][h] = 0x7fffffff;
-                            ga[v][h] = 0.0;
+                            ga[v][h] = T(0);
                             if (o < gnl[v] && o < 128) {
                                 gc[v][h] = ci[gnb[v] + o];
-                                ga[v][h] = av[gnb[v] + o];
+                                ga[v][h] = (T)av[gnb[v] + o];
                             }
                         }
                     }
@@ -525,7 +529,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(!RSL ? 1 : (
                             for (int h = 0; h < 2; ++h) {
                                 if (h * 64 < gnl[v]) {
                                     const int c = gc[v][h];
-                                    const double a = ga[v][h];
+                                    const T a = ga[v][h];
                                     if (c == i) NR[v * MMAX + (MMAX - 1)] = a;
                                     bool bad = false;
                                     if (c < i) {
@@ -565,10 +569,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(!RSL ? 1 : (
                     for (int h = 0; h * 64 < nl && !ovf; ++h) {
                         const int o = h * 64 + lane;
                         int c = 0x7fffffff;
-                        double a = 0.0;
+                        T a = T(0);
                         if (o < nl) {
                             c = ci[nb + o];
-                            a = av[nb + o];
+                            a = (T)av[nb + o];
                         }
                         if (c == i) NR[v * MMAX + (MMAX - 1)] = a;
                         bool bad = false;
@@ -605,18 +609,18 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(!RSL ? 1 : (
 
                 // factor update: lane l holds the running values of column l for the new rows
                 // (R[v] = entry (mb + v, l)) and, for the new columns, of the last row (R[G])
-                double R[GCAP + 1];
+                T R[GCAP + 1];
 #pragma unroll
-                for (int v = 0; v < GCAP; ++v) R[v] = (v < G && lane < m1) ? NR[v * MMAX + lane] : 0.0;
-                R[GCAP] = 0.0;
+                for (int v = 0; v < GCAP; ++v) R[v] = (v < G && lane < m1) ? NR[v * MMAX + lane] : T(0);
+                R[GCAP] = T(0);
 #pragma unroll
                 for (int w = 0; w < GCAP; ++w)
                     if (w < G && lane == mb + w) R[GCAP] = NR[w * MMAX + (MMAX - 1)];
                 switch (G) {
-                    case 1: spd = upd_lanes<1, GCAP>(mb, R, r_dinv, r_li, di, Lp, lane); break;
-                    case 2: spd = upd_lanes<(GCAP < 2 ? GCAP : 2), GCAP>(mb, R, r_dinv, r_li, di, Lp, lane); break;
-                    case 3: spd = upd_lanes<(GCAP < 3 ? GCAP : 3), GCAP>(mb, R, r_dinv, r_li, di, Lp, lane); break;
-                    default: spd = upd_lanes<GCAP, GCAP>(mb, R, r_dinv, r_li, di, Lp, lane); break;
+                    case 1: spd = upd_lanes<1, GCAP, T>(mb, R, r_dinv, r_li, di, Lp, lane); break;
+                    case 2: spd = upd_lanes<(GCAP < 2 ? GCAP : 2), GCAP, T>(mb, R, r_dinv, r_li, di, Lp, lane); break;
+                    case 3: spd = upd_lanes<(GCAP < 3 ? GCAP : 3), GCAP, T>(mb, R, r_dinv, r_li, di, Lp, lane); break;
+                    default: spd = upd_lanes<GCAP, GCAP, T>(mb, R, r_dinv, r_li, di, Lp, lane); break;
                 }
                 if (!spd) break;
                 __syncthreads();
@@ -627,23 +631,23 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(!RSL ? 1 : (
                 status = ROW_OVERFLOW;
                 break;
             }
-            if (spd && (!(di > 0.0) || !isfinite(di))) spd = false;
+            if (spd && (!(di > T(0)) || !isfinite(di))) spd = false;
             if (!spd) {
                 status = ROW_NOT_SPD;
                 break;
             }
 
             // ---- 5. g = L^-T e_m, positions from the last down
-            const double lmm = sqrt(di);
-            const double dm = 1.0 / lmm;
+            const T lmm = sqrt(di);
+            const T dm = T(1) / lmm;
             // l = mn-1 (row i of L), then the stored rows; lane t accumulates sum_l L[l][t] g_l
-            double gmine = (lane == mn - 1) ? dm : 0.0;
-            double acc = (lane < mn - 1) ? 0.0 + r_li * dm : 0.0;
+            T gmine = (lane == mn - 1) ? dm : T(0);
+            T acc = (lane < mn - 1) ? T(0) + r_li * dm : T(0);
             for (int l = mn - 2; l >= 0; --l) {
-                const double Lv = Lp[tri(l, lane < l ? lane : 0)];
-                const double gl = -(rl(acc, l) * rl(r_dinv, l));
+                const T Lv = Lp[tri(l, lane < l ? lane : 0)];
+                const T gl = -(rl(acc, l) * rl(r_dinv, l));
                 gmine = (lane == l) ? gl : gmine;
-                const double na = acc + Lv * gl;
+                const T na = acc + Lv * gl;
                 acc = (lane < l) ? na : acc;
             }
             if (lane < mn) r_g = gmine;
@@ -656,7 +660,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(!RSL ? 1 : (
             m = mn;
             steps = k;
             // ---- exit test (eq. exit_crit)
-            if (psi <= eps * psi0) {
+            if (psi <= epsT * psi0) {
                 reason = STOP_EPS;
                 break;
             }
@@ -691,29 +695,30 @@ typedef void (*RowsKernel)(int, const int32_t *, const int32_t *, const double *
                            int, int, double, double, int, const int32_t *, int, int32_t *, int, int, int32_t *, double *, int,
                            int32_t *, double *, int32_t *, int32_t *, int8_t *, int32_t *, int32_t *);
 
-template <int MMAX, bool RSL>
+template <int MMAX, bool RSL, typename T = double>
 static RowsKernel rows_kernel_cap(int cap) {
     switch (cap) {
-        case 128: return k_afsai_rows<MMAX, 128, RSL>;
-        case 256: return k_afsai_rows<MMAX, 256, RSL>;
-        case 512: return k_afsai_rows<MMAX, 512, RSL>;
-        case 1024: return k_afsai_rows<MMAX, 1024, RSL>;
-        case 2048: return k_afsai_rows<MMAX, 2048, RSL>;
-        case 4096: return k_afsai_rows<MMAX, 4096, RSL>;
-        case 8192: return k_afsai_rows<MMAX, 8192, RSL>;
+        case 128: return k_afsai_rows<MMAX, 128, RSL, T>;
+        case 256: return k_afsai_rows<MMAX, 256, RSL, T>;
+        case 512: return k_afsai_rows<MMAX, 512, RSL, T>;
+        case 1024: return k_afsai_rows<MMAX, 1024, RSL, T>;
+        case 2048: return k_afsai_rows<MMAX, 2048, RSL, T>;
+        case 4096: return k_afsai_rows<MMAX, 4096, RSL, T>;
+        case 8192: return k_afsai_rows<MMAX, 8192, RSL, T>;
         default: return nullptr;
     }
 }
 
-// dynamic LDS bytes of one k_afsai_rows<MMAX, CAP, RSL> block (rows 0..mmax-2 of L; RSL only)
-__host__ __forceinline__ size_t rows_lds_dyn_bytes(int mmax, bool rsl) {
-    return rsl ? (size_t)(mmax > 1 ? mmax - 1 : 1) * (size_t)mmax / 2 * 8 + 8 : 0;
+// dynamic LDS bytes of one k_afsai_rows<MMAX, CAP, RSL, T> block (rows 0..mmax-2 of L; RSL
+// only); tb = sizeof(T)
+__host__ __forceinline__ size_t rows_lds_dyn_bytes(int mmax, bool rsl, int tb = 8) {
+    return rsl ? (size_t)(mmax > 1 ? mmax - 1 : 1) * (size_t)mmax / 2 * tb + 8 : 0;
 }
-// LDS bytes of one k_afsai_rows<MMAX, CAP, RSL> block, static and dynamic
-__host__ __forceinline__ size_t rows_lds_bytes(int mmax_t, int mmax, int cap, bool rsl) {
+// LDS bytes of one k_afsai_rows<MMAX, CAP, RSL, T> block, static and dynamic
+__host__ __forceinline__ size_t rows_lds_bytes(int mmax_t, int mmax, int cap, bool rsl, int tb = 8) {
     if (rsl) {
-        const size_t nr = (size_t)cap >= (size_t)kGMax * mmax_t ? 8 : (size_t)kGMax * mmax_t * 8;
-        return (size_t)cap * 12 + 2 + 8 + nr + rows_lds_dyn_bytes(mmax, rsl) + 16;
+        const size_t nr = (size_t)cap >= (size_t)kGMax * mmax_t ? tb : (size_t)kGMax * mmax_t * tb;
+        return (size_t)cap * (4 + tb) + 2 + 8 + nr + rows_lds_dyn_bytes(mmax, rsl, tb) + 16;
     }
     const size_t slcap = cap >= 2048 ? 2 * (size_t)cap : 4 * (size_t)cap;
     return (size_t)cap * 13 + slcap * 2 + (size_t)mmax_t * (mmax_t - 1) / 2 * 8 + (size_t)kGMax * mmax_t * 8 + 16;

@@ -281,17 +281,27 @@ __global__ void k_block_check(int n, const int32_t *__restrict__ rp, const int32
 // host side
 // ---------------------------------------------------------------------------------------
 // fused per-row kernels, instantiated in rows.hip
-RowsKernel rows_kernel(int mmax_t, int cap, bool rsl);
+RowsKernel rows_kernel(int mmax_t, int cap, bool rsl, bool f32);
 
-static int launch_rows(RowsKernel kern, int mmax_t, int mmax, int64_t row_work, int cap, bool rsl, int gmax, const afsai_csr *A, const double *diag,
+static int launch_rows(RowsKernel kern, int mmax_t, int mmax, int64_t row_work, int cap, bool rsl, int tb, int gmax, const afsai_csr *A, const double *diag,
                        const int32_t *dlo, const afsai_params *p, const int32_t *list, int nlist, int32_t *counters,
                        int ldell, int32_t *ell_col, double *ell_val, int32_t *m, double *psi, int32_t *steps,
                        int32_t *reason, int8_t *st, int32_t *ovf_count, int32_t *ovf_list, const DeviceInfo &di,
                        hipStream_t s) {
-    // resident rows per CU: LDS is allocated in 512-byte granules
-    const size_t lds = (rows_lds_bytes(mmax_t, mmax, cap, rsl) + 511) / 512 * 512;
-    const size_t dyn = rows_lds_dyn_bytes(mmax, rsl);
+    // resident rows per CU: the runtime's occupancy for this kernel (registers and LDS, with
+    // its dynamic LDS), else from the LDS bytes (512-byte granules)
+    const size_t lds = (rows_lds_bytes(mmax_t, mmax, cap, rsl, tb) + 511) / 512 * 512;
+    const size_t dyn = rows_lds_dyn_bytes(mmax, rsl, tb);
     int per_cu = (int)((160 * 1024) / lds);
+    {
+        int occ = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, reinterpret_cast<const void *>(kern), 64, dyn) ==
+                hipSuccess &&
+            occ > 0)
+            per_cu = std::min(per_cu, occ);
+        else
+            (void)hipGetLastError();
+    }
     if (per_cu > 32) per_cu = 32;
     if (per_cu < 1) per_cu = 1;
     int64_t nb = (int64_t)di.num_cus * per_cu;
@@ -386,7 +396,7 @@ static int setup_core(const afsai_csr *A, const afsai_params *p, int nsys, const
     if (A->n <= 0 || A->nnz < A->n) AFSAI_FAIL(AFSAI_ERR_INVALID_ARG, "afsai_setup: n = %d, nnz = %d", A->n, A->nnz);
     if (!A->row_ptr || !A->col_idx || !A->val) AFSAI_FAIL(AFSAI_ERR_INVALID_ARG, "afsai_setup: null CSR array");
     if (p->kmax < 0 || (p->kmax > 0 && p->s < 1) || !(p->eps >= 0.0) || !(p->tie_rtol >= 0.0 && p->tie_rtol < 1.0) ||
-        (p->g_prec != AFSAI_F64 && p->g_prec != AFSAI_F32) || (p->flags & ~AFSAI_VALIDATE))
+        (p->g_prec != AFSAI_F64 && p->g_prec != AFSAI_F32) || (p->flags & ~(AFSAI_VALIDATE | AFSAI_SETUP_F32)))
         AFSAI_FAIL(AFSAI_ERR_INVALID_ARG, "afsai_setup: bad parameters (kmax=%d s=%d eps=%g tie_rtol=%g g_prec=%d)",
                    p->kmax, p->s, p->eps, p->tie_rtol, p->g_prec);
     const int64_t mmax64 = 1 + (int64_t)p->kmax * (p->kmax > 0 ? p->s : 0);
@@ -472,6 +482,13 @@ static int setup_core(const afsai_csr *A, const afsai_params *p, int nsys, const
     if (slopt == 2 && !rsl)
         AFSAI_FAIL(AFSAI_ERR_INVALID_ARG,
                    "afsai_setup: register slot lists need rows of at most 128 entries and n <= 2^24");
+    // FP32 setup arithmetic: register-list form only
+    const bool sf32 = (p->flags & AFSAI_SETUP_F32) != 0;
+    if (sf32 && !rsl)
+        AFSAI_FAIL(AFSAI_ERR_INVALID_ARG,
+                   "afsai_setup: FP32 setup arithmetic needs rows of at most 128 entries and n <= 2^24 "
+                   "(and register slot lists)");
+    const int tb = sf32 ? 4 : 8;
     int cap2 = pow2ceil(bound + 1);
     if (cap2 < cap1) cap2 = cap1;
     if (cap2 > 8192) cap2 = 8192;
@@ -491,11 +508,11 @@ static int setup_core(const afsai_csr *A, const afsai_params *p, int nsys, const
     int32_t *ovf_count = ovf.as<int32_t>() + n;
     hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, (int64_t)1, ovf_count, 0);
 
-    RowsKernel k1 = rows_kernel(mmax_t, cap1, rsl);
+    RowsKernel k1 = rows_kernel(mmax_t, cap1, rsl, sf32);
     if (!k1) AFSAI_FAIL(AFSAI_ERR_TOO_LARGE, "afsai_setup: no kernel for pattern %d / table %d", mmax_t, cap1);
     // table entries one row touches over its steps (bound per step times k_max, plus its own row)
     const int64_t row_work = (int64_t)p->kmax * bound + maxlen;
-    if ((rc = launch_rows(k1, mmax_t, mmax, row_work, cap1, rsl, gmax, A, diagb.as<double>(), dlob.as<int32_t>(), p, nullptr, n, ctr.as<int32_t>(), ldell,
+    if ((rc = launch_rows(k1, mmax_t, mmax, row_work, cap1, rsl, tb, gmax, A, diagb.as<double>(), dlob.as<int32_t>(), p, nullptr, n, ctr.as<int32_t>(), ldell,
                           ell_col.as<int32_t>(), ell_val.as<double>(), mcnt.as<int32_t>(), psi.as<double>(),
                           steps.as<int32_t>(), reason.as<int32_t>(), st.as<int8_t>(), ovf_count, ovf.as<int32_t>(), di,
                           s)))
@@ -512,9 +529,9 @@ static int setup_core(const afsai_csr *A, const afsai_params *p, int nsys, const
                            list2.as<int32_t>());
         int32_t *cnt2 = list2.as<int32_t>() + novf;
         hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, (int64_t)1, cnt2, 0);
-        RowsKernel k2 = rows_kernel(mmax_t, cap2, rsl);
+        RowsKernel k2 = rows_kernel(mmax_t, cap2, rsl, sf32);
         if (!k2) AFSAI_FAIL(AFSAI_ERR_TOO_LARGE, "afsai_setup: no kernel for table %d", cap2);
-        if ((rc = launch_rows(k2, mmax_t, mmax, row_work, cap2, rsl, gmax, A, diagb.as<double>(), dlob.as<int32_t>(), p, list2.as<int32_t>(), novf,
+        if ((rc = launch_rows(k2, mmax_t, mmax, row_work, cap2, rsl, tb, gmax, A, diagb.as<double>(), dlob.as<int32_t>(), p, list2.as<int32_t>(), novf,
                               ctr.as<int32_t>(), ldell, ell_col.as<int32_t>(), ell_val.as<double>(), mcnt.as<int32_t>(),
                               psi.as<double>(), steps.as<int32_t>(), reason.as<int32_t>(), st.as<int8_t>(), cnt2,
                               ovf.as<int32_t>(), di, s)))

@@ -230,6 +230,44 @@ def test_setup_slot_lists_refused(af):
         af.set_option(af.OPT_SETUP_SLOTS, 0)
 
 
+@pytest.mark.parametrize("make,kmax,s,min_same", [(lambda: synth.poisson7(16).A, 5, 1, 0.5),
+                                                  (lambda: synth.elast27(8, 1.0, 2), 10, 2, 0.5),
+                                                  (lambda: synth.lap7_lognormal(12, 11, 10, 1.0, 3), 5, 1, 0.5)])
+def test_setup_f32_against_oracle(af, make, kmax, s, min_same):
+    """Fully single-precision setup (gradient, selection, factorisation in FP32) against the FP64
+    oracle, the evaluation the paper's single-precision remark calls for: the share of rows
+    whose pattern is the oracle's, the relative error of G on those rows (FP32 rounding of
+    small dense solves), and PCG to rtol 1e-8 with either G taking about the same number of
+    iterations.  Rows may pick other columns where FP64 gradients tie within FP32 rounding."""
+    A = make()
+    dA = _dev(af, A)
+    P = af.setup(dA, kmax, s, 1e-2, setup_f32=True)
+    rp, ci, va = _gpu_factor(af, P)
+    R = oracle.setup_rows(A, kmax, s, 1e-2)
+    same, errs = 0, []
+    for i in range(A.n):
+        m = R.m[i]
+        cols = ci[rp[i]:rp[i + 1]]
+        if len(cols) == m and np.array_equal(cols, R.cols[i, :m]):
+            same += 1
+            ov = R.vals[i, :m]
+            errs.append(np.max(np.abs(va[rp[i]:rp[i + 1]] - ov)) / np.max(np.abs(ov)))
+    assert same / A.n >= min_same, f"only {same}/{A.n} rows with the oracle's pattern"
+    assert max(errs) < 1e-4, max(errs)
+    b = A.to_scipy() @ synth.uniform(3, 4, A.n, -1.0, 1.0)
+    x32, i32 = af.pcg_solve(dA, P, _vec(b), rtol=1e-8)
+    x64, i64 = af.pcg_solve(dA, af.setup(dA, kmax, s, 1e-2), _vec(b), rtol=1e-8)
+    assert i32.converged and i32.true_relres < 2e-8
+    assert abs(i32.iters - i64.iters) <= max(2, i64.iters // 10), (i32.iters, i64.iters)
+
+
+def test_setup_f32_refused(af):
+    A = synth.random_sparse_spd(2000, 90, 4)
+    with pytest.raises(af.AfsaiError) as e:
+        af.setup(_dev(af, A), 2, 1, 1e-2, setup_f32=True)
+    assert e.value.code == af.ERR_INVALID_ARG
+
+
 @pytest.mark.parametrize("gs,un", [(4, 1), (8, 2), (16, 8), (64, 4)])
 def test_spmv_shapes(af, gs, un):
     """Every group size / unroll of the CSR products gives the oracle's y within rounding."""
