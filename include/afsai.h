@@ -318,6 +318,12 @@ const char *afsai_last_error(void);
  *   AFSAI_OPT_SELL_TAIL       products with a split SELL-64 layout: 0 (automatic) the leading
  *                             entries of the long rows run in a launch of their own first,
  *                             1 inside the slices' kernel (identical results)
+ *   AFSAI_OPT_SELL_UNEVEN     SELL-64 layouts of matrices with uneven rows (G^T): 0 (automatic)
+ *                             each slice's rows ordered by length, every lane reading its own
+ *                             row's entries only; 1 split layouts (the slices keep each row's
+ *                             last w entries, a second layout the leading ones).  Products are
+ *                             identical row by row; fused dot products are summed in another
+ *                             order
  * Returns AFSAI_ERR_INVALID_ARG for an unknown option or value.  Not thread safe against
  * concurrent calls of the library.
  */
@@ -331,6 +337,7 @@ const char *afsai_last_error(void);
 #define AFSAI_OPT_PCG_GRAPH 8
 #define AFSAI_OPT_SETUP_SLOTS 9
 #define AFSAI_OPT_SELL_TAIL 10
+#define AFSAI_OPT_SELL_UNEVEN 11
 int afsai_set_option(int32_t option, int64_t value);
 
 /*

@@ -254,6 +254,7 @@ int afsai_set_option(int32_t opt, int64_t value) {
         case AFSAI_OPT_PCG_GRAPH: ok = (value >= 0 && value <= 2); break;
         case AFSAI_OPT_SETUP_SLOTS: ok = (value >= 0 && value <= 2); break;
         case AFSAI_OPT_SELL_TAIL: ok = (value == 0 || value == 1); break;
+        case AFSAI_OPT_SELL_UNEVEN: ok = (value == 0 || value == 1); break;
         default: ok = false;
     }
     if (!ok) AFSAI_FAIL(AFSAI_ERR_INVALID_ARG, "afsai_set_option: bad option %d / value %lld", opt, (long long)value);

@@ -162,6 +162,33 @@ __global__ __launch_bounds__(1024) void k_sell_sort(int n, const int32_t *__rest
     }
 }
 
+// rows of each slice ordered by length (longest first, ties by row), one wavefront per slice:
+// perm[sl * 64 + k] is the lane-k row (-1 past the slice's rows), lens[sl * 64 + k] its
+// length, iperm[sl * 64 + j] the lane holding the slice's j-th row.  A lane then stops at its
+// own row's length and the padding of the shorter rows, gathered at the slice's last lanes, is
+// never read.
+__global__ __launch_bounds__(256) void k_slice_sort(int n, int nslices, const int32_t *__restrict__ rp,
+                                                     const int32_t *__restrict__ m, const int32_t *__restrict__ srow0,
+                                                     int32_t *__restrict__ perm, int32_t *__restrict__ lens,
+                                                     int32_t *__restrict__ iperm) {
+    const int lane = threadIdx.x & 63;
+    for (int sl = (blockIdx.x * blockDim.x + threadIdx.x) >> 6; sl < nslices; sl += (gridDim.x * blockDim.x) >> 6) {
+        int r0, r1;
+        slice_rows(srow0, n, sl, r0, r1);
+        const int r = r0 + lane;
+        const bool valid = r < r1;
+        const int len = valid ? row_len(rp, m, r) : -1;
+        int rank = 0;
+        for (int j = 0; j < kSlice; ++j) {
+            const int lj = __builtin_amdgcn_readlane(len, j);
+            rank += (lj > len || (lj == len && j < lane)) ? 1 : 0;
+        }
+        perm[(int64_t)sl * kSlice + rank] = valid ? r : -1;
+        lens[(int64_t)sl * kSlice + rank] = valid ? len : 0;
+        iperm[(int64_t)sl * kSlice + lane] = rank;
+    }
+}
+
 // width of each slice = its longest row, capped at `cap` entries (one wavefront per slice)
 __global__ __launch_bounds__(256) void k_sell_width(int n, int nslices, const int32_t *__restrict__ rp,
                                                      const int32_t *__restrict__ m, const int32_t *__restrict__ perm,
@@ -299,6 +326,8 @@ void sell_free(Sell *S) {
     pool_free(S->col);
     pool_free(S->val);
     pool_free(S->perm);
+    pool_free(S->lens);
+    pool_free(S->iperm);
     pool_free(S->rowmap);
     pool_free(S->init);
     pool_free(S->toff);
@@ -435,6 +464,15 @@ static int sell_build(int n, int64_t nnz, const int32_t *rp, const int32_t *m, i
         const int forced = (int)option(AFSAI_OPT_SELL_WIDTH);
         if (forced > 0) {
             cap = forced;
+        } else if (padded && option(AFSAI_OPT_SELL_UNEVEN) != 1) {
+            // uneven rows: each slice's rows ordered by length, lanes stop at their own row
+            S.perm = (int32_t *)pool_alloc(sizeof(int32_t) * (size_t)S.nslices * kSlice);
+            S.lens = (int32_t *)pool_alloc(sizeof(int32_t) * (size_t)S.nslices * kSlice);
+            S.iperm = (int32_t *)pool_alloc(sizeof(int32_t) * (size_t)S.nslices * kSlice);
+            if (!S.perm || !S.lens || !S.iperm)
+                return fail(set_error_code(AFSAI_ERR_NO_MEMORY, "SELL layout: out of device memory"));
+            hipLaunchKernelGGL(k_slice_sort, dim3(nbs), dim3(256), 0, s, n, S.nslices, rp, m, S.srow0, S.perm, S.lens,
+                               S.iperm);
         } else if (padded) {
             // split at the width that minimises the work (host choice from device statistics)
             DevBuf hist;

@@ -29,6 +29,9 @@ struct Sell {
     int32_t *col = nullptr;     // [sptr[nslices] * 64]
     void *val = nullptr;        // double or float, same layout
     int32_t *perm = nullptr;    // [nslices * 64] row of each slice lane (nullptr: identity)
+    int32_t *lens = nullptr;    // [nslices * 64] entries of each slice lane's row (nullptr: all
+                                // lanes run the slice's width; else padding is never read)
+    int32_t *iperm = nullptr;   // with lens: [nslices * 64] lane holding the slice's k-th row
     int32_t *rowmap = nullptr;  // [n] output row of each row (nullptr: identity)
     uint64_t *init = nullptr;   // [nslices] lanes whose sums continue from y (nullptr: none)
     Sell *tail = nullptr;       // leading entries of the rows longer than the slices hold

@@ -271,7 +271,9 @@ __global__ __launch_bounds__(kThreads) void k_sell_spmv(int n, int nslices, cons
                                                          const double *__restrict__ x, double *__restrict__ y,
                                                          const double *__restrict__ w,
                                                          double *__restrict__ partials, PcgScalars *scs, Map mp,
-                                                         Systems sy, int nxcd, const uint32_t *__restrict__ tsptr,
+                                                         Systems sy, int nxcd, const int32_t *__restrict__ lens,
+                                                         const int32_t *__restrict__ iperm,
+                                                         const uint32_t *__restrict__ tsptr,
                                                          const int32_t *__restrict__ tcol,
                                                          const VT *__restrict__ tval,
                                                          const int32_t *__restrict__ toff) {
@@ -293,6 +295,7 @@ __global__ __launch_bounds__(kThreads) void k_sell_spmv(int n, int nslices, cons
         const int ro = (valid && rowmap) ? rowmap[r] : r;
         const uint32_t c0 = sptr[sl];
         const int width = (int)(sptr[sl + 1] - c0);
+        const int len = lens ? lens[(int64_t)sl * kSlice + lane] : width;  // entries this lane reads
         const int64_t base = (int64_t)c0 * kSlice + lane;
         // rows split between the two layouts start with their leading entries: run here from the
         // tail layout (tcol set; the slice's split rows are consecutive tail rows), or continue
@@ -319,7 +322,7 @@ __global__ __launch_bounds__(kThreads) void k_sell_spmv(int n, int nslices, cons
             for (int u = 0; u < U; ++u) {
                 c[u] = -1;
                 v[u] = VT(0);
-                if (k0 + u < width) {
+                if (k0 + u < len) {
                     const int64_t d = base + (int64_t)(k0 + u) * kSlice;
                     c[u] = __builtin_nontemporal_load(&col[d]);
                     v[u] = __builtin_nontemporal_load(&val[d]);
@@ -329,7 +332,16 @@ __global__ __launch_bounds__(kThreads) void k_sell_spmv(int n, int nslices, cons
             for (int u = 0; u < U; ++u)
                 if (c[u] >= 0) acc = fma((double)v[u], x[c[u]], acc);
         }
-        if (valid) {
+        if (lens) {
+            // lanes ordered by length: each lane takes its natural row's sum, so that y is
+            // written and the dot summed in row order as with unordered slices
+            const double an = __shfl(acc, iperm[(int64_t)sl * kSlice + lane]);
+            const int rn = r0 + lane;
+            if (rn < r1) {
+                y[rn] = an;
+                if (DOT) part = fma(an, w[rn], part);
+            }
+        } else if (valid) {
             y[ro] = acc;
             if (DOT) part = fma(acc, w[ro], part);
         }
@@ -722,11 +734,11 @@ static void launch_sell_t(const Sell &S, const double *x, double *y, const doubl
     if (w)
         hipLaunchKernelGGL((k_sell_spmv<U, VT, true>), dim3(nb), dim3(kThreads), 0, s, S.n, S.nslices, S.sptr,
                            S.srow0, S.perm, S.rowmap, S.init, S.col, (const VT *)S.val, x, y, w, partials, scs, mp,
-                           sy, nxcd, tsp, tcl, tvl, tof);
+                           sy, nxcd, S.lens, S.iperm, tsp, tcl, tvl, tof);
     else
         hipLaunchKernelGGL((k_sell_spmv<U, VT, false>), dim3(nb), dim3(kThreads), 0, s, S.n, S.nslices, S.sptr,
                            S.srow0, S.perm, S.rowmap, S.init, S.col, (const VT *)S.val, x, y, w, partials, scs, mp,
-                           sy, nxcd, tsp, tcl, tvl, tof);
+                           sy, nxcd, S.lens, S.iperm, tsp, tcl, tvl, tof);
 }
 
 template <typename VT>
@@ -954,7 +966,7 @@ class PcgRun {
         int nmax = 0;
         for (int k = 0; k < nsys_; ++k) nmax = std::max(nmax, row0_[k + 1] - row0_[k]);
         const bool want_fused = form == 2 || (form == 0 && nmax < kFusedMaxRows);
-        fused_ = P_ && use_sell_ && want_fused && !As_.tail && !P_->sg.tail;
+        fused_ = P_ && use_sell_ && want_fused && !As_.tail && !P_->sg.tail && !As_.perm && !P_->sg.perm;
         // iterations replayed from captured graphs only when asked for (never while the kernel
         // timer is on: its events would be captured); on MI355X with ROCm 7 enqueuing the
         // kernels measured faster than replaying graphs at every size tried

@@ -454,19 +454,53 @@ def test_split_layouts_identical(af, make, width):
     b = Pb.b if hasattr(Pb, "b") else A.to_scipy() @ synth.uniform(7, 2, A.n, -1.0, 1.0)
     dA = _dev(af, A)
     r = _vec(synth.uniform(5, 9, A.n))
-    P1 = af.setup(dA, 6, 2, 1e-2)
-    z1 = P1.apply(r)
-    x1, i1 = af.pcg_solve(dA, P1, _vec(b), maxit=2000)
     try:
+        af.set_option(af.OPT_SELL_UNEVEN, 1)  # split layouts, automatic width
+        P1 = af.setup(dA, 6, 2, 1e-2)
+        z1 = P1.apply(r)
+        x1, i1 = af.pcg_solve(dA, P1, _vec(b), maxit=2000)
         af.set_option(af.OPT_SELL_WIDTH, width)
         P2 = af.setup(dA, 6, 2, 1e-2)
         z2 = P2.apply(r)
         x2, i2 = af.pcg_solve(dA, P2, _vec(b), maxit=2000)
     finally:
         af.set_option(af.OPT_SELL_WIDTH, 0)
+        af.set_option(af.OPT_SELL_UNEVEN, 0)
     assert bool((z1 == z2).all())
     assert i1.iters == i2.iters
     assert bool((x1 == x2).all())
+
+
+@pytest.mark.parametrize("make", [lambda: synth.elasticity27(10), lambda: synth.random_sparse_spd(3000, 40, 3),
+                                  lambda: synth.poisson7(9)])
+def test_sorted_slices_against_split(af, make):
+    """Uneven rows (G^T; A of small Poisson grids) as slices ordered by length with every lane
+    reading only its own row against split layouts: G^T(G r) and A x bit for bit equal (each
+    row is the same sequential chain), PCG iterates equal to rounding of the fused dots and
+    both within the oracle's tolerance."""
+    Pb = make()
+    A = Pb.A if hasattr(Pb, "A") else Pb
+    b = Pb.b if hasattr(Pb, "b") else A.to_scipy() @ synth.uniform(7, 2, A.n, -1.0, 1.0)
+    dA = _dev(af, A)
+    r = _vec(synth.uniform(5, 9, A.n))
+    out = []
+    try:
+        for mode in (0, 1):
+            af.set_option(af.OPT_SELL_UNEVEN, mode)
+            P = af.setup(dA, 6, 2, 1e-2)
+            z = P.apply(r)
+            y = af.spmv(dA, r)
+            x, i = af.pcg_solve(dA, P, _vec(b), maxit=2000)
+            out.append((z, y, x, i))
+    finally:
+        af.set_option(af.OPT_SELL_UNEVEN, 0)
+    (z0, y0, x0, i0), (z1, y1, x1, i1) = out
+    assert bool((z0 == z1).all()) and bool((y0 == y1).all())
+    assert abs(i0.iters - i1.iters) <= 1 and i0.converged and i1.converged
+    assert float((x0 - x1).norm() / x1.norm()) < X_RTOL
+    G = oracle.setup(A, 6, 2, 1e-2)
+    ro = oracle.pcg(A, G, b, 1e-8, maxit=2000)
+    assert float(np.linalg.norm(x0.cpu().numpy() - ro.x) / np.linalg.norm(ro.x)) < 10 * X_RTOL
 
 
 @pytest.mark.parametrize("width", [0, 3, 8])
