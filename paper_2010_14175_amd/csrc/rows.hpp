@@ -85,16 +85,6 @@ __device__ __forceinline__ int table_find(uint32_t *hkey, uint32_t c, uint32_t i
     return -2;
 }
 
-// position t of the concatenated entry e: largest t < cnt with off[t] <= e
-__device__ __forceinline__ int seg_of(const int32_t *off, int cnt, int e) {
-    int lo = 0, hi = cnt - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (off[mid] <= e) lo = mid; else hi = mid - 1;
-    }
-    return lo;
-}
-
 // value of v in lane `src` (src uniform)
 __device__ __forceinline__ double rl(double v, int src) {
     const int lo = __builtin_amdgcn_readlane(__double2loint(v), src);

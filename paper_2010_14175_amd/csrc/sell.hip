@@ -123,45 +123,6 @@ __device__ __forceinline__ void slice_rows(const int32_t *srow0, int n, int sl, 
     }
 }
 
-// rows sorted by length (longest first, ties by row index) inside windows of kSortWindow rows;
-// one block per window, bitonic sort of (length, row) keys in LDS
-__global__ __launch_bounds__(1024) void k_sell_sort(int n, const int32_t *__restrict__ rp,
-                                                     const int32_t *__restrict__ m, int32_t *__restrict__ perm) {
-    __shared__ unsigned long long key[kSortWindow];
-    const int w0 = blockIdx.x * kSortWindow;
-    for (int j = threadIdx.x; j < kSortWindow; j += blockDim.x) {
-        const int r = w0 + j;
-        unsigned long long k = ~0ull;
-        if (r < n) {
-            const uint32_t len = (uint32_t)row_len(rp, m, r);
-            k = ((unsigned long long)(0xFFFFFFFFu - len) << 32) | (uint32_t)j;
-        }
-        key[j] = k;
-    }
-    __syncthreads();
-    for (int size = 2; size <= kSortWindow; size <<= 1) {
-        for (int stride = size >> 1; stride > 0; stride >>= 1) {
-            for (int t = threadIdx.x; t < kSortWindow / 2; t += blockDim.x) {
-                const int lo = 2 * t - (t & (stride - 1));
-                const int hi = lo + stride;
-                const bool up = ((lo & size) == 0);
-                const unsigned long long a = key[lo], b = key[hi];
-                if ((a > b) == up) {
-                    key[lo] = b;
-                    key[hi] = a;
-                }
-            }
-            __syncthreads();
-        }
-    }
-    for (int j = threadIdx.x; j < kSortWindow; j += blockDim.x) {
-        const unsigned long long k = key[j];
-        const int r = w0 + j;
-        if (r < ((n + kSlice - 1) / kSlice) * kSlice)
-            perm[r] = (k == ~0ull) ? -1 : w0 + (int)(k & 0xFFFFFFFFu);
-    }
-}
-
 // rows of each slice ordered by length (longest first, ties by row), one wavefront per slice:
 // perm[sl * 64 + k] is the lane-k row (-1 past the slice's rows), lens[sl * 64 + k] its
 // length, iperm[sl * 64 + j] the lane holding the slice's j-th row.  A lane then stops at its
@@ -208,7 +169,6 @@ __global__ __launch_bounds__(256) void k_sell_width(int n, int nslices, const in
 }
 
 constexpr int kHistBins = 256;
-constexpr bool kSortTail = false;  // tail rows stay in row order (local gathers and writes)
 
 // histogram of row lengths (the last bin holds every longer row)
 __global__ __launch_bounds__(256) void k_len_hist(int n, const int32_t *__restrict__ rp, const int32_t *__restrict__ m,
@@ -501,15 +461,6 @@ static int sell_build(int n, int64_t nnz, const int32_t *rp, const int32_t *m, i
                 cap = kNoCap;
             }
         }
-    } else if (padded && rp && kSortTail) {
-        // rows of very different lengths: sort by length inside windows, then re-measure
-        S.perm = (int32_t *)pool_alloc(sizeof(int32_t) * (size_t)S.nslices * kSlice);
-        if (!S.perm) return fail(set_error_code(AFSAI_ERR_NO_MEMORY, "SELL layout: out of device memory"));
-        const int nwin = (n + kSortWindow - 1) / kSortWindow;
-        hipLaunchKernelGGL(k_sell_sort, dim3(nwin), dim3(1024), 0, s, n, rp, m, S.perm);
-        hipLaunchKernelGGL(k_sell_width, dim3(nbs), dim3(256), 0, s, n, S.nslices, rp, m, S.perm, nullptr, kNoCap,
-                           width.as<int32_t>());
-        if ((rc = scan_counts(S.nslices, width.as<int32_t>(), (int32_t *)S.sptr, &cols, di, s))) return fail(rc);
     }
     if (cols >= ((int64_t)1 << 31))
         return fail(set_error_code(AFSAI_ERR_TOO_LARGE, "SELL layout: %lld columns", (long long)cols));

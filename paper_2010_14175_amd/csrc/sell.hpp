@@ -5,13 +5,15 @@
 // together.  Rows shorter than the slice's longest row are padded with (own row, 0.0).
 //
 // When that padding would exceed a tenth of the entries (rows of very different lengths, as
-// in G^T), the layout is split: every row keeps its last w entries in the slices (w chosen
-// from the length histogram), and the leading entries of the longer rows form a second, small
-// SELL matrix (`tail`) over those rows only, sorted by length inside windows of kSortWindow
-// rows (SELL-C-sigma, Kreutzer et al. 2014; `perm` maps its slice lanes to its rows and
-// `rowmap` its rows to rows of the full matrix).  The tail is multiplied first; the main
-// product then continues the sums of the rows marked in `init` from y.  Each row's sum is
-// one sequential chain over its entries in stored order either way, so all layouts give
+// in G^T), each slice's rows are ordered by length (`perm`, with `lens` the length of each
+// lane's row and `iperm` the lane of each row; SELL-C-sigma with sigma = C = 64, Kreutzer et
+// al. 2014): every lane stops at its own row's length, so the padding is never read, and the
+// row sums go back to their natural lanes before they are stored.  The alternative split form
+// keeps every row's last w entries in the slices (w chosen from the length histogram) and the
+// leading entries of the longer rows in a second SELL matrix (`tail`, in row order; `rowmap`
+// maps its rows to rows of the full matrix), multiplied first; the main product then continues
+// the sums of the rows marked in `init` from y (or runs them itself, `toff`).  Each row's sum is
+// one sequential chain over its entries in stored order in every form, so all layouts give
 // bit-identical products.
 #pragma once
 
@@ -20,7 +22,6 @@
 namespace afsai {
 
 constexpr int kSlice = 64;
-constexpr int kSortWindow = 4096;
 
 struct Sell {
     int n = 0;
