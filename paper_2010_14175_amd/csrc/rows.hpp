@@ -181,7 +181,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(!RSL ? 1 : (
     constexpr bool NR_ALIAS = RSL && CAP >= kGMax * MMAX;  // gathered rows in the gradient array
     constexpr uint32_t KM = RSL ? kCol24 : ~kPBit;
     constexpr int QB = kProdBatch;  // members whose entries one product round loads together (RSL)
-    constexpr int GCAP = MMAX <= 8 ? 2 : kGMax;  // rows one factor update appends at most
+    // rows one factor update appends at most: 2 up to 32 positions (the running values of the
+    // appended rows stay in registers; 4 would spill at the 5-wave budget), else kGMax
+    constexpr int GCAP = MMAX <= 32 ? 2 : kGMax;
     constexpr int LTRI = (MMAX * (MMAX - 1)) / 2;  // rows 0..MMAX-2 of L, packed lower
     constexpr int SPL = CAP / 64;                  // table slots per lane
     constexpr bool SEL_REG = SPL <= 16;            // selection from registers
