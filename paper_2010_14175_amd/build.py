@@ -17,7 +17,8 @@ LIB = os.path.join(HERE, "libafsai.so")
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 HIPCC = os.path.join(ROCM, "bin", "hipcc")
 
-SOURCES = ["rows.hip", "setup.hip", "solve.hip", "sell.hip", "serve.hip", "runtime.hip"]
+SOURCES = ["rows_reg.hip", "rows_lds.hip", "rows_f32.hip", "rows.hip", "setup.hip", "solve.hip", "sell.hip",
+           "serve.hip", "runtime.hip"]
 
 HIPFLAGS = [
     "--offload-arch=gfx950",
@@ -42,7 +43,7 @@ def _compile(src: str) -> str:
 
 def build(verbose: bool = True) -> str:
     os.makedirs(BUILD, exist_ok=True)
-    with cf.ThreadPoolExecutor(max_workers=min(len(SOURCES), 6)) as ex:
+    with cf.ThreadPoolExecutor(max_workers=min(len(SOURCES), 8)) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = LIB + ".tmp"
     cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs]
