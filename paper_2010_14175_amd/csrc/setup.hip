@@ -202,9 +202,9 @@ __global__ __launch_bounds__(256) void k_transpose_fill(int n, const int32_t *__
     }
 }
 
-// Sorts every row of G^T by column (= row of G).  One wavefront per row: rows of up to 64
-// entries are ranked in registers (each lane counts the smaller keys); longer rows fall back
-// to an insertion sort by one lane.
+// Sorts every row of G^T by column (= row of G).  One wavefront per row: rows of up to 128
+// entries are ranked in registers (each lane counts the smaller keys, one or two keys per
+// lane); longer rows fall back to an insertion sort by one lane.
 template <typename VT>
 __global__ __launch_bounds__(256) void k_sort_rows(int n, const int32_t *__restrict__ rp, int32_t *__restrict__ ci,
                                                    VT *__restrict__ val) {
@@ -223,6 +223,32 @@ __global__ __launch_bounds__(256) void k_sort_rows(int n, const int32_t *__restr
             if (lane < len) {
                 ci[a + rank] = key;
                 val[a + rank] = v;
+            }
+        } else if (len <= 128) {
+            // two keys per lane (the columns of a row are distinct, so the ranks are too)
+            int k0 = ci[a + lane], k1 = 0x7fffffff;
+            const VT v0 = val[a + lane];
+            VT v1 = VT(0);
+            if (lane + 64 < len) {
+                k1 = ci[a + 64 + lane];
+                v1 = val[a + 64 + lane];
+            }
+            int r0 = 0, r1 = 0;
+            for (int t = 0; t < 64; ++t) {
+                const int kt = __shfl(k0, t, 64);
+                r0 += (kt < k0) ? 1 : 0;
+                r1 += (kt < k1) ? 1 : 0;
+            }
+            for (int t = 0; t < len - 64; ++t) {
+                const int kt = __shfl(k1, t, 64);
+                r0 += (kt < k0) ? 1 : 0;
+                r1 += (kt < k1) ? 1 : 0;
+            }
+            ci[a + r0] = k0;
+            val[a + r0] = v0;
+            if (lane + 64 < len) {
+                ci[a + r1] = k1;
+                val[a + r1] = v1;
             }
         } else if (lane == 0) {
             for (int e = a + 1; e < b; ++e) {
