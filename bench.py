@@ -106,8 +106,8 @@ def batch_bench(args):
 
 def serve_bench(args):
     """Serving form: Poisson arrivals of SPD systems, n log-uniform in [1e4, 2e6], half 7-point
-    (log-normal sigma = 1 cell coefficients, k_max = 5, s = 1), half 27-point 3-dof (the C2
-    construction, k_max = 10, s = 2), FP32 G, FP64 PCG to rtol 1e-8, x0 = 0.  Matrices come from
+    (log-normal sigma = 1 cell coefficients, k_max = 5, s = 1), half 27-point 3-dof (the 64^3
+    workload's construction, k_max = 10, s = 2), FP32 G, FP64 PCG to rtol 1e-8, x0 = 0.  Matrices come from
     a seeded pool of distinct systems; every request gets its own right-hand side b = A x with
     x ~ U(-1, 1).  The plain form serves one request at a time in arrival order (one slot);
     continuous batching admits up to 16 requests by memory.  Loads are 0.5 and 0.8 of the plain

@@ -574,5 +574,5 @@ def test_full_size_elasticity150_sampled(af):
     dA, P = r["dA"], r["P"]
     x, info = af.pcg_solve(dA, P, _vec(Pb.b), rtol=1e-8)
     assert info.converged and info.true_relres <= 1.1e-8
-    print(f"C5: setup {r['info'].ms:.0f} ms, nnz(G) {r['info'].nnz_g}, PCG {info.iters} iterations "
+    print(f"150^3 27-point: setup {r['info'].ms:.0f} ms, nnz(G) {r['info'].nnz_g}, PCG {info.iters} iterations "
           f"{info.ms:.0f} ms, test {time.time() - t0:.0f} s")

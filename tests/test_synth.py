@@ -61,7 +61,7 @@ def test_elast27_counts_symmetry_spd():
         assert (S != S.T).nnz == 0  # bitwise symmetric
         ev = np.linalg.eigvalsh(S.toarray())
         assert ev[0] > 0
-    # C2 shape: 64^3 nodes, 786,432 rows, 61,731,000 nonzeros
+    # the 64^3-node shape: 786,432 rows, 61,731,000 nonzeros
     assert synth.lib().synth_elast27_nnz(64) == 61731000
     assert synth.lib().synth_elast27_nnz(150) == 809238528
 
