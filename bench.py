@@ -328,10 +328,10 @@ def kernel_source_hash(kernel: str) -> str | None:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel: str, workload: str):
-    """HBM bytes per launch from the committed counter summary of this kernel and workload,
-    or None when there is none or the kernel's sources changed since it was taken."""
-    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_traffic.md")
+def measured_value(kernel: str, workload: str, summary: str, key: str):
+    """A value of the committed counter summary profiles/{kernel}_{workload}_{summary}.md, or
+    None when there is none or the kernel's sources changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_{summary}.md")
     if not os.path.exists(path):
         return None
     vals = {}
@@ -343,9 +343,19 @@ def measured_traffic(kernel: str, workload: str):
     if vals.get("source_hash") != kernel_source_hash(kernel):
         return None
     try:
-        return float(vals["hbm_bytes_per_launch"])
+        return float(vals[key])
     except (KeyError, ValueError):
         return None
+
+
+def measured_traffic(kernel: str, workload: str):
+    """HBM bytes per launch from the committed FETCH_SIZE / WRITE_SIZE summary."""
+    return measured_value(kernel, workload, "traffic", "hbm_bytes_per_launch")
+
+
+# VALU issue: a wave64 VALU instruction occupies its SIMD for 4 cycles; 256 CUs x 4 SIMDs at
+# 2.4 GHz
+PEAK_VALU_GINST = 256 * 4 * 2.4 / 4
 
 
 def main():
@@ -454,6 +464,7 @@ def main():
 
     w_g = 4 if g_prec == af.F32 else 8
     roof = None
+    issue_roof = None
     kern_report = {}
     for name, (launches, ms) in kern_all.items():
         byt = kernel_bytes(name, pb.n, pb.A.nnz, sinfo.nnz_g, w_g, pb.kmax, sinfo.mmax)
@@ -468,6 +479,12 @@ def main():
         roof = {"kernel": dom, "bound": "hbm", "achieved": round(ach, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": round(ach / PEAK_HBM_GBS, 4), "traffic": measured_traffic(dom, args.workload),
                 "bytes_per_launch": byt, "avg_launch_us": round(avg_s * 1e6, 2)}
+        # the same launch against the VALU issue rate, from the committed instruction count
+        vi = measured_value(dom, args.workload, "sq_counters", "valu_insts_per_launch")
+        if vi:
+            g = vi / avg_s / 1e9
+            issue_roof = {"kernel": dom, "bound": "valu_issue", "achieved": round(g, 1), "peak": PEAK_VALU_GINST,
+                          "unit": "Ginst/s", "frac": round(g / PEAK_VALU_GINST, 4), "valu_insts_per_launch": vi}
 
     # whole-PCG achieved bandwidth from the per-iteration algorithmic bytes
     it_bytes = (kernel_bytes("spmv_A_dot", pb.n, pb.A.nnz, sinfo.nnz_g, w_g, pb.kmax, sinfo.mmax)
@@ -536,6 +553,7 @@ def main():
         "true_relres": info.true_relres,
         "pcg_hbm_gbs": round(pcg_gbs, 1),
         "roofline": roof,
+        "issue_roofline": issue_roof,
         "kernels": kern_report,
         "cpu_baseline": cpu,
     }
