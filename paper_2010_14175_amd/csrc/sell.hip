@@ -240,6 +240,44 @@ __global__ __launch_bounds__(256) void k_sell_fill(int n, int nslices, const int
     }
 }
 
+// The same layout for whole rows in row order (no split, no ordering): each group of 8 lanes
+// reads 8 consecutive entries of one row and writes them to 8 consecutive positions of their
+// slice columns, so a wave instruction touches 8 segments of the matrix instead of 64.
+template <typename VI, typename VO>
+__global__ __launch_bounds__(256) void k_sell_fill_rows(int n, int nslices, const int32_t *__restrict__ rp,
+                                                         const int32_t *__restrict__ m, int ld,
+                                                         const int32_t *__restrict__ ci, const VI *__restrict__ val,
+                                                        const int32_t *__restrict__ srow0,
+                                                        const int32_t *__restrict__ sptr, int32_t *__restrict__ col,
+                                                        VO *__restrict__ out) {
+    const int lane = threadIdx.x & 63;
+    const int sub = lane & 7, rsub = lane >> 3;
+    for (int sl = (blockIdx.x * blockDim.x + threadIdx.x) >> 6; sl < nslices; sl += (gridDim.x * blockDim.x) >> 6) {
+        int r0, r1;
+        slice_rows(srow0, n, sl, r0, r1);
+        const int64_t base = (int64_t)sptr[sl] * kSlice;
+        const int width = sptr[sl + 1] - sptr[sl];
+        for (int rb = 0; rb < kSlice; rb += 8) {
+            const int r = r0 + rb + rsub;
+            const bool valid = r < r1;
+            const int64_t start = valid ? row_start(rp, ld, r) : 0;
+            const int len = valid ? row_len(rp, m, r) : 0;
+            const int pad_col = valid ? r : r0;
+            for (int k = sub; k < width; k += 8) {
+                int c = pad_col;
+                VO v = VO(0);
+                if (k < len) {
+                    c = ci[start + k];
+                    v = (VO)val[start + k];
+                }
+                const int64_t d = base + (int64_t)k * kSlice + rb + rsub;
+                col[d] = c;
+                out[d] = v;
+            }
+        }
+    }
+}
+
 // leading entries of the rows longer than cap: count per row, and a 0/1 flag per row
 __global__ void k_tail_count(int n, const int32_t *__restrict__ rp, const int32_t *__restrict__ m, int cap,
                              int32_t *__restrict__ tl, int32_t *__restrict__ flag) {
@@ -469,7 +507,24 @@ static int sell_build(int n, int64_t nnz, const int32_t *rp, const int32_t *m, i
     S.val = pool_alloc((out_f32 ? sizeof(float) : sizeof(double)) * (size_t)cols * kSlice);
     if (!S.col || !S.val) return fail(set_error_code(AFSAI_ERR_NO_MEMORY, "SELL layout: out of device memory"));
     const int32_t *sp = (const int32_t *)S.sptr;
-    if (val_f32) {
+    if (!S.perm && cap == kNoCap && !S.init) {
+        // whole rows in row order
+        if (val_f32) {
+            if (out_f32)
+                hipLaunchKernelGGL((k_sell_fill_rows<float, float>), dim3(nbs), dim3(256), 0, s, n, S.nslices, rp, m, ld,
+                                   ci, (const float *)val, S.srow0, sp, S.col, (float *)S.val);
+            else
+                hipLaunchKernelGGL((k_sell_fill_rows<float, double>), dim3(nbs), dim3(256), 0, s, n, S.nslices, rp,
+                                   m, ld, ci, (const float *)val, S.srow0, sp, S.col, (double *)S.val);
+        } else {
+            if (out_f32)
+                hipLaunchKernelGGL((k_sell_fill_rows<double, float>), dim3(nbs), dim3(256), 0, s, n, S.nslices, rp,
+                                   m, ld, ci, (const double *)val, S.srow0, sp, S.col, (float *)S.val);
+            else
+                hipLaunchKernelGGL((k_sell_fill_rows<double, double>), dim3(nbs), dim3(256), 0, s, n, S.nslices, rp,
+                                   m, ld, ci, (const double *)val, S.srow0, sp, S.col, (double *)S.val);
+        }
+    } else if (val_f32) {
         if (out_f32)
             hipLaunchKernelGGL((k_sell_fill<float, float>), dim3(nbs), dim3(256), 0, s, n, S.nslices, rp, m, ld, ci,
                                (const float *)val, S.perm, S.srow0, sp, cap, S.col, (float *)S.val, S.init);
