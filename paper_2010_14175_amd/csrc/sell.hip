@@ -123,30 +123,41 @@ __device__ __forceinline__ void slice_rows(const int32_t *srow0, int n, int sl, 
     }
 }
 
-// rows of each slice ordered by length (longest first, ties by row), one wavefront per slice:
-// perm[sl * 64 + k] is the lane-k row (-1 past the slice's rows), lens[sl * 64 + k] its
-// length, iperm[sl * 64 + j] the lane holding the slice's j-th row.  A lane then stops at its
-// own row's length and the padding of the shorter rows, gathered at the slice's last lanes, is
-// never read.
-__global__ __launch_bounds__(256) void k_slice_sort(int n, int nslices, const int32_t *__restrict__ rp,
-                                                     const int32_t *__restrict__ m, const int32_t *__restrict__ srow0,
-                                                     int32_t *__restrict__ perm, int32_t *__restrict__ lens,
-                                                     int32_t *__restrict__ iperm) {
-    const int lane = threadIdx.x & 63;
-    for (int sl = (blockIdx.x * blockDim.x + threadIdx.x) >> 6; sl < nslices; sl += (gridDim.x * blockDim.x) >> 6) {
-        int r0, r1;
-        slice_rows(srow0, n, sl, r0, r1);
-        const int r = r0 + lane;
-        const bool valid = r < r1;
-        const int len = valid ? row_len(rp, m, r) : -1;
-        int rank = 0;
-        for (int j = 0; j < kSlice; ++j) {
-            const int lj = __builtin_amdgcn_readlane(len, j);
-            rank += (lj > len || (lj == len && j < lane)) ? 1 : 0;
+// rows of each window ordered by length (longest first, ties by row), one block of 256
+// threads per window: the window's k-th row goes to lane k % 64 of its slice k / 64 (perm: the
+// row, -1 past the window's rows; lens: its length).  A lane then stops at its own row's
+// length and the slices of a window hold rows of similar length.
+__global__ __launch_bounds__(kWin * kSlice) void k_window_sort(int n, int nwin, const int32_t *__restrict__ wsl,
+                                                               const int32_t *__restrict__ rp,
+                                                               const int32_t *__restrict__ m,
+                                                               const int32_t *__restrict__ srow0,
+                                                               int32_t *__restrict__ perm,
+                                                               int32_t *__restrict__ lens) {
+    __shared__ int32_t wl[kWin * kSlice];
+    const int t = threadIdx.x;
+    for (int w = blockIdx.x; w < nwin; w += gridDim.x) {
+        const int ws = wsl[w], we = wsl[w + 1];
+        int wr0, wr1, u0, u1;
+        slice_rows(srow0, n, ws, wr0, u0);
+        slice_rows(srow0, n, we - 1, u1, wr1);
+        const int cnt = wr1 - wr0;  // at most kWin * 64 rows
+        const int len = t < cnt ? row_len(rp, m, wr0 + t) : -1;
+        wl[t] = len;
+        __syncthreads();
+        if (t < cnt) {
+            int rank = 0;
+            for (int j = 0; j < cnt; ++j) {
+                const int lj = wl[j];
+                rank += (lj > len || (lj == len && j < t)) ? 1 : 0;
+            }
+            perm[(int64_t)ws * kSlice + rank] = wr0 + t;
+            lens[(int64_t)ws * kSlice + rank] = len;
         }
-        perm[(int64_t)sl * kSlice + rank] = valid ? r : -1;
-        lens[(int64_t)sl * kSlice + rank] = valid ? len : 0;
-        iperm[(int64_t)sl * kSlice + lane] = rank;
+        for (int k = cnt + t; k < (we - ws) * kSlice; k += blockDim.x) {
+            perm[(int64_t)ws * kSlice + k] = -1;
+            lens[(int64_t)ws * kSlice + k] = 0;
+        }
+        __syncthreads();
     }
 }
 
@@ -325,7 +336,8 @@ void sell_free(Sell *S) {
     pool_free(S->val);
     pool_free(S->perm);
     pool_free(S->lens);
-    pool_free(S->iperm);
+    pool_free(S->wsl);
+    pool_free(S->wofs);
     pool_free(S->rowmap);
     pool_free(S->init);
     pool_free(S->toff);
@@ -463,14 +475,41 @@ static int sell_build(int n, int64_t nnz, const int32_t *rp, const int32_t *m, i
         if (forced > 0) {
             cap = forced;
         } else if (padded && option(AFSAI_OPT_SELL_UNEVEN) != 1) {
-            // uneven rows: each slice's rows ordered by length, lanes stop at their own row
+            // uneven rows: the rows of each window of slices ordered by length, lanes stop at
+            // their own row; windows start at every system's first slice
+            std::vector<int32_t> hw, hofs(S.nslices + 1);
+            std::vector<int32_t> s0(2, 0);
+            if (seg.row0 && seg.nsys > 1) {
+                s0.resize(seg.nsys + 1);
+                segment_slices(seg, n, s0.data());
+            } else {
+                s0[1] = S.nslices;
+            }
+            for (size_t k = 0; k + 1 < s0.size(); ++k)
+                for (int w = s0[k]; w < s0[k + 1]; w += kWin) {
+                    for (int j = w; j < std::min(s0[k + 1], w + kWin); ++j) hofs[j] = (int32_t)hw.size();
+                    hw.push_back(w);
+                }
+            S.nwin = (int)hw.size();
+            hw.push_back(S.nslices);
+            hofs[S.nslices] = S.nwin;
             S.perm = (int32_t *)pool_alloc(sizeof(int32_t) * (size_t)S.nslices * kSlice);
             S.lens = (int32_t *)pool_alloc(sizeof(int32_t) * (size_t)S.nslices * kSlice);
-            S.iperm = (int32_t *)pool_alloc(sizeof(int32_t) * (size_t)S.nslices * kSlice);
-            if (!S.perm || !S.lens || !S.iperm)
+            S.wsl = (int32_t *)pool_alloc(sizeof(int32_t) * hw.size());
+            S.wofs = (int32_t *)pool_alloc(sizeof(int32_t) * hofs.size());
+            if (!S.perm || !S.lens || !S.wsl || !S.wofs)
                 return fail(set_error_code(AFSAI_ERR_NO_MEMORY, "SELL layout: out of device memory"));
-            hipLaunchKernelGGL(k_slice_sort, dim3(nbs), dim3(256), 0, s, n, S.nslices, rp, m, S.srow0, S.perm, S.lens,
-                               S.iperm);
+            if (hipMemcpyAsync(S.wsl, hw.data(), sizeof(int32_t) * hw.size(), hipMemcpyHostToDevice, s) != hipSuccess ||
+                hipMemcpyAsync(S.wofs, hofs.data(), sizeof(int32_t) * hofs.size(), hipMemcpyHostToDevice, s) !=
+                    hipSuccess ||
+                hipStreamSynchronize(s) != hipSuccess)
+                return fail(set_error_code(AFSAI_ERR_HIP, "SELL layout: copy of the windows failed"));
+            hipLaunchKernelGGL(k_window_sort, dim3(std::min(S.nwin, di.num_cus * 16)), dim3(kWin * kSlice), 0, s, n,
+                               S.nwin, S.wsl, rp, m, S.srow0, S.perm, S.lens);
+            // each slice's width is now its longest ordered row
+            hipLaunchKernelGGL(k_sell_width, dim3(nbs), dim3(256), 0, s, n, S.nslices, rp, m, S.perm, S.srow0, kNoCap,
+                               width.as<int32_t>());
+            if ((rc = scan_counts(S.nslices, width.as<int32_t>(), (int32_t *)S.sptr, &cols, di, s))) return fail(rc);
         } else if (padded) {
             // split at the width that minimises the work (host choice from device statistics)
             DevBuf hist;

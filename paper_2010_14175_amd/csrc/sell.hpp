@@ -5,10 +5,12 @@
 // together.  Rows shorter than the slice's longest row are padded with (own row, 0.0).
 //
 // When that padding would exceed a tenth of the entries (rows of very different lengths, as
-// in G^T), each slice's rows are ordered by length (`perm`, with `lens` the length of each
-// lane's row and `iperm` the lane of each row; SELL-C-sigma with sigma = C = 64, Kreutzer et
-// al. 2014): every lane stops at its own row's length, so the padding is never read, and the
-// row sums go back to their natural lanes before they are stored.  The alternative split form
+// in G^T), the rows of each window of 4 consecutive slices (256 rows, never across two systems
+// of a batch) are ordered by length and dealt to the window's slices (`perm`, with `lens` the
+// length of each lane's row; SELL-C-sigma with C = 64, sigma = 256, Kreutzer et al. 2014):
+// every lane stops at its own row's length, so the padding is never read, and the slices hold
+// rows of similar length.  The four wavefronts of a block multiply one window and return the
+// row sums to their natural rows through LDS before they are stored.  The alternative split form
 // keeps every row's last w entries in the slices (w chosen from the length histogram) and the
 // leading entries of the longer rows in a second SELL matrix (`tail`, in row order; `rowmap`
 // maps its rows to rows of the full matrix), multiplied first; the main product then continues
@@ -22,6 +24,7 @@
 namespace afsai {
 
 constexpr int kSlice = 64;
+constexpr int kWin = 4;  // slices per window of rows ordered by length (one block of 4 wavefronts)
 
 struct Sell {
     int n = 0;
@@ -32,7 +35,9 @@ struct Sell {
     int32_t *perm = nullptr;    // [nslices * 64] row of each slice lane (nullptr: identity)
     int32_t *lens = nullptr;    // [nslices * 64] entries of each slice lane's row (nullptr: all
                                 // lanes run the slice's width; else padding is never read)
-    int32_t *iperm = nullptr;   // with lens: [nslices * 64] lane holding the slice's k-th row
+    int32_t *wsl = nullptr;     // with lens: [nwin + 1] first slice of each window
+    int32_t *wofs = nullptr;    // with lens: [nslices + 1] window of each slice (nwin at the end)
+    int nwin = 0;
     int32_t *rowmap = nullptr;  // [n] output row of each row (nullptr: identity)
     uint64_t *init = nullptr;   // [nslices] lanes whose sums continue from y (nullptr: none)
     Sell *tail = nullptr;       // leading entries of the rows longer than the slices hold

@@ -259,7 +259,10 @@ __device__ __forceinline__ void sell_slice_rows(const int32_t *srow0, int n, int
 
 // SELL-64 product: one wavefront per slice of 64 rows, one lane per row; entry k of the 64
 // rows is one contiguous wave load.  Optional fused dot y.w.  For the tail of a split layout
-// (perm/rowmap set) the launch is not tied to systems (mp, sy empty, scs may be null).
+// (perm/rowmap set) the launch is not tied to systems (mp, sy empty, scs may be null).  With
+// rows ordered by length (lens set) a block takes whole windows of kWin slices, one per
+// wavefront, and the sums reach their natural rows through LDS, so that y is written and the
+// dot summed in row order.
 template <int U, typename VT, bool DOT>
 __global__ __launch_bounds__(kThreads) void k_sell_spmv(int n, int nslices, const uint32_t *__restrict__ sptr,
                                                          const int32_t *__restrict__ srow0,
@@ -272,7 +275,8 @@ __global__ __launch_bounds__(kThreads) void k_sell_spmv(int n, int nslices, cons
                                                          const double *__restrict__ w,
                                                          double *__restrict__ partials, PcgScalars *scs, Map mp,
                                                          Systems sy, int nxcd, const int32_t *__restrict__ lens,
-                                                         const int32_t *__restrict__ iperm,
+                                                         const int32_t *__restrict__ wsl,
+                                                         const int32_t *__restrict__ wofs,
                                                          const uint32_t *__restrict__ tsptr,
                                                          const int32_t *__restrict__ tcol,
                                                          const VT *__restrict__ tval,
@@ -283,9 +287,64 @@ __global__ __launch_bounds__(kThreads) void k_sell_spmv(int n, int nslices, cons
     const int sb = sy.slice0 ? sy.slice0[jb.k] : 0;
     const int sn = sy.slice0 ? sy.slice0[jb.k + 1] - sb : nslices;
     int s0, s1;
-    block_range(sb, sn, jb.lb, jb.nb, s0, s1);
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
     double part = 0.0;
+    if (lens) {
+        static_assert(kThreads == kWin * kSlice, "one wavefront per slice of a window");
+        __shared__ double sy_win[kWin * kSlice];
+        const int wa = wofs[sb], wb = wofs[sb + sn];
+        int w0, w1;
+        block_range(wa, wb - wa, jb.lb, jb.nb, w0, w1);
+        for (int wi = w0; wi < w1; ++wi) {
+            const int ws = wsl[wi], we = wsl[wi + 1];
+            int wr0, u0;
+            sell_slice_rows(srow0, n, ws, wr0, u0);
+            const int sl = ws + wv;
+            if (sl < we) {
+                const int64_t li = (int64_t)sl * kSlice + lane;
+                const int r = perm[li];
+                const int len = lens[li];
+                const int64_t base = (int64_t)sptr[sl] * kSlice + lane;
+                double acc = 0.0;
+                for (int k0 = 0; k0 < len; k0 += U) {
+                    int c[U];
+                    VT v[U];
+#pragma unroll
+                    for (int u = 0; u < U; ++u) {
+                        c[u] = -1;
+                        v[u] = VT(0);
+                        if (k0 + u < len) {
+                            const int64_t d = base + (int64_t)(k0 + u) * kSlice;
+                            c[u] = __builtin_nontemporal_load(&col[d]);
+                            v[u] = __builtin_nontemporal_load(&val[d]);
+                        }
+                    }
+#pragma unroll
+                    for (int u = 0; u < U; ++u)
+                        if (c[u] >= 0) acc = fma((double)v[u], x[c[u]], acc);
+                }
+                if (r >= 0) sy_win[r - wr0] = acc;
+            }
+            __syncthreads();
+            if (sl < we) {
+                int r0, r1;
+                sell_slice_rows(srow0, n, sl, r0, r1);
+                const int rn = r0 + lane;
+                if (rn < r1) {
+                    const double an = sy_win[rn - wr0];
+                    y[rn] = an;
+                    if (DOT) part = fma(an, w[rn], part);
+                }
+            }
+            __syncthreads();
+        }
+        if (DOT) {
+            const double bs = block_sum(part, sh);
+            store_partials(partials, 1, &bs, jb.gb);
+        }
+        return;
+    }
+    block_range(sb, sn, jb.lb, jb.nb, s0, s1);
     for (int sl = s0 + wv; sl < s1; sl += kThreads / 64) {
         int r0, r1;
         sell_slice_rows(srow0, n, sl, r0, r1);
@@ -295,7 +354,6 @@ __global__ __launch_bounds__(kThreads) void k_sell_spmv(int n, int nslices, cons
         const int ro = (valid && rowmap) ? rowmap[r] : r;
         const uint32_t c0 = sptr[sl];
         const int width = (int)(sptr[sl + 1] - c0);
-        const int len = lens ? lens[(int64_t)sl * kSlice + lane] : width;  // entries this lane reads
         const int64_t base = (int64_t)c0 * kSlice + lane;
         // rows split between the two layouts start with their leading entries: run here from the
         // tail layout (tcol set; the slice's split rows are consecutive tail rows), or continue
@@ -322,7 +380,7 @@ __global__ __launch_bounds__(kThreads) void k_sell_spmv(int n, int nslices, cons
             for (int u = 0; u < U; ++u) {
                 c[u] = -1;
                 v[u] = VT(0);
-                if (k0 + u < len) {
+                if (k0 + u < width) {
                     const int64_t d = base + (int64_t)(k0 + u) * kSlice;
                     c[u] = __builtin_nontemporal_load(&col[d]);
                     v[u] = __builtin_nontemporal_load(&val[d]);
@@ -332,16 +390,7 @@ __global__ __launch_bounds__(kThreads) void k_sell_spmv(int n, int nslices, cons
             for (int u = 0; u < U; ++u)
                 if (c[u] >= 0) acc = fma((double)v[u], x[c[u]], acc);
         }
-        if (lens) {
-            // lanes ordered by length: each lane takes its natural row's sum, so that y is
-            // written and the dot summed in row order as with unordered slices
-            const double an = __shfl(acc, iperm[(int64_t)sl * kSlice + lane]);
-            const int rn = r0 + lane;
-            if (rn < r1) {
-                y[rn] = an;
-                if (DOT) part = fma(an, w[rn], part);
-            }
-        } else if (valid) {
+        if (valid) {
             y[ro] = acc;
             if (DOT) part = fma(acc, w[ro], part);
         }
@@ -734,11 +783,11 @@ static void launch_sell_t(const Sell &S, const double *x, double *y, const doubl
     if (w)
         hipLaunchKernelGGL((k_sell_spmv<U, VT, true>), dim3(nb), dim3(kThreads), 0, s, S.n, S.nslices, S.sptr,
                            S.srow0, S.perm, S.rowmap, S.init, S.col, (const VT *)S.val, x, y, w, partials, scs, mp,
-                           sy, nxcd, S.lens, S.iperm, tsp, tcl, tvl, tof);
+                           sy, nxcd, S.lens, S.wsl, S.wofs, tsp, tcl, tvl, tof);
     else
         hipLaunchKernelGGL((k_sell_spmv<U, VT, false>), dim3(nb), dim3(kThreads), 0, s, S.n, S.nslices, S.sptr,
                            S.srow0, S.perm, S.rowmap, S.init, S.col, (const VT *)S.val, x, y, w, partials, scs, mp,
-                           sy, nxcd, S.lens, S.iperm, tsp, tcl, tvl, tof);
+                           sy, nxcd, S.lens, S.wsl, S.wofs, tsp, tcl, tvl, tof);
 }
 
 template <typename VT>
