@@ -251,13 +251,15 @@ __global__ __launch_bounds__(256) void k_sell_fill(int n, int nslices, const int
     }
 }
 
-// The same layout for whole rows in row order (no split, no ordering): each group of 8 lanes
-// reads 8 consecutive entries of one row and writes them to 8 consecutive positions of their
-// slice columns, so a wave instruction touches 8 segments of the matrix instead of 64.
+// The same layout for whole rows (no split; rows in row order, or those perm assigns to each
+// slice position): each group of 8 lanes reads 8 consecutive entries of one row and writes
+// them to 8 consecutive positions of their slice columns, so a wave instruction touches 8
+// segments of the matrix instead of 64.
 template <typename VI, typename VO>
 __global__ __launch_bounds__(256) void k_sell_fill_rows(int n, int nslices, const int32_t *__restrict__ rp,
                                                          const int32_t *__restrict__ m, int ld,
                                                          const int32_t *__restrict__ ci, const VI *__restrict__ val,
+                                                         const int32_t *__restrict__ perm,
                                                         const int32_t *__restrict__ srow0,
                                                         const int32_t *__restrict__ sptr, int32_t *__restrict__ col,
                                                         VO *__restrict__ out) {
@@ -269,8 +271,8 @@ __global__ __launch_bounds__(256) void k_sell_fill_rows(int n, int nslices, cons
         const int64_t base = (int64_t)sptr[sl] * kSlice;
         const int width = sptr[sl + 1] - sptr[sl];
         for (int rb = 0; rb < kSlice; rb += 8) {
-            const int r = r0 + rb + rsub;
-            const bool valid = r < r1;
+            const int r = perm ? perm[(int64_t)sl * kSlice + rb + rsub] : r0 + rb + rsub;
+            const bool valid = perm ? r >= 0 : r < r1;
             const int64_t start = valid ? row_start(rp, ld, r) : 0;
             const int len = valid ? row_len(rp, m, r) : 0;
             const int pad_col = valid ? r : r0;
@@ -546,22 +548,22 @@ static int sell_build(int n, int64_t nnz, const int32_t *rp, const int32_t *m, i
     S.val = pool_alloc((out_f32 ? sizeof(float) : sizeof(double)) * (size_t)cols * kSlice);
     if (!S.col || !S.val) return fail(set_error_code(AFSAI_ERR_NO_MEMORY, "SELL layout: out of device memory"));
     const int32_t *sp = (const int32_t *)S.sptr;
-    if (!S.perm && cap == kNoCap && !S.init) {
-        // whole rows in row order
+    if (cap == kNoCap && !S.init) {
+        // whole rows
         if (val_f32) {
             if (out_f32)
                 hipLaunchKernelGGL((k_sell_fill_rows<float, float>), dim3(nbs), dim3(256), 0, s, n, S.nslices, rp, m, ld,
-                                   ci, (const float *)val, S.srow0, sp, S.col, (float *)S.val);
+                                   ci, (const float *)val, S.perm, S.srow0, sp, S.col, (float *)S.val);
             else
                 hipLaunchKernelGGL((k_sell_fill_rows<float, double>), dim3(nbs), dim3(256), 0, s, n, S.nslices, rp,
-                                   m, ld, ci, (const float *)val, S.srow0, sp, S.col, (double *)S.val);
+                                   m, ld, ci, (const float *)val, S.perm, S.srow0, sp, S.col, (double *)S.val);
         } else {
             if (out_f32)
                 hipLaunchKernelGGL((k_sell_fill_rows<double, float>), dim3(nbs), dim3(256), 0, s, n, S.nslices, rp,
-                                   m, ld, ci, (const double *)val, S.srow0, sp, S.col, (float *)S.val);
+                                   m, ld, ci, (const double *)val, S.perm, S.srow0, sp, S.col, (float *)S.val);
             else
                 hipLaunchKernelGGL((k_sell_fill_rows<double, double>), dim3(nbs), dim3(256), 0, s, n, S.nslices, rp,
-                                   m, ld, ci, (const double *)val, S.srow0, sp, S.col, (double *)S.val);
+                                   m, ld, ci, (const double *)val, S.perm, S.srow0, sp, S.col, (double *)S.val);
         }
     } else if (val_f32) {
         if (out_f32)

@@ -202,6 +202,27 @@ __global__ __launch_bounds__(256) void k_transpose_fill(int n, const int32_t *__
     }
 }
 
+// The same from the padded per-row results (ld slots per row, m[i] valid): one thread per slot,
+// so every entry's slot reservation is independent of the others (the row is slot / ld)
+template <typename VT>
+__global__ __launch_bounds__(256) void k_transpose_fill_ell(int n, int ld, const int32_t *__restrict__ m,
+                                                            const int32_t *__restrict__ ell_col,
+                                                            const double *__restrict__ ell_val,
+                                                            const int32_t *__restrict__ t_rp,
+                                                            int32_t *__restrict__ fill, int32_t *__restrict__ t_ci,
+                                                            VT *__restrict__ t_val) {
+    const int64_t total = (int64_t)n * ld;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < total; k += (int64_t)gridDim.x * blockDim.x) {
+        const int i = (int)(k / ld), t = (int)(k - (int64_t)i * ld);
+        if (t < m[i]) {
+            const int c = ell_col[k];
+            const int d = t_rp[c] + atomicAdd(&fill[c], 1);
+            t_ci[d] = i;
+            t_val[d] = (VT)ell_val[k];
+        }
+    }
+}
+
 // Sorts every row of G^T by column (= row of G).  One wavefront per row: rows of up to 128
 // entries are ranked in registers (each lane counts the smaller keys, one or two keys per
 // lane); longer rows fall back to an insertion sort by one lane.
@@ -365,9 +386,12 @@ static void free_handle(afsai_precond_s *P) {
     delete P;
 }
 
-// G^T as SELL-64, built from the CSR G of the handle (count, scan, fill, sort, convert)
+// G^T as SELL-64, built from the CSR G of the handle (count, scan, fill, sort, convert); the
+// fill reads the padded per-row results when given (ld slots per row, m[i] valid)
 template <typename VT>
-static int build_transpose(afsai_precond_s *P, const DeviceInfo &di, hipStream_t s, const Segments &seg) {
+static int build_transpose(afsai_precond_s *P, const DeviceInfo &di, hipStream_t s, const Segments &seg,
+                           int ld = 0, const int32_t *m = nullptr, const int32_t *ell_col = nullptr,
+                           const double *ell_val = nullptr) {
     const int n = P->n;
     const int64_t nnz = P->nnz_g;
     DevBuf cnt, rp, ci, val;
@@ -386,9 +410,14 @@ static int build_transpose(afsai_precond_s *P, const DeviceInfo &di, hipStream_t
     {
         ProfScope ps("transpose", s);
         hipLaunchKernelGGL(k_fill_i32, dim3(grid1d(n, di)), dim3(256), 0, s, (int64_t)n, cnt.as<int32_t>(), 0);
-        hipLaunchKernelGGL((k_transpose_fill<VT>), dim3(grid1d((int64_t)n * 64, di)), dim3(256), 0, s, n, P->g_rp,
-                           P->g_ci, (const VT *)P->g_val, rp.as<int32_t>(), cnt.as<int32_t>(), ci.as<int32_t>(),
-                           val.as<VT>());
+        if (ell_col)
+            hipLaunchKernelGGL((k_transpose_fill_ell<VT>), dim3(grid1d((int64_t)n * ld, di)), dim3(256), 0, s, n, ld,
+                               m, ell_col, ell_val, rp.as<int32_t>(), cnt.as<int32_t>(), ci.as<int32_t>(),
+                               val.as<VT>());
+        else
+            hipLaunchKernelGGL((k_transpose_fill<VT>), dim3(grid1d((int64_t)n * 64, di)), dim3(256), 0, s, n,
+                               P->g_rp, P->g_ci, (const VT *)P->g_val, rp.as<int32_t>(), cnt.as<int32_t>(),
+                               ci.as<int32_t>(), val.as<VT>());
         hipLaunchKernelGGL((k_sort_rows<VT>), dim3(grid1d((int64_t)n * 64, di)), dim3(256), 0, s, n, rp.as<int32_t>(),
                            ci.as<int32_t>(), val.as<VT>());
     }
@@ -634,7 +663,10 @@ static int setup_core(const afsai_csr *A, const afsai_params *p, int nsys, const
             return fail(rc);
     }
     if (nsys > 1) P->seg_row0.assign(row0, row0 + nsys + 1);
-    rc = f32 ? build_transpose<float>(P, di, s, seg) : build_transpose<double>(P, di, s, seg);
+    rc = f32 ? build_transpose<float>(P, di, s, seg, ldell, mcnt.as<int32_t>(), ell_col.as<int32_t>(),
+                                      ell_val.as<double>())
+             : build_transpose<double>(P, di, s, seg, ldell, mcnt.as<int32_t>(), ell_col.as<int32_t>(),
+                                       ell_val.as<double>());
     if (rc) return fail(rc);
     P->psi = (double *)psi.release();
     P->steps = (int32_t *)steps.release();
