@@ -319,11 +319,12 @@ const char *afsai_last_error(void);
  *                             entries of the long rows run in a launch of their own first,
  *                             1 inside the slices' kernel (identical results)
  *   AFSAI_OPT_SELL_UNEVEN     SELL-64 layouts of matrices with uneven rows (G^T): 0 (automatic)
- *                             each slice's rows ordered by length, every lane reading its own
- *                             row's entries only; 1 split layouts (the slices keep each row's
- *                             last w entries, a second layout the leading ones).  Products are
- *                             identical row by row; fused dot products are summed in another
- *                             order
+ *                             the rows of each window of 4 slices (256 rows, within one system
+ *                             of a batch) ordered by length and dealt to the window's slices,
+ *                             every lane reading its own row's entries only; 1 split layouts
+ *                             (the slices keep each row's last w entries, a second layout the
+ *                             leading ones).  Products are identical row by row; fused dot
+ *                             products are summed in another order
  * Returns AFSAI_ERR_INVALID_ARG for an unknown option or value.  Not thread safe against
  * concurrent calls of the library.
  */

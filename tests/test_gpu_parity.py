@@ -474,10 +474,10 @@ def test_split_layouts_identical(af, make, width):
 @pytest.mark.parametrize("make", [lambda: synth.elasticity27(10), lambda: synth.random_sparse_spd(3000, 40, 3),
                                   lambda: synth.poisson7(9)])
 def test_sorted_slices_against_split(af, make):
-    """Uneven rows (G^T; A of small Poisson grids) as slices ordered by length with every lane
-    reading only its own row against split layouts: G^T(G r) and A x bit for bit equal (each
-    row is the same sequential chain), PCG iterates equal to rounding of the fused dots and
-    both within the oracle's tolerance."""
+    """Uneven rows (G^T; A of small Poisson grids) ordered by length within windows of slices,
+    every lane reading only its own row, against split layouts: G^T(G r) and A x bit for bit
+    equal (each row is the same sequential chain), PCG iterates equal to rounding of the fused
+    dots and both within the oracle's tolerance."""
     Pb = make()
     A = Pb.A if hasattr(Pb, "A") else Pb
     b = Pb.b if hasattr(Pb, "b") else A.to_scipy() @ synth.uniform(7, 2, A.n, -1.0, 1.0)
