@@ -85,6 +85,24 @@ def test_batched_pcg_equals_standalone(af, precond):
         assert infos[k].true_relres == pytest.approx(ik.true_relres, rel=1e-12, abs=1e-30)
 
 
+def test_batched_apply_equals_standalone(af):
+    """z = G^T (G r) with a batched preconditioner (the whole batch as one launch, its G^T
+    windows aligned at every system's first slice) equals each system's own preconditioner
+    applied to its share of r, bit for bit, and the oracle's G^T (G r) within 1e-10."""
+    probs, A, off, b, _ = _batch(7, 2, 16)
+    dA = af.DeviceCSR.from_host(A)
+    P = af.setup_batched(dA, off, 5, 1, 1e-2)
+    r = synth.uniform(11, 4, A.n, -1.0, 1.0)
+    z = P.apply(_vec(r)).cpu().numpy()
+    for k, pb in enumerate(probs):
+        Pk = af.setup(af.DeviceCSR.from_host(pb.A), 5, 1, 1e-2)
+        zk = Pk.apply(_vec(r[off[k]:off[k + 1]])).cpu().numpy()
+        assert np.array_equal(z[off[k]:off[k + 1]].view(np.int64), zk.view(np.int64)), k
+    G = oracle.setup(A, 5, 1, 1e-2).to_scipy()
+    zo = G.T @ (G @ r)
+    assert np.linalg.norm(z - zo) <= 1e-10 * np.linalg.norm(zo)
+
+
 def test_batched_pcg_against_oracle(af):
     probs, A, off, b, _ = _batch(5, 3, 9)
     dA = af.DeviceCSR.from_host(A)
