@@ -249,6 +249,52 @@ def jacobi_bench(args):
     print(json.dumps(out), flush=True)
 
 
+def spmm_bench(args):
+    """Y = A X for blocks of 1, 2, 4 and 8 right-hand sides with A of the 27-point 64^3
+    workload: the product kernel's time per block (HIP events on its launch stream, median of
+    the steps) and per right-hand side, and its algorithmic bytes (every matrix entry once, X
+    and Y once) over that time."""
+    import torch
+
+    import paper_2010_14175_amd as af
+    import synth
+
+    pb = workloads()["elast27_64"]()
+    dA = af.DeviceCSR.from_host(pb.A)
+    n, nnz = pb.n, pb.A.nnz
+    X8 = torch.from_numpy(synth.uniform(13, 5, n * 8, -1.0, 1.0).reshape(n, 8)).cuda()
+    res = {}
+    for k in (1, 2, 4, 8):
+        X = X8[:, :k].contiguous()
+        Y = torch.empty_like(X)
+        for _ in range(args.warmup):
+            af.spmm(dA, X, Y)
+        torch.cuda.synchronize()
+        af.profile_only(["spmm_A"])
+        us = []
+        try:
+            for _ in range(args.steps):
+                af.profile_read(reset=True)
+                af.profile_enable(True)
+                af.spmm(dA, X, Y)
+                af.profile_enable(False)
+                us.append(af.profile_read(reset=True)["spmm_A"][1] * 1e3)
+        finally:
+            af.profile_enable(False)
+            af.profile_only(None)
+        t = float(np.median(us))
+        byt = 12.0 * nnz + 4.0 * (n + 1) + 16.0 * k * n
+        res[f"k{k}"] = {"us": round(t, 2), "us_per_rhs": round(t / k, 2), "gbs": round(byt / (t * 1e-6) / 1e9, 1),
+                        "bytes": byt}
+        print(f"[bench] spmm k={k}: {t:.1f} us ({t / k:.1f} us per right-hand side, "
+              f"{res[f'k{k}']['gbs']} GB/s algorithmic)", file=sys.stderr, flush=True)
+    out = {"metric": "SpMM time per right-hand side, k = 8 against k = 1", "value":
+           round(res["k8"]["us_per_rhs"] / res["k1"]["us"], 4), "unit": "ratio", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "higher_is_better": False, "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic", "config": {"workload": "spmm", "n": n, "nnz": nnz}, "results": res}
+    print(json.dumps(out), flush=True)
+
+
 def workloads():
     import synth
 
@@ -364,7 +410,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="elast27_64",
-                    choices=sorted(list(workloads()) + list(BATCH_WORKLOADS) + ["serve", "jacobi_compare"]))
+                    choices=sorted(list(workloads()) + list(BATCH_WORKLOADS) + ["serve", "jacobi_compare", "spmm"]))
     ap.add_argument("--with-largest", action="store_true", help="jacobi_compare: add the 150^3 27-point workload")
     ap.add_argument("--requests", type=int, default=300, help="serve: number of requests")
     ap.add_argument("--pool", type=int, default=16, help="serve: distinct systems the requests draw from")
@@ -405,6 +451,9 @@ def main():
         return
     if args.workload == "jacobi_compare":
         jacobi_bench(args)
+        return
+    if args.workload == "spmm":
+        spmm_bench(args)
         return
     pb = workloads()[args.workload]()
     g_prec = af.F32 if args.g_prec == "f32" else af.F64

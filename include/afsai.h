@@ -248,6 +248,21 @@ int afsai_server_destroy(afsai_server S);
 /* afsai_spmv -- y = A x (group-per-row CSR product used by the solver).  Asynchronous. */
 int afsai_spmv(const afsai_csr *A, const double *x, double *y, void *stream);
 
+/*
+ * afsai_spmm -- Y = A X for k right-hand sides at once (the product of a PCG over several
+ *   right-hand sides, where every iteration multiplies one block of k vectors; Sec. 4.1 keeps
+ *   such dense blocks with each row's entries contiguous, for systems with several
+ *   right-hand sides).
+ *   X, Y (device): n x k, row-major (entry (i, j) at i * k + j, so the k values of a row are
+ *   contiguous); caller-owned, must not alias.  k: 1, 2, 4 or 8.
+ *   A is converted to its SELL-64 layout for the call (rows ordered by length when uneven) and
+ *   every matrix entry is read once for the k vectors; column j of Y equals the single-vector
+ *   SELL product of column j bit for bit.  Synchronous on stream.
+ *   Errors: AFSAI_ERR_INVALID_ARG (k, null or aliased blocks, a split layout forced with
+ *   AFSAI_OPT_SELL_UNEVEN = 1), AFSAI_ERR_NO_MEMORY, AFSAI_ERR_HIP.
+ */
+int afsai_spmm(const afsai_csr *A, int32_t k, const double *X, double *Y, void *stream);
+
 /* afsai_get_setup_info -- diagnostics of a handle (host struct). */
 int afsai_get_setup_info(afsai_precond P, afsai_setup_info *info);
 

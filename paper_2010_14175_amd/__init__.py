@@ -31,7 +31,7 @@ STOP_KMAX, STOP_EPS, STOP_NOCAND = 0, 1, 2
 # every symbol the C header declares
 EXPORTS = ("afsai_setup", "afsai_apply", "pcg_solve", "afsai_setup_batched", "pcg_solve_batched",
            "afsai_server_create", "afsai_server_submit", "afsai_server_poll", "afsai_server_pending",
-           "afsai_server_destroy", "afsai_spmv",
+           "afsai_server_destroy", "afsai_spmv", "afsai_spmm",
            "afsai_get_setup_info", "afsai_export",
            "afsai_export_rows", "afsai_import", "afsai_destroy", "afsai_last_error", "afsai_set_option",
            "afsai_release_cache",
@@ -104,6 +104,7 @@ def lib():
         L.afsai_apply.argtypes = [vp, vp, vp, vp]
         L.pcg_solve.argtypes = [P(CsrStruct), vp, vp, vp, ctypes.c_double, i32, vp, P(PcgInfoStruct)]
         L.afsai_spmv.argtypes = [P(CsrStruct), vp, vp, vp]
+        L.afsai_spmm.argtypes = [P(CsrStruct), ctypes.c_int32, vp, vp, vp]
         L.afsai_server_create.argtypes = [P(ServerConfigStruct), P(vp)]
         L.afsai_server_submit.argtypes = [vp, P(CsrStruct), P(ParamsStruct), vp, vp, P(ctypes.c_int64)]
         L.afsai_server_poll.argtypes = [vp, P(RequestResultStruct), i32, P(i32), i32]
@@ -417,6 +418,19 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+def spmm(A: DeviceCSR, X, Y=None, stream=None):
+    """Y = A X for an (n, k) row-major block of k = 1, 2, 4 or 8 vectors (``afsai_spmm``)."""
+    import torch
+
+    if X.dim() != 2 or X.shape[0] != A.n or not X.is_contiguous() or X.dtype != torch.float64:
+        raise ValueError("spmm: X must be a contiguous float64 (n, k) tensor")
+    if Y is None:
+        Y = torch.empty_like(X)
+    st = A.struct
+    _check(lib().afsai_spmm(ctypes.byref(st), int(X.shape[1]), _ptr(X), _ptr(Y), _stream(stream)), "afsai_spmm")
+    return Y
 
 
 def spmv(A: DeviceCSR, x, y=None, stream=None):

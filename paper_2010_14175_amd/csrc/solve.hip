@@ -875,6 +875,64 @@ static void sell_fused(const char *name, const Sell &S, const BatchMaps &bm, con
                        scs);
 }
 
+// Y = A X for K vectors stored row by row (entry (i, j) at i * K + j): one wavefront per
+// SELL-64 slice, one lane per row; every matrix entry is read once for the K vectors and the
+// K values of a gathered row are contiguous.  Each output is the same sequential chain over
+// the row's entries as in the single-vector product.
+template <int K, typename VT>
+__global__ __launch_bounds__(kThreads) void k_sell_spmm(int n, int nslices, const uint32_t *__restrict__ sptr,
+                                                         const int32_t *__restrict__ perm,
+                                                         const int32_t *__restrict__ lens,
+                                                         const int32_t *__restrict__ col,
+                                                         const VT *__restrict__ val, const double *__restrict__ x,
+                                                         double *__restrict__ y, int nxcd) {
+    constexpr int U = 4;
+    const int lb = xcd_block(blockIdx.x, gridDim.x, nxcd);
+    int s0, s1;
+    block_range(0, nslices, lb, gridDim.x, s0, s1);
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int sl = s0 + wv; sl < s1; sl += kThreads / 64) {
+        const uint32_t c0 = sptr[sl];
+        int r = sl * kSlice + lane;
+        bool valid = r < n;
+        int len = (int)(sptr[sl + 1] - c0);
+        if (lens) {
+            r = perm[(int64_t)sl * kSlice + lane];
+            len = lens[(int64_t)sl * kSlice + lane];
+            valid = r >= 0;
+        }
+        const int64_t base = (int64_t)c0 * kSlice + lane;
+        double acc[K];
+#pragma unroll
+        for (int j = 0; j < K; ++j) acc[j] = 0.0;
+        for (int k0 = 0; k0 < len; k0 += U) {
+            int c[U];
+            VT v[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                c[u] = -1;
+                v[u] = VT(0);
+                if (k0 + u < len) {
+                    const int64_t d = base + (int64_t)(k0 + u) * kSlice;
+                    c[u] = __builtin_nontemporal_load(&col[d]);
+                    v[u] = __builtin_nontemporal_load(&val[d]);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (c[u] >= 0) {
+                    const double *xc = x + (int64_t)c[u] * K;
+#pragma unroll
+                    for (int j = 0; j < K; ++j) acc[j] = fma((double)v[u], xc[j], acc[j]);
+                }
+        }
+        if (valid) {
+#pragma unroll
+            for (int j = 0; j < K; ++j) y[(int64_t)r * K + j] = acc[j];
+        }
+    }
+}
+
 static int check_csr_arg(const afsai_csr *A, const char *who) {
     if (!A) AFSAI_FAIL(AFSAI_ERR_INVALID_ARG, "%s: A is NULL", who);
     if (A->n <= 0 || A->nnz < A->n) AFSAI_FAIL(AFSAI_ERR_INVALID_ARG, "%s: n = %d, nnz = %d", who, A->n, A->nnz);
@@ -1355,6 +1413,46 @@ int afsai_spmv(const afsai_csr *A, const double *x, double *y, void *stream) {
     hipStream_t s = (hipStream_t)stream;
     spmv("spmv_A", csr_of(A), x, y, nullptr, nullptr, nullptr, FIN_NONE, di, s);
     AFSAI_HIP_TRY(hipGetLastError());
+    return AFSAI_OK;
+}
+
+int afsai_spmm(const afsai_csr *A, int32_t k, const double *X, double *Y, void *stream) {
+    if (k != 1 && k != 2 && k != 4 && k != 8) AFSAI_FAIL(AFSAI_ERR_INVALID_ARG, "afsai_spmm: k = %d (1, 2, 4 or 8)", k);
+    int rc = check_csr_arg(A, "afsai_spmm");
+    if (rc) return rc;
+    if (!X || !Y) AFSAI_FAIL(AFSAI_ERR_INVALID_ARG, "afsai_spmm: null block");
+    if (X == Y) AFSAI_FAIL(AFSAI_ERR_INVALID_ARG, "afsai_spmm: X and Y alias");
+    DeviceInfo di;
+    if ((rc = device_info(&di))) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    Sell S;
+    {
+        ProfScope ps("sell_A", s);
+        if ((rc = sell_from_csr(A->n, A->nnz, A->row_ptr, A->col_idx, A->val, false, false, &S, di, s))) return rc;
+    }
+    if (S.tail || S.srow0) {
+        sell_free(&S);
+        AFSAI_FAIL(AFSAI_ERR_INVALID_ARG, "afsai_spmm: split SELL layouts (AFSAI_OPT_SELL_UNEVEN = 1) are not supported");
+    }
+    {
+        ProfScope ps("spmm_A", s);
+        const int nb = blocks_for_slices(S.nslices, di);
+        const double *vx = X;
+        switch (k) {
+            case 1: hipLaunchKernelGGL((k_sell_spmm<1, double>), dim3(nb), dim3(kThreads), 0, s, S.n, S.nslices, S.sptr,
+                                       S.perm, S.lens, S.col, (const double *)S.val, vx, Y, di.num_xcds); break;
+            case 2: hipLaunchKernelGGL((k_sell_spmm<2, double>), dim3(nb), dim3(kThreads), 0, s, S.n, S.nslices, S.sptr,
+                                       S.perm, S.lens, S.col, (const double *)S.val, vx, Y, di.num_xcds); break;
+            case 4: hipLaunchKernelGGL((k_sell_spmm<4, double>), dim3(nb), dim3(kThreads), 0, s, S.n, S.nslices, S.sptr,
+                                       S.perm, S.lens, S.col, (const double *)S.val, vx, Y, di.num_xcds); break;
+            default: hipLaunchKernelGGL((k_sell_spmm<8, double>), dim3(nb), dim3(kThreads), 0, s, S.n, S.nslices, S.sptr,
+                                        S.perm, S.lens, S.col, (const double *)S.val, vx, Y, di.num_xcds); break;
+        }
+    }
+    const hipError_t le = hipGetLastError();
+    const hipError_t se = hipStreamSynchronize(s);
+    sell_free(&S);
+    if (le != hipSuccess || se != hipSuccess) AFSAI_FAIL(AFSAI_ERR_HIP, "afsai_spmm: %s", hipGetErrorString(le != hipSuccess ? le : se));
     return AFSAI_OK;
 }
 
