@@ -263,6 +263,22 @@ int afsai_spmv(const afsai_csr *A, const double *x, double *y, void *stream);
  */
 int afsai_spmm(const afsai_csr *A, int32_t k, const double *X, double *Y, void *stream);
 
+/*
+ * pcg_solve_multi -- PCG (M^-1 = G^T G, or plain CG with P == NULL) for k right-hand sides at
+ *   once, A X = B: k independent textbook recurrences (each with its own alpha, beta, rho and
+ *   stopping test ||r_j|| <= rtol ||b_j||, as pcg_solve) whose products with A, G and G^T are
+ *   block products reading each matrix once per iteration for all k columns (Sec. 4.1 keeps
+ *   such blocks with each row's entries contiguous).  A column that has stopped keeps its x.
+ *   B, X (device): n x k row-major, caller-owned, must not alias; X0 = 0 (X is overwritten).
+ *   k: 1, 2, 4 or 8.  P: a single-system preconditioner of A (not a batch, no split layouts).
+ *   info (host, may be NULL): k entries.  Synchronous (the host reads the stop flags after
+ *   every iteration).
+ *   Returns AFSAI_OK, AFSAI_ERR_NOT_CONVERGED (some column reached maxit), AFSAI_ERR_NOT_SPD
+ *   (p.Ap <= 0 in some column), AFSAI_ERR_INVALID_ARG, AFSAI_ERR_NO_MEMORY, AFSAI_ERR_HIP.
+ */
+int pcg_solve_multi(const afsai_csr *A, afsai_precond P, int32_t k, const double *B, double *X, double rtol,
+                    int32_t maxit, void *stream, afsai_pcg_info *info);
+
 /* afsai_get_setup_info -- diagnostics of a handle (host struct). */
 int afsai_get_setup_info(afsai_precond P, afsai_setup_info *info);
 

@@ -31,7 +31,7 @@ STOP_KMAX, STOP_EPS, STOP_NOCAND = 0, 1, 2
 # every symbol the C header declares
 EXPORTS = ("afsai_setup", "afsai_apply", "pcg_solve", "afsai_setup_batched", "pcg_solve_batched",
            "afsai_server_create", "afsai_server_submit", "afsai_server_poll", "afsai_server_pending",
-           "afsai_server_destroy", "afsai_spmv", "afsai_spmm",
+           "afsai_server_destroy", "afsai_spmv", "afsai_spmm", "pcg_solve_multi",
            "afsai_get_setup_info", "afsai_export",
            "afsai_export_rows", "afsai_import", "afsai_destroy", "afsai_last_error", "afsai_set_option",
            "afsai_release_cache",
@@ -105,6 +105,8 @@ def lib():
         L.pcg_solve.argtypes = [P(CsrStruct), vp, vp, vp, ctypes.c_double, i32, vp, P(PcgInfoStruct)]
         L.afsai_spmv.argtypes = [P(CsrStruct), vp, vp, vp]
         L.afsai_spmm.argtypes = [P(CsrStruct), ctypes.c_int32, vp, vp, vp]
+        L.pcg_solve_multi.argtypes = [P(CsrStruct), vp, ctypes.c_int32, vp, vp, ctypes.c_double, i32, vp,
+                                      P(PcgInfoStruct)]
         L.afsai_server_create.argtypes = [P(ServerConfigStruct), P(vp)]
         L.afsai_server_submit.argtypes = [vp, P(CsrStruct), P(ParamsStruct), vp, vp, P(ctypes.c_int64)]
         L.afsai_server_poll.argtypes = [vp, P(RequestResultStruct), i32, P(i32), i32]
@@ -298,6 +300,27 @@ def pcg_solve(A: DeviceCSR, P: Preconditioner | None, b, x=None, rtol: float = 1
     if raise_on_error:
         _check(rc, "pcg_solve", allow=(OK, ERR_NOT_CONVERGED))
     return x, PcgInfo(rc, inf.iters, bool(inf.converged), inf.relres, inf.true_relres, inf.ms)
+
+
+def pcg_solve_multi(A: DeviceCSR, P: Preconditioner | None, B, rtol: float = 1e-8, maxit: int | None = None,
+                    stream=None, raise_on_error: bool = True):
+    """PCG for an (n, k) row-major block B of k = 1, 2, 4 or 8 right-hand sides, X0 = 0
+    (``pcg_solve_multi``).  Returns (X, [PcgInfo per column])."""
+    import torch
+
+    if B.dim() != 2 or B.shape[0] != A.n or not B.is_contiguous() or B.dtype != torch.float64:
+        raise ValueError("pcg_solve_multi: B must be a contiguous float64 (n, k) tensor")
+    k = int(B.shape[1])
+    X = torch.empty_like(B)
+    maxit = A.n if maxit is None else int(maxit)
+    infs = (PcgInfoStruct * max(1, k))()
+    st = A.struct
+    rc = lib().pcg_solve_multi(ctypes.byref(st), None if P is None else P.handle, k, _ptr(B), _ptr(X), float(rtol),
+                               maxit, _stream(stream), infs)
+    if raise_on_error:
+        _check(rc, "pcg_solve_multi", allow=(OK, ERR_NOT_CONVERGED))
+    return X, [PcgInfo(OK if infs[j].converged else rc, infs[j].iters, bool(infs[j].converged), infs[j].relres,
+                       infs[j].true_relres, infs[j].ms) for j in range(k)]
 
 
 def _offsets(offsets):

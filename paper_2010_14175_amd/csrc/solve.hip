@@ -22,6 +22,7 @@
 // see it return at once, so the host enqueues chunks of iterations and reads the flag once
 // per chunk, one chunk behind.
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <vector>
 
@@ -879,14 +880,20 @@ static void sell_fused(const char *name, const Sell &S, const BatchMaps &bm, con
 // SELL-64 slice, one lane per row; every matrix entry is read once for the K vectors and the
 // K values of a gathered row are contiguous.  Each output is the same sequential chain over
 // the row's entries as in the single-vector product.
-template <int K, typename VT>
+template <int K, typename VT, bool DOT = false>
 __global__ __launch_bounds__(kThreads) void k_sell_spmm(int n, int nslices, const uint32_t *__restrict__ sptr,
                                                          const int32_t *__restrict__ perm,
                                                          const int32_t *__restrict__ lens,
                                                          const int32_t *__restrict__ col,
                                                          const VT *__restrict__ val, const double *__restrict__ x,
-                                                         double *__restrict__ y, int nxcd) {
+                                                         double *__restrict__ y, int nxcd,
+                                                         const double *__restrict__ w = nullptr,
+                                                         double *__restrict__ partials = nullptr) {
     constexpr int U = 4;
+    __shared__ double sh[kThreads / 64];
+    double part[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) part[j] = 0.0;
     const int lb = xcd_block(blockIdx.x, gridDim.x, nxcd);
     int s0, s1;
     block_range(0, nslices, lb, gridDim.x, s0, s1);
@@ -928,9 +935,224 @@ __global__ __launch_bounds__(kThreads) void k_sell_spmm(int n, int nslices, cons
         }
         if (valid) {
 #pragma unroll
-            for (int j = 0; j < K; ++j) y[(int64_t)r * K + j] = acc[j];
+            for (int j = 0; j < K; ++j) {
+                y[(int64_t)r * K + j] = acc[j];
+                if (DOT) part[j] = fma(acc[j], w[(int64_t)r * K + j], part[j]);
+            }
         }
     }
+    if (DOT) {
+        // per column j: this block's partial sum at partials[j * gridDim.x + lb]
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            const double bs = block_sum(part[j], sh);
+            if (threadIdx.x == 0) partials[(size_t)j * gridDim.x + lb] = bs;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------------------
+// PCG over a block of K right-hand sides (x0 = 0): K independent recurrences with their own
+// scalars and stopping tests; the vectors are n x K row-major blocks and every product reads
+// its matrix once for the K columns.
+// ---------------------------------------------------------------------------------------
+struct MultiScal {
+    double bb, rho, alpha, beta, rr, tr;
+    int32_t done, iters, status, pad;
+};
+enum : int { MF_BB = 0, MF_RHO0 = 1, MF_PQ = 2, MF_RR = 3, MF_RZ = 4, MF_TRUE = 5 };
+
+// One block per column: the column's partial sums (nb per column) added in block order, then
+// the scalar step of the textbook recurrence for that column.
+__global__ __launch_bounds__(kThreads) void k_fin_multi(const double *__restrict__ partials, int nb, int mode,
+                                                         double rtol, int maxit, MultiScal *sc) {
+    __shared__ double sh[kThreads / 64];
+    const int j = blockIdx.x;
+    const int per = (nb + kThreads - 1) / kThreads;
+    const int lo = threadIdx.x * per, hi = min(nb, lo + per);
+    double v = 0.0;
+    for (int b = lo; b < hi; ++b) v += partials[(size_t)j * nb + b];
+    const double t = block_sum(v, sh);
+    if (threadIdx.x != 0) return;
+    MultiScal &m = sc[j];
+    switch (mode) {
+        case MF_BB:
+            m.bb = t;
+            m.rr = t;
+            m.iters = 0;
+            m.done = 0;
+            m.status = AFSAI_ERR_NOT_CONVERGED;
+            if (t == 0.0 || sqrt(t) <= rtol * sqrt(t)) {
+                m.done = 1;  // b = 0 (x = 0) or converged at x0
+                m.status = AFSAI_OK;
+            } else if (maxit <= 0) {
+                m.done = 1;
+            }
+            break;
+        case MF_RHO0: m.rho = t; break;
+        case MF_PQ:
+            if (!m.done) {
+                if (!(t > 0.0)) {
+                    m.done = 1;
+                    m.status = AFSAI_ERR_NOT_SPD;
+                } else {
+                    m.alpha = m.rho / t;
+                }
+            }
+            break;
+        case MF_RR:
+            if (!m.done) {
+                m.rr = t;
+                m.iters += 1;
+                if (sqrt(t) <= rtol * sqrt(m.bb)) {
+                    m.done = 1;
+                    m.status = AFSAI_OK;
+                } else if (m.iters >= maxit) {
+                    m.done = 1;
+                }
+            }
+            break;
+        case MF_RZ:
+            if (!m.done) {
+                m.beta = t / m.rho;
+                m.rho = t;
+            }
+            break;
+        default: m.tr = t; break;
+    }
+}
+
+// rows [i0, i1) of block b: contiguous ranges in block order, so partial sums are fixed
+template <int K>
+__device__ __forceinline__ void multi_store(double (&part)[K], double *sh, double *partials) {
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        const double bs = block_sum(part[j], sh);
+        if (threadIdx.x == 0) partials[(size_t)j * gridDim.x + blockIdx.x] = bs;
+    }
+}
+
+// x = 0, r = b; partial sums of b.b per column
+template <int K>
+__global__ __launch_bounds__(kThreads) void k_multi_init(int n, const double *__restrict__ b, double *__restrict__ x,
+                                                          double *__restrict__ r, double *__restrict__ partials) {
+    __shared__ double sh[kThreads / 64];
+    int i0, i1;
+    block_range(0, n, blockIdx.x, gridDim.x, i0, i1);
+    double part[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) part[j] = 0.0;
+    for (int i = i0 + threadIdx.x; i < i1; i += kThreads)
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            const double bi = b[(int64_t)i * K + j];
+            x[(int64_t)i * K + j] = 0.0;
+            r[(int64_t)i * K + j] = bi;
+            part[j] = fma(bi, bi, part[j]);
+        }
+    multi_store<K>(part, sh, partials);
+}
+
+// partial sums of a.b per column (and z = a when copy is set)
+template <int K>
+__global__ __launch_bounds__(kThreads) void k_multi_dot(int n, const double *__restrict__ a, const double *__restrict__ b,
+                                                         double *__restrict__ copy, double *__restrict__ partials) {
+    __shared__ double sh[kThreads / 64];
+    int i0, i1;
+    block_range(0, n, blockIdx.x, gridDim.x, i0, i1);
+    double part[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) part[j] = 0.0;
+    for (int i = i0 + threadIdx.x; i < i1; i += kThreads)
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            const double ai = a[(int64_t)i * K + j];
+            if (copy) copy[(int64_t)i * K + j] = ai;
+            part[j] = fma(ai, b[(int64_t)i * K + j], part[j]);
+        }
+    multi_store<K>(part, sh, partials);
+}
+
+// columns still running: x += alpha p, r -= alpha q; partial sums of r.r per column
+template <int K>
+__global__ __launch_bounds__(kThreads) void k_multi_xr(int n, double *__restrict__ x, double *__restrict__ r,
+                                                        const double *__restrict__ p, const double *__restrict__ q,
+                                                        const MultiScal *__restrict__ sc, double *__restrict__ partials) {
+    __shared__ double sh[kThreads / 64];
+    int i0, i1;
+    block_range(0, n, blockIdx.x, gridDim.x, i0, i1);
+    double alpha[K], part[K];
+    bool run[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        run[j] = !sc[j].done;
+        alpha[j] = sc[j].alpha;
+        part[j] = 0.0;
+    }
+    for (int i = i0 + threadIdx.x; i < i1; i += kThreads)
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            const int64_t e = (int64_t)i * K + j;
+            double ri = r[e];
+            if (run[j]) {
+                x[e] = fma(alpha[j], p[e], x[e]);
+                ri = fma(-alpha[j], q[e], ri);
+                r[e] = ri;
+            }
+            part[j] = fma(ri, ri, part[j]);
+        }
+    multi_store<K>(part, sh, partials);
+}
+
+// columns still running: p = z + beta p
+template <int K>
+__global__ __launch_bounds__(kThreads) void k_multi_p(int n, const double *__restrict__ z, double *__restrict__ p,
+                                                       const MultiScal *__restrict__ sc) {
+    int i0, i1;
+    block_range(0, n, blockIdx.x, gridDim.x, i0, i1);
+    double beta[K];
+    bool run[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        run[j] = !sc[j].done;
+        beta[j] = sc[j].beta;
+    }
+    for (int i = i0 + threadIdx.x; i < i1; i += kThreads)
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            const int64_t e = (int64_t)i * K + j;
+            if (run[j]) p[e] = fma(beta[j], p[e], z[e]);
+        }
+}
+
+// partial sums of (b - q).(b - q) per column
+template <int K>
+__global__ __launch_bounds__(kThreads) void k_multi_resid(int n, const double *__restrict__ b,
+                                                           const double *__restrict__ q, double *__restrict__ partials) {
+    __shared__ double sh[kThreads / 64];
+    int i0, i1;
+    block_range(0, n, blockIdx.x, gridDim.x, i0, i1);
+    double part[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) part[j] = 0.0;
+    for (int i = i0 + threadIdx.x; i < i1; i += kThreads)
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            const double d = b[(int64_t)i * K + j] - q[(int64_t)i * K + j];
+            part[j] = fma(d, d, part[j]);
+        }
+    multi_store<K>(part, sh, partials);
+}
+
+template <int K, bool DOT>
+static void spmm_launch(const Sell &S, const double *x, double *y, const double *w, double *partials, int nb,
+                        const DeviceInfo &di, hipStream_t s) {
+    if (S.f32)
+        hipLaunchKernelGGL((k_sell_spmm<K, float, DOT>), dim3(nb), dim3(kThreads), 0, s, S.n, S.nslices, S.sptr, S.perm,
+                           S.lens, S.col, (const float *)S.val, x, y, di.num_xcds, w, partials);
+    else
+        hipLaunchKernelGGL((k_sell_spmm<K, double, DOT>), dim3(nb), dim3(kThreads), 0, s, S.n, S.nslices, S.sptr, S.perm,
+                           S.lens, S.col, (const double *)S.val, x, y, di.num_xcds, w, partials);
 }
 
 static int check_csr_arg(const afsai_csr *A, const char *who) {
@@ -1416,6 +1638,130 @@ int afsai_spmv(const afsai_csr *A, const double *x, double *y, void *stream) {
     return AFSAI_OK;
 }
 
+}  // extern "C"
+
+namespace afsai {
+
+template <int K>
+static int pcg_multi(const afsai_csr *A, afsai_precond P, const double *B, double *X, double rtol, int32_t maxit,
+                     hipStream_t s, const DeviceInfo &di, afsai_pcg_info *info) {
+    const int n = A->n;
+    int rc;
+    Sell SA;
+    {
+        ProfScope ps("sell_A", s);
+        if ((rc = sell_from_csr(n, A->nnz, A->row_ptr, A->col_idx, A->val, false, false, &SA, di, s))) return rc;
+    }
+    struct Free {
+        Sell *S;
+        ~Free() { sell_free(S); }
+    } free_sa{&SA};
+    if (SA.tail) AFSAI_FAIL(AFSAI_ERR_INVALID_ARG, "pcg_solve_multi: split SELL layouts are not supported");
+    const int nbA = blocks_for_slices(SA.nslices, di), nbv = blocks_for_vec(n, di);
+    const int nbG = P ? blocks_for_slices(P->sg.nslices, di) : 0;
+    const int nbGT = P ? blocks_for_slices(P->sgt.nslices, di) : 0;
+    const int nbmax = std::max(std::max(nbA, nbv), std::max(nbG, nbGT));
+    const size_t blk = (size_t)n * K;
+    DevBuf work, parts, scb;
+    if ((rc = dalloc(work, sizeof(double) * blk * 5, s))) return rc;
+    if ((rc = dalloc(parts, sizeof(double) * (size_t)K * nbmax, s))) return rc;
+    if ((rc = dalloc(scb, sizeof(MultiScal) * K, s))) return rc;
+    double *R = work.as<double>(), *Z = R + blk, *Pv = Z + blk, *Q = Pv + blk, *T = Q + blk;
+    double *pa = parts.as<double>();
+    MultiScal *sc = scb.as<MultiScal>();
+    auto fin = [&](int nb, int mode) {
+        hipLaunchKernelGGL(k_fin_multi, dim3(K), dim3(kThreads), 0, s, pa, nb, mode, rtol, (int)maxit, sc);
+    };
+    // Z = M R with partial sums of R.Z; returns the blocks of that launch
+    auto precond = [&]() {
+        if (P) {
+            spmm_launch<K, false>(P->sg, R, T, nullptr, nullptr, nbG, di, s);
+            spmm_launch<K, true>(P->sgt, T, Z, R, pa, nbGT, di, s);
+            return nbGT;
+        }
+        hipLaunchKernelGGL((k_multi_dot<K>), dim3(nbv), dim3(kThreads), 0, s, n, R, R, Z, pa);
+        return nbv;
+    };
+    std::vector<MultiScal> h(K);
+    auto read = [&]() -> int {
+        AFSAI_HIP_TRY(hipGetLastError());
+        AFSAI_HIP_TRY(hipMemcpyAsync(h.data(), sc, sizeof(MultiScal) * K, hipMemcpyDeviceToHost, s));
+        AFSAI_HIP_TRY(hipStreamSynchronize(s));
+        return AFSAI_OK;
+    };
+    auto all_done = [&]() {
+        for (int j = 0; j < K; ++j)
+            if (!h[j].done) return false;
+        return true;
+    };
+    hipLaunchKernelGGL((k_multi_init<K>), dim3(nbv), dim3(kThreads), 0, s, n, B, X, R, pa);
+    fin(nbv, MF_BB);
+    fin(precond(), MF_RHO0);
+    AFSAI_HIP_TRY(hipMemcpyAsync(Pv, Z, sizeof(double) * blk, hipMemcpyDeviceToDevice, s));
+    if ((rc = read())) return rc;
+    for (int it = 0; it < maxit && !all_done(); ++it) {
+        spmm_launch<K, true>(SA, Pv, Q, Pv, pa, nbA, di, s);
+        fin(nbA, MF_PQ);
+        hipLaunchKernelGGL((k_multi_xr<K>), dim3(nbv), dim3(kThreads), 0, s, n, X, R, Pv, Q, sc, pa);
+        fin(nbv, MF_RR);
+        if ((rc = read())) return rc;
+        if (all_done()) break;
+        fin(precond(), MF_RZ);
+        hipLaunchKernelGGL((k_multi_p<K>), dim3(nbv), dim3(kThreads), 0, s, n, Z, Pv, sc);
+    }
+    // true residuals ||b - A x|| per column
+    spmm_launch<K, false>(SA, X, Q, nullptr, nullptr, nbA, di, s);
+    hipLaunchKernelGGL((k_multi_resid<K>), dim3(nbv), dim3(kThreads), 0, s, n, B, Q, pa);
+    fin(nbv, MF_TRUE);
+    if ((rc = read())) return rc;
+    int worst = AFSAI_OK;
+    for (int j = 0; j < K; ++j) {
+        const MultiScal &m = h[j];
+        if (info) {
+            info[j].iters = m.iters;
+            info[j].converged = m.status == AFSAI_OK ? 1 : 0;
+            info[j].relres = m.bb > 0.0 ? std::sqrt(m.rr / m.bb) : 0.0;
+            info[j].true_relres = m.bb > 0.0 ? std::sqrt(m.tr / m.bb) : 0.0;
+        }
+        if (m.status == AFSAI_ERR_NOT_SPD) worst = AFSAI_ERR_NOT_SPD;
+        else if (m.status != AFSAI_OK && worst == AFSAI_OK) worst = m.status;
+    }
+    if (worst == AFSAI_ERR_NOT_SPD) set_error("pcg_solve_multi: p.Ap <= 0 in a column (A not SPD)");
+    else if (worst != AFSAI_OK) set_error("pcg_solve_multi: a column did not converge");
+    return worst;
+}
+
+}  // namespace afsai
+
+extern "C" {
+
+int pcg_solve_multi(const afsai_csr *A, afsai_precond P, int32_t k, const double *B, double *X, double rtol,
+                    int32_t maxit, void *stream, afsai_pcg_info *info) {
+    if (k != 1 && k != 2 && k != 4 && k != 8)
+        AFSAI_FAIL(AFSAI_ERR_INVALID_ARG, "pcg_solve_multi: k = %d (1, 2, 4 or 8)", k);
+    int rc = check_csr_arg(A, "pcg_solve_multi");
+    if (rc) return rc;
+    if (!B || !X || B == X) AFSAI_FAIL(AFSAI_ERR_INVALID_ARG, "pcg_solve_multi: null or aliased blocks");
+    if (!(rtol > 0.0) || maxit < 0) AFSAI_FAIL(AFSAI_ERR_INVALID_ARG, "pcg_solve_multi: rtol = %g, maxit = %d", rtol, maxit);
+    if (P && (P->n != A->n || !P->seg_row0.empty() || P->sg.tail || P->sgt.tail))
+        AFSAI_FAIL(AFSAI_ERR_INVALID_ARG,
+                   "pcg_solve_multi: the preconditioner must be a single system of A's size without split layouts");
+    DeviceInfo di;
+    if ((rc = device_info(&di))) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    const auto t0 = std::chrono::steady_clock::now();
+    switch (k) {
+        case 1: rc = pcg_multi<1>(A, P, B, X, rtol, maxit, s, di, info); break;
+        case 2: rc = pcg_multi<2>(A, P, B, X, rtol, maxit, s, di, info); break;
+        case 4: rc = pcg_multi<4>(A, P, B, X, rtol, maxit, s, di, info); break;
+        default: rc = pcg_multi<8>(A, P, B, X, rtol, maxit, s, di, info); break;
+    }
+    const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    if (info)
+        for (int j = 0; j < k; ++j) info[j].ms = ms;
+    return rc;
+}
+
 int afsai_spmm(const afsai_csr *A, int32_t k, const double *X, double *Y, void *stream) {
     if (k != 1 && k != 2 && k != 4 && k != 8) AFSAI_FAIL(AFSAI_ERR_INVALID_ARG, "afsai_spmm: k = %d (1, 2, 4 or 8)", k);
     int rc = check_csr_arg(A, "afsai_spmm");
@@ -1440,13 +1786,17 @@ int afsai_spmm(const afsai_csr *A, int32_t k, const double *X, double *Y, void *
         const double *vx = X;
         switch (k) {
             case 1: hipLaunchKernelGGL((k_sell_spmm<1, double>), dim3(nb), dim3(kThreads), 0, s, S.n, S.nslices, S.sptr,
-                                       S.perm, S.lens, S.col, (const double *)S.val, vx, Y, di.num_xcds); break;
+                                       S.perm, S.lens, S.col, (const double *)S.val, vx, Y, di.num_xcds, nullptr,
+                                       nullptr); break;
             case 2: hipLaunchKernelGGL((k_sell_spmm<2, double>), dim3(nb), dim3(kThreads), 0, s, S.n, S.nslices, S.sptr,
-                                       S.perm, S.lens, S.col, (const double *)S.val, vx, Y, di.num_xcds); break;
+                                       S.perm, S.lens, S.col, (const double *)S.val, vx, Y, di.num_xcds, nullptr,
+                                       nullptr); break;
             case 4: hipLaunchKernelGGL((k_sell_spmm<4, double>), dim3(nb), dim3(kThreads), 0, s, S.n, S.nslices, S.sptr,
-                                       S.perm, S.lens, S.col, (const double *)S.val, vx, Y, di.num_xcds); break;
+                                       S.perm, S.lens, S.col, (const double *)S.val, vx, Y, di.num_xcds, nullptr,
+                                       nullptr); break;
             default: hipLaunchKernelGGL((k_sell_spmm<8, double>), dim3(nb), dim3(kThreads), 0, s, S.n, S.nslices, S.sptr,
-                                        S.perm, S.lens, S.col, (const double *)S.val, vx, Y, di.num_xcds); break;
+                                        S.perm, S.lens, S.col, (const double *)S.val, vx, Y, di.num_xcds, nullptr,
+                                       nullptr); break;
         }
     }
     const hipError_t le = hipGetLastError();

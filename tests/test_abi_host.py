@@ -87,6 +87,8 @@ def test_invalid_arguments_rejected_on_host(L):
     assert L.afsai_export(None, None, None, None, None) == af.ERR_INVALID_ARG
     assert L.afsai_spmm(None, 3, None, None, None) == af.ERR_INVALID_ARG
     assert L.afsai_spmm(None, 4, None, None, None) == af.ERR_INVALID_ARG
+    assert L.pcg_solve_multi(None, None, 3, None, None, 1e-8, 10, None, None) == af.ERR_INVALID_ARG
+    assert L.pcg_solve_multi(None, None, 2, None, None, 1e-8, 10, None, None) == af.ERR_INVALID_ARG
     assert L.afsai_import(None, 0, None, ctypes.byref(h)) == af.ERR_INVALID_ARG
     assert b"null" in L.afsai_last_error() or len(L.afsai_last_error()) > 0
     L.afsai_destroy(None)

@@ -555,6 +555,52 @@ def test_spmm_against_oracle(af, make):
         af.spmm(dA, torch.zeros((A.n, 3), dtype=torch.float64, device="cuda"))
 
 
+@pytest.mark.parametrize("precond", [True, False])
+@pytest.mark.parametrize("make", [lambda: synth.elasticity27(8), lambda: synth.random_sparse_spd(3000, 40, 3)])
+def test_pcg_multi_against_oracle(af, make, precond):
+    """PCG over blocks of 2, 4 and 8 right-hand sides (one column zero, one a multiple of
+    another): each column's iteration count within one of the oracle's PCG on that column
+    alone, its true residual below the stopping bound, A (x - x_oracle) within the sum of the
+    two residuals (x within the oracle tolerance when preconditioned; plain CG amplifies the
+    rounding of the dots), the zero column x = 0 after 0 iterations; a block of one column
+    gives the iterates of the same column inside a block of eight, bit for bit."""
+    import torch
+
+    Pb = make()
+    A = Pb.A if hasattr(Pb, "A") else Pb
+    dA = _dev(af, A)
+    P = af.setup(dA, 6, 2, 1e-2) if precond else None
+    G = oracle.setup(A, 6, 2, 1e-2) if precond else None
+    Xt = synth.uniform(17, 3, A.n * 8, -1.0, 1.0).reshape(A.n, 8)
+    B8 = np.ascontiguousarray(np.column_stack([A.to_scipy() @ Xt[:, j] for j in range(8)]))
+    B8[:, 3] = 0.0
+    B8[:, 5] = 4.0 * B8[:, 1]
+    for k in (2, 4, 8):
+        X, infos = af.pcg_solve_multi(dA, P, torch.from_numpy(np.ascontiguousarray(B8[:, :k])).cuda(),
+                                      rtol=1e-8, maxit=3000)
+        X = X.cpu().numpy()
+        for j in range(k):
+            if j == 3:
+                assert infos[j].iters == 0 and infos[j].converged and not X[:, j].any()
+                continue
+            ro = oracle.pcg(A, G, B8[:, j], 1e-8, maxit=3000)
+            assert infos[j].converged and abs(infos[j].iters - ro.iters) <= 1, (k, j, infos[j].iters, ro.iters)
+            # both stop at ||b - A x|| <= 1e-8 ||b||, so ||A (x - x_o)|| is bounded by the sum of
+            # the two true residuals (each measured with the oracle's product)
+            nb = np.linalg.norm(B8[:, j])
+            r_gpu = np.linalg.norm(B8[:, j] - oracle.spmv(A, X[:, j]))
+            r_o = np.linalg.norm(B8[:, j] - oracle.spmv(A, ro.x))
+            assert r_gpu <= 1.01e-8 * nb and abs(infos[j].true_relres - r_gpu / nb) <= 1e-12, (k, j)
+            assert np.linalg.norm(oracle.spmv(A, X[:, j] - ro.x)) <= (r_gpu + r_o) * (1 + 1e-6), (k, j)
+            if precond:
+                assert np.linalg.norm(X[:, j] - ro.x) <= 10 * X_RTOL * np.linalg.norm(ro.x), (k, j)
+        if k == 8:
+            X1, i1 = af.pcg_solve_multi(dA, P, torch.from_numpy(np.ascontiguousarray(B8[:, 6:7])).cuda(),
+                                        rtol=1e-8, maxit=3000)
+            assert i1[0].iters == infos[6].iters
+            assert np.array_equal(X1.cpu().numpy()[:, 0].view(np.int64), X[:, 6].view(np.int64))
+
+
 def test_pcg_deterministic(af):
     Pb = synth.elasticity27(12)
     dA = _dev(af, Pb.A)
