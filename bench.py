@@ -288,6 +288,43 @@ def spmm_bench(args):
                         "bytes": byt}
         print(f"[bench] spmm k={k}: {t:.1f} us ({t / k:.1f} us per right-hand side, "
               f"{res[f'k{k}']['gbs']} GB/s algorithmic)", file=sys.stderr, flush=True)
+    # PCG over blocks (one setup reused): wall time of the solve per right-hand side, against
+    # pcg_solve of one right-hand side
+    P = af.setup(dA, pb.kmax, pb.s, pb.eps)
+    Bt = torch.from_numpy(np.ascontiguousarray(
+        np.column_stack([pb.A.to_scipy() @ synth.uniform(17, 3 + j, n, -1.0, 1.0) for j in range(8)]))).cuda()
+    solves = {}
+    b0 = Bt[:, 0].contiguous()
+    for _ in range(args.warmup):
+        af.pcg_solve(dA, P, b0, rtol=pb.rtol)
+    ms = []
+    for _ in range(args.steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, inf1 = af.pcg_solve(dA, P, b0, rtol=pb.rtol)
+        torch.cuda.synchronize()
+        ms.append((time.perf_counter() - t0) * 1e3)
+    solves["pcg_solve"] = {"ms": round(float(np.median(ms)), 3), "iters": inf1.iters}
+    for k in (1, 8):
+        B = Bt[:, :k].contiguous()
+        for _ in range(args.warmup):
+            af.pcg_solve_multi(dA, P, B, rtol=pb.rtol)
+        ms = []
+        for _ in range(args.steps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, infs = af.pcg_solve_multi(dA, P, B, rtol=pb.rtol)
+            torch.cuda.synchronize()
+            ms.append((time.perf_counter() - t0) * 1e3)
+        t = float(np.median(ms))
+        solves[f"multi_k{k}"] = {"ms": round(t, 3), "ms_per_rhs": round(t / k, 3),
+                                 "iters": [i.iters for i in infs], "worst_true_relres": max(i.true_relres for i in infs)}
+        print(f"[bench] pcg_solve_multi k={k}: {t:.2f} ms ({t / k:.2f} ms per right-hand side, iterations "
+              f"{[i.iters for i in infs]})", file=sys.stderr, flush=True)
+    print(f"[bench] pcg_solve: {solves['pcg_solve']['ms']:.2f} ms ({inf1.iters} iterations)", file=sys.stderr,
+          flush=True)
+    P.close()
+    res["pcg"] = solves
     out = {"metric": "SpMM time per right-hand side, k = 8 against k = 1", "value":
            round(res["k8"]["us_per_rhs"] / res["k1"]["us"], 4), "unit": "ratio", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "higher_is_better": False, "vs_baseline": None, "dtype": "f64",
