@@ -1022,13 +1022,32 @@ __global__ __launch_bounds__(kThreads) void k_fin_multi(const double *__restrict
     }
 }
 
-// rows [i0, i1) of block b: contiguous ranges in block order, so partial sums are fixed
+// The vector kernels take one thread per entry of the n x K block: block b covers the
+// entries of rows [i0, i1) (contiguous, in block order) and, since kThreads is a multiple of
+// K, thread t always meets column t % K, so every thread sums one column in a fixed order.
 template <int K>
-__device__ __forceinline__ void multi_store(double (&part)[K], double *sh, double *partials) {
+__device__ __forceinline__ void multi_range(int n, int64_t &e0, int64_t &e1) {
+    int i0, i1;
+    block_range(0, n, blockIdx.x, gridDim.x, i0, i1);
+    e0 = (int64_t)i0 * K;
+    e1 = (int64_t)i1 * K;
+}
+
+// this block's per-column sums of part (thread t holding column t % K) at
+// partials[j * gridDim.x + block]: lanes of one column added by shuffles, then the
+// wavefronts in order
+template <int K>
+__device__ __forceinline__ void multi_store(double part, double *sh /* kThreads / 64 * K */, double *partials) {
+    static_assert(kThreads % K == 0 && 64 % K == 0, "a thread keeps one column");
 #pragma unroll
-    for (int j = 0; j < K; ++j) {
-        const double bs = block_sum(part[j], sh);
-        if (threadIdx.x == 0) partials[(size_t)j * gridDim.x + blockIdx.x] = bs;
+    for (int off = 32; off >= K; off >>= 1) part += __shfl_xor(part, off, 64);
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (lane < K) sh[w * K + lane] = part;
+    __syncthreads();
+    if (threadIdx.x < K) {
+        double t = 0.0;
+        for (int k = 0; k < kThreads / 64; ++k) t += sh[k * K + threadIdx.x];
+        partials[(size_t)threadIdx.x * gridDim.x + blockIdx.x] = t;
     }
 }
 
@@ -1036,40 +1055,32 @@ __device__ __forceinline__ void multi_store(double (&part)[K], double *sh, doubl
 template <int K>
 __global__ __launch_bounds__(kThreads) void k_multi_init(int n, const double *__restrict__ b, double *__restrict__ x,
                                                           double *__restrict__ r, double *__restrict__ partials) {
-    __shared__ double sh[kThreads / 64];
-    int i0, i1;
-    block_range(0, n, blockIdx.x, gridDim.x, i0, i1);
-    double part[K];
-#pragma unroll
-    for (int j = 0; j < K; ++j) part[j] = 0.0;
-    for (int i = i0 + threadIdx.x; i < i1; i += kThreads)
-#pragma unroll
-        for (int j = 0; j < K; ++j) {
-            const double bi = b[(int64_t)i * K + j];
-            x[(int64_t)i * K + j] = 0.0;
-            r[(int64_t)i * K + j] = bi;
-            part[j] = fma(bi, bi, part[j]);
-        }
+    __shared__ double sh[kThreads / 64 * K];
+    int64_t e0, e1;
+    multi_range<K>(n, e0, e1);
+    double part = 0.0;
+    for (int64_t e = e0 + threadIdx.x; e < e1; e += kThreads) {
+        const double be = b[e];
+        x[e] = 0.0;
+        r[e] = be;
+        part = fma(be, be, part);
+    }
     multi_store<K>(part, sh, partials);
 }
 
-// partial sums of a.b per column (and z = a when copy is set)
+// partial sums of a.b per column (and copy = a when given)
 template <int K>
 __global__ __launch_bounds__(kThreads) void k_multi_dot(int n, const double *__restrict__ a, const double *__restrict__ b,
                                                          double *__restrict__ copy, double *__restrict__ partials) {
-    __shared__ double sh[kThreads / 64];
-    int i0, i1;
-    block_range(0, n, blockIdx.x, gridDim.x, i0, i1);
-    double part[K];
-#pragma unroll
-    for (int j = 0; j < K; ++j) part[j] = 0.0;
-    for (int i = i0 + threadIdx.x; i < i1; i += kThreads)
-#pragma unroll
-        for (int j = 0; j < K; ++j) {
-            const double ai = a[(int64_t)i * K + j];
-            if (copy) copy[(int64_t)i * K + j] = ai;
-            part[j] = fma(ai, b[(int64_t)i * K + j], part[j]);
-        }
+    __shared__ double sh[kThreads / 64 * K];
+    int64_t e0, e1;
+    multi_range<K>(n, e0, e1);
+    double part = 0.0;
+    for (int64_t e = e0 + threadIdx.x; e < e1; e += kThreads) {
+        const double ae = a[e];
+        if (copy) copy[e] = ae;
+        part = fma(ae, b[e], part);
+    }
     multi_store<K>(part, sh, partials);
 }
 
@@ -1078,29 +1089,22 @@ template <int K>
 __global__ __launch_bounds__(kThreads) void k_multi_xr(int n, double *__restrict__ x, double *__restrict__ r,
                                                         const double *__restrict__ p, const double *__restrict__ q,
                                                         const MultiScal *__restrict__ sc, double *__restrict__ partials) {
-    __shared__ double sh[kThreads / 64];
-    int i0, i1;
-    block_range(0, n, blockIdx.x, gridDim.x, i0, i1);
-    double alpha[K], part[K];
-    bool run[K];
-#pragma unroll
-    for (int j = 0; j < K; ++j) {
-        run[j] = !sc[j].done;
-        alpha[j] = sc[j].alpha;
-        part[j] = 0.0;
-    }
-    for (int i = i0 + threadIdx.x; i < i1; i += kThreads)
-#pragma unroll
-        for (int j = 0; j < K; ++j) {
-            const int64_t e = (int64_t)i * K + j;
-            double ri = r[e];
-            if (run[j]) {
-                x[e] = fma(alpha[j], p[e], x[e]);
-                ri = fma(-alpha[j], q[e], ri);
-                r[e] = ri;
-            }
-            part[j] = fma(ri, ri, part[j]);
+    __shared__ double sh[kThreads / 64 * K];
+    int64_t e0, e1;
+    multi_range<K>(n, e0, e1);
+    const int j = threadIdx.x % K;
+    const bool run = !sc[j].done;
+    const double alpha = sc[j].alpha;
+    double part = 0.0;
+    for (int64_t e = e0 + threadIdx.x; e < e1; e += kThreads) {
+        double re = r[e];
+        if (run) {
+            x[e] = fma(alpha, p[e], x[e]);
+            re = fma(-alpha, q[e], re);
+            r[e] = re;
         }
+        part = fma(re, re, part);
+    }
     multi_store<K>(part, sh, partials);
 }
 
@@ -1108,39 +1112,26 @@ __global__ __launch_bounds__(kThreads) void k_multi_xr(int n, double *__restrict
 template <int K>
 __global__ __launch_bounds__(kThreads) void k_multi_p(int n, const double *__restrict__ z, double *__restrict__ p,
                                                        const MultiScal *__restrict__ sc) {
-    int i0, i1;
-    block_range(0, n, blockIdx.x, gridDim.x, i0, i1);
-    double beta[K];
-    bool run[K];
-#pragma unroll
-    for (int j = 0; j < K; ++j) {
-        run[j] = !sc[j].done;
-        beta[j] = sc[j].beta;
-    }
-    for (int i = i0 + threadIdx.x; i < i1; i += kThreads)
-#pragma unroll
-        for (int j = 0; j < K; ++j) {
-            const int64_t e = (int64_t)i * K + j;
-            if (run[j]) p[e] = fma(beta[j], p[e], z[e]);
-        }
+    int64_t e0, e1;
+    multi_range<K>(n, e0, e1);
+    const int j = threadIdx.x % K;
+    if (sc[j].done) return;
+    const double beta = sc[j].beta;
+    for (int64_t e = e0 + threadIdx.x; e < e1; e += kThreads) p[e] = fma(beta, p[e], z[e]);
 }
 
 // partial sums of (b - q).(b - q) per column
 template <int K>
 __global__ __launch_bounds__(kThreads) void k_multi_resid(int n, const double *__restrict__ b,
                                                            const double *__restrict__ q, double *__restrict__ partials) {
-    __shared__ double sh[kThreads / 64];
-    int i0, i1;
-    block_range(0, n, blockIdx.x, gridDim.x, i0, i1);
-    double part[K];
-#pragma unroll
-    for (int j = 0; j < K; ++j) part[j] = 0.0;
-    for (int i = i0 + threadIdx.x; i < i1; i += kThreads)
-#pragma unroll
-        for (int j = 0; j < K; ++j) {
-            const double d = b[(int64_t)i * K + j] - q[(int64_t)i * K + j];
-            part[j] = fma(d, d, part[j]);
-        }
+    __shared__ double sh[kThreads / 64 * K];
+    int64_t e0, e1;
+    multi_range<K>(n, e0, e1);
+    double part = 0.0;
+    for (int64_t e = e0 + threadIdx.x; e < e1; e += kThreads) {
+        const double d = b[e] - q[e];
+        part = fma(d, d, part);
+    }
     multi_store<K>(part, sh, partials);
 }
 
