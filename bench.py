@@ -3,15 +3,18 @@
 
 One step = one adaptive FSAI setup of G plus one PCG solve of A x = b to rtol 1e-8 (x0 = 0) on
 a synthetic workload already resident in HBM; the handle is destroyed after each step.
-Default workload: 27-point 3-dof heterogeneous SPD operator on 64^3 nodes (786,432 unknowns,
-61,731,000 nonzeros, log-normal sigma = 1 cell coefficients), k_max = 10, s = 2, eps = 1e-2.
+Default workload: the largest single-GPU configuration, a 27-point 3-dof heterogeneous SPD
+operator on 150^3 nodes (10,125,000 unknowns, 809,238,528 nonzeros, log-normal sigma = 2 cell
+coefficients), k_max = 15, s = 3, eps = 1e-2, G stored in FP32 with the per-row Cholesky and
+the PCG in FP64.  The line also carries the 64^3 workload (786,432 unknowns, sigma = 1,
+k_max = 10, s = 2, FP64) under ``context``.
 
 Prints ONE JSON line.  ``value`` is the wall time of one solve (seconds, lower is better).
 ``roofline`` covers the kernel with the largest total event-measured time in one untimed
 profiled step; inside the timed region only that kernel is bracketed by HIP events (on its
 launch stream), and its average launch duration there gives ``achieved``.  ``kernels`` is the
 per-kernel breakdown of the profiled step.  ``cpu_baseline`` times the FP64 CPU oracle on the
-same workload (host cores).
+same workload (host cores): whole for up to 2M rows, on a stated sample above.
 """
 from __future__ import annotations
 
@@ -363,12 +366,13 @@ def kernel_bytes(name: str, n: int, nnz_a: int, nnz_g: int, w_g: int, kmax: int,
 
 
 def cpu_baseline(pb, iters_hint: int, threads: int, x_gpu=None) -> dict:
+    """The FP64 oracle on the whole workload: its setup of every row, then its PCG to rtol."""
     import oracle
 
+    oracle.set_threads(threads)
     t0 = time.perf_counter()
     G = oracle.setup(pb.A, pb.kmax, pb.s, pb.eps, nthreads=threads)
     t1 = time.perf_counter()
-    os.environ["OMP_NUM_THREADS"] = str(threads)
     res = oracle.pcg(pb.A, G, pb.b, pb.rtol)
     t2 = time.perf_counter()
     return {"value": round(t2 - t0, 3), "unit": "s", "cores": threads, "kind": "oracle",
@@ -378,6 +382,58 @@ def cpu_baseline(pb, iters_hint: int, threads: int, x_gpu=None) -> dict:
             "setup_s": round(t1 - t0, 3), "pcg_s": round(t2 - t1, 3), "iters": res.iters,
             "gpu_x_rel_err_vs_oracle": (float(np.linalg.norm(x_gpu - res.x) / np.linalg.norm(res.x))
                                         if x_gpu is not None else None)}
+
+
+def leading_block(A, ns: int):
+    """The leading principal ns x ns block of a CSR matrix (rows and columns below ns).  Rows of
+    G depend only on A's entries of lower index, so its setup gives rows 0..ns-1 of G exactly."""
+    import synth
+
+    e = int(A.row_ptr[ns])
+    col = A.col[:e]
+    keep = col < ns
+    rows = np.repeat(np.arange(ns, dtype=np.int64), np.diff(A.row_ptr[:ns + 1]))[keep]
+    rp = np.zeros(ns + 1, np.int64)
+    np.add.at(rp, rows + 1, 1)
+    return synth.CSR(np.cumsum(rp).astype(np.int32), col[keep].astype(np.int32), A.val[:e][keep].astype(np.float64))
+
+
+def cpu_baseline_sampled(pb, iters_gpu: int, nnz_g_gpu: int, threads: int, setup_stride: int = 64,
+                         slab_div: int = 64, pcg_iters: int = 10) -> dict:
+    """The FP64 oracle on a bounded sample of a workload too large to run whole (the oracle's
+    setup of all 10.1M rows of the 150^3 problem alone takes minutes on the host):
+
+    * setup: every ``setup_stride``-th row (rows are independent), timed, scaled by the number
+      of rows;
+    * PCG: ``pcg_iters`` oracle iterations on the leading principal block of n / slab_div rows
+      with the oracle's G of that block (its rows are the first rows of the full G), the time
+      per iteration scaled by the ratio of the whole problem's matrix entries (A, G and G^T) to
+      the block's, times the GPU's iteration count."""
+    import oracle
+
+    oracle.set_threads(threads)
+    n = pb.n
+    rows = np.arange(0, n, setup_stride, dtype=np.int32)
+    t0 = time.perf_counter()
+    oracle.setup_rows(pb.A, pb.kmax, pb.s, pb.eps, rows=rows, nthreads=threads)
+    t_rows = time.perf_counter() - t0
+    setup_s = t_rows * n / len(rows)
+    ns = n // slab_div
+    As = leading_block(pb.A, ns)
+    Gs = oracle.setup(As, pb.kmax, pb.s, pb.eps, nthreads=threads)
+    bs = oracle.spmv(As, pb.x_true[:ns])
+    t1 = time.perf_counter()
+    r = oracle.pcg(As, Gs, bs, 1e-30, maxit=pcg_iters)
+    t_it = (time.perf_counter() - t1) / max(1, r.iters)
+    scale = (pb.A.nnz + 2.0 * nnz_g_gpu) / (As.nnz + 2.0 * Gs.nnz)
+    pcg_s = t_it * scale * iters_gpu
+    return {"value": round(setup_s + pcg_s, 3), "unit": "s", "cores": threads, "kind": "oracle",
+            "sample": (f"oracle setup of every {setup_stride}th row ({len(rows)} of {n} rows, {t_rows:.2f} s, "
+                       f"scaled by rows) + {r.iters} oracle PCG iterations on the leading {ns}-row principal block "
+                       f"({t_it * 1e3:.1f} ms each, scaled by matrix entries x{scale:.1f} to the whole problem, times "
+                       f"the GPU's {iters_gpu} iterations); {threads} threads"),
+            "setup_s": round(setup_s, 3), "pcg_s": round(pcg_s, 3), "iters": iters_gpu,
+            "sample_setup_s": round(t_rows, 3), "sample_pcg_s_per_iter": round(t_it, 5)}
 
 
 COPY_BYTES = 1 << 30
@@ -441,12 +497,184 @@ def measured_traffic(kernel: str, workload: str):
 PEAK_VALU_GINST = 256 * 4 * 2.4 / 4
 
 
+# G storage each workload is specified with (the 150^3 one: FP32 G with FP64 Cholesky + PCG)
+WORKLOAD_G_PREC = {"elast27_150": "f32"}
+# above this many rows the oracle is timed on a sample instead of the whole workload
+CPU_WHOLE_MAX_ROWS = 2_000_000
+
+
+def run_workload(af, pb, g_prec, args, steps: int, warmup: int, profile: bool, with_cpu: bool,
+                 workload_name: str) -> dict:
+    """One workload: ``warmup`` untimed steps, one untimed profiled step (per-kernel breakdown,
+    dominant kernel), then ``steps`` timed steps with events only around the dominant kernel.
+    Returns the fields of the JSON line (without the common header)."""
+    import torch
+
+    dA = af.DeviceCSR.from_host(pb.A)
+    b = torch.from_numpy(pb.b).cuda()
+    x = torch.zeros_like(b)
+
+    def step():
+        P = af.setup(dA, pb.kmax, pb.s, pb.eps, g_prec=g_prec, setup_f32=args.setup_f32)
+        x.zero_()
+        _, info = af.pcg_solve(dA, P, b, x=x, rtol=pb.rtol)
+        sinfo = P.info()
+        P.close()
+        return sinfo, info
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+
+    kern_all = {}
+    dom = None
+    if profile:
+        # one untimed step with every kernel timed: the per-kernel breakdown and the dominant
+        # kernel; inside the timed region only the dominant kernel carries events
+        af.profile_only(None)
+        af.profile_read(reset=True)
+        af.profile_enable(True)
+        step()
+        torch.cuda.synchronize()
+        af.profile_enable(False)
+        kern_all = af.profile_read(reset=True)
+        dom = max(kern_all.items(), key=lambda kv: kv[1][1])[0]
+        af.profile_only([dom])
+        af.profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    setup_ms, pcg_ms, its = [], [], []
+    for k in range(steps):
+        sinfo, info = step()
+        setup_ms.append(sinfo.ms)
+        pcg_ms.append(info.ms)
+        its.append(info.iters)
+        print(f"[bench] {workload_name} step {k + 1}/{steps}: setup {sinfo.ms:.1f} ms, pcg {info.ms:.1f} ms, "
+              f"{info.iters} iterations", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    kern = {}
+    if profile:
+        af.profile_enable(False)
+        kern = af.profile_read(reset=True)
+        af.profile_only(None)
+    sec = (t1 - t0) / steps
+    print(f"[bench] {workload_name}: {steps} steps: {sec * 1e3:.2f} ms/step (setup {np.mean(setup_ms):.2f} ms, "
+          f"pcg {np.mean(pcg_ms):.2f} ms, {its[-1]} iterations, true relres {info.true_relres:.2e})",
+          file=sys.stderr, flush=True)
+
+    w_g = 4 if g_prec == af.F32 else 8
+    roof = None
+    issue_roof = None
+    kern_report = {}
+    for name, (launches, ms) in kern_all.items():
+        byt = kernel_bytes(name, pb.n, pb.A.nnz, sinfo.nnz_g, w_g, pb.kmax, sinfo.mmax)
+        avg_ms = ms / max(1, launches)
+        kern_report[name] = {"launches": launches, "total_ms": round(ms, 3), "avg_us": round(avg_ms * 1e3, 2),
+                             "gbs": round(byt / (avg_ms * 1e-3) / 1e9, 1) if avg_ms > 0 and byt == byt else None}
+    if kern and dom in kern:
+        launches, ms = kern[dom]
+        avg_s = ms / launches * 1e-3
+        byt = kernel_bytes(dom, pb.n, pb.A.nnz, sinfo.nnz_g, w_g, pb.kmax, sinfo.mmax)
+        ach = byt / avg_s / 1e9
+        roof = {"kernel": dom, "bound": "hbm", "achieved": round(ach, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": round(ach / PEAK_HBM_GBS, 4), "traffic": measured_traffic(dom, workload_name),
+                "bytes_per_launch": byt, "avg_launch_us": round(avg_s * 1e6, 2)}
+        # the same launch against the VALU issue rate, from the committed instruction count
+        vi = measured_value(dom, workload_name, "sq_counters", "valu_insts_per_launch")
+        if vi:
+            g = vi / avg_s / 1e9
+            issue_roof = {"kernel": dom, "bound": "valu_issue", "achieved": round(g, 1), "peak": PEAK_VALU_GINST,
+                          "unit": "Ginst/s", "frac": round(g / PEAK_VALU_GINST, 4), "valu_insts_per_launch": vi}
+
+    # whole-PCG achieved bandwidth from the per-iteration algorithmic bytes
+    it_bytes = (kernel_bytes("spmv_A_dot", pb.n, pb.A.nnz, sinfo.nnz_g, w_g, pb.kmax, sinfo.mmax)
+                + kernel_bytes("update_xr", pb.n, 0, 0, w_g, 0, 0)
+                + kernel_bytes("spmv_G", pb.n, 0, sinfo.nnz_g, w_g, 0, 0)
+                + kernel_bytes("spmv_GT_dot", pb.n, 0, sinfo.nnz_g, w_g, 0, 0)
+                + kernel_bytes("update_p", pb.n, 0, 0, w_g, 0, 0))
+    pcg_gbs = it_bytes * its[-1] / (np.mean(pcg_ms) * 1e-3) / 1e9
+
+    cpu = None
+    if with_cpu:
+        threads = args.cpu_threads or int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or (os.cpu_count() or 1)
+        print(f"[bench] cpu baseline: oracle on {threads} threads ...", file=sys.stderr, flush=True)
+        if pb.n <= CPU_WHOLE_MAX_ROWS:
+            cpu = cpu_baseline(pb, its[-1], threads, x.cpu().numpy())
+        else:
+            cpu = cpu_baseline_sampled(pb, its[-1], sinfo.nnz_g, threads)
+        print(f"[bench] cpu baseline: {cpu['value']} s ({cpu['sample']})", file=sys.stderr, flush=True)
+
+    f32_eval = None
+    if args.setup_f32:
+        f32_eval = setup_f32_eval(af, pb, dA, b, x, its[-1])
+
+    out = {
+        "value": round(sec, 6),
+        "ms_per_step": round(sec * 1e3, 3),
+        "dtype": ("f32 setup, " if args.setup_f32 else "") + ("f64" if g_prec == af.F64 else "f64 (G stored f32)"),
+        "config": {"workload": workload_name, "n": pb.n, "nnz": pb.A.nnz, "kmax": pb.kmax, "s": pb.s,
+                   "eps": pb.eps, "rtol": pb.rtol, "g_prec": "f32" if g_prec == af.F32 else "f64",
+                   "setup_prec": "f32" if args.setup_f32 else "f64", "nnz_g": sinfo.nnz_g},
+        "setup_ms": round(float(np.mean(setup_ms)), 3),
+        "pcg_ms": round(float(np.mean(pcg_ms)), 3),
+        "iters": its[-1],
+        "true_relres": info.true_relres,
+        "pcg_hbm_gbs": round(pcg_gbs, 1),
+        "roofline": roof,
+        "issue_roofline": issue_roof,
+        "kernels": kern_report,
+        "cpu_baseline": cpu,
+    }
+    if f32_eval:
+        out["setup_f32_eval"] = f32_eval
+    return out
+
+
+def setup_f32_eval(af, pb, dA, b, x, iters_f32: int) -> dict:
+    """The FP32 setup against the FP64 one (which equals the oracle's, tested): rows with the same
+    pattern, element-wise and Frobenius relative error of G on them, PCG iterations of both."""
+    P32 = af.setup(dA, pb.kmax, pb.s, pb.eps, setup_f32=True)
+    P64 = af.setup(dA, pb.kmax, pb.s, pb.eps)
+    (r32, c32, v32), (r64, c64, v64) = ([t.cpu().numpy() for t in Pk.export()] for Pk in (P32, P64))
+    rows_same = 0
+    gerr = None
+    rel = np.array([np.nan])
+    row_rel = np.array([np.nan])
+    if np.array_equal(r32, r64):
+        eq = c32 == c64
+        row_of = np.repeat(np.arange(pb.n), np.diff(r64))
+        bad = np.zeros(pb.n, bool)
+        np.logical_or.at(bad, row_of[~eq], True)
+        rows_same = int((~bad).sum())
+        ok = ~bad[row_of]
+        rel = np.abs(v32[ok] - v64[ok]) / np.maximum(np.abs(v64[ok]), 1e-300)
+        # per row, relative to the row's largest entry (the parity tests' measure)
+        d = np.maximum.reduceat(np.abs(v32 - v64), r64[:-1])
+        m = np.maximum.reduceat(np.abs(v64), r64[:-1])
+        row_rel = (d / m)[~bad]
+        gerr = float(np.linalg.norm(v32[ok] - v64[ok]) / np.linalg.norm(v64[ok]))
+    else:
+        rows_same = int(sum(np.array_equal(c32[r32[i]:r32[i + 1]], c64[r64[i]:r64[i + 1]]) for i in range(pb.n)))
+    x.zero_()
+    _, i64 = af.pcg_solve(dA, P64, b, x=x, rtol=pb.rtol)
+    P32.close()
+    P64.close()
+    ev = {"rows_same_pattern": rows_same / pb.n, "g_rel_err_same_rows_elementwise_max": float(np.nanmax(rel)),
+          "g_rel_err_same_rows_rowmax_max": float(np.nanmax(row_rel)),
+          "g_rel_err_same_rows_rowmax_p99": float(np.nanpercentile(row_rel, 99)),
+          "g_rel_err_fro": gerr, "iters_f32_setup": iters_f32, "iters_f64_setup": i64.iters}
+    print(f"[bench] FP32 setup: {100 * rows_same / pb.n:.4f}% rows with the FP64 pattern, iterations "
+          f"{iters_f32} vs {i64.iters}, {ev}", file=sys.stderr, flush=True)
+    return ev
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="elast27_64",
+    ap.add_argument("--workload", default="elast27_150",
                     choices=sorted(list(workloads()) + list(BATCH_WORKLOADS) + ["serve", "jacobi_compare", "spmm"]))
     ap.add_argument("--with-largest", action="store_true", help="jacobi_compare: add the 150^3 27-point workload")
     ap.add_argument("--requests", type=int, default=300, help="serve: number of requests")
@@ -454,12 +682,15 @@ def main():
     ap.add_argument("--budget-gb", type=int, default=96, help="serve: device memory budget of the servers")
     ap.add_argument("--serve-slots", type=int, nargs="+", default=[2, 4],
                     help="serve: slot counts of the continuous-batching runs")
-    ap.add_argument("--g-prec", default="f64", choices=["f64", "f32"])
+    ap.add_argument("--g-prec", default=None, choices=["f64", "f32"],
+                    help="storage of G (default: the workload's own, FP32 for the 150^3 problem, else FP64)")
     ap.add_argument("--setup-f32", action="store_true",
                     help="per-row setup arithmetic in FP32 (reports pattern agreement with the FP64 setup)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=0)
     ap.add_argument("--no-profile", action="store_true", help="do not time kernels with HIP events")
+    ap.add_argument("--no-context", action="store_true",
+                    help="skip the 64^3 context run that the default (150^3) line carries")
     ap.add_argument("--copy-check", action="store_true",
                     help="only run a plain 1 GiB device copy five times (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -492,159 +723,29 @@ def main():
     if args.workload == "spmm":
         spmm_bench(args)
         return
+    t_gen = time.perf_counter()
     pb = workloads()[args.workload]()
-    g_prec = af.F32 if args.g_prec == "f32" else af.F64
+    gp = args.g_prec or WORKLOAD_G_PREC.get(args.workload, "f64")
+    g_prec = af.F32 if gp == "f32" else af.F64
     print(f"[bench] workload {pb.name}: n={pb.n} nnz={pb.A.nnz} kmax={pb.kmax} s={pb.s} eps={pb.eps} "
-          f"g_prec={args.g_prec}", file=sys.stderr, flush=True)
-    dA = af.DeviceCSR.from_host(pb.A)
-    b = torch.from_numpy(pb.b).cuda()
-    x = torch.zeros_like(b)
-
-    def step():
-        P = af.setup(dA, pb.kmax, pb.s, pb.eps, g_prec=g_prec, setup_f32=args.setup_f32)
-        x.zero_()
-        _, info = af.pcg_solve(dA, P, b, x=x, rtol=pb.rtol)
-        sinfo = P.info()
-        P.close()
-        return sinfo, info
-
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-
-    profile = not args.no_profile
-    kern_all = {}
-    dom = None
-    if profile:
-        # one untimed step with every kernel timed: the per-kernel breakdown and the dominant
-        # kernel; inside the timed region only the dominant kernel carries events
-        af.profile_only(None)
-        af.profile_read(reset=True)
-        af.profile_enable(True)
-        step()
-        torch.cuda.synchronize()
-        af.profile_enable(False)
-        kern_all = af.profile_read(reset=True)
-        dom = max(kern_all.items(), key=lambda kv: kv[1][1])[0]
-        af.profile_only([dom])
-        af.profile_enable(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    setup_ms, pcg_ms, its = [], [], []
-    for _ in range(args.steps):
-        sinfo, info = step()
-        setup_ms.append(sinfo.ms)
-        pcg_ms.append(info.ms)
-        its.append(info.iters)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    kern = {}
-    if profile:
-        af.profile_enable(False)
-        kern = af.profile_read(reset=True)
-        af.profile_only(None)
-    sec = (t1 - t0) / args.steps
-    print(f"[bench] {args.steps} steps: {sec * 1e3:.2f} ms/step (setup {np.mean(setup_ms):.2f} ms, "
-          f"pcg {np.mean(pcg_ms):.2f} ms, {its[-1]} iterations, true relres {info.true_relres:.2e})",
-          file=sys.stderr, flush=True)
-
-    w_g = 4 if g_prec == af.F32 else 8
-    roof = None
-    issue_roof = None
-    kern_report = {}
-    for name, (launches, ms) in kern_all.items():
-        byt = kernel_bytes(name, pb.n, pb.A.nnz, sinfo.nnz_g, w_g, pb.kmax, sinfo.mmax)
-        avg_ms = ms / max(1, launches)
-        kern_report[name] = {"launches": launches, "total_ms": round(ms, 3), "avg_us": round(avg_ms * 1e3, 2),
-                             "gbs": round(byt / (avg_ms * 1e-3) / 1e9, 1) if avg_ms > 0 and byt == byt else None}
-    if kern and dom in kern:
-        launches, ms = kern[dom]
-        avg_s = ms / launches * 1e-3
-        byt = kernel_bytes(dom, pb.n, pb.A.nnz, sinfo.nnz_g, w_g, pb.kmax, sinfo.mmax)
-        ach = byt / avg_s / 1e9
-        roof = {"kernel": dom, "bound": "hbm", "achieved": round(ach, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                "frac": round(ach / PEAK_HBM_GBS, 4), "traffic": measured_traffic(dom, args.workload),
-                "bytes_per_launch": byt, "avg_launch_us": round(avg_s * 1e6, 2)}
-        # the same launch against the VALU issue rate, from the committed instruction count
-        vi = measured_value(dom, args.workload, "sq_counters", "valu_insts_per_launch")
-        if vi:
-            g = vi / avg_s / 1e9
-            issue_roof = {"kernel": dom, "bound": "valu_issue", "achieved": round(g, 1), "peak": PEAK_VALU_GINST,
-                          "unit": "Ginst/s", "frac": round(g / PEAK_VALU_GINST, 4), "valu_insts_per_launch": vi}
-
-    # whole-PCG achieved bandwidth from the per-iteration algorithmic bytes
-    it_bytes = (kernel_bytes("spmv_A_dot", pb.n, pb.A.nnz, sinfo.nnz_g, w_g, pb.kmax, sinfo.mmax)
-                + kernel_bytes("update_xr", pb.n, 0, 0, w_g, 0, 0)
-                + kernel_bytes("spmv_G", pb.n, 0, sinfo.nnz_g, w_g, 0, 0)
-                + kernel_bytes("spmv_GT_dot", pb.n, 0, sinfo.nnz_g, w_g, 0, 0)
-                + kernel_bytes("update_p", pb.n, 0, 0, w_g, 0, 0))
-    pcg_gbs = it_bytes * its[-1] / (np.mean(pcg_ms) * 1e-3) / 1e9
-
-    cpu = None
-    if not args.no_cpu_baseline:
-        threads = args.cpu_threads or int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or (os.cpu_count() or 1)
-        print(f"[bench] cpu baseline: oracle on {threads} threads ...", file=sys.stderr, flush=True)
-        cpu = cpu_baseline(pb, its[-1], threads, x.cpu().numpy())
-
-    f32_eval = None
-    if args.setup_f32:
-        # the FP32 setup against the FP64 one (which equals the oracle's bit for bit, tested):
-        # rows with the same pattern, relative error of G on them, PCG iterations of both
-        P32 = af.setup(dA, pb.kmax, pb.s, pb.eps, setup_f32=True)
-        P64 = af.setup(dA, pb.kmax, pb.s, pb.eps)
-        (r32, c32, v32), (r64, c64, v64) = ([t.cpu().numpy() for t in Pk.export()] for Pk in (P32, P64))
-        same_len = np.diff(r32) == np.diff(r64)
-        rows_same = 0
-        if same_len.all() and np.array_equal(r32, r64):
-            eq = c32 == c64
-            row_of = np.repeat(np.arange(pb.n), np.diff(r64))
-            bad = np.zeros(pb.n, bool)
-            np.logical_or.at(bad, row_of[~eq], True)
-            rows_same = int((~bad).sum())
-            ok = ~bad[row_of]
-            rel = np.abs(v32[ok] - v64[ok]) / np.maximum(np.abs(v64[ok]), 1e-300)
-            gerr = float(np.linalg.norm(v32 - v64) / np.linalg.norm(v64))
-        else:
-            rows_same = int(sum(np.array_equal(c32[r32[i]:r32[i + 1]], c64[r64[i]:r64[i + 1]]) for i in range(pb.n)))
-            rel = np.array([np.nan])
-            gerr = None
-        x.zero_()
-        _, i64 = af.pcg_solve(dA, P64, b, x=x, rtol=pb.rtol)
-        f32_eval = {"rows_same_pattern": rows_same / pb.n, "g_rel_err_same_rows_max": float(np.nanmax(rel)),
-                    "g_rel_err_fro": gerr, "iters_f32_setup": its[-1], "iters_f64_setup": i64.iters}
-        P32.close()
-        P64.close()
-        print(f"[bench] FP32 setup: {100 * rows_same / pb.n:.2f}% rows with the FP64 pattern, iterations "
-              f"{its[-1]} vs {i64.iters}", file=sys.stderr, flush=True)
-
-    out = {
-        "metric": METRIC,
-        "value": round(sec, 6),
-        "unit": "s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(sec * 1e3, 3),
-        "higher_is_better": False,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": ("f32 setup, " if args.setup_f32 else "") + ("f64" if g_prec == af.F64 else "f64 (G stored f32)"),
-        "data": "synthetic",
-        "config": {"workload": pb.name, "n": pb.n, "nnz": pb.A.nnz, "kmax": pb.kmax, "s": pb.s, "eps": pb.eps,
-                   "rtol": pb.rtol, "g_prec": args.g_prec, "setup_prec": "f32" if args.setup_f32 else "f64",
-                   "nnz_g": sinfo.nnz_g},
-        "setup_ms": round(float(np.mean(setup_ms)), 3),
-        "pcg_ms": round(float(np.mean(pcg_ms)), 3),
-        "iters": its[-1],
-        "true_relres": info.true_relres,
-        "pcg_hbm_gbs": round(pcg_gbs, 1),
-        "roofline": roof,
-        "issue_roofline": issue_roof,
-        "kernels": kern_report,
-        "cpu_baseline": cpu,
-    }
-    if f32_eval:
-        out["setup_f32_eval"] = f32_eval
+          f"g_prec={gp} (generated in {time.perf_counter() - t_gen:.1f} s)", file=sys.stderr, flush=True)
+    res = run_workload(af, pb, g_prec, args, args.steps, args.warmup, not args.no_profile,
+                       not args.no_cpu_baseline, args.workload)
+    context = None
+    if args.workload == "elast27_150" and not args.no_context:
+        # the 64^3 workload (786,432 rows, FP64 G) as context beside the headline
+        del pb
+        pc = workloads()["elast27_64"]()
+        c = run_workload(af, pc, af.F64, args, min(args.steps, 5), 1, not args.no_profile, False, "elast27_64")
+        context = {"elast27_64": {k: c[k] for k in ("ms_per_step", "setup_ms", "pcg_ms", "iters", "pcg_hbm_gbs",
+                                                    "roofline", "config")}}
+    out = {"metric": METRIC, "value": res.pop("value"), "unit": "s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": res.pop("ms_per_step"), "higher_is_better": False,
+           "scaling": "weak", "vs_baseline": None, "dtype": res.pop("dtype"), "data": "synthetic",
+           "config": res.pop("config")}
+    out.update(res)
+    if context:
+        out["context"] = context
     print(json.dumps(out), flush=True)
 
 

@@ -56,6 +56,8 @@ def _bind(L):
     L.oracle_afsai_rows.restype = ctypes.c_int
     L.oracle_afsai_rows.argtypes = [i32, i32p, i32p, f64p, i32, i32, ctypes.c_double, ctypes.c_double,
                                     i32, vp, i32, i32p, i32p, f64p, vp, vp, vp, i32]
+    L.oracle_set_threads.restype = None
+    L.oracle_set_threads.argtypes = [i32]
     L.oracle_spmv.restype = None
     L.oracle_spmv.argtypes = [i32, i32p, i32p, f64p, f64p, f64p]
     L.oracle_spmv_t.restype = None
@@ -171,6 +173,12 @@ def setup(A, kmax: int, s: int, eps: float, tau: float = TIE_RTOL, nthreads: int
     np.cumsum(R.m, out=rp[1:])
     mask = np.arange(R.cols.shape[1])[None, :] < R.m[:, None]
     return Factor(rp.astype(np.int32), R.cols[mask].astype(np.int32), R.vals[mask].astype(np.float64), R)
+
+
+def set_threads(nthreads: int) -> None:
+    """Threads of the oracle's parallel loops started from the calling thread afterwards
+    (results do not depend on it)."""
+    lib().oracle_set_threads(int(nthreads))
 
 
 def spmv(A, x: np.ndarray) -> np.ndarray:

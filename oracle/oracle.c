@@ -327,6 +327,17 @@ int oracle_afsai_rows(int32_t n, const int32_t *rp, const int32_t *ci, const dou
     return rc;
 }
 
+/* threads of the parallel loops started afterwards by the calling thread (the products and
+ * the setup without an explicit count); no effect on any result */
+void oracle_set_threads(int32_t nthreads)
+{
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+    (void)nthreads;
+#endif
+}
+
 /* y = A x: each row summed in ascending column order */
 void oracle_spmv(int32_t n, const int32_t *rp, const int32_t *ci, const double *av,
                  const double *x, double *y)

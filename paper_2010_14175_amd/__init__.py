@@ -151,6 +151,18 @@ def _ptr(t) -> ctypes.c_void_p:
     return ctypes.c_void_p(0 if t is None else t.data_ptr())
 
 
+def _check_dev(t, shape, what: str):
+    """Raises ValueError unless t is a contiguous float64 CUDA tensor of the given shape (the
+    library reads and writes exactly that many elements through its pointer)."""
+    import torch
+
+    if (not isinstance(t, torch.Tensor) or t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous()
+            or tuple(t.shape) != tuple(shape)):
+        got = (f"{tuple(t.shape)} {t.dtype} on {t.device}{'' if t.is_contiguous() else ', not contiguous'}"
+               if isinstance(t, torch.Tensor) else type(t).__name__)
+        raise ValueError(f"{what}: expected a contiguous float64 CUDA tensor of shape {tuple(shape)}, got {got}")
+
+
 class DeviceCSR:
     """A square CSR matrix resident on the GPU (int32 indices, fp64 values), held by torch
     tensors.  ``struct`` is the C view passed to the library."""
@@ -248,8 +260,11 @@ class Preconditioner:
         """z = G^T (G r)."""
         import torch
 
+        n = self.info().n
+        _check_dev(r, (n,), "apply: r")
         if z is None:
             z = torch.empty_like(r)
+        _check_dev(z, (n,), "apply: z")
         _check(lib().afsai_apply(self.handle, _ptr(r), _ptr(z), _stream(stream)), "afsai_apply")
         return z
 
@@ -290,8 +305,10 @@ def pcg_solve(A: DeviceCSR, P: Preconditioner | None, b, x=None, rtol: float = 1
     Returns (x, PcgInfo)."""
     import torch
 
+    _check_dev(b, (A.n,), "pcg_solve: b")
     if x is None:
         x = torch.zeros_like(b)
+    _check_dev(x, (A.n,), "pcg_solve: x")
     maxit = A.n if maxit is None else int(maxit)
     inf = PcgInfoStruct()
     st = A.struct
@@ -350,8 +367,10 @@ def pcg_solve_batched(A: DeviceCSR, P: Preconditioner | None, offsets, b, x=None
     import torch
 
     off, optr, nsys = _offsets(offsets)
+    _check_dev(b, (A.n,), "pcg_solve_batched: b")
     if x is None:
         x = torch.zeros_like(b)
+    _check_dev(x, (A.n,), "pcg_solve_batched: x")
     maxit = int(max(off[1:] - off[:-1])) if maxit is None else int(maxit)
     infs = (PcgInfoStruct * nsys)()
     st = A.struct
@@ -399,6 +418,8 @@ class Server:
                g_prec: int | None = None) -> int:
         """Queues A x = b (device data; x is overwritten), with the server's setup parameters or the
         ones given here.  Returns the request's ticket."""
+        _check_dev(b, (A.n,), "Server.submit: b")
+        _check_dev(x, (A.n,), "Server.submit: x")
         t = ctypes.c_int64()
         st = A.struct
         p = None
@@ -451,6 +472,7 @@ def spmm(A: DeviceCSR, X, Y=None, stream=None):
         raise ValueError("spmm: X must be a contiguous float64 (n, k) tensor")
     if Y is None:
         Y = torch.empty_like(X)
+    _check_dev(Y, tuple(X.shape), "spmm: Y")
     st = A.struct
     _check(lib().afsai_spmm(ctypes.byref(st), int(X.shape[1]), _ptr(X), _ptr(Y), _stream(stream)), "afsai_spmm")
     return Y
@@ -460,8 +482,10 @@ def spmv(A: DeviceCSR, x, y=None, stream=None):
     """y = A x (``afsai_spmv``)."""
     import torch
 
+    _check_dev(x, (A.n,), "spmv: x")
     if y is None:
         y = torch.empty_like(x)
+    _check_dev(y, (A.n,), "spmv: y")
     st = A.struct
     _check(lib().afsai_spmv(ctypes.byref(st), _ptr(x), _ptr(y), _stream(stream)), "afsai_spmv")
     return y

@@ -461,9 +461,17 @@ static int setup_core(const afsai_csr *A, const afsai_params *p, int nsys, const
     int rc = device_info(&di);
     if (rc) return rc;
     hipStream_t s = (hipStream_t)stream;
-    hipEvent_t t0, t1;
-    AFSAI_HIP_TRY(hipEventCreate(&t0));
-    AFSAI_HIP_TRY(hipEventCreate(&t1));
+    // the two timing events are destroyed on every return path
+    struct Events {
+        hipEvent_t e[2] = {nullptr, nullptr};
+        ~Events() {
+            for (hipEvent_t x : e)
+                if (x) (void)hipEventDestroy(x);
+        }
+    } ev;
+    AFSAI_HIP_TRY(hipEventCreate(&ev.e[0]));
+    AFSAI_HIP_TRY(hipEventCreate(&ev.e[1]));
+    hipEvent_t t0 = ev.e[0], t1 = ev.e[1];
     AFSAI_HIP_TRY(hipEventRecord(t0, s));
     const int n = A->n;
     const bool f32 = (p->g_prec == AFSAI_F32);
@@ -655,7 +663,10 @@ static int setup_core(const afsai_csr *A, const afsai_params *p, int nsys, const
                                mcnt.as<int32_t>(), ell_col.as<int32_t>(), ell_val.as<double>(), P->g_rp, P->g_ci,
                                (double *)P->g_val);
     }
-    AFSAI_HIP_TRY(hipGetLastError());
+    if (hipError_t e = hipGetLastError(); e != hipSuccess) {
+        set_error("afsai_setup: assembly of G: %s", hipGetErrorString(e));
+        return fail(AFSAI_ERR_HIP);
+    }
     {
         ProfScope ps("sell_G", s);
         if ((rc = sell_from_ell(n, P->nnz_g, ldell, mcnt.as<int32_t>(), ell_col.as<int32_t>(), ell_val.as<double>(), f32, &P->sg,
@@ -672,12 +683,16 @@ static int setup_core(const afsai_csr *A, const afsai_params *p, int nsys, const
     P->steps = (int32_t *)steps.release();
     P->reason = (int32_t *)reason.release();
     if ((rc = alloc_workspace(P, di))) return fail(rc);
-    AFSAI_HIP_TRY(hipEventRecord(t1, s));
-    AFSAI_HIP_TRY(hipStreamSynchronize(s));
+    {
+        hipError_t e = hipEventRecord(t1, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) {
+            set_error("afsai_setup: %s", hipGetErrorString(e));
+            return fail(AFSAI_ERR_HIP);
+        }
+    }
     float ms = 0.f;
     (void)hipEventElapsedTime(&ms, t0, t1);
-    (void)hipEventDestroy(t0);
-    (void)hipEventDestroy(t1);
     prof_flush();
 
     afsai_setup_info &inf = P->info;

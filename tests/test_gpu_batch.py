@@ -166,3 +166,33 @@ def test_batched_errors(af):
         af.pcg_solve(dA, P, _vec(b))  # a batch handle needs the batched solver
     with pytest.raises(af.AfsaiError):
         af.pcg_solve_batched(dA, P, [0, int(off[2]), A.n], _vec(b))  # other offsets
+
+
+def test_full_batch512_against_oracle(af):
+    """The full batched workload: 512 anisotropic 7-point systems (sides U{10..40}, 7,788,665
+    rows), one batched setup and one batched solve, in the launch configuration of the batched
+    benchmark.  Every row of G against the oracle's setup of the block-diagonal matrix (patterns
+    identical, values within 1e-10), and every system's PCG against the oracle's PCG on that
+    system with the oracle's G: the same iteration count and x within 1e-10."""
+    probs, A, off, b, _ = _batch(512, 10, 40, seed=3)
+    assert A.n == 7788665
+    dA = af.DeviceCSR.from_host(A)
+    P = af.setup_batched(dA, off, 5, 1, 1e-2)
+    x, infos = af.pcg_solve_batched(dA, P, off, _vec(b), rtol=1e-8)
+    xh = x.cpu().numpy()
+    rp, ci, va = _factor(P)
+    G = oracle.setup(A, 5, 1, 1e-2)
+    np.testing.assert_array_equal(G.row_ptr, rp)
+    np.testing.assert_array_equal(G.col, ci)
+    # per-row relative error (infinity norm); every row has at least its diagonal entry
+    dmax = np.maximum.reduceat(np.abs(va - G.val), G.row_ptr[:-1])
+    vmax = np.maximum.reduceat(np.abs(G.val), G.row_ptr[:-1])
+    assert np.max(dmax / vmax) <= 1e-10
+    for k, pb in enumerate(probs):
+        o0, o1 = int(off[k]), int(off[k + 1])
+        a0, a1 = int(G.row_ptr[o0]), int(G.row_ptr[o1])
+        Gk = oracle.Factor((G.row_ptr[o0:o1 + 1] - a0).astype(np.int32), (G.col[a0:a1] - o0).astype(np.int32),
+                           G.val[a0:a1], None)
+        ro = oracle.pcg(pb.A, Gk, pb.b, 1e-8)
+        assert infos[k].converged and infos[k].iters == ro.iters, (k, infos[k].iters, ro.iters)
+        assert np.linalg.norm(xh[o0:o1] - ro.x) <= 1e-10 * np.linalg.norm(ro.x), k

@@ -2,13 +2,17 @@
 device footprint and overlaps their setups and solves.
 
 Bars: every request's x is bit for bit the x of a separate afsai_setup + pcg_solve with the same
-parameters, whether it was served alone or among many; at no time do the admitted requests
-hold more than the budget or more slots than allowed; a request larger than the budget is
-refused; a failing request reports its error without disturbing the others.
+parameters, whether it was served alone or among many, and it is the FP64 oracle's PCG solution
+on the oracle's G: the same iteration count and x within 1e-10 relative with G stored in FP64;
+with G stored in FP32, converged to the same rtol, iteration count within 2 and x within 1e-6
+relative (the bound of the single-solve FP32-G parity test).  At no time do the admitted
+requests hold more than the budget or more slots than allowed; a request larger than the budget
+is refused; a failing request reports its error without disturbing the others.
 """
 import numpy as np
 import pytest
 
+import oracle
 import synth
 
 pytestmark = pytest.mark.gpu
@@ -44,8 +48,11 @@ def _requests():
     return probs
 
 
-def _serve(af, probs, budget, slots):
-    srv = af.Server(budget, slots, KMAX, S, EPS, rtol=1e-8, setup_threads=2)
+X_RTOL = 1e-10
+
+
+def _serve(af, probs, budget, slots, g_prec=0):
+    srv = af.Server(budget, slots, KMAX, S, EPS, rtol=1e-8, setup_threads=2, g_prec=g_prec)
     data = []
     for pb in probs:
         dA = af.DeviceCSR.from_host(pb.A)
@@ -78,6 +85,25 @@ def test_served_results_equal_separate_solves(af):
         assert np.array_equal(xm.view(np.int64), xa.view(np.int64)), f"{pb.name}: mix differs from alone"
         assert np.array_equal(xs.view(np.int64), xa.view(np.int64)), f"{pb.name}: one slot differs from alone"
         assert rm.true_relres == ia.true_relres
+        # against the oracle: its setup of the same matrix and its textbook PCG
+        ro = oracle.pcg(pb.A, oracle.setup(pb.A, pb.kmax, pb.s, EPS), pb.b, 1e-8)
+        assert rm.iters == ro.iters, (pb.name, rm.iters, ro.iters)
+        assert np.linalg.norm(xm - ro.x) <= X_RTOL * np.linalg.norm(ro.x), pb.name
+
+
+def test_served_fp32_g_against_oracle(af):
+    """The serving workload's precision form (G stored in FP32, FP64 PCG): every served x in a
+    mix of four slots against the oracle's FP64 solution, and bit for bit the x of the same
+    request served alone."""
+    probs = _requests()
+    mixed = _serve(af, probs, 1 << 34, 4, g_prec=af.F32)
+    single = _serve(af, probs, 1 << 34, 1, g_prec=af.F32)
+    for pb, (xm, rm), (xs, rs) in zip(probs, mixed, single):
+        ro = oracle.pcg(pb.A, oracle.setup(pb.A, pb.kmax, pb.s, EPS), pb.b, 1e-8)
+        assert rm.status == af.OK and rm.converged and rm.true_relres <= 1.5e-8, pb.name
+        assert abs(rm.iters - ro.iters) <= 2, (pb.name, rm.iters, ro.iters)
+        assert np.linalg.norm(xm - ro.x) <= 1e-6 * np.linalg.norm(ro.x), pb.name
+        assert rs.iters == rm.iters and np.array_equal(xm.view(np.int64), xs.view(np.int64)), pb.name
 
 
 def test_admission_respects_budget_and_slots(af):
