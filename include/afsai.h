@@ -142,6 +142,22 @@ int afsai_setup(const afsai_csr *A, const afsai_params *p, void *stream, afsai_p
 int afsai_apply(afsai_precond P, const double *r, double *z, void *stream);
 
 /*
+ * afsai_apply_noalloc -- afsai_apply for callers that cannot allocate device memory (code
+ *   under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ *   products and the same result as afsai_apply, bit for bit, with the intermediate t = G r in
+ *   a fixed device array of the library instead of the handle's workspace.  The call itself
+ *   allocates nothing (no hipMalloc, hipFree or pinned host memory; with the kernel timer off,
+ *   its default).
+ *   r, z (device) length n, caller-owned, must not alias.  n <= 16,777,216 (the array holds
+ *   2^24 doubles, 128 MiB per GPU the library runs on, kept until the process ends).
+ *   Asynchronous on `stream`.  Every call on one GPU shares that GPU's array: calls that
+ *   overlap in time on one GPU (different streams or host threads) race on it.
+ *   Errors: AFSAI_ERR_INVALID_ARG (null or aliased pointers), AFSAI_ERR_TOO_LARGE (n above
+ *   the limit), AFSAI_ERR_HIP.
+ */
+int afsai_apply_noalloc(afsai_precond P, const double *r, double *z, void *stream);
+
+/*
  * pcg_solve -- preconditioned conjugate gradient for A x = b with M^-1 = G^T G (P != NULL) or
  *   M = I (P == NULL, plain CG).  Textbook PCG (Sec. 5.2 stops at a residual reduction of eight
  *   orders of magnitude): x holds x0 on entry and the last iterate on return; the iteration

@@ -29,7 +29,7 @@ SETUP_F32 = 2
 STOP_KMAX, STOP_EPS, STOP_NOCAND = 0, 1, 2
 
 # every symbol the C header declares
-EXPORTS = ("afsai_setup", "afsai_apply", "pcg_solve", "afsai_setup_batched", "pcg_solve_batched",
+EXPORTS = ("afsai_setup", "afsai_apply", "afsai_apply_noalloc", "pcg_solve", "afsai_setup_batched", "pcg_solve_batched",
            "afsai_server_create", "afsai_server_submit", "afsai_server_poll", "afsai_server_pending",
            "afsai_server_destroy", "afsai_spmv", "afsai_spmm", "pcg_solve_multi",
            "afsai_get_setup_info", "afsai_export",
@@ -102,6 +102,7 @@ def lib():
         P = ctypes.POINTER
         L.afsai_setup.argtypes = [P(CsrStruct), P(ParamsStruct), vp, P(vp)]
         L.afsai_apply.argtypes = [vp, vp, vp, vp]
+        L.afsai_apply_noalloc.argtypes = [vp, vp, vp, vp]
         L.pcg_solve.argtypes = [P(CsrStruct), vp, vp, vp, ctypes.c_double, i32, vp, P(PcgInfoStruct)]
         L.afsai_spmv.argtypes = [P(CsrStruct), vp, vp, vp]
         L.afsai_spmm.argtypes = [P(CsrStruct), ctypes.c_int32, vp, vp, vp]
@@ -266,6 +267,14 @@ class Preconditioner:
             z = torch.empty_like(r)
         _check_dev(z, (n,), "apply: z")
         _check(lib().afsai_apply(self.handle, _ptr(r), _ptr(z), _stream(stream)), "afsai_apply")
+        return z
+
+    def apply_noalloc(self, r, z, stream=None):
+        """z = G^T (G r) through afsai_apply_noalloc (z must be given: the call allocates nothing)."""
+        n = self.info().n
+        _check_dev(r, (n,), "apply_noalloc: r")
+        _check_dev(z, (n,), "apply_noalloc: z")
+        _check(lib().afsai_apply_noalloc(self.handle, _ptr(r), _ptr(z), _stream(stream)), "afsai_apply_noalloc")
         return z
 
     def close(self):

@@ -24,6 +24,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <mutex>
 #include <vector>
 
 #include "handle.hpp"
@@ -1808,6 +1809,62 @@ int afsai_apply(afsai_precond P, const double *r, double *z, void *stream) {
     // products only (no dots): the whole matrix as one system
     BatchMaps bm;
     if ((rc = make_batch_maps(P->sg.nslices * kSlice, 1, nullptr, di, s, &bm))) return rc;
+    bm.sell.nblocks = blocks_for_slices(P->sg.nslices, di);
+    sell_spmv("spmv_G", P->sg, bm, r, t, nullptr, nullptr, nullptr, FIN_NONE, di, s);
+    bm.sell.nblocks = blocks_for_slices(P->sgt.nslices, di);
+    sell_spmv("spmv_GT", P->sgt, bm, t, z, nullptr, nullptr, nullptr, FIN_NONE, di, s);
+    AFSAI_HIP_TRY(hipGetLastError());
+    return AFSAI_OK;
+}
+
+}  // extern "C"
+
+namespace afsai {
+
+// Scratch of afsai_apply_noalloc: the intermediate t = G r of one application, for up to
+// kNoAllocMaxRows rows (128 MiB of doubles, held by every GPU the library runs on until the
+// process ends).  Host code never passes `scratch` itself to a kernel: each device's address
+// of the array is taken once with hipGetSymbolAddress (with that device current) and kept.
+constexpr int64_t kNoAllocMaxRows = (int64_t)1 << 24;
+static __device__ __align__(256) double scratch[kNoAllocMaxRows];
+
+// address of `scratch` on the current device, looked up on the first call there
+static int scratch_ptr(double **out) {
+    constexpr int kMaxDev = 64;
+    static std::mutex mu;
+    static double *ptr[kMaxDev] = {};
+    int dev = -1;
+    AFSAI_HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDev) AFSAI_FAIL(AFSAI_ERR_INVALID_ARG, "afsai_apply_noalloc: device %d", dev);
+    std::lock_guard<std::mutex> lk(mu);
+    if (!ptr[dev]) {
+        void *p = nullptr;
+        AFSAI_HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) AFSAI_FAIL(AFSAI_ERR_HIP, "afsai_apply_noalloc: no device address for the scratch array");
+        ptr[dev] = (double *)p;
+    }
+    *out = ptr[dev];
+    return AFSAI_OK;
+}
+
+}  // namespace afsai
+
+extern "C" {
+
+int afsai_apply_noalloc(afsai_precond P, const double *r, double *z, void *stream) {
+    if (!P || !r || !z) AFSAI_FAIL(AFSAI_ERR_INVALID_ARG, "afsai_apply_noalloc: null argument");
+    if (r == z) AFSAI_FAIL(AFSAI_ERR_INVALID_ARG, "afsai_apply_noalloc: r and z alias");
+    if ((int64_t)P->n > kNoAllocMaxRows)
+        AFSAI_FAIL(AFSAI_ERR_TOO_LARGE, "afsai_apply_noalloc: n = %d exceeds the scratch limit of %lld rows", P->n,
+                   (long long)kNoAllocMaxRows);
+    DeviceInfo di;
+    int rc = device_info(&di);
+    if (rc) return rc;
+    double *t = nullptr;
+    if ((rc = scratch_ptr(&t))) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    // the products of afsai_apply, the whole matrix as one system (no device block maps)
+    BatchMaps bm;
     bm.sell.nblocks = blocks_for_slices(P->sg.nslices, di);
     sell_spmv("spmv_G", P->sg, bm, r, t, nullptr, nullptr, nullptr, FIN_NONE, di, s);
     bm.sell.nblocks = blocks_for_slices(P->sgt.nslices, di);
