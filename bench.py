@@ -457,7 +457,8 @@ def kernel_source_hash(kernel: str) -> str | None:
     counter-derived traffic is only reported for the code that was measured)."""
     import hashlib
 
-    files = {"afsai_rows": ["rows.hpp", "rows.hip", "rows_reg.hip", "rows_lds.hip", "rows_f32.hip"]}.get(kernel)
+    files = {"afsai_rows": ["rows.hpp", "rows.hip", "rows_reg.hip", "rows_lds.hip", "rows_f32.hip", "rows_w.hpp",
+                           "rows_w.hip"]}.get(kernel)
     if not files:
         return None
     h = hashlib.sha256()

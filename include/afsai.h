@@ -337,7 +337,8 @@ const char *afsai_last_error(void);
  *                             update of the per-row setup kernel (1..4; any choice gives
  *                             identical G)
  *   AFSAI_OPT_SETUP_TABLE     slots of the first on-chip candidate table (power of two,
- *                             128..1024)
+ *                             64..1024; the inverse-factor form takes 64..1024, the
+ *                             Cholesky form 128..1024)
  *   AFSAI_OPT_SPMV_GROUP      lanes per row of the CSR products (4, 8, 16, 32 or 64)
  *   AFSAI_OPT_SPMV_UNROLL     independent loads per lane per round in the sparse products
  *                             (1, 2, 4, 8)
@@ -372,6 +373,14 @@ const char *afsai_last_error(void);
  *                             (the slices keep each row's last w entries, a second layout the
  *                             leading ones).  Products are identical row by row; fused dot
  *                             products are summed in another order
+ *   AFSAI_OPT_SETUP_FORM      per-row factorisation of the setup: 0 (automatic) the
+ *                             inverse-factor form where it applies (FP64 setup arithmetic,
+ *                             every row of A at most 128 entries, n <= 2^24), else the
+ *                             Cholesky form; 1 the Cholesky form (a factor appended row by
+ *                             row, then a back substitution per step); 2 the inverse-factor
+ *                             form (AFSAI_ERR_INVALID_ARG from afsai_setup when it does not
+ *                             apply).  Both forms compute the same G in exact arithmetic and
+ *                             differ by rounding only
  * Returns AFSAI_ERR_INVALID_ARG for an unknown option or value.  Not thread safe against
  * concurrent calls of the library.
  */
@@ -386,6 +395,7 @@ const char *afsai_last_error(void);
 #define AFSAI_OPT_SETUP_SLOTS 9
 #define AFSAI_OPT_SELL_TAIL 10
 #define AFSAI_OPT_SELL_UNEVEN 11
+#define AFSAI_OPT_SETUP_FORM 12
 int afsai_set_option(int32_t option, int64_t value);
 
 /*

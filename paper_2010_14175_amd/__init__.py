@@ -37,7 +37,7 @@ EXPORTS = ("afsai_setup", "afsai_apply", "afsai_apply_noalloc", "pcg_solve", "af
            "afsai_release_cache",
            "afsai_profile_enable", "afsai_profile_only", "afsai_profile_read")
 (OPT_SETUP_GROUP, OPT_SETUP_TABLE, OPT_SPMV_GROUP, OPT_SPMV_UNROLL, OPT_PCG_CSR_A, OPT_PCG_FORM,
- OPT_SELL_WIDTH, OPT_PCG_GRAPH, OPT_SETUP_SLOTS, OPT_SELL_TAIL, OPT_SELL_UNEVEN) = 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11
+ OPT_SELL_WIDTH, OPT_PCG_GRAPH, OPT_SETUP_SLOTS, OPT_SELL_TAIL, OPT_SELL_UNEVEN, OPT_SETUP_FORM) = range(1, 13)
 
 
 class ServerConfigStruct(ctypes.Structure):

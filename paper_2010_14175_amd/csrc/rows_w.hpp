@@ -1,0 +1,741 @@
+// The per-row adaptive FSAI setup (Sec. 2) in inverse-factor form: each row keeps W = L_o^-1,
+// the inverse of the Cholesky factor of A[P_o,P_o] over its off-diagonal positions, instead of
+// L itself.  Row i of G is the last row of L^-1 for the pattern with i last:
+//
+//     L = [ L_o   0  ]      L^-1 = [ W                 0     ]      l_i = W a_i,
+//         [ l_i^T d_i]             [ -l_i^T W / d_i    1/d_i ]      d_i^2 = a_ii - |l_i|^2,
+//
+// so g = ( -(W^T l_i)/d_i , 1/d_i ), psi = d_i^2 (the Schur complement of eq. diagScal2's
+// denominator; eq. DensSys with the scaling of eq. diagScal).  A new position u with row
+// a_u = A[P_o,u] extends W by the row ( -(W^T l_u)/d_u , 1/d_u ) with l_u = W a_u and
+// d_u^2 = a_uu - |l_u|^2 (bordering).  Both products are dense triangular matrix-vector
+// products over all lanes at once, with W in LDS (row-major packed: the entries one lane
+// reads for a fixed row or a fixed column fall in distinct banks) and the vector entries read
+// as LDS broadcasts; no step waits on the previous one, unlike a forward substitution.  l_i
+// grows by one entry per new row (a dot product of the new W row with a_i), and psi by one
+// subtraction, so row i needs no product of its own.
+//
+// Rows per wavefront: GS lanes own one row (lane t = pattern position t), 64 / GS rows share a
+// wavefront, each group with its own LDS table, factor and vectors; reductions stay inside a
+// group (DPP quad and mirror moves, a swizzle across 16 lanes, readlane across 32).  Control
+// flow is uniform inside a group; groups of a wavefront run their growth steps together.
+//
+// Per growth step of a row:
+//  1. product over the member rows r of P (their entries left of column i, looked up in the
+//     row's LDS hash table once, when r joined; the slots are kept in registers): every
+//     non-member column c accumulates v_c += a_rc g_r = (A g)_c, the Kaporin gradient of eq.
+//     grapsi up to a positive factor (LDS FP64 atomics);
+//  2. selection over the compact list of table entries: s rounds of "largest |v|, ties within
+//     the relative band tau go to the smallest column" (candidates with |v| <= 2^-40 max|v|
+//     are not eligible; none eligible stops the row);
+//  3. gather of the new rows (their entries up to column i): entries at member columns give
+//     a_u, the entry at column i gives a_iu, entries left of i are entered in the table;
+//  4. the new rows of W (blocks of NB: both products for the block at once, then the small
+//     coupling inside the block row by row), l_i's new entries and psi;
+//  5. g = -(W^T l_i)/d_i, the exit test psi/psi_0 <= eps (eq. exit_crit).
+#pragma once
+
+#include "common.hpp"
+#include "rows.hpp"
+
+#pragma clang fp contract(off)
+
+namespace afsai {
+namespace wform {
+
+constexpr uint32_t kEmptyKey = 0xFFFFFFFFu;
+constexpr uint32_t kMember = 0x80000000u;  // key bit 31: column is a member; bits 24..30: its position
+constexpr uint32_t kColBits = 0x00FFFFFFu;
+// member rows whose entries one product round loads together (16 loads per lane)
+__host__ __device__ constexpr int qb_of(int gs) { return 4; }
+constexpr int kPU = 8;  // unrolling of the two products with W
+
+__host__ __device__ constexpr int tri_w(int t) { return (t * (t + 1)) / 2; }
+__host__ __device__ constexpr int al16(int b) { return (b + 15) & ~15; }
+
+// slots per lane per member row (two 16-bit slots per register): GS * SPW entries left of
+// column i per member row at most
+__host__ __device__ constexpr int spw_of(int gs) { return gs == 64 ? 2 : (gs == 8 ? 2 : 4); }
+
+// LDS layout of one row group (bytes): table keys; gradients, whose array also holds, from
+// the end of the selection to the next product pass, the selected columns with their row
+// extents (at its end) and the gathered rows and W-product vectors (from its start, unless
+// they do not fit beside the former); the member records of the product pass (groups of
+// fewer than 64 lanes; 64 lanes broadcast them from registers); and W, sized at launch by the
+// largest pattern: rows 0..mm-2, row t with t + 1 entries.
+template <int GS, int MMAX, int CAP, int NB>
+struct Layout {
+    static constexpr int SPW = spw_of(GS);
+    static constexpr int LROW = GS * SPW;
+    static constexpr int ALV = (2 * NB + 1) * MMAX + NB;          // NR, LV (with LI), NAI in doubles
+    static constexpr bool ALIAS = ALV * 8 + 12 * MMAX <= CAP * 8;  // beside the selected columns
+    static constexpr int O_HKEY = 0;
+    static constexpr int O_HVAL = al16(CAP * 4);
+    static constexpr int O_SEL = O_HVAL + CAP * 8 - 12 * MMAX;    // sel, row start, row end [MMAX]
+    static constexpr int O_MS = O_HVAL + CAP * 8;                 // Memb[MMAX] (GS < 64)
+    static constexpr int O_AL = O_MS + (GS < 64 ? MMAX * 16 : 0);
+    static constexpr int FIXED = al16(O_AL + (ALIAS ? 0 : ALV * 8));
+    static __host__ __device__ constexpr int w_entries(int mm) { return mm > 1 ? (mm - 1) * mm / 2 : 0; }
+    static __host__ __device__ constexpr int bytes(int mm) { return FIXED + al16(w_entries(mm) * 8); }
+};
+
+struct Memb {
+    int32_t beg, len;  // row start, entries left of column i
+    double g;          // value of g at the member's position
+};
+
+// ---- moves and group reductions -------------------------------------------------------
+template <int CTRL>
+__device__ __forceinline__ int dmov(int v) {
+    return __builtin_amdgcn_update_dpp(v, v, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL>
+__device__ __forceinline__ double dmov(double v) {
+    const int lo = dmov<CTRL>(__double2loint(v)), hi = dmov<CTRL>(__double2hiint(v));
+    return __hiloint2double(hi, lo);
+}
+template <int CTRL>
+__device__ __forceinline__ uint32_t dmov(uint32_t v) { return (uint32_t)dmov<CTRL>((int)v); }
+// lane ^ 16 inside each half of the wavefront (ds_swizzle bit mode: and 0x1F, xor 0x10)
+__device__ __forceinline__ int xor16(int v) { return __builtin_amdgcn_ds_swizzle(v, 0x401F); }
+__device__ __forceinline__ uint32_t xor16(uint32_t v) { return (uint32_t)xor16((int)v); }
+__device__ __forceinline__ double xor16(double v) {
+    const int lo = xor16(__double2loint(v)), hi = xor16(__double2hiint(v));
+    return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ int rlane(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
+__device__ __forceinline__ uint32_t rlane(uint32_t v, int l) { return (uint32_t)__builtin_amdgcn_readlane((int)v, l); }
+__device__ __forceinline__ double rlane(double v, int l) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+    return __hiloint2double(hi, lo);
+}
+
+struct OpSum {
+    __device__ static double f(double a, double b) { return a + b; }
+};
+struct OpMax {
+    __device__ static double f(double a, double b) { return fmax(a, b); }
+};
+struct OpMinU {
+    __device__ static uint32_t f(uint32_t a, uint32_t b) { return a < b ? a : b; }
+};
+
+// All-reduce over each group of GS lanes; every lane of the group gets the result.  The
+// pairing is symmetric at every stage, so all lanes hold the same bits (sums too).
+template <int GS, class Op, class T>
+__device__ __forceinline__ T gred(T v) {
+    v = Op::f(v, dmov<0xB1>(v));   // quad_perm [1,0,3,2]: lane ^ 1
+    v = Op::f(v, dmov<0x4E>(v));   // quad_perm [2,3,0,1]: lane ^ 2
+    v = Op::f(v, dmov<0x141>(v));  // row_half_mirror: quads of one 8-lane half
+    if constexpr (GS >= 16) v = Op::f(v, dmov<0x140>(v));  // row_mirror: the two halves of a row
+    if constexpr (GS >= 32) v = Op::f(v, xor16(v));         // rows 0/1 and 2/3
+    if constexpr (GS == 64) v = Op::f(rlane(v, 0), rlane(v, 32));
+    return v;
+}
+
+// 1/sqrt(x) for x > 0: the hardware estimate refined by two Newton steps
+// (y <- y + y (1 - x y^2) / 2), well within the parity tolerance of G
+__device__ __forceinline__ double rsqrt_nr(double x) {
+    double y = __builtin_amdgcn_rsq(x);
+#pragma unroll
+    for (int it = 0; it < 2; ++it) {
+        const double e = fma(-x * y, y, 1.0);
+        y = fma(0.5 * y, e, y);
+    }
+    return y;
+}
+
+// Orders LDS accesses across the lanes of the block's one wavefront: a wavefront's LDS
+// instructions execute in issue order, so only the compiler must keep memory accesses on their
+// side of this point (no wait for global loads still in flight).
+__device__ __forceinline__ void wsync() {
+    __builtin_amdgcn_wave_barrier();
+    __asm__ __volatile__("" ::: "memory");
+}
+
+// Finds column c (< 2^24) in the table, inserting it when absent; returns the slot or -1 when
+// the table is full; `fresh` tells whether this call inserted it, `key` is the stored key.
+// Slots form buckets of four keys read with one 16-byte load; a column lives in the first
+// bucket from its hash on that has room (buckets in order), so most lookups take one read.
+// Within one call of the lanes of a group the columns are distinct, so a failed claim of an
+// empty slot means another column took it: the bucket is read again.
+template <int CAP>
+__device__ __forceinline__ int tfind(uint32_t *hkey, uint32_t c, bool &fresh, uint32_t &key) {
+    constexpr int NBK = CAP / 4;
+    constexpr int B = __builtin_ctz(NBK);
+    uint32_t b = (c * 2654435761u) >> (32 - B);
+    for (int probe = 0; probe < NBK;) {
+        const uint4 k4 = *reinterpret_cast<const uint4 *>(&hkey[4 * b]);
+        const uint32_t kk[4] = {k4.x, k4.y, k4.z, k4.w};
+        int empty = -1;
+#pragma unroll
+        for (int e = 3; e >= 0; --e) {
+            if (kk[e] == kEmptyKey) {
+                empty = e;
+            } else if ((kk[e] & kColBits) == c) {
+                key = kk[e];
+                return (int)(4 * b + e);
+            }
+        }
+        if (empty < 0) {
+            b = (b + 1) & (NBK - 1);
+            ++probe;
+            continue;
+        }
+        const uint32_t old = atomicCAS(&hkey[4 * b + empty], kEmptyKey, c);
+        if (old == kEmptyKey) {
+            fresh = true;
+            key = c;
+            return (int)(4 * b + empty);
+        }
+    }
+    return -1;
+}
+
+template <int GS>
+__device__ __forceinline__ uint64_t group_bits(int grp) {
+    if constexpr (GS == 64) return ~0ull;
+    else return ((1ull << GS) - 1ull) << (grp * GS);
+}
+// number of set bits of m below this lane
+__device__ __forceinline__ int bits_below(uint64_t m) {
+    return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+template <int GS, int MMAX, int CAP, int NB>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(GS == 8 ? 4 : (CAP <= 512 && MMAX <= 48 ? 3 : 1), 8))) void k_rows_w(
+    int n, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci, const double *__restrict__ av,
+    const double *__restrict__ diag, const int32_t *__restrict__ dlo, int kmax, int s, double eps, double tau,
+    int /*gmax*/, const int32_t *__restrict__ list, int nlist, int32_t *__restrict__ counters, int nxcd, int claim,
+    int32_t *__restrict__ ell_col, double *__restrict__ ell_val, int ldell, int32_t *__restrict__ m_out,
+    double *__restrict__ psi_out, int32_t *__restrict__ steps_out, int32_t *__restrict__ reason_out,
+    int8_t *__restrict__ status_out, int32_t *__restrict__ ovf_count, int32_t *__restrict__ ovf_list) {
+    using LY = Layout<GS, MMAX, CAP, NB>;
+    static_assert(MMAX <= GS && MMAX <= 64, "one lane per pattern position");
+    static_assert(CAP <= 65536, "16-bit slots");
+    constexpr int RPW = 64 / GS;
+    constexpr int SPW = LY::SPW;
+    constexpr int SLW = SPW / 2;
+    constexpr int SPL = CAP / GS;                 // table slots per lane
+    static_assert(12 * MMAX <= CAP * 8, "the selected columns fit in the gradient array");
+    constexpr int HMAX = (128 + GS - 1) / GS;     // chunks of a gathered row (rows <= 128 entries)
+    constexpr int PF = HMAX < 4 ? HMAX : 4;       // chunks loaded ahead for every gathered row
+    constexpr int QB = qb_of(GS);
+
+    extern __shared__ __align__(16) unsigned char lds_w[];
+    __shared__ int32_t s_row;
+    const int lane = threadIdx.x;
+    const int gl = lane & (GS - 1), grp = lane / GS;
+    const int mmx = kmax > 0 ? 1 + kmax * s : 1;  // largest pattern
+    unsigned char *gbase = lds_w + grp * LY::bytes(mmx);
+    uint32_t *hkey = reinterpret_cast<uint32_t *>(gbase + LY::O_HKEY);
+    double *hval = reinterpret_cast<double *>(gbase + LY::O_HVAL);
+    double *Wm = reinterpret_cast<double *>(gbase + LY::FIXED);
+    Memb *memb = reinterpret_cast<Memb *>(gbase + LY::O_MS);
+    int32_t *sel = reinterpret_cast<int32_t *>(gbase + LY::O_SEL);  // [MMAX] selected columns
+    int32_t *selb = sel + MMAX;                                     // [MMAX] their row starts
+    int32_t *sele = selb + MMAX;                                    // [MMAX] their row ends
+    double *NR = LY::ALIAS ? hval : reinterpret_cast<double *>(gbase + LY::O_AL);  // [NB][MMAX]
+    double *LV = NR + NB * MMAX;                                                   // [NB+1][MMAX]
+    double *NAI = LV + (NB + 1) * MMAX;                                            // [NB]: a_{u,i}
+    const uint64_t gm = group_bits<GS>(grp);
+    const double tauv = tau;
+
+    const int x = blockIdx.x % nxcd;
+    const int64_t per = ((int64_t)nlist + nxcd - 1) / nxcd;
+    const int q0 = (int)min<int64_t>(nlist, per * x), q1 = (int)min<int64_t>(nlist, per * (x + 1));
+    const int take = claim * RPW;
+
+    int qn = 0, qe = 0;
+    for (;;) {
+        if (qn >= qe) {
+            if (lane == 0) s_row = q0 + atomicAdd(&counters[x], take);
+            __syncthreads();
+            qn = s_row;
+            __syncthreads();
+            if (qn >= q1) break;
+            qe = min(qn + take, q1);
+        }
+        const int qi = qn + grp;
+        qn += RPW;
+        const bool have = qi < qe;
+        const int i = have ? (list ? list[qi] : qi) : 0;
+
+        // ---- row state (uniform inside the group) and per-position registers
+        int8_t status = ROW_OK;
+        int32_t reason = STOP_KMAX;
+        int steps = 0, m_o = 0;
+        double aii = 1.0;
+        int ibeg = 0, ilen = 0;
+        if (have) {
+            aii = diag[i];
+            ibeg = rp[i];
+            ilen = dlo[i];
+        }
+        bool act = have;
+        if (act && (!(aii > 0.0) || !isfinite(aii))) {
+            status = ROW_NOT_SPD;
+            act = false;
+        }
+        double psi = aii;
+        const double psi0 = aii;
+        double gi = act ? 1.0 / sqrt(aii) : 0.0;
+        int r_col = 0, r_beg = 0, r_len = 0;
+        double r_g = 0.0, r_ai = 0.0, r_li = 0.0;
+        uint32_t slr[MMAX][SLW];
+#pragma unroll
+        for (int q = 0; q < MMAX; ++q)
+#pragma unroll
+            for (int w = 0; w < SLW; ++w) slr[q][w] = 0u;
+
+        for (int j = gl; j < CAP; j += GS) hkey[j] = kEmptyKey;
+        wsync();
+        if (act && kmax > 0) {
+            if (ilen > LY::LROW) {
+                status = ROW_OVERFLOW;
+                act = false;
+            }
+        }
+        if (act && kmax > 0) {
+            // row i's entries left of the diagonal: the first candidates
+            bool bad = false;
+#pragma unroll
+            for (int h = 0; h < SPW; ++h) {
+                const int o = gl + GS * h;
+                if (o < ilen) {
+                    bool fresh = false;
+                    uint32_t kf;
+                    const int slot = tfind<CAP>(hkey, (uint32_t)ci[ibeg + o], fresh, kf);
+                    if (slot < 0) bad = true;
+                    else slr[0][h >> 1] |= (uint32_t)slot << (16 * (h & 1));
+                }
+            }
+            if (__ballot(bad) & gm) {
+                status = ROW_OVERFLOW;
+                act = false;
+            }
+        }
+
+        for (int k = 1; k <= kmax; ++k) {
+            if (!__ballot(act)) break;
+
+            // ---- 1. product pass
+            if (act) {
+#pragma unroll
+                for (int jj = 0; jj < SPL; ++jj) hval[gl + GS * jj] = 0.0;
+                if constexpr (GS < 64) {
+                    if (gl == 0) memb[0] = Memb{ibeg, ilen, gi};
+                    if (gl < m_o) memb[gl + 1] = Memb{r_beg, r_len, r_g};
+                }
+            }
+            wsync();
+            if (act) {
+#pragma unroll
+                for (int qb = 0; qb < MMAX; qb += QB) {
+                    if (qb <= m_o) {
+                        int slt[QB][SPW];
+                        double aa[QB][SPW], gg[QB];
+#pragma unroll
+                        for (int u = 0; u < QB; ++u) {
+                            const int q = qb + u;
+                            int beg = 0, len = 0;
+                            gg[u] = 0.0;
+                            if (q < MMAX && q <= m_o) {
+                                if constexpr (GS == 64) {
+                                    // member q: row i (q = 0) or position q - 1, uniform values
+                                    if (q == 0) {
+                                        beg = ibeg;
+                                        len = ilen;
+                                        gg[u] = gi;
+                                    } else {
+                                        beg = rlane(r_beg, q - 1);
+                                        len = rlane(r_len, q - 1);
+                                        gg[u] = rlane(r_g, q - 1);
+                                    }
+                                } else {
+                                    const Memb mb = memb[q];
+                                    beg = mb.beg;
+                                    len = mb.len;
+                                    gg[u] = mb.g;
+                                }
+                            }
+#pragma unroll
+                            for (int h = 0; h < SPW; ++h) {
+                                const int o = gl + GS * h;
+                                slt[u][h] = -1;
+                                aa[u][h] = 0.0;
+                                if (q < MMAX && o < len) {
+                                    slt[u][h] = (int)((slr[q < MMAX ? q : 0][h >> 1] >> (16 * (h & 1))) & 0xffffu);
+                                    aa[u][h] = av[beg + o];  // cached: rows are read again at later steps
+                                }
+                            }
+                        }
+#pragma unroll
+                        for (int u = 0; u < QB; ++u)
+#pragma unroll
+                            for (int h = 0; h < SPW; ++h)
+                                if (slt[u][h] >= 0)
+                                    __hip_atomic_fetch_add(&hval[slt[u][h]], aa[u][h] * gg[u], __ATOMIC_RELAXED,
+                                                           __HIP_MEMORY_SCOPE_WORKGROUP);
+                    }
+                }
+            }
+            wsync();
+
+            // ---- 2. selection: the table is scanned from LDS in every pass; a pass of round r
+            //         finds the smallest column in the band of the current maximum and each
+            //         lane's two largest eligible values (the next round's maximum without a
+            //         pass of its own: only the round's one winner leaves)
+            int ns = 0;
+            int r_js = 0, r_nb = 0, r_ne = 0;  // lane v: v-th column selected in this step, its row extents
+            if (act) {
+                double lm = -1.0;
+#pragma unroll 4
+                for (int jj = 0; jj < SPL; ++jj) {
+                    const int e = gl + GS * jj;
+                    const uint32_t kk = hkey[e];
+                    const double a = fabs(hval[e]);
+                    if (kk != kEmptyKey && !(kk & kMember)) lm = fmax(lm, a);
+                }
+                const double M = gred<GS, OpMax>(lm);
+                if (M > 0.0) {
+                    const double thr = 0x1.0p-40 * M;
+                    double Mp = M;
+                    for (int round = 0; round < s; ++round) {
+                        if (!(Mp > 0.0)) break;
+                        const double band = (1.0 - tauv) * Mp;
+                        uint32_t lb = kEmptyKey;
+                        int le = -1;
+                        double t1 = 0.0, t2 = 0.0;  // two largest eligible values of this lane
+                        uint32_t k1 = kEmptyKey;
+#pragma unroll 4
+                        for (int jj = 0; jj < SPL; ++jj) {
+                            const int e = gl + GS * jj;
+                            const uint32_t kk = hkey[e];
+                            const double a = fabs(hval[e]);
+                            if (kk != kEmptyKey && !(kk & kMember) && a > thr) {
+                                if (a >= band && kk < lb) {
+                                    lb = kk;
+                                    le = e;
+                                }
+                                if (a > t1) {
+                                    t2 = t1;
+                                    t1 = a;
+                                    k1 = kk;
+                                } else if (a > t2) {
+                                    t2 = a;
+                                }
+                            }
+                        }
+                        const uint32_t js = gred<GS, OpMinU>(lb);
+                        if (lb == js && le >= 0) hkey[le] = js | kMember | ((uint32_t)(m_o + ns) << 24);
+                        // the new row's extents, loaded while the next rounds run
+                        if (gl == ns) {
+                            r_js = (int)js;
+                            r_nb = rp[js];
+                            r_ne = rp[js + 1];
+                        }
+                        ++ns;
+                        Mp = gred<GS, OpMax>(k1 == js ? t2 : t1);
+                    }
+                }
+                if (ns == 0) {
+                    reason = STOP_NOCAND;
+                    act = false;
+                }
+            }
+            wsync();
+            // the selected columns into the gradient array's end (no longer read this step)
+            if (act && gl < ns) {
+                sel[gl] = r_js;
+                selb[gl] = r_nb;
+                sele[gl] = r_ne;
+            }
+            wsync();
+
+            // ---- 3./4. gather the new rows and extend W, NB rows at a time
+            bool spd = true;
+            double yi = 0.0;  // lane j: (W^T l_i)_j, accumulated over the blocks of this step
+            int nsd = 0;
+            bool first = true;
+            const int nsw = GS == 64 ? ns : (int)gred<64, OpMax>((double)(act ? ns : 0));
+            for (int nw = 0; nw < nsw; nw += NB) {
+                // old positions of this block (earlier blocks of the step included)
+                const int mwb = GS == 64 ? m_o : (int)gred<64, OpMax>((double)(act ? m_o : 0));
+                const bool blk = act && nsd < ns;
+                const int nbk = blk ? min(NB, ns - nsd) : 0;
+                if (blk) {
+                    for (int j = gl; j < NB * MMAX; j += GS) NR[j] = 0.0;
+                    if (gl < NB) NAI[gl] = 0.0;
+                }
+                wsync();
+                bool bad = false;
+                if (blk) {
+                    int gnb[NB], glen[NB];
+                    int gc[NB][PF];
+                    double ga[NB][PF];
+#pragma unroll
+                    for (int v = 0; v < NB; ++v) {
+                        gnb[v] = 0;
+                        glen[v] = 0;
+                        if (v < nbk) {
+                            gnb[v] = selb[nsd + v];
+                            glen[v] = sele[nsd + v] - gnb[v];
+                        }
+                        if (glen[v] > 128) bad = true;
+#pragma unroll
+                        for (int h = 0; h < PF; ++h) {
+                            const int o = gl + GS * h;
+                            gc[v][h] = 0x7fffffff;
+                            ga[v][h] = 0.0;
+                            if (o < glen[v] && o < 128) {
+                                gc[v][h] = ci[gnb[v] + o];
+                                ga[v][h] = av[gnb[v] + o];
+                            }
+                        }
+                    }
+#pragma unroll
+                    for (int v = 0; v < NB; ++v) {
+                        if (v < nbk && !bad) {
+                            const int p = m_o + v;  // position of this new row
+                            int nlo = 0;
+                            uint32_t pk[SLW];
+#pragma unroll
+                            for (int w = 0; w < SLW; ++w) pk[w] = 0u;
+#pragma unroll
+                            for (int h = 0; h < HMAX; ++h) {
+                                if (GS * h < glen[v]) {
+                                    const int o = gl + GS * h;
+                                    int c = 0x7fffffff;
+                                    double a = 0.0;
+                                    if (h < PF) {
+                                        c = gc[v][h < PF ? h : 0];
+                                        a = ga[v][h < PF ? h : 0];
+                                    } else if (o < glen[v]) {
+                                        c = ci[gnb[v] + o];
+                                        a = av[gnb[v] + o];
+                                    }
+                                    if (c == i) NAI[v] = a;
+                                    bool fresh = false;
+                                    int slot = -1;
+                                    if (c < i) {
+                                        if (o >= LY::LROW) {
+                                            bad = true;
+                                        } else {
+                                            uint32_t kf = 0u;
+                                            slot = tfind<CAP>(hkey, (uint32_t)c, fresh, kf);
+                                            if (slot < 0) {
+                                                bad = true;
+                                            } else {
+                                                if (h < SPW) pk[(h < SPW ? h : 0) >> 1] |= (uint32_t)slot << (16 * (h & 1));
+                                                if (kf & kMember) NR[v * MMAX + (int)((kf >> 24) & 0x7Fu)] = a;
+                                            }
+                                        }
+                                    }
+                                    nlo += __popcll(__ballot(c < i) & gm);
+                                    // the columns up to i form a prefix of the row
+                                    if ((__ballot(c <= i) & gm) != gm) break;
+                                }
+                            }
+                            if (gl == p) {
+                                r_beg = gnb[v];
+                                r_len = nlo;
+                                r_col = sel[nsd + v];
+                            }
+                            const int qm = p + 1;  // member index of position p
+#pragma unroll
+                            for (int q8 = 0; q8 < MMAX; q8 += 8) {
+                                if (qm >= q8 && qm < q8 + 8) {
+#pragma unroll
+                                    for (int qq = q8; qq < q8 + 8 && qq < MMAX; ++qq)
+                                        if (qq == qm)
+#pragma unroll
+                                            for (int w = 0; w < SLW; ++w) slr[qq][w] = pk[w];
+                                }
+                            }
+                        }
+                    }
+                }
+                if (__ballot(bad) & gm) {
+                    if (blk) {
+                        status = ROW_OVERFLOW;
+                        act = false;
+                    }
+                }
+                wsync();
+                const bool go = blk && act;
+                // a_{u,i} of the new positions
+                if (go && gl >= m_o && gl < m_o + nbk) r_ai = NAI[gl - m_o];
+
+                // pass A: l_v[t] = sum_{j <= t} W[t][j] a_v[j] for the old positions t < m_o
+                double la[NB];
+#pragma unroll
+                for (int v = 0; v < NB; ++v) la[v] = 0.0;
+                {
+                    // kPU entries of the row at a time, loads first (entries right of the
+                    // diagonal, and every entry of lanes without an old position, read as 0)
+                    const int lim = (go && gl < m_o) ? gl : -1;
+                    const double *wrow = Wm + tri_w(gl < MMAX - 1 ? gl : 0);
+                    for (int j0 = 0; j0 < mwb; j0 += kPU) {
+                        double wv[kPU];
+#pragma unroll
+                        for (int u = 0; u < kPU; ++u) {
+                            const int j = j0 + u;
+                            const double w = wrow[j <= lim ? j : 0];
+                            wv[u] = j <= lim ? w : 0.0;
+                        }
+#pragma unroll
+                        for (int v = 0; v < NB; ++v)
+                            if (v < nbk)
+#pragma unroll
+                                for (int u = 0; u < kPU; ++u) la[v] = fma(wv[u], NR[v * MMAX + j0 + u], la[v]);
+                    }
+                }
+                if (go && gl < MMAX) {
+                    // every entry of the rows (zeros past the old positions) for pass B's
+                    // unrolled reads
+#pragma unroll
+                    for (int v = 0; v < NB; ++v) LV[v * MMAX + gl] = gl < m_o ? la[v] : 0.0;
+                    LV[NB * MMAX + gl] = (first && gl < m_o) ? r_li : 0.0;
+                }
+                wsync();
+                // pass B: y_v[j] = sum_{j <= t < m_o} W[t][j] l_v[t], and the same with l_i
+                double yb[NB];
+#pragma unroll
+                for (int v = 0; v < NB; ++v) yb[v] = 0.0;
+                {
+                    const int lo = (go && gl < m_o) ? gl : 0x7fffffff;
+                    for (int t0 = 0; t0 < mwb; t0 += kPU) {
+                        double wv[kPU];
+#pragma unroll
+                        for (int u = 0; u < kPU; ++u) {
+                            const int t = t0 + u;
+                            const bool on = t >= lo && t < m_o;
+                            const double w = Wm[on ? tri_w(t) + gl : 0];
+                            wv[u] = on ? w : 0.0;
+                        }
+#pragma unroll
+                        for (int v = 0; v < NB; ++v)
+                            if (v < nbk)
+#pragma unroll
+                                for (int u = 0; u < kPU; ++u) yb[v] = fma(wv[u], LV[v * MMAX + t0 + u], yb[v]);
+#pragma unroll
+                        for (int u = 0; u < kPU; ++u) yi = fma(wv[u], LV[NB * MMAX + t0 + u], yi);
+                    }
+                }
+                // the new rows one by one: their coupling inside the block, d_u, and row p of W
+                double wn[NB];
+#pragma unroll
+                for (int v = 0; v < NB; ++v) wn[v] = 0.0;
+                if (go) {
+#pragma unroll
+                    for (int v = 0; v < NB; ++v) {
+                        if (v < nbk && spd) {
+                            const int p = m_o + v;
+                            const double sq = gred<GS, OpSum>(gl < m_o ? la[v] * la[v] : 0.0);
+                            double d2 = NR[v * MMAX + p] - sq;
+                            const double av_l = gl < MMAX ? NR[v * MMAX + (gl < MMAX ? gl : 0)] : 0.0;
+                            double cp[NB];
+#pragma unroll
+                            for (int w = 0; w < NB; ++w) {
+                                cp[w] = 0.0;
+                                if (w < v) {
+                                    cp[w] = gred<GS, OpSum>(wn[w] * av_l);
+                                    d2 = d2 - cp[w] * cp[w];
+                                }
+                            }
+                            if (!(d2 > 0.0) || !isfinite(d2)) {
+                                spd = false;
+                            } else {
+                                const double dinv = rsqrt_nr(d2);
+                                double y = yb[v];
+#pragma unroll
+                                for (int w = 0; w < NB; ++w)
+                                    if (w < v) y = fma(wn[w], cp[w], y);
+                                wn[v] = gl < p ? -(y * dinv) : (gl == p ? dinv : 0.0);
+                                if (gl <= p) Wm[tri_w(p) + gl] = wn[v];
+                            }
+                        }
+                    }
+                    if (spd) {
+                        // l_i at the new positions and psi
+#pragma unroll
+                        for (int w = 0; w < NB; ++w) {
+                            if (w < nbk) {
+                                const double li = gred<GS, OpSum>(wn[w] * r_ai);
+                                if (gl == m_o + w) r_li = li;
+                                psi = psi - li * li;
+                                yi = fma(wn[w], li, yi);
+                            }
+                        }
+                    } else {
+                        status = ROW_NOT_SPD;
+                        act = false;
+                    }
+                }
+                if (blk) {
+                    m_o += nbk;
+                    nsd += nbk;
+                    first = false;
+                }
+                wsync();
+            }
+
+            // ---- 5. g, psi and the exit test
+            if (act) {
+                if (!(psi > 0.0) || !isfinite(psi)) {
+                    status = ROW_NOT_SPD;
+                    act = false;
+                } else {
+                    const double dinv = rsqrt_nr(psi);
+                    gi = dinv;
+                    r_g = gl < m_o ? -(yi * dinv) : 0.0;
+                    steps = k;
+                    if (psi <= eps * psi0) {
+                        reason = STOP_EPS;
+                        act = false;
+                    }
+                }
+            }
+        }
+
+        // ---- outputs: the row with ascending columns (i, the largest, last)
+        if (have && status == ROW_OK) {
+            const int col = gl < m_o ? r_col : (gl == m_o ? i : 0x7fffffff);
+            if (gl <= m_o) sel[gl] = col;
+            wsync();
+            int rank = 0;
+            for (int t = 0; t <= m_o; ++t) rank += (sel[t] < col) ? 1 : 0;
+            if (gl <= m_o) {
+                ell_col[(size_t)i * ldell + rank] = col;
+                ell_val[(size_t)i * ldell + rank] = gl < m_o ? r_g : gi;
+            }
+        } else {
+            wsync();
+        }
+        if (have && gl == 0) {
+            m_out[i] = (status == ROW_OK) ? m_o + 1 : 0;
+            psi_out[i] = psi;
+            steps_out[i] = steps;
+            reason_out[i] = reason;
+            status_out[i] = status;
+            if (status == ROW_OVERFLOW) {
+                const int pos = atomicAdd(ovf_count, 1);
+                ovf_list[pos] = i;
+            }
+        }
+        wsync();
+    }
+}
+
+}  // namespace wform
+
+// LDS bytes (dynamic) of one block of k_rows_w<GS, MMAX, CAP, NB> for patterns of at most mm
+// positions
+template <int GS, int MMAX, int CAP, int NB>
+__host__ constexpr size_t rows_w_lds_bytes(int mm) {
+    return (size_t)(64 / GS) * (size_t)wform::Layout<GS, MMAX, CAP, NB>::bytes(mm);
+}
+
+}  // namespace afsai

@@ -245,7 +245,7 @@ int afsai_set_option(int32_t opt, int64_t value) {
     bool ok = false;
     switch (opt) {
         case AFSAI_OPT_SETUP_GROUP: ok = (value >= 0 && value <= 4); break;
-        case AFSAI_OPT_SETUP_TABLE: ok = value == 0 || (pow2(value) && value >= 128 && value <= 1024); break;
+        case AFSAI_OPT_SETUP_TABLE: ok = value == 0 || (pow2(value) && value >= 64 && value <= 1024); break;
         case AFSAI_OPT_SPMV_GROUP: ok = value == 0 || (pow2(value) && value >= 4 && value <= 64); break;
         case AFSAI_OPT_SPMV_UNROLL: ok = value == 0 || (pow2(value) && value <= 8); break;
         case AFSAI_OPT_PCG_CSR_A: ok = (value == 0 || value == 1); break;
@@ -255,6 +255,7 @@ int afsai_set_option(int32_t opt, int64_t value) {
         case AFSAI_OPT_SETUP_SLOTS: ok = (value >= 0 && value <= 2); break;
         case AFSAI_OPT_SELL_TAIL: ok = (value == 0 || value == 1); break;
         case AFSAI_OPT_SELL_UNEVEN: ok = (value == 0 || value == 1); break;
+        case AFSAI_OPT_SETUP_FORM: ok = (value >= 0 && value <= 2); break;
         default: ok = false;
     }
     if (!ok) AFSAI_FAIL(AFSAI_ERR_INVALID_ARG, "afsai_set_option: bad option %d / value %lld", opt, (long long)value);

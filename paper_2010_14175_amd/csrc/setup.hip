@@ -327,19 +327,27 @@ __global__ void k_block_check(int n, const int32_t *__restrict__ rp, const int32
 // ---------------------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------------------
-// fused per-row kernels, instantiated in rows.hip
+// fused per-row kernels, instantiated in rows.hip (Cholesky form) and rows_w.hip (inverse-factor form)
 RowsKernel rows_kernel(int mmax_t, int cap, bool rsl, bool f32);
+RowsKernel rows_kernel_w(int mmax, int maxlen, int cap, int *gs_out, size_t *lds_out);
+RowsKernel rows_kernel_w_large(int mmax, int cap, size_t *lds_out);
 
-static int launch_rows(RowsKernel kern, int mmax_t, int mmax, int64_t row_work, int cap, bool rsl, int tb, int gmax, const afsai_csr *A, const double *diag,
+// Launch of a per-row kernel over `nlist` rows.  Inverse-factor form: wdyn > 0 is its dynamic
+// LDS per block and rpw its rows per wavefront; the Cholesky form sizes its LDS from the
+// pattern and table (wdyn = 0).
+static int launch_rows(RowsKernel kern, size_t wdyn, int rpw, int mmax_t, int mmax, int64_t row_work, int cap, bool rsl, int tb, int gmax, const afsai_csr *A, const double *diag,
                        const int32_t *dlo, const afsai_params *p, const int32_t *list, int nlist, int32_t *counters,
                        int ldell, int32_t *ell_col, double *ell_val, int32_t *m, double *psi, int32_t *steps,
                        int32_t *reason, int8_t *st, int32_t *ovf_count, int32_t *ovf_list, const DeviceInfo &di,
                        hipStream_t s) {
     // resident rows per CU: the runtime's occupancy for this kernel (registers and LDS, with
     // its dynamic LDS), else from the LDS bytes (512-byte granules)
-    const size_t lds = (rows_lds_bytes(mmax_t, mmax, cap, rsl, tb) + 511) / 512 * 512;
-    const size_t dyn = rows_lds_dyn_bytes(mmax, rsl, tb);
+    const size_t lds = ((wdyn ? wdyn + 16 : rows_lds_bytes(mmax_t, mmax, cap, rsl, tb)) + 511) / 512 * 512;
+    const size_t dyn = wdyn ? wdyn : rows_lds_dyn_bytes(mmax, rsl, tb);
     int per_cu = (int)((160 * 1024) / lds);
+    if (dyn > 48 * 1024)
+        AFSAI_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
+                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn));
     {
         int occ = 0;
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, reinterpret_cast<const void *>(kern), 64, dyn) ==
@@ -352,14 +360,15 @@ static int launch_rows(RowsKernel kern, int mmax_t, int mmax, int64_t row_work, 
     if (per_cu > 32) per_cu = 32;
     if (per_cu < 1) per_cu = 1;
     int64_t nb = (int64_t)di.num_cus * per_cu;
-    if (nb > nlist) nb = nlist;
+    if (nb > (nlist + rpw - 1) / rpw) nb = (nlist + rpw - 1) / rpw;
     const int nx = di.num_xcds;
     nb = ((nb + nx - 1) / nx) * nx;
     if (nb < nx) nb = nx;
     // rows per claim (one atomic on the XCD's counter each): enough rows for about 4,000 table
     // entries of work, 1..16, and at most a quarter of a resident row-slot's share (short tail)
-    int64_t claim64 = (4000 + row_work - 1) / std::max<int64_t>(1, row_work);
-    claim64 = std::min<int64_t>(claim64, std::max<int64_t>(1, nlist / (nb * 4)));
+    // (claims are counted in wavefronts' worth of rows: rpw rows each)
+    int64_t claim64 = (4000 + row_work * rpw - 1) / std::max<int64_t>(1, row_work * rpw);
+    claim64 = std::min<int64_t>(claim64, std::max<int64_t>(1, nlist / ((int64_t)rpw * nb * 4)));
     const int claim = (int)std::min<int64_t>(16, std::max<int64_t>(1, claim64));
     hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, (int64_t)nx, counters, 0);
     {
@@ -571,11 +580,41 @@ static int setup_core(const afsai_csr *A, const afsai_params *p, int nsys, const
     int32_t *ovf_count = ovf.as<int32_t>() + n;
     hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, (int64_t)1, ovf_count, 0);
 
-    RowsKernel k1 = rows_kernel(mmax_t, cap1, rsl, sf32);
+    // inverse-factor form where it applies (FP64 arithmetic, register slot lists), its first
+    // table from 64 slots; rows that overflow it are redone by the Cholesky form below
+    const int64_t form = option(AFSAI_OPT_SETUP_FORM);
+    RowsKernel k1 = nullptr;
+    size_t wdyn = 0;
+    int wrpw = 1;
+    if (form != 1 && !sf32 && rsl) {
+        int wcap = pow2ceil(bound / 4 + 1);
+        if (wcap < 64) wcap = 64;
+        if (wcap > 512) wcap = 512;
+        if (option(AFSAI_OPT_SETUP_TABLE) > 0) wcap = (int)std::max<int64_t>(64, std::min<int64_t>(1024, pow2ceil(option(AFSAI_OPT_SETUP_TABLE))));
+        int gs = 64;
+        k1 = rows_kernel_w(mmax, maxlen, wcap, &gs, &wdyn);
+        // automatic choice: patterns of 17..32 positions (two rows per wavefront of 32 lanes
+        // each) measured faster in the Cholesky form (786,432-row 27-point workload: 25.9
+        // against 31.9 ms), every other shape in the inverse-factor form
+        if (k1 && form == 0 && gs == 32) {
+            k1 = nullptr;
+            wdyn = 0;
+        }
+        if (k1) {
+            wrpw = 64 / gs;
+            cap1 = wcap;
+            if (cap2 < cap1) cap2 = cap1;
+        }
+    }
+    if (form == 2 && !k1)
+        AFSAI_FAIL(AFSAI_ERR_INVALID_ARG,
+                   "afsai_setup: the inverse-factor form needs FP64 setup arithmetic, rows of at most 128 entries "
+                   "and n <= 2^24");
+    if (!k1) k1 = rows_kernel(mmax_t, cap1, rsl, sf32);
     if (!k1) AFSAI_FAIL(AFSAI_ERR_TOO_LARGE, "afsai_setup: no kernel for pattern %d / table %d", mmax_t, cap1);
     // table entries one row touches over its steps (bound per step times k_max, plus its own row)
     const int64_t row_work = (int64_t)p->kmax * bound + maxlen;
-    if ((rc = launch_rows(k1, mmax_t, mmax, row_work, cap1, rsl, tb, gmax, A, diagb.as<double>(), dlob.as<int32_t>(), p, nullptr, n, ctr.as<int32_t>(), ldell,
+    if ((rc = launch_rows(k1, wdyn, wrpw, mmax_t, mmax, row_work, cap1, rsl, tb, gmax, A, diagb.as<double>(), dlob.as<int32_t>(), p, nullptr, n, ctr.as<int32_t>(), ldell,
                           ell_col.as<int32_t>(), ell_val.as<double>(), mcnt.as<int32_t>(), psi.as<double>(),
                           steps.as<int32_t>(), reason.as<int32_t>(), st.as<int8_t>(), ovf_count, ovf.as<int32_t>(), di,
                           s)))
@@ -592,9 +631,11 @@ static int setup_core(const afsai_csr *A, const afsai_params *p, int nsys, const
                            list2.as<int32_t>());
         int32_t *cnt2 = list2.as<int32_t>() + novf;
         hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, (int64_t)1, cnt2, 0);
-        RowsKernel k2 = rows_kernel(mmax_t, cap2, rsl, sf32);
+        // the same form as the first launch, with the larger table
+        size_t wdyn2 = 0;
+        RowsKernel k2 = wdyn ? rows_kernel_w_large(mmax, cap2, &wdyn2) : rows_kernel(mmax_t, cap2, rsl, sf32);
         if (!k2) AFSAI_FAIL(AFSAI_ERR_TOO_LARGE, "afsai_setup: no kernel for table %d", cap2);
-        if ((rc = launch_rows(k2, mmax_t, mmax, row_work, cap2, rsl, tb, gmax, A, diagb.as<double>(), dlob.as<int32_t>(), p, list2.as<int32_t>(), novf,
+        if ((rc = launch_rows(k2, wdyn2, 1, mmax_t, mmax, row_work, cap2, rsl, tb, gmax, A, diagb.as<double>(), dlob.as<int32_t>(), p, list2.as<int32_t>(), novf,
                               ctr.as<int32_t>(), ldell, ell_col.as<int32_t>(), ell_val.as<double>(), mcnt.as<int32_t>(),
                               psi.as<double>(), steps.as<int32_t>(), reason.as<int32_t>(), st.as<int8_t>(), cnt2,
                               ovf.as<int32_t>(), di, s)))

@@ -3,9 +3,11 @@
 Bars (from the method's arithmetic):
   * patterns of G: identical (the selection is an integer decision; both sides use the same
     tie band, so rounding noise in the gradient cannot flip it);
-  * values of G: within 1e-10 relative per row (infinity norm); the Cholesky factorisation
-    and solve follow the same rounding sequence as the oracle, so they are expected to agree
-    bit for bit and the fraction of bitwise-equal values is also checked;
+  * values of G: within 1e-10 relative per row (infinity norm), the independent bar.  The
+    default (inverse-factor) form rounds differently from the oracle's Cholesky factorisation
+    and meets only this bar; the Cholesky form (AFSAI_OPT_SETUP_FORM = 1) follows the oracle's
+    rounding sequence (growth order, reciprocal pivots), so where it is forced the fraction of
+    bitwise-equal values is checked too;
   * psi, steps and stop reasons per row: identical values / within 1e-12 relative;
   * PCG: the same iteration count and the solution within 1e-10 relative (FP64 G); with FP32
     storage of G: converged to the same rtol, iteration count within 2, and
@@ -50,11 +52,16 @@ def _gpu_factor(af, P):
     return rp.cpu().numpy(), ci.cpu().numpy(), va.cpu().numpy()
 
 
-def compare_factor(af, A, kmax, s, eps, g_prec=0, rows=None):
-    """Runs the GPU setup and the oracle; returns statistics; asserts the bars (vectorised over
-    the rows, so that every row of the full-size workloads is checked)."""
+def compare_factor(af, A, kmax, s, eps, g_prec=0, rows=None, form=0):
+    """Runs the GPU setup (form: 0 automatic, 1 Cholesky, 2 inverse factor) and the oracle;
+    returns statistics; asserts the bars (vectorised over the rows, so that every row of the
+    full-size workloads is checked)."""
     dA = _dev(af, A)
-    P = af.setup(dA, kmax, s, eps, g_prec=g_prec)
+    try:
+        af.set_option(af.OPT_SETUP_FORM, form)
+        P = af.setup(dA, kmax, s, eps, g_prec=g_prec)
+    finally:
+        af.set_option(af.OPT_SETUP_FORM, 0)
     rp, ci, va = _gpu_factor(af, P)
     psi, steps, reason = (t.cpu().numpy() for t in P.export_rows())
     info = P.info()
@@ -84,8 +91,10 @@ def compare_factor(af, A, kmax, s, eps, g_prec=0, rows=None):
         assert err.size == 0 or err[worst] <= G_RTOL, f"row {rows[worst]}: relative error {err[worst]:.3e}"
         nbit = int(np.sum((gvals.view(np.int64) == ov.view(np.int64)) & live))
     else:
-        badv = np.nonzero((gvals.astype(np.float32) != ov.astype(np.float32)).any(axis=1))[0]
-        assert badv.size == 0, f"row {rows[badv[0]]}: FP32 values differ from the oracle's rounded to FP32"
+        # FP32 storage: the stored value is the FP64 result rounded to FP32 (half an FP32 ulp,
+        # 2^-24 relative) of a value within rounding of the oracle's
+        badv = np.nonzero((np.abs(gvals - ov) > 2.0 ** -23 * np.abs(ov)).any(axis=1))[0]
+        assert badv.size == 0, f"row {rows[badv[0]]}: FP32 values beyond FP32 rounding of the oracle's"
         nbit = 0
     ntot = int(lens.sum())
     bads = np.nonzero((steps[rows] != R.steps) | (reason[rows] != R.reason))[0]
@@ -99,12 +108,14 @@ def compare_factor(af, A, kmax, s, eps, g_prec=0, rows=None):
 # --------------------------------------------------------------------------------------
 # setup parity
 # --------------------------------------------------------------------------------------
-def test_setup_poisson20(af):
+@pytest.mark.parametrize("form", [0, 1])
+def test_setup_poisson20(af, form):
     """20^3 7-point Laplacian, k_max = 5, s = 1, eps = 1e-2 (nnz(G) = 47,985 exactly)."""
     Pb = synth.poisson7(20)
-    r = compare_factor(af, Pb.A, 5, 1, 1e-2)
+    r = compare_factor(af, Pb.A, 5, 1, 1e-2, form=form)
     assert r["info"].nnz_g == 47985
-    assert r["bitwise"] == 1.0, r["bitwise"]
+    if form == 1:
+        assert r["bitwise"] == 1.0, r["bitwise"]
 
 
 @pytest.mark.parametrize("case", ["tridiag3_k1", "tridiag3_k2", "dense8_full", "diag", "one", "two",
@@ -145,25 +156,70 @@ def test_setup_small_cases(af, case):
         compare_factor(af, A, 5, 2, 1e-2)
 
 
-def test_setup_elasticity_reduced(af):
+@pytest.mark.parametrize("form", [0, 1])
+def test_setup_elasticity_reduced(af, form):
     """27-point 3-dof heterogeneous operator at 12^3 nodes (5,184 rows), k_max = 10, s = 2."""
     A = synth.elast27(12, 1.0, 2)
-    r = compare_factor(af, A, 10, 2, 1e-2)
-    assert r["bitwise"] > 0.999
+    r = compare_factor(af, A, 10, 2, 1e-2, form=form)
+    if form == 1:
+        assert r["bitwise"] > 0.999
 
 
-def test_setup_elasticity_24(af):
+@pytest.mark.parametrize("form", [0, 1])
+def test_setup_elasticity_24(af, form):
     """24^3 nodes (41,472 rows): the reduced form of the 64^3 workload, every row checked."""
     A = synth.elast27(24, 1.0, 2)
-    r = compare_factor(af, A, 10, 2, 1e-2)
-    assert r["bitwise"] > 0.999
+    r = compare_factor(af, A, 10, 2, 1e-2, form=form)
+    if form == 1:
+        assert r["bitwise"] > 0.999
 
 
-def test_setup_large_pattern(af):
+@pytest.mark.parametrize("form", [0, 1])
+def test_setup_large_pattern(af, form):
     """k_max = 15, s = 3 (46 entries per row, the 150^3 workload's parameters) on a small grid,
     sigma = 2."""
     A = synth.elast27(7, 2.0, 5)
-    compare_factor(af, A, 15, 3, 1e-2)
+    compare_factor(af, A, 15, 3, 1e-2, form=form)
+
+
+@pytest.mark.parametrize("make,kmax,s", [(lambda: synth.lap7(9, 8, 7), 5, 1), (lambda: synth.lap7(9, 8, 7), 7, 2),
+                                         (lambda: synth.elast27(6, 1.0, 2), 5, 3),
+                                         (lambda: synth.elast27(7, 2.0, 5), 10, 2),
+                                         (lambda: synth.elast27(6, 2.0, 5), 21, 3),
+                                         (lambda: synth.elast27(5, 1.0, 7), 9, 7)])
+def test_setup_inverse_factor_shapes(af, make, kmax, s):
+    """The inverse-factor form over its lane-group shapes (8, 16, 32 and 64 lanes per row) and
+    block sizes (s above the rows appended per block), against the oracle."""
+    A = make()
+    compare_factor(af, A, kmax, s, 1e-2, form=2)
+
+
+@pytest.mark.parametrize("make,kmax,s", [(lambda: synth.elast27(9, 1.0, 2), 10, 2), (lambda: synth.lap7(14), 5, 1),
+                                         (lambda: synth.elast27(6, 2.0, 5), 15, 3)])
+def test_setup_inverse_factor_table_sizes(af, make, kmax, s):
+    """The inverse-factor form's result does not depend on the table size (slots only rank
+    candidates; every table size gives the same G bit for bit) and agrees with the Cholesky
+    form to rounding."""
+    A = make()
+    dA = _dev(af, A)
+    outs = []
+    try:
+        af.set_option(af.OPT_SETUP_FORM, 2)
+        for cap in (0, 128, 256, 1024):
+            af.set_option(af.OPT_SETUP_TABLE, cap)
+            outs.append(_gpu_factor(af, af.setup(dA, kmax, s, 1e-2)))
+        af.set_option(af.OPT_SETUP_TABLE, 0)
+        af.set_option(af.OPT_SETUP_FORM, 1)
+        chol = _gpu_factor(af, af.setup(dA, kmax, s, 1e-2))
+    finally:
+        af.set_option(af.OPT_SETUP_FORM, 0)
+        af.set_option(af.OPT_SETUP_TABLE, 0)
+    for o in outs[1:]:
+        for a, b in zip(outs[0], o):
+            np.testing.assert_array_equal(a, b)
+    np.testing.assert_array_equal(outs[0][0], chol[0])
+    np.testing.assert_array_equal(outs[0][1], chol[1])
+    np.testing.assert_allclose(outs[0][2], chol[2], rtol=G_RTOL, atol=G_RTOL * np.abs(chol[2]).max())
 
 
 def test_setup_overflow_retry(af):
@@ -184,12 +240,13 @@ def test_setup_fp32_storage(af):
 @pytest.mark.parametrize("make,kmax,s", [(lambda: synth.elast27(10, 1.0, 6), 10, 2), (lambda: synth.lap7(16), 5, 1),
                                          (lambda: synth.elast27(6, 2.0, 5), 7, 4)])
 def test_setup_forms_identical(af, make, kmax, s):
-    """Appending one or two rows per factor update instead of up to four, and any first table
-    size, give G bit for bit identical."""
+    """Cholesky form: appending one or two rows per factor update instead of up to four, and
+    any first table size, give G bit for bit identical."""
     A = make()
     dA = _dev(af, A)
-    ref = _gpu_factor(af, af.setup(dA, kmax, s, 1e-2))
     try:
+        af.set_option(af.OPT_SETUP_FORM, 1)
+        ref = _gpu_factor(af, af.setup(dA, kmax, s, 1e-2))
         outs = []
         for g in (1, 2):
             af.set_option(af.OPT_SETUP_GROUP, g)
@@ -200,6 +257,7 @@ def test_setup_forms_identical(af, make, kmax, s):
     finally:
         af.set_option(af.OPT_SETUP_GROUP, 0)
         af.set_option(af.OPT_SETUP_TABLE, 0)
+        af.set_option(af.OPT_SETUP_FORM, 0)
     for o in outs:
         for a, b in zip(ref, o):
             np.testing.assert_array_equal(a, b)
@@ -211,17 +269,20 @@ def test_setup_forms_identical(af, make, kmax, s):
                                          (lambda: synth.elast27(7, 2.0, 5), 15, 3),
                                          (lambda: synth.elast27(6, 1.0, 3), 21, 3)])
 def test_setup_slot_lists(af, slots, make, kmax, s):
-    """The table slots of the pattern rows' entries kept in LDS (1) or in registers (2): both
-    give the oracle's patterns and values (bitwise here), and equal each other bit for bit."""
+    """Cholesky form: the table slots of the pattern rows' entries kept in LDS (1) or in
+    registers (2): both give the oracle's patterns and values (bitwise here), and equal each
+    other bit for bit."""
     A = make()
     try:
         af.set_option(af.OPT_SETUP_SLOTS, slots)
-        r = compare_factor(af, A, kmax, s, 1e-2)
+        r = compare_factor(af, A, kmax, s, 1e-2, form=1)
         other = 1 if slots == 2 else 2
         af.set_option(af.OPT_SETUP_SLOTS, other)
+        af.set_option(af.OPT_SETUP_FORM, 1)
         o = _gpu_factor(af, af.setup(r["dA"], kmax, s, 1e-2))
     finally:
         af.set_option(af.OPT_SETUP_SLOTS, 0)
+        af.set_option(af.OPT_SETUP_FORM, 0)
     assert r["bitwise"] > 0.999
     for a, b in zip(_gpu_factor(af, r["P"]), o):
         np.testing.assert_array_equal(a, b)
@@ -631,7 +692,6 @@ def test_full_size_elasticity64(af):
     oracle's PCG on the oracle's G: the same iteration count and x within 1e-10."""
     Pb = synth.elasticity27(64)
     r = compare_factor(af, Pb.A, 10, 2, 1e-2)
-    assert r["bitwise"] > 0.999
     dA, P = r["dA"], r["P"]
     x, info = af.pcg_solve(dA, P, _vec(Pb.b), rtol=1e-8)
     assert info.converged and info.true_relres <= 1.1e-8
@@ -644,8 +704,8 @@ def test_full_size_elasticity64(af):
 def test_full_size_elasticity150_sampled(af):
     """The largest configuration (150^3 nodes x 3 dof: 10,125,000 rows, 809,238,528 nonzeros,
     log-normal sigma = 2, k_max = 15, s = 3, patterns of up to 46 entries) with G stored in FP32:
-    3,000 sampled rows against the oracle (pattern identical, values equal after rounding the
-    oracle's to FP32), and the solve by its true residual."""
+    3,000 sampled rows against the oracle (pattern identical, values within FP32 rounding of
+    the oracle's), and the solve by its true residual."""
     import time
 
     t0 = time.time()
