@@ -381,6 +381,11 @@ const char *afsai_last_error(void);
  *                             form (AFSAI_ERR_INVALID_ARG from afsai_setup when it does not
  *                             apply).  Both forms compute the same G in exact arithmetic and
  *                             differ by rounding only
+ *   AFSAI_OPT_SETUP_LANES     inverse-factor form: lanes that own one row (8, 16, 32 or 64;
+ *                             64 / lanes rows per wavefront; 0 automatic: 8 or 16 when they hold
+ *                             the pattern, else 64; 32 only when asked for).  A request smaller
+ *                             than the pattern takes the next size that holds it.  Any choice
+ *                             gives identical G
  * Returns AFSAI_ERR_INVALID_ARG for an unknown option or value.  Not thread safe against
  * concurrent calls of the library.
  */
@@ -396,6 +401,7 @@ const char *afsai_last_error(void);
 #define AFSAI_OPT_SELL_TAIL 10
 #define AFSAI_OPT_SELL_UNEVEN 11
 #define AFSAI_OPT_SETUP_FORM 12
+#define AFSAI_OPT_SETUP_LANES 13
 int afsai_set_option(int32_t option, int64_t value);
 
 /*

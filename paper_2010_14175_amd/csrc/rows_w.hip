@@ -47,24 +47,27 @@ static RowsKernel w_cap_large(int cap, int mm, size_t *lds) {
 // row entries left of column i in their slot lists.  Returns nullptr when none fits (rows
 // longer than 128 entries, or no such table size); *gs_out and *lds_out (dynamic LDS bytes of
 // one block) are set on success.
-RowsKernel rows_kernel_w(int mmax, int maxlen, int cap, int *gs_out, size_t *lds_out) {
+RowsKernel rows_kernel_w(int mmax, int maxlen, int cap, int lanes, int *gs_out, size_t *lds_out) {
     if (maxlen > 128 || mmax > 64) return nullptr;
     RowsKernel k = nullptr;
     int gs = 0;
-    // the compact candidate list takes CAP / GS registers per lane in the selection: groups of
-    // 8 and 16 lanes only with small tables
-    if (mmax <= 8 && maxlen <= 8 * wform::spw_of(8) && cap <= 128) {
+    // groups of 8 and 16 lanes only with small tables (a selection pass visits CAP / GS slots
+    // per lane); `lanes` asks for at least that many lanes per row
+    if (lanes <= 8 && mmax <= 8 && maxlen <= 8 * wform::spw_of(8) && cap <= 128) {
         gs = 8;
         k = w_cap<8, 8, 1>(cap, mmax, lds_out);
-    } else if (mmax <= 16 && maxlen <= 16 * wform::spw_of(16) && cap <= 256) {
+    } else if (lanes <= 16 && mmax <= 16 && maxlen <= 16 * wform::spw_of(16) && cap <= 256) {
         gs = 16;
         k = w_cap<16, 16, 2>(cap, mmax, lds_out);
-    } else if (mmax <= 32 && cap >= 128) {
+    } else if (lanes == 32 && mmax <= 32 && cap >= 128) {
+        // two rows per wavefront of 32 lanes each: only when asked for (one row per wavefront
+        // of 64 lanes measured faster: more wavefronts resident)
         gs = 32;
         k = mmax <= 24 ? w_cap<32, 24, 2>(cap, mmax, lds_out) : w_cap<32, 32, 2>(cap, mmax, lds_out);
     } else if (cap >= 128) {
         gs = 64;
-        k = mmax <= 48 ? w_cap<64, 48, 4>(cap, mmax, lds_out) : w_cap<64, 64, 4>(cap, mmax, lds_out);
+        k = mmax <= 24 ? w_cap<64, 24, 2>(cap, mmax, lds_out)
+                       : (mmax <= 48 ? w_cap<64, 48, 4>(cap, mmax, lds_out) : w_cap<64, 64, 4>(cap, mmax, lds_out));
     }
     if (k) *gs_out = gs;
     return k;

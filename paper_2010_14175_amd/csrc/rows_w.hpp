@@ -76,7 +76,8 @@ struct Layout {
     static constexpr int O_AL = O_MS + (GS < 64 ? MMAX * 16 : 0);
     static constexpr int FIXED = al16(O_AL + (ALIAS ? 0 : ALV * 8));
     static __host__ __device__ constexpr int w_entries(int mm) { return mm > 1 ? (mm - 1) * mm / 2 : 0; }
-    static __host__ __device__ constexpr int bytes(int mm) { return FIXED + al16(w_entries(mm) * 8); }
+    // (8 doubles after W: the unrolled products read up to 7 entries past a row's diagonal)
+    static __host__ __device__ constexpr int bytes(int mm) { return FIXED + al16((w_entries(mm) + 8) * 8); }
 };
 
 struct Memb {
@@ -203,8 +204,33 @@ __device__ __forceinline__ int bits_below(uint64_t m) {
     return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
 }
 
+// The two largest candidates (|gradient|, key, slot) among this lane's table slots; members
+// and empty slots (whose keys carry the member bit) are skipped
+template <int GS, int SPL>
+__device__ __forceinline__ void top2(const uint32_t *hkey, const double *hval, int gl, double &a1, double &a2,
+                                     uint32_t &k1, uint32_t &k2, int &e1, int &e2) {
+    a1 = -1.0;
+    a2 = -1.0;
+    k1 = k2 = kEmptyKey;
+    e1 = e2 = 0;
+#pragma unroll 4
+    for (int jj = 0; jj < SPL; ++jj) {
+        const int e = gl + GS * jj;
+        const uint32_t kk = hkey[e];
+        const double a = (kk & kMember) ? -1.0 : fabs(hval[e]);
+        // value selects only (conditional stores to the pair would become a private array)
+        const bool g1 = a > a1, g2 = a > a2;
+        a2 = g1 ? a1 : (g2 ? a : a2);
+        k2 = g1 ? k1 : (g2 ? kk : k2);
+        e2 = g1 ? e1 : (g2 ? e : e2);
+        a1 = g1 ? a : a1;
+        k1 = g1 ? kk : k1;
+        e1 = g1 ? e : e1;
+    }
+}
+
 template <int GS, int MMAX, int CAP, int NB>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(GS == 8 ? 4 : (CAP <= 512 && MMAX <= 48 ? 3 : 1), 8))) void k_rows_w(
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(GS == 8 || (GS == 64 && MMAX <= 24) ? 4 : (CAP <= 512 && MMAX <= 48 ? 3 : 1), 8))) void k_rows_w(
     int n, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci, const double *__restrict__ av,
     const double *__restrict__ diag, const int32_t *__restrict__ dlo, int kmax, int s, double eps, double tau,
     int /*gmax*/, const int32_t *__restrict__ list, int nlist, int32_t *__restrict__ counters, int nxcd, int claim,
@@ -383,53 +409,62 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(GS == 8 ? 4 
             }
             wsync();
 
-            // ---- 2. selection: the table is scanned from LDS in every pass; a pass of round r
-            //         finds the smallest column in the band of the current maximum and each
-            //         lane's two largest eligible values (the next round's maximum without a
-            //         pass of its own: only the round's one winner leaves)
+            // ---- 2. selection.  One pass over the table keeps each lane's two largest
+            //         candidates (value, key, slot).  A round then needs only reductions: with
+            //         at most one candidate of each lane in the band of the current maximum, the
+            //         smallest key among the lanes' largest candidates in the band wins, and the
+            //         winning lane moves up its second (and marks its state as partial: its next
+            //         candidate is unknown).  A lane with two candidates in the band, or a partial
+            //         lane whose largest is in the band, makes the round exact the slow way: a
+            //         pass over the table for the smallest key in the band, then a new first
+            //         pass.  Candidates must exceed 2^-40 of the first maximum (eligibility).
             int ns = 0;
             int r_js = 0, r_nb = 0, r_ne = 0;  // lane v: v-th column selected in this step, its row extents
             if (act) {
-                double lm = -1.0;
-#pragma unroll 4
-                for (int jj = 0; jj < SPL; ++jj) {
-                    const int e = gl + GS * jj;
-                    const uint32_t kk = hkey[e];
-                    const double a = fabs(hval[e]);
-                    if (kk != kEmptyKey && !(kk & kMember)) lm = fmax(lm, a);
-                }
-                const double M = gred<GS, OpMax>(lm);
+                double a1, a2;
+                uint32_t k1, k2;
+                int e1, e2;
+                top2<GS, SPL>(hkey, hval, gl, a1, a2, k1, k2, e1, e2);
+                const double M = gred<GS, OpMax>(a1);
                 if (M > 0.0) {
                     const double thr = 0x1.0p-40 * M;
-                    double Mp = M;
+                    bool partial = false;
                     for (int round = 0; round < s; ++round) {
+                        const double v1 = a1 > thr ? a1 : -1.0;
+                        const double v2 = a2 > thr ? a2 : -1.0;
+                        const double Mp = round == 0 ? M : gred<GS, OpMax>(v1);
                         if (!(Mp > 0.0)) break;
                         const double band = (1.0 - tauv) * Mp;
-                        uint32_t lb = kEmptyKey;
-                        int le = -1;
-                        double t1 = 0.0, t2 = 0.0;  // two largest eligible values of this lane
-                        uint32_t k1 = kEmptyKey;
+                        const bool slow = (__ballot(v2 >= band || (partial && v1 >= band)) & gm) != 0;
+                        uint32_t js;
+                        if (!slow) {
+                            js = gred<GS, OpMinU>(v1 >= band ? k1 : kEmptyKey);
+                            const bool won = v1 >= band && k1 == js;
+                            if (won) hkey[e1] = js | kMember | ((uint32_t)(m_o + ns) << 24);
+                            a1 = won ? a2 : a1;
+                            k1 = won ? k2 : k1;
+                            e1 = won ? e2 : e1;
+                            a2 = won ? -1.0 : a2;
+                            k2 = won ? kEmptyKey : k2;
+                            partial = partial || won;
+                        } else {
+                            uint32_t lb = kEmptyKey;
+                            int le = 0;
 #pragma unroll 4
-                        for (int jj = 0; jj < SPL; ++jj) {
-                            const int e = gl + GS * jj;
-                            const uint32_t kk = hkey[e];
-                            const double a = fabs(hval[e]);
-                            if (kk != kEmptyKey && !(kk & kMember) && a > thr) {
-                                if (a >= band && kk < lb) {
+                            for (int jj = 0; jj < SPL; ++jj) {
+                                const int e = gl + GS * jj;
+                                const uint32_t kk = hkey[e];
+                                const double a = (kk & kMember) ? -1.0 : fabs(hval[e]);
+                                if (a > thr && a >= band && kk < lb) {
                                     lb = kk;
                                     le = e;
                                 }
-                                if (a > t1) {
-                                    t2 = t1;
-                                    t1 = a;
-                                    k1 = kk;
-                                } else if (a > t2) {
-                                    t2 = a;
-                                }
                             }
+                            js = gred<GS, OpMinU>(lb);
+                            if (lb == js) hkey[le] = js | kMember | ((uint32_t)(m_o + ns) << 24);
+                            top2<GS, SPL>(hkey, hval, gl, a1, a2, k1, k2, e1, e2);
+                            partial = false;
                         }
-                        const uint32_t js = gred<GS, OpMinU>(lb);
-                        if (lb == js && le >= 0) hkey[le] = js | kMember | ((uint32_t)(m_o + ns) << 24);
                         // the new row's extents, loaded while the next rounds run
                         if (gl == ns) {
                             r_js = (int)js;
@@ -437,7 +472,6 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(GS == 8 ? 4 
                             r_ne = rp[js + 1];
                         }
                         ++ns;
-                        Mp = gred<GS, OpMax>(k1 == js ? t2 : t1);
                     }
                 }
                 if (ns == 0) {
@@ -573,18 +607,18 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(GS == 8 ? 4 
 #pragma unroll
                 for (int v = 0; v < NB; ++v) la[v] = 0.0;
                 {
-                    // kPU entries of the row at a time, loads first (entries right of the
-                    // diagonal, and every entry of lanes without an old position, read as 0)
+                    // kPU entries of the row at a time: all loads first (in bounds: at most 7
+                    // past the diagonal of the lane's row, or of row 0 for lanes without a row,
+                    // within W's padding), then the entries right of the diagonal zeroed
                     const int lim = (go && gl < m_o) ? gl : -1;
-                    const double *wrow = Wm + tri_w(gl < MMAX - 1 ? gl : 0);
+                    const double *wrow = Wm + tri_w(lim >= 0 ? gl : 0);
                     for (int j0 = 0; j0 < mwb; j0 += kPU) {
                         double wv[kPU];
 #pragma unroll
-                        for (int u = 0; u < kPU; ++u) {
-                            const int j = j0 + u;
-                            const double w = wrow[j <= lim ? j : 0];
-                            wv[u] = j <= lim ? w : 0.0;
-                        }
+                        for (int u = 0; u < kPU; ++u) wv[u] = wrow[j0 + u];
+                        const int d = lim - j0;
+#pragma unroll
+                        for (int u = 0; u < kPU; ++u) wv[u] = u <= d ? wv[u] : 0.0;
 #pragma unroll
                         for (int v = 0; v < NB; ++v)
                             if (v < nbk)
@@ -605,15 +639,22 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(GS == 8 ? 4 
 #pragma unroll
                 for (int v = 0; v < NB; ++v) yb[v] = 0.0;
                 {
+                    // all loads first: rows t of the chunk past the old positions read the last
+                    // old row, lanes without an old position column 0 (in bounds); then the
+                    // entries with t < j or t >= m_o zeroed
+                    const int jc = (go && gl < m_o) ? gl : 0;
                     const int lo = (go && gl < m_o) ? gl : 0x7fffffff;
                     for (int t0 = 0; t0 < mwb; t0 += kPU) {
                         double wv[kPU];
 #pragma unroll
                         for (int u = 0; u < kPU; ++u) {
+                            const int tc = min(t0 + u, m_o - 1);
+                            wv[u] = Wm[tri_w(tc) + jc];
+                        }
+#pragma unroll
+                        for (int u = 0; u < kPU; ++u) {
                             const int t = t0 + u;
-                            const bool on = t >= lo && t < m_o;
-                            const double w = Wm[on ? tri_w(t) + gl : 0];
-                            wv[u] = on ? w : 0.0;
+                            wv[u] = (t >= lo && t < m_o) ? wv[u] : 0.0;
                         }
 #pragma unroll
                         for (int v = 0; v < NB; ++v)

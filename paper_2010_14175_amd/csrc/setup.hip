@@ -329,7 +329,7 @@ __global__ void k_block_check(int n, const int32_t *__restrict__ rp, const int32
 // ---------------------------------------------------------------------------------------
 // fused per-row kernels, instantiated in rows.hip (Cholesky form) and rows_w.hip (inverse-factor form)
 RowsKernel rows_kernel(int mmax_t, int cap, bool rsl, bool f32);
-RowsKernel rows_kernel_w(int mmax, int maxlen, int cap, int *gs_out, size_t *lds_out);
+RowsKernel rows_kernel_w(int mmax, int maxlen, int cap, int lanes, int *gs_out, size_t *lds_out);
 RowsKernel rows_kernel_w_large(int mmax, int cap, size_t *lds_out);
 
 // Launch of a per-row kernel over `nlist` rows.  Inverse-factor form: wdyn > 0 is its dynamic
@@ -591,15 +591,11 @@ static int setup_core(const afsai_csr *A, const afsai_params *p, int nsys, const
         if (wcap < 64) wcap = 64;
         if (wcap > 512) wcap = 512;
         if (option(AFSAI_OPT_SETUP_TABLE) > 0) wcap = (int)std::max<int64_t>(64, std::min<int64_t>(1024, pow2ceil(option(AFSAI_OPT_SETUP_TABLE))));
+        const int lanes = (int)option(AFSAI_OPT_SETUP_LANES);
+        // groups of 32 and 64 lanes take tables from 128 slots
+        if (wcap < 128 && (lanes >= 32 || mmax > 16 || maxlen > 64)) wcap = 128;
         int gs = 64;
-        k1 = rows_kernel_w(mmax, maxlen, wcap, &gs, &wdyn);
-        // automatic choice: patterns of 17..32 positions (two rows per wavefront of 32 lanes
-        // each) measured faster in the Cholesky form (786,432-row 27-point workload: 25.9
-        // against 31.9 ms), every other shape in the inverse-factor form
-        if (k1 && form == 0 && gs == 32) {
-            k1 = nullptr;
-            wdyn = 0;
-        }
+        k1 = rows_kernel_w(mmax, maxlen, wcap, lanes, &gs, &wdyn);
         if (k1) {
             wrpw = 64 / gs;
             cap1 = wcap;
