@@ -458,7 +458,7 @@ def kernel_source_hash(kernel: str) -> str | None:
     import hashlib
 
     files = {"afsai_rows": ["rows.hpp", "rows.hip", "rows_reg.hip", "rows_lds.hip", "rows_f32.hip", "rows_w.hpp",
-                           "rows_w.hip"]}.get(kernel)
+                           "rows_w.hip", "rows_w_inst.hpp", "rows_w_g32.hip"]}.get(kernel)
     if not files:
         return None
     h = hashlib.sha256()
@@ -505,7 +505,7 @@ CPU_WHOLE_MAX_ROWS = 2_000_000
 
 
 def run_workload(af, pb, g_prec, args, steps: int, warmup: int, profile: bool, with_cpu: bool,
-                 workload_name: str) -> dict:
+                 workload_name: str, with_forms: bool = False, forms_steps: int = 3) -> dict:
     """One workload: ``warmup`` untimed steps, one untimed profiled step (per-kernel breakdown,
     dominant kernel), then ``steps`` timed steps with events only around the dominant kernel.
     Returns the fields of the JSON line (without the common header)."""
@@ -516,7 +516,7 @@ def run_workload(af, pb, g_prec, args, steps: int, warmup: int, profile: bool, w
     x = torch.zeros_like(b)
 
     def step():
-        P = af.setup(dA, pb.kmax, pb.s, pb.eps, g_prec=g_prec, setup_f32=args.setup_f32)
+        P = af.setup(dA, pb.kmax, pb.s, pb.eps, g_prec=g_prec, setup_f32=args.setup_f32, grad_f32=args.grad_f32)
         x.zero_()
         _, info = af.pcg_solve(dA, P, b, x=x, rtol=pb.rtol)
         sinfo = P.info()
@@ -606,6 +606,9 @@ def run_workload(af, pb, g_prec, args, steps: int, warmup: int, profile: bool, w
             cpu = cpu_baseline_sampled(pb, its[-1], sinfo.nnz_g, threads)
         print(f"[bench] cpu baseline: {cpu['value']} s ({cpu['sample']})", file=sys.stderr, flush=True)
 
+    forms = None
+    if with_forms:
+        forms = forms_compare(af, pb, dA, b, x, forms_steps)
     f32_eval = None
     if args.setup_f32:
         f32_eval = setup_f32_eval(af, pb, dA, b, x, its[-1])
@@ -613,10 +616,12 @@ def run_workload(af, pb, g_prec, args, steps: int, warmup: int, profile: bool, w
     out = {
         "value": round(sec, 6),
         "ms_per_step": round(sec * 1e3, 3),
-        "dtype": ("f32 setup, " if args.setup_f32 else "") + ("f64" if g_prec == af.F64 else "f64 (G stored f32)"),
+        "dtype": ("f32 setup, " if args.setup_f32 else "") + ("f32 gradient, " if args.grad_f32 else "")
+                 + ("f64" if g_prec == af.F64 else "f64 (G stored f32)"),
         "config": {"workload": workload_name, "n": pb.n, "nnz": pb.A.nnz, "kmax": pb.kmax, "s": pb.s,
                    "eps": pb.eps, "rtol": pb.rtol, "g_prec": "f32" if g_prec == af.F32 else "f64",
-                   "setup_prec": "f32" if args.setup_f32 else "f64", "nnz_g": sinfo.nnz_g},
+                   "setup_prec": "f32" if args.setup_f32 else "f64",
+                   "gradient_prec": "f32" if (args.setup_f32 or args.grad_f32) else "f64", "nnz_g": sinfo.nnz_g},
         "setup_ms": round(float(np.mean(setup_ms)), 3),
         "pcg_ms": round(float(np.mean(pcg_ms)), 3),
         "iters": its[-1],
@@ -629,7 +634,53 @@ def run_workload(af, pb, g_prec, args, steps: int, warmup: int, profile: bool, w
     }
     if f32_eval:
         out["setup_f32_eval"] = f32_eval
+    if forms:
+        out["forms"] = forms
     return out
+
+
+def forms_compare(af, pb, dA, b, x, steps: int) -> dict:
+    """Time to solution (setup + PCG to rtol, median of ``steps`` after one warm-up) of the
+    plain form (G and every setup step in FP64) against the precision forms: G stored and
+    applied in FP32, and in addition the gradient reading FP32 values of A (the dense
+    factorisation, the PCG recurrences and A stay FP64).  The FP32-gradient form's patterns
+    are compared with the FP64 setup's row by row when G is small enough to export."""
+    import torch
+
+    kinds = {"plain_f64": dict(g_prec=af.F64), "g_f32": dict(g_prec=af.F32),
+             "g_f32_grad_f32": dict(g_prec=af.F32, grad_f32=True)}
+    res = {}
+    for name, kw in kinds.items():
+        runs = []
+        for k in range(steps + 1):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            P = af.setup(dA, pb.kmax, pb.s, pb.eps, **kw)
+            x.zero_()
+            _, info = af.pcg_solve(dA, P, b, x=x, rtol=pb.rtol)
+            torch.cuda.synchronize()
+            wall = (time.perf_counter() - t0) * 1e3
+            si = P.info()
+            P.close()
+            if k:
+                runs.append((wall, si.ms, info.ms, info.iters, info.true_relres))
+        w, su, pc, it, tr = (np.median([r[j] for r in runs]) for j in range(5))
+        res[name] = {"ms": round(float(w), 3), "setup_ms": round(float(su), 3), "pcg_ms": round(float(pc), 3),
+                     "iters": int(it), "true_relres": float(tr)}
+    base = res["plain_f64"]["ms"]
+    for name in kinds:
+        res[name]["speedup_vs_plain"] = round(base / res[name]["ms"], 4)
+    if pb.n <= CPU_WHOLE_MAX_ROWS:
+        P64 = af.setup(dA, pb.kmax, pb.s, pb.eps)
+        P32 = af.setup(dA, pb.kmax, pb.s, pb.eps, grad_f32=True)
+        (r64, c64, _), (r32, c32, _) = ([t.cpu().numpy() for t in Pk.export()] for Pk in (P64, P32))
+        P64.close()
+        P32.close()
+        same = int(np.sum([np.array_equal(c64[r64[i]:r64[i + 1]], c32[r32[i]:r32[i + 1]]) for i in range(pb.n)])) \
+            if not np.array_equal(r64, r32) or not np.array_equal(c64, c32) else pb.n
+        res["g_f32_grad_f32"]["rows_with_fp64_pattern"] = same / pb.n
+    print(f"[bench] precision forms: {json.dumps(res)}", file=sys.stderr, flush=True)
+    return res
 
 
 def setup_f32_eval(af, pb, dA, b, x, iters_f32: int) -> dict:
@@ -685,6 +736,10 @@ def main():
                     help="serve: slot counts of the continuous-batching runs")
     ap.add_argument("--g-prec", default=None, choices=["f64", "f32"],
                     help="storage of G (default: the workload's own, FP32 for the 150^3 problem, else FP64)")
+    ap.add_argument("--grad-f32", action="store_true",
+                    help="precision form's gradient: FP32 values of A in the gradient, FP64 factorisation")
+    ap.add_argument("--no-forms", action="store_true",
+                    help="skip the comparison of the plain and precision forms at the 150^3 and 64^3 workloads")
     ap.add_argument("--setup-f32", action="store_true",
                     help="per-row setup arithmetic in FP32 (reports pattern agreement with the FP64 setup)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -730,16 +785,18 @@ def main():
     g_prec = af.F32 if gp == "f32" else af.F64
     print(f"[bench] workload {pb.name}: n={pb.n} nnz={pb.A.nnz} kmax={pb.kmax} s={pb.s} eps={pb.eps} "
           f"g_prec={gp} (generated in {time.perf_counter() - t_gen:.1f} s)", file=sys.stderr, flush=True)
+    forms = args.workload in ("elast27_150", "elast27_64") and not args.no_forms
     res = run_workload(af, pb, g_prec, args, args.steps, args.warmup, not args.no_profile,
-                       not args.no_cpu_baseline, args.workload)
+                       not args.no_cpu_baseline, args.workload, with_forms=forms, forms_steps=2)
     context = None
     if args.workload == "elast27_150" and not args.no_context:
         # the 64^3 workload (786,432 rows, FP64 G) as context beside the headline
         del pb
         pc = workloads()["elast27_64"]()
-        c = run_workload(af, pc, af.F64, args, min(args.steps, 5), 1, not args.no_profile, False, "elast27_64")
+        c = run_workload(af, pc, af.F64, args, min(args.steps, 5), 1, not args.no_profile, False, "elast27_64",
+                         with_forms=not args.no_forms, forms_steps=5)
         context = {"elast27_64": {k: c[k] for k in ("ms_per_step", "setup_ms", "pcg_ms", "iters", "pcg_hbm_gbs",
-                                                    "roofline", "config")}}
+                                                    "roofline", "config", "forms") if k in c}}
     out = {"metric": METRIC, "value": res.pop("value"), "unit": "s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": res.pop("ms_per_step"), "higher_is_better": False,
            "scaling": "weak", "vs_baseline": None, "dtype": res.pop("dtype"), "data": "synthetic",

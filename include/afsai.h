@@ -54,6 +54,15 @@ extern "C" {
  * rounding of each other.  Needs every row of A to have at most 128 entries and n <= 2^24
  * (AFSAI_ERR_INVALID_ARG otherwise). */
 #define AFSAI_SETUP_F32 2u
+/* the precision form's gradient: the Kaporin gradient (the product over the pattern rows that
+ * ranks the candidates, eq. grapsi) reads an FP32 copy of A's values (the paper's A_s =
+ * single(A) of Sec. 4.3), while the gathered systems, the dense factorisation, g and psi stay
+ * FP64.  Halves the value bytes of the gradient pass; candidates whose gradients are within
+ * FP32 rounding of each other may rank differently from an FP64 gradient, and then the
+ * pattern (and G) of that row differs.  Inverse-factor form only: needs FP64 setup arithmetic,
+ * rows of at most 128 entries and n <= 2^24 (AFSAI_ERR_INVALID_ARG otherwise).  The setup
+ * allocates the copy (4 bytes per entry) for the call. */
+#define AFSAI_GRAD_F32 4u
 
 /*
  * Square sparse matrix in CSR, 0-based, int32 indices (the paper's 4-byte local indices,
@@ -81,7 +90,7 @@ typedef struct afsai_csr {
  *             any hardware)
  *   g_prec    AFSAI_F64 or AFSAI_F32 storage for G and G^T (values widened to FP64 in every
  *             product; the per-row Cholesky is FP64 in both cases)
- *   flags     AFSAI_VALIDATE, AFSAI_SETUP_F32, both or 0
+ *   flags     AFSAI_VALIDATE, AFSAI_SETUP_F32, AFSAI_GRAD_F32 (or-ed; not the last two together)
  */
 typedef struct afsai_params {
     int32_t kmax;

@@ -26,6 +26,7 @@ OK, ERR_INVALID_ARG, ERR_BAD_MATRIX, ERR_NOT_SPD, ERR_NO_MEMORY, ERR_NOT_CONVERG
 F64, F32 = 0, 1
 VALIDATE = 1
 SETUP_F32 = 2
+GRAD_F32 = 4
 STOP_KMAX, STOP_EPS, STOP_NOCAND = 0, 1, 2
 
 # every symbol the C header declares
@@ -37,7 +38,8 @@ EXPORTS = ("afsai_setup", "afsai_apply", "afsai_apply_noalloc", "pcg_solve", "af
            "afsai_release_cache",
            "afsai_profile_enable", "afsai_profile_only", "afsai_profile_read")
 (OPT_SETUP_GROUP, OPT_SETUP_TABLE, OPT_SPMV_GROUP, OPT_SPMV_UNROLL, OPT_PCG_CSR_A, OPT_PCG_FORM,
- OPT_SELL_WIDTH, OPT_PCG_GRAPH, OPT_SETUP_SLOTS, OPT_SELL_TAIL, OPT_SELL_UNEVEN, OPT_SETUP_FORM) = range(1, 13)
+ OPT_SELL_WIDTH, OPT_PCG_GRAPH, OPT_SETUP_SLOTS, OPT_SELL_TAIL, OPT_SELL_UNEVEN, OPT_SETUP_FORM,
+ OPT_SETUP_LANES) = range(1, 14)
 
 
 class ServerConfigStruct(ctypes.Structure):
@@ -290,10 +292,11 @@ class Preconditioner:
 
 
 def setup(A: DeviceCSR, kmax: int, s: int, eps: float, tie_rtol: float = TIE_RTOL, g_prec: int = F64,
-          validate: bool = False, stream=None, setup_f32: bool = False) -> Preconditioner:
-    """Adaptive FSAI setup (``afsai_setup``); setup_f32: the per-row arithmetic in FP32."""
+          validate: bool = False, stream=None, setup_f32: bool = False, grad_f32: bool = False) -> Preconditioner:
+    """Adaptive FSAI setup (``afsai_setup``); setup_f32: the per-row arithmetic in FP32;
+    grad_f32: the gradient reads FP32 values of A (the factorisation stays FP64)."""
     p = ParamsStruct(int(kmax), int(s), float(eps), float(tie_rtol), int(g_prec),
-                     (VALIDATE if validate else 0) | (SETUP_F32 if setup_f32 else 0))
+                     (VALIDATE if validate else 0) | (SETUP_F32 if setup_f32 else 0) | (GRAD_F32 if grad_f32 else 0))
     h = ctypes.c_void_p()
     st = A.struct
     _check(lib().afsai_setup(ctypes.byref(st), ctypes.byref(p), _stream(stream), ctypes.byref(h)), "afsai_setup")

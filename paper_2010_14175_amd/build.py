@@ -17,7 +17,7 @@ LIB = os.path.join(HERE, "libafsai.so")
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 HIPCC = os.path.join(ROCM, "bin", "hipcc")
 
-SOURCES = ["rows_w.hip", "rows_reg.hip", "rows_lds.hip", "rows_f32.hip", "rows.hip", "setup.hip", "solve.hip", "sell.hip",
+SOURCES = ["rows_w.hip", "rows_w_g32.hip", "rows_reg.hip", "rows_lds.hip", "rows_f32.hip", "rows.hip", "setup.hip", "solve.hip", "sell.hip",
            "serve.hip", "runtime.hip"]
 
 HIPFLAGS = [

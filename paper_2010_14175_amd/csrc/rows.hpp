@@ -171,6 +171,7 @@ constexpr int sl_cap() { return CAP >= 2048 ? 2 * CAP : 4 * CAP; }
 template <int MMAX, int CAP, bool RSL, typename T>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(!RSL ? 1 : (MMAX <= 8 && CAP <= 256) ? 8 : ((MMAX <= 32 && CAP <= 512) ? (sizeof(T) == 4 ? 6 : 5) : 1), 8))) void k_afsai_rows(
     int n, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci, const double *__restrict__ av,
+    const float *__restrict__ /* FP32 gradient values: inverse-factor form only */,
     const double *__restrict__ diag, const int32_t *__restrict__ dlo, int kmax, int s, double eps, double tau,
     int gmax, const int32_t *__restrict__ list, int nlist, int32_t *__restrict__ counters, int nxcd, int claim,
     int32_t *__restrict__ ell_col, double *__restrict__ ell_val, int ldell, int32_t *__restrict__ m_out,
@@ -683,7 +684,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(!RSL ? 1 : (
     }
 }
 
-typedef void (*RowsKernel)(int, const int32_t *, const int32_t *, const double *, const double *, const int32_t *,
+typedef void (*RowsKernel)(int, const int32_t *, const int32_t *, const double *, const float *, const double *,
+                           const int32_t *,
                            int, int, double, double, int, const int32_t *, int, int32_t *, int, int, int32_t *, double *, int,
                            int32_t *, double *, int32_t *, int32_t *, int8_t *, int32_t *, int32_t *);
 

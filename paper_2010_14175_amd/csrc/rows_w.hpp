@@ -35,6 +35,8 @@
 //  5. g = -(W^T l_i)/d_i, the exit test psi/psi_0 <= eps (eq. exit_crit).
 #pragma once
 
+#include <type_traits>
+
 #include "common.hpp"
 #include "rows.hpp"
 
@@ -229,10 +231,10 @@ __device__ __forceinline__ void top2(const uint32_t *hkey, const double *hval, i
     }
 }
 
-template <int GS, int MMAX, int CAP, int NB>
+template <int GS, int MMAX, int CAP, int NB, bool G32>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(GS == 8 || (GS == 64 && MMAX <= 24) ? 4 : (CAP <= 512 && MMAX <= 48 ? 3 : 1), 8))) void k_rows_w(
     int n, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci, const double *__restrict__ av,
-    const double *__restrict__ diag, const int32_t *__restrict__ dlo, int kmax, int s, double eps, double tau,
+    const float *__restrict__ av32, const double *__restrict__ diag, const int32_t *__restrict__ dlo, int kmax, int s, double eps, double tau,
     int /*gmax*/, const int32_t *__restrict__ list, int nlist, int32_t *__restrict__ counters, int nxcd, int claim,
     int32_t *__restrict__ ell_col, double *__restrict__ ell_val, int ldell, int32_t *__restrict__ m_out,
     double *__restrict__ psi_out, int32_t *__restrict__ steps_out, int32_t *__restrict__ reason_out,
@@ -248,6 +250,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(GS == 8 || (
     constexpr int HMAX = (128 + GS - 1) / GS;     // chunks of a gathered row (rows <= 128 entries)
     constexpr int PF = HMAX < 4 ? HMAX : 4;       // chunks loaded ahead for every gathered row
     constexpr int QB = qb_of(GS);
+    using AVT = typename std::conditional<G32, float, double>::type;
 
     extern __shared__ __align__(16) unsigned char lds_w[];
     __shared__ int32_t s_row;
@@ -361,7 +364,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(GS == 8 || (
                 for (int qb = 0; qb < MMAX; qb += QB) {
                     if (qb <= m_o) {
                         int slt[QB][SPW];
-                        double aa[QB][SPW], gg[QB];
+                        AVT aa[QB][SPW];
+                        double gg[QB];
 #pragma unroll
                         for (int u = 0; u < QB; ++u) {
                             const int q = qb + u;
@@ -390,10 +394,13 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(GS == 8 || (
                             for (int h = 0; h < SPW; ++h) {
                                 const int o = gl + GS * h;
                                 slt[u][h] = -1;
-                                aa[u][h] = 0.0;
+                                aa[u][h] = AVT(0);
                                 if (q < MMAX && o < len) {
                                     slt[u][h] = (int)((slr[q < MMAX ? q : 0][h >> 1] >> (16 * (h & 1))) & 0xffffu);
-                                    aa[u][h] = av[beg + o];  // cached: rows are read again at later steps
+                                    // cached loads (rows are read again at later steps); FP32 values
+                                    // for the precision form's gradient
+                                    if constexpr (G32) aa[u][h] = av32[beg + o];
+                                    else aa[u][h] = av[beg + o];
                                 }
                             }
                         }
@@ -402,7 +409,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(GS == 8 || (
 #pragma unroll
                             for (int h = 0; h < SPW; ++h)
                                 if (slt[u][h] >= 0)
-                                    __hip_atomic_fetch_add(&hval[slt[u][h]], aa[u][h] * gg[u], __ATOMIC_RELAXED,
+                                    __hip_atomic_fetch_add(&hval[slt[u][h]], (double)aa[u][h] * gg[u], __ATOMIC_RELAXED,
                                                            __HIP_MEMORY_SCOPE_WORKGROUP);
                     }
                 }

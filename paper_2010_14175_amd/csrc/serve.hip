@@ -235,7 +235,7 @@ int afsai_server_create(const afsai_server_config *cfg, afsai_server *out) {
 static bool params_ok(const afsai_params &p) {
     return !(p.kmax < 0 || (p.kmax > 0 && p.s < 1) || 1 + (int64_t)p.kmax * (p.kmax > 0 ? p.s : 0) > 64 ||
              !(p.eps >= 0.0) || !(p.tie_rtol >= 0.0 && p.tie_rtol < 1.0) ||
-             (p.g_prec != AFSAI_F64 && p.g_prec != AFSAI_F32) || (p.flags & ~AFSAI_VALIDATE));
+             (p.g_prec != AFSAI_F64 && p.g_prec != AFSAI_F32) || (p.flags & ~(AFSAI_VALIDATE | AFSAI_GRAD_F32)));
 }
 
 int afsai_server_submit(afsai_server S, const afsai_csr *A, const afsai_params *p, const double *b, double *x,

@@ -329,13 +329,13 @@ __global__ void k_block_check(int n, const int32_t *__restrict__ rp, const int32
 // ---------------------------------------------------------------------------------------
 // fused per-row kernels, instantiated in rows.hip (Cholesky form) and rows_w.hip (inverse-factor form)
 RowsKernel rows_kernel(int mmax_t, int cap, bool rsl, bool f32);
-RowsKernel rows_kernel_w(int mmax, int maxlen, int cap, int lanes, int *gs_out, size_t *lds_out);
-RowsKernel rows_kernel_w_large(int mmax, int cap, size_t *lds_out);
+RowsKernel rows_kernel_w(int mmax, int maxlen, int cap, int lanes, bool g32, int *gs_out, size_t *lds_out);
+RowsKernel rows_kernel_w_large(int mmax, int cap, bool g32, size_t *lds_out);
 
 // Launch of a per-row kernel over `nlist` rows.  Inverse-factor form: wdyn > 0 is its dynamic
 // LDS per block and rpw its rows per wavefront; the Cholesky form sizes its LDS from the
 // pattern and table (wdyn = 0).
-static int launch_rows(RowsKernel kern, size_t wdyn, int rpw, int mmax_t, int mmax, int64_t row_work, int cap, bool rsl, int tb, int gmax, const afsai_csr *A, const double *diag,
+static int launch_rows(RowsKernel kern, size_t wdyn, int rpw, int mmax_t, int mmax, int64_t row_work, int cap, bool rsl, int tb, int gmax, const afsai_csr *A, const float *av32, const double *diag,
                        const int32_t *dlo, const afsai_params *p, const int32_t *list, int nlist, int32_t *counters,
                        int ldell, int32_t *ell_col, double *ell_val, int32_t *m, double *psi, int32_t *steps,
                        int32_t *reason, int8_t *st, int32_t *ovf_count, int32_t *ovf_list, const DeviceInfo &di,
@@ -373,7 +373,7 @@ static int launch_rows(RowsKernel kern, size_t wdyn, int rpw, int mmax_t, int mm
     hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, (int64_t)nx, counters, 0);
     {
         ProfScope ps("afsai_rows", s);
-        hipLaunchKernelGGL(kern, dim3((unsigned)nb), dim3(64), dyn, s, A->n, A->row_ptr, A->col_idx, A->val, diag, dlo,
+        hipLaunchKernelGGL(kern, dim3((unsigned)nb), dim3(64), dyn, s, A->n, A->row_ptr, A->col_idx, A->val, av32, diag, dlo,
                            p->kmax, p->s, p->eps, p->tie_rtol, gmax, list, nlist, counters, nx, claim, ell_col, ell_val,
                            ldell, m, psi, steps, reason, st, ovf_count, ovf_list);
     }
@@ -460,7 +460,9 @@ static int setup_core(const afsai_csr *A, const afsai_params *p, int nsys, const
     if (A->n <= 0 || A->nnz < A->n) AFSAI_FAIL(AFSAI_ERR_INVALID_ARG, "afsai_setup: n = %d, nnz = %d", A->n, A->nnz);
     if (!A->row_ptr || !A->col_idx || !A->val) AFSAI_FAIL(AFSAI_ERR_INVALID_ARG, "afsai_setup: null CSR array");
     if (p->kmax < 0 || (p->kmax > 0 && p->s < 1) || !(p->eps >= 0.0) || !(p->tie_rtol >= 0.0 && p->tie_rtol < 1.0) ||
-        (p->g_prec != AFSAI_F64 && p->g_prec != AFSAI_F32) || (p->flags & ~(AFSAI_VALIDATE | AFSAI_SETUP_F32)))
+        (p->g_prec != AFSAI_F64 && p->g_prec != AFSAI_F32) ||
+        (p->flags & ~(AFSAI_VALIDATE | AFSAI_SETUP_F32 | AFSAI_GRAD_F32)) ||
+        ((p->flags & AFSAI_SETUP_F32) && (p->flags & AFSAI_GRAD_F32)))
         AFSAI_FAIL(AFSAI_ERR_INVALID_ARG, "afsai_setup: bad parameters (kmax=%d s=%d eps=%g tie_rtol=%g g_prec=%d)",
                    p->kmax, p->s, p->eps, p->tie_rtol, p->g_prec);
     const int64_t mmax64 = 1 + (int64_t)p->kmax * (p->kmax > 0 ? p->s : 0);
@@ -595,14 +597,15 @@ static int setup_core(const afsai_csr *A, const afsai_params *p, int nsys, const
         // groups of 32 and 64 lanes take tables from 128 slots
         if (wcap < 128 && (lanes >= 32 || mmax > 16 || maxlen > 64)) wcap = 128;
         int gs = 64;
-        k1 = rows_kernel_w(mmax, maxlen, wcap, lanes, &gs, &wdyn);
+        k1 = rows_kernel_w(mmax, maxlen, wcap, lanes, (p->flags & AFSAI_GRAD_F32) != 0, &gs, &wdyn);
         if (k1) {
             wrpw = 64 / gs;
             cap1 = wcap;
             if (cap2 < cap1) cap2 = cap1;
         }
     }
-    if (form == 2 && !k1)
+    const bool gf32 = (p->flags & AFSAI_GRAD_F32) != 0;
+    if ((form == 2 || gf32) && !k1)
         AFSAI_FAIL(AFSAI_ERR_INVALID_ARG,
                    "afsai_setup: the inverse-factor form needs FP64 setup arithmetic, rows of at most 128 entries "
                    "and n <= 2^24");
@@ -610,7 +613,15 @@ static int setup_core(const afsai_csr *A, const afsai_params *p, int nsys, const
     if (!k1) AFSAI_FAIL(AFSAI_ERR_TOO_LARGE, "afsai_setup: no kernel for pattern %d / table %d", mmax_t, cap1);
     // table entries one row touches over its steps (bound per step times k_max, plus its own row)
     const int64_t row_work = (int64_t)p->kmax * bound + maxlen;
-    if ((rc = launch_rows(k1, wdyn, wrpw, mmax_t, mmax, row_work, cap1, rsl, tb, gmax, A, diagb.as<double>(), dlob.as<int32_t>(), p, nullptr, n, ctr.as<int32_t>(), ldell,
+    // the precision form's gradient values: A's values rounded to FP32, for this call
+    DevBuf av32b;
+    if (gf32) {
+        if ((rc = dalloc(av32b, sizeof(float) * (size_t)A->nnz, s))) return rc;
+        hipLaunchKernelGGL((k_narrow<float>), dim3(grid1d(A->nnz, di)), dim3(256), 0, s, (int64_t)A->nnz, A->val,
+                           av32b.as<float>());
+    }
+    const float *av32 = gf32 ? av32b.as<float>() : nullptr;
+    if ((rc = launch_rows(k1, wdyn, wrpw, mmax_t, mmax, row_work, cap1, rsl, tb, gmax, A, av32, diagb.as<double>(), dlob.as<int32_t>(), p, nullptr, n, ctr.as<int32_t>(), ldell,
                           ell_col.as<int32_t>(), ell_val.as<double>(), mcnt.as<int32_t>(), psi.as<double>(),
                           steps.as<int32_t>(), reason.as<int32_t>(), st.as<int8_t>(), ovf_count, ovf.as<int32_t>(), di,
                           s)))
@@ -629,9 +640,9 @@ static int setup_core(const afsai_csr *A, const afsai_params *p, int nsys, const
         hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, (int64_t)1, cnt2, 0);
         // the same form as the first launch, with the larger table
         size_t wdyn2 = 0;
-        RowsKernel k2 = wdyn ? rows_kernel_w_large(mmax, cap2, &wdyn2) : rows_kernel(mmax_t, cap2, rsl, sf32);
+        RowsKernel k2 = wdyn ? rows_kernel_w_large(mmax, cap2, (p->flags & AFSAI_GRAD_F32) != 0, &wdyn2) : rows_kernel(mmax_t, cap2, rsl, sf32);
         if (!k2) AFSAI_FAIL(AFSAI_ERR_TOO_LARGE, "afsai_setup: no kernel for table %d", cap2);
-        if ((rc = launch_rows(k2, wdyn2, 1, mmax_t, mmax, row_work, cap2, rsl, tb, gmax, A, diagb.as<double>(), dlob.as<int32_t>(), p, list2.as<int32_t>(), novf,
+        if ((rc = launch_rows(k2, wdyn2, 1, mmax_t, mmax, row_work, cap2, rsl, tb, gmax, A, av32, diagb.as<double>(), dlob.as<int32_t>(), p, list2.as<int32_t>(), novf,
                               ctr.as<int32_t>(), ldell, ell_col.as<int32_t>(), ell_val.as<double>(), mcnt.as<int32_t>(),
                               psi.as<double>(), steps.as<int32_t>(), reason.as<int32_t>(), st.as<int8_t>(), cnt2,
                               ovf.as<int32_t>(), di, s)))

@@ -334,6 +334,58 @@ def test_setup_f32_against_oracle(af, make, kmax, s, min_same):
     assert abs(i32.iters - i64.iters) <= max(2, i64.iters // 10), (i32.iters, i64.iters)
 
 
+@pytest.mark.parametrize("make,kmax,s", [(lambda: synth.elast27(12, 1.0, 2), 10, 2),
+                                         (lambda: synth.lap7_lognormal(12, 11, 10, 1.0, 3), 5, 1),
+                                         (lambda: synth.elast27(7, 2.0, 5), 15, 3),
+                                         (lambda: synth.poisson7(14).A, 5, 1)])
+def test_setup_grad_f32_against_oracle(af, make, kmax, s):
+    """The precision form's gradient (FP32 values of A in the ranking product, FP64 systems,
+    factorisation and g) against the FP64 oracle: nearly every row keeps the oracle's pattern
+    (a row changes only where two candidates' gradients are within FP32 rounding of each
+    other), and on those rows G is the FP64 result (within 1e-10 of the oracle, since the
+    dense systems are gathered in FP64); PCG to rtol 1e-8 takes about the FP64 setup's
+    iterations.  On the constant-coefficient Laplacian the FP32 values are exact, so every
+    pattern is the oracle's."""
+    A = make()
+    dA = _dev(af, A)
+    P = af.setup(dA, kmax, s, 1e-2, grad_f32=True)
+    rp, ci, va = _gpu_factor(af, P)
+    R = oracle.setup_rows(A, kmax, s, 1e-2)
+    same, worst = 0, 0.0
+    for i in range(A.n):
+        m = R.m[i]
+        cols = ci[rp[i]:rp[i + 1]]
+        if len(cols) == m and np.array_equal(cols, R.cols[i, :m]):
+            same += 1
+            ov = R.vals[i, :m]
+            worst = max(worst, np.max(np.abs(va[rp[i]:rp[i + 1]] - ov)) / np.max(np.abs(ov)))
+    exact = np.array_equal(A.val.astype(np.float32).astype(np.float64), A.val)
+    print(f"grad_f32: {same}/{A.n} rows with the oracle's pattern, worst G error on them {worst:.2e}")
+    assert same == A.n if exact else same >= 0.98 * A.n, (same, A.n)
+    assert worst <= G_RTOL, worst
+    b = A.to_scipy() @ synth.uniform(3, 4, A.n, -1.0, 1.0)
+    x32, i32 = af.pcg_solve(dA, P, _vec(b), rtol=1e-8)
+    x64, i64 = af.pcg_solve(dA, af.setup(dA, kmax, s, 1e-2), _vec(b), rtol=1e-8)
+    assert i32.converged and i32.true_relres < 2e-8
+    assert abs(i32.iters - i64.iters) <= max(2, i64.iters // 10), (i32.iters, i64.iters)
+
+
+def test_setup_grad_f32_refused(af):
+    """The FP32 gradient belongs to the inverse-factor form with FP64 setup arithmetic."""
+    A = synth.elast27(5, 1.0, 2)
+    dA = _dev(af, A)
+    with pytest.raises(af.AfsaiError) as e:
+        af.setup(dA, 5, 2, 1e-2, grad_f32=True, setup_f32=True)
+    assert e.value.code == af.ERR_INVALID_ARG
+    try:
+        af.set_option(af.OPT_SETUP_FORM, 1)
+        with pytest.raises(af.AfsaiError) as e:
+            af.setup(dA, 5, 2, 1e-2, grad_f32=True)
+        assert e.value.code == af.ERR_INVALID_ARG
+    finally:
+        af.set_option(af.OPT_SETUP_FORM, 0)
+
+
 def test_setup_f32_refused(af):
     A = synth.random_sparse_spd(2000, 90, 4)
     with pytest.raises(af.AfsaiError) as e:
