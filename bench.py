@@ -19,6 +19,7 @@ same workload (host cores): whole for up to 2M rows, on a stated sample above.
 from __future__ import annotations
 
 import argparse
+import contextlib
 import json
 import math
 import os
@@ -53,6 +54,12 @@ def batch_bench(args):
     dA = af.DeviceCSR.from_host(A)
     b = torch.from_numpy(b_h).cuda()
     x = torch.zeros_like(b)
+    choice = None
+    if args.tune:
+        from paper_2010_14175_amd import tune
+
+        choice = tune.autotune(dA, 5, 1, 1e-2, b, offsets=off, reps=2, cache=args.tune_cache)
+        print(f"[bench] tuned: {choice}", file=sys.stderr, flush=True)
 
     def step():
         P = af.setup_batched(dA, off, 5, 1, 1e-2)
@@ -62,24 +69,41 @@ def batch_bench(args):
         P.close()
         return sinfo, infos
 
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    kern = {}
-    if not args.no_profile:
-        # per-kernel breakdown from one untimed profiled step (events stay out of the timed steps)
-        af.profile_read(reset=True)
-        af.profile_enable(True)
-        step()
+    ctx = tune.apply(choice) if choice else contextlib.nullcontext()
+    with ctx:
+        for _ in range(args.warmup):
+            step()
         torch.cuda.synchronize()
-        af.profile_enable(False)
-        kern = {k: {"launches": v[0], "total_ms": round(v[1], 3), "avg_us": round(v[1] / max(1, v[0]) * 1e3, 2)}
-                for k, v in af.profile_read(reset=True).items()}
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        sinfo, infos = step()
-    torch.cuda.synchronize()
-    sec = (time.perf_counter() - t0) / args.steps
+        kern, kern_raw = {}, {}
+        if not args.no_profile:
+            # per-kernel breakdown from one untimed profiled step; inside the timed steps only
+            # the dominant kernel carries events (on its launch stream)
+            af.profile_only(None)
+            af.profile_read(reset=True)
+            af.profile_enable(True)
+            step()
+            torch.cuda.synchronize()
+            af.profile_enable(False)
+            kern_raw = af.profile_read(reset=True)
+            kern = {k: {"launches": v[0], "total_ms": round(v[1], 3), "avg_us": round(v[1] / max(1, v[0]) * 1e3, 2)}
+                    for k, v in kern_raw.items()}
+            dom = max(kern_raw.items(), key=lambda kv: kv[1][1])[0]
+            af.profile_only([dom])
+            af.profile_enable(True)
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            sinfo, infos = step()
+        torch.cuda.synchronize()
+        sec = (time.perf_counter() - t0) / args.steps
+        kern_timed = {}
+        if not args.no_profile:
+            af.profile_enable(False)
+            kern_timed = af.profile_read(reset=True)
+            af.profile_only(None)
+        # G of the batch for the per-system algorithmic bytes
+        Pg = af.setup_batched(dA, off, 5, 1, 1e-2)
+        g_rp = Pg.export()[0].cpu().numpy()
+        Pg.close()
     its = np.array([i.iters for i in infos])
     worst = max(i.true_relres for i in infos)
     # plain form, one system after another (timed once after one warm-up system)
@@ -96,6 +120,30 @@ def batch_bench(args):
     print(f"[bench] {args.steps} steps: {sec * 1e3:.2f} ms/step batched (setup {sinfo.ms:.2f} ms, pcg "
           f"{infos[0].ms:.2f} ms, iterations {its.min()}..{its.max()}, worst true relres {worst:.2e}); "
           f"plain one by one {plain * 1e3:.1f} ms", file=sys.stderr, flush=True)
+    # aggregate PCG bandwidth: every system's algorithmic bytes per iteration (A, G and G^T once,
+    # row pointers, 15 vector passes) times its own iterations, over the batched solve's time
+    a_rp = A.row_ptr
+    sys_bytes = 0.0
+    for k in range(nsys):
+        o0, o1 = int(off[k]), int(off[k + 1])
+        nk, nnz_a, nnz_g = o1 - o0, int(a_rp[o1] - a_rp[o0]), int(g_rp[o1] - g_rp[o0])
+        per_it = 12.0 * nnz_a + 2 * (8 + 4) * nnz_g + 3 * 4 * (nk + 1) + 15 * 8 * nk
+        sys_bytes += per_it * int(infos[k].iters)
+    pcg_gbs = sys_bytes / (infos[0].ms * 1e-3) / 1e9
+    pcg_roof = {"kernel": "pcg (all systems, aggregate)", "bound": "hbm", "achieved": round(pcg_gbs, 1),
+                "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(pcg_gbs / PEAK_HBM_GBS, 4),
+                "bytes": sys_bytes, "pcg_ms": round(infos[0].ms, 3)}
+    roof = None
+    if kern_timed:
+        dom, (launches, ms) = max(kern_timed.items(), key=lambda kv: kv[1][1])
+        avg_s = ms / launches * 1e-3
+        byt = kernel_bytes(dom, A.n, A.nnz, int(g_rp[-1]), 8, 5, 6)
+        ach = byt / avg_s / 1e9
+        roof = {"kernel": dom, "bound": "hbm", "achieved": round(ach, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": round(ach / PEAK_HBM_GBS, 4), "traffic": measured_traffic(dom, args.workload),
+                "bytes_per_launch": byt, "avg_launch_us": round(avg_s * 1e6, 2)}
+    print(f"[bench] aggregate PCG {pcg_gbs:.0f} GB/s ({pcg_gbs / PEAK_HBM_GBS:.3f} of peak)", file=sys.stderr,
+          flush=True)
     out = {"metric": METRIC, "value": round(sec, 6), "unit": "s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": round(sec * 1e3, 3), "higher_is_better": False, "scaling": "weak",
            "vs_baseline": None, "dtype": "f64", "data": "synthetic",
@@ -103,7 +151,8 @@ def batch_bench(args):
                       "eps": 1e-2, "rtol": 1e-8},
            "setup_ms": round(sinfo.ms, 3), "pcg_ms": round(infos[0].ms, 3), "iters_min": int(its.min()),
            "iters_max": int(its.max()), "worst_true_relres": worst, "plain_one_by_one_s": round(plain, 4),
-           "speedup_vs_plain": round(plain / sec, 2), "roofline": None, "kernels": kern, "cpu_baseline": None}
+           "speedup_vs_plain": round(plain / sec, 2), "roofline": roof, "pcg_roofline": pcg_roof, "kernels": kern,
+           "tuned": choice, "cpu_baseline": None}
     print(json.dumps(out), flush=True)
 
 
@@ -736,6 +785,9 @@ def main():
                     help="serve: slot counts of the continuous-batching runs")
     ap.add_argument("--g-prec", default=None, choices=["f64", "f32"],
                     help="storage of G (default: the workload's own, FP32 for the 150^3 problem, else FP64)")
+    ap.add_argument("--tune", action="store_true",
+                    help="pick launch choices with the autotuner first (cached by shape) and apply them")
+    ap.add_argument("--tune-cache", default=None, help="JSON cache of the autotuner (default: none, tune afresh)")
     ap.add_argument("--grad-f32", action="store_true",
                     help="precision form's gradient: FP32 values of A in the gradient, FP64 factorisation")
     ap.add_argument("--no-forms", action="store_true",

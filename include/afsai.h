@@ -395,6 +395,10 @@ const char *afsai_last_error(void);
  *                             the pattern, else 64; 32 only when asked for).  A request smaller
  *                             than the pattern takes the next size that holds it.  Any choice
  *                             gives identical G
+ *   AFSAI_OPT_SETUP_CLAIM     wavefronts' worth of rows one atomic claim of the setup kernel takes
+ *                             from its XCD's counter (1..64; 0 automatic: enough rows for about
+ *                             4,000 table entries of work, at most 16).  Any choice gives
+ *                             identical G
  * Returns AFSAI_ERR_INVALID_ARG for an unknown option or value.  Not thread safe against
  * concurrent calls of the library.
  */
@@ -411,6 +415,7 @@ const char *afsai_last_error(void);
 #define AFSAI_OPT_SELL_UNEVEN 11
 #define AFSAI_OPT_SETUP_FORM 12
 #define AFSAI_OPT_SETUP_LANES 13
+#define AFSAI_OPT_SETUP_CLAIM 14
 int afsai_set_option(int32_t option, int64_t value);
 
 /*

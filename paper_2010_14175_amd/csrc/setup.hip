@@ -369,7 +369,8 @@ static int launch_rows(RowsKernel kern, size_t wdyn, int rpw, int mmax_t, int mm
     // (claims are counted in wavefronts' worth of rows: rpw rows each)
     int64_t claim64 = (4000 + row_work * rpw - 1) / std::max<int64_t>(1, row_work * rpw);
     claim64 = std::min<int64_t>(claim64, std::max<int64_t>(1, nlist / ((int64_t)rpw * nb * 4)));
-    const int claim = (int)std::min<int64_t>(16, std::max<int64_t>(1, claim64));
+    int claim = (int)std::min<int64_t>(16, std::max<int64_t>(1, claim64));
+    if (option(AFSAI_OPT_SETUP_CLAIM) > 0) claim = (int)option(AFSAI_OPT_SETUP_CLAIM);
     hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, (int64_t)nx, counters, 0);
     {
         ProfScope ps("afsai_rows", s);
