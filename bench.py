@@ -195,11 +195,11 @@ def serve_bench(args):
         bs.append(af.spmv(dA, xq))
     torch.cuda.synchronize()
 
-    def run(slots, arrivals):
+    def run(slots, arrivals, max_heavy=0):
         """Serves the requests arriving at `arrivals` (s) with `slots` slots; latency = completion
         minus arrival."""
         srv = af.Server(args.budget_gb * 2**30, slots, 5, 1, 1e-2, rtol=1e-8, g_prec=af.F32,
-                        setup_threads=4 if slots > 1 else 1)
+                        setup_threads=4 if slots > 1 else 1, max_heavy=max_heavy)
         xs = [torch.empty_like(b) for b in bs]
         t0 = time.perf_counter()
         sub, lat, bad = {}, [], 0
@@ -232,16 +232,22 @@ def serve_bench(args):
     for load in (0.5, 0.8):
         qps = load * sat
         arrivals = np.cumsum(-np.log(rng_u) / qps)
-        for name, slots in [("plain_fifo", 1)] + [(f"continuous{k}", k) for k in args.serve_slots]:
-            lat, span, bad = run(slots, arrivals)
+        runs = [("plain_fifo", 1, 0)] + [(f"continuous{k}", k, 0) for k in args.serve_slots]
+        if args.serve_uncapped:
+            runs += [(f"continuous{k}_uncapped", k, -1) for k in args.serve_slots]
+        for mh in args.serve_heavy:
+            runs += [(f"continuous{k}_heavy{mh}", k, mh) for k in args.serve_slots]
+        for name, slots, mh in runs:
+            lat, span, bad = run(slots, arrivals, mh)
             key = f"{name}@{load}"
-            res[key] = {"qps": round(qps, 3), "slots": slots, "mean_s": round(float(lat.mean()), 4),
+            res[key] = {"qps": round(qps, 3), "slots": slots, "max_heavy": mh, "mean_s": round(float(lat.mean()), 4),
                         "p50_s": round(float(np.percentile(lat, 50)), 4),
                         "p99_s": round(float(np.percentile(lat, 99)), 4), "solves_per_s": round(nreq / span, 3),
                         "failed": bad}
             print(f"[bench] {key}: mean {res[key]['mean_s']} s, p50 {res[key]['p50_s']} s, p99 {res[key]['p99_s']} s, "
                   f"{res[key]['solves_per_s']} solves/s", file=sys.stderr, flush=True)
-    best = min((k for k in res if k.startswith("continuous") and k.endswith("@0.8")), key=lambda k: res[k]["p99_s"])
+    best = min((k for k in res if k.startswith("continuous") and k.endswith("@0.8") and "_" not in k.split("@")[0]),
+               key=lambda k: res[k]["p99_s"])
     out = {"metric": METRIC, "value": res[best]["p99_s"], "unit": f"s (p99 latency, {best})",
            "n_gpus": 1, "steps": nreq, "warmup": 0, "higher_is_better": False, "scaling": "weak",
            "vs_baseline": None, "dtype": "f64 (G stored f32)", "data": "synthetic",
@@ -778,9 +784,13 @@ def main():
     ap.add_argument("--workload", default="elast27_150",
                     choices=sorted(list(workloads()) + list(BATCH_WORKLOADS) + ["serve", "jacobi_compare", "spmm"]))
     ap.add_argument("--with-largest", action="store_true", help="jacobi_compare: add the 150^3 27-point workload")
-    ap.add_argument("--requests", type=int, default=300, help="serve: number of requests")
+    ap.add_argument("--requests", type=int, default=600, help="serve: number of requests")
     ap.add_argument("--pool", type=int, default=16, help="serve: distinct systems the requests draw from")
     ap.add_argument("--budget-gb", type=int, default=96, help="serve: device memory budget of the servers")
+    ap.add_argument("--serve-heavy", type=int, nargs="*", default=[],
+                    help="serve: also run continuous batching with these limits of heavy requests at a time")
+    ap.add_argument("--serve-uncapped", action="store_true",
+                    help="serve: also run continuous batching without the limit of one heavy request at a time")
     ap.add_argument("--serve-slots", type=int, nargs="+", default=[2, 4],
                     help="serve: slot counts of the continuous-batching runs")
     ap.add_argument("--g-prec", default=None, choices=["f64", "f32"],

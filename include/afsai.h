@@ -233,6 +233,8 @@ typedef struct afsai_server_config {
     afsai_params params;    /* setup parameters of every request */
     double rtol;            /* PCG stopping tolerance of every request */
     int32_t maxit;          /* PCG iteration limit of every request */
+    int32_t max_heavy;      /* heavy requests admitted at once (0: 1; < 0: no limit) */
+    int64_t heavy_nnz;      /* matrix entries from which a request is heavy (0: 2^22) */
 } afsai_server_config;
 
 typedef struct afsai_request_result {

@@ -65,7 +65,7 @@ class ParamsStruct(ctypes.Structure):
 
 ServerConfigStruct._fields_ = [("hbm_budget", ctypes.c_size_t), ("max_slots", ctypes.c_int32),
                                ("setup_threads", ctypes.c_int32), ("params", ParamsStruct), ("rtol", ctypes.c_double),
-                               ("maxit", ctypes.c_int32)]
+                               ("maxit", ctypes.c_int32), ("max_heavy", ctypes.c_int32), ("heavy_nnz", ctypes.c_int64)]
 
 
 class SetupInfoStruct(ctypes.Structure):
@@ -416,10 +416,11 @@ class Server:
     budget allow, set up and solved concurrently; results come back through ``poll``."""
 
     def __init__(self, hbm_budget: int, max_slots: int, kmax: int, s: int, eps: float, rtol: float = 1e-8,
-                 maxit: int = 100000, g_prec: int = F64, setup_threads: int = 2, tie_rtol: float = TIE_RTOL):
+                 maxit: int = 100000, g_prec: int = F64, setup_threads: int = 2, tie_rtol: float = TIE_RTOL,
+                 max_heavy: int = 0, heavy_nnz: int = 0):
         cfg = ServerConfigStruct(int(hbm_budget), int(max_slots), int(setup_threads),
                                  ParamsStruct(int(kmax), int(s), float(eps), float(tie_rtol), int(g_prec), 0),
-                                 float(rtol), int(maxit))
+                                 float(rtol), int(maxit), int(max_heavy), int(heavy_nnz))
         h = ctypes.c_void_p()
         _check(lib().afsai_server_create(ctypes.byref(cfg), ctypes.byref(h)), "afsai_server_create")
         self._h = h

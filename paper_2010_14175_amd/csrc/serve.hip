@@ -5,7 +5,11 @@
 // of the admitted requests' device footprints (setup temporaries, G and G^T, the SELL copy of
 // A, the Krylov vectors) stays within the budget; a finished request frees its slot and its
 // memory at once and the waiting requests behind it are admitted (continuous batching, not a
-// queue served one at a time).  Every admitted request owns a HIP stream.  Setup workers (host
+// queue served one at a time).  Heavy requests (many matrix entries) are admitted at most
+// max_heavy at a time, in arrival order among themselves; lighter requests behind a heavy one
+// that has to wait are admitted past it.  Two heavy solves sharing the device would both finish
+// late (the slowest requests set the tail latency), while light ones take little of it.  The
+// scheduler enqueues the next chunks of the solving requests lightest first.  Every admitted request owns a HIP stream.  Setup workers (host
 // threads) run the setups of newly admitted requests while one scheduler thread advances the
 // PCG iterations of all solving requests without blocking: each step enqueues the next chunk of
 // a request whose previous chunk has completed, so the kernels of many requests are in flight
@@ -34,6 +38,7 @@ struct Request {
     const double *b = nullptr;
     double *x = nullptr;
     size_t footprint = 0;
+    bool heavy = false;
     double t_submit = 0, t_admit = 0, t_setup = 0, t_done = 0;
     afsai_precond P = nullptr;
     hipStream_t stream = nullptr;
@@ -80,13 +85,24 @@ struct afsai_server_s {
 
     double now() const { return std::chrono::duration<double, std::milli>(Clock::now() - t0).count(); }
 
-    // admits waiting requests in arrival order while a slot and the memory are free (mu held)
+    int heavy_in = 0;  // heavy requests admitted
+
+    int heavy_cap() const { return cfg.max_heavy == 0 ? 1 : cfg.max_heavy; }
+
+    // admits waiting requests in arrival order while a slot and the memory are free; a heavy
+    // request over the heavy cap waits, and the lighter ones behind it may pass (mu held)
     void admit_locked() {
-        while (!waiting.empty() && slots < cfg.max_slots && used + waiting.front()->footprint <= cfg.hbm_budget) {
-            Request *r = waiting.front();
-            waiting.pop_front();
+        for (auto it = waiting.begin(); it != waiting.end() && slots < cfg.max_slots;) {
+            Request *r = *it;
+            if (used + r->footprint > cfg.hbm_budget) break;  // memory: keep arrival order
+            if (r->heavy && heavy_cap() > 0 && heavy_in >= heavy_cap()) {
+                ++it;
+                continue;
+            }
+            it = waiting.erase(it);
             used += r->footprint;
             ++slots;
+            heavy_in += r->heavy ? 1 : 0;
             r->t_admit = now();
             to_setup.push_back(r);
             cv_work.notify_one();
@@ -115,6 +131,7 @@ struct afsai_server_s {
         if (r->stream) streams.push_back(r->stream);
         used -= r->footprint;
         --slots;
+        heavy_in -= r->heavy ? 1 : 0;
         --outstanding;
         completed.push_back(res);
         delete r;
@@ -182,6 +199,9 @@ struct afsai_server_s {
                 }
             }
             bool progressed = !fresh.empty();
+            // lightest first: their next chunks go to the device ahead of the heavy ones'
+            std::stable_sort(solving.begin(), solving.end(),
+                             [](const Request *a, const Request *b) { return a->A.nnz < b->A.nnz; });
             for (size_t k = 0; k < solving.size();) {
                 Request *r = solving[k];
                 bool fin = false;
@@ -193,8 +213,7 @@ struct afsai_server_s {
                 progressed = true;
                 if (rc == AFSAI_OK) rc = pcg_task_finish(r->task, &r->info);
                 r->status = rc;
-                solving[k] = solving.back();
-                solving.pop_back();
+                solving.erase(solving.begin() + (std::ptrdiff_t)k);
                 complete(r);
             }
             if (!progressed && !solving.empty()) {
@@ -251,6 +270,7 @@ int afsai_server_submit(afsai_server S, const afsai_csr *A, const afsai_params *
     r->b = b;
     r->x = x;
     r->footprint = footprint(*A, r->params);
+    r->heavy = (int64_t)A->nnz >= (S->cfg.heavy_nnz > 0 ? S->cfg.heavy_nnz : ((int64_t)1 << 22));
     if (r->footprint > S->cfg.hbm_budget) {
         const size_t fp = r->footprint;
         delete r;

@@ -51,8 +51,9 @@ def _requests():
 X_RTOL = 1e-10
 
 
-def _serve(af, probs, budget, slots, g_prec=0):
-    srv = af.Server(budget, slots, KMAX, S, EPS, rtol=1e-8, setup_threads=2, g_prec=g_prec)
+def _serve(af, probs, budget, slots, g_prec=0, max_heavy=0, heavy_nnz=0):
+    srv = af.Server(budget, slots, KMAX, S, EPS, rtol=1e-8, setup_threads=2, g_prec=g_prec, max_heavy=max_heavy,
+                    heavy_nnz=heavy_nnz)
     data = []
     for pb in probs:
         dA = af.DeviceCSR.from_host(pb.A)
@@ -133,6 +134,31 @@ def test_admission_respects_budget_and_slots(af):
     admits = [r.admit_ms for r in res]
     assert admits == sorted(admits)
     assert any(b.admit_ms < a.done_ms for a, b in zip(res, res[1:]))
+
+
+def test_heavy_requests_one_at_a_time(af):
+    """Requests from heavy_nnz entries on are heavy: at most one of them is admitted at any
+    instant, they are admitted in arrival order among themselves, lighter ones pass a heavy
+    one that waits, and every result is still the one the request gets alone."""
+    probs = _requests()
+    nnz = sorted(pb.A.nnz for pb in probs)
+    heavy_nnz = nnz[len(nnz) // 2]  # the larger half is heavy
+    out = _serve(af, probs, 1 << 40, 4, max_heavy=1, heavy_nnz=heavy_nnz)
+    res = [r for _, r in out]
+    assert all(r.status == af.OK for r in res)
+    heavy = [pb.A.nnz >= heavy_nnz for pb in probs]
+    events = sorted([(r.admit_ms, 1, h) for r, h in zip(res, heavy)] + [(r.done_ms, 0, h) for r, h in zip(res, heavy)],
+                    key=lambda e: (e[0], e[1]))
+    held = 0
+    for _, kind, h in events:
+        if h:
+            held += 1 if kind else -1
+        assert held <= 1
+    hadm = [r.admit_ms for r, h in zip(res, heavy) if h]
+    assert hadm == sorted(hadm)
+    for (x, r), pb in zip(out, probs):
+        xa, ia = _alone(af, pb)
+        assert r.iters == ia.iters and np.array_equal(x.view(np.int64), xa.view(np.int64)), pb.name
 
 
 def test_refuses_oversize_and_isolates_failures(af):
