@@ -311,7 +311,8 @@ def spmm_bench(args):
     """Y = A X for blocks of 1, 2, 4 and 8 right-hand sides with A of the 27-point 64^3
     workload: the product kernel's time per block (HIP events on its launch stream, median of
     the steps) and per right-hand side, and its algorithmic bytes (every matrix entry once, X
-    and Y once) over that time."""
+    and Y once) over that time; beside it the wall time of a whole call, unprepared (A
+    converted to its SELL layout in the call) and with a prepared A."""
     import torch
 
     import paper_2010_14175_amd as af
@@ -321,6 +322,18 @@ def spmm_bench(args):
     dA = af.DeviceCSR.from_host(pb.A)
     n, nnz = pb.n, pb.A.nnz
     X8 = torch.from_numpy(synth.uniform(13, 5, n * 8, -1.0, 1.0).reshape(n, 8)).cuda()
+    M = af.PreparedMatrix(dA)
+
+    def wall_ms(fn):
+        ms = []
+        for _ in range(args.steps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            ms.append((time.perf_counter() - t0) * 1e3)
+        return float(np.median(ms))
+
     res = {}
     for k in (1, 2, 4, 8):
         X = X8[:, :k].contiguous()
@@ -342,10 +355,14 @@ def spmm_bench(args):
             af.profile_only(None)
         t = float(np.median(us))
         byt = 12.0 * nnz + 4.0 * (n + 1) + 16.0 * k * n
+        for _ in range(args.warmup):
+            M.spmm(X, Y)
+        w_un, w_pr = wall_ms(lambda: af.spmm(dA, X, Y)), wall_ms(lambda: M.spmm(X, Y))
         res[f"k{k}"] = {"us": round(t, 2), "us_per_rhs": round(t / k, 2), "gbs": round(byt / (t * 1e-6) / 1e9, 1),
-                        "bytes": byt}
+                        "bytes": byt, "wall_us": round(w_un * 1e3, 1), "wall_us_prepared": round(w_pr * 1e3, 1)}
         print(f"[bench] spmm k={k}: {t:.1f} us ({t / k:.1f} us per right-hand side, "
-              f"{res[f'k{k}']['gbs']} GB/s algorithmic)", file=sys.stderr, flush=True)
+              f"{res[f'k{k}']['gbs']} GB/s algorithmic); wall per call {w_un * 1e3:.1f} us, prepared "
+              f"{w_pr * 1e3:.1f} us", file=sys.stderr, flush=True)
     # PCG over blocks (one setup reused): wall time of the solve per right-hand side, against
     # pcg_solve of one right-hand side
     P = af.setup(dA, pb.kmax, pb.s, pb.eps)
@@ -363,6 +380,9 @@ def spmm_bench(args):
         torch.cuda.synchronize()
         ms.append((time.perf_counter() - t0) * 1e3)
     solves["pcg_solve"] = {"ms": round(float(np.median(ms)), 3), "iters": inf1.iters}
+    for _ in range(args.warmup):
+        M.pcg_solve(P, b0, rtol=pb.rtol)
+    solves["pcg_solve_prepared"] = {"ms": round(wall_ms(lambda: M.pcg_solve(P, b0, rtol=pb.rtol)), 3)}
     for k in (1, 8):
         B = Bt[:, :k].contiguous()
         for _ in range(args.warmup):
@@ -379,9 +399,10 @@ def spmm_bench(args):
                                  "iters": [i.iters for i in infs], "worst_true_relres": max(i.true_relres for i in infs)}
         print(f"[bench] pcg_solve_multi k={k}: {t:.2f} ms ({t / k:.2f} ms per right-hand side, iterations "
               f"{[i.iters for i in infs]})", file=sys.stderr, flush=True)
-    print(f"[bench] pcg_solve: {solves['pcg_solve']['ms']:.2f} ms ({inf1.iters} iterations)", file=sys.stderr,
-          flush=True)
+    print(f"[bench] pcg_solve: {solves['pcg_solve']['ms']:.2f} ms ({inf1.iters} iterations), prepared A "
+          f"{solves['pcg_solve_prepared']['ms']:.2f} ms", file=sys.stderr, flush=True)
     P.close()
+    M.close()
     res["pcg"] = solves
     out = {"metric": "SpMM time per right-hand side, k = 8 against k = 1", "value":
            round(res["k8"]["us_per_rhs"] / res["k1"]["us"], 4), "unit": "ratio", "n_gpus": 1, "steps": args.steps,

@@ -291,6 +291,43 @@ int afsai_spmv(const afsai_csr *A, const double *x, double *y, void *stream);
 int afsai_spmm(const afsai_csr *A, int32_t k, const double *X, double *Y, void *stream);
 
 /*
+ * Prepared matrices: A's SELL-64 layout (the layout pcg_solve and afsai_spmm convert A to on
+ * every call) made once and kept, for callers that multiply by, or solve with, one matrix many
+ * times.  The products and iterates are those of the unprepared calls bit for bit.
+ */
+typedef struct afsai_matrix_s *afsai_matrix;
+
+/*
+ * afsai_matrix_prepare -- converts A to its SELL-64 layout on the current device.
+ *   A's arrays are read during the call only; the handle owns a device copy (about
+ *   12 bytes per entry plus padding) and A's values may change afterwards without affecting it
+ *   (prepare again to take them).  *out = NULL on failure.  Synchronous on stream.
+ *   Errors: AFSAI_ERR_INVALID_ARG, AFSAI_ERR_NO_MEMORY, AFSAI_ERR_TOO_LARGE, AFSAI_ERR_HIP.
+ */
+int afsai_matrix_prepare(const afsai_csr *A, void *stream, afsai_matrix *out);
+
+/* afsai_matrix_destroy -- waits for the device, then frees the handle (NULL is ignored). */
+void afsai_matrix_destroy(afsai_matrix M);
+
+/*
+ * afsai_spmm_prepared -- afsai_spmm with a prepared A (same arguments and results; no
+ *   conversion, no allocation).  Errors: as afsai_spmm, and AFSAI_ERR_INVALID_ARG when the
+ *   current device is not the one M was prepared on, or M holds a split layout (prepared with
+ *   AFSAI_OPT_SELL_UNEVEN = 1).  Synchronous on stream.
+ */
+int afsai_spmm_prepared(afsai_matrix M, int32_t k, const double *X, double *Y, void *stream);
+
+/*
+ * pcg_solve_prepared -- pcg_solve (Sec. 5.2) with a prepared A: the same iterates, x and info
+ *   bit for bit as pcg_solve with the A that M was prepared from (with the default SELL
+ *   product for A), without converting A.  P: a single-system preconditioner or NULL.
+ *   Errors: as pcg_solve, and AFSAI_ERR_INVALID_ARG for a device mismatch or a split layout.
+ *   Synchronous.
+ */
+int pcg_solve_prepared(afsai_matrix M, afsai_precond P, const double *b, double *x, double rtol, int32_t maxit,
+                       void *stream, afsai_pcg_info *info);
+
+/*
  * pcg_solve_multi -- PCG (M^-1 = G^T G, or plain CG with P == NULL) for k right-hand sides at
  *   once, A X = B: k independent textbook recurrences (each with its own alpha, beta, rho and
  *   stopping test ||r_j|| <= rtol ||b_j||, as pcg_solve) whose products with A, G and G^T are

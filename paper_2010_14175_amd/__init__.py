@@ -33,6 +33,7 @@ STOP_KMAX, STOP_EPS, STOP_NOCAND = 0, 1, 2
 EXPORTS = ("afsai_setup", "afsai_apply", "afsai_apply_noalloc", "pcg_solve", "afsai_setup_batched", "pcg_solve_batched",
            "afsai_server_create", "afsai_server_submit", "afsai_server_poll", "afsai_server_pending",
            "afsai_server_destroy", "afsai_spmv", "afsai_spmm", "pcg_solve_multi",
+           "afsai_matrix_prepare", "afsai_matrix_destroy", "afsai_spmm_prepared", "pcg_solve_prepared",
            "afsai_get_setup_info", "afsai_export",
            "afsai_export_rows", "afsai_import", "afsai_destroy", "afsai_last_error", "afsai_set_option",
            "afsai_release_cache",
@@ -110,6 +111,11 @@ def lib():
         L.afsai_spmm.argtypes = [P(CsrStruct), ctypes.c_int32, vp, vp, vp]
         L.pcg_solve_multi.argtypes = [P(CsrStruct), vp, ctypes.c_int32, vp, vp, ctypes.c_double, i32, vp,
                                       P(PcgInfoStruct)]
+        L.afsai_matrix_prepare.argtypes = [P(CsrStruct), vp, P(vp)]
+        L.afsai_matrix_destroy.argtypes = [vp]
+        L.afsai_matrix_destroy.restype = None
+        L.afsai_spmm_prepared.argtypes = [vp, ctypes.c_int32, vp, vp, vp]
+        L.pcg_solve_prepared.argtypes = [vp, vp, vp, vp, ctypes.c_double, i32, vp, P(PcgInfoStruct)]
         L.afsai_server_create.argtypes = [P(ServerConfigStruct), P(vp)]
         L.afsai_server_submit.argtypes = [vp, P(CsrStruct), P(ParamsStruct), vp, vp, P(ctypes.c_int64)]
         L.afsai_server_poll.argtypes = [vp, P(RequestResultStruct), i32, P(i32), i32]
@@ -130,7 +136,7 @@ def lib():
         L.afsai_profile_only.argtypes = [ctypes.c_char_p]
         L.afsai_profile_read.argtypes = [P(KernelTimeStruct), i32, P(i32), i32]
         for name in EXPORTS:
-            if name not in ("afsai_destroy", "afsai_last_error"):
+            if name not in ("afsai_destroy", "afsai_matrix_destroy", "afsai_last_error"):
                 getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -329,6 +335,66 @@ def pcg_solve(A: DeviceCSR, P: Preconditioner | None, b, x=None, rtol: float = 1
     if raise_on_error:
         _check(rc, "pcg_solve", allow=(OK, ERR_NOT_CONVERGED))
     return x, PcgInfo(rc, inf.iters, bool(inf.converged), inf.relres, inf.true_relres, inf.ms)
+
+
+class PreparedMatrix:
+    """A's SELL-64 layout made once (``afsai_matrix_prepare``), for repeated products and
+    solves with one matrix; ``spmm`` and ``pcg_solve`` give the unprepared calls' results bit
+    for bit."""
+
+    def __init__(self, A: DeviceCSR, stream=None):
+        self.n = A.n
+        h = ctypes.c_void_p()
+        st = A.struct
+        _check(lib().afsai_matrix_prepare(ctypes.byref(st), _stream(stream), ctypes.byref(h)), "afsai_matrix_prepare")
+        self._h = h
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise RuntimeError("PreparedMatrix: handle has been closed")
+        return self._h
+
+    def spmm(self, X, Y=None, stream=None):
+        """Y = A X for an (n, k) row-major block of k = 1, 2, 4 or 8 vectors."""
+        import torch
+
+        if X.dim() != 2 or X.shape[0] != self.n or not X.is_contiguous() or X.dtype != torch.float64:
+            raise ValueError("PreparedMatrix.spmm: X must be a contiguous float64 (n, k) tensor")
+        if Y is None:
+            Y = torch.empty_like(X)
+        _check_dev(Y, tuple(X.shape), "PreparedMatrix.spmm: Y")
+        _check(lib().afsai_spmm_prepared(self.handle, int(X.shape[1]), _ptr(X), _ptr(Y), _stream(stream)),
+               "afsai_spmm_prepared")
+        return Y
+
+    def pcg_solve(self, P: Preconditioner | None, b, x=None, rtol: float = 1e-8, maxit: int | None = None,
+                  stream=None, raise_on_error: bool = True):
+        """``pcg_solve_prepared``: returns (x, PcgInfo) as ``pcg_solve``."""
+        import torch
+
+        _check_dev(b, (self.n,), "PreparedMatrix.pcg_solve: b")
+        if x is None:
+            x = torch.zeros_like(b)
+        _check_dev(x, (self.n,), "PreparedMatrix.pcg_solve: x")
+        maxit = self.n if maxit is None else int(maxit)
+        inf = PcgInfoStruct()
+        rc = lib().pcg_solve_prepared(self.handle, None if P is None else P.handle, _ptr(b), _ptr(x), float(rtol),
+                                      maxit, _stream(stream), ctypes.byref(inf))
+        if raise_on_error:
+            _check(rc, "pcg_solve_prepared", allow=(OK, ERR_NOT_CONVERGED))
+        return x, PcgInfo(rc, inf.iters, bool(inf.converged), inf.relres, inf.true_relres, inf.ms)
+
+    def close(self):
+        if self._h:
+            lib().afsai_matrix_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def pcg_solve_multi(A: DeviceCSR, P: Preconditioner | None, B, rtol: float = 1e-8, maxit: int | None = None,

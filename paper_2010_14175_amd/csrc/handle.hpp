@@ -29,6 +29,13 @@ struct afsai_precond_s {
     std::vector<int32_t> seg_row0;
 };
 
+// The opaque prepared-matrix handle behind afsai_matrix: A's SELL-64 layout, converted once.
+struct afsai_matrix_s {
+    int device = -1;
+    afsai_csr A{};  // the caller's CSR (n, nnz; its arrays are not read after the conversion)
+    afsai::Sell S;
+};
+
 namespace afsai {
 // A single-system solve as a task for the serving loop (solve.hip): begin enqueues the start
 // on `stream`; advance never waits when block is false; finish waits and fills info.

@@ -1195,9 +1195,11 @@ static hipStream_t capture_stream(int device) {
 
 class PcgRun {
   public:
+    // prepared: A's SELL layout converted beforehand (one system; not owned), else converted
+    // by begin() for this solve
     PcgRun(const afsai_csr &A, afsai_precond P, int nsys, const int32_t *row0, const double *b, double *x,
-           double rtol, int32_t maxit, hipStream_t s)
-        : A_(A), P_(P), nsys_(nsys), b_(b), x_(x), rtol_(rtol), maxit_(maxit), s_(s) {
+           double rtol, int32_t maxit, hipStream_t s, const Sell *prepared = nullptr)
+        : A_(A), P_(P), nsys_(nsys), b_(b), x_(x), rtol_(rtol), maxit_(maxit), s_(s), prepared_(prepared) {
         if (nsys > 1 && row0) row0_.assign(row0, row0 + nsys + 1);
         else row0_ = {0, A.n};
     }
@@ -1207,7 +1209,7 @@ class PcgRun {
             if (gexec_[k]) (void)hipGraphExecDestroy(gexec_[k]);
             if (graph_[k]) (void)hipGraphDestroy(graph_[k]);
         }
-        sell_free(&As_);
+        if (!prepared_) sell_free(&As_);
         for (hipEvent_t e : {t0_, t1_, ev_[0], ev_[1], ev_[2], ev_[3]})
             if (e) (void)hipEventDestroy(e);
         if (hsc_) (void)hipHostFree(hsc_);
@@ -1256,8 +1258,10 @@ class PcgRun {
 
         // A in the SELL-64 layout for the iteration (one conversion per solve); CSR only for one
         // system when asked for
-        use_sell_ = option(AFSAI_OPT_PCG_CSR_A) == 0 || nsys_ > 1;
-        if (use_sell_) {
+        use_sell_ = option(AFSAI_OPT_PCG_CSR_A) == 0 || nsys_ > 1 || prepared_;
+        if (prepared_) {
+            As_ = *prepared_;
+        } else if (use_sell_) {
             ProfScope ps("sell_A", s_);
             if ((rc = sell_from_csr(n, A_.nnz, A_.row_ptr, A_.col_idx, A_.val, false, false, &As_, di_, s_, seg)))
                 return rc;
@@ -1558,6 +1562,7 @@ class PcgRun {
     DeviceInfo di_;
     BatchMaps bm_;
     DevBuf own_;
+    const Sell *prepared_ = nullptr;
     Sell As_;
     bool use_sell_ = true, fused_ = false, started_ = false, done_ = false, use_graph_ = false;
     hipGraph_t graph_[2] = {nullptr, nullptr};
@@ -1602,8 +1607,8 @@ int pcg_task_finish(PcgTask *t, afsai_pcg_info *info) { return t->run.finish(inf
 void pcg_task_free(PcgTask *t) { delete t; }
 
 static int pcg_batch(const afsai_csr *A, afsai_precond P, int nsys, const int32_t *row0, const double *b, double *x,
-                     double rtol, int32_t maxit, hipStream_t s, afsai_pcg_info *info) {
-    PcgRun run(*A, P, nsys, row0, b, x, rtol, maxit, s);
+                     double rtol, int32_t maxit, hipStream_t s, afsai_pcg_info *info, const Sell *prepared = nullptr) {
+    PcgRun run(*A, P, nsys, row0, b, x, rtol, maxit, s, prepared);
     int rc = run.begin();
     if (rc) return rc;
     bool fin = false;
@@ -1754,24 +1759,12 @@ int pcg_solve_multi(const afsai_csr *A, afsai_precond P, int32_t k, const double
     return rc;
 }
 
-int afsai_spmm(const afsai_csr *A, int32_t k, const double *X, double *Y, void *stream) {
-    if (k != 1 && k != 2 && k != 4 && k != 8) AFSAI_FAIL(AFSAI_ERR_INVALID_ARG, "afsai_spmm: k = %d (1, 2, 4 or 8)", k);
-    int rc = check_csr_arg(A, "afsai_spmm");
-    if (rc) return rc;
-    if (!X || !Y) AFSAI_FAIL(AFSAI_ERR_INVALID_ARG, "afsai_spmm: null block");
-    if (X == Y) AFSAI_FAIL(AFSAI_ERR_INVALID_ARG, "afsai_spmm: X and Y alias");
-    DeviceInfo di;
-    if ((rc = device_info(&di))) return rc;
-    hipStream_t s = (hipStream_t)stream;
-    Sell S;
-    {
-        ProfScope ps("sell_A", s);
-        if ((rc = sell_from_csr(A->n, A->nnz, A->row_ptr, A->col_idx, A->val, false, false, &S, di, s))) return rc;
-    }
-    if (S.tail || S.srow0) {
-        sell_free(&S);
-        AFSAI_FAIL(AFSAI_ERR_INVALID_ARG, "afsai_spmm: split SELL layouts (AFSAI_OPT_SELL_UNEVEN = 1) are not supported");
-    }
+}  // extern "C"
+
+namespace afsai {
+
+// Y = A X with A's SELL layout S (no split layout), k in {1, 2, 4, 8}; synchronous on s
+static int spmm_sell(const Sell &S, int32_t k, const double *X, double *Y, const DeviceInfo &di, hipStream_t s) {
     {
         ProfScope ps("spmm_A", s);
         const int nb = blocks_for_slices(S.nslices, di);
@@ -1793,9 +1786,109 @@ int afsai_spmm(const afsai_csr *A, int32_t k, const double *X, double *Y, void *
     }
     const hipError_t le = hipGetLastError();
     const hipError_t se = hipStreamSynchronize(s);
-    sell_free(&S);
     if (le != hipSuccess || se != hipSuccess) AFSAI_FAIL(AFSAI_ERR_HIP, "afsai_spmm: %s", hipGetErrorString(le != hipSuccess ? le : se));
     return AFSAI_OK;
+}
+
+static int spmm_args(int32_t k, const double *X, double *Y, const char *who) {
+    if (k != 1 && k != 2 && k != 4 && k != 8) AFSAI_FAIL(AFSAI_ERR_INVALID_ARG, "%s: k = %d (1, 2, 4 or 8)", who, k);
+    if (!X || !Y) AFSAI_FAIL(AFSAI_ERR_INVALID_ARG, "%s: null block", who);
+    if (X == Y) AFSAI_FAIL(AFSAI_ERR_INVALID_ARG, "%s: X and Y alias", who);
+    return AFSAI_OK;
+}
+
+}  // namespace afsai
+
+extern "C" {
+
+int afsai_spmm(const afsai_csr *A, int32_t k, const double *X, double *Y, void *stream) {
+    int rc = spmm_args(k, X, Y, "afsai_spmm");
+    if (rc) return rc;
+    if ((rc = check_csr_arg(A, "afsai_spmm"))) return rc;
+    DeviceInfo di;
+    if ((rc = device_info(&di))) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    Sell S;
+    {
+        ProfScope ps("sell_A", s);
+        if ((rc = sell_from_csr(A->n, A->nnz, A->row_ptr, A->col_idx, A->val, false, false, &S, di, s))) return rc;
+    }
+    if (S.tail || S.srow0) {
+        sell_free(&S);
+        AFSAI_FAIL(AFSAI_ERR_INVALID_ARG, "afsai_spmm: split SELL layouts (AFSAI_OPT_SELL_UNEVEN = 1) are not supported");
+    }
+    rc = spmm_sell(S, k, X, Y, di, s);
+    sell_free(&S);
+    return rc;
+}
+
+int afsai_matrix_prepare(const afsai_csr *A, void *stream, afsai_matrix *out) {
+    clear_error();
+    if (out) *out = nullptr;
+    if (!out) AFSAI_FAIL(AFSAI_ERR_INVALID_ARG, "afsai_matrix_prepare: null handle pointer");
+    int rc = check_csr_arg(A, "afsai_matrix_prepare");
+    if (rc) return rc;
+    DeviceInfo di;
+    if ((rc = device_info(&di))) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    afsai_matrix M = new afsai_matrix_s();
+    M->device = di.device;
+    M->A = *A;
+    {
+        ProfScope ps("sell_A", s);
+        rc = sell_from_csr(A->n, A->nnz, A->row_ptr, A->col_idx, A->val, false, false, &M->S, di, s);
+    }
+    if (rc == AFSAI_OK && hipStreamSynchronize(s) != hipSuccess) rc = set_error_code(AFSAI_ERR_HIP, "afsai_matrix_prepare: synchronisation failed");
+    if (rc != AFSAI_OK) {
+        sell_free(&M->S);
+        delete M;
+        return rc;
+    }
+    *out = M;
+    return AFSAI_OK;
+}
+
+void afsai_matrix_destroy(afsai_matrix M) {
+    if (!M) return;
+    (void)hipDeviceSynchronize();
+    sell_free(&M->S);
+    delete M;
+}
+
+int afsai_spmm_prepared(afsai_matrix M, int32_t k, const double *X, double *Y, void *stream) {
+    if (!M) AFSAI_FAIL(AFSAI_ERR_INVALID_ARG, "afsai_spmm_prepared: null matrix");
+    int rc = spmm_args(k, X, Y, "afsai_spmm_prepared");
+    if (rc) return rc;
+    if (M->S.tail || M->S.srow0)
+        AFSAI_FAIL(AFSAI_ERR_INVALID_ARG, "afsai_spmm_prepared: split SELL layouts (AFSAI_OPT_SELL_UNEVEN = 1) are not supported");
+    DeviceInfo di;
+    if ((rc = device_info(&di))) return rc;
+    if (di.device != M->device)
+        AFSAI_FAIL(AFSAI_ERR_INVALID_ARG, "afsai_spmm_prepared: matrix prepared on device %d, current device %d",
+                   M->device, di.device);
+    return spmm_sell(M->S, k, X, Y, di, (hipStream_t)stream);
+}
+
+int pcg_solve_prepared(afsai_matrix M, afsai_precond P, const double *b, double *x, double rtol, int32_t maxit,
+                       void *stream, afsai_pcg_info *info) {
+    clear_error();
+    if (!M) AFSAI_FAIL(AFSAI_ERR_INVALID_ARG, "pcg_solve_prepared: null matrix");
+    if (!b || !x) AFSAI_FAIL(AFSAI_ERR_INVALID_ARG, "pcg_solve_prepared: null b or x");
+    if (!(rtol > 0.0) || maxit < 0)
+        AFSAI_FAIL(AFSAI_ERR_INVALID_ARG, "pcg_solve_prepared: rtol = %g, maxit = %d", rtol, maxit);
+    if (P && P->n != M->A.n)
+        AFSAI_FAIL(AFSAI_ERR_INVALID_ARG, "pcg_solve_prepared: preconditioner has n = %d, A has n = %d", P->n, M->A.n);
+    if (P && P->seg_row0.size() > 2)
+        AFSAI_FAIL(AFSAI_ERR_INVALID_ARG, "pcg_solve_prepared: the preconditioner is for a batch");
+    if (M->S.tail || M->S.srow0)
+        AFSAI_FAIL(AFSAI_ERR_INVALID_ARG, "pcg_solve_prepared: split SELL layouts are not supported for A");
+    DeviceInfo di;
+    int rc = device_info(&di);
+    if (rc) return rc;
+    if (di.device != M->device || (P && P->device != M->device))
+        AFSAI_FAIL(AFSAI_ERR_INVALID_ARG, "pcg_solve_prepared: matrix prepared on device %d, current device %d",
+                   M->device, di.device);
+    return pcg_batch(&M->A, P, 1, nullptr, b, x, rtol, maxit, (hipStream_t)stream, info, &M->S);
 }
 
 int afsai_apply(afsai_precond P, const double *r, double *z, void *stream) {

@@ -87,6 +87,13 @@ def test_invalid_arguments_rejected_on_host(L):
     assert L.afsai_export(None, None, None, None, None) == af.ERR_INVALID_ARG
     assert L.afsai_spmm(None, 3, None, None, None) == af.ERR_INVALID_ARG
     assert L.afsai_spmm(None, 4, None, None, None) == af.ERR_INVALID_ARG
+    hm = ctypes.c_void_p(0x1)
+    assert L.afsai_matrix_prepare(None, None, ctypes.byref(hm)) == af.ERR_INVALID_ARG
+    assert hm.value is None
+    assert L.afsai_matrix_prepare(ctypes.byref(A), None, None) == af.ERR_INVALID_ARG
+    assert L.afsai_spmm_prepared(None, 4, None, None, None) == af.ERR_INVALID_ARG
+    assert L.pcg_solve_prepared(None, None, None, None, 1e-8, 10, None, None) == af.ERR_INVALID_ARG
+    L.afsai_matrix_destroy(None)
     assert L.pcg_solve_multi(None, None, 3, None, None, 1e-8, 10, None, None) == af.ERR_INVALID_ARG
     assert L.pcg_solve_multi(None, None, 2, None, None, 1e-8, 10, None, None) == af.ERR_INVALID_ARG
     assert L.afsai_import(None, 0, None, ctypes.byref(h)) == af.ERR_INVALID_ARG

@@ -680,15 +680,47 @@ def test_spmm_against_oracle(af, make):
         af.spmm(dA, torch.zeros((A.n, 3), dtype=torch.float64, device="cuda"))
 
 
+@pytest.mark.parametrize("make", [lambda: synth.elasticity27(8), lambda: synth.random_sparse_spd(3000, 40, 3)])
+def test_prepared_matrix_matches_unprepared(af, make):
+    """A prepared once: its block products and its PCG solves (preconditioned and plain, two
+    right-hand sides in a row) equal the unprepared calls bit for bit, with the same iteration
+    counts; A's device arrays may be overwritten after preparing without changing them."""
+    import torch
+
+    Pb = make()
+    A = Pb.A if hasattr(Pb, "A") else Pb
+    dA = _dev(af, A)
+    M = af.PreparedMatrix(dA)
+    X8 = torch.from_numpy(synth.uniform(19, 5, A.n * 8, -1.0, 1.0).reshape(A.n, 8)).cuda()
+    for k in (1, 4, 8):
+        Xk = X8[:, :k].contiguous()
+        assert torch.equal(M.spmm(Xk), af.spmm(dA, Xk)), k
+    P = af.setup(dA, 6, 2, 1e-2)
+    bs = [_vec(synth.uniform(23 + t, 5, A.n, -1.0, 1.0)) for t in range(2)]
+    for Pc in (P, None):
+        for b in bs:
+            x0, i0 = af.pcg_solve(dA, Pc, b, rtol=1e-8, maxit=3000)
+            x1, i1 = M.pcg_solve(Pc, b, rtol=1e-8, maxit=3000)
+            assert i0.iters == i1.iters and i0.converged == i1.converged
+            assert torch.equal(x0, x1)
+    ref = af.spmm(dA, X8)
+    dA.val.zero_()  # the prepared copy does not read A's arrays again
+    assert torch.equal(M.spmm(X8), ref)
+    M.close()
+    P.close()
+
+
 @pytest.mark.parametrize("precond", [True, False])
 @pytest.mark.parametrize("make", [lambda: synth.elasticity27(8), lambda: synth.random_sparse_spd(3000, 40, 3)])
 def test_pcg_multi_against_oracle(af, make, precond):
-    """PCG over blocks of 2, 4 and 8 right-hand sides (one column zero, one a multiple of
-    another): each column's iteration count within one of the oracle's PCG on that column
-    alone, its true residual below the stopping bound, A (x - x_oracle) within the sum of the
-    two residuals (x within the oracle tolerance when preconditioned; plain CG amplifies the
-    rounding of the dots), the zero column x = 0 after 0 iterations; a second solve of the
-    block of eight gives the same iterates bit for bit."""
+    """PCG over blocks of 1, 2, 4 and 8 right-hand sides (one column zero, one a multiple of
+    another): each column's true residual below the stopping bound, A (x - x_oracle) within
+    the sum of the two residuals, the zero column x = 0 after 0 iterations; preconditioned,
+    every column takes the oracle's iteration count and x is within 1e-10 of the oracle's
+    (the bar of the single-vector solver); plain CG amplifies the rounding of the dots (the
+    block sums each column's terms in a fixed tree order, the oracle in row order), so there
+    its count is held within one.  A second solve of the block of eight gives the same
+    iterates bit for bit."""
     import torch
 
     Pb = make()
@@ -700,7 +732,7 @@ def test_pcg_multi_against_oracle(af, make, precond):
     B8 = np.ascontiguousarray(np.column_stack([A.to_scipy() @ Xt[:, j] for j in range(8)]))
     B8[:, 3] = 0.0
     B8[:, 5] = 4.0 * B8[:, 1]
-    for k in (2, 4, 8):
+    for k in (1, 2, 4, 8):
         X, infos = af.pcg_solve_multi(dA, P, torch.from_numpy(np.ascontiguousarray(B8[:, :k])).cuda(),
                                       rtol=1e-8, maxit=3000)
         X = X.cpu().numpy()
@@ -709,7 +741,8 @@ def test_pcg_multi_against_oracle(af, make, precond):
                 assert infos[j].iters == 0 and infos[j].converged and not X[:, j].any()
                 continue
             ro = oracle.pcg(A, G, B8[:, j], 1e-8, maxit=3000)
-            assert infos[j].converged and abs(infos[j].iters - ro.iters) <= 1, (k, j, infos[j].iters, ro.iters)
+            assert infos[j].converged and abs(infos[j].iters - ro.iters) <= (0 if precond else 1), \
+                (k, j, infos[j].iters, ro.iters)
             # both stop at ||b - A x|| <= 1e-8 ||b||, so ||A (x - x_o)|| is bounded by the sum of
             # the two true residuals (each measured with the oracle's product)
             nb = np.linalg.norm(B8[:, j])
@@ -718,7 +751,7 @@ def test_pcg_multi_against_oracle(af, make, precond):
             assert r_gpu <= 1.01e-8 * nb and abs(infos[j].true_relres - r_gpu / nb) <= 1e-12, (k, j)
             assert np.linalg.norm(oracle.spmv(A, X[:, j] - ro.x)) <= (r_gpu + r_o) * (1 + 1e-6), (k, j)
             if precond:
-                assert np.linalg.norm(X[:, j] - ro.x) <= 10 * X_RTOL * np.linalg.norm(ro.x), (k, j)
+                assert np.linalg.norm(X[:, j] - ro.x) <= X_RTOL * np.linalg.norm(ro.x), (k, j)
         if k == 8:
             X2, i2 = af.pcg_solve_multi(dA, P, torch.from_numpy(np.ascontiguousarray(B8)).cuda(), rtol=1e-8,
                                         maxit=3000)
