@@ -432,6 +432,27 @@ void segment_slices(const Segments &seg, int n, int32_t *slice0) {
         slice0[k + 1] = slice0[k] + (seg.row0[k + 1] - seg.row0[k] + kSlice - 1) / kSlice;
 }
 
+// windows of kWin slices, starting at every system's first slice: first slice of each window
+// (nwin + 1 entries) and window of each slice (nslices + 1 entries)
+static void make_windows(int nslices, int n, const Segments &seg, std::vector<int32_t> &hw, std::vector<int32_t> &hofs) {
+    hw.clear();
+    hofs.assign(nslices + 1, 0);
+    std::vector<int32_t> s0(2, 0);
+    if (seg.row0 && seg.nsys > 1) {
+        s0.resize(seg.nsys + 1);
+        segment_slices(seg, n, s0.data());
+    } else {
+        s0[1] = nslices;
+    }
+    for (size_t k = 0; k + 1 < s0.size(); ++k)
+        for (int w = s0[k]; w < s0[k + 1]; w += kWin) {
+            for (int j = w; j < std::min(s0[k + 1], w + kWin); ++j) hofs[j] = (int32_t)hw.size();
+            hw.push_back(w);
+        }
+    hofs[nslices] = (int32_t)hw.size();
+    hw.push_back(nslices);
+}
+
 static int sell_build(int n, int64_t nnz, const int32_t *rp, const int32_t *m, int ld, const int32_t *ci,
                       const void *val, bool val_f32, bool out_f32, bool top, Sell *out, const DeviceInfo &di,
                       hipStream_t s, const Segments &seg) {
@@ -479,22 +500,9 @@ static int sell_build(int n, int64_t nnz, const int32_t *rp, const int32_t *m, i
         } else if (padded && option(AFSAI_OPT_SELL_UNEVEN) != 1) {
             // uneven rows: the rows of each window of slices ordered by length, lanes stop at
             // their own row; windows start at every system's first slice
-            std::vector<int32_t> hw, hofs(S.nslices + 1);
-            std::vector<int32_t> s0(2, 0);
-            if (seg.row0 && seg.nsys > 1) {
-                s0.resize(seg.nsys + 1);
-                segment_slices(seg, n, s0.data());
-            } else {
-                s0[1] = S.nslices;
-            }
-            for (size_t k = 0; k + 1 < s0.size(); ++k)
-                for (int w = s0[k]; w < s0[k + 1]; w += kWin) {
-                    for (int j = w; j < std::min(s0[k + 1], w + kWin); ++j) hofs[j] = (int32_t)hw.size();
-                    hw.push_back(w);
-                }
-            S.nwin = (int)hw.size();
-            hw.push_back(S.nslices);
-            hofs[S.nslices] = S.nwin;
+            std::vector<int32_t> hw, hofs;
+            make_windows(S.nslices, n, seg, hw, hofs);
+            S.nwin = (int)hw.size() - 1;
             S.perm = (int32_t *)pool_alloc(sizeof(int32_t) * (size_t)S.nslices * kSlice);
             S.lens = (int32_t *)pool_alloc(sizeof(int32_t) * (size_t)S.nslices * kSlice);
             S.wsl = (int32_t *)pool_alloc(sizeof(int32_t) * hw.size());

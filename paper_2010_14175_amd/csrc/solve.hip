@@ -259,6 +259,53 @@ __device__ __forceinline__ void sell_slice_rows(const int32_t *srow0, int n, int
     }
 }
 
+// One lane's sum over `len` entries stored `stride` apart from base, continuing acc: one
+// sequential fma chain in stored order.  Software pipeline: the columns and values of the
+// next U entries are loaded before the gathers of the current U, so one round trip to memory
+// serves both.
+template <int U, int STRIDE, typename VT>
+__device__ __forceinline__ double lane_chain(const int32_t *__restrict__ col, const VT *__restrict__ val,
+                                             const double *__restrict__ x, int64_t base, int len, double acc) {
+    int c[U];
+    VT v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        c[u] = 0;
+        v[u] = VT(0);
+        if (u < len) {
+            const int64_t d = base + (int64_t)u * STRIDE;
+            c[u] = __builtin_nontemporal_load(&col[d]);
+            v[u] = __builtin_nontemporal_load(&val[d]);
+        }
+    }
+    for (int k0 = 0; k0 < len; k0 += U) {
+        int cn[U];
+        VT vn[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            cn[u] = 0;
+            vn[u] = VT(0);
+            if (k0 + U + u < len) {
+                const int64_t d = base + (int64_t)(k0 + U + u) * STRIDE;
+                cn[u] = __builtin_nontemporal_load(&col[d]);
+                vn[u] = __builtin_nontemporal_load(&val[d]);
+            }
+        }
+        double xv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) xv[u] = (k0 + u < len) ? x[c[u]] : 0.0;
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (k0 + u < len) acc = fma((double)v[u], xv[u], acc);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            c[u] = cn[u];
+            v[u] = vn[u];
+        }
+    }
+    return acc;
+}
+
 // SELL-64 product: one wavefront per slice of 64 rows, one lane per row; entry k of the 64
 // rows is one contiguous wave load.  Optional fused dot y.w.  For the tail of a split layout
 // (perm/rowmap set) the launch is not tied to systems (mp, sy empty, scs may be null).  With
@@ -307,24 +354,7 @@ __global__ __launch_bounds__(kThreads) void k_sell_spmv(int n, int nslices, cons
                 const int r = perm[li];
                 const int len = lens[li];
                 const int64_t base = (int64_t)sptr[sl] * kSlice + lane;
-                double acc = 0.0;
-                for (int k0 = 0; k0 < len; k0 += U) {
-                    int c[U];
-                    VT v[U];
-#pragma unroll
-                    for (int u = 0; u < U; ++u) {
-                        c[u] = -1;
-                        v[u] = VT(0);
-                        if (k0 + u < len) {
-                            const int64_t d = base + (int64_t)(k0 + u) * kSlice;
-                            c[u] = __builtin_nontemporal_load(&col[d]);
-                            v[u] = __builtin_nontemporal_load(&val[d]);
-                        }
-                    }
-#pragma unroll
-                    for (int u = 0; u < U; ++u)
-                        if (c[u] >= 0) acc = fma((double)v[u], x[c[u]], acc);
-                }
+                const double acc = lane_chain<U, kSlice>(col, val, x, base, len, 0.0);
                 if (r >= 0) sy_win[r - wr0] = acc;
             }
             __syncthreads();
@@ -375,23 +405,7 @@ __global__ __launch_bounds__(kThreads) void k_sell_spmv(int n, int nslices, cons
                 acc = y[ro];
             }
         }
-        for (int k0 = 0; k0 < width; k0 += U) {
-            int c[U];
-            VT v[U];
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                c[u] = -1;
-                v[u] = VT(0);
-                if (k0 + u < width) {
-                    const int64_t d = base + (int64_t)(k0 + u) * kSlice;
-                    c[u] = __builtin_nontemporal_load(&col[d]);
-                    v[u] = __builtin_nontemporal_load(&val[d]);
-                }
-            }
-#pragma unroll
-            for (int u = 0; u < U; ++u)
-                if (c[u] >= 0) acc = fma((double)v[u], x[c[u]], acc);
-        }
+        acc = lane_chain<U, kSlice>(col, val, x, base, width, acc);
         if (valid) {
             y[ro] = acc;
             if (DOT) part = fma(acc, w[ro], part);
@@ -446,25 +460,51 @@ __global__ __launch_bounds__(kThreads) void k_sell_fused(int n, int nslices, con
         const int width = (int)(sptr[sl + 1] - c0);
         const int64_t base = (int64_t)c0 * kSlice + lane;
         double acc = 0.0;
+        // software pipeline as in lane_chain: the next U columns and values are loaded before
+        // the current gathers
+        int c[U];
+        VT v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            c[u] = 0;
+            v[u] = VT(0);
+            if (u < width) {
+                const int64_t d = base + (int64_t)u * kSlice;
+                c[u] = __builtin_nontemporal_load(&col[d]);
+                v[u] = __builtin_nontemporal_load(&val[d]);
+            }
+        }
         for (int k0 = 0; k0 < width; k0 += U) {
-            int c[U];
-            VT v[U];
+            int cn[U];
+            VT vn[U];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                c[u] = -1;
-                v[u] = VT(0);
-                if (k0 + u < width) {
-                    const int64_t d = base + (int64_t)(k0 + u) * kSlice;
-                    c[u] = __builtin_nontemporal_load(&col[d]);
-                    v[u] = __builtin_nontemporal_load(&val[d]);
+                cn[u] = 0;
+                vn[u] = VT(0);
+                if (k0 + U + u < width) {
+                    const int64_t d = base + (int64_t)(k0 + U + u) * kSlice;
+                    cn[u] = __builtin_nontemporal_load(&col[d]);
+                    vn[u] = __builtin_nontemporal_load(&val[d]);
                 }
+            }
+            double xa[U], xb[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const bool in = k0 + u < width;
+                xa[u] = in ? va[c[u]] : 0.0;
+                xb[u] = (in && !(MODE == FUSE_AP && first)) ? vb[c[u]] : 0.0;
             }
 #pragma unroll
             for (int u = 0; u < U; ++u)
-                if (c[u] >= 0) {
-                    const double xv = (MODE == FUSE_AP && first) ? va[c[u]] : fma(coef, vb[c[u]], va[c[u]]);
+                if (k0 + u < width) {
+                    const double xv = (MODE == FUSE_AP && first) ? xa[u] : fma(coef, xb[u], xa[u]);
                     acc = fma((double)v[u], xv, acc);
                 }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                c[u] = cn[u];
+                v[u] = vn[u];
+            }
         }
         if (r < r1) {
             const double own = (MODE == FUSE_AP && first) ? va[r] : fma(coef, vb[r], va[r]);
@@ -913,26 +953,45 @@ __global__ __launch_bounds__(kThreads) void k_sell_spmm(int n, int nslices, cons
         double acc[K];
 #pragma unroll
         for (int j = 0; j < K; ++j) acc[j] = 0.0;
+        // software pipeline as in lane_chain: the next U columns and values are loaded before
+        // the current gathers
+        int c[U];
+        VT v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            c[u] = 0;
+            v[u] = VT(0);
+            if (u < len) {
+                const int64_t d = base + (int64_t)u * kSlice;
+                c[u] = __builtin_nontemporal_load(&col[d]);
+                v[u] = __builtin_nontemporal_load(&val[d]);
+            }
+        }
         for (int k0 = 0; k0 < len; k0 += U) {
-            int c[U];
-            VT v[U];
+            int cn[U];
+            VT vn[U];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                c[u] = -1;
-                v[u] = VT(0);
-                if (k0 + u < len) {
-                    const int64_t d = base + (int64_t)(k0 + u) * kSlice;
-                    c[u] = __builtin_nontemporal_load(&col[d]);
-                    v[u] = __builtin_nontemporal_load(&val[d]);
+                cn[u] = 0;
+                vn[u] = VT(0);
+                if (k0 + U + u < len) {
+                    const int64_t d = base + (int64_t)(k0 + U + u) * kSlice;
+                    cn[u] = __builtin_nontemporal_load(&col[d]);
+                    vn[u] = __builtin_nontemporal_load(&val[d]);
                 }
             }
 #pragma unroll
             for (int u = 0; u < U; ++u)
-                if (c[u] >= 0) {
+                if (k0 + u < len) {
                     const double *xc = x + (int64_t)c[u] * K;
 #pragma unroll
                     for (int j = 0; j < K; ++j) acc[j] = fma((double)v[u], xc[j], acc[j]);
                 }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                c[u] = cn[u];
+                v[u] = vn[u];
+            }
         }
         if (valid) {
 #pragma unroll
