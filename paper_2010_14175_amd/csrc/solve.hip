@@ -309,10 +309,11 @@ __device__ __forceinline__ double lane_chain(const int32_t *__restrict__ col, co
 // SELL-64 product: one wavefront per slice of 64 rows, one lane per row; entry k of the 64
 // rows is one contiguous wave load.  Optional fused dot y.w.  For the tail of a split layout
 // (perm/rowmap set) the launch is not tied to systems (mp, sy empty, scs may be null).  With
-// rows ordered by length (lens set) a block takes whole windows of kWin slices, one per
-// wavefront, and the sums reach their natural rows through LDS, so that y is written and the
-// dot summed in row order.
-template <int U, typename VT, bool DOT>
+// rows ordered by length (lens set, instance ORD) a block takes whole windows of kWin slices,
+// one per wavefront, and the sums reach their natural rows through LDS, so that y is written
+// and the dot summed in row order.  The ordered instance keeps twice as many entries in flight
+// (its gathers are scattered over the window's rows and wait longest).
+template <int U, typename VT, bool DOT, bool ORD = false>
 __global__ __launch_bounds__(kThreads) void k_sell_spmv(int n, int nslices, const uint32_t *__restrict__ sptr,
                                                          const int32_t *__restrict__ srow0,
                                                          const int32_t *__restrict__ perm,
@@ -338,8 +339,9 @@ __global__ __launch_bounds__(kThreads) void k_sell_spmv(int n, int nslices, cons
     int s0, s1;
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
     double part = 0.0;
-    if (lens) {
+    if constexpr (ORD) {
         static_assert(kThreads == kWin * kSlice, "one wavefront per slice of a window");
+        constexpr int UO = U >= 8 ? 16 : U;
         __shared__ double sy_win[kWin * kSlice];
         const int wa = wofs[sb], wb = wofs[sb + sn];
         int w0, w1;
@@ -354,7 +356,7 @@ __global__ __launch_bounds__(kThreads) void k_sell_spmv(int n, int nslices, cons
                 const int r = perm[li];
                 const int len = lens[li];
                 const int64_t base = (int64_t)sptr[sl] * kSlice + lane;
-                const double acc = lane_chain<U, kSlice>(col, val, x, base, len, 0.0);
+                const double acc = lane_chain<UO, kSlice>(col, val, x, base, len, 0.0);
                 if (r >= 0) sy_win[r - wr0] = acc;
             }
             __syncthreads();
@@ -822,6 +824,17 @@ static void launch_sell_t(const Sell &S, const double *x, double *y, const doubl
     const int32_t *tcl = T ? T->col : nullptr;
     const VT *tvl = T ? (const VT *)T->val : nullptr;
     const int32_t *tof = T ? S.toff : nullptr;
+    if (S.lens) {
+        if (w)
+            hipLaunchKernelGGL((k_sell_spmv<U, VT, true, true>), dim3(nb), dim3(kThreads), 0, s, S.n, S.nslices,
+                               S.sptr, S.srow0, S.perm, S.rowmap, S.init, S.col, (const VT *)S.val, x, y, w, partials,
+                               scs, mp, sy, nxcd, S.lens, S.wsl, S.wofs, tsp, tcl, tvl, tof);
+        else
+            hipLaunchKernelGGL((k_sell_spmv<U, VT, false, true>), dim3(nb), dim3(kThreads), 0, s, S.n, S.nslices,
+                               S.sptr, S.srow0, S.perm, S.rowmap, S.init, S.col, (const VT *)S.val, x, y, w, partials,
+                               scs, mp, sy, nxcd, S.lens, S.wsl, S.wofs, tsp, tcl, tvl, tof);
+        return;
+    }
     if (w)
         hipLaunchKernelGGL((k_sell_spmv<U, VT, true>), dim3(nb), dim3(kThreads), 0, s, S.n, S.nslices, S.sptr,
                            S.srow0, S.perm, S.rowmap, S.init, S.col, (const VT *)S.val, x, y, w, partials, scs, mp,
