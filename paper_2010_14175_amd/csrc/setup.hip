@@ -335,7 +335,7 @@ RowsKernel rows_kernel_w_large(int mmax, int cap, bool g32, size_t *lds_out);
 // Launch of a per-row kernel over `nlist` rows.  Inverse-factor form: wdyn > 0 is its dynamic
 // LDS per block and rpw its rows per wavefront; the Cholesky form sizes its LDS from the
 // pattern and table (wdyn = 0).
-static int launch_rows(RowsKernel kern, size_t wdyn, int rpw, int mmax_t, int mmax, int64_t row_work, int cap, bool rsl, int tb, int gmax, const afsai_csr *A, const float *av32, const double *diag,
+static int launch_rows(const char *prof_name, RowsKernel kern, size_t wdyn, int rpw, int mmax_t, int mmax, int64_t row_work, int cap, bool rsl, int tb, int gmax, const afsai_csr *A, const float *av32, const double *diag,
                        const int32_t *dlo, const afsai_params *p, const int32_t *list, int nlist, int32_t *counters,
                        int ldell, int32_t *ell_col, double *ell_val, int32_t *m, double *psi, int32_t *steps,
                        int32_t *reason, int8_t *st, int32_t *ovf_count, int32_t *ovf_list, const DeviceInfo &di,
@@ -373,7 +373,7 @@ static int launch_rows(RowsKernel kern, size_t wdyn, int rpw, int mmax_t, int mm
     if (option(AFSAI_OPT_SETUP_CLAIM) > 0) claim = (int)option(AFSAI_OPT_SETUP_CLAIM);
     hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, (int64_t)nx, counters, 0);
     {
-        ProfScope ps("afsai_rows", s);
+        ProfScope ps(prof_name, s);
         hipLaunchKernelGGL(kern, dim3((unsigned)nb), dim3(64), dyn, s, A->n, A->row_ptr, A->col_idx, A->val, av32, diag, dlo,
                            p->kmax, p->s, p->eps, p->tie_rtol, gmax, list, nlist, counters, nx, claim, ell_col, ell_val,
                            ldell, m, psi, steps, reason, st, ovf_count, ovf_list);
@@ -622,7 +622,7 @@ static int setup_core(const afsai_csr *A, const afsai_params *p, int nsys, const
                            av32b.as<float>());
     }
     const float *av32 = gf32 ? av32b.as<float>() : nullptr;
-    if ((rc = launch_rows(k1, wdyn, wrpw, mmax_t, mmax, row_work, cap1, rsl, tb, gmax, A, av32, diagb.as<double>(), dlob.as<int32_t>(), p, nullptr, n, ctr.as<int32_t>(), ldell,
+    if ((rc = launch_rows("afsai_rows", k1, wdyn, wrpw, mmax_t, mmax, row_work, cap1, rsl, tb, gmax, A, av32, diagb.as<double>(), dlob.as<int32_t>(), p, nullptr, n, ctr.as<int32_t>(), ldell,
                           ell_col.as<int32_t>(), ell_val.as<double>(), mcnt.as<int32_t>(), psi.as<double>(),
                           steps.as<int32_t>(), reason.as<int32_t>(), st.as<int8_t>(), ovf_count, ovf.as<int32_t>(), di,
                           s)))
@@ -643,7 +643,7 @@ static int setup_core(const afsai_csr *A, const afsai_params *p, int nsys, const
         size_t wdyn2 = 0;
         RowsKernel k2 = wdyn ? rows_kernel_w_large(mmax, cap2, (p->flags & AFSAI_GRAD_F32) != 0, &wdyn2) : rows_kernel(mmax_t, cap2, rsl, sf32);
         if (!k2) AFSAI_FAIL(AFSAI_ERR_TOO_LARGE, "afsai_setup: no kernel for table %d", cap2);
-        if ((rc = launch_rows(k2, wdyn2, 1, mmax_t, mmax, row_work, cap2, rsl, tb, gmax, A, av32, diagb.as<double>(), dlob.as<int32_t>(), p, list2.as<int32_t>(), novf,
+        if ((rc = launch_rows("afsai_rows_retry", k2, wdyn2, 1, mmax_t, mmax, row_work, cap2, rsl, tb, gmax, A, av32, diagb.as<double>(), dlob.as<int32_t>(), p, list2.as<int32_t>(), novf,
                               ctr.as<int32_t>(), ldell, ell_col.as<int32_t>(), ell_val.as<double>(), mcnt.as<int32_t>(),
                               psi.as<double>(), steps.as<int32_t>(), reason.as<int32_t>(), st.as<int8_t>(), cnt2,
                               ovf.as<int32_t>(), di, s)))

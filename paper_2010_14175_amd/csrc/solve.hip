@@ -310,8 +310,8 @@ __device__ __forceinline__ double lane_chain(const int32_t *__restrict__ col, co
 // rows is one contiguous wave load.  Optional fused dot y.w.  For the tail of a split layout
 // (perm/rowmap set) the launch is not tied to systems (mp, sy empty, scs may be null).  With
 // rows ordered by length (lens set, instance ORD) a block takes whole windows of kWin slices,
-// one per wavefront, and the sums reach their natural rows through LDS, so that y is written
-// and the dot summed in row order.  The ordered instance keeps twice as many entries in flight
+// its wavefronts taking the slices in turn, and the sums reach their natural rows through LDS,
+// so that y is written and the dot summed in row order.  The ordered instance keeps twice as many entries in flight
 // (its gathers are scattered over the window's rows and wait longest).
 template <int U, typename VT, bool DOT, bool ORD = false>
 __global__ __launch_bounds__(kThreads) void k_sell_spmv(int n, int nslices, const uint32_t *__restrict__ sptr,
@@ -340,7 +340,7 @@ __global__ __launch_bounds__(kThreads) void k_sell_spmv(int n, int nslices, cons
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
     double part = 0.0;
     if constexpr (ORD) {
-        static_assert(kThreads == kWin * kSlice, "one wavefront per slice of a window");
+        static_assert(kWin * kSlice % kThreads == 0, "the wavefronts of a block take a window's slices in turn");
         constexpr int UO = U >= 8 ? 16 : U;
         __shared__ double sy_win[kWin * kSlice];
         const int wa = wofs[sb], wb = wofs[sb + sn];
@@ -350,8 +350,7 @@ __global__ __launch_bounds__(kThreads) void k_sell_spmv(int n, int nslices, cons
             const int ws = wsl[wi], we = wsl[wi + 1];
             int wr0, u0;
             sell_slice_rows(srow0, n, ws, wr0, u0);
-            const int sl = ws + wv;
-            if (sl < we) {
+            for (int sl = ws + wv; sl < we; sl += kThreads / 64) {
                 const int64_t li = (int64_t)sl * kSlice + lane;
                 const int r = perm[li];
                 const int len = lens[li];
@@ -360,7 +359,7 @@ __global__ __launch_bounds__(kThreads) void k_sell_spmv(int n, int nslices, cons
                 if (r >= 0) sy_win[r - wr0] = acc;
             }
             __syncthreads();
-            if (sl < we) {
+            for (int sl = ws + wv; sl < we; sl += kThreads / 64) {
                 int r0, r1;
                 sell_slice_rows(srow0, n, sl, r0, r1);
                 const int rn = r0 + lane;
