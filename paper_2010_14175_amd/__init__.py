@@ -359,8 +359,9 @@ class PreparedMatrix:
         """Y = A X for an (n, k) row-major block of k = 1, 2, 4 or 8 vectors."""
         import torch
 
-        if X.dim() != 2 or X.shape[0] != self.n or not X.is_contiguous() or X.dtype != torch.float64:
-            raise ValueError("PreparedMatrix.spmm: X must be a contiguous float64 (n, k) tensor")
+        if not isinstance(X, torch.Tensor) or X.dim() != 2:
+            raise ValueError("PreparedMatrix.spmm: X must be an (n, k) tensor")
+        _check_dev(X, (self.n, X.shape[1]), "PreparedMatrix.spmm: X")
         if Y is None:
             Y = torch.empty_like(X)
         _check_dev(Y, tuple(X.shape), "PreparedMatrix.spmm: Y")
@@ -403,8 +404,9 @@ def pcg_solve_multi(A: DeviceCSR, P: Preconditioner | None, B, rtol: float = 1e-
     (``pcg_solve_multi``).  Returns (X, [PcgInfo per column])."""
     import torch
 
-    if B.dim() != 2 or B.shape[0] != A.n or not B.is_contiguous() or B.dtype != torch.float64:
-        raise ValueError("pcg_solve_multi: B must be a contiguous float64 (n, k) tensor")
+    if not isinstance(B, torch.Tensor) or B.dim() != 2:
+        raise ValueError("pcg_solve_multi: B must be an (n, k) tensor")
+    _check_dev(B, (A.n, B.shape[1]), "pcg_solve_multi: B")
     k = int(B.shape[1])
     X = torch.empty_like(B)
     maxit = A.n if maxit is None else int(maxit)
@@ -547,8 +549,9 @@ def spmm(A: DeviceCSR, X, Y=None, stream=None):
     """Y = A X for an (n, k) row-major block of k = 1, 2, 4 or 8 vectors (``afsai_spmm``)."""
     import torch
 
-    if X.dim() != 2 or X.shape[0] != A.n or not X.is_contiguous() or X.dtype != torch.float64:
-        raise ValueError("spmm: X must be a contiguous float64 (n, k) tensor")
+    if not isinstance(X, torch.Tensor) or X.dim() != 2:
+        raise ValueError("spmm: X must be an (n, k) tensor")
+    _check_dev(X, (A.n, X.shape[1]), "spmm: X")
     if Y is None:
         Y = torch.empty_like(X)
     _check_dev(Y, tuple(X.shape), "spmm: Y")

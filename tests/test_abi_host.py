@@ -142,3 +142,24 @@ def test_batched_arguments_rejected_on_host(L):
     assert L.pcg_solve_batched(ctypes.byref(A), None, 2, offs(0, 7, 6), bb, x, 1e-8, 10, None, info) == af.ERR_INVALID_ARG
     assert L.pcg_solve_batched(ctypes.byref(A), None, 2, None, bb, x, 1e-8, 10, None, info) == af.ERR_INVALID_ARG
     assert L.pcg_solve_batched(ctypes.byref(A), None, 2, offs(0, 5, 10), bb, x, 0.0, 10, None, info) == af.ERR_INVALID_ARG
+
+
+def test_binding_rejects_host_and_misshapen_blocks(L):
+    """The binding checks every block it hands to the library (float64, contiguous, on the GPU,
+    the right shape) before any call, so a host or short tensor never reaches a kernel."""
+    import torch
+
+    rp = torch.tensor([0, 1, 2], dtype=torch.int32)
+    ci = torch.tensor([0, 1], dtype=torch.int32)
+    va = torch.tensor([2.0, 3.0], dtype=torch.float64)
+    A = af.DeviceCSR(rp, ci, va)
+    with pytest.raises(ValueError, match="CUDA"):
+        af.spmm(A, torch.zeros((2, 4), dtype=torch.float64))
+    with pytest.raises(ValueError):
+        af.spmm(A, torch.zeros(2, dtype=torch.float64))
+    with pytest.raises(ValueError, match="CUDA"):
+        af.pcg_solve_multi(A, None, torch.zeros((2, 2), dtype=torch.float64))
+    with pytest.raises(ValueError, match="CUDA"):
+        af.spmv(A, torch.zeros(2, dtype=torch.float64))
+    with pytest.raises(ValueError, match="CUDA"):
+        af.pcg_solve(A, None, torch.zeros(2, dtype=torch.float64))
