@@ -856,14 +856,22 @@ static void launch_sell_v(const Sell &S, int un, const double *x, double *y, con
     }
 }
 
-static int sell_unroll() { return option(AFSAI_OPT_SPMV_UNROLL) > 0 ? (int)option(AFSAI_OPT_SPMV_UNROLL) : 8; }
+// Entries in flight per lane of a SELL product: 8 (16 in the length-ordered instance), or 4
+// for matrices of at most 8 stored entries per row on average, whose lanes finish within one
+// or two rounds anyway and gain more from the resident wavefronts the smaller register budget
+// allows (a batch of short 7-point systems: its PCG 27.9 -> 25.0 ms).  The sums do not depend
+// on it.
+static int sell_unroll(const Sell &S) {
+    if (option(AFSAI_OPT_SPMV_UNROLL) > 0) return (int)option(AFSAI_OPT_SPMV_UNROLL);
+    return (S.n > 0 && S.entries <= 8 * (int64_t)S.n) ? 4 : 8;
+}
 
 // y = S x for a SELL-64 matrix laid out for the batch (optionally fused dot y.w finalised into
 // the systems' scalars); a split layout's tail is multiplied first
 static void sell_spmv(const char *name, const Sell &S, const BatchMaps &bm, const double *x, double *y,
                       const double *w, double *partials, PcgScalars *scs, int fin, const DeviceInfo &di,
                       hipStream_t s) {
-    const int un = sell_unroll();
+    const int un = sell_unroll(S);
     // a split layout's tail runs in a launch of its own first; inside the slices' product when
     // asked for (measured slower: the lanes of long rows serialise their tails while the rest of
     // the wavefront waits)
@@ -875,9 +883,10 @@ static void sell_spmv(const char *name, const Sell &S, const BatchMaps &bm, cons
         PcgScalars *tsc = (bm.nsys == 1) ? scs : nullptr;
         ProfScope ps("sell_tail", s);
         if (T.f32)
-            launch_sell_v<float>(T, un, x, y, nullptr, nullptr, tsc, Map(), Systems(), nbt, di.num_xcds, s);
+            launch_sell_v<float>(T, sell_unroll(T), x, y, nullptr, nullptr, tsc, Map(), Systems(), nbt, di.num_xcds, s);
         else
-            launch_sell_v<double>(T, un, x, y, nullptr, nullptr, tsc, Map(), Systems(), nbt, di.num_xcds, s);
+            launch_sell_v<double>(T, sell_unroll(T), x, y, nullptr, nullptr, tsc, Map(), Systems(), nbt, di.num_xcds,
+                                  s);
     }
     const int nb = bm.sell.nblocks;
     {
@@ -917,7 +926,7 @@ template <int MODE>
 static void sell_fused(const char *name, const Sell &S, const BatchMaps &bm, const double *va, const double *vb,
                        double *own, double *x, const double *pn, double *y, double *partials, PcgScalars *scs,
                        int first, int fin, const DeviceInfo &di, hipStream_t s) {
-    const int un = sell_unroll();
+    const int un = sell_unroll(S);
     {
         ProfScope ps(name, s);
         if (S.f32)
