@@ -223,9 +223,9 @@ __global__ __launch_bounds__(256) void k_transpose_fill_ell(int n, int ld, const
     }
 }
 
-// Sorts every row of G^T by column (= row of G).  One wavefront per row: rows of up to 128
-// entries are ranked in registers (each lane counts the smaller keys, one or two keys per
-// lane); longer rows fall back to an insertion sort by one lane.
+// Sorts every row of G^T by column (= row of G).  One wavefront per row: rows of up to 256
+// entries are ranked in registers (each lane counts the smaller keys, one, two or four keys
+// per lane); longer rows fall back to an insertion sort by one lane.
 template <typename VT>
 __global__ __launch_bounds__(256) void k_sort_rows(int n, const int32_t *__restrict__ rp, int32_t *__restrict__ ci,
                                                    VT *__restrict__ val) {
@@ -271,6 +271,37 @@ __global__ __launch_bounds__(256) void k_sort_rows(int n, const int32_t *__restr
                 ci[a + r1] = k1;
                 val[a + r1] = v1;
             }
+        } else if (len <= 256) {
+            // four keys per lane (rows of G^T past 128 entries: columns chosen by many rows)
+            int k[4];
+            VT v[4];
+            int r[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int o = lane + 64 * j;
+                k[j] = 0x7fffffff;
+                v[j] = VT(0);
+                r[j] = 0;
+                if (o < len) {
+                    k[j] = ci[a + o];
+                    v[j] = val[a + o];
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const int lim = min(64, len - 64 * c);
+                for (int t = 0; t < lim; ++t) {
+                    const int kt = __shfl(k[c], t, 64);
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) r[j] += (kt < k[j]) ? 1 : 0;
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                if (lane + 64 * j < len) {
+                    ci[a + r[j]] = k[j];
+                    val[a + r[j]] = v[j];
+                }
         } else if (lane == 0) {
             for (int e = a + 1; e < b; ++e) {
                 const int c = ci[e];

@@ -463,6 +463,29 @@ def test_spmv_and_apply(af, make):
     np.testing.assert_allclose(z, zo, rtol=1e-12, atol=1e-13 * np.abs(zo).max())
 
 
+def test_apply_with_long_transpose_rows(af):
+    """The 27-point operator with k_max = 15, s = 3 on a 12^3 grid (5,184 rows): 65 rows of G^T
+    hold more than 128 entries (up to 190), which the transpose sorts four keys per lane.  The
+    setup's G applied as G^T (G r) is within 1e-10 of the oracle's application of its own G, the
+    oracle's G imported and applied within 1e-12 of it, and PCG takes the oracle's iterations."""
+    Pb = synth.elasticity27(12, 2.0, 5, kmax=15, s=3)
+    G = oracle.setup(Pb.A, 15, 3, 1e-2)
+    assert np.bincount(np.asarray(G.col), minlength=Pb.n).max() > 128
+    dA = _dev(af, Pb.A)
+    P = af.setup(dA, 15, 3, 1e-2)
+    r = synth.uniform(3, 8, Pb.n, -1.0, 1.0)
+    z = P.apply(_vec(r)).cpu().numpy()
+    zo = oracle.apply(G, r)
+    assert np.linalg.norm(z - zo) <= 1e-10 * np.linalg.norm(zo)
+    Pi = _import_oracle_G(af, G)
+    zi = Pi.apply(_vec(r)).cpu().numpy()
+    np.testing.assert_allclose(zi, zo, rtol=1e-12, atol=1e-13 * np.abs(zo).max())
+    x, info = af.pcg_solve(dA, P, _vec(Pb.b), rtol=1e-8)
+    ro = oracle.pcg(Pb.A, G, Pb.b, 1e-8)
+    assert info.converged and info.iters == ro.iters, (info.iters, ro.iters)
+    assert np.linalg.norm(x.cpu().numpy() - ro.x) <= X_RTOL * np.linalg.norm(ro.x)
+
+
 # --------------------------------------------------------------------------------------
 # PCG parity
 # --------------------------------------------------------------------------------------
