@@ -162,7 +162,7 @@ def test_setup_elasticity_reduced(af, form):
     A = synth.elast27(12, 1.0, 2)
     r = compare_factor(af, A, 10, 2, 1e-2, form=form)
     if form == 1:
-        assert r["bitwise"] > 0.999
+        assert r["bitwise"] == 1.0, r["bitwise"]
 
 
 @pytest.mark.parametrize("form", [0, 1])
@@ -171,7 +171,7 @@ def test_setup_elasticity_24(af, form):
     A = synth.elast27(24, 1.0, 2)
     r = compare_factor(af, A, 10, 2, 1e-2, form=form)
     if form == 1:
-        assert r["bitwise"] > 0.999
+        assert r["bitwise"] == 1.0, r["bitwise"]
 
 
 @pytest.mark.parametrize("form", [0, 1])
@@ -283,7 +283,7 @@ def test_setup_slot_lists(af, slots, make, kmax, s):
     finally:
         af.set_option(af.OPT_SETUP_SLOTS, 0)
         af.set_option(af.OPT_SETUP_FORM, 0)
-    assert r["bitwise"] > 0.999
+    assert r["bitwise"] == 1.0, r["bitwise"]
     for a, b in zip(_gpu_factor(af, r["P"]), o):
         np.testing.assert_array_equal(a, b)
 
