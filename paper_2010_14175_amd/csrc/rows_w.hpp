@@ -196,6 +196,83 @@ __device__ __forceinline__ int tfind(uint32_t *hkey, uint32_t c, bool &fresh, ui
     return -1;
 }
 
+// tfind for two columns of one lane at once (act0/act1: whether to look each up): the bucket
+// reads of both go out together, then the claims of both, so the two lookups share their LDS
+// round trips.  Same placement rule and results per column as tfind; slot -1 when the table
+// is full (or the column was not looked up).  Equal columns would also be found right: both
+// lookups claim the same empty slot, one claim wins and the other reads the bucket again.
+template <int CAP>
+__device__ __forceinline__ void tfind2(uint32_t *hkey, uint32_t c0, bool act0, uint32_t c1, bool act1, int &s0,
+                                       int &s1, uint32_t &k0, uint32_t &k1) {
+    constexpr int NBK = CAP / 4;
+    constexpr int B = __builtin_ctz(NBK);
+    uint32_t b0 = (c0 * 2654435761u) >> (32 - B), b1 = (c1 * 2654435761u) >> (32 - B);
+    int p0 = 0, p1 = 0;
+    bool w0 = act0, w1 = act1;  // still looking
+    s0 = -1;
+    s1 = -1;
+    k0 = 0u;
+    k1 = 0u;
+    while (w0 || w1) {
+        uint4 q0 = make_uint4(0u, 0u, 0u, 0u), q1 = make_uint4(0u, 0u, 0u, 0u);
+        if (w0) q0 = *reinterpret_cast<const uint4 *>(&hkey[4 * b0]);
+        if (w1) q1 = *reinterpret_cast<const uint4 *>(&hkey[4 * b1]);
+        int e0 = -1, e1 = -1;  // smallest empty slot of each bucket
+        if (w0) {
+            const uint32_t kk[4] = {q0.x, q0.y, q0.z, q0.w};
+#pragma unroll
+            for (int e = 3; e >= 0; --e) {
+                if (kk[e] == kEmptyKey) {
+                    e0 = e;
+                } else if ((kk[e] & kColBits) == c0) {
+                    s0 = (int)(4 * b0 + e);
+                    k0 = kk[e];
+                }
+            }
+            if (s0 >= 0) {
+                w0 = false;
+                e0 = -1;
+            } else if (e0 < 0) {  // full bucket without the column: the next one
+                b0 = (b0 + 1) & (NBK - 1);
+                if (++p0 >= NBK) w0 = false;
+            }
+        }
+        if (w1) {
+            const uint32_t kk[4] = {q1.x, q1.y, q1.z, q1.w};
+#pragma unroll
+            for (int e = 3; e >= 0; --e) {
+                if (kk[e] == kEmptyKey) {
+                    e1 = e;
+                } else if ((kk[e] & kColBits) == c1) {
+                    s1 = (int)(4 * b1 + e);
+                    k1 = kk[e];
+                }
+            }
+            if (s1 >= 0) {
+                w1 = false;
+                e1 = -1;
+            } else if (e1 < 0) {
+                b1 = (b1 + 1) & (NBK - 1);
+                if (++p1 >= NBK) w1 = false;
+            }
+        }
+        uint32_t o0 = 0u, o1 = 0u;
+        if (e0 >= 0) o0 = atomicCAS(&hkey[4 * b0 + e0], kEmptyKey, c0);
+        if (e1 >= 0) o1 = atomicCAS(&hkey[4 * b1 + e1], kEmptyKey, c1);
+        // a failed claim means another column took the slot: its bucket is read again
+        if (e0 >= 0 && o0 == kEmptyKey) {
+            s0 = (int)(4 * b0 + e0);
+            k0 = c0;
+            w0 = false;
+        }
+        if (e1 >= 0 && o1 == kEmptyKey) {
+            s1 = (int)(4 * b1 + e1);
+            k1 = c1;
+            w1 = false;
+        }
+    }
+}
+
 template <int GS>
 __device__ __forceinline__ uint64_t group_bits(int grp) {
     if constexpr (GS == 64) return ~0ull;
@@ -544,6 +621,37 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(GS == 8 || (
                             uint32_t pk[SLW];
 #pragma unroll
                             for (int w = 0; w < SLW; ++w) pk[w] = 0u;
+                            if constexpr (GS == 64) {
+                                // both chunks of the row (entries gl and gl + 64, loaded above)
+                                // entered in the table by one paired lookup; the second only
+                                // when the first lies entirely in the prefix up to column i
+                                static_assert(HMAX == 2 && PF == 2 && SLW == 1 && LY::LROW == 128,
+                                              "64 lanes: two chunks of a row, one slot word");
+                                const int c0 = gc[v][0];
+                                const double a0 = ga[v][0];
+                                const bool two = glen[v] > GS && (__ballot(c0 <= i) & gm) == gm;
+                                const int c1 = two ? gc[v][1] : 0x7fffffff;
+                                const double a1 = ga[v][1];
+                                if (c0 == i) NAI[v] = a0;
+                                if (c1 == i) NAI[v] = a1;
+                                const bool l0 = c0 < i, l1 = c1 < i;
+                                int s0, s1;
+                                uint32_t k0, k1;
+                                tfind2<CAP>(hkey, (uint32_t)c0, l0, (uint32_t)c1, l1, s0, s1, k0, k1);
+                                if ((l0 && s0 < 0) || (l1 && s1 < 0)) {
+                                    bad = true;
+                                } else {
+                                    if (l0) {
+                                        pk[0] |= (uint32_t)s0;
+                                        if (k0 & kMember) NR[v * MMAX + (int)((k0 >> 24) & 0x7Fu)] = a0;
+                                    }
+                                    if (l1) {
+                                        pk[0] |= (uint32_t)s1 << 16;
+                                        if (k1 & kMember) NR[v * MMAX + (int)((k1 >> 24) & 0x7Fu)] = a1;
+                                    }
+                                }
+                                nlo = __popcll(__ballot(l0) & gm) + __popcll(__ballot(l1) & gm);
+                            } else {
 #pragma unroll
                             for (int h = 0; h < HMAX; ++h) {
                                 if (GS * h < glen[v]) {
@@ -578,6 +686,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(GS == 8 || (
                                     // the columns up to i form a prefix of the row
                                     if ((__ballot(c <= i) & gm) != gm) break;
                                 }
+                            }
                             }
                             if (gl == p) {
                                 r_beg = gnb[v];
