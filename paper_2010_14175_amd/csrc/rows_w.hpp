@@ -292,7 +292,7 @@ __device__ __forceinline__ void top2(const uint32_t *hkey, const double *hval, i
     a2 = -1.0;
     k1 = k2 = kEmptyKey;
     e1 = e2 = 0;
-#pragma unroll 4
+#pragma unroll
     for (int jj = 0; jj < SPL; ++jj) {
         const int e = gl + GS * jj;
         const uint32_t kk = hkey[e];
