@@ -727,8 +727,11 @@ def test_prepared_matrix_matches_unprepared(af, make):
             assert i0.iters == i1.iters and i0.converged == i1.converged
             assert torch.equal(x0, x1)
     ref = af.spmm(dA, X8)
+    x_ref, i_ref = M.pcg_solve(P, bs[0], rtol=1e-8, maxit=3000)
     dA.val.zero_()  # the prepared copy does not read A's arrays again
     assert torch.equal(M.spmm(X8), ref)
+    x2, i2 = M.pcg_solve(P, bs[0], rtol=1e-8, maxit=3000)
+    assert i2.iters == i_ref.iters and torch.equal(x2, x_ref)
     M.close()
     P.close()
 
