@@ -951,7 +951,7 @@ __global__ __launch_bounds__(kThreads) void k_sell_spmm(int n, int nslices, cons
                                                          double *__restrict__ y, int nxcd,
                                                          const double *__restrict__ w = nullptr,
                                                          double *__restrict__ partials = nullptr) {
-    constexpr int U = 4;
+    constexpr int U = K <= 2 ? 8 : 4;  // entries in flight per lane (fewer for wide blocks: registers)
     __shared__ double sh[kThreads / 64];
     double part[K];
 #pragma unroll
