@@ -273,6 +273,20 @@ __device__ __forceinline__ void tfind2(uint32_t *hkey, uint32_t c0, bool act0, u
     }
 }
 
+// With one row per wavefront (GS = 64) every row-state value is the same in all lanes; read as
+// a scalar, a condition or loop bound on it becomes a scalar branch instead of exec-mask
+// bookkeeping, and a loop over such a bound a scalar loop instead of a divergent one.  Groups
+// of fewer lanes keep their per-group values.
+template <int GS>
+__device__ __forceinline__ int wu(int v) {
+    if constexpr (GS == 64) return __builtin_amdgcn_readfirstlane(v);
+    else return v;
+}
+template <int GS>
+__device__ __forceinline__ bool wu(bool b) {
+    return wu<GS>(b ? 1 : 0) != 0;
+}
+
 template <int GS>
 __device__ __forceinline__ uint64_t group_bits(int grp) {
     if constexpr (GS == 64) return ~0ull;
@@ -309,7 +323,7 @@ __device__ __forceinline__ void top2(const uint32_t *hkey, const double *hval, i
 }
 
 template <int GS, int MMAX, int CAP, int NB, bool G32>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(GS == 8 || (GS == 64 && MMAX <= 24) ? 4 : (CAP <= 512 && MMAX <= 48 ? 3 : 1), 8))) void k_rows_w(
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(GS == 8 || (GS == 64 && MMAX <= 24 && CAP <= 512) ? 4 : (CAP <= 512 && MMAX <= 48 ? 3 : 1), 8))) void k_rows_w(
     int n, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci, const double *__restrict__ av,
     const float *__restrict__ av32, const double *__restrict__ diag, const int32_t *__restrict__ dlo, int kmax, int s, double eps, double tau,
     int /*gmax*/, const int32_t *__restrict__ list, int nlist, int32_t *__restrict__ counters, int nxcd, int claim,
@@ -427,7 +441,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(GS == 8 || (
             if (!__ballot(act)) break;
 
             // ---- 1. product pass
-            if (act) {
+            if (wu<GS>(act)) {
 #pragma unroll
                 for (int jj = 0; jj < SPL; ++jj) hval[gl + GS * jj] = 0.0;
                 if constexpr (GS < 64) {
@@ -436,10 +450,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(GS == 8 || (
                 }
             }
             wsync();
-            if (act) {
+            const int mo_u = wu<GS>(m_o);
+            if (wu<GS>(act)) {
 #pragma unroll
                 for (int qb = 0; qb < MMAX; qb += QB) {
-                    if (qb <= m_o) {
+                    if (qb <= mo_u) {
                         int slt[QB][SPW];
                         AVT aa[QB][SPW];
                         double gg[QB];
@@ -448,7 +463,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(GS == 8 || (
                             const int q = qb + u;
                             int beg = 0, len = 0;
                             gg[u] = 0.0;
-                            if (q < MMAX && q <= m_o) {
+                            if (q < MMAX && q <= mo_u) {
                                 if constexpr (GS == 64) {
                                     // member q: row i (q = 0) or position q - 1, uniform values
                                     if (q == 0) {
@@ -504,20 +519,20 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(GS == 8 || (
             //         pass.  Candidates must exceed 2^-40 of the first maximum (eligibility).
             int ns = 0;
             int r_js = 0, r_nb = 0, r_ne = 0;  // lane v: v-th column selected in this step, its row extents
-            if (act) {
+            if (wu<GS>(act)) {
                 double a1, a2;
                 uint32_t k1, k2;
                 int e1, e2;
                 top2<GS, SPL>(hkey, hval, gl, a1, a2, k1, k2, e1, e2);
                 const double M = gred<GS, OpMax>(a1);
-                if (M > 0.0) {
+                if (wu<GS>(M > 0.0)) {
                     const double thr = 0x1.0p-40 * M;
                     bool partial = false;
                     for (int round = 0; round < s; ++round) {
                         const double v1 = a1 > thr ? a1 : -1.0;
                         const double v2 = a2 > thr ? a2 : -1.0;
                         const double Mp = round == 0 ? M : gred<GS, OpMax>(v1);
-                        if (!(Mp > 0.0)) break;
+                        if (!wu<GS>(Mp > 0.0)) break;
                         const double band = (1.0 - tauv) * Mp;
                         const bool slow = (__ballot(v2 >= band || (partial && v1 >= band)) & gm) != 0;
                         uint32_t js;
@@ -577,12 +592,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(GS == 8 || (
             double yi = 0.0;  // lane j: (W^T l_i)_j, accumulated over the blocks of this step
             int nsd = 0;
             bool first = true;
-            const int nsw = GS == 64 ? ns : (int)gred<64, OpMax>((double)(act ? ns : 0));
+            const int nsw = GS == 64 ? wu<GS>(ns) : (int)gred<64, OpMax>((double)(act ? ns : 0));
             for (int nw = 0; nw < nsw; nw += NB) {
                 // old positions of this block (earlier blocks of the step included)
-                const int mwb = GS == 64 ? m_o : (int)gred<64, OpMax>((double)(act ? m_o : 0));
-                const bool blk = act && nsd < ns;
-                const int nbk = blk ? min(NB, ns - nsd) : 0;
+                const int mwb = GS == 64 ? wu<GS>(m_o) : (int)gred<64, OpMax>((double)(act ? m_o : 0));
+                const bool blk = wu<GS>(act && nsd < ns);
+                const int nbk = wu<GS>(blk ? min(NB, ns - nsd) : 0);
                 if (blk) {
                     for (int j = gl; j < NB * MMAX; j += GS) NR[j] = 0.0;
                     if (gl < NB) NAI[gl] = 0.0;
@@ -785,10 +800,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(GS == 8 || (
                 double wn[NB];
 #pragma unroll
                 for (int v = 0; v < NB; ++v) wn[v] = 0.0;
-                if (go) {
+                if (wu<GS>(go)) {
 #pragma unroll
                     for (int v = 0; v < NB; ++v) {
-                        if (v < nbk && spd) {
+                        if (v < nbk && wu<GS>(spd)) {
                             const int p = m_o + v;
                             const double sq = gred<GS, OpSum>(gl < m_o ? la[v] * la[v] : 0.0);
                             double d2 = NR[v * MMAX + p] - sq;
@@ -815,7 +830,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(GS == 8 || (
                             }
                         }
                     }
-                    if (spd) {
+                    if (wu<GS>(spd)) {
                         // l_i at the new positions and psi
 #pragma unroll
                         for (int w = 0; w < NB; ++w) {
@@ -840,7 +855,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(GS == 8 || (
             }
 
             // ---- 5. g, psi and the exit test
-            if (act) {
+            if (wu<GS>(act)) {
                 if (!(psi > 0.0) || !isfinite(psi)) {
                     status = ROW_NOT_SPD;
                     act = false;
