@@ -372,7 +372,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(GS == 8 || (
         if (qn >= qe) {
             if (lane == 0) s_row = q0 + atomicAdd(&counters[x], take);
             __syncthreads();
-            qn = s_row;
+            qn = __builtin_amdgcn_readfirstlane(s_row);  // the block is one wavefront: a scalar
             __syncthreads();
             if (qn >= q1) break;
             qe = min(qn + take, q1);
@@ -409,7 +409,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(GS == 8 || (
 #pragma unroll
             for (int w = 0; w < SLW; ++w) slr[q][w] = 0u;
 
-        for (int j = gl; j < CAP; j += GS) hkey[j] = kEmptyKey;
+#pragma unroll
+        for (int jj = 0; jj < CAP / GS; ++jj) hkey[gl + GS * jj] = kEmptyKey;
         wsync();
         if (act && kmax > 0) {
             if (ilen > LY::LROW) {
@@ -599,7 +600,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(GS == 8 || (
                 const bool blk = wu<GS>(act && nsd < ns);
                 const int nbk = wu<GS>(blk ? min(NB, ns - nsd) : 0);
                 if (blk) {
-                    for (int j = gl; j < NB * MMAX; j += GS) NR[j] = 0.0;
+#pragma unroll
+                    for (int jj = 0; jj < (NB * MMAX + GS - 1) / GS; ++jj)
+                        if (gl + GS * jj < NB * MMAX) NR[gl + GS * jj] = 0.0;
                     if (gl < NB) NAI[gl] = 0.0;
                 }
                 wsync();
@@ -873,12 +876,13 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(GS == 8 || (
         }
 
         // ---- outputs: the row with ascending columns (i, the largest, last)
-        if (have && status == ROW_OK) {
+        if (wu<GS>(have && status == ROW_OK)) {
             const int col = gl < m_o ? r_col : (gl == m_o ? i : 0x7fffffff);
             if (gl <= m_o) sel[gl] = col;
             wsync();
             int rank = 0;
-            for (int t = 0; t <= m_o; ++t) rank += (sel[t] < col) ? 1 : 0;
+            const int mo_u = wu<GS>(m_o);
+            for (int t = 0; t <= mo_u; ++t) rank += (sel[t] < col) ? 1 : 0;
             if (gl <= m_o) {
                 ell_col[(size_t)i * ldell + rank] = col;
                 ell_val[(size_t)i * ldell + rank] = gl < m_o ? r_g : gi;
