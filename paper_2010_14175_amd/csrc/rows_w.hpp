@@ -597,6 +597,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(GS == 8 || (
             for (int nw = 0; nw < nsw; nw += NB) {
                 // old positions of this block (earlier blocks of the step included)
                 const int mwb = GS == 64 ? wu<GS>(m_o) : (int)gred<64, OpMax>((double)(act ? m_o : 0));
+                const int mo = wu<GS>(m_o);  // this row's old positions (a scalar with 64 lanes)
                 const bool blk = wu<GS>(act && nsd < ns);
                 const int nbk = wu<GS>(blk ? min(NB, ns - nsd) : 0);
                 if (blk) {
@@ -634,7 +635,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(GS == 8 || (
 #pragma unroll
                     for (int v = 0; v < NB; ++v) {
                         if (v < nbk && !bad) {
-                            const int p = m_o + v;  // position of this new row
+                            const int p = mo + v;  // position of this new row
                             int nlo = 0;
                             uint32_t pk[SLW];
 #pragma unroll
@@ -734,7 +735,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(GS == 8 || (
                 wsync();
                 const bool go = blk && act;
                 // a_{u,i} of the new positions
-                if (go && gl >= m_o && gl < m_o + nbk) r_ai = NAI[gl - m_o];
+                if (go && gl >= mo && gl < mo + nbk) r_ai = NAI[gl - mo];
 
                 // pass A: l_v[t] = sum_{j <= t} W[t][j] a_v[j] for the old positions t < m_o
                 double la[NB];
@@ -744,7 +745,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(GS == 8 || (
                     // kPU entries of the row at a time: all loads first (in bounds: at most 7
                     // past the diagonal of the lane's row, or of row 0 for lanes without a row,
                     // within W's padding), then the entries right of the diagonal zeroed
-                    const int lim = (go && gl < m_o) ? gl : -1;
+                    const int lim = (go && gl < mo) ? gl : -1;
                     const double *wrow = Wm + tri_w(lim >= 0 ? gl : 0);
                     for (int j0 = 0; j0 < mwb; j0 += kPU) {
                         double wv[kPU];
@@ -764,8 +765,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(GS == 8 || (
                     // every entry of the rows (zeros past the old positions) for pass B's
                     // unrolled reads
 #pragma unroll
-                    for (int v = 0; v < NB; ++v) LV[v * MMAX + gl] = gl < m_o ? la[v] : 0.0;
-                    LV[NB * MMAX + gl] = (first && gl < m_o) ? r_li : 0.0;
+                    for (int v = 0; v < NB; ++v) LV[v * MMAX + gl] = gl < mo ? la[v] : 0.0;
+                    LV[NB * MMAX + gl] = (first && gl < mo) ? r_li : 0.0;
                 }
                 wsync();
                 // pass B: y_v[j] = sum_{j <= t < m_o} W[t][j] l_v[t], and the same with l_i
@@ -776,19 +777,19 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(GS == 8 || (
                     // all loads first: rows t of the chunk past the old positions read the last
                     // old row, lanes without an old position column 0 (in bounds); then the
                     // entries with t < j or t >= m_o zeroed
-                    const int jc = (go && gl < m_o) ? gl : 0;
-                    const int lo = (go && gl < m_o) ? gl : 0x7fffffff;
+                    const int jc = (go && gl < mo) ? gl : 0;
+                    const int lo = (go && gl < mo) ? gl : 0x7fffffff;
                     for (int t0 = 0; t0 < mwb; t0 += kPU) {
                         double wv[kPU];
 #pragma unroll
                         for (int u = 0; u < kPU; ++u) {
-                            const int tc = min(t0 + u, m_o - 1);
+                            const int tc = min(t0 + u, mo - 1);
                             wv[u] = Wm[tri_w(tc) + jc];
                         }
 #pragma unroll
                         for (int u = 0; u < kPU; ++u) {
                             const int t = t0 + u;
-                            wv[u] = (t >= lo && t < m_o) ? wv[u] : 0.0;
+                            wv[u] = (t >= lo && t < mo) ? wv[u] : 0.0;
                         }
 #pragma unroll
                         for (int v = 0; v < NB; ++v)
@@ -807,8 +808,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(GS == 8 || (
 #pragma unroll
                     for (int v = 0; v < NB; ++v) {
                         if (v < nbk && wu<GS>(spd)) {
-                            const int p = m_o + v;
-                            const double sq = gred<GS, OpSum>(gl < m_o ? la[v] * la[v] : 0.0);
+                            const int p = mo + v;
+                            const double sq = gred<GS, OpSum>(gl < mo ? la[v] * la[v] : 0.0);
                             double d2 = NR[v * MMAX + p] - sq;
                             const double av_l = gl < MMAX ? NR[v * MMAX + (gl < MMAX ? gl : 0)] : 0.0;
                             double cp[NB];
@@ -839,7 +840,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(GS == 8 || (
                         for (int w = 0; w < NB; ++w) {
                             if (w < nbk) {
                                 const double li = gred<GS, OpSum>(wn[w] * r_ai);
-                                if (gl == m_o + w) r_li = li;
+                                if (gl == mo + w) r_li = li;
                                 psi = psi - li * li;
                                 yi = fma(wn[w], li, yi);
                             }
