@@ -259,6 +259,12 @@ __device__ __forceinline__ void sell_slice_rows(const int32_t *srow0, int n, int
     }
 }
 
+// The wavefront's index within its block, as a scalar: slice indices, their offsets and widths
+// then stay in scalar registers and the per-lane loops over a slice run on scalar bounds
+// (from the thread index the compiler would keep them in vector registers and guard every
+// unrolled step with exec-mask branches).
+__device__ __forceinline__ int wave_index() { return __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)); }
+
 // One lane's sum over `len` entries stored `stride` apart from base, continuing acc: one
 // sequential fma chain in stored order.  Software pipeline: the columns and values of the
 // next U entries are loaded before the gathers of the current U, so one round trip to memory
@@ -337,7 +343,8 @@ __global__ __launch_bounds__(kThreads) void k_sell_spmv(int n, int nslices, cons
     const int sb = sy.slice0 ? sy.slice0[jb.k] : 0;
     const int sn = sy.slice0 ? sy.slice0[jb.k + 1] - sb : nslices;
     int s0, s1;
-    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    // (the ordered instance keeps the thread-derived index: measured faster there)
+    const int wv = ORD ? (int)(threadIdx.x >> 6) : wave_index(), lane = threadIdx.x & 63;
     double part = 0.0;
     if constexpr (ORD) {
         static_assert(kWin * kSlice % kThreads == 0, "the wavefronts of a block take a window's slices in turn");
@@ -451,7 +458,7 @@ __global__ __launch_bounds__(kThreads) void k_sell_fused(int n, int nslices, con
     const int sn = sy.slice0 ? sy.slice0[jb.k + 1] - sb : nslices;
     int s0, s1;
     block_range(sb, sn, jb.lb, jb.nb, s0, s1);
-    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int wv = wave_index(), lane = threadIdx.x & 63;
     double part = 0.0;
     for (int sl = s0 + wv; sl < s1; sl += kThreads / 64) {
         int r0, r1;
@@ -959,7 +966,7 @@ __global__ __launch_bounds__(kThreads) void k_sell_spmm(int n, int nslices, cons
     const int lb = xcd_block(blockIdx.x, gridDim.x, nxcd);
     int s0, s1;
     block_range(0, nslices, lb, gridDim.x, s0, s1);
-    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int wv = wave_index(), lane = threadIdx.x & 63;
     for (int sl = s0 + wv; sl < s1; sl += kThreads / 64) {
         const uint32_t c0 = sptr[sl];
         int r = sl * kSlice + lane;
