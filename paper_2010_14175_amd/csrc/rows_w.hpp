@@ -306,7 +306,9 @@ __device__ __forceinline__ void top2(const uint32_t *hkey, const double *hval, i
     a2 = -1.0;
     k1 = k2 = kEmptyKey;
     e1 = e2 = 0;
-#pragma unroll
+    // unrolled in full only for short scans (16 slots a lane at most for a wavefront per row, 8
+    // for smaller groups): the long scans of big tables spill when unrolled in full
+#pragma unroll(SPL <= (GS == 64 ? 16 : 8) ? SPL : 4)
     for (int jj = 0; jj < SPL; ++jj) {
         const int e = gl + GS * jj;
         const uint32_t kk = hkey[e];
@@ -593,10 +595,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(GS == 8 || (
             double yi = 0.0;  // lane j: (W^T l_i)_j, accumulated over the blocks of this step
             int nsd = 0;
             bool first = true;
-            const int nsw = GS == 64 ? wu<GS>(ns) : (int)gred<64, OpMax>((double)(act ? ns : 0));
+            const int nsw = GS == 64 ? wu<GS>(ns)
+                                     : __builtin_amdgcn_readfirstlane((int)gred<64, OpMax>((double)(act ? ns : 0)));
             for (int nw = 0; nw < nsw; nw += NB) {
                 // old positions of this block (earlier blocks of the step included)
-                const int mwb = GS == 64 ? wu<GS>(m_o) : (int)gred<64, OpMax>((double)(act ? m_o : 0));
+                const int mwb = GS == 64 ? wu<GS>(m_o)
+                                         : __builtin_amdgcn_readfirstlane((int)gred<64, OpMax>((double)(act ? m_o : 0)));
                 const int mo = wu<GS>(m_o);  // this row's old positions (a scalar with 64 lanes)
                 const bool blk = wu<GS>(act && nsd < ns);
                 const int nbk = wu<GS>(blk ? min(NB, ns - nsd) : 0);
