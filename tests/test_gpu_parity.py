@@ -195,11 +195,14 @@ def test_setup_inverse_factor_shapes(af, make, kmax, s):
 
 
 @pytest.mark.parametrize("make,kmax,s", [(lambda: synth.elast27(9, 1.0, 2), 10, 2), (lambda: synth.lap7(14), 5, 1),
+                                         (lambda: synth.lap7(12), 5, 3),
                                          (lambda: synth.elast27(6, 2.0, 5), 15, 3)])
 def test_setup_inverse_factor_table_sizes(af, make, kmax, s):
     """The inverse-factor form's result does not depend on the table size (slots only rank
     candidates; every table size gives the same G bit for bit) and agrees with the Cholesky
-    form to rounding."""
+    form to rounding.  Tables of 128 and 256 slots put the 7-point rows (6 and 16 positions)
+    on groups of 8 or 16 lanes, where a lane scans 8 or 16 slots (16 in unrolled steps rather
+    than all at once); the 27-point rows run 64 lanes per row."""
     A = make()
     dA = _dev(af, A)
     outs = []
