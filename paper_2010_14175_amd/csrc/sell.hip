@@ -251,44 +251,90 @@ __global__ __launch_bounds__(256) void k_sell_fill(int n, int nslices, const int
     }
 }
 
+// Orders LDS accesses across the lanes of one wavefront: a wavefront's LDS instructions
+// execute in issue order, so only the compiler must keep them on their side of this point.
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_wave_barrier();
+    __asm__ __volatile__("" ::: "memory");
+}
+
 // The same layout for whole rows (no split; rows in row order, or those perm assigns to each
-// slice position): each group of 8 lanes reads 8 consecutive entries of one row and writes
-// them to 8 consecutive positions of their slice columns, so a wave instruction touches 8
-// segments of the matrix instead of 64.
-template <typename VI, typename VO>
+// slice position), staged through LDS: one wavefront per slice takes its 64 rows KF entries
+// at a time, reading each row's run of KF consecutive entries with KF lanes (64 / KF rows per
+// instruction), then storing each entry position of the slice with one contiguous 64-lane
+// store.  KF = 32 for long rows (81-entry rows of the 27-point matrices: A 4.9 -> 4.0 ms at
+// 150^3), 16 otherwise (46-entry rows of G: 2.5 ms against 3.8 ms with 32).
+template <typename VI, typename VO, int KF>
 __global__ __launch_bounds__(256) void k_sell_fill_rows(int n, int nslices, const int32_t *__restrict__ rp,
                                                          const int32_t *__restrict__ m, int ld,
                                                          const int32_t *__restrict__ ci, const VI *__restrict__ val,
                                                          const int32_t *__restrict__ perm,
-                                                        const int32_t *__restrict__ srow0,
-                                                        const int32_t *__restrict__ sptr, int32_t *__restrict__ col,
-                                                        VO *__restrict__ out) {
-    const int lane = threadIdx.x & 63;
-    const int sub = lane & 7, rsub = lane >> 3;
+                                                         const int32_t *__restrict__ srow0,
+                                                         const int32_t *__restrict__ sptr, int32_t *__restrict__ col,
+                                                         VO *__restrict__ out) {
+    constexpr int RPI = 64 / KF;  // rows per read instruction
+    __shared__ int32_t lcol[4][KF][kSlice + 1];
+    __shared__ VO lval[4][KF][kSlice + 1];
+    __shared__ int64_t lstart[4][kSlice];
+    __shared__ int32_t llen[4][kSlice], lpad[4][kSlice];
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int kk = lane % KF, rq = lane / KF;
     for (int sl = (blockIdx.x * blockDim.x + threadIdx.x) >> 6; sl < nslices; sl += (gridDim.x * blockDim.x) >> 6) {
         int r0, r1;
         slice_rows(srow0, n, sl, r0, r1);
         const int64_t base = (int64_t)sptr[sl] * kSlice;
         const int width = sptr[sl + 1] - sptr[sl];
-        for (int rb = 0; rb < kSlice; rb += 8) {
-            const int r = perm ? perm[(int64_t)sl * kSlice + rb + rsub] : r0 + rb + rsub;
+        {
+            // lane = slice position: its row's start, length and padding column
+            const int r = perm ? perm[(int64_t)sl * kSlice + lane] : r0 + lane;
             const bool valid = perm ? r >= 0 : r < r1;
-            const int64_t start = valid ? row_start(rp, ld, r) : 0;
-            const int len = valid ? row_len(rp, m, r) : 0;
-            const int pad_col = valid ? r : r0;
-            for (int k = sub; k < width; k += 8) {
-                int c = pad_col;
-                VO v = VO(0);
-                if (k < len) {
-                    c = ci[start + k];
-                    v = (VO)val[start + k];
+            lstart[wv][lane] = valid ? row_start(rp, ld, r) : 0;
+            llen[wv][lane] = valid ? row_len(rp, m, r) : 0;
+            lpad[wv][lane] = valid ? r : r0;
+        }
+        wave_lds_sync();
+        for (int k0 = 0; k0 < width; k0 += KF) {
+            const int k = k0 + kk;
+            int c[kSlice / RPI];
+            VO v[kSlice / RPI];
+#pragma unroll
+            for (int j = 0; j < kSlice / RPI; ++j) {
+                const int rr = j * RPI + rq;
+                c[j] = lpad[wv][rr];
+                v[j] = VO(0);
+                if (k < llen[wv][rr]) {
+                    const int64_t e = lstart[wv][rr] + k;
+                    c[j] = ci[e];
+                    v[j] = (VO)val[e];
                 }
-                const int64_t d = base + (int64_t)k * kSlice + rb + rsub;
-                col[d] = c;
-                out[d] = v;
             }
+#pragma unroll
+            for (int j = 0; j < kSlice / RPI; ++j) {
+                lcol[wv][kk][j * RPI + rq] = c[j];
+                lval[wv][kk][j * RPI + rq] = v[j];
+            }
+            wave_lds_sync();
+            const int kn = min(KF, width - k0);
+            for (int t = 0; t < kn; ++t) {
+                const int64_t d = base + (int64_t)(k0 + t) * kSlice + lane;
+                col[d] = lcol[wv][t][lane];
+                out[d] = lval[wv][t][lane];
+            }
+            wave_lds_sync();
         }
     }
+}
+
+template <typename VI, typename VO>
+static void launch_fill_rows(bool wide, int nbs, hipStream_t s, int n, int nslices, const int32_t *rp, const int32_t *m,
+                             int ld, const int32_t *ci, const VI *val, const int32_t *perm, const int32_t *srow0,
+                             const int32_t *sptr, int32_t *col, VO *out) {
+    if (wide)
+        hipLaunchKernelGGL((k_sell_fill_rows<VI, VO, 32>), dim3(nbs), dim3(256), 0, s, n, nslices, rp, m, ld, ci, val,
+                           perm, srow0, sptr, col, out);
+    else
+        hipLaunchKernelGGL((k_sell_fill_rows<VI, VO, 16>), dim3(nbs), dim3(256), 0, s, n, nslices, rp, m, ld, ci, val,
+                           perm, srow0, sptr, col, out);
 }
 
 // leading entries of the rows longer than cap: count per row, and a 0/1 flag per row
@@ -557,21 +603,22 @@ static int sell_build(int n, int64_t nnz, const int32_t *rp, const int32_t *m, i
     if (!S.col || !S.val) return fail(set_error_code(AFSAI_ERR_NO_MEMORY, "SELL layout: out of device memory"));
     const int32_t *sp = (const int32_t *)S.sptr;
     if (cap == kNoCap && !S.init) {
-        // whole rows
+        // whole rows, staged 32 entries a row at a time for rows of 64 entries or more on average
+        const bool wide = nnz >= (int64_t)64 * n;
         if (val_f32) {
             if (out_f32)
-                hipLaunchKernelGGL((k_sell_fill_rows<float, float>), dim3(nbs), dim3(256), 0, s, n, S.nslices, rp, m, ld,
-                                   ci, (const float *)val, S.perm, S.srow0, sp, S.col, (float *)S.val);
+                launch_fill_rows<float, float>(wide, nbs, s, n, S.nslices, rp, m, ld, ci, (const float *)val, S.perm,
+                                               S.srow0, sp, S.col, (float *)S.val);
             else
-                hipLaunchKernelGGL((k_sell_fill_rows<float, double>), dim3(nbs), dim3(256), 0, s, n, S.nslices, rp,
-                                   m, ld, ci, (const float *)val, S.perm, S.srow0, sp, S.col, (double *)S.val);
+                launch_fill_rows<float, double>(wide, nbs, s, n, S.nslices, rp, m, ld, ci, (const float *)val, S.perm,
+                                                S.srow0, sp, S.col, (double *)S.val);
         } else {
             if (out_f32)
-                hipLaunchKernelGGL((k_sell_fill_rows<double, float>), dim3(nbs), dim3(256), 0, s, n, S.nslices, rp,
-                                   m, ld, ci, (const double *)val, S.perm, S.srow0, sp, S.col, (float *)S.val);
+                launch_fill_rows<double, float>(wide, nbs, s, n, S.nslices, rp, m, ld, ci, (const double *)val,
+                                                S.perm, S.srow0, sp, S.col, (float *)S.val);
             else
-                hipLaunchKernelGGL((k_sell_fill_rows<double, double>), dim3(nbs), dim3(256), 0, s, n, S.nslices, rp,
-                                   m, ld, ci, (const double *)val, S.perm, S.srow0, sp, S.col, (double *)S.val);
+                launch_fill_rows<double, double>(wide, nbs, s, n, S.nslices, rp, m, ld, ci, (const double *)val,
+                                                 S.perm, S.srow0, sp, S.col, (double *)S.val);
         }
     } else if (val_f32) {
         if (out_f32)
