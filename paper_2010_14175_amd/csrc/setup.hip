@@ -202,43 +202,73 @@ __global__ __launch_bounds__(256) void k_transpose_fill(int n, const int32_t *__
     }
 }
 
+// An entry of G^T as the fill leaves it: (row of G, value) in one 8- or 16-byte word, so that
+// each entry is one scattered store instead of two
+template <typename VT>
+struct TPair;
+template <>
+struct alignas(8) TPair<float> {
+    int32_t i;
+    float v;
+};
+template <>
+struct alignas(16) TPair<double> {
+    int32_t i, pad;
+    double v;
+};
+
 // The same from the padded per-row results (ld slots per row, m[i] valid): one thread per slot,
-// so every entry's slot reservation is independent of the others (the row is slot / ld)
+// so every entry's slot reservation is independent of the others (the row is slot / ld); the
+// entries go to `pr` as pairs, which k_sort_rows splits into columns and values
 template <typename VT>
 __global__ __launch_bounds__(256) void k_transpose_fill_ell(int n, int ld, const int32_t *__restrict__ m,
                                                             const int32_t *__restrict__ ell_col,
                                                             const double *__restrict__ ell_val,
                                                             const int32_t *__restrict__ t_rp,
-                                                            int32_t *__restrict__ fill, int32_t *__restrict__ t_ci,
-                                                            VT *__restrict__ t_val) {
+                                                            int32_t *__restrict__ fill, TPair<VT> *__restrict__ pr) {
     const int64_t total = (int64_t)n * ld;
     for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < total; k += (int64_t)gridDim.x * blockDim.x) {
         const int i = (int)(k / ld), t = (int)(k - (int64_t)i * ld);
         if (t < m[i]) {
             const int c = ell_col[k];
             const int d = t_rp[c] + atomicAdd(&fill[c], 1);
-            t_ci[d] = i;
-            t_val[d] = (VT)ell_val[k];
+            TPair<VT> e;
+            if constexpr (sizeof(VT) == 8) e.pad = 0;
+            e.i = i;
+            e.v = (VT)ell_val[k];
+            pr[d] = e;
         }
     }
 }
 
-// Sorts every row of G^T by column (= row of G).  One wavefront per row: rows of up to 256
-// entries are ranked in registers (each lane counts the smaller keys, one, two or four keys
-// per lane); longer rows fall back to an insertion sort by one lane.
+// entry e of a row of G^T before sorting: from the pairs of the fill when given, else in place
+template <typename VT>
+__device__ __forceinline__ void sort_load(const int32_t *ci, const VT *val, const TPair<VT> *pr, int64_t e, int &k,
+                                          VT &v) {
+    if (pr) {
+        const TPair<VT> q = pr[e];
+        k = q.i;
+        v = q.v;
+    } else {
+        k = ci[e];
+        v = val[e];
+    }
+}
+
+// Sorts every row of G^T by column (= row of G), reading the rows from the fill's pairs (pr)
+// or in place (pr null).  One wavefront per row: rows of up to 256 entries are ranked in
+// registers (each lane counts the smaller keys, one, two or four keys per lane); longer rows
+// fall back to an insertion sort by one lane.
 template <typename VT>
 __global__ __launch_bounds__(256) void k_sort_rows(int n, const int32_t *__restrict__ rp, int32_t *__restrict__ ci,
-                                                   VT *__restrict__ val) {
+                                                   VT *__restrict__ val, const TPair<VT> *__restrict__ pr) {
     const int lane = threadIdx.x & 63;
     for (int i = (blockIdx.x * blockDim.x + threadIdx.x) >> 6; i < n; i += (gridDim.x * blockDim.x) >> 6) {
         const int a = rp[i], b = rp[i + 1], len = b - a;
         if (len <= 64) {
             int key = 0x7fffffff;
             VT v = VT(0);
-            if (lane < len) {
-                key = ci[a + lane];
-                v = val[a + lane];
-            }
+            if (lane < len) sort_load(ci, val, pr, a + lane, key, v);
             int rank = 0;
             for (int t = 0; t < len; ++t) rank += (__shfl(key, t, 64) < key) ? 1 : 0;
             if (lane < len) {
@@ -247,13 +277,10 @@ __global__ __launch_bounds__(256) void k_sort_rows(int n, const int32_t *__restr
             }
         } else if (len <= 128) {
             // two keys per lane (the columns of a row are distinct, so the ranks are too)
-            int k0 = ci[a + lane], k1 = 0x7fffffff;
-            const VT v0 = val[a + lane];
-            VT v1 = VT(0);
-            if (lane + 64 < len) {
-                k1 = ci[a + 64 + lane];
-                v1 = val[a + 64 + lane];
-            }
+            int k0, k1 = 0x7fffffff;
+            VT v0, v1 = VT(0);
+            sort_load(ci, val, pr, a + lane, k0, v0);
+            if (lane + 64 < len) sort_load(ci, val, pr, a + 64 + lane, k1, v1);
             int r0 = 0, r1 = 0;
             for (int t = 0; t < 64; ++t) {
                 const int kt = __shfl(k0, t, 64);
@@ -282,10 +309,7 @@ __global__ __launch_bounds__(256) void k_sort_rows(int n, const int32_t *__restr
                 k[j] = 0x7fffffff;
                 v[j] = VT(0);
                 r[j] = 0;
-                if (o < len) {
-                    k[j] = ci[a + o];
-                    v[j] = val[a + o];
-                }
+                if (o < len) sort_load(ci, val, pr, a + o, k[j], v[j]);
             }
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
@@ -303,6 +327,8 @@ __global__ __launch_bounds__(256) void k_sort_rows(int n, const int32_t *__restr
                     val[a + r[j]] = v[j];
                 }
         } else if (lane == 0) {
+            if (pr)
+                for (int e = a; e < b; ++e) sort_load(ci, val, pr, e, ci[e], val[e]);
             for (int e = a + 1; e < b; ++e) {
                 const int c = ci[e];
                 const VT v = val[e];
@@ -449,18 +475,20 @@ static int build_transpose(afsai_precond_s *P, const DeviceInfo &di, hipStream_t
     int64_t tot = 0;
     if ((rc = scan_counts(n, cnt.as<int32_t>(), rp.as<int32_t>(), &tot, di, s))) return rc;
     {
+        // the fill's pairs, released (after the sort) before the SELL layout takes its memory
+        DevBuf pairs;
+        if (ell_col && (rc = dalloc(pairs, sizeof(TPair<VT>) * (size_t)nnz, s))) return rc;
         ProfScope ps("transpose", s);
         hipLaunchKernelGGL(k_fill_i32, dim3(grid1d(n, di)), dim3(256), 0, s, (int64_t)n, cnt.as<int32_t>(), 0);
         if (ell_col)
             hipLaunchKernelGGL((k_transpose_fill_ell<VT>), dim3(grid1d((int64_t)n * ld, di)), dim3(256), 0, s, n, ld,
-                               m, ell_col, ell_val, rp.as<int32_t>(), cnt.as<int32_t>(), ci.as<int32_t>(),
-                               val.as<VT>());
+                               m, ell_col, ell_val, rp.as<int32_t>(), cnt.as<int32_t>(), (TPair<VT> *)pairs.p);
         else
             hipLaunchKernelGGL((k_transpose_fill<VT>), dim3(grid1d((int64_t)n * 64, di)), dim3(256), 0, s, n,
                                P->g_rp, P->g_ci, (const VT *)P->g_val, rp.as<int32_t>(), cnt.as<int32_t>(),
                                ci.as<int32_t>(), val.as<VT>());
         hipLaunchKernelGGL((k_sort_rows<VT>), dim3(grid1d((int64_t)n * 64, di)), dim3(256), 0, s, n, rp.as<int32_t>(),
-                           ci.as<int32_t>(), val.as<VT>());
+                           ci.as<int32_t>(), val.as<VT>(), (const TPair<VT> *)pairs.p);
     }
     AFSAI_HIP_TRY(hipGetLastError());
     const bool f32 = sizeof(VT) == 4;
