@@ -438,6 +438,11 @@ const char *afsai_last_error(void);
  *                             from its XCD's counter (1..64; 0 automatic: enough rows for about
  *                             4,000 table entries of work, at most 16).  Any choice gives
  *                             identical G
+ *   AFSAI_OPT_SELL_RUNS       pcg_solve's SELL-64 layout of A (separate-update form): 0
+ *                             (automatic) one column index per run of three consecutive
+ *                             columns when every row of A is made of such runs (3 x 3 blocks
+ *                             of a 3-dof discretisation), 1 one index per entry.  Identical
+ *                             results
  * Returns AFSAI_ERR_INVALID_ARG for an unknown option or value.  Not thread safe against
  * concurrent calls of the library.
  */
@@ -455,6 +460,7 @@ const char *afsai_last_error(void);
 #define AFSAI_OPT_SETUP_FORM 12
 #define AFSAI_OPT_SETUP_LANES 13
 #define AFSAI_OPT_SETUP_CLAIM 14
+#define AFSAI_OPT_SELL_RUNS 15
 int afsai_set_option(int32_t option, int64_t value);
 
 /*

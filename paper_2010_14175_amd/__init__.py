@@ -40,7 +40,7 @@ EXPORTS = ("afsai_setup", "afsai_apply", "afsai_apply_noalloc", "pcg_solve", "af
            "afsai_profile_enable", "afsai_profile_only", "afsai_profile_read")
 (OPT_SETUP_GROUP, OPT_SETUP_TABLE, OPT_SPMV_GROUP, OPT_SPMV_UNROLL, OPT_PCG_CSR_A, OPT_PCG_FORM,
  OPT_SELL_WIDTH, OPT_PCG_GRAPH, OPT_SETUP_SLOTS, OPT_SELL_TAIL, OPT_SELL_UNEVEN, OPT_SETUP_FORM,
- OPT_SETUP_LANES, OPT_SETUP_CLAIM) = range(1, 15)
+ OPT_SETUP_LANES, OPT_SETUP_CLAIM, OPT_SELL_RUNS) = range(1, 16)
 
 
 class ServerConfigStruct(ctypes.Structure):

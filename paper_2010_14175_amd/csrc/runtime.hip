@@ -258,6 +258,7 @@ int afsai_set_option(int32_t opt, int64_t value) {
         case AFSAI_OPT_SETUP_FORM: ok = (value >= 0 && value <= 2); break;
         case AFSAI_OPT_SETUP_LANES: ok = value == 0 || (pow2(value) && value >= 8 && value <= 64); break;
         case AFSAI_OPT_SETUP_CLAIM: ok = (value >= 0 && value <= 64); break;
+        case AFSAI_OPT_SELL_RUNS: ok = (value == 0 || value == 1); break;
         default: ok = false;
     }
     if (!ok) AFSAI_FAIL(AFSAI_ERR_INVALID_ARG, "afsai_set_option: bad option %d / value %lld", opt, (long long)value);

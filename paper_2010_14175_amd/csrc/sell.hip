@@ -381,6 +381,7 @@ void sell_free(Sell *S) {
     if (!S) return;
     pool_free(S->sptr);
     pool_free(S->col);
+    pool_free(S->col3);
     pool_free(S->val);
     pool_free(S->perm);
     pool_free(S->lens);
@@ -651,6 +652,80 @@ static int sell_build(int n, int64_t nnz, const int32_t *rp, const int32_t *m, i
                                        (long long)ntail, S.tail->n));
     }
     *out = S;
+    return AFSAI_OK;
+}
+
+// slices whose width is not a multiple of three (their runs would cross slices)
+__global__ __launch_bounds__(256) void k_runs_widths(int nslices, const uint32_t *__restrict__ sptr,
+                                                     int32_t *__restrict__ bad) {
+    for (int sl = blockIdx.x * blockDim.x + threadIdx.x; sl < nslices; sl += gridDim.x * blockDim.x)
+        if ((sptr[sl + 1] - sptr[sl]) % 3u) atomicOr(bad, 1);
+}
+
+// one index per run: entries 3j, 3j+1, 3j+2 of a lane either hold consecutive columns (a run)
+// or are padding (one column three times, zero values); anything else marks the matrix
+template <typename VT>
+__global__ __launch_bounds__(256) void k_sell_runs(int n, int64_t nruns, const int32_t *__restrict__ col,
+                                                   const VT *__restrict__ val, int32_t *__restrict__ col3,
+                                                   int32_t *__restrict__ bad) {
+    bool err = false;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < nruns * kSlice;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t j = t / kSlice, lane = t % kSlice;
+        const int64_t e = 3 * j * kSlice + lane;
+        const int c0 = col[e], c1 = col[e + kSlice], c2 = col[e + 2 * kSlice];
+        int c = c0;
+        if (c1 == c0 + 1 && c2 == c0 + 2) {
+            if (c0 < 0 || c2 >= n) err = true;
+        } else if (c0 == c1 && c1 == c2 && val[e] == VT(0) && val[e + kSlice] == VT(0) &&
+                   val[e + 2 * kSlice] == VT(0)) {
+            c = max(0, min(c0, n - 3));
+        } else {
+            err = true;
+        }
+        col3[t] = c;
+    }
+    if (err) atomicOr(bad, 1);
+}
+
+int sell_group_runs(Sell *S, const DeviceInfo &di, hipStream_t s) {
+    if (S->col3 || !S->col || S->perm || S->lens || S->tail || S->init || S->rowmap || S->n < 3 || S->nslices < 1)
+        return AFSAI_OK;
+    uint32_t cols = 0;
+    if (hipMemcpyAsync(&cols, S->sptr + S->nslices, sizeof(uint32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return set_error_code(AFSAI_ERR_HIP, "SELL runs: copy of the column count failed");
+    if (cols % 3u) return AFSAI_OK;
+    const int64_t nruns = cols / 3u;
+    DevBuf flag;
+    int rc;
+    if ((rc = dalloc(flag, sizeof(int32_t), s))) return rc;
+    int32_t *c3 = (int32_t *)pool_alloc(sizeof(int32_t) * (size_t)(nruns > 0 ? nruns : 1) * kSlice);
+    if (!c3) return set_error_code(AFSAI_ERR_NO_MEMORY, "SELL runs: out of device memory");
+    int32_t hbad = 1;
+    if (hipMemsetAsync(flag.p, 0, sizeof(int32_t), s) == hipSuccess) {
+        hipLaunchKernelGGL(k_runs_widths, dim3(grid1d(S->nslices, di)), dim3(256), 0, s, S->nslices, S->sptr,
+                           flag.as<int32_t>());
+        if (S->f32)
+            hipLaunchKernelGGL((k_sell_runs<float>), dim3(grid1d(nruns * kSlice, di)), dim3(256), 0, s, S->n, nruns,
+                               S->col, (const float *)S->val, c3, flag.as<int32_t>());
+        else
+            hipLaunchKernelGGL((k_sell_runs<double>), dim3(grid1d(nruns * kSlice, di)), dim3(256), 0, s, S->n, nruns,
+                               S->col, (const double *)S->val, c3, flag.as<int32_t>());
+        if (hipGetLastError() != hipSuccess ||
+            hipMemcpyAsync(&hbad, flag.p, sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess) {
+            pool_free(c3);
+            return set_error_code(AFSAI_ERR_HIP, "SELL runs: conversion failed");
+        }
+    }
+    if (hbad) {
+        pool_free(c3);
+        return AFSAI_OK;
+    }
+    pool_free(S->col);
+    S->col = nullptr;
+    S->col3 = c3;
     return AFSAI_OK;
 }
 

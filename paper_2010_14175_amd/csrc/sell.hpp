@@ -30,7 +30,10 @@ struct Sell {
     int n = 0;
     int nslices = 0;
     uint32_t *sptr = nullptr;   // [nslices + 1] offsets in 64-entry columns
-    int32_t *col = nullptr;     // [sptr[nslices] * 64]
+    int32_t *col = nullptr;     // [sptr[nslices] * 64] (nullptr when col3 holds the columns)
+    int32_t *col3 = nullptr;    // column runs: every row stores runs of three consecutive
+                                // columns (c, c+1, c+2), so one index per run is kept:
+                                // [sptr[nslices] / 3 * 64], run j of a slice at its entry 3j
     void *val = nullptr;        // double or float, same layout
     int32_t *perm = nullptr;    // [nslices * 64] row of each slice lane (nullptr: identity)
     int32_t *lens = nullptr;    // [nslices * 64] entries of each slice lane's row (nullptr: all
@@ -68,5 +71,12 @@ int sell_from_csr(int n, int64_t nnz, const int32_t *rp, const int32_t *ci, cons
 int sell_from_ell(int n, int64_t nnz, int ld, const int32_t *m, const int32_t *ell_col, const double *ell_val,
                   bool out_f32, Sell *out, const DeviceInfo &di, hipStream_t s, const Segments &seg = Segments());
 void sell_free(Sell *S);
+// Replace a plain layout's column array (no ordering, split or tail) by one index per run of
+// three consecutive columns when every slice's stored entries, padding included, fall into
+// such runs (the 3 x 3 blocks of a 3-dof discretisation; padding runs are (r, r, r) with
+// zero values and become (c, c+1, c+2) with c <= n - 3).  Values and their order are
+// unchanged, so every row's sum is the same chain.  Leaves S as it is when the matrix does
+// not qualify.  Synchronous on s.
+int sell_group_runs(Sell *S, const DeviceInfo &di, hipStream_t s);
 
 }  // namespace afsai

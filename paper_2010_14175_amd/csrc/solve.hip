@@ -452,6 +452,106 @@ __global__ __launch_bounds__(kThreads) void k_sell_spmv(int n, int nslices, cons
     }
 }
 
+// One lane's sum over `nr` runs of three consecutive columns (the layout with one column
+// index per run): the values of run j are entries 3j..3j+2 of the lane, stored kSlice apart
+// from vbase, its first column at rbase + j * kSlice.  The same sequential fma chain over the
+// entries in stored order as lane_chain, with UR runs (3 UR entries) in flight.
+template <int UR, typename VT>
+__device__ __forceinline__ double run_chain(const int32_t *__restrict__ col3, const VT *__restrict__ val,
+                                            const double *__restrict__ x, int64_t rbase, int64_t vbase, int nr,
+                                            double acc) {
+    int c[UR];
+    VT v[UR][3];
+#pragma unroll
+    for (int u = 0; u < UR; ++u) {
+        c[u] = 0;
+#pragma unroll
+        for (int e = 0; e < 3; ++e) v[u][e] = VT(0);
+        if (u < nr) {
+            c[u] = __builtin_nontemporal_load(&col3[rbase + (int64_t)u * kSlice]);
+#pragma unroll
+            for (int e = 0; e < 3; ++e) v[u][e] = __builtin_nontemporal_load(&val[vbase + (int64_t)(3 * u + e) * kSlice]);
+        }
+    }
+    for (int j0 = 0; j0 < nr; j0 += UR) {
+        int cn[UR];
+        VT vn[UR][3];
+#pragma unroll
+        for (int u = 0; u < UR; ++u) {
+            cn[u] = 0;
+#pragma unroll
+            for (int e = 0; e < 3; ++e) vn[u][e] = VT(0);
+            if (j0 + UR + u < nr) {
+                const int j = j0 + UR + u;
+                cn[u] = __builtin_nontemporal_load(&col3[rbase + (int64_t)j * kSlice]);
+#pragma unroll
+                for (int e = 0; e < 3; ++e)
+                    vn[u][e] = __builtin_nontemporal_load(&val[vbase + (int64_t)(3 * j + e) * kSlice]);
+            }
+        }
+        double xv[UR][3];
+#pragma unroll
+        for (int u = 0; u < UR; ++u)
+#pragma unroll
+            for (int e = 0; e < 3; ++e) xv[u][e] = (j0 + u < nr) ? x[c[u] + e] : 0.0;
+#pragma unroll
+        for (int u = 0; u < UR; ++u)
+            if (j0 + u < nr) {
+#pragma unroll
+                for (int e = 0; e < 3; ++e) acc = fma((double)v[u][e], xv[u][e], acc);
+            }
+#pragma unroll
+        for (int u = 0; u < UR; ++u) {
+            c[u] = cn[u];
+#pragma unroll
+            for (int e = 0; e < 3; ++e) v[u][e] = vn[u][e];
+        }
+    }
+    return acc;
+}
+
+// SELL-64 product over the layout with one column index per run of three (plain layouts
+// only: natural row order, no split): the walk, row sums, stores and fused dot of k_sell_spmv,
+// so products and dots are identical to it bit for bit.
+template <int UR, typename VT, bool DOT>
+__global__ __launch_bounds__(kThreads) void k_sell_spmv_runs(int n, const uint32_t *__restrict__ sptr,
+                                                             const int32_t *__restrict__ srow0,
+                                                             const int32_t *__restrict__ col3,
+                                                             const VT *__restrict__ val,
+                                                             const double *__restrict__ x, double *__restrict__ y,
+                                                             const double *__restrict__ w,
+                                                             double *__restrict__ partials, PcgScalars *scs, Map mp,
+                                                             Systems sy, int nslices, int nxcd) {
+    const Job jb = block_job(mp, nxcd);
+    if (scs && scs[jb.k].done) return;
+    __shared__ double sh[kThreads / 64];
+    const int sb = sy.slice0 ? sy.slice0[jb.k] : 0;
+    const int sn = sy.slice0 ? sy.slice0[jb.k + 1] - sb : nslices;
+    const int wv = wave_index(), lane = threadIdx.x & 63;
+    double part = 0.0;
+    int w0, w1, wstep;
+    window_walk((sn + kWin - 1) / kWin, jb.lb, jb.nb, nxcd, w0, w1, wstep);
+    for (int wi = w0; wi < w1; wi += wstep) {
+        const int sl = sb + wi * kWin + wv;
+        if (sl >= sb + sn) break;
+        int r0, r1;
+        sell_slice_rows(srow0, n, sl, r0, r1);
+        const int r = r0 + lane;
+        const uint32_t c0 = sptr[sl];
+        const int nr = (int)(sptr[sl + 1] - c0) / 3;
+        const double acc = run_chain<UR, VT>(col3, val, x, (int64_t)(c0 / 3u) * kSlice + lane,
+                                             (int64_t)c0 * kSlice + lane, nr, 0.0);
+        if (r < r1) {
+            y[r] = acc;
+            if (DOT) part = fma(acc, w[r], part);
+        }
+    }
+    if (DOT) {
+        const double bs = block_sum(part, sh);
+        store_partials(partials, 1, &bs, jb.gb);
+    }
+}
+
 // Fused PCG products (SELL-64, one lane per row, layouts without a tail).  The vector being
 // multiplied is formed on the fly from two others with the same fma the separate update
 // kernel would use, so the result is identical to update-then-multiply; the owner lane of
@@ -859,6 +959,17 @@ static void launch_sell_t(const Sell &S, const double *x, double *y, const doubl
     const int32_t *tcl = T ? T->col : nullptr;
     const VT *tvl = T ? (const VT *)T->val : nullptr;
     const int32_t *tof = T ? S.toff : nullptr;
+    if (S.col3) {
+        // runs of three: about as many entries in flight as U
+        constexpr int UR = U >= 8 ? 3 : 1;
+        if (w)
+            hipLaunchKernelGGL((k_sell_spmv_runs<UR, VT, true>), dim3(nb), dim3(kThreads), 0, s, S.n, S.sptr,
+                               S.srow0, S.col3, (const VT *)S.val, x, y, w, partials, scs, mp, sy, S.nslices, nxcd);
+        else
+            hipLaunchKernelGGL((k_sell_spmv_runs<UR, VT, false>), dim3(nb), dim3(kThreads), 0, s, S.n, S.sptr,
+                               S.srow0, S.col3, (const VT *)S.val, x, y, w, partials, scs, mp, sy, S.nslices, nxcd);
+        return;
+    }
     if (S.lens) {
         if (w)
             hipLaunchKernelGGL((k_sell_spmv<U, VT, true, true>), dim3(nb), dim3(kThreads), 0, s, S.n, S.nslices,
@@ -1410,6 +1521,13 @@ class PcgRun {
         for (int k = 0; k < nsys_; ++k) nmax = std::max(nmax, row0_[k + 1] - row0_[k]);
         const bool want_fused = form == 2 || (form == 0 && nmax < kFusedMaxRows);
         fused_ = P_ && use_sell_ && want_fused && !As_.tail && !P_->sg.tail && !As_.perm && !P_->sg.perm;
+        // A's product with one column index per run of three consecutive columns where every
+        // row is made of such runs (3 x 3 blocks): 9.3 instead of 12 bytes per FP64 entry, the
+        // same sums (the fused kernels keep the plain layout)
+        if (use_sell_ && !prepared_ && !fused_ && option(AFSAI_OPT_SELL_RUNS) != 1) {
+            ProfScope ps("sell_A_runs", s_);
+            if ((rc = sell_group_runs(&As_, di_, s_))) return rc;
+        }
         // iterations replayed from captured graphs only when asked for (never while the kernel
         // timer is on: its events would be captured); on MI355X with ROCm 7 enqueuing the
         // kernels measured faster than replaying graphs at every size tried

@@ -105,6 +105,9 @@ def test_options_validated_on_host(L):
     assert L.afsai_set_option(af.OPT_SPMV_GROUP, 3) == af.ERR_INVALID_ARG
     assert L.afsai_set_option(af.OPT_SETUP_TABLE, 4096) == af.ERR_INVALID_ARG
     assert L.afsai_set_option(99, 0) == af.ERR_INVALID_ARG
+    assert L.afsai_set_option(af.OPT_SELL_RUNS, 2) == af.ERR_INVALID_ARG
+    assert L.afsai_set_option(af.OPT_SELL_RUNS, 1) == af.OK
+    assert L.afsai_set_option(af.OPT_SELL_RUNS, 0) == af.OK
     assert L.afsai_set_option(af.OPT_SPMV_GROUP, 16) == af.OK
     assert L.afsai_set_option(af.OPT_SPMV_GROUP, 0) == af.OK
 

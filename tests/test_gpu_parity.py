@@ -516,6 +516,33 @@ def test_pcg_elasticity_reduced(af):
     assert np.linalg.norm(x - ro.x) <= X_RTOL * np.linalg.norm(ro.x)
 
 
+@pytest.mark.parametrize("make", [lambda: synth.elasticity27(16), lambda: synth.elasticity27(11, sigma=2.0, seed=5),
+                                  lambda: synth.poisson7(12)])
+def test_pcg_column_runs_layout(af, make):
+    """A's SELL layout with one column index per run of three consecutive columns (every row of
+    a 3-dof 27-point operator; the 11^3 grid leaves a ragged last slice) gives the per-entry
+    layout's iterates bit for bit, and the oracle's iteration count and x within 1e-10; a
+    matrix without such runs (7-point) keeps the per-entry layout."""
+    Pb = make()
+    dA = _dev(af, Pb.A)
+    P = af.setup(dA, 10, 2, 1e-2)
+    b = _vec(Pb.b)
+    af.set_option(af.OPT_PCG_FORM, 1)  # the separate-update form multiplies with this layout
+    try:
+        x1, i1 = af.pcg_solve(dA, P, b, rtol=Pb.rtol)
+        af.set_option(af.OPT_SELL_RUNS, 1)
+        x0, i0 = af.pcg_solve(dA, P, b, rtol=Pb.rtol)
+    finally:
+        af.set_option(af.OPT_SELL_RUNS, 0)
+        af.set_option(af.OPT_PCG_FORM, 0)
+    assert i1.iters == i0.iters and i1.converged
+    assert np.array_equal(x1.cpu().numpy(), x0.cpu().numpy())
+    G = oracle.setup(Pb.A, 10, 2, 1e-2)
+    ro = oracle.pcg(Pb.A, G, Pb.b, Pb.rtol)
+    assert i1.iters == ro.iters, (i1.iters, ro.iters)
+    assert np.linalg.norm(x1.cpu().numpy() - ro.x) <= X_RTOL * np.linalg.norm(ro.x)
+
+
 def test_pcg_fp32_g(af):
     Pb = synth.elasticity27(16)
     x, info, ro = _pcg_pair(af, Pb, 10, 2, g_prec=1)
