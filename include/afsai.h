@@ -300,7 +300,8 @@ typedef struct afsai_matrix_s *afsai_matrix;
 /*
  * afsai_matrix_prepare -- converts A to its SELL-64 layout on the current device.
  *   A's arrays are read during the call only; the handle owns a device copy (about
- *   12 bytes per entry plus padding) and A's values may change afterwards without affecting it
+ *   12 bytes per entry plus padding, 13.3 when A's rows are made of runs of three
+ *   consecutive columns and run indices are kept beside the columns) and A's values may change afterwards without affecting it
  *   (prepare again to take them).  *out = NULL on failure.  Synchronous on stream.
  *   Errors: AFSAI_ERR_INVALID_ARG, AFSAI_ERR_NO_MEMORY, AFSAI_ERR_TOO_LARGE, AFSAI_ERR_HIP.
  */
@@ -442,7 +443,8 @@ const char *afsai_last_error(void);
  *                             (automatic) one column index per run of three consecutive
  *                             columns when every row of A is made of such runs (3 x 3 blocks
  *                             of a 3-dof discretisation), 1 one index per entry.  Identical
- *                             results
+ *                             results.  A prepared matrix takes the setting in force at
+ *                             afsai_matrix_prepare
  * Returns AFSAI_ERR_INVALID_ARG for an unknown option or value.  Not thread safe against
  * concurrent calls of the library.
  */

@@ -688,7 +688,7 @@ __global__ __launch_bounds__(256) void k_sell_runs(int n, int64_t nruns, const i
     if (err) atomicOr(bad, 1);
 }
 
-int sell_group_runs(Sell *S, const DeviceInfo &di, hipStream_t s) {
+int sell_group_runs(Sell *S, const DeviceInfo &di, hipStream_t s, bool keep_col) {
     if (S->col3 || !S->col || S->perm || S->lens || S->tail || S->init || S->rowmap || S->n < 3 || S->nslices < 1)
         return AFSAI_OK;
     uint32_t cols = 0;
@@ -723,8 +723,10 @@ int sell_group_runs(Sell *S, const DeviceInfo &di, hipStream_t s) {
         pool_free(c3);
         return AFSAI_OK;
     }
-    pool_free(S->col);
-    S->col = nullptr;
+    if (!keep_col) {
+        pool_free(S->col);
+        S->col = nullptr;
+    }
     S->col3 = c3;
     return AFSAI_OK;
 }

@@ -76,7 +76,8 @@ void sell_free(Sell *S);
 // such runs (the 3 x 3 blocks of a 3-dof discretisation; padding runs are (r, r, r) with
 // zero values and become (c, c+1, c+2) with c <= n - 3).  Values and their order are
 // unchanged, so every row's sum is the same chain.  Leaves S as it is when the matrix does
-// not qualify.  Synchronous on s.
-int sell_group_runs(Sell *S, const DeviceInfo &di, hipStream_t s);
+// not qualify.  With keep_col the per-entry columns stay beside the run indices (for kernels
+// that read them, such as the block products of a prepared matrix).  Synchronous on s.
+int sell_group_runs(Sell *S, const DeviceInfo &di, hipStream_t s, bool keep_col = false);
 
 }  // namespace afsai

@@ -2073,6 +2073,9 @@ int afsai_matrix_prepare(const afsai_csr *A, void *stream, afsai_matrix *out) {
     {
         ProfScope ps("sell_A", s);
         rc = sell_from_csr(A->n, A->nnz, A->row_ptr, A->col_idx, A->val, false, false, &M->S, di, s);
+        // run indices for pcg_solve_prepared's products, the per-entry columns kept for the
+        // block products
+        if (rc == AFSAI_OK && option(AFSAI_OPT_SELL_RUNS) != 1) rc = sell_group_runs(&M->S, di, s, true);
     }
     if (rc == AFSAI_OK && hipStreamSynchronize(s) != hipSuccess) rc = set_error_code(AFSAI_ERR_HIP, "afsai_matrix_prepare: synchronisation failed");
     if (rc != AFSAI_OK) {

@@ -543,6 +543,31 @@ def test_pcg_column_runs_layout(af, make):
     assert np.linalg.norm(x1.cpu().numpy() - ro.x) <= X_RTOL * np.linalg.norm(ro.x)
 
 
+def test_prepared_matrix_column_runs(af):
+    """A prepared 3-dof matrix keeps run indices beside its per-entry columns: its PCG in the
+    separate-update form (which multiplies with the run layout) and its block products (which
+    read the per-entry columns) equal the unprepared calls bit for bit."""
+    import torch
+
+    Pb = synth.elasticity27(12, sigma=2.0, seed=7)
+    dA = _dev(af, Pb.A)
+    P = af.setup(dA, 10, 2, 1e-2)
+    b = _vec(Pb.b)
+    af.set_option(af.OPT_PCG_FORM, 1)
+    try:
+        M = af.PreparedMatrix(dA)
+        x0, i0 = af.pcg_solve(dA, P, b, rtol=Pb.rtol)
+        x1, i1 = M.pcg_solve(P, b, rtol=Pb.rtol)
+    finally:
+        af.set_option(af.OPT_PCG_FORM, 0)
+    assert i0.iters == i1.iters and i1.converged
+    assert torch.equal(x0, x1)
+    X = torch.from_numpy(synth.uniform(29, 5, Pb.n * 4, -1.0, 1.0).reshape(Pb.n, 4)).cuda()
+    assert torch.equal(M.spmm(X), af.spmm(dA, X))
+    M.close()
+    P.close()
+
+
 def test_pcg_fp32_g(af):
     Pb = synth.elasticity27(16)
     x, info, ro = _pcg_pair(af, Pb, 10, 2, g_prec=1)
