@@ -543,6 +543,68 @@ def test_pcg_column_runs_layout(af, make):
     assert np.linalg.norm(x1.cpu().numpy() - ro.x) <= X_RTOL * np.linalg.norm(ro.x)
 
 
+def _broken_runs_elasticity():
+    """8^3 27-point 3-dof operator with three symmetric pairs of entries removed from one
+    interior row, each from a different run of three columns: the slices keep widths that are
+    multiples of three, but that row's and three other rows' triples are no longer runs."""
+    import scipy.sparse as sp
+
+    A = synth.elast27(8, 1.0, 2)
+    M = sp.csr_matrix((A.val, A.col, A.row_ptr), shape=(A.n, A.n)).tolil()
+    i = 3 * (4 * 64 + 4 * 8 + 4)  # first dof of an interior node
+    cols = [c for c in M.rows[i] if c // 3 != i // 3]
+    for j in (cols[0], cols[len(cols) // 2 + 1], cols[-1]):
+        M[i, j] = 0.0
+        M[j, i] = 0.0
+    M = M.tocsr()
+    M.eliminate_zeros()
+    M.sort_indices()
+    return synth.CSR(M.indptr.astype(np.int32), M.indices.astype(np.int32), M.data.astype(np.float64))
+
+
+def test_pcg_column_runs_rejected(af):
+    """A matrix whose triples are not all runs keeps the per-entry layout: the separate-update
+    PCG equals the run option switched off bit for bit and the oracle within 1e-10."""
+    A = _broken_runs_elasticity()
+    lens = np.diff(A.row_ptr)
+    assert np.count_nonzero(lens % 3) == 3  # the three partner rows
+    assert all(lens[k:k + 64].max() % 3 == 0 for k in range(0, A.n, 64))  # slice widths pass
+    assert np.linalg.eigvalsh(_dense(A)).min() > 0.0  # still SPD
+    xt = synth.uniform(31, 5, A.n, -1.0, 1.0)
+    b = _spmv_host(A, xt)
+    dA = _dev(af, A)
+    P = af.setup(dA, 10, 2, 1e-2)
+    af.set_option(af.OPT_PCG_FORM, 1)
+    try:
+        x1, i1 = af.pcg_solve(dA, P, _vec(b), rtol=1e-8)
+        af.set_option(af.OPT_SELL_RUNS, 1)
+        x0, i0 = af.pcg_solve(dA, P, _vec(b), rtol=1e-8)
+    finally:
+        af.set_option(af.OPT_SELL_RUNS, 0)
+        af.set_option(af.OPT_PCG_FORM, 0)
+    assert i1.iters == i0.iters and i1.converged
+    assert np.array_equal(x1.cpu().numpy(), x0.cpu().numpy())
+    G = oracle.setup(A, 10, 2, 1e-2)
+    ro = oracle.pcg(A, G, b, 1e-8)
+    assert i1.iters == ro.iters, (i1.iters, ro.iters)
+    assert np.linalg.norm(x1.cpu().numpy() - ro.x) <= X_RTOL * np.linalg.norm(ro.x)
+
+
+def _dense(A):
+    D = np.zeros((A.n, A.n))
+    for r in range(A.n):
+        D[r, A.col[A.row_ptr[r]:A.row_ptr[r + 1]]] = A.val[A.row_ptr[r]:A.row_ptr[r + 1]]
+    return D
+
+
+def _spmv_host(A, x):
+    y = np.zeros(A.n)
+    for r in range(A.n):
+        lo, hi = A.row_ptr[r], A.row_ptr[r + 1]
+        y[r] = np.dot(A.val[lo:hi], x[A.col[lo:hi]])
+    return y
+
+
 def test_prepared_matrix_column_runs(af):
     """A prepared 3-dof matrix keeps run indices beside its per-entry columns: its PCG in the
     separate-update form (which multiplies with the run layout) and its block products (which
