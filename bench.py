@@ -825,6 +825,9 @@ def main():
                     help="skip the comparison of the plain and precision forms at the 150^3 and 64^3 workloads")
     ap.add_argument("--setup-f32", action="store_true",
                     help="per-row setup arithmetic in FP32 (reports pattern agreement with the FP64 setup)")
+    ap.add_argument("--per-entry-a", action="store_true",
+                    help="A's SELL layout in the PCG with one column index per entry (AFSAI_OPT_SELL_RUNS = 1) "
+                         "instead of one per run of three consecutive columns")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=0)
     ap.add_argument("--no-profile", action="store_true", help="do not time kernels with HIP events")
@@ -849,6 +852,8 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     af.lib()
+    if args.per_entry_a:
+        af.set_option(af.OPT_SELL_RUNS, 1)
 
     if args.workload in BATCH_WORKLOADS:
         batch_bench(args)
