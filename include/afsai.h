@@ -372,7 +372,8 @@ void afsai_destroy(afsai_precond P);
 
 /*
  * afsai_release_cache -- the library keeps device blocks it has freed (temporaries of setup
- *   and solve, destroyed handles) for reuse; this returns them all to the HIP runtime.
+ *   and solve, destroyed handles) and the pinned host blocks of finished solves for reuse;
+ *   this returns them all to the HIP runtime.
  *   Call only while no other library call is running.
  */
 int afsai_release_cache(void);

@@ -46,6 +46,9 @@ int64_t option(int id);
 // ---------------------------------------------------------------------------------------
 void *pool_alloc(size_t bytes);  // nullptr on failure
 void pool_free(void *p);          // p may be nullptr; the caller guarantees no pending use
+// pinned host memory from the same kind of cache (hipHostMalloc only on a miss)
+void *pinned_alloc(size_t bytes);  // nullptr on failure
+void pinned_free(void *p);         // p may be nullptr; the caller guarantees no pending use
 
 // temporary device buffer, returned to the pool when it goes out of scope; the stream is
 // synchronised first so that no enqueued kernel still uses it

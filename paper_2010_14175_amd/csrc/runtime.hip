@@ -107,6 +107,44 @@ void pool_free(void *p) {
     pool_live.erase(it);
 }
 
+// pinned host blocks (device-visible scalars of the solver), cached by size class like the
+// device blocks; pinned memory is not tied to a device
+namespace {
+std::map<void *, size_t> pinned_live;
+std::multimap<size_t, void *> pinned_free_;
+}  // namespace
+
+void *pinned_alloc(size_t bytes) {
+    const size_t sz = size_class(bytes);
+    {
+        std::lock_guard<std::mutex> lk(pool_mu);
+        auto it = pinned_free_.lower_bound(sz);
+        if (it != pinned_free_.end() && it->first <= 2 * sz) {
+            void *p = it->second;
+            pinned_live[p] = it->first;
+            pinned_free_.erase(it);
+            return p;
+        }
+    }
+    void *p = nullptr;
+    if (hipHostMalloc(&p, sz, hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lk(pool_mu);
+    pinned_live[p] = sz;
+    return p;
+}
+
+void pinned_free(void *p) {
+    if (!p) return;
+    std::lock_guard<std::mutex> lk(pool_mu);
+    auto it = pinned_live.find(p);
+    if (it == pinned_live.end()) return;
+    pinned_free_.emplace(it->second, p);
+    pinned_live.erase(it);
+}
+
 int device_info(DeviceInfo *out) {
     static std::mutex mu;
     static std::map<int, DeviceInfo> cache;
@@ -267,14 +305,17 @@ int afsai_set_option(int32_t opt, int64_t value) {
 }
 
 int afsai_release_cache(void) {
-    std::vector<void *> drop;
+    std::vector<void *> drop, dropped_pinned;
     {
         std::lock_guard<std::mutex> lk(afsai::pool_mu);
         for (auto &dv : afsai::pool_free_)
             for (auto &kv : dv.second) drop.push_back(kv.second);
         afsai::pool_free_.clear();
+        for (auto &kv : afsai::pinned_free_) dropped_pinned.push_back(kv.second);
+        afsai::pinned_free_.clear();
     }
     for (void *q : drop) AFSAI_HIP_TRY(hipFree(q));
+    for (void *q : dropped_pinned) AFSAI_HIP_TRY(hipHostFree(q));
     return AFSAI_OK;
 }
 

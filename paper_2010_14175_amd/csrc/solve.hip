@@ -1441,7 +1441,7 @@ class PcgRun {
         if (!prepared_) sell_free(&As_);
         for (hipEvent_t e : {t0_, t1_, ev_[0], ev_[1], ev_[2], ev_[3]})
             if (e) (void)hipEventDestroy(e);
-        if (hsc_) (void)hipHostFree(hsc_);
+        pinned_free(hsc_);
     }
     PcgRun(const PcgRun &) = delete;
     PcgRun &operator=(const PcgRun &) = delete;
@@ -1453,7 +1453,9 @@ class PcgRun {
         AFSAI_HIP_TRY(hipEventCreate(&t0_));
         AFSAI_HIP_TRY(hipEventCreate(&t1_));
         for (hipEvent_t &e : ev_) AFSAI_HIP_TRY(hipEventCreate(&e));
-        AFSAI_HIP_TRY(hipHostMalloc(&hsc_, 2 * sizeof(PcgScalars) * (size_t)nsys_, hipHostMallocDefault));
+        // the host copies of the scalars (cached pinned blocks: no hipHostMalloc per solve)
+        hsc_ = (PcgScalars *)pinned_alloc(2 * sizeof(PcgScalars) * (size_t)nsys_);
+        if (!hsc_) return set_error_code(AFSAI_ERR_NO_MEMORY, "pcg: out of pinned host memory");
         hs_[0] = hsc_;
         hs_[1] = hsc_ + nsys_;
         AFSAI_HIP_TRY(hipHostGetDevicePointer((void **)&dhs_[0], hsc_, 0));
