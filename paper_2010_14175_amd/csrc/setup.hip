@@ -581,12 +581,14 @@ static int setup_core(const afsai_csr *A, const afsai_params *p, int nsys, const
         DevBuf r0b;
         if ((rc = dalloc(r0b, sizeof(int32_t) * (size_t)(nsys + 1), s))) return rc;
         AFSAI_HIP_TRY(hipMemcpyAsync(r0b.p, row0, sizeof(int32_t) * (size_t)(nsys + 1), hipMemcpyHostToDevice, s));
+        // a result of its own: the row scan's (longest row) stays in `so`
+        ScanOut sb{};
         AFSAI_HIP_TRY(hipMemsetAsync(scanb.p, 0, sizeof(ScanOut), s));
         hipLaunchKernelGGL(k_block_check, dim3(grid1d(n, di)), dim3(256), 0, s, n, A->row_ptr, A->col_idx, nsys,
                            r0b.as<int32_t>(), scanb.as<ScanOut>());
-        AFSAI_HIP_TRY(hipMemcpyAsync(&so, scanb.p, sizeof so, hipMemcpyDeviceToHost, s));
+        AFSAI_HIP_TRY(hipMemcpyAsync(&sb, scanb.p, sizeof sb, hipMemcpyDeviceToHost, s));
         AFSAI_HIP_TRY(hipStreamSynchronize(s));
-        if (so.bad) AFSAI_FAIL(AFSAI_ERR_BAD_MATRIX, "afsai_setup_batched: a row has entries outside its system");
+        if (sb.bad) AFSAI_FAIL(AFSAI_ERR_BAD_MATRIX, "afsai_setup_batched: a row has entries outside its system");
     }
     const int maxlen = so.maxlen > 0 ? so.maxlen : 1;
 

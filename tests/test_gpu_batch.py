@@ -105,6 +105,52 @@ def test_batched_apply_equals_standalone(af):
     assert np.linalg.norm(z - zo) <= 1e-10 * np.linalg.norm(zo)
 
 
+def test_batched_setup_wide_rows(af):
+    """Batches of 27-point 3-dof systems (rows of up to 81 entries): the candidate tables are
+    sized from the longest row of the batch, so every system's G equals its separate setup
+    bit for bit (the batch check once overwrote that length, and such batches overflowed)."""
+    probs = [synth.elasticity27(N, sigma=2.0, seed=40 + N) for N in (5, 7, 9, 11)]
+    A, off, _, _ = synth.block_diag(probs)
+    P = af.setup_batched(af.DeviceCSR.from_host(A), off, 10, 2, 1e-2)
+    rp, ci, va = _factor(P)
+    for k, pb in enumerate(probs):
+        rk, ck, vk = _factor(af.setup(af.DeviceCSR.from_host(pb.A), 10, 2, 1e-2))
+        lo, hi = rp[off[k]], rp[off[k + 1]]
+        assert np.array_equal(rp[off[k]:off[k + 1] + 1] - lo, rk), k
+        assert np.array_equal(ci[lo:hi] - off[k], ck), k
+        assert np.array_equal(va[lo:hi].view(np.int64), vk.view(np.int64)), k
+
+
+def test_batched_column_runs(af):
+    """A batch of 3-dof systems (375 .. 3,993 rows, slices starting at every system's first row,
+    ragged last slices) in the separate-update form multiplies with A's column-run layout: each
+    system's iterates equal its separate solve and the per-entry layout's bit for bit."""
+    import torch
+
+    probs = [synth.elasticity27(N, sigma=2.0, seed=40 + N) for N in (5, 7, 9, 11)]
+    A, off, b, _ = synth.block_diag(probs)
+    dA = af.DeviceCSR.from_host(A)
+    P = af.setup_batched(dA, off, 10, 2, 1e-2)
+    af.set_option(af.OPT_PCG_FORM, 1)
+    try:
+        x, infos = af.pcg_solve_batched(dA, P, off, _vec(b), rtol=1e-8)
+        af.set_option(af.OPT_SELL_RUNS, 1)
+        xe, infe = af.pcg_solve_batched(dA, P, off, _vec(b), rtol=1e-8)
+        af.set_option(af.OPT_SELL_RUNS, 0)
+        xh = x.cpu().numpy()
+        assert torch.equal(x, xe)
+        for k, pb in enumerate(probs):
+            assert infos[k].iters == infe[k].iters and infos[k].converged
+            dk = af.DeviceCSR.from_host(pb.A)
+            Pk = af.setup(dk, 10, 2, 1e-2)
+            xk, ik = af.pcg_solve(dk, Pk, _vec(pb.b), rtol=1e-8)
+            assert infos[k].iters == ik.iters, (k, infos[k].iters, ik.iters)
+            assert np.array_equal(xh[off[k]:off[k + 1]].view(np.int64), xk.cpu().numpy().view(np.int64)), k
+    finally:
+        af.set_option(af.OPT_SELL_RUNS, 0)
+        af.set_option(af.OPT_PCG_FORM, 0)
+
+
 def test_batched_pcg_against_oracle(af):
     probs, A, off, b, _ = _batch(5, 3, 9)
     dA = af.DeviceCSR.from_host(A)
