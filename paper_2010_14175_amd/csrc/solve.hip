@@ -1181,6 +1181,98 @@ __global__ __launch_bounds__(kThreads) void k_sell_spmm(int n, int nslices, cons
     }
 }
 
+// Block product over the layout with one column index per run of three (plain layouts: no
+// length ordering): a lane reads a run's index and its three values and the 3K consecutive
+// entries of X's rows c..c+2; per column the sum is the same chain over the entries in stored
+// order as k_sell_spmm's, so Y and the partial sums are identical to it bit for bit.
+template <int K, bool DOT = false>
+__global__ __launch_bounds__(kThreads) void k_sell_spmm_runs(int n, int nslices, const uint32_t *__restrict__ sptr,
+                                                              const int32_t *__restrict__ col3,
+                                                              const double *__restrict__ val,
+                                                              const double *__restrict__ x, double *__restrict__ y,
+                                                              int nxcd, const double *__restrict__ w = nullptr,
+                                                              double *__restrict__ partials = nullptr) {
+    constexpr int UR = K <= 2 ? 3 : 1;  // runs in flight per lane (9 or 3 entries)
+    __shared__ double sh[kThreads / 64];
+    double part[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) part[j] = 0.0;
+    const int lb = xcd_block(blockIdx.x, gridDim.x, nxcd);
+    const int wv = wave_index(), lane = threadIdx.x & 63;
+    int w0, w1, wstep;
+    window_walk((nslices + kWin - 1) / kWin, lb, gridDim.x, nxcd, w0, w1, wstep);
+    for (int wi = w0; wi < w1; wi += wstep) {
+        const int sl = wi * kWin + wv;
+        if (sl >= nslices) break;
+        const uint32_t c0 = sptr[sl];
+        const int r = sl * kSlice + lane;
+        const int nr = (int)(sptr[sl + 1] - c0) / 3;
+        const int64_t rbase = (int64_t)(c0 / 3u) * kSlice + lane, vbase = (int64_t)c0 * kSlice + lane;
+        double acc[K];
+#pragma unroll
+        for (int j = 0; j < K; ++j) acc[j] = 0.0;
+        int c[UR];
+        double v[UR][3];
+#pragma unroll
+        for (int u = 0; u < UR; ++u) {
+            c[u] = 0;
+#pragma unroll
+            for (int e = 0; e < 3; ++e) v[u][e] = 0.0;
+            if (u < nr) {
+                c[u] = __builtin_nontemporal_load(&col3[rbase + (int64_t)u * kSlice]);
+#pragma unroll
+                for (int e = 0; e < 3; ++e) v[u][e] = __builtin_nontemporal_load(&val[vbase + (int64_t)(3 * u + e) * kSlice]);
+            }
+        }
+        for (int j0 = 0; j0 < nr; j0 += UR) {
+            int cn[UR];
+            double vn[UR][3];
+#pragma unroll
+            for (int u = 0; u < UR; ++u) {
+                cn[u] = 0;
+#pragma unroll
+                for (int e = 0; e < 3; ++e) vn[u][e] = 0.0;
+                if (j0 + UR + u < nr) {
+                    const int jr = j0 + UR + u;
+                    cn[u] = __builtin_nontemporal_load(&col3[rbase + (int64_t)jr * kSlice]);
+#pragma unroll
+                    for (int e = 0; e < 3; ++e)
+                        vn[u][e] = __builtin_nontemporal_load(&val[vbase + (int64_t)(3 * jr + e) * kSlice]);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < UR; ++u)
+                if (j0 + u < nr) {
+                    const double *xc = x + (int64_t)c[u] * K;
+#pragma unroll
+                    for (int e = 0; e < 3; ++e)
+#pragma unroll
+                        for (int j = 0; j < K; ++j) acc[j] = fma(v[u][e], xc[e * K + j], acc[j]);
+                }
+#pragma unroll
+            for (int u = 0; u < UR; ++u) {
+                c[u] = cn[u];
+#pragma unroll
+                for (int e = 0; e < 3; ++e) v[u][e] = vn[u][e];
+            }
+        }
+        if (r < n) {
+#pragma unroll
+            for (int j = 0; j < K; ++j) {
+                y[(int64_t)r * K + j] = acc[j];
+                if (DOT) part[j] = fma(acc[j], w[(int64_t)r * K + j], part[j]);
+            }
+        }
+    }
+    if (DOT) {
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            const double bs = block_sum(part[j], sh);
+            if (threadIdx.x == 0) partials[(size_t)j * gridDim.x + lb] = bs;
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------------------
 // PCG over a block of K right-hand sides (x0 = 0): K independent recurrences with their own
 // scalars and stopping tests; the vectors are n x K row-major blocks and every product reads
@@ -1368,7 +1460,10 @@ __global__ __launch_bounds__(kThreads) void k_multi_resid(int n, const double *_
 template <int K, bool DOT>
 static void spmm_launch(const Sell &S, const double *x, double *y, const double *w, double *partials, int nb,
                         const DeviceInfo &di, hipStream_t s) {
-    if (S.f32)
+    if (S.col3 && !S.f32 && !S.lens)
+        hipLaunchKernelGGL((k_sell_spmm_runs<K, DOT>), dim3(nb), dim3(kThreads), 0, s, S.n, S.nslices, S.sptr, S.col3,
+                           (const double *)S.val, x, y, di.num_xcds, w, partials);
+    else if (S.f32)
         hipLaunchKernelGGL((k_sell_spmm<K, float, DOT>), dim3(nb), dim3(kThreads), 0, s, S.n, S.nslices, S.sptr, S.perm,
                            S.lens, S.col, (const float *)S.val, x, y, di.num_xcds, w, partials);
     else
@@ -1892,6 +1987,10 @@ static int pcg_multi(const afsai_csr *A, afsai_precond P, const double *B, doubl
         ~Free() { sell_free(S); }
     } free_sa{&SA};
     if (SA.tail) AFSAI_FAIL(AFSAI_ERR_INVALID_ARG, "pcg_solve_multi: split SELL layouts are not supported");
+    if (option(AFSAI_OPT_SELL_RUNS) != 1) {
+        ProfScope ps("sell_A_runs", s);
+        if ((rc = sell_group_runs(&SA, di, s))) return rc;
+    }
     const int nbA = blocks_for_slices(SA.nslices, di), nbv = blocks_for_vec(n, di);
     const int nbG = P ? blocks_for_slices(P->sg.nslices, di) : 0;
     const int nbGT = P ? blocks_for_slices(P->sgt.nslices, di) : 0;
@@ -2006,20 +2105,11 @@ static int spmm_sell(const Sell &S, int32_t k, const double *X, double *Y, const
     {
         ProfScope ps("spmm_A", s);
         const int nb = blocks_for_slices(S.nslices, di);
-        const double *vx = X;
         switch (k) {
-            case 1: hipLaunchKernelGGL((k_sell_spmm<1, double>), dim3(nb), dim3(kThreads), 0, s, S.n, S.nslices, S.sptr,
-                                       S.perm, S.lens, S.col, (const double *)S.val, vx, Y, di.num_xcds, nullptr,
-                                       nullptr); break;
-            case 2: hipLaunchKernelGGL((k_sell_spmm<2, double>), dim3(nb), dim3(kThreads), 0, s, S.n, S.nslices, S.sptr,
-                                       S.perm, S.lens, S.col, (const double *)S.val, vx, Y, di.num_xcds, nullptr,
-                                       nullptr); break;
-            case 4: hipLaunchKernelGGL((k_sell_spmm<4, double>), dim3(nb), dim3(kThreads), 0, s, S.n, S.nslices, S.sptr,
-                                       S.perm, S.lens, S.col, (const double *)S.val, vx, Y, di.num_xcds, nullptr,
-                                       nullptr); break;
-            default: hipLaunchKernelGGL((k_sell_spmm<8, double>), dim3(nb), dim3(kThreads), 0, s, S.n, S.nslices, S.sptr,
-                                        S.perm, S.lens, S.col, (const double *)S.val, vx, Y, di.num_xcds, nullptr,
-                                       nullptr); break;
+            case 1: spmm_launch<1, false>(S, X, Y, nullptr, nullptr, nb, di, s); break;
+            case 2: spmm_launch<2, false>(S, X, Y, nullptr, nullptr, nb, di, s); break;
+            case 4: spmm_launch<4, false>(S, X, Y, nullptr, nullptr, nb, di, s); break;
+            default: spmm_launch<8, false>(S, X, Y, nullptr, nullptr, nb, di, s); break;
         }
     }
     const hipError_t le = hipGetLastError();

@@ -627,6 +627,16 @@ def test_prepared_matrix_column_runs(af):
     X = torch.from_numpy(synth.uniform(29, 5, Pb.n * 4, -1.0, 1.0).reshape(Pb.n, 4)).cuda()
     assert torch.equal(M.spmm(X), af.spmm(dA, X))
     M.close()
+    # the block PCG's products with A over run indices equal the per-entry layout's
+    B2 = torch.from_numpy(synth.uniform(37, 5, Pb.n * 2, -1.0, 1.0).reshape(Pb.n, 2)).cuda()
+    Xr, ir = af.pcg_solve_multi(dA, P, B2, rtol=1e-8)
+    af.set_option(af.OPT_SELL_RUNS, 1)
+    try:
+        Xe, ie = af.pcg_solve_multi(dA, P, B2, rtol=1e-8)
+    finally:
+        af.set_option(af.OPT_SELL_RUNS, 0)
+    assert [i.iters for i in ir] == [i.iters for i in ie]
+    assert torch.equal(Xr, Xe)
     P.close()
 
 
